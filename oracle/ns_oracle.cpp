@@ -1,0 +1,903 @@
+// ns_oracle.cpp -- plain FP64 CPU oracle for the stabilised discrete unsteady adjoint of the
+// compressible Navier-Stokes equations (Talnikar, Wang & Laskowski, GT2016-56689).
+//
+// TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library against the paper.
+// Only the test suite, the smoke check and the benchmark's CPU-baseline leg load it; the
+// product path never links, imports or calls it, and it shares no code, header, table or
+// helper with the GPU kernels.
+//
+// Written for clarity, not speed: every residual is a loop over faces, every derivative comes
+// from forward-mode dual numbers (automatic differentiation, the tool the paper used to obtain
+// its discrete adjoint, section "Implementation"), and every reduction is a serial sum in a
+// fixed order.  The only parallelism is OpenMP over independent faces/cells with per-thread
+// accumulators that are summed in thread order afterwards.
+//
+// What is computed (paper section / equation in brackets):
+//   * residual  R(w; s) = -div_h F(w) + div_h F^v(w) + s          [Physics, Eq. (navier); vector form; index form with s_i]
+//       - convective face flux  0.5 (F_d(w_L) + F_d(w_R))          (central finite volume)
+//       - viscous face flux     (0, sigma_d., u_f . sigma_d. + alpha d_d e) with face gradients:
+//         normal (phi_R - phi_L)/dx_d, tangential = mean of the two cells' central differences
+//       - sigma = mu (grad u + grad u^T) - (2 mu / 3) (div u) I,  p = (gamma-1) rho e,
+//         e = E - |u|^2/2,  alpha = gamma mu / Pr  (heat flux alpha grad e = k grad T)
+//   * classical RK4 in time with fixed dt
+//   * discrete adjoint of the RK4 step [Implementation; terminal condition and backward solve]:
+//       the transposed Jacobian of every face flux is assembled from dual-number local Jacobians
+//   * artificial adjoint viscosity  d_l( lambda sigma_1 delta_ki delta_jl d_j w^_k )  [Stabilizing
+//     adjoint equations, last equation], discretised as a symmetric face-based Laplacian
+//   * growth matrix M = M1 - M2 and its largest singular value sigma_1 [Energy Analysis, M1/M2]
+//   * adjoint energy E = int |v^|^2 dV with v^ = T^{-T} w^ [Symmetrization, Energy Analysis]
+//   * objectives: volume-mean pressure, volume-mean viscous dissipation sigma:grad u, and the
+//     density-weighted stagnation-pressure loss on a plane [Eqs. (1)-(3), pressure loss]
+//
+// Layout: SoA, var-major, w[v*N + (k*ny + j)*nx + i], v = (rho, rho u1, rho u2, rho u3, rho E).
+// Boundaries: periodic in y and z; x either periodic or inviscid-mirror slip walls (ghost cell
+// mirrors the first interior cell with the x-momentum sign flipped).
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+extern "C" {
+typedef struct orc_grid {
+  int32_t n[3];
+  int32_t bc_x;  // 0: periodic in x, 1: slip walls at x = 0 and x = L_x
+  double L[3];
+  double gamma, prandtl, mu, dt;
+} orc_grid;
+
+typedef struct orc_obj {
+  int32_t kind;     // 0 none, 1 mean pressure, 2 viscous dissipation, 3 stagnation-pressure loss
+  int32_t plane_i;  // kind 3: the x-face between cells plane_i-1 and plane_i
+  double pt_ref;    // kind 3: reference (inlet / free-stream) stagnation pressure
+} orc_obj;
+}
+
+namespace {
+
+// ------------------------------------------------------------------------------------------
+// Forward-mode dual numbers: value plus N directional derivatives.
+// ------------------------------------------------------------------------------------------
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+  Dual() : v(0.0) { for (int i = 0; i < N; ++i) d[i] = 0.0; }
+  Dual(double x) : v(x) { for (int i = 0; i < N; ++i) d[i] = 0.0; }
+};
+template <int N> Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v + b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+template <int N> Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v - b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+template <int N> Dual<N> operator-(const Dual<N>& a) { Dual<N> r; r.v = -a.v; for (int i = 0; i < N; ++i) r.d[i] = -a.d[i]; return r; }
+template <int N> Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v * b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
+template <int N> Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v / b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
+  return r;
+}
+template <int N> Dual<N> operator+(const Dual<N>& a, double b) { Dual<N> r = a; r.v += b; return r; }
+template <int N> Dual<N> operator+(double a, const Dual<N>& b) { return b + a; }
+template <int N> Dual<N> operator-(const Dual<N>& a, double b) { Dual<N> r = a; r.v -= b; return r; }
+template <int N> Dual<N> operator-(double a, const Dual<N>& b) { return -(b - a); }
+template <int N> Dual<N> operator*(const Dual<N>& a, double b) { Dual<N> r; r.v = a.v * b; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b; return r; }
+template <int N> Dual<N> operator*(double a, const Dual<N>& b) { return b * a; }
+template <int N> Dual<N> operator/(const Dual<N>& a, double b) { Dual<N> r; r.v = a.v / b; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] / b; return r; }
+template <int N> Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
+template <int N> Dual<N>& operator+=(Dual<N>& a, const Dual<N>& b) { a = a + b; return a; }
+template <int N> Dual<N>& operator-=(Dual<N>& a, const Dual<N>& b) { a = a - b; return a; }
+template <int N> Dual<N> sqrt(const Dual<N>& a) {
+  Dual<N> r; r.v = std::sqrt(a.v);
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] / (2.0 * r.v);
+  return r;
+}
+template <int N> Dual<N> pow(const Dual<N>& a, double e) {
+  Dual<N> r; r.v = std::pow(a.v, e);
+  const double dr = e * std::pow(a.v, e - 1.0);
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * dr;
+  return r;
+}
+using std::sqrt;
+using std::pow;
+
+// ------------------------------------------------------------------------------------------
+// Grid helpers
+// ------------------------------------------------------------------------------------------
+struct G {
+  long nx, ny, nz, N;
+  double dx[3];
+  int wall;
+  double gamma, pr, mu, alpha, dt;
+  explicit G(const orc_grid* g) {
+    nx = g->n[0]; ny = g->n[1]; nz = g->n[2]; N = nx * ny * nz;
+    for (int d = 0; d < 3; ++d) dx[d] = g->L[d] / (double)g->n[d];
+    wall = g->bc_x;
+    gamma = g->gamma; pr = g->prandtl; mu = g->mu; dt = g->dt;
+    alpha = gamma * mu / pr;  // heat flux alpha grad e == (mu c_p / Pr) grad T, since e = c_v T
+  }
+  long n(int d) const { return d == 0 ? nx : (d == 1 ? ny : nz); }
+  long idx(long i, long j, long k) const { return (k * ny + j) * nx + i; }
+};
+
+inline long wrap(long i, long n) { i %= n; return i < 0 ? i + n : i; }
+
+// A stencil slot: which cell provides the value, and whether it is the x-wall mirror image.
+struct Slot { long c; int mirror; bool real; };
+
+Slot slot(const G& g, long i, long j, long k) {
+  Slot s; s.mirror = 0; s.real = true;
+  j = wrap(j, g.ny); k = wrap(k, g.nz);
+  if (!g.wall) {
+    i = wrap(i, g.nx);
+  } else if (i < 0) {
+    i = -1 - i; s.mirror = 1; s.real = false;
+  } else if (i >= g.nx) {
+    i = 2 * g.nx - 1 - i; s.mirror = 1; s.real = false;
+  }
+  s.c = g.idx(i, j, k);
+  return s;
+}
+// Mirror ghost: rho, tangential momentum and total energy even; x-momentum odd.
+inline double mirror_sign(int mirror, int v) { return (mirror && v == 1) ? -1.0 : 1.0; }
+
+template <class T>
+void load_slot(const G& g, const T* w, const Slot& s, T out[5]) {
+  for (int v = 0; v < 5; ++v) out[v] = mirror_sign(s.mirror, v) * w[v * g.N + s.c];
+}
+
+template <class T>
+struct Prim { T rho, u[3], e, p, E; };
+
+// Primitive variables from w = (rho, rho u, rho E)   [Physics: p = (gamma-1) rho e, e = E - u.u/2]
+template <class T>
+Prim<T> prim(const G& g, const T w[5]) {
+  Prim<T> q;
+  q.rho = w[0];
+  for (int k = 0; k < 3; ++k) q.u[k] = w[1 + k] / q.rho;
+  q.E = w[4];
+  q.e = q.E / q.rho - 0.5 * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
+  q.p = (g.gamma - 1.0) * q.rho * q.e;
+  return q;
+}
+
+// Convective flux in direction d   [vector form: F = (rho u, rho u u + p I, (rho E + p) u)]
+template <class T>
+void conv_flux(int d, const Prim<T>& q, T F[5]) {
+  T m = q.rho * q.u[d];
+  F[0] = m;
+  for (int k = 0; k < 3; ++k) F[1 + k] = m * q.u[k];
+  F[1 + d] = F[1 + d] + q.p;
+  F[4] = (q.E + q.p) * q.u[d];
+}
+
+inline void tangents(int d, int& t1, int& t2) { t1 = (d == 0) ? 1 : 0; t2 = (d == 2) ? 1 : 2; }
+
+// Stencil of the face between cell L=(i,j,k) and R=L+e_d: slots
+//   0 L, 1 R, 2 L+e_t1, 3 L-e_t1, 4 L+e_t2, 5 L-e_t2, 6 R+e_t1, 7 R-e_t1, 8 R+e_t2, 9 R-e_t2
+void face_slots(const G& g, int d, long i, long j, long k, Slot st[10]) {
+  long L[3] = {i, j, k};
+  long R[3] = {i, j, k};
+  R[d] += 1;
+  int t1, t2; tangents(d, t1, t2);
+  auto sl = [&](const long* c, int t, int sgn) {
+    long p[3] = {c[0], c[1], c[2]};
+    if (t >= 0) p[t] += sgn;
+    return slot(g, p[0], p[1], p[2]);
+  };
+  st[0] = sl(L, -1, 0); st[1] = sl(R, -1, 0);
+  st[2] = sl(L, t1, +1); st[3] = sl(L, t1, -1); st[4] = sl(L, t2, +1); st[5] = sl(L, t2, -1);
+  st[6] = sl(R, t1, +1); st[7] = sl(R, t1, -1); st[8] = sl(R, t2, +1); st[9] = sl(R, t2, -1);
+}
+
+// Total face flux H = F~ - F~^v on the face between slot 0 (L) and slot 1 (R) in direction d.
+//   F~   = 0.5 (F_d(w_L) + F_d(w_R))
+//   F~^v = (0, sigma_d., u_f . sigma_d. + alpha d_d e), u_f = 0.5 (u_L + u_R)
+//   face gradient d_l u_k: l == d -> (u_R - u_L)/dx_d ; l != d -> mean of the central
+//   differences of cells L and R in direction l.
+template <class T>
+void face_flux(const G& g, int d, const T st[10][5], T H[5]) {
+  Prim<T> q[10];
+  for (int s = 0; s < 10; ++s) q[s] = prim(g, st[s]);
+  T FL[5], FR[5];
+  conv_flux(d, q[0], FL);
+  conv_flux(d, q[1], FR);
+  int t[2]; tangents(d, t[0], t[1]);
+  T gu[3][3];  // gu[l][k] = d_l u_k at the face
+  for (int k = 0; k < 3; ++k) {
+    gu[d][k] = (q[1].u[k] - q[0].u[k]) / g.dx[d];
+    for (int a = 0; a < 2; ++a) {
+      int l = t[a];
+      const Prim<T>& Lp = q[2 + 2 * a]; const Prim<T>& Lm = q[3 + 2 * a];
+      const Prim<T>& Rp = q[6 + 2 * a]; const Prim<T>& Rm = q[7 + 2 * a];
+      gu[l][k] = ((Lp.u[k] - Lm.u[k]) + (Rp.u[k] - Rm.u[k])) / (4.0 * g.dx[l]);
+    }
+  }
+  T de = (q[1].e - q[0].e) / g.dx[d];
+  T div = gu[0][0] + gu[1][1] + gu[2][2];
+  T sig[3];
+  for (int k = 0; k < 3; ++k) {
+    sig[k] = g.mu * (gu[d][k] + gu[k][d]);
+    if (k == d) sig[k] = sig[k] - (2.0 * g.mu / 3.0) * div;
+  }
+  T work = 0.0;
+  for (int k = 0; k < 3; ++k) work = work + 0.5 * (q[0].u[k] + q[1].u[k]) * sig[k];
+  H[0] = 0.5 * (FL[0] + FR[0]);
+  for (int k = 0; k < 3; ++k) H[1 + k] = 0.5 * (FL[1 + k] + FR[1 + k]) - sig[k];
+  H[4] = 0.5 * (FL[4] + FR[4]) - (work + g.alpha * de);
+}
+
+// Face ranges: in x with walls the faces run from the wall face (ghost -1 | 0) to (nx-1 | ghost nx).
+void face_range(const G& g, int d, long& i0, long& i1) {
+  if (d == 0 && g.wall) { i0 = -1; i1 = g.nx; } else { i0 = 0; i1 = g.n(d); }
+}
+
+int nthreads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+int thread_id() {
+#ifdef _OPENMP
+  return omp_get_thread_num();
+#else
+  return 0;
+#endif
+}
+
+// Runs body(d, i, j, k, acc) over every face, in parallel over the outermost face index, with a
+// private accumulator per thread; the accumulators are added into `out` in thread order.
+template <class T, class Body>
+void face_scatter(const G& g, long out_len, T* out, Body body) {
+  int nt = nthreads();
+  std::vector<std::vector<T>> acc(nt, std::vector<T>(out_len, T(0.0)));
+  for (int d = 0; d < 3; ++d) {
+    long i0, i1; face_range(g, d, i0, i1);
+    // faces of direction d are indexed by the L cell (i,j,k); i in [i0, i1) along x
+    long ilen = (d == 0) ? (i1 - i0) : g.nx;
+    long jlen = (d == 1) ? g.ny : g.ny;
+    long nfaces = ilen * jlen * g.nz;
+#pragma omp parallel for schedule(static)
+    for (long f = 0; f < nfaces; ++f) {
+      long ii = f % ilen, rest = f / ilen;
+      long j = rest % jlen, k = rest / jlen;
+      long i = (d == 0) ? ii + i0 : ii;
+      body(d, i, j, k, acc[thread_id()].data());
+    }
+  }
+  for (int t = 0; t < nt; ++t)
+    for (long x = 0; x < out_len; ++x) out[x] += acc[t][x];
+}
+
+// ------------------------------------------------------------------------------------------
+// Residual R(w; s)
+// ------------------------------------------------------------------------------------------
+template <class T>
+void residual(const G& g, const T* w, const T* s, T* R) {
+  for (long x = 0; x < 5 * g.N; ++x) R[x] = T(0.0);
+  face_scatter<T>(g, 5 * g.N, R, [&](int d, long i, long j, long k, T* acc) {
+    Slot sl[10]; face_slots(g, d, i, j, k, sl);
+    T st[10][5];
+    for (int a = 0; a < 10; ++a) load_slot(g, w, sl[a], st[a]);
+    T H[5]; face_flux(g, d, st, H);
+    for (int v = 0; v < 5; ++v) {
+      if (sl[0].real) acc[v * g.N + sl[0].c] -= H[v] / g.dx[d];
+      if (sl[1].real) acc[v * g.N + sl[1].c] += H[v] / g.dx[d];
+    }
+  });
+  if (s)
+    for (long x = 0; x < 5 * g.N; ++x) R[x] += s[x];
+}
+
+// out = J_R(W)^T kh : for every face, the 5 x 50 local Jacobian dH/d(stencil) from dual numbers,
+// contracted with the adjoint weights (kh_R - kh_L)/dx_d and scattered to the stencil cells.
+void vjp(const G& g, const double* W, const double* kh, double* out) {
+  constexpr int ND = 50;
+  for (long x = 0; x < 5 * g.N; ++x) out[x] = 0.0;
+  face_scatter<double>(g, 5 * g.N, out, [&](int d, long i, long j, long k, double* acc) {
+    Slot sl[10]; face_slots(g, d, i, j, k, sl);
+    Dual<ND> st[10][5];
+    for (int a = 0; a < 10; ++a)
+      for (int v = 0; v < 5; ++v) {
+        double sg = mirror_sign(sl[a].mirror, v);
+        st[a][v] = Dual<ND>(sg * W[v * g.N + sl[a].c]);
+        st[a][v].d[a * 5 + v] = sg;
+      }
+    Dual<ND> H[5]; face_flux(g, d, st, H);
+    double om[5];
+    for (int o = 0; o < 5; ++o) {
+      double r = sl[1].real ? kh[o * g.N + sl[1].c] : 0.0;
+      double l = sl[0].real ? kh[o * g.N + sl[0].c] : 0.0;
+      om[o] = (r - l) / g.dx[d];
+    }
+    for (int a = 0; a < 10; ++a)
+      for (int v = 0; v < 5; ++v) {
+        double sum = 0.0;
+        for (int o = 0; o < 5; ++o) sum += om[o] * H[o].d[a * 5 + v];
+        acc[v * g.N + sl[a].c] += sum;
+      }
+  });
+}
+
+// out = J_R(W) v  (tangent), by evaluating the residual on single-direction dual numbers.
+void jvp(const G& g, const double* W, const double* v, double* out) {
+  std::vector<Dual<1>> wd(5 * g.N), Rd(5 * g.N);
+  for (long x = 0; x < 5 * g.N; ++x) { wd[x] = Dual<1>(W[x]); wd[x].d[0] = v[x]; }
+  residual<Dual<1>>(g, wd.data(), nullptr, Rd.data());
+  for (long x = 0; x < 5 * g.N; ++x) out[x] = Rd[x].d[0];
+}
+
+// ------------------------------------------------------------------------------------------
+// Artificial adjoint viscosity  (L_nu q)_i = sum_d [nu_{i+1/2}(q_{i+1}-q_i) - nu_{i-1/2}(q_i-q_{i-1})]/dx_d^2
+// with nu_f = (nu_L + nu_R)/2, applied to each of the 5 components (delta_ki delta_jl).  Wall faces
+// carry no artificial flux.  Accumulates into out.
+// ------------------------------------------------------------------------------------------
+void lnu_apply(const G& g, const double* nu, const double* q, double* out) {
+  face_scatter<double>(g, 5 * g.N, out, [&](int d, long i, long j, long k, double* acc) {
+    Slot sl[10]; face_slots(g, d, i, j, k, sl);
+    if (!sl[0].real || !sl[1].real) return;
+    double nf = 0.5 * (nu[sl[0].c] + nu[sl[1].c]);
+    for (int v = 0; v < 5; ++v) {
+      double flux = nf * (q[v * g.N + sl[1].c] - q[v * g.N + sl[0].c]) / (g.dx[d] * g.dx[d]);
+      acc[v * g.N + sl[0].c] += flux;
+      acc[v * g.N + sl[1].c] -= flux;
+    }
+  });
+}
+
+// ------------------------------------------------------------------------------------------
+// Growth matrix M = M1 - M2 and sigma_1   [Energy Analysis: M1, M2 as printed; sigma_1 = largest
+// singular value of M].  a = sqrt((gamma-1)/gamma) c, b = c / sqrt(gamma).
+// grads: grho[3], gu[3][3] with gu[k][j] = d_j u_k, gp[3], ga[3], gb[3].
+// ------------------------------------------------------------------------------------------
+void cell_growth_matrix(double gamma, double rho, double p, double a, double b, const double grho[3],
+                        const double gu[3][3], const double gp[3], const double ga[3],
+                        const double gb[3], double M[5][5]) {
+  double div = gu[0][0] + gu[1][1] + gu[2][2];
+  double M1[5][5] = {{0}}, M2[5][5] = {{0}};
+  M1[0][0] = div;
+  for (int j = 0; j < 3; ++j) {
+    M1[0][1 + j] = gb[j]; M1[1 + j][0] = gb[j];
+    M1[1 + j][1 + j] = div;
+    M1[1 + j][4] = ga[j]; M1[4][1 + j] = ga[j];
+  }
+  M1[4][4] = div;
+  for (int r = 0; r < 5; ++r)
+    for (int c = 0; c < 5; ++c) M1[r][c] *= 0.5;
+  for (int j = 0; j < 3; ++j) M2[0][1 + j] = (b / rho) * grho[j];
+  M2[0][4] = 0.5 * std::sqrt(gamma - 1.0) * div;
+  for (int k = 0; k < 3; ++k) {
+    for (int j = 0; j < 3; ++j) M2[1 + k][1 + j] = gu[k][j];
+    M2[1 + k][4] = (a / (2.0 * p)) * gp[k];
+  }
+  for (int j = 0; j < 3; ++j) M2[4][1 + j] = (2.0 / (gamma - 1.0)) * ga[j];
+  M2[4][4] = 0.5 * (gamma - 1.0) * div;
+  for (int r = 0; r < 5; ++r)
+    for (int c = 0; c < 5; ++c) M[r][c] = M1[r][c] - M2[r][c];
+}
+
+// Largest eigenvalue of a symmetric 5x5 matrix by cyclic Jacobi rotations, iterated until the
+// off-diagonal mass is below 1e-30 of the total (or 100 sweeps).
+double sym_lambda_max(double A[5][5]) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int p = 0; p < 5; ++p)
+      for (int q = 0; q < 5; ++q) {
+        tot += A[p][q] * A[p][q];
+        if (p != q) off += A[p][q] * A[p][q];
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < 4; ++p)
+      for (int q = p + 1; q < 5; ++q) {
+        if (A[p][q] == 0.0) continue;
+        double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < 5; ++r) {  // A <- A J
+          double arp = A[r][p], arq = A[r][q];
+          A[r][p] = c * arp - s * arq;
+          A[r][q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < 5; ++r) {  // A <- J^T A
+          double apr = A[p][r], aqr = A[q][r];
+          A[p][r] = c * apr - s * aqr;
+          A[q][r] = s * apr + c * aqr;
+        }
+      }
+  }
+  double m = A[0][0];
+  for (int i = 1; i < 5; ++i) m = std::max(m, A[i][i]);
+  return m;
+}
+
+double sigma1_of(const double M[5][5]) {
+  double A[5][5];
+  for (int r = 0; r < 5; ++r)
+    for (int c = 0; c < 5; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < 5; ++k) s += M[k][r] * M[k][c];
+      A[r][c] = s;
+    }
+  return std::sqrt(std::max(sym_lambda_max(A), 0.0));
+}
+
+struct CellQ { double rho, u[3], p, a, b; };
+CellQ cellq(const G& g, const double w[5]) {
+  Prim<double> q = prim(g, w);
+  CellQ c; c.rho = q.rho; for (int k = 0; k < 3; ++k) c.u[k] = q.u[k]; c.p = q.p;
+  double cs = std::sqrt(g.gamma * q.p / q.rho);
+  c.a = std::sqrt((g.gamma - 1.0) / g.gamma) * cs;
+  c.b = cs / std::sqrt(g.gamma);
+  return c;
+}
+
+// M at cell (i,j,k) with cell-centred central differences of rho, u, p, a, b.
+void grid_growth_matrix(const G& g, const double* w, long i, long j, long k, double M[5][5]) {
+  double wc[5]; load_slot(g, w, slot(g, i, j, k), wc);
+  CellQ c = cellq(g, wc);
+  double grho[3], gu[3][3], gp[3], ga[3], gb[3];
+  for (int l = 0; l < 3; ++l) {
+    long pp[3] = {i, j, k}, mm[3] = {i, j, k};
+    pp[l] += 1; mm[l] -= 1;
+    double wp[5], wm[5];
+    load_slot(g, w, slot(g, pp[0], pp[1], pp[2]), wp);
+    load_slot(g, w, slot(g, mm[0], mm[1], mm[2]), wm);
+    CellQ P = cellq(g, wp), Mq = cellq(g, wm);
+    double h = 2.0 * g.dx[l];
+    grho[l] = (P.rho - Mq.rho) / h;
+    for (int kk = 0; kk < 3; ++kk) gu[kk][l] = (P.u[kk] - Mq.u[kk]) / h;
+    gp[l] = (P.p - Mq.p) / h;
+    ga[l] = (P.a - Mq.a) / h;
+    gb[l] = (P.b - Mq.b) / h;
+  }
+  cell_growth_matrix(g.gamma, c.rho, c.p, c.a, c.b, grho, gu, gp, ga, gb, M);
+}
+
+void sigma1_field(const G& g, const double* w, double* sig) {
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < g.N; ++c) {
+    long i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+    double M[5][5];
+    grid_growth_matrix(g, w, i, j, k, M);
+    sig[c] = sigma1_of(M);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Objectives j(w) and dj/dw (dual numbers on each local contribution; serial fixed-order sums)
+// ------------------------------------------------------------------------------------------
+// Volume-mean viscous dissipation contribution of one cell from its 6 face neighbours
+// (slots: 0 +x, 1 -x, 2 +y, 3 -y, 4 +z, 5 -z), Phi = sigma_ij d_j u_i with central gradients.
+template <class T>
+T dissipation_cell(const G& g, const T nb[6][5]) {
+  T gu[3][3];  // gu[l][k] = d_l u_k
+  for (int l = 0; l < 3; ++l) {
+    Prim<T> P = prim(g, nb[2 * l]), Mq = prim(g, nb[2 * l + 1]);
+    for (int k = 0; k < 3; ++k) gu[l][k] = (P.u[k] - Mq.u[k]) / (2.0 * g.dx[l]);
+  }
+  T div = gu[0][0] + gu[1][1] + gu[2][2];
+  T phi = 0.0;
+  for (int l = 0; l < 3; ++l)
+    for (int k = 0; k < 3; ++k) {
+      T sig = g.mu * (gu[l][k] + gu[k][l]);
+      if (l == k) sig = sig - (2.0 * g.mu / 3.0) * div;
+      phi = phi + sig * gu[l][k];
+    }
+  return phi;
+}
+
+// Stagnation pressure of the face state  p_t = p (1 + (gamma-1)/2 M^2)^(gamma/(gamma-1))   [Eq. (3)]
+template <class T>
+void plane_terms(const G& g, double pt_ref, const T wf[5], T& num, T& den) {
+  Prim<T> q = prim(g, wf);
+  T u2 = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+  T c2 = g.gamma * q.p / q.rho;
+  T pt = q.p * pow(1.0 + 0.5 * (g.gamma - 1.0) * u2 / c2, g.gamma / (g.gamma - 1.0));
+  num = q.rho * (pt_ref - pt);
+  den = q.rho;
+}
+
+int objective(const G& g, const orc_obj* ob, const double* w, double* jout, double* djdw) {
+  const long N = g.N;
+  if (djdw)
+    for (long x = 0; x < 5 * N; ++x) djdw[x] = 0.0;
+  if (ob->kind == 0) { *jout = 0.0; return 0; }
+  if (ob->kind == 1) {  // j = (1/N) sum_c p_c
+    std::vector<double> pc(N);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; ++c) {
+      Dual<5> wd[5];
+      for (int v = 0; v < 5; ++v) { wd[v] = Dual<5>(w[v * N + c]); wd[v].d[v] = 1.0; }
+      Prim<Dual<5>> q = prim(g, wd);
+      pc[c] = q.p.v;
+      if (djdw)
+        for (int v = 0; v < 5; ++v) djdw[v * N + c] = q.p.d[v] / (double)N;
+    }
+    double s = 0.0;
+    for (long c = 0; c < N; ++c) s += pc[c];
+    *jout = s / (double)N;
+    return 0;
+  }
+  if (ob->kind == 2) {  // j = (1/N) sum_c Phi_c
+    std::vector<double> phic(N);
+    std::vector<double> contrib(djdw ? 30 * N : 0);
+    std::vector<long> cells(djdw ? 6 * N : 0);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; ++c) {
+      long i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+      Slot sl[6];
+      for (int l = 0; l < 3; ++l) {
+        long pp[3] = {i, j, k}, mm[3] = {i, j, k};
+        pp[l] += 1; mm[l] -= 1;
+        sl[2 * l] = slot(g, pp[0], pp[1], pp[2]);
+        sl[2 * l + 1] = slot(g, mm[0], mm[1], mm[2]);
+      }
+      Dual<30> nb[6][5];
+      for (int a = 0; a < 6; ++a)
+        for (int v = 0; v < 5; ++v) {
+          double sg = mirror_sign(sl[a].mirror, v);
+          nb[a][v] = Dual<30>(sg * w[v * N + sl[a].c]);
+          nb[a][v].d[a * 5 + v] = sg;
+        }
+      Dual<30> phi = dissipation_cell(g, nb);
+      phic[c] = phi.v;
+      if (djdw) {
+        for (int a = 0; a < 30; ++a) contrib[30 * c + a] = phi.d[a] / (double)N;
+        for (int a = 0; a < 6; ++a) cells[6 * c + a] = sl[a].c;
+      }
+    }
+    double s = 0.0;
+    for (long c = 0; c < N; ++c) s += phic[c];
+    *jout = s / (double)N;
+    if (djdw)
+      for (long c = 0; c < N; ++c)
+        for (int a = 0; a < 6; ++a)
+          for (int v = 0; v < 5; ++v) djdw[v * N + cells[6 * c + a]] += contrib[30 * c + a * 5 + v];
+    return 0;
+  }
+  if (ob->kind == 3) {  // j = sum rho_f (pt_ref - pt_f) / (pt_ref sum rho_f), face state = mean of L, R
+    if (ob->plane_i < 1 || ob->plane_i >= g.nx) return -1;
+    long il = ob->plane_i - 1, ir = ob->plane_i;
+    double num = 0.0, den = 0.0;
+    std::vector<double> dnum(djdw ? 10 * g.ny * g.nz : 0), dden(djdw ? 10 * g.ny * g.nz : 0);
+    for (long k = 0; k < g.nz; ++k)
+      for (long j = 0; j < g.ny; ++j) {
+        long cl = g.idx(il, j, k), cr = g.idx(ir, j, k);
+        Dual<10> wf[5];
+        for (int v = 0; v < 5; ++v) {
+          wf[v] = Dual<10>(0.5 * (w[v * N + cl] + w[v * N + cr]));
+          wf[v].d[v] = 0.5; wf[v].d[5 + v] = 0.5;
+        }
+        Dual<10> nm, dn;
+        plane_terms(g, ob->pt_ref, wf, nm, dn);
+        num += nm.v; den += dn.v;
+        if (djdw) {
+          long f = k * g.ny + j;
+          for (int a = 0; a < 10; ++a) { dnum[10 * f + a] = nm.d[a]; dden[10 * f + a] = dn.d[a]; }
+        }
+      }
+    double jv = num / (den * ob->pt_ref);
+    *jout = jv;
+    if (djdw)
+      for (long k = 0; k < g.nz; ++k)
+        for (long j = 0; j < g.ny; ++j) {
+          long f = k * g.ny + j;
+          long cl = g.idx(il, j, k), cr = g.idx(ir, j, k);
+          for (int v = 0; v < 5; ++v) {
+            // quotient rule: d(num/(den pt))/dx = (dnum - (num/den) dden) / (den pt)
+            double gl = (dnum[10 * f + v] - (num / den) * dden[10 * f + v]) / (den * ob->pt_ref);
+            double gr = (dnum[10 * f + 5 + v] - (num / den) * dden[10 * f + 5 + v]) / (den * ob->pt_ref);
+            djdw[v * N + cl] += gl;
+            djdw[v * N + cr] += gr;
+          }
+        }
+    return 0;
+  }
+  return -1;
+}
+
+// ------------------------------------------------------------------------------------------
+// RK4 stages
+// ------------------------------------------------------------------------------------------
+template <class T>
+void rk4_step(const G& g, const T* w, const T* s, T* wn) {
+  const long M = 5 * g.N;
+  std::vector<T> k1(M), k2(M), k3(M), k4(M), W(M);
+  residual<T>(g, w, s, k1.data());
+  for (long x = 0; x < M; ++x) W[x] = w[x] + (0.5 * g.dt) * k1[x];
+  residual<T>(g, W.data(), s, k2.data());
+  for (long x = 0; x < M; ++x) W[x] = w[x] + (0.5 * g.dt) * k2[x];
+  residual<T>(g, W.data(), s, k3.data());
+  for (long x = 0; x < M; ++x) W[x] = w[x] + g.dt * k3[x];
+  residual<T>(g, W.data(), s, k4.data());
+  for (long x = 0; x < M; ++x)
+    wn[x] = w[x] + (g.dt / 6.0) * (k1[x] + 2.0 * k2[x] + 2.0 * k3[x] + k4[x]);
+}
+
+// The four RK4 stage states W1 = w, W2, W3, W4 of one step.
+void rk4_stage_states(const G& g, const double* w, const double* s, std::vector<double> Ws[4]) {
+  const long M = 5 * g.N;
+  std::vector<double> k(M);
+  Ws[0].assign(w, w + M);
+  const double c[3] = {0.5 * g.dt, 0.5 * g.dt, g.dt};
+  for (int m = 0; m < 3; ++m) {
+    residual<double>(g, Ws[m].data(), s, k.data());
+    Ws[m + 1].resize(M);
+    for (long x = 0; x < M; ++x) Ws[m + 1][x] = w[x] + c[m] * k[x];
+  }
+}
+
+}  // namespace
+
+// ==========================================================================================
+// C entry points (ctypes).  All arrays are host FP64 SoA; return 0 on success, -1 on bad input.
+// ==========================================================================================
+extern "C" {
+
+int orc_num_threads(void) { return nthreads(); }
+
+static int check(const orc_grid* g) {
+  if (!g) return -1;
+  for (int d = 0; d < 3; ++d)
+    if (g->n[d] < 1 || !(g->L[d] > 0)) return -1;
+  if (g->bc_x == 1 && g->n[0] < 2) return -1;
+  return 0;
+}
+
+// R = R(w; s)
+int orc_residual(const orc_grid* gr, const double* w, const double* s, double* R) {
+  if (check(gr)) return -1;
+  G g(gr);
+  residual<double>(g, w, s, R);
+  return 0;
+}
+
+// out = J_R(W) v
+int orc_jvp(const orc_grid* gr, const double* W, const double* v, double* out) {
+  if (check(gr)) return -1;
+  G g(gr);
+  jvp(g, W, v, out);
+  return 0;
+}
+
+// out = J_R(W)^T kh
+int orc_vjp(const orc_grid* gr, const double* W, const double* kh, double* out) {
+  if (check(gr)) return -1;
+  G g(gr);
+  vjp(g, W, kh, out);
+  return 0;
+}
+
+// out += L_nu q
+int orc_lnu_apply(const orc_grid* gr, const double* nu, const double* q, double* out) {
+  if (check(gr)) return -1;
+  G g(gr);
+  lnu_apply(g, nu, q, out);
+  return 0;
+}
+
+// w_next = RK4 step of w with source s (s may be NULL)
+int orc_primal_step(const orc_grid* gr, const double* w, const double* s, double* wn) {
+  if (check(gr)) return -1;
+  G g(gr);
+  rk4_step<double>(g, w, s, wn);
+  return 0;
+}
+
+// Complex-step primal: the state and source carry imaginary parts (re, im arrays).
+int orc_primal_step_complex(const orc_grid* gr, const double* w_re, const double* w_im,
+                            const double* s_re, const double* s_im, double* out_re, double* out_im) {
+  if (check(gr)) return -1;
+  G g(gr);
+  const long M = 5 * g.N;
+  std::vector<std::complex<double>> w(M), s(M), wn(M);
+  for (long x = 0; x < M; ++x) {
+    w[x] = {w_re[x], w_im ? w_im[x] : 0.0};
+    s[x] = {s_re ? s_re[x] : 0.0, s_im ? s_im[x] : 0.0};
+  }
+  rk4_step<std::complex<double>>(g, w.data(), s.data(), wn.data());
+  for (long x = 0; x < M; ++x) { out_re[x] = wn[x].real(); out_im[x] = wn[x].imag(); }
+  return 0;
+}
+
+// Tangent-linear RK4 step: (w, dw) -> (w_next, dw_next) for perturbations dw of the state and ds
+// of the source.  With lambda > 0 the tangent of every stage also carries L_nu dW with
+// nu = lambda sigma_1(w) frozen over the step (the operator whose transpose the stabilised
+// adjoint applies).
+int orc_tlm_step(const orc_grid* gr, const double* w, const double* s, const double* dw,
+                 const double* ds, double lambda, double* wn, double* dwn) {
+  if (check(gr)) return -1;
+  G g(gr);
+  const long M = 5 * g.N;
+  std::vector<double> nu;
+  if (lambda != 0.0) {
+    nu.resize(g.N);
+    sigma1_field(g, w, nu.data());
+    for (auto& x : nu) x *= lambda;
+  }
+  std::vector<double> Ws[4];
+  rk4_stage_states(g, w, s, Ws);
+  std::vector<double> dW(dw, dw + M), dk[4];
+  const double c[3] = {0.5 * g.dt, 0.5 * g.dt, g.dt};
+  for (int m = 0; m < 4; ++m) {
+    dk[m].assign(M, 0.0);
+    jvp(g, Ws[m].data(), dW.data(), dk[m].data());
+    if (lambda != 0.0) lnu_apply(g, nu.data(), dW.data(), dk[m].data());
+    if (ds)
+      for (long x = 0; x < M; ++x) dk[m][x] += ds[x];
+    if (m < 3)
+      for (long x = 0; x < M; ++x) dW[x] = dw[x] + c[m] * dk[m][x];
+  }
+  for (long x = 0; x < M; ++x)
+    dwn[x] = dw[x] + (g.dt / 6.0) * (dk[0][x] + 2.0 * dk[1][x] + 2.0 * dk[2][x] + dk[3][x]);
+  if (wn) rk4_step<double>(g, w, s, wn);
+  return 0;
+}
+
+// One reverse RK4 step of the discrete adjoint   [Implementation; adjoint terminal condition and
+// backward integration; stabilised adjoint equation]:
+//   recompute W1..W4 from w_n;  nu = lambda sigma_1(w_n)
+//   k^4 = dt/6 a;           g4 = (J(W4)^T + L_nu) k^4
+//   k^3 = dt/3 a + dt g4;   g3 = (J(W3)^T + L_nu) k^3
+//   k^2 = dt/3 a + dt/2 g3; g2 = (J(W2)^T + L_nu) k^2
+//   k^1 = dt/6 a + dt/2 g2; g1 = (J(W1)^T + L_nu) k^1
+//   w^_n = a + g1 + g2 + g3 + g4 + c_n dj/dw(w_n);   grad_s += k^1 + k^2 + k^3 + k^4
+// where a = w^_{n+1}.  grad_s may be NULL; obj may be NULL (no injection).
+int orc_adjoint_step(const orc_grid* gr, const double* w, const double* s, const double* a,
+                     double lambda, const orc_obj* ob, double c_n, double* wh, double* grad_s) {
+  if (check(gr)) return -1;
+  G g(gr);
+  const long M = 5 * g.N;
+  std::vector<double> Ws[4];
+  rk4_stage_states(g, w, s, Ws);
+  std::vector<double> nu;
+  if (lambda != 0.0) {
+    nu.resize(g.N);
+    sigma1_field(g, w, nu.data());
+    for (auto& x : nu) x *= lambda;
+  }
+  const double dt = g.dt;
+  const double ca[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};  // weight of a in k^m, m = 1..4
+  const double cg[4] = {dt / 2.0, dt / 2.0, dt, 0.0};             // weight of g_{m+1} in k^m
+  std::vector<double> gnext(M, 0.0), gm(M), kh(M), sum_g(M, 0.0), sum_k(M, 0.0);
+  for (int m = 3; m >= 0; --m) {
+    for (long x = 0; x < M; ++x) kh[x] = ca[m] * a[x] + cg[m] * gnext[x];
+    vjp(g, Ws[m].data(), kh.data(), gm.data());
+    if (lambda != 0.0) lnu_apply(g, nu.data(), kh.data(), gm.data());
+    for (long x = 0; x < M; ++x) { sum_g[x] += gm[x]; sum_k[x] += kh[x]; }
+    gnext = gm;
+  }
+  std::vector<double> dj(M, 0.0);
+  if (ob && ob->kind != 0 && c_n != 0.0) {
+    double jv;
+    if (objective(g, ob, w, &jv, dj.data())) return -1;
+  }
+  for (long x = 0; x < M; ++x) wh[x] = a[x] + sum_g[x] + c_n * dj[x];
+  if (grad_s)
+    for (long x = 0; x < M; ++x) grad_s[x] += sum_k[x];
+  return 0;
+}
+
+// Objective value and (optionally) gradient dj/dw (overwritten).
+int orc_objective(const orc_grid* gr, const orc_obj* ob, const double* w, double* j, double* djdw) {
+  if (check(gr) || !ob) return -1;
+  G g(gr);
+  return objective(g, ob, w, j, djdw);
+}
+
+// sigma_1 per cell
+int orc_sigma1(const orc_grid* gr, const double* w, double* sig) {
+  if (check(gr)) return -1;
+  G g(gr);
+  sigma1_field(g, w, sig);
+  return 0;
+}
+
+// Growth matrix at every cell, row-major 25 values per cell (for tests).
+int orc_growth_matrix_field(const orc_grid* gr, const double* w, double* Mout) {
+  if (check(gr)) return -1;
+  G g(gr);
+  for (long c = 0; c < g.N; ++c) {
+    long i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+    double M[5][5];
+    grid_growth_matrix(g, w, i, j, k, M);
+    for (int r = 0; r < 5; ++r)
+      for (int q = 0; q < 5; ++q) Mout[25 * c + 5 * r + q] = M[r][q];
+  }
+  return 0;
+}
+
+// Pointwise growth matrix from given gradients: grads = [grho(3), gu(9, gu[k][j] = d_j u_k),
+// gp(3), ga(3), gb(3)]; a and b derive from (gamma, rho, p).
+int orc_cell_growth_matrix(double gamma, double rho, double p, const double* grads, double* Mout) {
+  double cs = std::sqrt(gamma * p / rho);
+  double a = std::sqrt((gamma - 1.0) / gamma) * cs, b = cs / std::sqrt(gamma);
+  double gu[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j) gu[k][j] = grads[3 + 3 * k + j];
+  double M[5][5];
+  cell_growth_matrix(gamma, rho, p, a, b, grads, gu, grads + 12, grads + 15, grads + 18, M);
+  for (int r = 0; r < 5; ++r)
+    for (int q = 0; q < 5; ++q) Mout[5 * r + q] = M[r][q];
+  return 0;
+}
+
+// Largest singular value of a single 5x5 matrix (row-major), for tests.
+double orc_matrix_sigma1(const double* Min) {
+  double M[5][5];
+  for (int r = 0; r < 5; ++r)
+    for (int q = 0; q < 5; ++q) M[r][q] = Min[5 * r + q];
+  return sigma1_of(M);
+}
+
+// Symmetrised adjoint v^ = T^{-T} w^ per cell (closed form, out: 5N) and the adjoint energy
+// E = (1/dV) sum_cells |v^|^2  [Symmetrization: w^ = T^T v^; Energy Analysis: E_v^].
+//   q^ = V^{-T} w^: q^_rho = w^_1 + u.w^_m + |u|^2/2 w^_E, q^_u = rho w^_m + rho u w^_E,
+//                   q^_p = w^_E/(gamma-1)
+//   v^ = S^{-T} q^: v^_1 = (rho/b) q^_rho + rho b q^_p, v^_{2..4} = q^_u, v^_5 = rho a q^_p
+int orc_energy_vhat(const orc_grid* gr, const double* w, const double* wh, double* vhat, double* E) {
+  if (check(gr)) return -1;
+  G g(gr);
+  const long N = g.N;
+  std::vector<double> e2(N);
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < N; ++c) {
+    double wc[5], h[5];
+    for (int v = 0; v < 5; ++v) { wc[v] = w[v * N + c]; h[v] = wh[v * N + c]; }
+    CellQ q = cellq(g, wc);
+    double u2 = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+    double qr = h[0] + q.u[0] * h[1] + q.u[1] * h[2] + q.u[2] * h[3] + 0.5 * u2 * h[4];
+    double qu[3];
+    for (int k = 0; k < 3; ++k) qu[k] = q.rho * h[1 + k] + q.rho * q.u[k] * h[4];
+    double qp = h[4] / (g.gamma - 1.0);
+    double vv[5] = {(q.rho / q.b) * qr + q.rho * q.b * qp, qu[0], qu[1], qu[2], q.rho * q.a * qp};
+    double s = 0.0;
+    for (int v = 0; v < 5; ++v) { s += vv[v] * vv[v]; if (vhat) vhat[v * N + c] = vv[v]; }
+    e2[c] = s;
+  }
+  double tot = 0.0;
+  for (long c = 0; c < N; ++c) tot += e2[c];
+  if (E) *E = tot / (g.dx[0] * g.dx[1] * g.dx[2]);
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// BF16 checkpoint codec (per-snapshot, per-variable affine scaling), FP32 arithmetic:
+//   m_v = (max_v + min_v)/2, s_v = (max_v - min_v)/2 (1 if the range is 0),
+//   q = bf16_round_nearest_even((w - m_v) / s_v),   decode w' = fma(s_v, q, m_v).
+// ------------------------------------------------------------------------------------------
+static uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u; std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+static float bf16_to_f32(uint16_t h) { uint32_t u = (uint32_t)h << 16; float f; std::memcpy(&f, &u, 4); return f; }
+
+int orc_ckpt_encode(long N, const float* w, uint16_t* q, float* meanscale) {
+  for (int v = 0; v < 5; ++v) {
+    float mn = w[v * N], mx = w[v * N];
+    for (long c = 1; c < N; ++c) { mn = std::min(mn, w[v * N + c]); mx = std::max(mx, w[v * N + c]); }
+    float m = 0.5f * (mx + mn), s = 0.5f * (mx - mn);
+    if (!(s > 0.0f)) s = 1.0f;
+    meanscale[2 * v] = m; meanscale[2 * v + 1] = s;
+    for (long c = 0; c < N; ++c) {
+      float t = (w[v * N + c] - m) / s;
+      q[v * N + c] = f32_to_bf16_rne(t);
+    }
+  }
+  return 0;
+}
+
+int orc_ckpt_decode(long N, const uint16_t* q, const float* meanscale, float* w) {
+  for (int v = 0; v < 5; ++v)
+    for (long c = 0; c < N; ++c)
+      w[v * N + c] = std::fma(meanscale[2 * v + 1], bf16_to_f32(q[v * N + c]), meanscale[2 * v]);
+  return 0;
+}
+
+}  // extern "C"
