@@ -1,0 +1,160 @@
+/* adjns.h -- C ABI of the MI355X (gfx950) library for the stabilised discrete unsteady adjoint
+ * of the compressible Navier-Stokes equations (Talnikar, Wang & Laskowski, GT2016-56689).
+ *
+ * The method: the primal state w = (rho, rho u1, rho u2, rho u3, rho E) obeys the compressible
+ * Navier-Stokes equations with an ideal gas and a source term s (section "Physics", Eq. navier;
+ * "Unsteady adjoint", vector and index forms).  A time-averaged objective J = sum_n c_n j(w_n)
+ * is differentiated with the discrete adjoint, integrated backwards in time from a zero terminal
+ * value ("Unsteady adjoint", terminal condition; "Implementation": discrete adjoint), optionally
+ * stabilised by the artificial adjoint viscosity d_l(lambda sigma_1 d_l w^) where sigma_1 is the
+ * largest singular value of the adjoint-energy growth matrix M = M1 - M2 ("Stabilizing adjoint
+ * equations": Energy Analysis, last equation).
+ *
+ * Discretisation (identical in every entry point):
+ *   - uniform Cartesian cells, n[d] cells over length L[d], dx_d = L[d]/n[d]; periodic in y, z;
+ *     x periodic or slip walls (mirror ghost cell, x-momentum odd);
+ *   - residual R(w; s) = -sum_d (F~_{d,+} - F~_{d,-})/dx_d + s, with F~ = 0.5 (F(w_L) + F(w_R))
+ *     minus the viscous face flux (0, sigma_d., u_f . sigma_d. + alpha d_d e): normal face
+ *     gradients (phi_R - phi_L)/dx_d, tangential ones the mean of the two cells' central
+ *     differences; sigma = mu (grad u + grad u^T) - (2/3) mu (div u) I; alpha = gamma mu / Pr;
+ *   - classical RK4 with fixed dt.
+ *
+ * Memory: every state-sized array is a DEVICE pointer owned by the caller, structure-of-arrays,
+ * var-major: a[v*N + (k*ny + j)*nx + i], v = 0..4, N = nx*ny*nz, element type double when
+ * grid->precision == ADJ_F64 and float when ADJ_F32.  Scalars marked "device double" are FP64 in
+ * device memory in both precisions.  The library never allocates, frees or synchronises: every
+ * call enqueues kernels on `stream` (a hipStream_t; NULL = the default stream) and returns.
+ * Scratch memory is the caller's `ws` of at least adj_workspace_bytes(grid) bytes, 256-byte
+ * aligned; calls that share a `ws` must be ordered on one stream.
+ *
+ * Errors: every entry point validates its arguments on the host before launching anything and
+ * returns a negative adj_status without touching device memory when they are invalid;
+ * adj_last_error() then describes the problem (thread-local).  Launch failures return ADJ_EHIP.
+ */
+#ifndef ADJNS_H
+#define ADJNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum adj_status {
+  ADJ_OK = 0,
+  ADJ_EINVAL = -1,     /* null pointer, bad enum, non-positive size or parameter */
+  ADJ_ESHAPE = -2,     /* grid too small for the requested boundary treatment or objective */
+  ADJ_EUNSTABLE = -3,  /* requested dt / lambda outside the explicit stability bound */
+  ADJ_ENONFINITE = -4, /* a reduction met a NaN or Inf */
+  ADJ_EHIP = -5,       /* a HIP runtime call or kernel launch failed */
+  ADJ_EWORKSPACE = -6  /* workspace missing, too small or misaligned */
+} adj_status;
+
+enum { ADJ_BC_PERIODIC = 0, ADJ_BC_SLIP_WALLS = 1 };
+enum { ADJ_F64 = 0, ADJ_F32 = 1 };
+enum { ADJ_CKPT_NATIVE = 0, ADJ_CKPT_BF16 = 1 };
+enum {
+  ADJ_OBJ_NONE = 0,
+  ADJ_OBJ_MEAN_PRESSURE = 1,  /* j = (1/N) sum_cells p                                         */
+  ADJ_OBJ_KE_DISSIPATION = 2, /* j = (1/N) sum_cells sigma_ij d_j u_i, central cell gradients     */
+  ADJ_OBJ_PT_LOSS_PLANE = 3   /* j = sum_f rho_f (pt_ref - p_t,f) / (pt_ref sum_f rho_f) on the
+                                 x-face between cells plane_i-1 and plane_i, face state the mean of
+                                 its two cells, p_t = p (1 + (gamma-1)/2 M^2)^(gamma/(gamma-1))
+                                 (Eqs. (1)-(3), pressure loss)                                    */
+};
+
+/* Grid, gas and scheme.  dt is fixed over a window. */
+typedef struct adj_grid {
+  int32_t n[3];        /* cells in x, y, z (each >= 1; >= 2 in x with slip walls)           */
+  int32_t bc_x;        /* ADJ_BC_PERIODIC or ADJ_BC_SLIP_WALLS                               */
+  double L[3];         /* box lengths                                                        */
+  double gamma;        /* ratio of specific heats                                            */
+  double prandtl;      /* Prandtl number; heat conduction coefficient alpha = gamma mu / Pr  */
+  double mu;           /* constant dynamic viscosity                                         */
+  double dt;           /* time step                                                          */
+  int32_t precision;   /* ADJ_F64 or ADJ_F32: element type of states and stencil arithmetic  */
+  int32_t ckpt_format; /* ADJ_CKPT_NATIVE or ADJ_CKPT_BF16 (ADJ_F32 only): form of w_n handed
+                          to adj_adjoint_step and of ckpt_out written by adj_primal_step       */
+} adj_grid;
+
+typedef struct adj_objective {
+  int32_t kind;    /* ADJ_OBJ_*                                       */
+  int32_t plane_i; /* PT_LOSS_PLANE: 1 <= plane_i <= n[0]-1           */
+  double pt_ref;   /* PT_LOSS_PLANE: reference stagnation pressure > 0 */
+} adj_objective;
+
+/* Bytes of scratch the caller must pass as `ws` to any call on this grid. */
+size_t adj_workspace_bytes(const adj_grid* grid);
+
+/* Bytes of one BF16 checkpoint record: a 64-byte header of 5 (mean, scale) FP32 pairs followed
+ * by 5N bfloat16 codes in the state layout. */
+size_t adj_ckpt_bytes(const adj_grid* grid);
+
+/* One RK4 step of the primal  [Physics; Numerical methods (time marching)].
+ *   w_n   in : state at step n                     (state-sized)
+ *   s     in : source field, or NULL for s = 0      (state-sized)
+ *   w_np1 out: state at step n+1 (must not alias w_n)
+ *   ckpt_out : NULL, or an adj_ckpt_bytes() record receiving the BF16 encoding of w_np1
+ *              (precision ADJ_F32 only)  [Implementation: checkpointing] */
+int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* One reverse RK4 step of the discrete adjoint with artificial viscosity  [Unsteady adjoint:
+ * terminal condition and backward integration; Implementation; Stabilizing adjoint equations]:
+ *   recompute the stage states W1 = w_n, W2, W3, W4; nu = lambda sigma_1(w_n) held over the step;
+ *   k^4 = dt/6 a, g4 = (J_R(W4)^T + L_nu) k^4; k^3 = dt/3 a + dt g4, g3 = ...;
+ *   k^2 = dt/3 a + dt/2 g3, g2 = ...; k^1 = dt/6 a + dt/2 g2, g1 = ...;
+ *   w^_n = a + g1 + g2 + g3 + g4 + c_n dj/dw(w_n);  grad_s += k^1 + k^2 + k^3 + k^4,
+ * where a = w^_{n+1} and (L_nu q)_i = sum_d [nu_{i+1/2}(q_{i+1}-q_i) - nu_{i-1/2}(q_i-q_{i-1})]/dx_d^2
+ * with face nu the mean of its cells (no artificial flux through slip walls).
+ *   w_n     in : primal state at step n (state-sized), or a BF16 record when ckpt_format says so
+ *   s       in : source field or NULL
+ *   wh_np1  in : adjoint at step n+1 (state-sized)
+ *   lambda  in : artificial-viscosity scale, units length^2 (>= 0; 0 = plain adjoint)
+ *   obj, c_n   : objective injected with weight c_n (obj NULL or kind NONE or c_n == 0: none)
+ *   wh_n   out : adjoint at step n (must not alias wh_np1)
+ *   grad_s inout: accumulated dJ/ds (+=), or NULL */
+int adj_adjoint_step(const adj_grid* grid, const void* w_n, const void* s, const void* wh_np1,
+                     double lambda, const adj_objective* obj, double c_n, void* wh_n, void* grad_s,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* out[c] = scale * sigma_1(c): largest singular value of M = M1 - M2 at every cell, from central
+ * differences of rho, u, p, a = sqrt((gamma-1)/gamma) c, b = c/sqrt(gamma)  [Energy Analysis].
+ *   w in: state; out: N elements of the grid's precision. */
+int adj_growth_sigma1(const adj_grid* grid, const void* w, double scale, void* out, void* stream);
+
+/* Objective j(w) and its gradient  [Eqs. (1)-(3); time-averaged objective]:
+ *   J_accum (device double, may be NULL): J_accum += weight * j(w)
+ *   djdw    (state-sized, may be NULL)   : djdw += weight * dj/dw(w) */
+int adj_objective_and_grad(const adj_grid* grid, const adj_objective* obj, const void* w, double weight,
+                           double* J_accum, void* djdw, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint energy E = (1/dV) sum_cells |T^{-T} w^|^2 in symmetrised variables  [Symmetrization:
+ * w^ = T^T v^; Energy Analysis: E_v^]; E is a device double (overwritten), FP64 accumulation. */
+int adj_energy_vhat(const adj_grid* grid, const void* w, const void* wh, double* E, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* out (device double) = sum over all 5N entries of a*b, FP64 accumulation in a fixed order. */
+int adj_dot(const adj_grid* grid, const void* a, const void* b, double* out, void* ws, size_t ws_bytes,
+            void* stream);
+
+/* BF16 checkpoint codec (ADJ_F32 states): per variable v, m_v = (max+min)/2, s_v = (max-min)/2
+ * (1 when the range is empty), code = bf16_round_nearest_even((w - m_v)/s_v) in FP32; decode
+ * w' = fma(s_v, code, m_v).  ckpt is an adj_ckpt_bytes() record. */
+int adj_ckpt_encode(const adj_grid* grid, const float* w, void* ckpt, void* ws, size_t ws_bytes, void* stream);
+int adj_ckpt_decode(const adj_grid* grid, const void* ckpt, float* w, void* stream);
+
+/* Operator-level entry points (used to check single stages):
+ *   adj_residual: R = R(w; s)
+ *   adj_vjp     : out = J_R(W)^T kh + (nu ? L_nu kh : 0), nu an N-element field or NULL */
+int adj_residual(const adj_grid* grid, const void* w, const void* s, void* R, void* stream);
+int adj_vjp(const adj_grid* grid, const void* W, const void* kh, const void* nu, void* out, void* stream);
+
+const char* adj_last_error(void);
+const char* adj_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADJNS_H */

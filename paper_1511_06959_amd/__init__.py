@@ -1,0 +1,228 @@
+"""MI355X (gfx950) stabilised discrete unsteady adjoint of compressible Navier-Stokes.
+
+Thin ctypes binding over ``libadjns.so`` (the C ABI of ``include/adjns.h``).  Every function
+here only marshals arguments: tensors are passed as device pointers, the stream is torch's
+current HIP stream, and all arithmetic runs in the library's kernels.  There is no fallback:
+if the library is missing or cannot be loaded, every call raises.
+
+Functions keep the names of the C entry points without the ``adj_`` prefix:
+``primal_step``, ``adjoint_step``, ``growth_sigma1``, ``objective_and_grad``, ``energy_vhat``,
+``dot``, ``ckpt_encode``, ``ckpt_decode``, ``residual``, ``vjp``, ``workspace_bytes``,
+``ckpt_bytes``.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadjns.so")
+
+F64, F32 = 0, 1
+CKPT_NATIVE, CKPT_BF16 = 0, 1
+BC_PERIODIC, BC_SLIP_WALLS = 0, 1
+OBJ_NONE, OBJ_MEAN_PRESSURE, OBJ_KE_DISSIPATION, OBJ_PT_LOSS_PLANE = 0, 1, 2, 3
+
+STATUS = {0: "ADJ_OK", -1: "ADJ_EINVAL", -2: "ADJ_ESHAPE", -3: "ADJ_EUNSTABLE", -4: "ADJ_ENONFINITE",
+          -5: "ADJ_EHIP", -6: "ADJ_EWORKSPACE"}
+
+
+class AdjError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    """Mirror of ``adj_grid``."""
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("bc_x", ctypes.c_int32),
+        ("L", ctypes.c_double * 3),
+        ("gamma", ctypes.c_double),
+        ("prandtl", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("ckpt_format", ctypes.c_int32),
+    ]
+
+    @classmethod
+    def make(cls, n, L, mu, dt, gamma=1.4, prandtl=0.72, bc_x=0, precision=F64, ckpt_format=CKPT_NATIVE):
+        g = cls()
+        for d in range(3):
+            g.n[d] = int(n[d])
+            g.L[d] = float(L[d])
+        g.bc_x = int(bc_x)
+        g.gamma, g.prandtl, g.mu, g.dt = float(gamma), float(prandtl), float(mu), float(dt)
+        g.precision, g.ckpt_format = int(precision), int(ckpt_format)
+        return g
+
+    @property
+    def ncells(self):
+        return self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def dtype(self):
+        return torch.float64 if self.precision == F64 else torch.float32
+
+
+class Objective(ctypes.Structure):
+    """Mirror of ``adj_objective``."""
+    _fields_ = [("kind", ctypes.c_int32), ("plane_i", ctypes.c_int32), ("pt_ref", ctypes.c_double)]
+
+    @classmethod
+    def make(cls, kind, plane_i=0, pt_ref=0.0):
+        o = cls()
+        o.kind, o.plane_i, o.pt_ref = int(kind), int(plane_i), float(pt_ref)
+        return o
+
+
+_lib = None
+EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjoint_step", "adj_growth_sigma1",
+           "adj_objective_and_grad", "adj_energy_vhat", "adj_dot", "adj_ckpt_encode", "adj_ckpt_decode",
+           "adj_residual", "adj_vjp", "adj_last_error", "adj_version")
+
+
+def lib():
+    """Load libadjns.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1511_06959_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, gp, op = ctypes.c_void_p, ctypes.POINTER(Grid), ctypes.POINTER(Objective)
+    sz, dbl = ctypes.c_size_t, ctypes.c_double
+    sig = {
+        "adj_workspace_bytes": ([gp], sz),
+        "adj_ckpt_bytes": ([gp], sz),
+        "adj_primal_step": ([gp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_adjoint_step": ([gp, vp, vp, vp, dbl, op, dbl, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_growth_sigma1": ([gp, vp, dbl, vp, vp], ctypes.c_int),
+        "adj_objective_and_grad": ([gp, op, vp, dbl, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_energy_vhat": ([gp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_dot": ([gp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_ckpt_encode": ([gp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_ckpt_decode": ([gp, vp, vp, vp], ctypes.c_int),
+        "adj_residual": ([gp, vp, vp, vp, vp], ctypes.c_int),
+        "adj_vjp": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "adj_last_error": ([], ctypes.c_char_p),
+        "adj_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise AdjError(rc, lib().adj_last_error().decode())
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _state(g, t):
+    p = _ptr(t, g.dtype)
+    if t is not None and t.numel() != 5 * g.ncells:
+        raise ValueError(f"state tensors hold 5*N = {5 * g.ncells} values, got {t.numel()}")
+    return p
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def version():
+    return lib().adj_version().decode()
+
+
+def workspace_bytes(g):
+    n = lib().adj_workspace_bytes(ctypes.byref(g))
+    if n == 0:
+        raise AdjError(-1, lib().adj_last_error().decode())
+    return n
+
+
+def ckpt_bytes(g):
+    return lib().adj_ckpt_bytes(ctypes.byref(g))
+
+
+def workspace(g, device="cuda"):
+    """A workspace tensor (uint8) of adj_workspace_bytes(g) bytes."""
+    return torch.empty(workspace_bytes(g), dtype=torch.uint8, device=device)
+
+
+def _ws(ws):
+    return _ptr(ws, torch.uint8), ctypes.c_size_t(ws.numel())
+
+
+def primal_step(g, w_n, s, w_np1, ws, ckpt_out=None):
+    wp, wb = _ws(ws)
+    _check(lib().adj_primal_step(ctypes.byref(g), _state(g, w_n), _state(g, s), _state(g, w_np1),
+                                 _ptr(ckpt_out, torch.uint8), wp, wb, _stream()))
+
+
+def adjoint_step(g, w_n, s, wh_np1, wh_n, ws, lam=0.0, obj=None, c_n=0.0, grad_s=None):
+    """w_n is a state tensor, or a uint8 BF16 record when g.ckpt_format == CKPT_BF16."""
+    wp, wb = _ws(ws)
+    wn_p = _ptr(w_n, torch.uint8) if g.ckpt_format == CKPT_BF16 else _state(g, w_n)
+    _check(lib().adj_adjoint_step(ctypes.byref(g), wn_p, _state(g, s), _state(g, wh_np1), float(lam),
+                                  ctypes.byref(obj) if obj is not None else None, float(c_n), _state(g, wh_n),
+                                  _state(g, grad_s), wp, wb, _stream()))
+
+
+def growth_sigma1(g, w, out, scale=1.0):
+    if out.numel() != g.ncells:
+        raise ValueError("sigma_1 output holds N values")
+    _check(lib().adj_growth_sigma1(ctypes.byref(g), _state(g, w), float(scale), _ptr(out, g.dtype), _stream()))
+
+
+def objective_and_grad(g, obj, w, ws, weight=1.0, J_accum=None, djdw=None):
+    wp, wb = _ws(ws)
+    _check(lib().adj_objective_and_grad(ctypes.byref(g), ctypes.byref(obj), _state(g, w), float(weight),
+                                        _ptr(J_accum, torch.float64), _state(g, djdw), wp, wb, _stream()))
+
+
+def energy_vhat(g, w, wh, E, ws):
+    wp, wb = _ws(ws)
+    _check(lib().adj_energy_vhat(ctypes.byref(g), _state(g, w), _state(g, wh), _ptr(E, torch.float64), wp, wb,
+                                 _stream()))
+
+
+def dot(g, a, b, out, ws):
+    wp, wb = _ws(ws)
+    _check(lib().adj_dot(ctypes.byref(g), _state(g, a), _state(g, b), _ptr(out, torch.float64), wp, wb, _stream()))
+
+
+def ckpt_encode(g, w, ckpt, ws):
+    wp, wb = _ws(ws)
+    _check(lib().adj_ckpt_encode(ctypes.byref(g), _state(g, w), _ptr(ckpt, torch.uint8), wp, wb, _stream()))
+
+
+def ckpt_decode(g, ckpt, w):
+    _check(lib().adj_ckpt_decode(ctypes.byref(g), _ptr(ckpt, torch.uint8), _state(g, w), _stream()))
+
+
+def residual(g, w, s, R):
+    _check(lib().adj_residual(ctypes.byref(g), _state(g, w), _state(g, s), _state(g, R), _stream()))
+
+
+def vjp(g, W, kh, out, nu=None):
+    _check(lib().adj_vjp(ctypes.byref(g), _state(g, W), _state(g, kh), _ptr(nu, g.dtype), _state(g, out),
+                         _stream()))

@@ -1,0 +1,670 @@
+// aux.hip -- gfx950 kernels for the growth-matrix singular value sigma_1, the objectives and their
+// gradients, the FP64 reductions (adjoint energy, inner products) and the BF16 checkpoint codec.
+#include "kernels.hpp"
+
+namespace adjns {
+
+namespace {
+
+// ------------------------------------------------------------------------------------------
+// Deterministic FP64 reductions: fixed grid, grid-stride per-thread sums, LDS tree per block,
+// then one block folds the per-block partials in index order.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+#pragma unroll
+  for (int o = RB / 2; o > 0; o >>= 1) {
+    __syncthreads();
+    if (t < o) sh[t] += sh[t + o];
+  }
+  __syncthreads();
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+inline int reduce_blocks(long long n) {
+  long long b = (n + RB - 1) / RB;
+  if (b > MAX_PARTIALS) b = MAX_PARTIALS;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// partials has `nsets` consecutive arrays of `nblk` values; dst[s] = beta dst[s] + alpha[s] sum_s
+__global__ __launch_bounds__(RB) void k_fold(const double* __restrict__ partials, int nblk, int nsets,
+                                             double* __restrict__ dst, double alpha, double beta) {
+  __shared__ double sh[RB];
+  for (int s = 0; s < nsets; ++s) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += RB) v += partials[s * nblk + i];
+    const double tot = block_sum(v, sh);
+    if (threadIdx.x == 0) dst[s] = beta * dst[s] + alpha * tot;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_dot_partial(const T* __restrict__ a, const T* __restrict__ b, long long n,
+                                                    double* __restrict__ partials) {
+  __shared__ double sh[RB];
+  double v = 0.0;
+  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB)
+    v += (double)a[i] * (double)b[i];
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// Primitive quantities of a cell (or its wall mirror image), in FP64.
+struct Q64 {
+  double rho, u[3], e, p, ri;
+};
+
+template <typename T>
+__device__ __forceinline__ Q64 load_q64(const Consts<T>& c, const T* __restrict__ w, long long gi, int mirror,
+                                        double gamma) {
+  const long long N = c.N;
+  Q64 q;
+  q.rho = (double)w[gi];
+  double m1 = (double)w[N + gi];
+  if (mirror) m1 = -m1;
+  const double m2 = (double)w[2 * N + gi], m3 = (double)w[3 * N + gi], Et = (double)w[4 * N + gi];
+  q.ri = 1.0 / q.rho;
+  q.u[0] = m1 * q.ri;
+  q.u[1] = m2 * q.ri;
+  q.u[2] = m3 * q.ri;
+  q.e = Et * q.ri - 0.5 * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
+  q.p = (gamma - 1.0) * q.rho * q.e;
+  return q;
+}
+
+// ------------------------------------------------------------------------------------------
+// Adjoint energy: v^ = T^{-T} w^ per cell (closed form from S and V)
+//   q^_rho = w^_1 + u.w^_m + |u|^2/2 w^_E, q^_u = rho (w^_m + u w^_E), q^_p = w^_E/(gamma-1)
+//   v^_1 = (rho/b) q^_rho + rho b q^_p, v^_{2..4} = q^_u, v^_5 = rho a q^_p
+// [Symmetrization: S, V, T = S V, w^ = T^T v^; Energy Analysis: E_v^]
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(RB) void k_energy_partial(Consts<T> c, const T* __restrict__ w,
+                                                       const T* __restrict__ wh, double* __restrict__ partials) {
+  __shared__ double sh[RB];
+  const double g = (double)c.gamma;
+  const double sa = sqrt((g - 1.0) / g), sb = 1.0 / sqrt(g);
+  const long long N = c.N;
+  double v = 0.0;
+  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < N; i += (long long)gridDim.x * RB) {
+    const Q64 q = load_q64(c, w, i, 0, g);
+    const double cs = sqrt(g * q.p * q.ri);
+    const double a = sa * cs, b = sb * cs;
+    double h[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) h[k] = (double)wh[k * N + i];
+    const double usq = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+    const double qr = h[0] + q.u[0] * h[1] + q.u[1] * h[2] + q.u[2] * h[3] + 0.5 * usq * h[4];
+    const double qp = h[4] / (g - 1.0);
+    const double v1 = (q.rho / b) * qr + q.rho * b * qp;
+    const double v5 = q.rho * a * qp;
+    double s = v1 * v1 + v5 * v5;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double qu = q.rho * (h[1 + k] + q.u[k] * h[4]);
+      s += qu * qu;
+    }
+    v += s;
+  }
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// ------------------------------------------------------------------------------------------
+// sigma_1: M = M1 - M2 from central differences [Energy Analysis, printed M1 and M2], then the
+// largest eigenvalue of M^T M by cyclic Jacobi rotations.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+struct QS {
+  T rho, u[3], p, a, b;
+};
+
+template <typename T>
+__device__ __forceinline__ QS<T> load_qs(const Consts<T>& c, const T* __restrict__ w, int gx, int gy, int gz) {
+  int mirror, real;
+  const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, gx, gy, gz, mirror, real);
+  const long long N = c.N;
+  QS<T> q;
+  q.rho = w[gi];
+  T m1 = w[N + gi];
+  if (mirror) m1 = -m1;
+  const T ri = T(1) / q.rho;
+  q.u[0] = m1 * ri;
+  q.u[1] = w[2 * N + gi] * ri;
+  q.u[2] = w[3 * N + gi] * ri;
+  const T e = w[4 * N + gi] * ri - T(0.5) * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
+  const T g = c.gamma;
+  q.p = (g - T(1)) * q.rho * e;
+  const T cs = sqrt(g * q.p * ri);
+  q.a = sqrt((g - T(1)) / g) * cs;
+  q.b = cs / sqrt(g);
+  return q;
+}
+
+template <typename T>
+struct JacobiTol;
+template <>
+struct JacobiTol<double> {
+  static constexpr double rel = 1e-30;
+  static constexpr int sweeps = 12;
+};
+template <>
+struct JacobiTol<float> {
+  static constexpr float rel = 1e-14f;
+  static constexpr int sweeps = 8;
+};
+
+template <typename T>
+__device__ __forceinline__ void jrot(T (&A)[5][5], int p, int q) {
+  const T apq = A[p][q];
+  if (apq == T(0)) return;
+  const T theta = (A[q][q] - A[p][p]) / (T(2) * apq);
+  const T at = fabs(theta);
+  T t;
+  if (at > T(1e15))
+    t = T(0.5) / theta;
+  else
+    t = (theta >= T(0) ? T(1) : T(-1)) / (at + sqrt(theta * theta + T(1)));
+  const T cs = T(1) / sqrt(t * t + T(1));
+  const T sn = t * cs;
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    const T arp = A[r][p], arq = A[r][q];
+    A[r][p] = cs * arp - sn * arq;
+    A[r][q] = sn * arp + cs * arq;
+  }
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    const T apr = A[p][r], aqr = A[q][r];
+    A[p][r] = cs * apr - sn * aqr;
+    A[q][r] = sn * apr + cs * aqr;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_sigma1(Consts<T> c, const T* __restrict__ w, T scale, T* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * RB + threadIdx.x;
+  if (i >= c.N) return;
+  const int gx = (int)(i % c.nx);
+  const int gy = (int)((i / c.nx) % c.ny);
+  const int gz = (int)(i / ((long long)c.nx * c.ny));
+  const QS<T> q0 = load_qs(c, w, gx, gy, gz);
+  T grho[3], gu[3][3], gp[3], ga[3], gb[3];  // gu[k][j] = d_j u_k
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const QS<T> P = load_qs(c, w, gx + (l == 0), gy + (l == 1), gz + (l == 2));
+    const QS<T> M = load_qs(c, w, gx - (l == 0), gy - (l == 1), gz - (l == 2));
+    const T h = T(0.5) * c.idx[l];
+    grho[l] = (P.rho - M.rho) * h;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gu[k][l] = (P.u[k] - M.u[k]) * h;
+    gp[l] = (P.p - M.p) * h;
+    ga[l] = (P.a - M.a) * h;
+    gb[l] = (P.b - M.b) * h;
+  }
+  const T g = c.gamma;
+  const T div = gu[0][0] + gu[1][1] + gu[2][2];
+  T Mx[5][5];
+  // M1 (halved as printed) minus M2
+  Mx[0][0] = T(0.5) * div;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    Mx[0][1 + j] = T(0.5) * gb[j] - (q0.b / q0.rho) * grho[j];
+    Mx[1 + j][0] = T(0.5) * gb[j];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Mx[1 + k][1 + j] = (j == k ? T(0.5) * div : T(0)) - gu[k][j];
+    Mx[1 + j][4] = T(0.5) * ga[j] - (q0.a / (T(2) * q0.p)) * gp[j];
+    Mx[4][1 + j] = T(0.5) * ga[j] - (T(2) / (g - T(1))) * ga[j];
+    Mx[4][0] = T(0);
+  }
+  Mx[0][4] = -T(0.5) * sqrt(g - T(1)) * div;
+  Mx[4][4] = T(0.5) * div - T(0.5) * (g - T(1)) * div;
+  T A[5][5];
+  T tot = T(0);
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) acc += Mx[k][r] * Mx[k][s];
+      A[r][s] = acc;
+    }
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int s = 0; s < 5; ++s) tot += A[r][s] * A[r][s];
+  for (int sweep = 0; sweep < JacobiTol<T>::sweeps; ++sweep) {
+    T off = T(0);
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+      for (int s = 0; s < 5; ++s)
+        if (r != s) off += A[r][s] * A[r][s];
+    if (off <= JacobiTol<T>::rel * tot) break;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int qq = p + 1; qq < 5; ++qq) jrot(A, p, qq);
+  }
+  T lm = A[0][0];
+#pragma unroll
+  for (int r = 1; r < 5; ++r) lm = fmax(lm, A[r][r]);
+  out[i] = scale * sqrt(fmax(lm, T(0)));
+}
+
+// ------------------------------------------------------------------------------------------
+// Objectives (FP64 accumulation) and their gradients (added in the state precision)
+// ------------------------------------------------------------------------------------------
+// mean pressure: j = (1/N) sum p;  dp/dw = (gamma-1) (|u|^2/2, -u, 1)
+template <typename T>
+__global__ __launch_bounds__(RB) void k_meanp(Consts<T> c, const T* __restrict__ w, double wgt,
+                                              double* __restrict__ partials, T* __restrict__ djdw) {
+  __shared__ double sh[RB];
+  const double g = (double)c.gamma;
+  const long long N = c.N;
+  double v = 0.0;
+  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < N; i += (long long)gridDim.x * RB) {
+    const Q64 q = load_q64(c, w, i, 0, g);
+    v += q.p;
+    if (djdw) {
+      const double f = wgt * (g - 1.0) / (double)N;
+      const double usq = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+      djdw[i] += (T)(f * 0.5 * usq);
+      djdw[N + i] += (T)(-f * q.u[0]);
+      djdw[2 * N + i] += (T)(-f * q.u[1]);
+      djdw[3 * N + i] += (T)(-f * q.u[2]);
+      djdw[4 * N + i] += (T)f;
+    }
+  }
+  if (partials) {
+    const double tot = block_sum(v, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  }
+}
+
+// Central-difference velocity gradient at cell (gx,gy,gz): G[l][k] = d_l u_k
+template <typename T>
+__device__ __forceinline__ void cell_grad_u(const Consts<T>& c, const T* __restrict__ w, int gx, int gy, int gz,
+                                            double G[3][3]) {
+  const double g = (double)c.gamma;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    int mp, mm, rp, rm;
+    const long long ip = box_cell(c.nx, c.ny, c.nz, c.wall, gx + (l == 0), gy + (l == 1), gz + (l == 2), mp, rp);
+    const long long im = box_cell(c.nx, c.ny, c.nz, c.wall, gx - (l == 0), gy - (l == 1), gz - (l == 2), mm, rm);
+    const Q64 P = load_q64(c, w, ip, mp, g), M = load_q64(c, w, im, mm, g);
+    const double h = 0.5 * (double)c.idx[l];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) G[l][k] = (P.u[k] - M.u[k]) * h;
+  }
+}
+
+__device__ __forceinline__ void stress_from(double mu, const double G[3][3], double S[3][3]) {
+  const double div = G[0][0] + G[1][1] + G[2][2];
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) S[l][k] = mu * (G[l][k] + G[k][l]) - (l == k ? (2.0 / 3.0) * mu * div : 0.0);
+}
+
+// viscous dissipation: j = (1/N) sum_cells sigma_lk d_l u_k
+template <typename T>
+__global__ __launch_bounds__(RB) void k_ked(Consts<T> c, const T* __restrict__ w, double* __restrict__ partials) {
+  __shared__ double sh[RB];
+  const double mu = (double)c.mu;
+  double v = 0.0;
+  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < c.N; i += (long long)gridDim.x * RB) {
+    const int gx = (int)(i % c.nx), gy = (int)((i / c.nx) % c.ny), gz = (int)(i / ((long long)c.nx * c.ny));
+    double G[3][3], S[3][3];
+    cell_grad_u(c, w, gx, gy, gz, G);
+    stress_from(mu, G, S);
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v += S[l][k] * G[l][k];
+  }
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// Gradient of the dissipation, gathered at cell (gx,gy,gz) or at its wall ghost image (gxv):
+//   u^_k = (wgt/N) sum_l (sigma_lk(j - e_l) - sigma_lk(j + e_l)) / dx_l  (d Phi/d G_lk = 2 sigma_lk;
+//   sigma of a ghost cell is zero: it owns no dissipation term), then to conservative variables.
+template <typename T>
+__device__ __forceinline__ void ked_gather(const Consts<T>& c, const T* __restrict__ w, int gxv, int gy, int gz,
+                                           double f, double out[5]) {
+  const double mu = (double)c.mu;
+  double uh[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+#pragma unroll
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+      const int x = gxv + sgn * (l == 0), y = gy + sgn * (l == 1), z = gz + sgn * (l == 2);
+      if (c.wall && (x < 0 || x >= c.nx)) continue;
+      double G[3][3], S[3][3];
+      cell_grad_u(c, w, x, y, z, G);
+      stress_from(mu, G, S);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) uh[k] += -sgn * S[l][k] * (double)c.idx[l];
+    }
+  }
+  int mirror, real;
+  const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, gxv, gy, gz, mirror, real);
+  const Q64 q = load_q64(c, w, gi, mirror, (double)c.gamma);
+  const double uu = q.u[0] * uh[0] + q.u[1] * uh[1] + q.u[2] * uh[2];
+  out[0] = -f * q.ri * uu;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[1 + k] = f * q.ri * uh[k];
+  out[4] = 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_ked_grad(Consts<T> c, const T* __restrict__ w, double wgt,
+                                                 T* __restrict__ djdw) {
+  const long long i = (long long)blockIdx.x * RB + threadIdx.x;
+  if (i >= c.N) return;
+  const int gx = (int)(i % c.nx), gy = (int)((i / c.nx) % c.ny), gz = (int)(i / ((long long)c.nx * c.ny));
+  const double f = wgt / (double)c.N;
+  double o[5];
+  ked_gather(c, w, gx, gy, gz, f, o);
+  if (c.wall && (gx == 0 || gx == c.nx - 1)) {
+    double ov[5];
+    ked_gather(c, w, gx == 0 ? -1 : c.nx, gy, gz, f, ov);
+    o[0] += ov[0];
+    o[1] -= ov[1];
+    o[2] += ov[2];
+    o[3] += ov[3];
+    o[4] += ov[4];
+  }
+  const long long N = c.N;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) djdw[v * N + i] += (T)o[v];
+}
+
+// Stagnation-pressure loss on an x-face plane [Eqs. (1)-(3)]: per face (j,k) the face state
+// w_f = (w_L + w_R)/2; num_f = rho (pt_ref - p_t), den_f = rho, p_t = p X^kappa,
+// X = 1 + (gamma-1) rho |u|^2 / (2 gamma p), kappa = gamma/(gamma-1).
+struct PlaneTerms {
+  double num, den;
+  double dnum[5];  // d num / d w_f
+};
+
+__device__ __forceinline__ PlaneTerms plane_terms(double g, double pt_ref, const double wf[5]) {
+  PlaneTerms t;
+  const double r = wf[0], ri = 1.0 / r;
+  const double m[3] = {wf[1], wf[2], wf[3]};
+  const double E = wf[4];
+  const double msq = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+  const double K = 0.5 * msq * ri;  // kinetic energy density
+  const double p = (g - 1.0) * (E - K);
+  const double X = 1.0 + K / (g * (E - K));
+  const double kap = g / (g - 1.0);
+  const double Xk = pow(X, kap);
+  const double pt = p * Xk;
+  t.num = r * (pt_ref - pt);
+  t.den = r;
+  // derivatives of K, p and X with respect to (rho, m, E)
+  const double u[3] = {m[0] * ri, m[1] * ri, m[2] * ri};
+  const double dK[5] = {-K * ri, u[0], u[1], u[2], 0.0};
+  const double dXdK = E / (g * (E - K) * (E - K));
+  const double dXdE = -K / (g * (E - K) * (E - K));
+  const double dXk = kap * pow(X, kap - 1.0);
+  for (int v = 0; v < 5; ++v) {
+    const double dp = (g - 1.0) * ((v == 4 ? 1.0 : 0.0) - dK[v]);
+    const double dX = dXdK * dK[v] + (v == 4 ? dXdE : 0.0);
+    const double dpt = dp * Xk + p * dXk * dX;
+    t.dnum[v] = (v == 0 ? (pt_ref - pt) : 0.0) - r * dpt;
+  }
+  return t;
+}
+
+template <typename T>
+__device__ __forceinline__ void plane_face(const Consts<T>& c, const T* __restrict__ w, int plane_i, long long f,
+                                           long long& il, long long& ir, double wf[5]) {
+  const int j = (int)(f % c.ny), k = (int)(f / c.ny);
+  il = ((long long)k * c.ny + j) * c.nx + (plane_i - 1);
+  ir = il + 1;
+  const long long N = c.N;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) wf[v] = 0.5 * ((double)w[v * N + il] + (double)w[v * N + ir]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_ptloss_partial(Consts<T> c, const T* __restrict__ w, int plane_i,
+                                                       double pt_ref, double* __restrict__ partials) {
+  __shared__ double sh[RB];
+  const long long nf = (long long)c.ny * c.nz;
+  double vn = 0.0, vd = 0.0;
+  for (long long f = (long long)blockIdx.x * RB + threadIdx.x; f < nf; f += (long long)gridDim.x * RB) {
+    long long il, ir;
+    double wf[5];
+    plane_face(c, w, plane_i, f, il, ir, wf);
+    const PlaneTerms t = plane_terms((double)c.gamma, pt_ref, wf);
+    vn += t.num;
+    vd += t.den;
+  }
+  const double tn = block_sum(vn, sh);
+  const double td = block_sum(vd, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = tn;
+    partials[gridDim.x + blockIdx.x] = td;
+  }
+}
+
+// scratch[0] = num, scratch[1] = den (already folded); J_accum += wgt num/(den pt_ref)
+__global__ void k_ptloss_value(const double* __restrict__ scratch, double pt_ref, double wgt, double* J_accum) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *J_accum += wgt * scratch[0] / (scratch[1] * pt_ref);
+}
+
+// dj/dw_L = dj/dw_R = 0.5 (dnum_f - (num/den) dden_f) / (den pt_ref)
+template <typename T>
+__global__ __launch_bounds__(RB) void k_ptloss_grad(Consts<T> c, const T* __restrict__ w, int plane_i,
+                                                    double pt_ref, const double* __restrict__ scratch, double wgt,
+                                                    T* __restrict__ djdw) {
+  const long long f = (long long)blockIdx.x * RB + threadIdx.x;
+  if (f >= (long long)c.ny * c.nz) return;
+  long long il, ir;
+  double wf[5];
+  plane_face(c, w, plane_i, f, il, ir, wf);
+  const PlaneTerms t = plane_terms((double)c.gamma, pt_ref, wf);
+  const double num = scratch[0], den = scratch[1];
+  const double sc = wgt * 0.5 / (den * pt_ref);
+  const long long N = c.N;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double gv = sc * (t.dnum[v] - (v == 0 ? num / den : 0.0));
+    djdw[v * N + il] += (T)gv;
+    djdw[v * N + ir] += (T)gv;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// BF16 codec
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(RB) void k_minmax_partial(Consts<float> c, const float* __restrict__ w,
+                                                       float* __restrict__ partials) {
+  __shared__ float smn[RB], smx[RB];
+  const long long N = c.N;
+  for (int v = 0; v < 5; ++v) {
+    float mn = INFINITY, mx = -INFINITY;
+    for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < N; i += (long long)gridDim.x * RB) {
+      const float x = w[v * N + i];
+      mn = fminf(mn, x);
+      mx = fmaxf(mx, x);
+    }
+    smn[threadIdx.x] = mn;
+    smx[threadIdx.x] = mx;
+    for (int o = RB / 2; o > 0; o >>= 1) {
+      __syncthreads();
+      if (threadIdx.x < o) {
+        smn[threadIdx.x] = fminf(smn[threadIdx.x], smn[threadIdx.x + o]);
+        smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + o]);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      partials[(2 * v) * gridDim.x + blockIdx.x] = smn[0];
+      partials[(2 * v + 1) * gridDim.x + blockIdx.x] = smx[0];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(RB) void k_minmax_fold(const float* __restrict__ partials, int nblk,
+                                                    float* __restrict__ header) {
+  __shared__ float smn[RB], smx[RB];
+  for (int v = 0; v < 5; ++v) {
+    float mn = INFINITY, mx = -INFINITY;
+    for (int i = threadIdx.x; i < nblk; i += RB) {
+      mn = fminf(mn, partials[(2 * v) * nblk + i]);
+      mx = fmaxf(mx, partials[(2 * v + 1) * nblk + i]);
+    }
+    smn[threadIdx.x] = mn;
+    smx[threadIdx.x] = mx;
+    for (int o = RB / 2; o > 0; o >>= 1) {
+      __syncthreads();
+      if (threadIdx.x < o) {
+        smn[threadIdx.x] = fminf(smn[threadIdx.x], smn[threadIdx.x + o]);
+        smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + o]);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const float m = 0.5f * (smx[0] + smn[0]);
+      float s = 0.5f * (smx[0] - smn[0]);
+      if (!(s > 0.0f)) s = 1.0f;
+      header[2 * v] = m;
+      header[2 * v + 1] = s;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(RB) void k_encode(Consts<float> c, const float* __restrict__ w,
+                                               const float* __restrict__ header, uint16_t* __restrict__ codes) {
+  const long long n = 5 * c.N;
+  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
+    const int v = (int)(i / c.N);
+    const float t = __fdiv_rn(w[i] - header[2 * v], header[2 * v + 1]);
+    codes[i] = bf16_rne(t);
+  }
+}
+
+__global__ __launch_bounds__(RB) void k_decode(Consts<float> c, const float* __restrict__ header,
+                                               const uint16_t* __restrict__ codes, float* __restrict__ w) {
+  const long long n = 5 * c.N;
+  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
+    const int v = (int)(i / c.N);
+    w[i] = fmaf(header[2 * v + 1], __uint_as_float((uint32_t)codes[i] << 16), header[2 * v]);
+  }
+}
+
+inline int ew_blocks(long long n) {
+  long long b = (n + RB - 1) / RB;
+  const long long cap = 256 * 64;
+  return (int)(b > cap ? cap : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_sigma1(const Consts<T>& c, const T* w, T scale, T* out, hipStream_t st) {
+  const int nb = (int)((c.N + RB - 1) / RB);
+  hipLaunchKernelGGL((k_sigma1<T>), dim3(nb), dim3(RB), 0, st, c, w, scale, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dot(const Consts<T>& c, const T* a, const T* b, double* partials, double* dst, double alpha,
+                      double beta, hipStream_t st) {
+  const long long n = 5 * c.N;
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL((k_dot_partial<T>), dim3(nb), dim3(RB), 0, st, a, b, n, partials);
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 1, dst, alpha, beta);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_energy_vhat(const Consts<T>& c, const T* w, const T* wh, double* partials, double* dst,
+                              hipStream_t st) {
+  const int nb = reduce_blocks(c.N);
+  hipLaunchKernelGGL((k_energy_partial<T>), dim3(nb), dim3(RB), 0, st, c, w, wh, partials);
+  const double inv_dv = 1.0 / ((double)c.dx[0] * (double)c.dx[1] * (double)c.dx[2]);
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 1, dst, inv_dv, 0.0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt_ref, const T* w, double weight,
+                            double* J_accum, T* djdw, double* partials, double* scratch, hipStream_t st) {
+  if (kind == 1) {
+    const int nb = reduce_blocks(c.N);
+    hipLaunchKernelGGL((k_meanp<T>), dim3(nb), dim3(RB), 0, st, c, w, weight, J_accum ? partials : nullptr, djdw);
+    if (J_accum)
+      hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 1, J_accum, weight / (double)c.N, 1.0);
+  } else if (kind == 2) {
+    if (J_accum) {
+      const int nb = reduce_blocks(c.N);
+      hipLaunchKernelGGL((k_ked<T>), dim3(nb), dim3(RB), 0, st, c, w, partials);
+      hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 1, J_accum, weight / (double)c.N, 1.0);
+    }
+    if (djdw) {
+      const int nb = (int)((c.N + RB - 1) / RB);
+      hipLaunchKernelGGL((k_ked_grad<T>), dim3(nb), dim3(RB), 0, st, c, w, weight, djdw);
+    }
+  } else if (kind == 3) {
+    const long long nf = (long long)c.ny * c.nz;
+    const int nb = reduce_blocks(nf);
+    hipLaunchKernelGGL((k_ptloss_partial<T>), dim3(nb), dim3(RB), 0, st, c, w, plane_i, pt_ref, partials);
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 2, scratch, 1.0, 0.0);
+    if (J_accum) hipLaunchKernelGGL(k_ptloss_value, dim3(1), dim3(64), 0, st, scratch, pt_ref, weight, J_accum);
+    if (djdw) {
+      const int ng = (int)((nf + RB - 1) / RB);
+      hipLaunchKernelGGL((k_ptloss_grad<T>), dim3(ng), dim3(RB), 0, st, c, w, plane_i, pt_ref, scratch, weight, djdw);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ckpt_encode(const Consts<float>& c, const float* w, float* header, uint16_t* codes,
+                              float* partials, hipStream_t st) {
+  const int nb = reduce_blocks(c.N);
+  hipLaunchKernelGGL(k_minmax_partial, dim3(nb), dim3(RB), 0, st, c, w, partials);
+  hipLaunchKernelGGL(k_minmax_fold, dim3(1), dim3(RB), 0, st, partials, nb, header);
+  hipLaunchKernelGGL(k_encode, dim3(ew_blocks(5 * c.N)), dim3(RB), 0, st, c, w, header, codes);
+  return hipGetLastError();
+}
+
+hipError_t launch_ckpt_decode(const Consts<float>& c, const float* header, const uint16_t* codes, float* w,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_decode, dim3(ew_blocks(5 * c.N)), dim3(RB), 0, st, c, header, codes, w);
+  return hipGetLastError();
+}
+
+#define ADJNS_INST(T)                                                                                          \
+  template hipError_t launch_sigma1<T>(const Consts<T>&, const T*, T, T*, hipStream_t);                        \
+  template hipError_t launch_dot<T>(const Consts<T>&, const T*, const T*, double*, double*, double, double,    \
+                                    hipStream_t);                                                              \
+  template hipError_t launch_energy_vhat<T>(const Consts<T>&, const T*, const T*, double*, double*, hipStream_t); \
+  template hipError_t launch_objective<T>(const Consts<T>&, int, int, double, const T*, double, double*, T*,   \
+                                          double*, double*, hipStream_t);
+ADJNS_INST(float)
+ADJNS_INST(double)
+#undef ADJNS_INST
+
+}  // namespace adjns

@@ -1,0 +1,371 @@
+// capi.hip -- the C ABI declared in include/adjns.h: host-side validation, workspace layout and
+// the launch sequences of one primal step and one reverse step.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/adjns.h"
+#include "kernels.hpp"
+
+using namespace adjns;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(ADJ_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+long long ncells(const adj_grid* g) { return (long long)g->n[0] * g->n[1] * g->n[2]; }
+size_t elem(const adj_grid* g) { return g->precision == ADJ_F64 ? sizeof(double) : sizeof(float); }
+
+// Workspace layout (each region 256-byte aligned): five state-sized stage buffers
+// (W2, W3, W4 / g2, g4, g3), one decoded checkpoint, the nu field, reduction partials, scalars.
+struct WsLayout {
+  size_t W2, W3, W4, g4, g3, wdec, nu, partials, scratch, total;
+};
+
+WsLayout layout(const adj_grid* g) {
+  const size_t S = up(5 * (size_t)ncells(g) * elem(g));
+  WsLayout L;
+  L.W2 = 0;
+  L.W3 = L.W2 + S;
+  L.W4 = L.W3 + S;
+  L.g4 = L.W4 + S;
+  L.g3 = L.g4 + S;
+  L.wdec = L.g3 + S;
+  L.nu = L.wdec + S;
+  L.partials = L.nu + up((size_t)ncells(g) * elem(g));
+  L.scratch = L.partials + up((size_t)MAX_PARTIALS * 10 * sizeof(double));
+  L.total = L.scratch + up(64 * sizeof(double));
+  return L;
+}
+
+int check_grid(const adj_grid* g, bool need_dt) {
+  if (!g) return fail(ADJ_EINVAL, "grid is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (g->n[d] < 1) return fail(ADJ_EINVAL, "n[%d] = %d must be >= 1", d, g->n[d]);
+    if (!(g->L[d] > 0.0) || !std::isfinite(g->L[d])) return fail(ADJ_EINVAL, "L[%d] must be positive", d);
+  }
+  if ((g->n[1] + TY - 1) / TY > 65535 || (g->n[2] + TZ - 1) / TZ > 65535)
+    return fail(ADJ_ESHAPE, "grid too large in y or z for the tile launch");
+  if (g->bc_x != ADJ_BC_PERIODIC && g->bc_x != ADJ_BC_SLIP_WALLS) return fail(ADJ_EINVAL, "bad bc_x %d", g->bc_x);
+  if (g->bc_x == ADJ_BC_SLIP_WALLS && g->n[0] < 2) return fail(ADJ_ESHAPE, "slip walls need n[0] >= 2");
+  if (!(g->gamma > 1.0) || !std::isfinite(g->gamma)) return fail(ADJ_EINVAL, "gamma must be > 1");
+  if (!(g->prandtl > 0.0)) return fail(ADJ_EINVAL, "prandtl must be > 0");
+  if (!(g->mu >= 0.0) || !std::isfinite(g->mu)) return fail(ADJ_EINVAL, "mu must be >= 0");
+  if (need_dt && (!(g->dt > 0.0) || !std::isfinite(g->dt))) return fail(ADJ_EINVAL, "dt must be > 0");
+  if (g->precision != ADJ_F64 && g->precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", g->precision);
+  if (g->ckpt_format != ADJ_CKPT_NATIVE && g->ckpt_format != ADJ_CKPT_BF16)
+    return fail(ADJ_EINVAL, "bad ckpt_format %d", g->ckpt_format);
+  if (g->ckpt_format == ADJ_CKPT_BF16 && g->precision != ADJ_F32)
+    return fail(ADJ_EINVAL, "BF16 checkpoints need precision ADJ_F32");
+  return ADJ_OK;
+}
+
+int check_ws(const adj_grid* g, const void* ws, size_t ws_bytes) {
+  if (!ws) return fail(ADJ_EWORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % ALIGN) return fail(ADJ_EWORKSPACE, "workspace must be 256-byte aligned");
+  const size_t need = layout(g).total;
+  if (ws_bytes < need) return fail(ADJ_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  return ADJ_OK;
+}
+
+int check_obj(const adj_grid* g, const adj_objective* o) {
+  if (!o) return ADJ_OK;
+  if (o->kind < ADJ_OBJ_NONE || o->kind > ADJ_OBJ_PT_LOSS_PLANE) return fail(ADJ_EINVAL, "bad objective kind %d", o->kind);
+  if (o->kind == ADJ_OBJ_PT_LOSS_PLANE) {
+    if (o->plane_i < 1 || o->plane_i > g->n[0] - 1)
+      return fail(ADJ_ESHAPE, "plane_i = %d outside [1, n[0]-1]", o->plane_i);
+    if (!(o->pt_ref > 0.0)) return fail(ADJ_EINVAL, "pt_ref must be > 0");
+  }
+  return ADJ_OK;
+}
+
+template <typename T>
+Consts<T> consts(const adj_grid* g) {
+  Consts<T> c;
+  c.nx = g->n[0];
+  c.ny = g->n[1];
+  c.nz = g->n[2];
+  c.wall = g->bc_x == ADJ_BC_SLIP_WALLS;
+  c.N = ncells(g);
+  for (int d = 0; d < 3; ++d) {
+    const double h = g->L[d] / g->n[d];
+    c.dx[d] = (T)h;
+    c.idx[d] = (T)(1.0 / h);
+  }
+  c.gamma = (T)g->gamma;
+  c.mu = (T)g->mu;
+  c.alpha = (T)(g->gamma * g->mu / g->prandtl);
+  c.dt = (T)g->dt;
+  return c;
+}
+
+inline char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+template <typename T>
+int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, void* ws, hipStream_t st) {
+  const Consts<T> c = consts<T>(g);
+  const WsLayout L = layout(g);
+  T* W2 = (T*)at(ws, L.W2);
+  T* W3 = (T*)at(ws, L.W3);
+  T* W4 = (T*)at(ws, L.W4);
+  const T h = c.dt * T(0.5);
+  hipError_t e;
+  if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st))) return hip_fail(e, "primal stage 1");
+  if ((e = launch_primal_stage<T>(STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st))) return hip_fail(e, "primal stage 2");
+  if ((e = launch_primal_stage<T>(STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st))) return hip_fail(e, "primal stage 3");
+  if ((e = launch_primal_stage<T>(STAGE_FIN, c, W4, wn, s, W2, W3, T(0), out, st))) return hip_fail(e, "primal stage 4");
+  if (ckpt) {
+    if constexpr (sizeof(T) == sizeof(float)) {
+      float* hdr = (float*)ckpt;
+      uint16_t* codes = (uint16_t*)at(ckpt, 64);
+      if ((e = launch_ckpt_encode(c, (const float*)out, hdr, codes, (float*)at(ws, L.partials), st)))
+        return hip_fail(e, "checkpoint encode");
+    }
+  }
+  return ADJ_OK;
+}
+
+template <typename T>
+int adjoint_step(const adj_grid* g, const void* wn_in, const T* s, const T* a, double lambda, const adj_objective* o,
+                 double c_n, T* wh, T* grad_s, void* ws, hipStream_t st) {
+  const Consts<T> c = consts<T>(g);
+  const WsLayout L = layout(g);
+  T* W2 = (T*)at(ws, L.W2);
+  T* W3 = (T*)at(ws, L.W3);
+  T* W4 = (T*)at(ws, L.W4);
+  T* g4 = (T*)at(ws, L.g4);
+  T* g3 = (T*)at(ws, L.g3);
+  T* g2 = W4;  // W4 is dead once the stage-4 gather has run
+  T* nu = (T*)at(ws, L.nu);
+  hipError_t e;
+  const T* wn = (const T*)wn_in;
+  if (g->ckpt_format == ADJ_CKPT_BF16) {
+    if constexpr (sizeof(T) == sizeof(float)) {
+      float* dec = (float*)at(ws, L.wdec);
+      if ((e = launch_ckpt_decode(c, (const float*)wn_in, (const uint16_t*)((const char*)wn_in + 64), dec, st)))
+        return hip_fail(e, "checkpoint decode");
+      wn = (const T*)dec;
+    }
+  }
+  // forward recompute of the stage states
+  const T h = c.dt * T(0.5);
+  if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st))) return hip_fail(e, "recompute W2");
+  if ((e = launch_primal_stage<T>(STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st))) return hip_fail(e, "recompute W3");
+  if ((e = launch_primal_stage<T>(STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st))) return hip_fail(e, "recompute W4");
+  const T* nup = nullptr;
+  if (lambda > 0.0) {
+    if ((e = launch_sigma1<T>(c, wn, (T)lambda, nu, st))) return hip_fail(e, "sigma_1");
+    nup = nu;
+  }
+  const T dt = c.dt;
+  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, W4, a, nullptr, nup, dt / T(6), T(0), nullptr, nullptr, g4, nullptr, st)))
+    return hip_fail(e, "adjoint stage 4");
+  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, W3, a, g4, nup, dt / T(3), dt, nullptr, nullptr, g3, nullptr, st)))
+    return hip_fail(e, "adjoint stage 3");
+  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, W2, a, g3, nup, dt / T(3), dt * T(0.5), nullptr, nullptr, g2, nullptr, st)))
+    return hip_fail(e, "adjoint stage 2");
+  if ((e = launch_adjoint_stage<T>(STAGE_FIN, c, wn, a, g2, nup, dt / T(6), dt * T(0.5), g3, g4, wh, grad_s, st)))
+    return hip_fail(e, "adjoint stage 1");
+  if (o && o->kind != ADJ_OBJ_NONE && c_n != 0.0) {
+    if ((e = launch_objective<T>(c, o->kind, o->plane_i, o->pt_ref, wn, c_n, nullptr, wh,
+                                 (double*)at(ws, L.partials), (double*)at(ws, L.scratch), st)))
+      return hip_fail(e, "objective gradient");
+  }
+  return ADJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t adj_workspace_bytes(const adj_grid* grid) {
+  if (check_grid(grid, false)) return 0;
+  return layout(grid).total;
+}
+
+size_t adj_ckpt_bytes(const adj_grid* grid) {
+  if (check_grid(grid, false)) return 0;
+  return 64 + 5 * (size_t)ncells(grid) * sizeof(uint16_t);
+}
+
+int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out, void* ws,
+                    size_t ws_bytes, void* stream) {
+  int r;
+  if ((r = check_grid(grid, true))) return r;
+  if ((r = check_ws(grid, ws, ws_bytes))) return r;
+  if (!w_n || !w_np1) return fail(ADJ_EINVAL, "w_n and w_np1 must be non-NULL");
+  if (w_n == w_np1) return fail(ADJ_EINVAL, "w_np1 must not alias w_n");
+  if (ckpt_out && grid->precision != ADJ_F32) return fail(ADJ_EINVAL, "BF16 checkpoints need precision ADJ_F32");
+  hipStream_t st = (hipStream_t)stream;
+  if (grid->precision == ADJ_F64)
+    return primal_step<double>(grid, (const double*)w_n, (const double*)s, (double*)w_np1, nullptr, ws, st);
+  return primal_step<float>(grid, (const float*)w_n, (const float*)s, (float*)w_np1, ckpt_out, ws, st);
+}
+
+int adj_adjoint_step(const adj_grid* grid, const void* w_n, const void* s, const void* wh_np1, double lambda,
+                     const adj_objective* obj, double c_n, void* wh_n, void* grad_s, void* ws, size_t ws_bytes,
+                     void* stream) {
+  int r;
+  if ((r = check_grid(grid, true))) return r;
+  if ((r = check_ws(grid, ws, ws_bytes))) return r;
+  if ((r = check_obj(grid, obj))) return r;
+  if (!w_n || !wh_np1 || !wh_n) return fail(ADJ_EINVAL, "w_n, wh_np1 and wh_n must be non-NULL");
+  if (wh_n == wh_np1) return fail(ADJ_EINVAL, "wh_n must not alias wh_np1");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(ADJ_EINVAL, "lambda must be finite and >= 0");
+  if (!std::isfinite(c_n)) return fail(ADJ_EINVAL, "c_n must be finite");
+  hipStream_t st = (hipStream_t)stream;
+  if (grid->precision == ADJ_F64)
+    return adjoint_step<double>(grid, w_n, (const double*)s, (const double*)wh_np1, lambda, obj, c_n, (double*)wh_n,
+                                (double*)grad_s, ws, st);
+  return adjoint_step<float>(grid, w_n, (const float*)s, (const float*)wh_np1, lambda, obj, c_n, (float*)wh_n,
+                             (float*)grad_s, ws, st);
+}
+
+int adj_growth_sigma1(const adj_grid* grid, const void* w, double scale, void* out, void* stream) {
+  int r;
+  if ((r = check_grid(grid, false))) return r;
+  if (!w || !out) return fail(ADJ_EINVAL, "w and out must be non-NULL");
+  if (!std::isfinite(scale)) return fail(ADJ_EINVAL, "scale must be finite");
+  hipError_t e;
+  hipStream_t st = (hipStream_t)stream;
+  if (grid->precision == ADJ_F64)
+    e = launch_sigma1<double>(consts<double>(grid), (const double*)w, scale, (double*)out, st);
+  else
+    e = launch_sigma1<float>(consts<float>(grid), (const float*)w, (float)scale, (float*)out, st);
+  return e ? hip_fail(e, "sigma_1") : ADJ_OK;
+}
+
+int adj_objective_and_grad(const adj_grid* grid, const adj_objective* obj, const void* w, double weight,
+                           double* J_accum, void* djdw, void* ws, size_t ws_bytes, void* stream) {
+  int r;
+  if ((r = check_grid(grid, false))) return r;
+  if (!obj) return fail(ADJ_EINVAL, "objective is NULL");
+  if ((r = check_obj(grid, obj))) return r;
+  if ((r = check_ws(grid, ws, ws_bytes))) return r;
+  if (!w) return fail(ADJ_EINVAL, "w must be non-NULL");
+  if (!std::isfinite(weight)) return fail(ADJ_EINVAL, "weight must be finite");
+  if (obj->kind == ADJ_OBJ_NONE) return ADJ_OK;
+  const WsLayout L = layout(grid);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (grid->precision == ADJ_F64)
+    e = launch_objective<double>(consts<double>(grid), obj->kind, obj->plane_i, obj->pt_ref, (const double*)w, weight,
+                                 J_accum, (double*)djdw, (double*)at(ws, L.partials), (double*)at(ws, L.scratch), st);
+  else
+    e = launch_objective<float>(consts<float>(grid), obj->kind, obj->plane_i, obj->pt_ref, (const float*)w, weight,
+                                J_accum, (float*)djdw, (double*)at(ws, L.partials), (double*)at(ws, L.scratch), st);
+  return e ? hip_fail(e, "objective") : ADJ_OK;
+}
+
+int adj_energy_vhat(const adj_grid* grid, const void* w, const void* wh, double* E, void* ws, size_t ws_bytes,
+                    void* stream) {
+  int r;
+  if ((r = check_grid(grid, false))) return r;
+  if ((r = check_ws(grid, ws, ws_bytes))) return r;
+  if (!w || !wh || !E) return fail(ADJ_EINVAL, "w, wh and E must be non-NULL");
+  const WsLayout L = layout(grid);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (grid->precision == ADJ_F64)
+    e = launch_energy_vhat<double>(consts<double>(grid), (const double*)w, (const double*)wh, (double*)at(ws, L.partials), E, st);
+  else
+    e = launch_energy_vhat<float>(consts<float>(grid), (const float*)w, (const float*)wh, (double*)at(ws, L.partials), E, st);
+  return e ? hip_fail(e, "energy") : ADJ_OK;
+}
+
+int adj_dot(const adj_grid* grid, const void* a, const void* b, double* out, void* ws, size_t ws_bytes, void* stream) {
+  int r;
+  if ((r = check_grid(grid, false))) return r;
+  if ((r = check_ws(grid, ws, ws_bytes))) return r;
+  if (!a || !b || !out) return fail(ADJ_EINVAL, "a, b and out must be non-NULL");
+  const WsLayout L = layout(grid);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (grid->precision == ADJ_F64)
+    e = launch_dot<double>(consts<double>(grid), (const double*)a, (const double*)b, (double*)at(ws, L.partials), out, 1.0, 0.0, st);
+  else
+    e = launch_dot<float>(consts<float>(grid), (const float*)a, (const float*)b, (double*)at(ws, L.partials), out, 1.0, 0.0, st);
+  return e ? hip_fail(e, "dot") : ADJ_OK;
+}
+
+int adj_ckpt_encode(const adj_grid* grid, const float* w, void* ckpt, void* ws, size_t ws_bytes, void* stream) {
+  int r;
+  if ((r = check_grid(grid, false))) return r;
+  if (grid->precision != ADJ_F32) return fail(ADJ_EINVAL, "BF16 checkpoints need precision ADJ_F32");
+  if ((r = check_ws(grid, ws, ws_bytes))) return r;
+  if (!w || !ckpt) return fail(ADJ_EINVAL, "w and ckpt must be non-NULL");
+  if ((uintptr_t)ckpt % 64) return fail(ADJ_EINVAL, "ckpt must be 64-byte aligned");
+  const WsLayout L = layout(grid);
+  hipError_t e = launch_ckpt_encode(consts<float>(grid), w, (float*)ckpt, (uint16_t*)at(ckpt, 64),
+                                    (float*)at(ws, L.partials), (hipStream_t)stream);
+  return e ? hip_fail(e, "encode") : ADJ_OK;
+}
+
+int adj_ckpt_decode(const adj_grid* grid, const void* ckpt, float* w, void* stream) {
+  int r;
+  if ((r = check_grid(grid, false))) return r;
+  if (grid->precision != ADJ_F32) return fail(ADJ_EINVAL, "BF16 checkpoints need precision ADJ_F32");
+  if (!w || !ckpt) return fail(ADJ_EINVAL, "w and ckpt must be non-NULL");
+  if ((uintptr_t)ckpt % 64) return fail(ADJ_EINVAL, "ckpt must be 64-byte aligned");
+  hipError_t e = launch_ckpt_decode(consts<float>(grid), (const float*)ckpt,
+                                    (const uint16_t*)((const char*)ckpt + 64), w, (hipStream_t)stream);
+  return e ? hip_fail(e, "decode") : ADJ_OK;
+}
+
+int adj_residual(const adj_grid* grid, const void* w, const void* s, void* R, void* stream) {
+  int r;
+  if ((r = check_grid(grid, false))) return r;
+  if (!w || !R) return fail(ADJ_EINVAL, "w and R must be non-NULL");
+  if (w == R) return fail(ADJ_EINVAL, "R must not alias w");
+  hipError_t e;
+  hipStream_t st = (hipStream_t)stream;
+  if (grid->precision == ADJ_F64)
+    e = launch_primal_stage<double>(STAGE_RES, consts<double>(grid), (const double*)w, nullptr, (const double*)s,
+                                    nullptr, nullptr, 0.0, (double*)R, st);
+  else
+    e = launch_primal_stage<float>(STAGE_RES, consts<float>(grid), (const float*)w, nullptr, (const float*)s, nullptr,
+                                   nullptr, 0.0f, (float*)R, st);
+  return e ? hip_fail(e, "residual") : ADJ_OK;
+}
+
+int adj_vjp(const adj_grid* grid, const void* W, const void* kh, const void* nu, void* out, void* stream) {
+  int r;
+  if ((r = check_grid(grid, false))) return r;
+  if (!W || !kh || !out) return fail(ADJ_EINVAL, "W, kh and out must be non-NULL");
+  if (out == kh || out == W) return fail(ADJ_EINVAL, "out must not alias its inputs");
+  hipError_t e;
+  hipStream_t st = (hipStream_t)stream;
+  if (grid->precision == ADJ_F64)
+    e = launch_adjoint_stage<double>(STAGE_VJP, consts<double>(grid), (const double*)W, (const double*)kh, nullptr,
+                                     (const double*)nu, 1.0, 0.0, nullptr, nullptr, (double*)out, nullptr, st);
+  else
+    e = launch_adjoint_stage<float>(STAGE_VJP, consts<float>(grid), (const float*)W, (const float*)kh, nullptr,
+                                    (const float*)nu, 1.0f, 0.0f, nullptr, nullptr, (float*)out, nullptr, st);
+  return e ? hip_fail(e, "vjp") : ADJ_OK;
+}
+
+const char* adj_last_error(void) { return g_err.c_str(); }
+
+const char* adj_version(void) { return "adjns 0.1 gfx950"; }
+
+}  // extern "C"

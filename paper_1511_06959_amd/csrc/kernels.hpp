@@ -1,0 +1,41 @@
+// kernels.hpp -- launchers of the gfx950 kernels (host-side declarations).
+#pragma once
+#include "common.hpp"
+
+namespace adjns {
+
+enum { STAGE_RES = 0, STAGE_LIN = 1, STAGE_FIN = 2 };  // primal stage modes
+enum { STAGE_VJP = 0 };                                  // adjoint stage modes (STAGE_FIN shared)
+
+template <typename T>
+hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
+                               const T* W3, T cR, T* out, hipStream_t st);
+
+template <typename T>
+hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,
+                                T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st);
+
+// out[c] = scale * sigma_1(w) at every cell
+template <typename T>
+hipError_t launch_sigma1(const Consts<T>& c, const T* w, T scale, T* out, hipStream_t st);
+
+// Reductions write FP64 per-block partials to `partials` and a single-block pass folds them in a
+// fixed order:  *dst = beta * (*dst) + alpha * sum   (beta 0 overwrites, 1 accumulates).
+template <typename T>
+hipError_t launch_dot(const Consts<T>& c, const T* a, const T* b, double* partials, double* dst, double alpha,
+                      double beta, hipStream_t st);
+template <typename T>
+hipError_t launch_energy_vhat(const Consts<T>& c, const T* w, const T* wh, double* partials, double* dst,
+                              hipStream_t st);
+// objective kinds follow adjns.h; scratch holds 4 doubles of intermediate plane sums
+template <typename T>
+hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt_ref, const T* w, double weight,
+                            double* J_accum, T* djdw, double* partials, double* scratch, hipStream_t st);
+
+// BF16 checkpoint codec; header = 10 floats (mean, scale) x 5 at the start of the record
+hipError_t launch_ckpt_encode(const Consts<float>& c, const float* w, float* header, uint16_t* codes,
+                              float* partials, hipStream_t st);
+hipError_t launch_ckpt_decode(const Consts<float>& c, const float* header, const uint16_t* codes, float* w,
+                              hipStream_t st);
+
+}  // namespace adjns

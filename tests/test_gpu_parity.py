@@ -1,0 +1,180 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle, element by element.
+
+Tolerances (FP64 path): a single operator or step on identical inputs agrees to 1e-13 of the
+largest oracle value (the only differences are summation order); a whole 50-step window agrees
+to 1e-10 (the target of the FP64 path).  FP32 operators agree to 1e-5 of the largest value.
+Grids are ragged with respect to the 16x4x4 tile so that every tile shape, halo wrap and wall
+mirror is exercised.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1511_06959_amd as adj
+import workloads as W
+from tests.gpu_helpers import dev, grids, host, relerr, smooth_state
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [((19, 6, 9), 0), ((19, 6, 9), 1), ((4, 4, 4), 0), ((33, 5, 1), 0), ((7, 1, 3), 1)]
+IDS = ["19x6x9-periodic", "19x6x9-walls", "4x4x4", "33x5x1", "7x1x3-walls"]
+
+
+def _setup(orc, shape, bc_x, precision=adj.F64, seed=0):
+    L = (2.0, 1.3, 1.7)
+    g, og = grids(orc, shape, L, mu=0.02, dt=0.004, bc_x=bc_x, precision=precision)
+    w = smooth_state(shape, L, seed=seed)
+    return g, og, w
+
+
+@pytest.mark.parametrize("shape,bc_x", SHAPES, ids=IDS)
+def test_residual_parity_f64(orc, shape, bc_x):
+    g, og, w = _setup(orc, shape, bc_x)
+    s = 1e-2 * np.random.default_rng(1).standard_normal(w.size)
+    R = torch.empty(w.size, dtype=torch.float64, device="cuda")
+    adj.residual(g, dev(w), dev(s), R)
+    assert relerr(host(R), orc.residual(og, w, s)) <= 1e-13
+
+
+@pytest.mark.parametrize("shape,bc_x", SHAPES, ids=IDS)
+@pytest.mark.parametrize("with_nu", [False, True], ids=["plain", "lnu"])
+def test_vjp_parity_f64(orc, shape, bc_x, with_nu):
+    g, og, w = _setup(orc, shape, bc_x)
+    rng = np.random.default_rng(2)
+    kh = rng.standard_normal(w.size)
+    nu = np.abs(rng.standard_normal(w.size // 5)) * 1e-2 if with_nu else None
+    out = torch.empty(w.size, dtype=torch.float64, device="cuda")
+    adj.vjp(g, dev(w), dev(kh), out, dev(nu) if with_nu else None)
+    ref = orc.vjp(og, w, kh)
+    if with_nu:
+        ref = ref + orc.lnu_apply(og, nu, kh)
+    assert relerr(host(out), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("shape,bc_x", SHAPES, ids=IDS)
+def test_primal_step_parity_f64(orc, shape, bc_x):
+    g, og, w = _setup(orc, shape, bc_x)
+    s = 1e-2 * np.random.default_rng(3).standard_normal(w.size)
+    ws = adj.workspace(g)
+    out = torch.empty(w.size, dtype=torch.float64, device="cuda")
+    adj.primal_step(g, dev(w), dev(s), out, ws)
+    ref = orc.primal_step(og, w, s)
+    # compare the increment, which is what the step computes on top of w
+    assert relerr(host(out) - w, ref - w) <= 1e-12
+
+
+OBJS = [(W.OBJ_NONE, 0), (W.OBJ_MEAN_PRESSURE, 0), (W.OBJ_KE_DISSIPATION, 0), (W.OBJ_PT_LOSS_PLANE, 0),
+        (W.OBJ_KE_DISSIPATION, 1), (W.OBJ_PT_LOSS_PLANE, 1)]
+
+
+@pytest.mark.parametrize("kind,bc_x", OBJS, ids=["none", "meanp", "ked", "ptloss", "ked-walls", "ptloss-walls"])
+@pytest.mark.parametrize("lam", [0.0, 3e-3], ids=["lam0", "lam"])
+def test_adjoint_step_parity_f64(orc, kind, bc_x, lam):
+    shape = (19, 6, 9)
+    g, og, w = _setup(orc, shape, bc_x, seed=4)
+    rng = np.random.default_rng(5)
+    s = 1e-2 * rng.standard_normal(w.size)
+    a = rng.standard_normal(w.size)
+    gs0 = rng.standard_normal(w.size)
+    obj = adj.Objective.make(kind, 7, 1.1)
+    oobj = orc.make_obj(kind, 7, 1.1)
+    ws = adj.workspace(g)
+    wh = torch.empty(w.size, dtype=torch.float64, device="cuda")
+    gs = dev(gs0)
+    adj.adjoint_step(g, dev(w), dev(s), dev(a), wh, ws, lam=lam, obj=obj, c_n=0.37, grad_s=gs)
+    gref = gs0.copy()
+    ref = orc.adjoint_step(og, w, s, a, lam, oobj, 0.37, gref)
+    assert relerr(host(wh) - a, ref - a) <= 1e-12
+    assert relerr(host(gs) - gs0, gref - gs0) <= 1e-12
+
+
+@pytest.mark.parametrize("shape,bc_x", SHAPES, ids=IDS)
+def test_sigma1_parity_f64(orc, shape, bc_x):
+    g, og, w = _setup(orc, shape, bc_x, seed=6)
+    out = torch.empty(w.size // 5, dtype=torch.float64, device="cuda")
+    adj.growth_sigma1(g, dev(w), out, scale=2.0)
+    assert relerr(host(out), 2.0 * orc.sigma1(og, w)) <= 1e-12
+
+
+@pytest.mark.parametrize("kind,bc_x", OBJS[1:], ids=["meanp", "ked", "ptloss", "ked-walls", "ptloss-walls"])
+def test_objective_parity_f64(orc, kind, bc_x):
+    g, og, w = _setup(orc, (19, 6, 9), bc_x, seed=7)
+    obj = adj.Objective.make(kind, 5, 1.2)
+    ws = adj.workspace(g)
+    J = torch.full((1,), 0.25, dtype=torch.float64, device="cuda")
+    jr, djr = orc.objective(og, orc.make_obj(kind, 5, 1.2), w)
+    # the gradient is accumulated (+=) onto an existing field of the gradient's own magnitude
+    base = np.random.default_rng(8).standard_normal(w.size) * np.abs(djr).max()
+    dj = dev(base)
+    adj.objective_and_grad(g, obj, dev(w), ws, weight=0.5, J_accum=J, djdw=dj)
+    assert abs(host(J)[0] - (0.25 + 0.5 * jr)) <= 1e-13 * abs(0.25 + 0.5 * jr)
+    assert relerr(host(dj) - base, 0.5 * djr) <= 1e-12
+
+
+def test_energy_and_dot_parity(orc):
+    g, og, w = _setup(orc, (19, 6, 9), 0, seed=9)
+    rng = np.random.default_rng(10)
+    wh = rng.standard_normal(w.size)
+    ws = adj.workspace(g)
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    adj.energy_vhat(g, dev(w), dev(wh), E, ws)
+    Er, _ = orc.energy_vhat(og, w, wh)
+    assert abs(host(E)[0] - Er) <= 1e-13 * Er
+    b = rng.standard_normal(w.size)
+    d = torch.zeros(1, dtype=torch.float64, device="cuda")
+    adj.dot(g, dev(wh), dev(b), d, ws)
+    assert abs(host(d)[0] - float(wh @ b)) <= 1e-12 * np.abs(wh * b).sum()
+
+
+def test_codec_bitwise(orc):
+    shape = (19, 6, 9)
+    g = adj.Grid.make(shape, (1, 1, 1), 0.01, 0.01, precision=adj.F32, ckpt_format=adj.CKPT_BF16)
+    w = smooth_state(shape, seed=11).astype(np.float32)
+    ws = adj.workspace(g)
+    rec = torch.zeros(adj.ckpt_bytes(g), dtype=torch.uint8, device="cuda")
+    adj.ckpt_encode(g, dev(w, torch.float32), rec, ws)
+    torch.cuda.synchronize()
+    raw = rec.cpu().numpy()
+    hdr = raw[:40].view(np.float32)
+    codes = raw[64:].view(np.uint16)
+    q, ms = orc.ckpt_encode(w)
+    assert np.array_equal(hdr, ms)
+    assert np.array_equal(codes, q)
+    out = torch.empty(w.size, dtype=torch.float32, device="cuda")
+    adj.ckpt_decode(g, rec, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), orc.ckpt_decode(q, ms))
+
+
+def test_adjoint_step_deterministic():
+    shape = (19, 6, 9)
+    g = adj.Grid.make(shape, (2.0, 1.3, 1.7), 0.02, 0.004)
+    w = dev(smooth_state(shape, seed=12))
+    a = dev(np.random.default_rng(13).standard_normal(w.numel()))
+    ws = adj.workspace(g)
+    outs = []
+    for _ in range(2):
+        wh = torch.empty_like(w)
+        gs = torch.zeros_like(w)
+        adj.adjoint_step(g, w, None, a, wh, ws, lam=2e-3, obj=adj.Objective.make(W.OBJ_KE_DISSIPATION), c_n=0.3,
+                         grad_s=gs)
+        E = torch.zeros(1, dtype=torch.float64, device="cuda")
+        adj.energy_vhat(g, w, wh, E, ws)
+        outs.append((host(wh), host(gs), host(E)))
+    for x, y in zip(outs[0], outs[1]):
+        assert np.array_equal(x, y)
+
+
+def test_fp32_operators(orc):
+    shape = (19, 6, 9)
+    g, og, w = _setup(orc, shape, 0, precision=adj.F32, seed=14)
+    w32 = w.astype(np.float32).astype(np.float64)
+    kh = np.random.default_rng(15).standard_normal(w.size).astype(np.float32).astype(np.float64)
+    R = torch.empty(w.size, dtype=torch.float32, device="cuda")
+    adj.residual(g, dev(w32, torch.float32), None, R)
+    assert relerr(host(R), orc.residual(og, w32)) <= 1e-5
+    out = torch.empty(w.size, dtype=torch.float32, device="cuda")
+    adj.vjp(g, dev(w32, torch.float32), dev(kh, torch.float32), out)
+    assert relerr(host(out), orc.vjp(og, w32, kh)) <= 1e-5
