@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Throughput of the stabilised discrete unsteady adjoint on one MI355X.
+
+Workload (the GPU configuration of the plain method, FP32 and FP64): 64^3 periodic Taylor-Green
+vortex, Mach 0.1, Re 1600, 1000 RK4 steps forward storing every state in HBM, then the full
+reverse sweep (stage recomputation, transposed convective + viscous operator, objective
+injection, body-force sensitivity), lambda = 0; objective = time-averaged volume-mean viscous
+dissipation; gradient with respect to a 5 x 64^3 body-force field (seeded N(0, 1e-4^2), zero
+mean).  Synthetic data (seeded), inputs resident in HBM before the timed region.
+
+One benchmark step = one whole window (forward sweep + reverse sweep).  `value` is the
+whole-job rate in adjoint cell-steps per second: cells x window steps / seconds per window, on
+the FP32 path.  The FP64 path is timed the same way and reported beside it, together with the
+FP32-vs-FP64 relative error of J, dJ/dw_0 and dJ/ds (the FP64 path matches the FP64 oracle to
+1e-10 in the test suite).
+
+Roofline: the dominant kernel is the reverse-stage gather.  Its average launch duration is
+measured with HIP events recorded on its own stream around every launch in the timed region;
+`achieved` = algorithmic bytes per launch / that duration, against 8 TB/s.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "adjoint cell-steps/s + % HBM roofline, FP32/BF16-ckpt vs FP64 at stated rel err"
+
+# Algorithmic values moved per cell by the four reverse-stage launches of one adjoint step
+# (stage 4: W, a in, g4 out = 15; stages 3 and 2: W, a, g_next in, g out = 20 each;
+# stage 1: W, a, g2, g3, g4 in, w^_n out, grad_s read+write = 40), i.e. 95 values per
+# adjoint cell-step, 23.75 per launch and cell.
+VALUES_PER_STAGE_LAUNCH = 95.0 / 4.0
+
+
+def traffic_from_profiles(kernel_src_hash, precision):
+    """HBM bytes per cell and launch of the reverse-stage kernel from the committed rocprofv3
+    counter summary, or None when it was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_adjoint_stage_tgv64.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_src_hash:
+        return None
+    key = f"bytes_per_cell_launch_{precision}"
+    return float(vals[key]) if key in vals else None
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for name in ("stencil.hip", "common.hpp", "kernels.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1511_06959_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def run_gpu(wl, precision, steps, warmup):
+    import torch
+
+    import paper_1511_06959_amd as adj
+    from paper_1511_06959_amd import sweep
+
+    dt = torch.float64 if precision == adj.F64 else torch.float32
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision)
+    obj = adj.Objective.make(wl.obj_kind)
+    w0 = torch.from_numpy(wl.w0).to("cuda", dt)
+    s = torch.from_numpy(wl.s).to("cuda", dt)
+    ws = adj.workspace(g)
+    traj = sweep.Trajectory(g, wl.nsteps)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gs = torch.zeros(5 * g.ncells, dtype=dt, device="cuda")
+    out = {}
+
+    def window(ev=None):
+        J.zero_()
+        gs.zero_()
+        sweep.forward(g, w0, s, wl.nsteps, obj, wl.weights, ws, traj=traj, J=J)
+        if ev is not None:
+            ev.record()
+        wh0, _, _ = sweep.backward(g, traj, s, obj, wl.weights, 0.0, ws, grad_s=gs)
+        return wh0
+
+    for _ in range(warmup):
+        window()
+    adj.profile_enable(True)  # one profiled window grows the event pool outside the timed region
+    window()
+    torch.cuda.synchronize()
+    adj.profile_enable(True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    mids = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wh0 = None
+    for k in range(steps):
+        starts[k].record()
+        wh0 = window(mids[k])
+        ends[k].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    adj.profile_enable(False)
+    fwd = sum(starts[k].elapsed_time(mids[k]) for k in range(steps)) / steps
+    bwd = sum(mids[k].elapsed_time(ends[k]) for k in range(steps)) / steps
+    prof = {}
+    for name, cls in (("adjoint_stage", adj.PROF_ADJOINT_STAGE), ("primal_stage", adj.PROF_PRIMAL_STAGE),
+                      ("objective", adj.PROF_OBJECTIVE), ("sigma1", adj.PROF_SIGMA1), ("codec", adj.PROF_CODEC),
+                      ("reduce", adj.PROF_REDUCE)):
+        ms, n = adj.profile_read(cls)
+        prof[name] = (ms, n)
+    cells = g.ncells
+    out["ms_per_step"] = wall * 1e3 / steps
+    out["fwd_ms"] = fwd
+    out["bwd_ms"] = bwd
+    out["value"] = cells * wl.nsteps / (out["ms_per_step"] / 1e3)
+    out["adjoint_sweep_cell_steps_per_s"] = cells * wl.nsteps / (bwd / 1e3)
+    out["primal_cell_steps_per_s"] = cells * wl.nsteps / (fwd / 1e3)
+    out["prof"] = prof
+    esz = 8 if precision == adj.F64 else 4
+    ms, n = prof["adjoint_stage"]
+    avg_s = ms / n / 1e3
+    alg_bytes = VALUES_PER_STAGE_LAUNCH * esz * cells
+    out["stage_avg_us"] = avg_s * 1e6
+    out["stage_alg_bytes"] = alg_bytes
+    out["stage_achieved_gbs"] = alg_bytes / avg_s / 1e9
+    out["J"] = float(J.cpu()[0])
+    out["wh0"] = wh0.double().cpu().numpy()
+    out["grad_s"] = gs.double().cpu().numpy()
+    del traj, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(wl, budget_s):
+    """The FP64 oracle as it stands, on the host cores: whole primal + reverse steps of the
+    same 64^3 field, repeated until about budget_s seconds have been spent."""
+    import oracle
+
+    og = oracle.grid_from(wl.params())
+    obj = oracle.make_obj(wl.obj_kind)
+    w = wl.w0
+    a = np.random.default_rng(0).standard_normal(w.size) * 1e-3
+    gs = np.zeros_like(w)
+    nsteps = 0
+    t_pr = t_ad = 0.0
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        wn = oracle.primal_step(og, w, wl.s)
+        t1 = time.perf_counter()
+        a = oracle.adjoint_step(og, w, wl.s, a, 0.0, obj, 1.0 / wl.nsteps, gs)
+        t2 = time.perf_counter()
+        t_pr += t1 - t0
+        t_ad += t2 - t1
+        w = wn
+        nsteps += 1
+        if time.perf_counter() - t_start >= budget_s:
+            break
+    cells = wl.ncells
+    return {
+        "value": cells * nsteps / (t_pr + t_ad),
+        "unit": "cell-steps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"{nsteps} primal RK4 step(s) + {nsteps} reverse step(s) of the 64^3 Taylor-Green field "
+                   f"(FP64, OpenMP), {t_pr + t_ad:.1f} s; rate = cells x steps / (primal + reverse time), "
+                   f"the same per-step definition as value"),
+        "primal_cell_steps_per_s": cells * nsteps / t_pr,
+        "adjoint_cell_steps_per_s": cells * nsteps / t_ad,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed windows")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed windows before the timed ones")
+    ap.add_argument("--window", type=int, default=1000, help="RK4 steps per window")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
+              "design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1511_06959_amd as adj
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    adj.lib()
+    wl = W.tgv_64(nsteps=args.window)
+    print(f"[bench] workload {wl.name}: {wl.n} cells, {wl.nsteps} steps, dt {wl.dt:.4e}", file=sys.stderr, flush=True)
+    r32 = run_gpu(wl, adj.F32, args.steps, args.warmup)
+    print(f"[bench] f32 window {r32['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
+    r64 = None
+    if not args.no_f64:
+        r64 = run_gpu(wl, adj.F64, args.steps, args.warmup)
+        print(f"[bench] f64 window {r64['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    khash = kernel_hash()
+    traffic = traffic_from_profiles(khash, "f32")
+    line = {
+        "metric": METRIC,
+        "value": r32["value"],
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"Taylor-Green vortex 64^3 periodic, Mach 0.1, Re 1600, {wl.nsteps} RK4 steps forward "
+                         "(every state stored) + full adjoint sweep, lambda 0, objective time-averaged viscous "
+                         "dissipation, gradient wrt a 5x64^3 body force"),
+            "cells": wl.ncells,
+            "window_steps": wl.nsteps,
+            "dt": wl.dt,
+            "step": "one whole window: forward sweep + reverse sweep",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": r32["stage_achieved_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": r32["stage_achieved_gbs"] / HBM_PEAK_GBS,
+            "traffic": None if traffic is None else traffic * wl.ncells,
+            "kernel": "k_adjoint_stage (reverse-stage gather)",
+            "avg_launch_us": r32["stage_avg_us"],
+            "alg_bytes_per_launch": r32["stage_alg_bytes"],
+        },
+        "adjoint_sweep_cell_steps_per_s": r32["adjoint_sweep_cell_steps_per_s"],
+        "primal_cell_steps_per_s": r32["primal_cell_steps_per_s"],
+        "kernel_ms_per_window": {k: v[0] / args.steps for k, v in r32["prof"].items()},
+    }
+    if r64 is not None:
+        line["f64"] = {
+            "value": r64["value"],
+            "ms_per_step": r64["ms_per_step"],
+            "adjoint_sweep_cell_steps_per_s": r64["adjoint_sweep_cell_steps_per_s"],
+            "primal_cell_steps_per_s": r64["primal_cell_steps_per_s"],
+            "roofline": {"achieved": r64["stage_achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": r64["stage_achieved_gbs"] / HBM_PEAK_GBS, "avg_launch_us": r64["stage_avg_us"]},
+            "kernel_ms_per_window": {k: v[0] / args.steps for k, v in r64["prof"].items()},
+        }
+        line["f32_speedup_over_f64"] = r32["value"] / r64["value"]
+        line["rel_err_f32_vs_f64"] = {
+            "J": abs(r32["J"] - r64["J"]) / abs(r64["J"]),
+            "dJ_dw0": rel(r32["wh0"], r64["wh0"]),
+            "dJ_ds": rel(r32["grad_s"], r64["grad_s"]),
+        }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

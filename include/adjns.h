@@ -151,6 +151,23 @@ int adj_ckpt_decode(const adj_grid* grid, const void* ckpt, float* w, void* stre
 int adj_residual(const adj_grid* grid, const void* w, const void* s, void* R, void* stream);
 int adj_vjp(const adj_grid* grid, const void* W, const void* kh, const void* nu, void* out, void* stream);
 
+/* Instrumentation.  While enabled, every kernel the library launches is bracketed by a pair of
+ * HIP events recorded on the same stream, grouped by class; adj_profile_read waits for the
+ * recorded events and returns the summed kernel time (milliseconds) and the launch count of one
+ * class.  adj_profile_enable(1) clears earlier records and starts recording, adj_profile_enable(0)
+ * stops recording and keeps the records; not thread-safe (one host thread). */
+enum {
+  ADJ_PROF_ADJOINT_STAGE = 0, /* reverse-stage gather kernels                   */
+  ADJ_PROF_PRIMAL_STAGE = 1,  /* RK4 stage kernels (primal and recomputation)   */
+  ADJ_PROF_SIGMA1 = 2,        /* growth-matrix singular value                   */
+  ADJ_PROF_OBJECTIVE = 3,     /* objective values and gradients                 */
+  ADJ_PROF_CODEC = 4,         /* checkpoint encode / decode                     */
+  ADJ_PROF_REDUCE = 5,        /* energy and inner products                      */
+  ADJ_PROF_NCLASS = 6
+};
+int adj_profile_enable(int on);
+int adj_profile_read(int kernel_class, double* total_ms, long long* launches);
+
 const char* adj_last_error(void);
 const char* adj_version(void);
 

@@ -22,6 +22,7 @@ F64, F32 = 0, 1
 CKPT_NATIVE, CKPT_BF16 = 0, 1
 BC_PERIODIC, BC_SLIP_WALLS = 0, 1
 OBJ_NONE, OBJ_MEAN_PRESSURE, OBJ_KE_DISSIPATION, OBJ_PT_LOSS_PLANE = 0, 1, 2, 3
+PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, PROF_SIGMA1, PROF_OBJECTIVE, PROF_CODEC, PROF_REDUCE = range(6)
 
 STATUS = {0: "ADJ_OK", -1: "ADJ_EINVAL", -2: "ADJ_ESHAPE", -3: "ADJ_EUNSTABLE", -4: "ADJ_ENONFINITE",
           -5: "ADJ_EHIP", -6: "ADJ_EWORKSPACE"}
@@ -81,7 +82,7 @@ class Objective(ctypes.Structure):
 _lib = None
 EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjoint_step", "adj_growth_sigma1",
            "adj_objective_and_grad", "adj_energy_vhat", "adj_dot", "adj_ckpt_encode", "adj_ckpt_decode",
-           "adj_residual", "adj_vjp", "adj_last_error", "adj_version")
+           "adj_residual", "adj_vjp", "adj_profile_enable", "adj_profile_read", "adj_last_error", "adj_version")
 
 
 def lib():
@@ -107,6 +108,9 @@ def lib():
         "adj_ckpt_decode": ([gp, vp, vp, vp], ctypes.c_int),
         "adj_residual": ([gp, vp, vp, vp, vp], ctypes.c_int),
         "adj_vjp": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "adj_profile_enable": ([ctypes.c_int], ctypes.c_int),
+        "adj_profile_read": ([ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)],
+                             ctypes.c_int),
         "adj_last_error": ([], ctypes.c_char_p),
         "adj_version": ([], ctypes.c_char_p),
     }
@@ -226,3 +230,16 @@ def residual(g, w, s, R):
 def vjp(g, W, kh, out, nu=None):
     _check(lib().adj_vjp(ctypes.byref(g), _state(g, W), _state(g, kh), _ptr(nu, g.dtype), _state(g, out),
                          _stream()))
+
+
+def profile_enable(on=True):
+    """Start (clearing earlier records) or stop event timing of every library kernel launch."""
+    _check(lib().adj_profile_enable(1 if on else 0))
+
+
+def profile_read(kernel_class):
+    """(total milliseconds, launches) of one kernel class since profile_enable(True)."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_longlong(0)
+    _check(lib().adj_profile_read(int(kernel_class), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

@@ -584,6 +584,7 @@ inline int ew_blocks(long long n) {
 // ------------------------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_sigma1(const Consts<T>& c, const T* w, T scale, T* out, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_SIGMA1, st);
   const int nb = (int)((c.N + RB - 1) / RB);
   hipLaunchKernelGGL((k_sigma1<T>), dim3(nb), dim3(RB), 0, st, c, w, scale, out);
   return hipGetLastError();
@@ -592,6 +593,7 @@ hipError_t launch_sigma1(const Consts<T>& c, const T* w, T scale, T* out, hipStr
 template <typename T>
 hipError_t launch_dot(const Consts<T>& c, const T* a, const T* b, double* partials, double* dst, double alpha,
                       double beta, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_REDUCE, st);
   const long long n = 5 * c.N;
   const int nb = reduce_blocks(n);
   hipLaunchKernelGGL((k_dot_partial<T>), dim3(nb), dim3(RB), 0, st, a, b, n, partials);
@@ -602,6 +604,7 @@ hipError_t launch_dot(const Consts<T>& c, const T* a, const T* b, double* partia
 template <typename T>
 hipError_t launch_energy_vhat(const Consts<T>& c, const T* w, const T* wh, double* partials, double* dst,
                               hipStream_t st) {
+  ProfScope ps(ADJ_PROF_REDUCE, st);
   const int nb = reduce_blocks(c.N);
   hipLaunchKernelGGL((k_energy_partial<T>), dim3(nb), dim3(RB), 0, st, c, w, wh, partials);
   const double inv_dv = 1.0 / ((double)c.dx[0] * (double)c.dx[1] * (double)c.dx[2]);
@@ -612,6 +615,7 @@ hipError_t launch_energy_vhat(const Consts<T>& c, const T* w, const T* wh, doubl
 template <typename T>
 hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt_ref, const T* w, double weight,
                             double* J_accum, T* djdw, double* partials, double* scratch, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_OBJECTIVE, st);
   if (kind == 1) {
     const int nb = reduce_blocks(c.N);
     hipLaunchKernelGGL((k_meanp<T>), dim3(nb), dim3(RB), 0, st, c, w, weight, J_accum ? partials : nullptr, djdw);
@@ -643,6 +647,7 @@ hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt
 
 hipError_t launch_ckpt_encode(const Consts<float>& c, const float* w, float* header, uint16_t* codes,
                               float* partials, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_CODEC, st);
   const int nb = reduce_blocks(c.N);
   hipLaunchKernelGGL(k_minmax_partial, dim3(nb), dim3(RB), 0, st, c, w, partials);
   hipLaunchKernelGGL(k_minmax_fold, dim3(1), dim3(RB), 0, st, partials, nb, header);
@@ -652,6 +657,7 @@ hipError_t launch_ckpt_encode(const Consts<float>& c, const float* w, float* hea
 
 hipError_t launch_ckpt_decode(const Consts<float>& c, const float* header, const uint16_t* codes, float* w,
                               hipStream_t st) {
+  ProfScope ps(ADJ_PROF_CODEC, st);
   hipLaunchKernelGGL(k_decode, dim3(ew_blocks(5 * c.N)), dim3(RB), 0, st, c, header, codes, w);
   return hipGetLastError();
 }

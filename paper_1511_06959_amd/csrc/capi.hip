@@ -11,6 +11,13 @@
 
 using namespace adjns;
 
+namespace adjns {
+ProfState& prof_state() {
+  static ProfState st;
+  return st;
+}
+}  // namespace adjns
+
 namespace {
 
 thread_local std::string g_err;
@@ -362,6 +369,33 @@ int adj_vjp(const adj_grid* grid, const void* W, const void* kh, const void* nu,
     e = launch_adjoint_stage<float>(STAGE_VJP, consts<float>(grid), (const float*)W, (const float*)kh, nullptr,
                                     (const float*)nu, 1.0f, 0.0f, nullptr, nullptr, (float*)out, nullptr, st);
   return e ? hip_fail(e, "vjp") : ADJ_OK;
+}
+
+int adj_profile_enable(int on) {
+  ProfState& P = prof_state();
+  if (on)
+    for (int k = 0; k < ADJ_PROF_NCLASS; ++k) P.used[k] = 0;
+  P.on = on != 0;
+  return ADJ_OK;
+}
+
+int adj_profile_read(int kernel_class, double* total_ms, long long* launches) {
+  if (kernel_class < 0 || kernel_class >= ADJ_PROF_NCLASS) return fail(ADJ_EINVAL, "bad kernel class %d", kernel_class);
+  if (!total_ms || !launches) return fail(ADJ_EINVAL, "total_ms and launches must be non-NULL");
+  ProfState& P = prof_state();
+  double tot = 0.0;
+  for (size_t i = 0; i < P.used[kernel_class]; ++i) {
+    auto& pr = P.ev[kernel_class][i];
+    hipError_t e = hipEventSynchronize(pr.second);
+    if (e != hipSuccess) return hip_fail(e, "profile read");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess) return hip_fail(e, "profile read");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (long long)P.used[kernel_class];
+  return ADJ_OK;
 }
 
 const char* adj_last_error(void) { return g_err.c_str(); }

@@ -1,6 +1,7 @@
 // kernels.hpp -- launchers of the gfx950 kernels (host-side declarations).
 #pragma once
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace adjns {
 

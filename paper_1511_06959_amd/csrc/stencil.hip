@@ -399,6 +399,7 @@ static dim3 tile_grid(int nx, int ny, int nz) {
 template <typename T>
 hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
                                const T* W3, T cR, T* out, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st);
   dim3 grid = tile_grid(c.nx, c.ny, c.nz);
   if (mode == STAGE_RES)
     hipLaunchKernelGGL((k_primal_stage<T, STAGE_RES>), grid, dim3(NT), 0, st, c, W, wn, s, W2, W3, cR, out);
@@ -412,6 +413,7 @@ hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T
 template <typename T>
 hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,
                                 T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st);
   dim3 grid = tile_grid(c.nx, c.ny, c.nz);
   if (c.wall) {
     if (mode == STAGE_VJP)
