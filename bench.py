@@ -64,14 +64,21 @@ def kernel_hash():
     return h.hexdigest()
 
 
-def run_gpu(wl, precision, steps, warmup):
+def run_gpu(wl, precision, steps, warmup, tune=True):
     import torch
 
     import paper_1511_06959_amd as adj
-    from paper_1511_06959_amd import sweep
+    from paper_1511_06959_amd import autotune, sweep
 
     dt = torch.float64 if precision == adj.F64 else torch.float32
     g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision)
+    tiles = {}
+    if tune:
+        res = autotune.tune(g, use_cache=False)
+        for kc, name in ((adj.PROF_ADJOINT_STAGE, "adjoint_stage"), (adj.PROF_PRIMAL_STAGE, "primal_stage")):
+            best, times = res[kc]
+            tiles[name] = {"tile": "x".join(map(str, adj.TILES[best])),
+                           "us": {"x".join(map(str, adj.TILES[t])): round(ms * 1e3, 2) for t, ms in times.items()}}
     obj = adj.Objective.make(wl.obj_kind)
     w0 = torch.from_numpy(wl.w0).to("cuda", dt)
     s = torch.from_numpy(wl.s).to("cuda", dt)
@@ -132,6 +139,7 @@ def run_gpu(wl, precision, steps, warmup):
     out["stage_avg_us"] = avg_s * 1e6
     out["stage_alg_bytes"] = alg_bytes
     out["stage_achieved_gbs"] = alg_bytes / avg_s / 1e9
+    out["tiles"] = tiles
     out["J"] = float(J.cpu()[0])
     out["wh0"] = wh0.double().cpu().numpy()
     out["grad_s"] = gs.double().cpu().numpy()
@@ -188,6 +196,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
@@ -203,11 +212,11 @@ def main():
     adj.lib()
     wl = W.tgv_64(nsteps=args.window)
     print(f"[bench] workload {wl.name}: {wl.n} cells, {wl.nsteps} steps, dt {wl.dt:.4e}", file=sys.stderr, flush=True)
-    r32 = run_gpu(wl, adj.F32, args.steps, args.warmup)
+    r32 = run_gpu(wl, adj.F32, args.steps, args.warmup, not args.no_autotune)
     print(f"[bench] f32 window {r32['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_f64:
-        r64 = run_gpu(wl, adj.F64, args.steps, args.warmup)
+        r64 = run_gpu(wl, adj.F64, args.steps, args.warmup, not args.no_autotune)
         print(f"[bench] f64 window {r64['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
 
     def rel(a, b):
@@ -251,6 +260,7 @@ def main():
         "adjoint_sweep_cell_steps_per_s": r32["adjoint_sweep_cell_steps_per_s"],
         "primal_cell_steps_per_s": r32["primal_cell_steps_per_s"],
         "kernel_ms_per_window": {k: v[0] / args.steps for k, v in r32["prof"].items()},
+        "tiles": r32["tiles"],
     }
     if r64 is not None:
         line["f64"] = {
@@ -261,6 +271,7 @@ def main():
             "roofline": {"achieved": r64["stage_achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": r64["stage_achieved_gbs"] / HBM_PEAK_GBS, "avg_launch_us": r64["stage_avg_us"]},
             "kernel_ms_per_window": {k: v[0] / args.steps for k, v in r64["prof"].items()},
+            "tiles": r64["tiles"],
         }
         line["f32_speedup_over_f64"] = r32["value"] / r64["value"]
         line["rel_err_f32_vs_f64"] = {

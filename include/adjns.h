@@ -168,6 +168,14 @@ enum {
 int adj_profile_enable(int on);
 int adj_profile_read(int kernel_class, double* total_ms, long long* launches);
 
+/* Launch configuration of the two stencil kernel classes (ADJ_PROF_ADJOINT_STAGE and
+ * ADJ_PROF_PRIMAL_STAGE), per precision: the output tile each work-group covers.  Process-wide;
+ * set it before enqueuing work that should use it (the autotuner does).  adj_get_tile returns
+ * the tile id or a negative status. */
+enum { ADJ_TILE_16x4x4 = 0, ADJ_TILE_32x4x2 = 1, ADJ_TILE_32x4x4 = 2, ADJ_TILE_32x8x2 = 3, ADJ_NTILES = 4 };
+int adj_set_tile(int kernel_class, int precision, int tile);
+int adj_get_tile(int kernel_class, int precision);
+
 const char* adj_last_error(void);
 const char* adj_version(void);
 

@@ -23,6 +23,7 @@ CKPT_NATIVE, CKPT_BF16 = 0, 1
 BC_PERIODIC, BC_SLIP_WALLS = 0, 1
 OBJ_NONE, OBJ_MEAN_PRESSURE, OBJ_KE_DISSIPATION, OBJ_PT_LOSS_PLANE = 0, 1, 2, 3
 PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, PROF_SIGMA1, PROF_OBJECTIVE, PROF_CODEC, PROF_REDUCE = range(6)
+TILES = {0: (16, 4, 4), 1: (32, 4, 2), 2: (32, 4, 4), 3: (32, 8, 2)}
 
 STATUS = {0: "ADJ_OK", -1: "ADJ_EINVAL", -2: "ADJ_ESHAPE", -3: "ADJ_EUNSTABLE", -4: "ADJ_ENONFINITE",
           -5: "ADJ_EHIP", -6: "ADJ_EWORKSPACE"}
@@ -82,7 +83,8 @@ class Objective(ctypes.Structure):
 _lib = None
 EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjoint_step", "adj_growth_sigma1",
            "adj_objective_and_grad", "adj_energy_vhat", "adj_dot", "adj_ckpt_encode", "adj_ckpt_decode",
-           "adj_residual", "adj_vjp", "adj_profile_enable", "adj_profile_read", "adj_last_error", "adj_version")
+           "adj_residual", "adj_vjp", "adj_profile_enable", "adj_profile_read", "adj_set_tile", "adj_get_tile",
+           "adj_last_error", "adj_version")
 
 
 def lib():
@@ -111,6 +113,8 @@ def lib():
         "adj_profile_enable": ([ctypes.c_int], ctypes.c_int),
         "adj_profile_read": ([ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)],
                              ctypes.c_int),
+        "adj_set_tile": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "adj_get_tile": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "adj_last_error": ([], ctypes.c_char_p),
         "adj_version": ([], ctypes.c_char_p),
     }
@@ -243,3 +247,15 @@ def profile_read(kernel_class):
     n = ctypes.c_longlong(0)
     _check(lib().adj_profile_read(int(kernel_class), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def set_tile(kernel_class, precision, tile):
+    """Tile shape id (see TILES) of the adjoint- or primal-stage kernels for one precision."""
+    _check(lib().adj_set_tile(int(kernel_class), int(precision), int(tile)))
+
+
+def get_tile(kernel_class, precision):
+    t = lib().adj_get_tile(int(kernel_class), int(precision))
+    if t < 0:
+        _check(t)
+    return t

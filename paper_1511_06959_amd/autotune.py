@@ -1,0 +1,98 @@
+"""Tile-shape autotuner for the two stencil kernel classes.
+
+For a grid and precision, every compiled tile shape of the reverse-stage kernel (timed through
+``vjp``) and of the RK4-stage kernel (timed through ``residual``) is run on the device with
+HIP events, and the fastest is installed with ``set_tile``.  Results are cached in a JSON file
+keyed by device name, kernel class, precision, grid shape and boundary type, so a process pays
+for the search once per configuration.
+"""
+import json
+import os
+
+import torch
+
+from . import (F64, PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, TILES, get_tile, residual, set_tile, vjp)
+
+CACHE = os.environ.get("ADJNS_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "adjns_tiles.json"))
+
+
+def _key(g, kclass):
+    dev = torch.cuda.get_device_name()
+    return f"{dev}|{'adjoint' if kclass == PROF_ADJOINT_STAGE else 'primal'}|{'f64' if g.precision == F64 else 'f32'}|" \
+           f"{g.n[0]}x{g.n[1]}x{g.n[2]}|bc{g.bc_x}"
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(db):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def _state(g, seed):
+    """A smooth positive-density state and a random adjoint field of the grid's shape."""
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    N = g.ncells
+    w = torch.empty(5, N, dtype=g.dtype, device="cuda")
+    w[0] = 1.0 + 0.05 * torch.rand(N, generator=gen, device="cuda", dtype=g.dtype)
+    w[1:4] = 0.1 * torch.randn(3, N, generator=gen, device="cuda", dtype=g.dtype)
+    w[4] = 2.5 + 0.05 * torch.rand(N, generator=gen, device="cuda", dtype=g.dtype)
+    kh = torch.randn(5 * N, generator=gen, device="cuda", dtype=g.dtype)
+    return w.reshape(-1).contiguous(), kh
+
+
+def _time(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(g, reps=20, use_cache=True, verbose=False):
+    """Pick and install the fastest tile of both kernel classes for grid g; returns
+    {kernel_class: (tile_id, {tile_id: ms})}."""
+    db = _load() if use_cache else {}
+    out = {}
+    w, kh = _state(g, 0)
+    buf = torch.empty_like(w)
+    for kclass in (PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE):
+        key = _key(g, kclass)
+        if use_cache and key in db:
+            set_tile(kclass, g.precision, db[key]["tile"])
+            out[kclass] = (db[key]["tile"], {int(k): v for k, v in db[key]["ms"].items()})
+            continue
+        prev = get_tile(kclass, g.precision)
+        times = {}
+        for t in TILES:
+            set_tile(kclass, g.precision, t)
+            if kclass == PROF_ADJOINT_STAGE:
+                times[t] = _time(lambda: vjp(g, w, kh, buf), reps)
+            else:
+                times[t] = _time(lambda: residual(g, w, None, buf), reps)
+        best = min(times, key=times.get) if times else prev
+        set_tile(kclass, g.precision, best)
+        out[kclass] = (best, times)
+        db[key] = {"tile": best, "ms": times}
+        if verbose:
+            print(f"[autotune] {key}: " + ", ".join(f"{TILES[t]} {ms * 1e3:.1f} us" for t, ms in times.items()),
+                  flush=True)
+    if use_cache:
+        _store(db)
+    return out

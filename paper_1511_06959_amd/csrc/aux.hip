@@ -287,103 +287,138 @@ __global__ __launch_bounds__(RB) void k_meanp(Consts<T> c, const T* __restrict__
   }
 }
 
-// Central-difference velocity gradient at cell (gx,gy,gz): G[l][k] = d_l u_k
-template <typename T>
-__device__ __forceinline__ void cell_grad_u(const Consts<T>& c, const T* __restrict__ w, int gx, int gy, int gz,
-                                            double G[3][3]) {
-  const double g = (double)c.gamma;
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    int mp, mm, rp, rm;
-    const long long ip = box_cell(c.nx, c.ny, c.nz, c.wall, gx + (l == 0), gy + (l == 1), gz + (l == 2), mp, rp);
-    const long long im = box_cell(c.nx, c.ny, c.nz, c.wall, gx - (l == 0), gy - (l == 1), gz - (l == 2), mm, rm);
-    const Q64 P = load_q64(c, w, ip, mp, g), M = load_q64(c, w, im, mm, g);
-    const double h = 0.5 * (double)c.idx[l];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) G[l][k] = (P.u[k] - M.u[k]) * h;
-  }
-}
-
-__device__ __forceinline__ void stress_from(double mu, const double G[3][3], double S[3][3]) {
-  const double div = G[0][0] + G[1][1] + G[2][2];
+// Viscous dissipation j = (1/N) sum_cells sigma_lk d_l u_k with cell-centred central gradients.
+// Both kernels stage the tile's velocities in LDS (halo 1 for the value, halo 2 for the gradient).
+template <typename T, int NB>
+__device__ __forceinline__ void tile_grad(const T (*su)[NB], int p, const int st[3], const T idx[3], T G[3][3]) {
 #pragma unroll
   for (int l = 0; l < 3; ++l)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) S[l][k] = mu * (G[l][k] + G[k][l]) - (l == k ? (2.0 / 3.0) * mu * div : 0.0);
+    for (int k = 0; k < 3; ++k) G[l][k] = (su[k][p + st[l]] - su[k][p - st[l]]) * (T(0.5) * idx[l]);
 }
 
-// viscous dissipation: j = (1/N) sum_cells sigma_lk d_l u_k
+// Loads velocities of the box whose origin is (x0 - hx, y0 - hy, z0 - hy) into su.
+template <typename T, int HX, int HY>
+__device__ __forceinline__ void load_box_u(const Consts<T>& c, const T* __restrict__ w, int x0, int y0, int z0,
+                                           T (*su)[Box<HX, HY>::NB]) {
+  using B = Box<HX, HY>;
+  const long long N = c.N;
+  for (int b = threadIdx.x; b < B::NB; b += NT) {
+    const int bx = b % B::BX, by = (b / B::BX) % B::BY, bz = b / (B::BX * B::BY);
+    int mirror, real;
+    const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - HX, y0 + by - HY, z0 + bz - HY, mirror, real);
+    const T ri = T(1) / w[gi];
+    T m1 = w[N + gi];
+    if (mirror) m1 = -m1;
+    su[0][b] = m1 * ri;
+    su[1][b] = w[2 * N + gi] * ri;
+    su[2][b] = w[3 * N + gi] * ri;
+  }
+}
+
 template <typename T>
-__global__ __launch_bounds__(RB) void k_ked(Consts<T> c, const T* __restrict__ w, double* __restrict__ partials) {
-  __shared__ double sh[RB];
-  const double mu = (double)c.mu;
-  double v = 0.0;
-  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < c.N; i += (long long)gridDim.x * RB) {
-    const int gx = (int)(i % c.nx), gy = (int)((i / c.nx) % c.ny), gz = (int)(i / ((long long)c.nx * c.ny));
-    double G[3][3], S[3][3];
-    cell_grad_u(c, w, gx, gy, gz, G);
-    stress_from(mu, G, S);
+__global__ __launch_bounds__(NT) void k_ked_tile(Consts<T> c, const T* __restrict__ w, double* __restrict__ partials) {
+  using B = Box<1, 1>;
+  __shared__ T su[3][B::NB];
+  __shared__ double sh[NT];
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+  load_box_u<T, 1, 1>(c, w, x0, y0, z0, su);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
+  double phi = 0.0;
+  if (x0 + tx < c.nx && y0 + ty < c.ny && z0 + tz < c.nz) {
+    const int st[3] = {1, B::SY, B::SZ};
+    const int p = (tz + 1) * B::SZ + (ty + 1) * B::SY + (tx + 1);
+    T G[3][3];
+    tile_grad<T, B::NB>(su, p, st, c.idx, G);
+    const T div = G[0][0] + G[1][1] + G[2][2];
+    T acc = T(0);
 #pragma unroll
     for (int l = 0; l < 3; ++l)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) v += S[l][k] * G[l][k];
+      for (int k = 0; k < 3; ++k) {
+        T sg = c.mu * (G[l][k] + G[k][l]);
+        if (l == k) sg -= (T(2) / T(3)) * c.mu * div;
+        acc += sg * G[l][k];
+      }
+    phi = (double)acc;
   }
-  const double tot = block_sum(v, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  const double tot = block_sum(phi, sh);
+  if (tid == 0) partials[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
-// Gradient of the dissipation, gathered at cell (gx,gy,gz) or at its wall ghost image (gxv):
-//   u^_k = (wgt/N) sum_l (sigma_lk(j - e_l) - sigma_lk(j + e_l)) / dx_l  (d Phi/d G_lk = 2 sigma_lk;
-//   sigma of a ghost cell is zero: it owns no dissipation term), then to conservative variables.
+// Gradient: u^_k(j) = (wgt/N) sum_l (sigma_lk(j - e_l) - sigma_lk(j + e_l)) / dx_l (since
+// d Phi / d G_lk = 2 sigma_lk); a ghost cell beyond a slip wall owns no dissipation term (sigma = 0),
+// so the gather at the ghost image of a wall cell reduces to -+ sigma_xk(cell)/dx and is folded
+// back through the mirror.  Then to conservative variables via u = m / rho.
 template <typename T>
-__device__ __forceinline__ void ked_gather(const Consts<T>& c, const T* __restrict__ w, int gxv, int gy, int gz,
-                                           double f, double out[5]) {
-  const double mu = (double)c.mu;
-  double uh[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-#pragma unroll
-    for (int sgn = -1; sgn <= 1; sgn += 2) {
-      const int x = gxv + sgn * (l == 0), y = gy + sgn * (l == 1), z = gz + sgn * (l == 2);
-      if (c.wall && (x < 0 || x >= c.nx)) continue;
-      double G[3][3], S[3][3];
-      cell_grad_u(c, w, x, y, z, G);
-      stress_from(mu, G, S);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) uh[k] += -sgn * S[l][k] * (double)c.idx[l];
-    }
+__global__ __launch_bounds__(NT) void k_ked_grad_tile(Consts<T> c, const T* __restrict__ w, double wgt,
+                                                      T* __restrict__ djdw) {
+  using O = Box<2, 2>;
+  using I = Box<1, 1>;
+  __shared__ T su[3][O::NB];
+  __shared__ T ss[6][I::NB];  // sigma xx, yy, zz, xy, xz, yz on the inner box
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+  load_box_u<T, 2, 2>(c, w, x0, y0, z0, su);
+  __syncthreads();
+  const int sto[3] = {1, O::SY, O::SZ};
+  for (int b = threadIdx.x; b < I::NB; b += NT) {
+    const int bx = b % I::BX, by = (b / I::BX) % I::BY, bz = b / (I::BX * I::BY);
+    const int gx = x0 + bx - 1;
+    const bool real = !c.wall || (gx >= 0 && gx < c.nx);
+    const int po = (bz + 1) * O::SZ + (by + 1) * O::SY + (bx + 1);
+    T G[3][3];
+    tile_grad<T, O::NB>(su, po, sto, c.idx, G);
+    const T div = G[0][0] + G[1][1] + G[2][2];
+    const T z = real ? T(1) : T(0);
+    const T m = c.mu * z;
+    ss[0][b] = m * (T(2) * G[0][0]) - (T(2) / T(3)) * m * div;
+    ss[1][b] = m * (T(2) * G[1][1]) - (T(2) / T(3)) * m * div;
+    ss[2][b] = m * (T(2) * G[2][2]) - (T(2) / T(3)) * m * div;
+    ss[3][b] = m * (G[0][1] + G[1][0]);
+    ss[4][b] = m * (G[0][2] + G[2][0]);
+    ss[5][b] = m * (G[1][2] + G[2][1]);
   }
-  int mirror, real;
-  const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, gxv, gy, gz, mirror, real);
-  const Q64 q = load_q64(c, w, gi, mirror, (double)c.gamma);
-  const double uu = q.u[0] * uh[0] + q.u[1] * uh[1] + q.u[2] * uh[2];
-  out[0] = -f * q.ri * uu;
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
+  const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
+  if (gx >= c.nx || gy >= c.ny || gz >= c.nz) return;
+  const int sti[3] = {1, I::SY, I::SZ};
+  const int p = (tz + 1) * I::SZ + (ty + 1) * I::SY + (tx + 1);
+  // sym[l][k]: index of sigma_lk in ss
+  constexpr int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+  T uh[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) out[1 + k] = f * q.ri * uh[k];
-  out[4] = 0.0;
-}
-
-template <typename T>
-__global__ __launch_bounds__(RB) void k_ked_grad(Consts<T> c, const T* __restrict__ w, double wgt,
-                                                 T* __restrict__ djdw) {
-  const long long i = (long long)blockIdx.x * RB + threadIdx.x;
-  if (i >= c.N) return;
-  const int gx = (int)(i % c.nx), gy = (int)((i / c.nx) % c.ny), gz = (int)(i / ((long long)c.nx * c.ny));
-  const double f = wgt / (double)c.N;
-  double o[5];
-  ked_gather(c, w, gx, gy, gz, f, o);
-  if (c.wall && (gx == 0 || gx == c.nx - 1)) {
-    double ov[5];
-    ked_gather(c, w, gx == 0 ? -1 : c.nx, gy, gz, f, ov);
-    o[0] += ov[0];
-    o[1] -= ov[1];
-    o[2] += ov[2];
-    o[3] += ov[3];
-    o[4] += ov[4];
+  for (int k = 0; k < 3; ++k) {
+    T acc = T(0);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) acc += (ss[sym[l][k]][p - sti[l]] - ss[sym[l][k]][p + sti[l]]) * c.idx[l];
+    uh[k] = acc;
   }
   const long long N = c.N;
+  const long long gi = ((long long)gz * c.ny + gy) * c.nx + gx;
+  const T ri = T(1) / w[gi];
+  const T u[3] = {w[N + gi] * ri, w[2 * N + gi] * ri, w[3 * N + gi] * ri};
+  const T f = (T)(wgt / (double)N);
+  T o0 = -f * ri * (u[0] * uh[0] + u[1] * uh[1] + u[2] * uh[2]);
+  T o[3] = {f * ri * uh[0], f * ri * uh[1], f * ri * uh[2]};
+  if (c.wall && (gx == 0 || gx == c.nx - 1)) {
+    // ghost image: u^_k(ghost) = -+ sigma_xk(cell)/dx; ghost velocity (-u_x, u_y, u_z)
+    const T sgn = gx == 0 ? T(-1) : T(1);
+    T vh[3];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) djdw[v * N + i] += (T)o[v];
+    for (int k = 0; k < 3; ++k) vh[k] = sgn * ss[sym[0][k]][p] * c.idx[0];
+    o0 += -f * ri * (-u[0] * vh[0] + u[1] * vh[1] + u[2] * vh[2]);
+    o[0] -= f * ri * vh[0];
+    o[1] += f * ri * vh[1];
+    o[2] += f * ri * vh[2];
+  }
+  djdw[gi] += o0;
+  djdw[N + gi] += o[0];
+  djdw[2 * N + gi] += o[1];
+  djdw[3 * N + gi] += o[2];
 }
 
 // Stagnation-pressure loss on an x-face plane [Eqs. (1)-(3)]: per face (j,k) the face state
@@ -622,15 +657,14 @@ hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt
     if (J_accum)
       hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 1, J_accum, weight / (double)c.N, 1.0);
   } else if (kind == 2) {
+    const dim3 grid((c.nx + TX - 1) / TX, (c.ny + TY - 1) / TY, (c.nz + TZ - 1) / TZ);
     if (J_accum) {
-      const int nb = reduce_blocks(c.N);
-      hipLaunchKernelGGL((k_ked<T>), dim3(nb), dim3(RB), 0, st, c, w, partials);
+      const int nb = (int)(grid.x * grid.y * grid.z);
+      // one partial per tile: the workspace partial region holds max(10 * MAX_PARTIALS, tiles) values
+      hipLaunchKernelGGL((k_ked_tile<T>), grid, dim3(NT), 0, st, c, w, partials);
       hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 1, J_accum, weight / (double)c.N, 1.0);
     }
-    if (djdw) {
-      const int nb = (int)((c.N + RB - 1) / RB);
-      hipLaunchKernelGGL((k_ked_grad<T>), dim3(nb), dim3(RB), 0, st, c, w, weight, djdw);
-    }
+    if (djdw) hipLaunchKernelGGL((k_ked_grad_tile<T>), grid, dim3(NT), 0, st, c, w, weight, djdw);
   } else if (kind == 3) {
     const long long nf = (long long)c.ny * c.nz;
     const int nb = reduce_blocks(nf);

@@ -16,6 +16,12 @@ ProfState& prof_state() {
   static ProfState st;
   return st;
 }
+
+// Tile shape per stencil kernel class (adjoint stage, primal stage) and precision (FP32, FP64).
+int& tile_choice(int kernel_class, int fp64) {
+  static int choice[2][2] = {{TILE_32x4x4, TILE_32x4x2}, {TILE_32x4x4, TILE_32x4x2}};
+  return choice[kernel_class == ADJ_PROF_PRIMAL_STAGE ? 1 : 0][fp64 ? 1 : 0];
+}
 }  // namespace adjns
 
 namespace {
@@ -60,7 +66,9 @@ WsLayout layout(const adj_grid* g) {
   L.wdec = L.g3 + S;
   L.nu = L.wdec + S;
   L.partials = L.nu + up((size_t)ncells(g) * elem(g));
-  L.scratch = L.partials + up((size_t)MAX_PARTIALS * 10 * sizeof(double));
+  const size_t tiles = (size_t)((g->n[0] + TX - 1) / TX) * ((g->n[1] + TY - 1) / TY) * ((g->n[2] + TZ - 1) / TZ);
+  const size_t npart = tiles > (size_t)MAX_PARTIALS * 10 ? tiles : (size_t)MAX_PARTIALS * 10;
+  L.scratch = L.partials + up(npart * sizeof(double));
   L.total = L.scratch + up(64 * sizeof(double));
   return L;
 }
@@ -396,6 +404,21 @@ int adj_profile_read(int kernel_class, double* total_ms, long long* launches) {
   *total_ms = tot;
   *launches = (long long)P.used[kernel_class];
   return ADJ_OK;
+}
+
+int adj_set_tile(int kernel_class, int precision, int tile) {
+  if (kernel_class != ADJ_PROF_ADJOINT_STAGE && kernel_class != ADJ_PROF_PRIMAL_STAGE)
+    return fail(ADJ_EINVAL, "tile shapes exist for the adjoint- and primal-stage kernels only");
+  if (precision != ADJ_F64 && precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", precision);
+  if (tile < 0 || tile >= NTILES) return fail(ADJ_EINVAL, "bad tile id %d", tile);
+  tile_choice(kernel_class, precision == ADJ_F64) = tile;
+  return ADJ_OK;
+}
+
+int adj_get_tile(int kernel_class, int precision) {
+  if (kernel_class != ADJ_PROF_ADJOINT_STAGE && kernel_class != ADJ_PROF_PRIMAL_STAGE) return fail(ADJ_EINVAL, "bad class");
+  if (precision != ADJ_F64 && precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", precision);
+  return tile_choice(kernel_class, precision == ADJ_F64);
 }
 
 const char* adj_last_error(void) { return g_err.c_str(); }

@@ -15,6 +15,21 @@ constexpr int RB = 256;
 // Upper bound on the number of per-block FP64 partial sums a reduction writes to the workspace.
 constexpr int MAX_PARTIALS = 4096;
 
+// LDS box of a TX_ x TY_ x TZ_ tile plus its halo: HX cells in x, HY in y and z.
+template <int TX_, int TY_, int TZ_, int HX, int HY>
+struct TBox {
+  static constexpr int BX = TX_ + 2 * HX, BY = TY_ + 2 * HY, BZ = TZ_ + 2 * HY;
+  static constexpr int SY = BX, SZ = BX * BY, NB = BX * BY * BZ;
+};
+template <int HX, int HY = 1>
+using Box = TBox<TX, TY, TZ, HX, HY>;
+
+// Tile shapes the stencil kernels are compiled for (index = adj_set_tile's tile id).  A
+// wavefront covers 64 consecutive threads, x fastest: rows of 32 let each half-wavefront read 32
+// consecutive LDS words (conflict-free) and 128-byte global segments.
+enum { TILE_16x4x4 = 0, TILE_32x4x2 = 1, TILE_32x4x4 = 2, TILE_32x8x2 = 3, NTILES = 4 };
+int& tile_choice(int kernel_class, int fp64);
+
 template <typename T>
 struct Consts {
   int nx, ny, nz, wall;  // wall: 1 = slip walls at x = 0 and x = L_x (mirror ghosts)

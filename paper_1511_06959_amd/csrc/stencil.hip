@@ -16,12 +16,6 @@ namespace adjns {
 // ------------------------------------------------------------------------------------------
 namespace {
 
-template <int HX>
-struct Box {
-  static constexpr int BX = TX + 2 * HX, BY = TY + 2, BZ = TZ + 2;
-  static constexpr int SY = BX, SZ = BX * BY, NB = BX * BY * BZ;
-};
-
 // LDS field order of the primal box
 enum { P_RHO = 0, P_U1, P_U2, P_U3, P_E, P_P, P_ET, P_NF };
 
@@ -101,12 +95,13 @@ __device__ __forceinline__ void residual_dir(const T (*sm)[NB], const int st[3],
 //       FIN  out = (W2 + 2 W3 + W - wn)/3 + (dt/6) R(W; s)      (stage 4, W = W4;
 //            equals wn + dt/6 (k1 + 2 k2 + 2 k3 + k4) since k1 = 2(W2-wn)/dt, k2 = 2(W3-wn)/dt,
 //            k3 = (W4-wn)/dt)
-template <typename T, int MODE>
-__global__ __launch_bounds__(NT) void k_primal_stage(Consts<T> c, const T* __restrict__ W,
-                                                     const T* __restrict__ wn, const T* __restrict__ s,
-                                                     const T* __restrict__ W2, const T* __restrict__ W3,
-                                                     T cR, T* __restrict__ out) {
-  using Bx = Box<1>;
+template <typename T, int MODE, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, const T* __restrict__ W,
+                                                               const T* __restrict__ wn, const T* __restrict__ s,
+                                                               const T* __restrict__ W2, const T* __restrict__ W3,
+                                                               T cR, T* __restrict__ out) {
+  constexpr int NT = TX * TY * TZ;
+  using Bx = TBox<TX, TY, TZ, 1, 1>;
   constexpr int NB = Bx::NB;
   __shared__ T sm[P_NF][NB];
   const int tid = threadIdx.x;
@@ -140,8 +135,11 @@ __global__ __launch_bounds__(NT) void k_primal_stage(Consts<T> c, const T* __res
   const int p = (tz + 1) * Bx::SZ + (ty + 1) * Bx::SY + (tx + 1);
   T R[5] = {T(0), T(0), T(0), T(0), T(0)};
   residual_dir<T, NB, 0>(sm, st, p, c, R);
+  __builtin_amdgcn_sched_barrier(0);
   residual_dir<T, NB, 1>(sm, st, p, c, R);
+  __builtin_amdgcn_sched_barrier(0);
   residual_dir<T, NB, 2>(sm, st, p, c, R);
+  __builtin_amdgcn_sched_barrier(0);
   const long long gi = ((long long)gz * c.ny + gy) * c.nx + gx;
   if (s) {
 #pragma unroll
@@ -185,7 +183,7 @@ __global__ __launch_bounds__(NT) void k_primal_stage(Consts<T> c, const T* __res
 // ------------------------------------------------------------------------------------------
 namespace {
 
-enum { A_K0 = 0, A_K1, A_K2, A_K3, A_K4, A_U1, A_U2, A_U3, A_E, A_RI, A_NU, A_NF };
+enum { A_K0 = 0, A_K1, A_K2, A_K3, A_K4, A_U1, A_U2, A_U3, A_NU };
 
 template <typename T, int NB>
 __device__ __forceinline__ void face_adj(const T (*sm)[NB], int A, int B, T in, T sh[3], T& GhE) {
@@ -212,6 +210,7 @@ __device__ __forceinline__ void chat(const T (*sm)[NB], const int st[3], int q, 
       const T shd = (sm[A_K1 + D][A] - sm[A_K1 + D][B]) * in + GhE * (T(0.5) * (sm[A_U1 + D][A] + sm[A_U1 + D][B]));
       C[D] += T(0.5) * c.mu * shl;
       C[L] -= (c.mu / T(3)) * shd;
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -237,6 +236,7 @@ __device__ __forceinline__ void adj_faces_dir(const T (*sm)[NB], const int st[3]
       uh[k] += sgn * P * in + T(0.5) * GhE * sig[k];
     }
     eh += sgn * c.alpha * GhE * in;
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -259,36 +259,47 @@ __device__ __forceinline__ void adj_conv_dir(const T (*sm)[NB], const int st[3],
 }
 
 // Full gather at box cell p.  gx: global x of the cell (for wall faces of L_nu); LNU: add L_nu.
-template <typename T, int NB, int SY, int SZ>
-__device__ __forceinline__ void adj_cell(const T (*sm)[NB], int p, const Consts<T>& c, bool lnu, int gx,
-                                         T acc[5]) {
+// e and ri (internal energy and 1/rho of the cell) come from the calling thread: a wall ghost
+// image has the same e and rho as its cell.
+template <typename T, int NB, int SY, int SZ, int LNU>
+__device__ __forceinline__ void adj_cell(const T (*sm)[NB], int p, const Consts<T>& c, int gx, T e, T ri, T acc[5]) {
   const int st[3] = {1, SY, SZ};
   const T u[3] = {sm[A_U1][p], sm[A_U2][p], sm[A_U3][p]};
-  const T e = sm[A_E][p], ri = sm[A_RI][p];
   const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const T H = c.gamma * e + T(0.5) * usq;
   const T phi = T(0.5) * (c.gamma - T(1)) * usq;
 #pragma unroll
   for (int v = 0; v < 5; ++v) acc[v] = T(0);
+  // The scheduling barriers keep each direction's LDS reads next to their use: hoisting them
+  // across directions raises the live register count and halves the resident wavefronts.
   adj_conv_dir<T, NB, 0>(sm, st, p, c, u, H, phi, acc);
+  __builtin_amdgcn_sched_barrier(0);
   adj_conv_dir<T, NB, 1>(sm, st, p, c, u, H, phi, acc);
+  __builtin_amdgcn_sched_barrier(0);
   adj_conv_dir<T, NB, 2>(sm, st, p, c, u, H, phi, acc);
+  __builtin_amdgcn_sched_barrier(0);
   T uh[3] = {T(0), T(0), T(0)}, eh = T(0);
   adj_faces_dir<T, NB, 0>(sm, st, p, c, uh, eh);
+  __builtin_amdgcn_sched_barrier(0);
   adj_faces_dir<T, NB, 1>(sm, st, p, c, uh, eh);
+  __builtin_amdgcn_sched_barrier(0);
   adj_faces_dir<T, NB, 2>(sm, st, p, c, uh, eh);
+  __builtin_amdgcn_sched_barrier(0);
   {
     T Cm[3], Cp[3];
     chat<T, NB, 0>(sm, st, p - st[0], c, Cm);
     chat<T, NB, 0>(sm, st, p + st[0], c, Cp);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) uh[k] += (Cm[k] - Cp[k]) * (T(0.5) * c.idx[0]);
     chat<T, NB, 1>(sm, st, p - st[1], c, Cm);
     chat<T, NB, 1>(sm, st, p + st[1], c, Cp);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) uh[k] += (Cm[k] - Cp[k]) * (T(0.5) * c.idx[1]);
     chat<T, NB, 2>(sm, st, p - st[2], c, Cm);
     chat<T, NB, 2>(sm, st, p + st[2], c, Cp);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) uh[k] += (Cm[k] - Cp[k]) * (T(0.5) * c.idx[2]);
   }
@@ -297,7 +308,7 @@ __device__ __forceinline__ void adj_cell(const T (*sm)[NB], int p, const Consts<
 #pragma unroll
   for (int k = 0; k < 3; ++k) acc[1 + k] += ri * (uh[k] - eh * u[k]);
   acc[4] += eh * ri;
-  if (lnu) {
+  if (LNU) {
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
       const T i2 = c.idx[D] * c.idx[D];
@@ -305,7 +316,7 @@ __device__ __forceinline__ void adj_cell(const T (*sm)[NB], int p, const Consts<
       for (int side = 0; side < 2; ++side) {
         if (D == 0 && c.wall && ((side == 0 && gx == 0) || (side == 1 && gx == c.nx - 1))) continue;
         const int q = side ? p + st[D] : p - st[D];
-        const T nf = T(0.5) * (sm[A_NU][p] + sm[A_NU][q]) * i2;
+        const T nf = T(0.5) * (sm[LNU ? A_NU : 0][p] + sm[LNU ? A_NU : 0][q]) * i2;
 #pragma unroll
         for (int v = 0; v < 5; ++v) acc[v] += nf * (sm[A_K0 + v][q] - sm[A_K0 + v][p]);
       }
@@ -318,16 +329,17 @@ __device__ __forceinline__ void adj_cell(const T (*sm)[NB], int p, const Consts<
 // MODE: STAGE_VJP  out = g = J^T kh (+ L_nu kh)
 //       STAGE_FIN  (RK4 stage 1) g1 = J(w_n)^T kh + ...; out = w^_n = a + g1 + gnext + g3 + g4;
 //                  grad_s += dt a + dt g4 + dt/2 (g3 + gnext)   (= k^1 + k^2 + k^3 + k^4)
-template <typename T, int MODE, int WALL>
-__global__ __launch_bounds__(NT) void k_adjoint_stage(Consts<T> c, const T* __restrict__ W,
+template <typename T, int MODE, int WALL, int LNU, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, const T* __restrict__ W,
                                                       const T* __restrict__ a, const T* __restrict__ gnext,
                                                       const T* __restrict__ nu, T ca, T cg,
                                                       const T* __restrict__ g3, const T* __restrict__ g4,
                                                       T* __restrict__ out, T* __restrict__ grad_s) {
-  using Bx = Box<WALL ? 2 : 1>;
+  constexpr int NT = TX * TY * TZ;
   constexpr int HX = WALL ? 2 : 1;
+  using Bx = TBox<TX, TY, TZ, HX, 1>;
   constexpr int NB = Bx::NB;
-  __shared__ T sm[A_NF][NB];
+  __shared__ T sm[LNU ? A_NU + 1 : A_NU][NB];
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
   const long long N = c.N;
@@ -335,37 +347,36 @@ __global__ __launch_bounds__(NT) void k_adjoint_stage(Consts<T> c, const T* __re
     const int bx = b % Bx::BX, by = (b / Bx::BX) % Bx::BY, bz = b / (Bx::BX * Bx::BY);
     int mirror, real;
     const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - HX, y0 + by - 1, z0 + bz - 1, mirror, real);
-    const T r = W[gi];
+    const T ri = T(1) / W[gi];
     T m1 = W[N + gi];
-    const T m2 = W[2 * N + gi], m3 = W[3 * N + gi], Et = W[4 * N + gi];
     if (mirror) m1 = -m1;
-    const T ri = T(1) / r;
-    const T u1 = m1 * ri, u2 = m2 * ri, u3 = m3 * ri;
-    sm[A_U1][b] = u1;
-    sm[A_U2][b] = u2;
-    sm[A_U3][b] = u3;
-    sm[A_E][b] = Et * ri - T(0.5) * (u1 * u1 + u2 * u2 + u3 * u3);
-    sm[A_RI][b] = ri;
+    sm[A_U1][b] = m1 * ri;
+    sm[A_U2][b] = W[2 * N + gi] * ri;
+    sm[A_U3][b] = W[3 * N + gi] * ri;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       T k = ca * a[v * N + gi];
       if (gnext) k += cg * gnext[v * N + gi];
       sm[A_K0 + v][b] = real ? k : T(0);
     }
-    sm[A_NU][b] = (nu && real) ? nu[gi] : T(0);
+    if (LNU) sm[LNU ? A_NU : 0][b] = real ? nu[gi] : T(0);
   }
   __syncthreads();
   const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
   const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
   if (gx >= c.nx || gy >= c.ny || gz >= c.nz) return;
   const int p = (tz + 1) * Bx::SZ + (ty + 1) * Bx::SY + (tx + HX);
+  const long long gi = ((long long)gz * c.ny + gy) * c.nx + gx;
+  const T ri = T(1) / W[gi];
+  const T uc[3] = {W[N + gi] * ri, W[2 * N + gi] * ri, W[3 * N + gi] * ri};
+  const T e = W[4 * N + gi] * ri - T(0.5) * (uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
   T g[5];
-  adj_cell<T, NB, Bx::SY, Bx::SZ>(sm, p, c, nu != nullptr, gx, g);
+  adj_cell<T, NB, Bx::SY, Bx::SZ, LNU>(sm, p, c, gx, e, ri, g);
   if (WALL) {
     // contributions through the mirror ghost of a wall-adjacent cell: g += M^T gather(ghost)
     if (gx == 0 || gx == c.nx - 1) {
       T gv[5];
-      adj_cell<T, NB, Bx::SY, Bx::SZ>(sm, gx == 0 ? p - 1 : p + 1, c, false, gx, gv);
+      adj_cell<T, NB, Bx::SY, Bx::SZ, 0>(sm, gx == 0 ? p - 1 : p + 1, c, gx, e, ri, gv);
       g[0] += gv[0];
       g[1] -= gv[1];
       g[2] += gv[2];
@@ -373,7 +384,7 @@ __global__ __launch_bounds__(NT) void k_adjoint_stage(Consts<T> c, const T* __re
       g[4] += gv[4];
     }
   }
-  const long long gi = ((long long)gz * c.ny + gy) * c.nx + gx;
+  __builtin_amdgcn_sched_barrier(0);
   if (MODE == STAGE_VJP) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[v * N + gi] = g[v];
@@ -390,41 +401,76 @@ __global__ __launch_bounds__(NT) void k_adjoint_stage(Consts<T> c, const T* __re
 }
 
 // ------------------------------------------------------------------------------------------
-// Host-side launchers
+// Host-side launchers: the tile shape of each kernel class and precision is a process-wide
+// setting (adj_set_tile), dispatched here to the matching instantiation.
 // ------------------------------------------------------------------------------------------
+template <int TX, int TY, int TZ>
 static dim3 tile_grid(int nx, int ny, int nz) {
   return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY, (nz + TZ - 1) / TZ);
+}
+
+template <typename T, int TX, int TY, int TZ>
+static void primal_tile(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2, const T* W3,
+                        T cR, T* out, hipStream_t st) {
+  const dim3 grid = tile_grid<TX, TY, TZ>(c.nx, c.ny, c.nz), blk(TX * TY * TZ);
+  if (mode == STAGE_RES)
+    hipLaunchKernelGGL((k_primal_stage<T, STAGE_RES, TX, TY, TZ>), grid, blk, 0, st, c, W, wn, s, W2, W3, cR, out);
+  else if (mode == STAGE_LIN)
+    hipLaunchKernelGGL((k_primal_stage<T, STAGE_LIN, TX, TY, TZ>), grid, blk, 0, st, c, W, wn, s, W2, W3, cR, out);
+  else
+    hipLaunchKernelGGL((k_primal_stage<T, STAGE_FIN, TX, TY, TZ>), grid, blk, 0, st, c, W, wn, s, W2, W3, cR, out);
 }
 
 template <typename T>
 hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
                                const T* W3, T cR, T* out, hipStream_t st) {
   ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st);
-  dim3 grid = tile_grid(c.nx, c.ny, c.nz);
-  if (mode == STAGE_RES)
-    hipLaunchKernelGGL((k_primal_stage<T, STAGE_RES>), grid, dim3(NT), 0, st, c, W, wn, s, W2, W3, cR, out);
-  else if (mode == STAGE_LIN)
-    hipLaunchKernelGGL((k_primal_stage<T, STAGE_LIN>), grid, dim3(NT), 0, st, c, W, wn, s, W2, W3, cR, out);
-  else
-    hipLaunchKernelGGL((k_primal_stage<T, STAGE_FIN>), grid, dim3(NT), 0, st, c, W, wn, s, W2, W3, cR, out);
+  switch (tile_choice(ADJ_PROF_PRIMAL_STAGE, sizeof(T) == 8)) {
+    case TILE_16x4x4: primal_tile<T, 16, 4, 4>(mode, c, W, wn, s, W2, W3, cR, out, st); break;
+    case TILE_32x4x2: primal_tile<T, 32, 4, 2>(mode, c, W, wn, s, W2, W3, cR, out, st); break;
+    case TILE_32x4x4: primal_tile<T, 32, 4, 4>(mode, c, W, wn, s, W2, W3, cR, out, st); break;
+    default: primal_tile<T, 32, 8, 2>(mode, c, W, wn, s, W2, W3, cR, out, st); break;
+  }
   return hipGetLastError();
+}
+
+template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
+static void adjoint_tile(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu, T ca, T cg,
+                         const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
+  const dim3 grid = tile_grid<TX, TY, TZ>(c.nx, c.ny, c.nz), blk(TX * TY * TZ);
+  if (mode == STAGE_VJP)
+    hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_VJP, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, c, W, a, gnext, nu, ca,
+                       cg, g3, g4, out, grad_s);
+  else
+    hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_FIN, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, c, W, a, gnext, nu, ca,
+                       cg, g3, g4, out, grad_s);
+}
+
+template <typename T, int WALL, int LNU>
+static void adjoint_variant(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu, T ca,
+                            T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
+  switch (tile_choice(ADJ_PROF_ADJOINT_STAGE, sizeof(T) == 8)) {
+    case TILE_16x4x4: adjoint_tile<T, WALL, LNU, 16, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
+    case TILE_32x4x2: adjoint_tile<T, WALL, LNU, 32, 4, 2>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
+    case TILE_32x4x4: adjoint_tile<T, WALL, LNU, 32, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
+    default: adjoint_tile<T, WALL, LNU, 32, 8, 2>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
+  }
 }
 
 template <typename T>
 hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,
                                 T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
   ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st);
-  dim3 grid = tile_grid(c.nx, c.ny, c.nz);
   if (c.wall) {
-    if (mode == STAGE_VJP)
-      hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_VJP, 1>), grid, dim3(NT), 0, st, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s);
+    if (nu)
+      adjoint_variant<T, 1, 1>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
     else
-      hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_FIN, 1>), grid, dim3(NT), 0, st, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s);
+      adjoint_variant<T, 1, 0>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
   } else {
-    if (mode == STAGE_VJP)
-      hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_VJP, 0>), grid, dim3(NT), 0, st, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s);
+    if (nu)
+      adjoint_variant<T, 0, 1>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
     else
-      hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_FIN, 0>), grid, dim3(NT), 0, st, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s);
+      adjoint_variant<T, 0, 0>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
   }
   return hipGetLastError();
 }

@@ -178,3 +178,36 @@ def test_fp32_operators(orc):
     out = torch.empty(w.size, dtype=torch.float32, device="cuda")
     adj.vjp(g, dev(w32, torch.float32), dev(kh, torch.float32), out)
     assert relerr(host(out), orc.vjp(og, w32, kh)) <= 1e-5
+
+
+@pytest.fixture
+def restore_tiles():
+    saved = {(k, p): adj.get_tile(k, p) for k in (adj.PROF_ADJOINT_STAGE, adj.PROF_PRIMAL_STAGE)
+             for p in (adj.F32, adj.F64)}
+    yield
+    for (k, p), t in saved.items():
+        adj.set_tile(k, p, t)
+
+
+@pytest.mark.parametrize("tile", sorted(adj.TILES), ids=[f"{a}x{b}x{c}" for a, b, c in adj.TILES.values()])
+@pytest.mark.parametrize("bc_x", [0, 1], ids=["periodic", "walls"])
+def test_every_tile_shape_f64(orc, restore_tiles, tile, bc_x):
+    shape = (37, 7, 5)
+    for k in (adj.PROF_ADJOINT_STAGE, adj.PROF_PRIMAL_STAGE):
+        adj.set_tile(k, adj.F64, tile)
+    g, og, w = _setup(orc, shape, bc_x, seed=16)
+    rng = np.random.default_rng(17)
+    s = 1e-2 * rng.standard_normal(w.size)
+    R = torch.empty(w.size, dtype=torch.float64, device="cuda")
+    adj.residual(g, dev(w), dev(s), R)
+    assert relerr(host(R), orc.residual(og, w, s)) <= 1e-13
+    a = rng.standard_normal(w.size)
+    ws = adj.workspace(g)
+    wh = torch.empty(w.size, dtype=torch.float64, device="cuda")
+    gs = torch.zeros(w.size, dtype=torch.float64, device="cuda")
+    obj = adj.Objective.make(W.OBJ_KE_DISSIPATION)
+    adj.adjoint_step(g, dev(w), dev(s), dev(a), wh, ws, lam=2e-3, obj=obj, c_n=0.2, grad_s=gs)
+    gref = np.zeros(w.size)
+    ref = orc.adjoint_step(og, w, s, a, 2e-3, orc.make_obj(W.OBJ_KE_DISSIPATION), 0.2, gref)
+    assert relerr(host(wh) - a, ref - a) <= 1e-12
+    assert relerr(host(gs), gref) <= 1e-12
