@@ -14,9 +14,11 @@ the FP32 path.  The FP64 path is timed the same way and reported beside it, toge
 FP32-vs-FP64 relative error of J, dJ/dw_0 and dJ/ds (the FP64 path matches the FP64 oracle to
 1e-10 in the test suite).
 
+Launch: the timed windows replay the forward and reverse sweeps as two captured HIP graphs.
 Roofline: the dominant kernel is the reverse-stage gather.  Its average launch duration is
-measured with HIP events recorded on its own stream around every launch in the timed region;
-`achieved` = algorithmic bytes per launch / that duration, against 8 TB/s.
+measured with HIP events recorded on its own stream around every launch of `--steps` eager
+(uncaptured) windows timed just before; `achieved` = algorithmic bytes per launch / that
+duration, against 8 TB/s.
 """
 import argparse
 import hashlib
@@ -87,44 +89,54 @@ def run_gpu(wl, precision, steps, warmup, tune=True):
     J = torch.zeros(1, dtype=torch.float64, device="cuda")
     gs = torch.zeros(5 * g.ncells, dtype=dt, device="cuda")
     out = {}
+    cells = g.ncells
 
-    def window(ev=None):
+    def window():
         J.zero_()
         gs.zero_()
         sweep.forward(g, w0, s, wl.nsteps, obj, wl.weights, ws, traj=traj, J=J)
-        if ev is not None:
-            ev.record()
         wh0, _, _ = sweep.backward(g, traj, s, obj, wl.weights, 0.0, ws, grad_s=gs)
         return wh0
 
-    for _ in range(warmup):
-        window()
-    adj.profile_enable(True)  # one profiled window grows the event pool outside the timed region
+    # (1) eager windows with every kernel launch bracketed by HIP events on its stream: the
+    #     per-kernel durations of the roofline entry come from these timed windows
+    adj.profile_enable(True)  # one profiled window grows the event pool before timing
     window()
     torch.cuda.synchronize()
     adj.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        window()
+    torch.cuda.synchronize()
+    out["eager_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / steps
+    adj.profile_enable(False)
+    prof = {}
+    for name, cls in (("adjoint_stage", adj.PROF_ADJOINT_STAGE), ("primal_stage", adj.PROF_PRIMAL_STAGE),
+                      ("objective", adj.PROF_OBJECTIVE), ("sigma1", adj.PROF_SIGMA1), ("codec", adj.PROF_CODEC),
+                      ("reduce", adj.PROF_REDUCE)):
+        prof[name] = adj.profile_read(cls)
+    del traj, ws
+    torch.cuda.empty_cache()
+
+    # (2) the same window captured as two HIP graphs and replayed: the throughput (value)
+    cw = sweep.CapturedWindow(g, w0, s, wl.nsteps, obj, wl.weights, lam=0.0)
+    for _ in range(warmup):
+        cw.run()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     mids = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    wh0 = None
     for k in range(steps):
         starts[k].record()
-        wh0 = window(mids[k])
+        cw.run_forward()
+        mids[k].record()
+        cw.run_backward()
         ends[k].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    adj.profile_enable(False)
     fwd = sum(starts[k].elapsed_time(mids[k]) for k in range(steps)) / steps
     bwd = sum(mids[k].elapsed_time(ends[k]) for k in range(steps)) / steps
-    prof = {}
-    for name, cls in (("adjoint_stage", adj.PROF_ADJOINT_STAGE), ("primal_stage", adj.PROF_PRIMAL_STAGE),
-                      ("objective", adj.PROF_OBJECTIVE), ("sigma1", adj.PROF_SIGMA1), ("codec", adj.PROF_CODEC),
-                      ("reduce", adj.PROF_REDUCE)):
-        ms, n = adj.profile_read(cls)
-        prof[name] = (ms, n)
-    cells = g.ncells
     out["ms_per_step"] = wall * 1e3 / steps
     out["fwd_ms"] = fwd
     out["bwd_ms"] = bwd
@@ -139,11 +151,12 @@ def run_gpu(wl, precision, steps, warmup, tune=True):
     out["stage_avg_us"] = avg_s * 1e6
     out["stage_alg_bytes"] = alg_bytes
     out["stage_achieved_gbs"] = alg_bytes / avg_s / 1e9
+    Jt, wh0, gs = cw.J, cw.wh0, cw.grad_s
     out["tiles"] = tiles
-    out["J"] = float(J.cpu()[0])
+    out["J"] = float(Jt.cpu()[0])
     out["wh0"] = wh0.double().cpu().numpy()
     out["grad_s"] = gs.double().cpu().numpy()
-    del traj, ws
+    del cw
     torch.cuda.empty_cache()
     return out
 
@@ -260,6 +273,8 @@ def main():
         "adjoint_sweep_cell_steps_per_s": r32["adjoint_sweep_cell_steps_per_s"],
         "primal_cell_steps_per_s": r32["primal_cell_steps_per_s"],
         "kernel_ms_per_window": {k: v[0] / args.steps for k, v in r32["prof"].items()},
+        "eager_ms_per_step": r32["eager_ms_per_step"],
+        "launch": "each window replayed as two captured HIP graphs (forward sweep, reverse sweep)",
         "tiles": r32["tiles"],
     }
     if r64 is not None:
@@ -271,6 +286,7 @@ def main():
             "roofline": {"achieved": r64["stage_achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": r64["stage_achieved_gbs"] / HBM_PEAK_GBS, "avg_launch_us": r64["stage_avg_us"]},
             "kernel_ms_per_window": {k: v[0] / args.steps for k, v in r64["prof"].items()},
+            "eager_ms_per_step": r64["eager_ms_per_step"],
             "tiles": r64["tiles"],
         }
         line["f32_speedup_over_f64"] = r32["value"] / r64["value"]

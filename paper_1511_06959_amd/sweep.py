@@ -102,3 +102,179 @@ def backward(g, traj, s, obj=None, weights=None, lam=0.0, ws=None, grad_s=None, 
         if energy:
             energy_vhat(g, state(n), a, E[n:n + 1], ws)
     return a, grad_s, E
+
+
+class CapturedWindow:
+    """A whole window captured once as two HIP graphs (forward sweep, reverse sweep) and replayed.
+
+    Every buffer the sweeps touch is allocated up front, so a replay launches the recorded
+    kernels only (no host work per step).  Buffers are reused across replays: ``run`` returns
+    views that the next replay overwrites.  Profiling must be off while capturing.
+    """
+
+    def __init__(self, g, w0, s, nsteps, obj=None, weights=None, lam=0.0, ws=None):
+        dev = w0.device
+        self.g, self.nsteps, self.obj, self.weights, self.lam = g, nsteps, obj, weights, lam
+        self.ws = workspace(g) if ws is None else ws
+        self.w0 = w0.clone()
+        self.s = None if s is None else s.clone()
+        self.traj = Trajectory(g, nsteps, dev)
+        self.J = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.grad_s = torch.zeros(5 * g.ncells, dtype=g.dtype, device=dev)
+        self.wh0 = torch.zeros(5 * g.ncells, dtype=g.dtype, device=dev)
+        self._fwd = torch.cuda.CUDAGraph()
+        self._bwd = torch.cuda.CUDAGraph()
+        # one eager pass settles torch's allocator state for the buffers used inside the sweeps
+        self._forward()
+        self._backward()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(self._fwd):
+            self._forward()
+        with torch.cuda.graph(self._bwd):
+            self._backward()
+        torch.cuda.synchronize()
+
+    def _forward(self):
+        self.J.zero_()
+        forward(self.g, self.w0, self.s, self.nsteps, self.obj, self.weights, self.ws, traj=self.traj, J=self.J)
+
+    def _backward(self):
+        self.grad_s.zero_()
+        wh0, _, _ = backward(self.g, self.traj, self.s, self.obj, self.weights, self.lam, self.ws, grad_s=self.grad_s)
+        self.wh0.copy_(wh0)
+
+    def run_forward(self):
+        self._fwd.replay()
+
+    def run_backward(self):
+        self._bwd.replay()
+
+    def run(self):
+        """Replay both sweeps; returns (J, dJ/dw_0, dJ/ds) device tensors owned by this object."""
+        self._fwd.replay()
+        self._bwd.replay()
+        return self.J, self.wh0, self.grad_s
+
+
+class RevolveSweep:
+    """Forward and reverse sweep with a fixed number of snapshot slots (binomial checkpointing).
+
+    ``forward(w0)`` runs the primal once over the window, accumulating J on every state and
+    storing the snapshots the reverse schedule starts from; ``backward(scale)`` replays the rest
+    of the schedule: recomputation from snapshots and reverse steps, with objective weights
+    multiplied by ``scale``.  With ``g.ckpt_format == CKPT_BF16`` the slots hold BF16 records; the
+    working state is always full precision.  Slots = nsteps + 1 reproduces the store-all sweep.
+    """
+
+    def __init__(self, g, nsteps, slots, s=None, obj=None, weights=None, lam=0.0, ws=None, device="cuda"):
+        from . import revolve
+        self.g = g
+        self.bf16 = g.ckpt_format == CKPT_BF16
+        self.gn = Grid.make(tuple(g.n), tuple(g.L), g.mu, g.dt, g.gamma, g.prandtl, g.bc_x, g.precision, 0)
+        self.nsteps, self.slots = nsteps, int(slots)
+        self.s, self.obj, self.weights, self.lam = s, obj, weights, lam
+        self.ws = workspace(g, device) if ws is None else ws
+        self.acts = revolve.schedule(nsteps, self.slots)
+        self.first_rev = next(i for i, a in enumerate(self.acts) if a[0] == "reverse")
+        N5 = 5 * g.ncells
+        if self.bf16:
+            self.pool = torch.empty((self.slots, ckpt_bytes(g)), dtype=torch.uint8, device=device)
+        else:
+            self.pool = torch.empty((self.slots, N5), dtype=g.dtype, device=device)
+        self.free = list(range(self.slots))
+        self.where = {}
+        self.cur = torch.empty(N5, dtype=g.dtype, device=device)
+        self.tmp = torch.empty(N5, dtype=g.dtype, device=device)
+        self.wN = torch.empty(N5, dtype=g.dtype, device=device)
+        self.cur_step = None
+        self.advanced = 0
+        self.use_obj = obj is not None and obj.kind != OBJ_NONE and weights is not None
+
+    # -- slot handling ----------------------------------------------------------------------
+    def _store(self, n, state):
+        k = self.free.pop()
+        self.where[n] = k
+        if self.bf16:
+            from . import ckpt_encode
+            ckpt_encode(self.g, state, self.pool[k], self.ws)
+        else:
+            self.pool[k].copy_(state)
+
+    def _load(self, n):
+        """Working state := stored state n."""
+        k = self.where[n]
+        if self.bf16:
+            from . import ckpt_decode
+            ckpt_decode(self.g, self.pool[k], self.cur)
+        else:
+            self.cur.copy_(self.pool[k])
+        self.cur_step = n
+
+    def _advance(self, i, j, J=None):
+        if self.cur_step != i:
+            self._load(i)
+        for n in range(i, j):
+            primal_step(self.gn, self.cur, self.s, self.tmp, self.ws)
+            self.cur, self.tmp = self.tmp, self.cur
+            self.advanced += 1
+            if J is not None and self.use_obj and self.weights[n + 1] != 0.0:
+                objective_and_grad(self.gn, self.obj, self.cur, self.ws, weight=float(self.weights[n + 1]), J_accum=J)
+        self.cur_step = j
+
+    # -- sweeps ------------------------------------------------------------------------------
+    def forward(self, w0, J=None):
+        dev = w0.device
+        J = torch.zeros(1, dtype=torch.float64, device=dev) if J is None else J
+        self.free = list(range(self.slots))
+        self.where = {}
+        self.cur.copy_(w0)
+        self.cur_step = 0
+        self.advanced = 0
+        self._store(0, self.cur)
+        if self.use_obj and self.weights[0] != 0.0:
+            objective_and_grad(self.gn, self.obj, self.cur, self.ws, weight=float(self.weights[0]), J_accum=J)
+        for act in self.acts[:self.first_rev]:
+            if act[0] == "advance":
+                self._advance(act[1], act[2], J)
+            elif act[0] == "store":
+                self._store(act[1], self.cur)
+            else:
+                raise AssertionError(act)
+        # the working state is w_{N-1}; the final state w_N feeds J and the terminal adjoint
+        if self.cur_step != self.nsteps - 1:
+            self._advance(self.cur_step, self.nsteps - 1, J)
+        primal_step(self.gn, self.cur, self.s, self.wN, self.ws)
+        self.advanced += 1
+        if self.use_obj and self.weights[self.nsteps] != 0.0:
+            objective_and_grad(self.gn, self.obj, self.wN, self.ws, weight=float(self.weights[self.nsteps]), J_accum=J)
+        return J
+
+    def backward(self, scale=1.0, grad_s=None):
+        g, dev = self.g, self.cur.device
+        N5 = 5 * g.ncells
+        a = torch.zeros(N5, dtype=g.dtype, device=dev)
+        b = torch.empty_like(a)
+        grad_s = torch.zeros(N5, dtype=g.dtype, device=dev) if grad_s is None else grad_s
+        if self.use_obj and self.weights[self.nsteps] != 0.0:
+            objective_and_grad(self.gn, self.obj, self.wN, self.ws, weight=scale * float(self.weights[self.nsteps]),
+                               djdw=a)
+        for act in self.acts[self.first_rev:]:
+            kind = act[0]
+            if kind == "advance":
+                self._advance(act[1], act[2])
+            elif kind == "store":
+                self._store(act[1], self.cur)
+            elif kind == "free":
+                self.free.append(self.where.pop(act[1]))
+            else:
+                n = act[1]
+                c_n = scale * float(self.weights[n]) if self.use_obj else 0.0
+                o = self.obj if self.use_obj else None
+                if self.cur_step == n:
+                    adjoint_step(self.gn, self.cur, self.s, a, b, self.ws, lam=self.lam, obj=o, c_n=c_n, grad_s=grad_s)
+                else:
+                    gg = self.g if self.bf16 else self.gn
+                    adjoint_step(gg, self.pool[self.where[n]], self.s, a, b, self.ws, lam=self.lam, obj=o, c_n=c_n,
+                                 grad_s=grad_s)
+                a, b = b, a
+        return a, grad_s

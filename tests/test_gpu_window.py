@@ -79,3 +79,27 @@ def test_gpu_gradient_vs_finite_difference():
     eps = 1e-4
     fd = (J(s0 + eps * d) - J(s0 - eps * d)) / (2 * eps)
     assert abs(fd - gd) <= 1e-7 * abs(gd)
+
+
+def test_captured_window_replays_match_eager():
+    # graph replays, interleaved with eager work and synchronisations, reproduce the eager window
+    wl = W.tgv_small(nsteps=12)
+    wl.weights = W.window_weights(12, 1, 12)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F64)
+    obj = adj.Objective.make(W.OBJ_KE_DISSIPATION)
+    w0 = dev(wl.w0)
+    s = dev(1e-3 * np.random.default_rng(30).standard_normal(wl.w0.size))
+    ws = adj.workspace(g)
+    traj, _, Je = sweep.forward(g, w0, s, wl.nsteps, obj, wl.weights, ws)
+    whe, gse, _ = sweep.backward(g, traj, s, obj, wl.weights, 1e-3, ws)
+    Je, whe, gse = host(Je), host(whe), host(gse)
+    cw = sweep.CapturedWindow(g, w0, s, wl.nsteps, obj, wl.weights, lam=1e-3)
+    for k in range(3):
+        J, wh, gs = cw.run()
+        assert np.array_equal(host(J), Je)
+        assert np.array_equal(host(wh), whe)
+        assert np.array_equal(host(gs), gse)
+        # unrelated eager work between replays
+        tmp = torch.empty_like(w0)
+        adj.primal_step(g, w0, s, tmp, ws)
+        torch.cuda.synchronize()
