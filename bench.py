@@ -66,14 +66,15 @@ def kernel_hash():
     return h.hexdigest()
 
 
-def run_gpu(wl, precision, steps, warmup, tune=True):
+def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=False):
     import torch
 
     import paper_1511_06959_amd as adj
     from paper_1511_06959_amd import autotune, sweep
 
     dt = torch.float64 if precision == adj.F64 else torch.float32
-    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision,
+                      adj.CKPT_BF16 if ckpt_bf16 else adj.CKPT_NATIVE)
     tiles = {}
     if tune:
         res = autotune.tune(g, use_cache=False)
@@ -81,7 +82,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True):
             best, times = res[kc]
             tiles[name] = {"tile": "x".join(map(str, adj.TILES[best])),
                            "us": {"x".join(map(str, adj.TILES[t])): round(ms * 1e3, 2) for t, ms in times.items()}}
-    obj = adj.Objective.make(wl.obj_kind)
+    obj = adj.Objective.make(wl.obj_kind, wl.plane_i, wl.pt_ref)
     w0 = torch.from_numpy(wl.w0).to("cuda", dt)
     s = torch.from_numpy(wl.s).to("cuda", dt)
     ws = adj.workspace(g)
@@ -95,7 +96,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True):
         J.zero_()
         gs.zero_()
         sweep.forward(g, w0, s, wl.nsteps, obj, wl.weights, ws, traj=traj, J=J)
-        wh0, _, _ = sweep.backward(g, traj, s, obj, wl.weights, 0.0, ws, grad_s=gs)
+        wh0, _, _ = sweep.backward(g, traj, s, obj, wl.weights, wl.lam, ws, grad_s=gs)
         return wh0
 
     # (1) eager windows with every kernel launch bracketed by HIP events on its stream: the
@@ -119,7 +120,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True):
     torch.cuda.empty_cache()
 
     # (2) the same window captured as two HIP graphs and replayed: the throughput (value)
-    cw = sweep.CapturedWindow(g, w0, s, wl.nsteps, obj, wl.weights, lam=0.0)
+    cw = sweep.CapturedWindow(g, w0, s, wl.nsteps, obj, wl.weights, lam=wl.lam, stages=stages)
     for _ in range(warmup):
         cw.run()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -200,16 +201,41 @@ def cpu_baseline(wl, budget_s):
     }
 
 
+WORKLOADS = {
+    "tgv64": "Taylor-Green vortex 64^3 periodic, Mach 0.1, Re 1600, {n} RK4 steps forward + full adjoint sweep, "
+             "lambda 0, objective time-averaged viscous dissipation, gradient wrt a 5x64^3 body force",
+    "turb384": "decaying turbulence 384^3 periodic (k^4 exp(-2k^2/k0^2), k0 4, Mach_rms 0.4, nu 2.887e-3), "
+               "{n}-step window sample of the 5000-step case, lambda 0.1 dx^2 sigma_1, mean pressure",
+    "wake": "temporally developing wake 512x256x32 (slip walls in x, free stream Mach 0.85, centre 0.5, Re 5e4), "
+            "{n}-step window sample of the 4000-step case, lambda 0.1 dx^2 sigma_1, stagnation-pressure loss",
+}
+
+
+def make_workload(name, window):
+    import workloads as W
+    if name == "tgv64":
+        return W.tgv_64(nsteps=window or 1000)
+    if name == "turb384":
+        return W.turb_384(nsteps=window or 10, lam_factor=0.1)
+    if name == "wake":
+        return W.wake(nsteps=window or 20, lam_factor=0.1)
+    raise SystemExit(f"unknown workload {name}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed windows")
     ap.add_argument("--warmup", type=int, default=1, help="untimed windows before the timed ones")
-    ap.add_argument("--window", type=int, default=1000, help="RK4 steps per window")
+    ap.add_argument("--workload", default="tgv64", choices=sorted(WORKLOADS))
+    ap.add_argument("--window", type=int, default=0, help="RK4 steps per window (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--schedule", default="stages", choices=("stages", "recompute"),
+                    help="stages: the forward sweep keeps the RK4 stage states in HBM; recompute: the reverse "
+                         "step recomputes them from w_n")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
@@ -219,17 +245,24 @@ def main():
     import torch
 
     import paper_1511_06959_amd as adj
-    import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     adj.lib()
-    wl = W.tgv_64(nsteps=args.window)
-    print(f"[bench] workload {wl.name}: {wl.n} cells, {wl.nsteps} steps, dt {wl.dt:.4e}", file=sys.stderr, flush=True)
-    r32 = run_gpu(wl, adj.F32, args.steps, args.warmup, not args.no_autotune)
+    wl = make_workload(args.workload, args.window)
+    big = args.workload != "tgv64"
+    stages = args.schedule == "stages" and not big
+    print(f"[bench] workload {wl.name}: {wl.n} cells, {wl.nsteps} steps, dt {wl.dt:.4e}, lambda {wl.lam:.3e}",
+          file=sys.stderr, flush=True)
+    # the large configurations keep BF16 checkpoint records on the FP32 path
+    r32 = run_gpu(wl, adj.F32, args.steps, args.warmup, not args.no_autotune, stages=stages, ckpt_bf16=big)
     print(f"[bench] f32 window {r32['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
+    r32b = None
+    if stages:
+        r32b = run_gpu(wl, adj.F32, args.steps, args.warmup, False, stages=False)
+        print(f"[bench] f32 window, recompute schedule {r32b['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_f64:
-        r64 = run_gpu(wl, adj.F64, args.steps, args.warmup, not args.no_autotune)
+        r64 = run_gpu(wl, adj.F64, args.steps, args.warmup, not args.no_autotune, stages=stages)
         print(f"[bench] f64 window {r64['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
 
     def rel(a, b):
@@ -251,13 +284,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"Taylor-Green vortex 64^3 periodic, Mach 0.1, Re 1600, {wl.nsteps} RK4 steps forward "
-                         "(every state stored) + full adjoint sweep, lambda 0, objective time-averaged viscous "
-                         "dissipation, gradient wrt a 5x64^3 body force"),
+            "workload": WORKLOADS[args.workload].format(n=wl.nsteps),
             "cells": wl.ncells,
             "window_steps": wl.nsteps,
             "dt": wl.dt,
             "step": "one whole window: forward sweep + reverse sweep",
+            "schedule": ("stage states of every step kept in HBM by the forward sweep" if stages else
+                         "reverse step recomputes the stage states from the stored w_n"),
+            "checkpoints": "BF16 records (per-variable affine)" if big else "native FP32 / FP64 states",
         },
         "roofline": {
             "bound": "hbm",
@@ -265,7 +299,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": r32["stage_achieved_gbs"] / HBM_PEAK_GBS,
-            "traffic": None if traffic is None else traffic * wl.ncells,
+            "traffic": None if (traffic is None or big) else traffic * wl.ncells,
             "kernel": "k_adjoint_stage (reverse-stage gather)",
             "avg_launch_us": r32["stage_avg_us"],
             "alg_bytes_per_launch": r32["stage_alg_bytes"],
@@ -277,6 +311,9 @@ def main():
         "launch": "each window replayed as two captured HIP graphs (forward sweep, reverse sweep)",
         "tiles": r32["tiles"],
     }
+    if r32b is not None:
+        line["f32_recompute_schedule"] = {"value": r32b["value"], "ms_per_step": r32b["ms_per_step"],
+                                          "adjoint_sweep_cell_steps_per_s": r32b["adjoint_sweep_cell_steps_per_s"]}
     if r64 is not None:
         line["f64"] = {
             "value": r64["value"],
@@ -294,8 +331,9 @@ def main():
             "J": abs(r32["J"] - r64["J"]) / abs(r64["J"]),
             "dJ_dw0": rel(r32["wh0"], r64["wh0"]),
             "dJ_ds": rel(r32["grad_s"], r64["grad_s"]),
+            "note": "the FP64 path matches the FP64 oracle to 1e-10 on the 16^3 window in the test suite",
         }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not big:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -119,6 +119,16 @@ int adj_adjoint_step(const adj_grid* grid, const void* w_n, const void* s, const
                      double lambda, const adj_objective* obj, double c_n, void* wh_n, void* grad_s,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* Store-stages schedule (for windows whose stage states fit in memory): adj_primal_step_stages
+ * is adj_primal_step that also writes the RK4 stage states W2, W3, W4 of the step into
+ * stages_out (3 consecutive state-sized arrays); adj_adjoint_step_stages is adj_adjoint_step
+ * that reads them from `stages` instead of recomputing them from w_n.  Native states only. */
+int adj_primal_step_stages(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* stages_out,
+                           void* ws, size_t ws_bytes, void* stream);
+int adj_adjoint_step_stages(const adj_grid* grid, const void* w_n, const void* stages, const void* s,
+                            const void* wh_np1, double lambda, const adj_objective* obj, double c_n, void* wh_n,
+                            void* grad_s, void* ws, size_t ws_bytes, void* stream);
+
 /* out[c] = scale * sigma_1(c): largest singular value of M = M1 - M2 at every cell, from central
  * differences of rho, u, p, a = sqrt((gamma-1)/gamma) c, b = c/sqrt(gamma)  [Energy Analysis].
  *   w in: state; out: N elements of the grid's precision. */

@@ -81,7 +81,8 @@ class Objective(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjoint_step", "adj_growth_sigma1",
+EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjoint_step", "adj_primal_step_stages",
+           "adj_adjoint_step_stages", "adj_growth_sigma1",
            "adj_objective_and_grad", "adj_energy_vhat", "adj_dot", "adj_ckpt_encode", "adj_ckpt_decode",
            "adj_residual", "adj_vjp", "adj_profile_enable", "adj_profile_read", "adj_set_tile", "adj_get_tile",
            "adj_last_error", "adj_version")
@@ -102,6 +103,8 @@ def lib():
         "adj_ckpt_bytes": ([gp], sz),
         "adj_primal_step": ([gp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "adj_adjoint_step": ([gp, vp, vp, vp, dbl, op, dbl, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_primal_step_stages": ([gp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_adjoint_step_stages": ([gp, vp, vp, vp, vp, dbl, op, dbl, vp, vp, vp, sz, vp], ctypes.c_int),
         "adj_growth_sigma1": ([gp, vp, dbl, vp, vp], ctypes.c_int),
         "adj_objective_and_grad": ([gp, op, vp, dbl, vp, vp, vp, sz, vp], ctypes.c_int),
         "adj_energy_vhat": ([gp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
@@ -193,6 +196,28 @@ def adjoint_step(g, w_n, s, wh_np1, wh_n, ws, lam=0.0, obj=None, c_n=0.0, grad_s
     _check(lib().adj_adjoint_step(ctypes.byref(g), wn_p, _state(g, s), _state(g, wh_np1), float(lam),
                                   ctypes.byref(obj) if obj is not None else None, float(c_n), _state(g, wh_n),
                                   _state(g, grad_s), wp, wb, _stream()))
+
+
+def _stages(g, t):
+    p = _ptr(t, g.dtype)
+    if t.numel() != 15 * g.ncells:
+        raise ValueError("stage tensors hold 3 states (15*N values)")
+    return p
+
+
+def primal_step_stages(g, w_n, s, w_np1, stages_out, ws):
+    """primal_step that also stores the stage states W2, W3, W4 in stages_out (15*N values)."""
+    wp, wb = _ws(ws)
+    _check(lib().adj_primal_step_stages(ctypes.byref(g), _state(g, w_n), _state(g, s), _state(g, w_np1),
+                                        _stages(g, stages_out), wp, wb, _stream()))
+
+
+def adjoint_step_stages(g, w_n, stages, s, wh_np1, wh_n, ws, lam=0.0, obj=None, c_n=0.0, grad_s=None):
+    """adjoint_step reading the stored stage states instead of recomputing them."""
+    wp, wb = _ws(ws)
+    _check(lib().adj_adjoint_step_stages(ctypes.byref(g), _state(g, w_n), _stages(g, stages), _state(g, s),
+                                         _state(g, wh_np1), float(lam), ctypes.byref(obj) if obj is not None else None,
+                                         float(c_n), _state(g, wh_n), _state(g, grad_s), wp, wb, _stream()))
 
 
 def growth_sigma1(g, w, out, scale=1.0):

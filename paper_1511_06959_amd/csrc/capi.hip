@@ -137,12 +137,13 @@ Consts<T> consts(const adj_grid* g) {
 inline char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
 template <typename T>
-int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, void* ws, hipStream_t st) {
+int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, T* stages, void* ws, hipStream_t st) {
   const Consts<T> c = consts<T>(g);
   const WsLayout L = layout(g);
-  T* W2 = (T*)at(ws, L.W2);
-  T* W3 = (T*)at(ws, L.W3);
-  T* W4 = (T*)at(ws, L.W4);
+  const long long S5 = 5 * c.N;
+  T* W2 = stages ? stages : (T*)at(ws, L.W2);
+  T* W3 = stages ? stages + S5 : (T*)at(ws, L.W3);
+  T* W4 = stages ? stages + 2 * S5 : (T*)at(ws, L.W4);
   const T h = c.dt * T(0.5);
   hipError_t e;
   if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st))) return hip_fail(e, "primal stage 1");
@@ -161,16 +162,17 @@ int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, 
 }
 
 template <typename T>
-int adjoint_step(const adj_grid* g, const void* wn_in, const T* s, const T* a, double lambda, const adj_objective* o,
-                 double c_n, T* wh, T* grad_s, void* ws, hipStream_t st) {
+int adjoint_step(const adj_grid* g, const void* wn_in, const T* stages, const T* s, const T* a, double lambda,
+                 const adj_objective* o, double c_n, T* wh, T* grad_s, void* ws, hipStream_t st) {
   const Consts<T> c = consts<T>(g);
   const WsLayout L = layout(g);
+  const long long S5 = 5 * c.N;
   T* W2 = (T*)at(ws, L.W2);
   T* W3 = (T*)at(ws, L.W3);
   T* W4 = (T*)at(ws, L.W4);
   T* g4 = (T*)at(ws, L.g4);
   T* g3 = (T*)at(ws, L.g3);
-  T* g2 = W4;  // W4 is dead once the stage-4 gather has run
+  T* g2 = W4;  // W4 is dead once the stage-4 gather has run (or unused when stages are given)
   T* nu = (T*)at(ws, L.nu);
   hipError_t e;
   const T* wn = (const T*)wn_in;
@@ -182,22 +184,30 @@ int adjoint_step(const adj_grid* g, const void* wn_in, const T* s, const T* a, d
       wn = (const T*)dec;
     }
   }
-  // forward recompute of the stage states
-  const T h = c.dt * T(0.5);
-  if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st))) return hip_fail(e, "recompute W2");
-  if ((e = launch_primal_stage<T>(STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st))) return hip_fail(e, "recompute W3");
-  if ((e = launch_primal_stage<T>(STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st))) return hip_fail(e, "recompute W4");
+  const T *sW2 = W2, *sW3 = W3, *sW4 = W4;
+  if (stages) {
+    // stage states stored by the forward sweep (adj_primal_step_stages)
+    sW2 = stages;
+    sW3 = stages + S5;
+    sW4 = stages + 2 * S5;
+  } else {
+    // forward recompute of the stage states
+    const T h = c.dt * T(0.5);
+    if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st))) return hip_fail(e, "recompute W2");
+    if ((e = launch_primal_stage<T>(STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st))) return hip_fail(e, "recompute W3");
+    if ((e = launch_primal_stage<T>(STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st))) return hip_fail(e, "recompute W4");
+  }
   const T* nup = nullptr;
   if (lambda > 0.0) {
     if ((e = launch_sigma1<T>(c, wn, (T)lambda, nu, st))) return hip_fail(e, "sigma_1");
     nup = nu;
   }
   const T dt = c.dt;
-  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, W4, a, nullptr, nup, dt / T(6), T(0), nullptr, nullptr, g4, nullptr, st)))
+  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, sW4, a, nullptr, nup, dt / T(6), T(0), nullptr, nullptr, g4, nullptr, st)))
     return hip_fail(e, "adjoint stage 4");
-  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, W3, a, g4, nup, dt / T(3), dt, nullptr, nullptr, g3, nullptr, st)))
+  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, sW3, a, g4, nup, dt / T(3), dt, nullptr, nullptr, g3, nullptr, st)))
     return hip_fail(e, "adjoint stage 3");
-  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, W2, a, g3, nup, dt / T(3), dt * T(0.5), nullptr, nullptr, g2, nullptr, st)))
+  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, sW2, a, g3, nup, dt / T(3), dt * T(0.5), nullptr, nullptr, g2, nullptr, st)))
     return hip_fail(e, "adjoint stage 2");
   if ((e = launch_adjoint_stage<T>(STAGE_FIN, c, wn, a, g2, nup, dt / T(6), dt * T(0.5), g3, g4, wh, grad_s, st)))
     return hip_fail(e, "adjoint stage 1");
@@ -223,8 +233,8 @@ size_t adj_ckpt_bytes(const adj_grid* grid) {
   return 64 + 5 * (size_t)ncells(grid) * sizeof(uint16_t);
 }
 
-int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out, void* ws,
-                    size_t ws_bytes, void* stream) {
+static int primal_entry(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out,
+                        void* stages, void* ws, size_t ws_bytes, void* stream) {
   int r;
   if ((r = check_grid(grid, true))) return r;
   if ((r = check_ws(grid, ws, ws_bytes))) return r;
@@ -233,13 +243,26 @@ int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* 
   if (ckpt_out && grid->precision != ADJ_F32) return fail(ADJ_EINVAL, "BF16 checkpoints need precision ADJ_F32");
   hipStream_t st = (hipStream_t)stream;
   if (grid->precision == ADJ_F64)
-    return primal_step<double>(grid, (const double*)w_n, (const double*)s, (double*)w_np1, nullptr, ws, st);
-  return primal_step<float>(grid, (const float*)w_n, (const float*)s, (float*)w_np1, ckpt_out, ws, st);
+    return primal_step<double>(grid, (const double*)w_n, (const double*)s, (double*)w_np1, nullptr, (double*)stages,
+                               ws, st);
+  return primal_step<float>(grid, (const float*)w_n, (const float*)s, (float*)w_np1, ckpt_out, (float*)stages, ws, st);
 }
 
-int adj_adjoint_step(const adj_grid* grid, const void* w_n, const void* s, const void* wh_np1, double lambda,
-                     const adj_objective* obj, double c_n, void* wh_n, void* grad_s, void* ws, size_t ws_bytes,
-                     void* stream) {
+int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out, void* ws,
+                    size_t ws_bytes, void* stream) {
+  return primal_entry(grid, w_n, s, w_np1, ckpt_out, nullptr, ws, ws_bytes, stream);
+}
+
+int adj_primal_step_stages(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* stages_out,
+                           void* ws, size_t ws_bytes, void* stream) {
+  if (!stages_out) return fail(ADJ_EINVAL, "stages_out must be non-NULL");
+  if (grid && grid->ckpt_format != ADJ_CKPT_NATIVE) return fail(ADJ_EINVAL, "stage states are stored natively");
+  return primal_entry(grid, w_n, s, w_np1, nullptr, stages_out, ws, ws_bytes, stream);
+}
+
+static int adjoint_entry(const adj_grid* grid, const void* w_n, const void* stages, const void* s, const void* wh_np1,
+                         double lambda, const adj_objective* obj, double c_n, void* wh_n, void* grad_s, void* ws,
+                         size_t ws_bytes, void* stream) {
   int r;
   if ((r = check_grid(grid, true))) return r;
   if ((r = check_ws(grid, ws, ws_bytes))) return r;
@@ -250,10 +273,24 @@ int adj_adjoint_step(const adj_grid* grid, const void* w_n, const void* s, const
   if (!std::isfinite(c_n)) return fail(ADJ_EINVAL, "c_n must be finite");
   hipStream_t st = (hipStream_t)stream;
   if (grid->precision == ADJ_F64)
-    return adjoint_step<double>(grid, w_n, (const double*)s, (const double*)wh_np1, lambda, obj, c_n, (double*)wh_n,
-                                (double*)grad_s, ws, st);
-  return adjoint_step<float>(grid, w_n, (const float*)s, (const float*)wh_np1, lambda, obj, c_n, (float*)wh_n,
-                             (float*)grad_s, ws, st);
+    return adjoint_step<double>(grid, w_n, (const double*)stages, (const double*)s, (const double*)wh_np1, lambda, obj,
+                                c_n, (double*)wh_n, (double*)grad_s, ws, st);
+  return adjoint_step<float>(grid, w_n, (const float*)stages, (const float*)s, (const float*)wh_np1, lambda, obj, c_n,
+                             (float*)wh_n, (float*)grad_s, ws, st);
+}
+
+int adj_adjoint_step(const adj_grid* grid, const void* w_n, const void* s, const void* wh_np1, double lambda,
+                     const adj_objective* obj, double c_n, void* wh_n, void* grad_s, void* ws, size_t ws_bytes,
+                     void* stream) {
+  return adjoint_entry(grid, w_n, nullptr, s, wh_np1, lambda, obj, c_n, wh_n, grad_s, ws, ws_bytes, stream);
+}
+
+int adj_adjoint_step_stages(const adj_grid* grid, const void* w_n, const void* stages, const void* s,
+                            const void* wh_np1, double lambda, const adj_objective* obj, double c_n, void* wh_n,
+                            void* grad_s, void* ws, size_t ws_bytes, void* stream) {
+  if (!stages) return fail(ADJ_EINVAL, "stages must be non-NULL");
+  if (grid && grid->ckpt_format != ADJ_CKPT_NATIVE) return fail(ADJ_EINVAL, "stage states are stored natively");
+  return adjoint_entry(grid, w_n, stages, s, wh_np1, lambda, obj, c_n, wh_n, grad_s, ws, ws_bytes, stream);
 }
 
 int adj_growth_sigma1(const adj_grid* grid, const void* w, double scale, void* out, void* stream) {

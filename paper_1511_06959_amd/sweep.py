@@ -10,25 +10,33 @@ Only scheduling happens here; all arithmetic runs in the library's kernels.
 """
 import torch
 
-from . import (CKPT_BF16, OBJ_NONE, Grid, Objective, adjoint_step, ckpt_bytes, energy_vhat, objective_and_grad,
-               primal_step, workspace)
+from . import (CKPT_BF16, OBJ_NONE, Grid, Objective, adjoint_step, adjoint_step_stages, ckpt_bytes, energy_vhat,
+               objective_and_grad, primal_step, primal_step_stages, workspace)
 
 
 class Trajectory:
-    """States w_0..w_N of one window, kept in HBM as full-precision states or BF16 records."""
+    """States w_0..w_N of one window, kept in HBM as full-precision states or BF16 records;
+    with ``stages=True`` also the RK4 stage states W2, W3, W4 of every step (native states),
+    so that the reverse sweep needs no recomputation (4x the memory of the states)."""
 
-    def __init__(self, g, nsteps, device="cuda"):
+    def __init__(self, g, nsteps, device="cuda", stages=False):
         self.g = g
         self.nsteps = nsteps
         N5 = 5 * g.ncells
         if g.ckpt_format == CKPT_BF16:
+            if stages:
+                raise ValueError("stage states are stored natively, not as BF16 records")
             self.rec_bytes = ckpt_bytes(g)
             self.store = torch.empty((nsteps + 1, self.rec_bytes), dtype=torch.uint8, device=device)
         else:
             self.store = torch.empty((nsteps + 1, N5), dtype=g.dtype, device=device)
+        self.stages = torch.empty((nsteps, 3 * N5), dtype=g.dtype, device=device) if stages else None
 
     def slot(self, n):
         return self.store[n]
+
+    def stage_slot(self, n):
+        return self.stages[n]
 
 
 def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None):
@@ -54,7 +62,10 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
         if bf16:
             primal_step(g, cur, s, nxt, ws, ckpt_out=traj.slot(n + 1))
         else:
-            primal_step(g, cur, s, traj.slot(n + 1), ws)
+            if traj.stages is not None:
+                primal_step_stages(g, cur, s, traj.slot(n + 1), traj.stage_slot(n), ws)
+            else:
+                primal_step(g, cur, s, traj.slot(n + 1), ws)
             nxt = traj.slot(n + 1)
         if use_obj and weights[n + 1] != 0.0:
             objective_and_grad(g, obj, nxt, ws, weight=float(weights[n + 1]), J_accum=J)
@@ -97,7 +108,11 @@ def backward(g, traj, s, obj=None, weights=None, lam=0.0, ws=None, grad_s=None, 
         energy_vhat(g, state(N), a, E[N:N + 1], ws)
     for n in range(N - 1, -1, -1):
         c_n = float(weights[n]) if use_obj else 0.0
-        adjoint_step(g, traj.slot(n), s, a, b, ws, lam=lam, obj=obj if use_obj else None, c_n=c_n, grad_s=grad_s)
+        if traj.stages is not None:
+            adjoint_step_stages(g, traj.slot(n), traj.stage_slot(n), s, a, b, ws, lam=lam,
+                                obj=obj if use_obj else None, c_n=c_n, grad_s=grad_s)
+        else:
+            adjoint_step(g, traj.slot(n), s, a, b, ws, lam=lam, obj=obj if use_obj else None, c_n=c_n, grad_s=grad_s)
         a, b = b, a
         if energy:
             energy_vhat(g, state(n), a, E[n:n + 1], ws)
@@ -112,13 +127,13 @@ class CapturedWindow:
     views that the next replay overwrites.  Profiling must be off while capturing.
     """
 
-    def __init__(self, g, w0, s, nsteps, obj=None, weights=None, lam=0.0, ws=None):
+    def __init__(self, g, w0, s, nsteps, obj=None, weights=None, lam=0.0, ws=None, stages=False):
         dev = w0.device
         self.g, self.nsteps, self.obj, self.weights, self.lam = g, nsteps, obj, weights, lam
         self.ws = workspace(g) if ws is None else ws
         self.w0 = w0.clone()
         self.s = None if s is None else s.clone()
-        self.traj = Trajectory(g, nsteps, dev)
+        self.traj = Trajectory(g, nsteps, dev, stages=stages)
         self.J = torch.zeros(1, dtype=torch.float64, device=dev)
         self.grad_s = torch.zeros(5 * g.ncells, dtype=g.dtype, device=dev)
         self.wh0 = torch.zeros(5 * g.ncells, dtype=g.dtype, device=dev)

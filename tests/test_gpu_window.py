@@ -103,3 +103,24 @@ def test_captured_window_replays_match_eager():
         tmp = torch.empty_like(w0)
         adj.primal_step(g, w0, s, tmp, ws)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precision", [adj.F64, adj.F32])
+def test_stored_stages_equal_recomputation(precision):
+    # the store-stages schedule reads exactly the states the recomputation would produce
+    wl = W.tgv_small(nsteps=8)
+    wl.weights = W.window_weights(8, 1, 8)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision)
+    dt = torch.float64 if precision == adj.F64 else torch.float32
+    obj = adj.Objective.make(W.OBJ_KE_DISSIPATION)
+    w0 = dev(wl.w0, dt)
+    s = dev(1e-3 * np.random.default_rng(31).standard_normal(wl.w0.size), dt)
+    ws = adj.workspace(g)
+    res = []
+    for stages in (False, True):
+        traj = sweep.Trajectory(g, wl.nsteps, stages=stages)
+        _, _, J = sweep.forward(g, w0, s, wl.nsteps, obj, wl.weights, ws, traj=traj)
+        wh, gs, _ = sweep.backward(g, traj, s, obj, wl.weights, 1e-3, ws)
+        res.append((host(J), host(wh), host(gs)))
+    for x, y in zip(*res):
+        assert np.array_equal(x, y)
