@@ -108,55 +108,83 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, cons
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
   const long long N = c.N;
   const T gm1 = c.gamma - T(1);
-  for (int b = tid; b < NB; b += NT) {
+  // all of this thread's box loads are issued before any is used: one memory latency, not NIT
+  // (branch-free: the tail iteration re-reads the last box cell and does not store it)
+  constexpr int NIT = (NB + NT - 1) / NT;
+  T wv[NIT][5];
+  int mir[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int b = min(tid + it * NT, NB - 1);
     const int bx = b % Bx::BX, by = (b / Bx::BX) % Bx::BY, bz = b / (Bx::BX * Bx::BY);
-    int mirror, real;
-    const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - 1, y0 + by - 1, z0 + bz - 1, mirror, real);
-    const T r = W[gi];
-    T m1 = W[N + gi];
-    const T m2 = W[2 * N + gi], m3 = W[3 * N + gi], Et = W[4 * N + gi];
-    if (mirror) m1 = -m1;
-    const T ri = T(1) / r;
-    const T u1 = m1 * ri, u2 = m2 * ri, u3 = m3 * ri;
-    const T e = Et * ri - T(0.5) * (u1 * u1 + u2 * u2 + u3 * u3);
-    sm[P_RHO][b] = r;
-    sm[P_U1][b] = u1;
-    sm[P_U2][b] = u2;
-    sm[P_U3][b] = u3;
-    sm[P_E][b] = e;
-    sm[P_P][b] = gm1 * r * e;
-    sm[P_ET][b] = Et;
+    int real;
+    const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - 1, y0 + by - 1, z0 + bz - 1, mir[it], real);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) wv[it][v] = W[v * N + gi];
   }
-  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int b = tid + it * NT;
+    if (it + 1 < NIT || b < NB) {
+      const T r = wv[it][0], Et = wv[it][4];
+      const T m1 = mir[it] ? -wv[it][1] : wv[it][1];
+      const T ri = T(1) / r;
+      const T u1 = m1 * ri, u2 = wv[it][2] * ri, u3 = wv[it][3] * ri;
+      const T e = Et * ri - T(0.5) * (u1 * u1 + u2 * u2 + u3 * u3);
+      sm[P_RHO][b] = r;
+      sm[P_U1][b] = u1;
+      sm[P_U2][b] = u2;
+      sm[P_U3][b] = u3;
+      sm[P_E][b] = e;
+      sm[P_P][b] = gm1 * r * e;
+      sm[P_ET][b] = Et;
+    }
+  }
   const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
   const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
-  if (gx >= c.nx || gy >= c.ny || gz >= c.nz) return;
+  const bool active = gx < c.nx && gy < c.ny && gz < c.nz;
+  const long long gi = ((long long)(active ? gz : 0) * c.ny + (active ? gy : 0)) * c.nx + (active ? gx : 0);
+  // per-cell operands, fetched before the barrier so that their latency overlaps the staging
+  T sv[5] = {T(0), T(0), T(0), T(0), T(0)}, base[5];
+  if (active) {
+    if (s) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sv[v] = s[v * N + gi];
+    }
+    if (MODE == STAGE_LIN) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) base[v] = wn[v * N + gi];
+    } else if (MODE == STAGE_FIN) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const long long q = v * N + gi;
+        base[v] = (W2[q] + T(2) * W3[q] - wn[q]);
+      }
+    }
+  }
+  __syncthreads();
+  if (!active) return;
   const int st[3] = {1, Bx::SY, Bx::SZ};
   const int p = (tz + 1) * Bx::SZ + (ty + 1) * Bx::SY + (tx + 1);
-  T R[5] = {T(0), T(0), T(0), T(0), T(0)};
+  T R[5] = {sv[0], sv[1], sv[2], sv[3], sv[4]};
   residual_dir<T, NB, 0>(sm, st, p, c, R);
   __builtin_amdgcn_sched_barrier(0);
   residual_dir<T, NB, 1>(sm, st, p, c, R);
   __builtin_amdgcn_sched_barrier(0);
   residual_dir<T, NB, 2>(sm, st, p, c, R);
   __builtin_amdgcn_sched_barrier(0);
-  const long long gi = ((long long)gz * c.ny + gy) * c.nx + gx;
-  if (s) {
-#pragma unroll
-    for (int v = 0; v < 5; ++v) R[v] += s[v * N + gi];
-  }
   if (MODE == STAGE_RES) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[v * N + gi] = R[v];
   } else if (MODE == STAGE_LIN) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out[v * N + gi] = wn[v * N + gi] + cR * R[v];
+    for (int v = 0; v < 5; ++v) out[v * N + gi] = base[v] + cR * R[v];
   } else {
     const T third = T(1) / T(3), h6 = c.dt / T(6);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const long long q = v * N + gi;
-      out[q] = (W2[q] + T(2) * W3[q] + W[q] - wn[q]) * third + h6 * R[v];
+      out[q] = (base[v] + W[q]) * third + h6 * R[v];
     }
   }
 }
@@ -180,63 +208,128 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, cons
 //   L_nu        sum_d sum_{+-} nu_f (kh_nb - kh_j)/dx_d^2, nu_f = (nu_j + nu_nb)/2, no wall faces.
 // Slip walls: ghost cells carry mirrored primitives and kh = 0 (they own no residual); a cell
 // next to a wall adds M^T times the gather evaluated at its ghost image (M flips x-momentum).
+//
+// Every face adjoint sigma^ is shared by six cells (the two it separates and four tangential
+// neighbours), so the kernel evaluates the faces once per work-group, one direction at a
+// time: a face-record buffer in LDS receives s~ = dx_d sigma^ and dK_E = kh_E,L - kh_E,R of all
+// direction-d faces of the box, plus the work term 0.5 G^_E sigma_d. of the faces bounding the
+// tile; the cells then gather from the records.  Three record phases reuse one buffer.
 // ------------------------------------------------------------------------------------------
 namespace {
 
 enum { A_K0 = 0, A_K1, A_K2, A_K3, A_K4, A_U1, A_U2, A_U3, A_NU };
 
-template <typename T, int NB>
-__device__ __forceinline__ void face_adj(const T (*sm)[NB], int A, int B, T in, T sh[3], T& GhE) {
-  GhE = (sm[A_K4][A] - sm[A_K4][B]) * in;
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    sh[k] = (sm[A_K1 + k][A] - sm[A_K1 + k][B]) * in + GhE * (T(0.5) * (sm[A_U1 + k][A] + sm[A_U1 + k][B]));
-}
+// Direction-D faces of the box, indexed by their lower cell (ax, ay, az) in box coordinates.
+// Records cover every lower cell that a tile cell or a tangential neighbour needs; work terms
+// (Q) cover the faces bounding tile cells.
+template <int TX, int TY, int TZ, int HX, int D>
+struct FaceSet {
+  using B = TBox<TX, TY, TZ, HX, 1>;
+  static constexpr int X0 = D == 0 ? HX - 1 : 0;
+  static constexpr int NX = D == 0 ? TX + 1 : B::BX;
+  static constexpr int NY = D == 1 ? TY + 1 : B::BY;
+  static constexpr int NZ = D == 2 ? TZ + 1 : B::BZ;
+  static constexpr int N = NX * NY * NZ;
+  static constexpr int QX0 = D == 0 ? HX - 1 : HX;
+  static constexpr int QY0 = D == 1 ? 0 : 1;
+  static constexpr int QZ0 = D == 2 ? 0 : 1;
+  static constexpr int NQX = D == 0 ? TX + 1 : TX;
+  static constexpr int NQY = D == 1 ? TY + 1 : TY;
+  static constexpr int NQZ = D == 2 ? TZ + 1 : TZ;
+  static constexpr int NQ = NQX * NQY * NQZ;
+  __device__ static int idx(int ax, int ay, int az) { return (ax - X0) + NX * (ay + NY * az); }
+  __device__ static int qidx(int ax, int ay, int az) { return (ax - QX0) + NQX * ((ay - QY0) + NQY * (az - QZ0)); }
+  __device__ static bool has(int ax) { return ax >= X0 && ax < X0 + NX; }
+  __device__ static bool hasq(int ax) { return ax >= QX0 && ax < QX0 + NQX; }
+};
 
-// C_l at box cell q (tangential-gradient adjoint), all 3 components
-template <typename T, int NB, int L>
-__device__ __forceinline__ void chat(const T (*sm)[NB], const int st[3], int q, const Consts<T>& c, T C[3]) {
-  C[0] = C[1] = C[2] = T(0);
+template <int A, int B, int C>
+struct Max3 {
+  static constexpr int v = A > B ? (A > C ? A : C) : (B > C ? B : C);
+};
+
+// Record phase of direction D (all threads).
+template <typename T, int TX, int TY, int TZ, int HX, int D, int NB, int NF, int NQF>
+__device__ __forceinline__ void face_records(const T (*sm)[NB], T (*fr)[NF], T (*fq)[NQF], const int st[3],
+                                             const Consts<T>& c) {
+  using F = FaceSet<TX, TY, TZ, HX, D>;
+  using B = TBox<TX, TY, TZ, HX, 1>;
+  constexpr int NT = TX * TY * TZ;
+  for (int f = threadIdx.x; f < F::N; f += NT) {
+    const int ax = F::X0 + f % F::NX, ay = (f / F::NX) % F::NY, az = f / (F::NX * F::NY);
+    const int A = az * B::SZ + ay * B::SY + ax, Bc = A + st[D];
+    const T dK4 = sm[A_K4][A] - sm[A_K4][Bc];
+    const T hd = T(0.5) * dK4;
 #pragma unroll
-  for (int D = 0; D < 3; ++D) {
-    if (D == L) continue;
+    for (int k = 0; k < 3; ++k)
+      fr[k][f] = (sm[A_K1 + k][A] - sm[A_K1 + k][Bc]) + hd * (sm[A_U1 + k][A] + sm[A_U1 + k][Bc]);
+    fr[3][f] = dK4;
+  }
+  const T qs = T(0.5) * c.idx[D];
+  for (int q = threadIdx.x; q < F::NQ; q += NT) {
+    const int ax = F::QX0 + q % F::NQX, ay = F::QY0 + (q / F::NQX) % F::NQY, az = F::QZ0 + q / (F::NQX * F::NQY);
+    const int A = az * B::SZ + ay * B::SY + ax;
+    T sig[3];
+    face_stress<T, NB, D>(&sm[A_U1][0], st, A, c.mu, c.idx, sig);
+    const T g = qs * (sm[A_K4][A] - sm[A_K4][A + st[D]]);
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int A = side ? q : q - st[D];
-      const int B = A + st[D];
-      const T in = c.idx[D];
-      const T GhE = (sm[A_K4][A] - sm[A_K4][B]) * in;
-      const T shl = (sm[A_K1 + L][A] - sm[A_K1 + L][B]) * in + GhE * (T(0.5) * (sm[A_U1 + L][A] + sm[A_U1 + L][B]));
-      const T shd = (sm[A_K1 + D][A] - sm[A_K1 + D][B]) * in + GhE * (T(0.5) * (sm[A_U1 + D][A] + sm[A_U1 + D][B]));
-      C[D] += T(0.5) * c.mu * shl;
-      C[L] -= (c.mu / T(3)) * shd;
-      __builtin_amdgcn_sched_barrier(0);
-    }
+    for (int k = 0; k < 3; ++k) fq[k][q] = g * sig[k];
   }
 }
 
-template <typename T, int NB, int D>
-__device__ __forceinline__ void adj_faces_dir(const T (*sm)[NB], const int st[3], int p, const Consts<T>& c,
-                                              T uh[3], T& eh) {
+// Gather of the direction-D records at box cell (qx, qy, qz).  VIRT: the cell is the ghost image
+// of a wall cell (only faces with a real cell contribute; lower cells outside the record set
+// are faces between two ghosts and count as zero).
+template <typename T, int TX, int TY, int TZ, int HX, int D, int NF, int NQF, bool VIRT>
+__device__ __forceinline__ void face_gather(const T (*fr)[NF], const T (*fq)[NQF], int qx, int qy, int qz,
+                                            const Consts<T>& c, T uh[3], T& eh) {
+  using F = FaceSet<TX, TY, TZ, HX, D>;
+  const T in = c.idx[D];
+  const T pm = c.mu * in * in, pe = c.alpha * in * in;
+  // direct faces: lower cell q - e_D (sign +) and q (sign -)
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
-    // side 0: face (p - e_D | p), p is R;  side 1: face (p | p + e_D), p is L
-    const int A = side ? p : p - st[D];
-    const int B = A + st[D];
-    const T in = c.idx[D];
-    T sh[3], GhE;
-    face_adj<T, NB>(sm, A, B, in, sh, GhE);
-    T sig[3];
-    face_stress<T, NB, D>(&sm[A_U1][0], st, A, c.mu, c.idx, sig);
-    const T sgn = side ? T(-1) : T(1);
+    const int ax = qx - (D == 0 && side == 0), ay = qy - (D == 1 && side == 0), az = qz - (D == 2 && side == 0);
+    if (VIRT && D != 0) continue;
+    if (VIRT && !F::has(ax)) continue;
+    const int f = F::idx(ax, ay, az);
+    const T sg = side == 0 ? T(1) : T(-1);
+    const T sD = fr[D][f];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      T P = c.mu * sh[k];
-      if (k == D) P += (c.mu / T(3)) * sh[D];
-      uh[k] += sgn * P * in + T(0.5) * GhE * sig[k];
+      T P = fr[k][f];
+      if (k == D) P += sD * (T(1) / T(3));
+      uh[k] += sg * pm * P;
     }
-    eh += sgn * c.alpha * GhE * in;
-    __builtin_amdgcn_sched_barrier(0);
+    eh += sg * pe * fr[3][f];
+    if (!VIRT || F::hasq(ax)) {
+      const int qi = F::qidx(ax, ay, az);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) uh[k] += fq[k][qi];
+    }
+  }
+  // tangential chain: cells q -+ e_l (l != D), each with its two direction-D faces
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (l == D) continue;
+    T tl = T(0), tD = T(0);
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int cx = qx + (l == 0 ? (sl ? 1 : -1) : 0), cy = qy + (l == 1 ? (sl ? 1 : -1) : 0),
+                cz = qz + (l == 2 ? (sl ? 1 : -1) : 0);
+      const T sgn = sl ? T(-1) : T(1);
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int ax = cx - (D == 0 && side == 0), ay = cy - (D == 1 && side == 0), az = cz - (D == 2 && side == 0);
+        if (VIRT && D == 0 && !F::has(ax)) continue;
+        const int f = F::idx(ax, ay, az);
+        tl += sgn * fr[l][f];
+        tD += sgn * fr[D][f];
+      }
+    }
+    const T h = T(0.5) * c.idx[l] * in;
+    uh[D] += (T(0.5) * c.mu * h) * tl;
+    uh[l] -= ((c.mu / T(3)) * h) * tD;
   }
 }
 
@@ -258,56 +351,140 @@ __device__ __forceinline__ void adj_conv_dir(const T (*sm)[NB], const int st[3],
   acc[4] += gm1 * v[1 + D] + c.gamma * ud * v[4];
 }
 
-// Full gather at box cell p.  gx: global x of the cell (for wall faces of L_nu); LNU: add L_nu.
-// e and ri (internal energy and 1/rho of the cell) come from the calling thread: a wall ghost
-// image has the same e and rho as its cell.
-template <typename T, int NB, int SY, int SZ, int LNU>
-__device__ __forceinline__ void adj_cell(const T (*sm)[NB], int p, const Consts<T>& c, int gx, T e, T ri, T acc[5]) {
-  const int st[3] = {1, SY, SZ};
-  const T u[3] = {sm[A_U1][p], sm[A_U2][p], sm[A_U3][p]};
+// Convective transpose at box cell p with primitive velocity u and internal energy e.
+template <typename T, int NB>
+__device__ __forceinline__ void adj_conv(const T (*sm)[NB], const int st[3], int p, const Consts<T>& c, const T u[3],
+                                         T e, T acc[5]) {
   const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const T H = c.gamma * e + T(0.5) * usq;
   const T phi = T(0.5) * (c.gamma - T(1)) * usq;
-#pragma unroll
-  for (int v = 0; v < 5; ++v) acc[v] = T(0);
-  // The scheduling barriers keep each direction's LDS reads next to their use: hoisting them
-  // across directions raises the live register count and halves the resident wavefronts.
   adj_conv_dir<T, NB, 0>(sm, st, p, c, u, H, phi, acc);
-  __builtin_amdgcn_sched_barrier(0);
   adj_conv_dir<T, NB, 1>(sm, st, p, c, u, H, phi, acc);
-  __builtin_amdgcn_sched_barrier(0);
   adj_conv_dir<T, NB, 2>(sm, st, p, c, u, H, phi, acc);
-  __builtin_amdgcn_sched_barrier(0);
-  T uh[3] = {T(0), T(0), T(0)}, eh = T(0);
-  adj_faces_dir<T, NB, 0>(sm, st, p, c, uh, eh);
-  __builtin_amdgcn_sched_barrier(0);
-  adj_faces_dir<T, NB, 1>(sm, st, p, c, uh, eh);
-  __builtin_amdgcn_sched_barrier(0);
-  adj_faces_dir<T, NB, 2>(sm, st, p, c, uh, eh);
-  __builtin_amdgcn_sched_barrier(0);
-  {
-    T Cm[3], Cp[3];
-    chat<T, NB, 0>(sm, st, p - st[0], c, Cm);
-    chat<T, NB, 0>(sm, st, p + st[0], c, Cp);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) uh[k] += (Cm[k] - Cp[k]) * (T(0.5) * c.idx[0]);
-    chat<T, NB, 1>(sm, st, p - st[1], c, Cm);
-    chat<T, NB, 1>(sm, st, p + st[1], c, Cp);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) uh[k] += (Cm[k] - Cp[k]) * (T(0.5) * c.idx[1]);
-    chat<T, NB, 2>(sm, st, p - st[2], c, Cm);
-    chat<T, NB, 2>(sm, st, p + st[2], c, Cp);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) uh[k] += (Cm[k] - Cp[k]) * (T(0.5) * c.idx[2]);
-  }
+}
+
+// (u^, e^) -> conservative adjoint at a cell with velocity u, internal energy e, 1/rho = ri.
+template <typename T>
+__device__ __forceinline__ void prim_to_cons(const T u[3], T e, T ri, const T uh[3], T eh, T acc[5]) {
+  const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const T uu = u[0] * uh[0] + u[1] * uh[1] + u[2] * uh[2];
   acc[0] += -ri * uu + eh * ri * (T(0.5) * usq - e);
 #pragma unroll
   for (int k = 0; k < 3; ++k) acc[1 + k] += ri * (uh[k] - eh * u[k]);
   acc[4] += eh * ri;
+}
+
+}  // namespace
+
+// MODE: STAGE_VJP  out = g = J^T kh (+ L_nu kh)
+//       STAGE_FIN  (RK4 stage 1) g1 = J(w_n)^T kh + ...; out = w^_n = a + g1 + gnext + g3 + g4;
+//                  grad_s += dt a + dt g4 + dt/2 (g3 + gnext)   (= k^1 + k^2 + k^3 + k^4)
+template <typename T, int MODE, int WALL, int LNU, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, const T* __restrict__ W,
+                                                                const T* __restrict__ a, const T* __restrict__ gnext,
+                                                                const T* __restrict__ nu, T ca, T cg,
+                                                                const T* __restrict__ g3, const T* __restrict__ g4,
+                                                                T* __restrict__ out, T* __restrict__ grad_s) {
+  constexpr int NT = TX * TY * TZ;
+  constexpr int HX = WALL ? 2 : 1;
+  using Bx = TBox<TX, TY, TZ, HX, 1>;
+  constexpr int NB = Bx::NB;
+  using F0 = FaceSet<TX, TY, TZ, HX, 0>;
+  using F1 = FaceSet<TX, TY, TZ, HX, 1>;
+  using F2 = FaceSet<TX, TY, TZ, HX, 2>;
+  constexpr int NF = Max3<F0::N, F1::N, F2::N>::v;
+  constexpr int NQF = Max3<F0::NQ, F1::NQ, F2::NQ>::v;
+  __shared__ T sm[LNU ? A_NU + 1 : A_NU][NB];
+  __shared__ T fr[4][NF];
+  __shared__ T fq[3][NQF];
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+  const long long N = c.N;
+  // all of this thread's box loads are issued before any is used: one memory latency, not NIT
+  // (branch-free: the tail iteration re-reads the last box cell and does not store it; a missing
+  // g_next is read as a with weight 0)
+  constexpr int NIT = (NB + NT - 1) / NT;
+  const T* __restrict__ gn = gnext ? gnext : a;
+  const T cgn = gnext ? cg : T(0);
+  T wv[NIT][4], av[NIT][5], gv[NIT][5], nv[NIT];
+  int mir[NIT], rl[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int b = min(tid + it * NT, NB - 1);
+    const int bx = b % Bx::BX, by = (b / Bx::BX) % Bx::BY, bz = b / (Bx::BX * Bx::BY);
+    const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - HX, y0 + by - 1, z0 + bz - 1, mir[it], rl[it]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) wv[it][v] = W[v * N + gi];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) av[it][v] = a[v * N + gi];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) gv[it][v] = gn[v * N + gi];
+    nv[it] = LNU ? nu[gi] : T(0);
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int b = tid + it * NT;
+    if (it + 1 < NIT || b < NB) {
+      const T ri = T(1) / wv[it][0];
+      sm[A_U1][b] = (mir[it] ? -wv[it][1] : wv[it][1]) * ri;
+      sm[A_U2][b] = wv[it][2] * ri;
+      sm[A_U3][b] = wv[it][3] * ri;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sm[A_K0 + v][b] = rl[it] ? ca * av[it][v] + cgn * gv[it][v] : T(0);
+      if (LNU) sm[LNU ? A_NU : 0][b] = rl[it] ? nv[it] : T(0);
+    }
+  }
+  const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
+  const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
+  const bool active = gx < c.nx && gy < c.ny && gz < c.nz;
+  const bool virt = WALL && active && (gx == 0 || gx == c.nx - 1);
+  const int qx = tx + HX, qy = ty + 1, qz = tz + 1;
+  const int vx = gx == 0 ? qx - 1 : qx + 1;  // box x of the ghost image
+  const int st[3] = {1, Bx::SY, Bx::SZ};
+  const int p = qz * Bx::SZ + qy * Bx::SY + qx;
+  const long long gi = ((long long)(active ? gz : 0) * c.ny + (active ? gy : 0)) * c.nx + (active ? gx : 0);
+  T ri = T(0), e = T(0), uc[3] = {T(0), T(0), T(0)};
+  if (active) {
+    ri = T(1) / W[gi];
+    uc[0] = W[N + gi] * ri;
+    uc[1] = W[2 * N + gi] * ri;
+    uc[2] = W[3 * N + gi] * ri;
+    e = W[4 * N + gi] * ri - T(0.5) * (uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
+  }
+  // stage-1 operands at the cell itself, fetched now so that their latency hides behind the
+  // face phases
+  T fa[5], f2[5], f3[5], f4[5];
+  if (MODE != STAGE_VJP && active) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const long long q = v * N + gi;
+      fa[v] = a[q];
+      f2[v] = gnext[q];
+      f3[v] = g3[q];
+      f4[v] = g4[q];
+    }
+  }
+  T uh[3] = {T(0), T(0), T(0)}, eh = T(0);
+  T uhv[3] = {T(0), T(0), T(0)}, ehv = T(0);
+  __syncthreads();
+  face_records<T, TX, TY, TZ, HX, 0, NB, NF, NQF>(sm, fr, fq, st, c);
+  __syncthreads();
+  if (active) face_gather<T, TX, TY, TZ, HX, 0, NF, NQF, false>(fr, fq, qx, qy, qz, c, uh, eh);
+  if (virt) face_gather<T, TX, TY, TZ, HX, 0, NF, NQF, true>(fr, fq, vx, qy, qz, c, uhv, ehv);
+  __syncthreads();
+  face_records<T, TX, TY, TZ, HX, 1, NB, NF, NQF>(sm, fr, fq, st, c);
+  __syncthreads();
+  if (active) face_gather<T, TX, TY, TZ, HX, 1, NF, NQF, false>(fr, fq, qx, qy, qz, c, uh, eh);
+  if (virt) face_gather<T, TX, TY, TZ, HX, 1, NF, NQF, true>(fr, fq, vx, qy, qz, c, uhv, ehv);
+  __syncthreads();
+  face_records<T, TX, TY, TZ, HX, 2, NB, NF, NQF>(sm, fr, fq, st, c);
+  __syncthreads();
+  if (active) face_gather<T, TX, TY, TZ, HX, 2, NF, NQF, false>(fr, fq, qx, qy, qz, c, uh, eh);
+  if (virt) face_gather<T, TX, TY, TZ, HX, 2, NF, NQF, true>(fr, fq, vx, qy, qz, c, uhv, ehv);
+  if (!active) return;
+  T g[5] = {T(0), T(0), T(0), T(0), T(0)};
+  adj_conv<T, NB>(sm, st, p, c, uc, e, g);
+  prim_to_cons(uc, e, ri, uh, eh, g);
   if (LNU) {
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
@@ -318,73 +495,24 @@ __device__ __forceinline__ void adj_cell(const T (*sm)[NB], int p, const Consts<
         const int q = side ? p + st[D] : p - st[D];
         const T nf = T(0.5) * (sm[LNU ? A_NU : 0][p] + sm[LNU ? A_NU : 0][q]) * i2;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) acc[v] += nf * (sm[A_K0 + v][q] - sm[A_K0 + v][p]);
+        for (int v = 0; v < 5; ++v) g[v] += nf * (sm[A_K0 + v][q] - sm[A_K0 + v][p]);
       }
     }
   }
-}
-
-}  // namespace
-
-// MODE: STAGE_VJP  out = g = J^T kh (+ L_nu kh)
-//       STAGE_FIN  (RK4 stage 1) g1 = J(w_n)^T kh + ...; out = w^_n = a + g1 + gnext + g3 + g4;
-//                  grad_s += dt a + dt g4 + dt/2 (g3 + gnext)   (= k^1 + k^2 + k^3 + k^4)
-template <typename T, int MODE, int WALL, int LNU, int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, const T* __restrict__ W,
-                                                      const T* __restrict__ a, const T* __restrict__ gnext,
-                                                      const T* __restrict__ nu, T ca, T cg,
-                                                      const T* __restrict__ g3, const T* __restrict__ g4,
-                                                      T* __restrict__ out, T* __restrict__ grad_s) {
-  constexpr int NT = TX * TY * TZ;
-  constexpr int HX = WALL ? 2 : 1;
-  using Bx = TBox<TX, TY, TZ, HX, 1>;
-  constexpr int NB = Bx::NB;
-  __shared__ T sm[LNU ? A_NU + 1 : A_NU][NB];
-  const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
-  const long long N = c.N;
-  for (int b = tid; b < NB; b += NT) {
-    const int bx = b % Bx::BX, by = (b / Bx::BX) % Bx::BY, bz = b / (Bx::BX * Bx::BY);
-    int mirror, real;
-    const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - HX, y0 + by - 1, z0 + bz - 1, mirror, real);
-    const T ri = T(1) / W[gi];
-    T m1 = W[N + gi];
-    if (mirror) m1 = -m1;
-    sm[A_U1][b] = m1 * ri;
-    sm[A_U2][b] = W[2 * N + gi] * ri;
-    sm[A_U3][b] = W[3 * N + gi] * ri;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      T k = ca * a[v * N + gi];
-      if (gnext) k += cg * gnext[v * N + gi];
-      sm[A_K0 + v][b] = real ? k : T(0);
-    }
-    if (LNU) sm[LNU ? A_NU : 0][b] = real ? nu[gi] : T(0);
+  if (virt) {
+    // contributions through the mirror ghost of a wall cell: g += M^T gather(ghost); the ghost has
+    // the cell's rho and e and the mirrored velocity (-u_x, u_y, u_z)
+    const int pv = qz * Bx::SZ + qy * Bx::SY + vx;
+    const T um[3] = {-uc[0], uc[1], uc[2]};
+    T gv[5] = {T(0), T(0), T(0), T(0), T(0)};
+    adj_conv<T, NB>(sm, st, pv, c, um, e, gv);
+    prim_to_cons(um, e, ri, uhv, ehv, gv);
+    g[0] += gv[0];
+    g[1] -= gv[1];
+    g[2] += gv[2];
+    g[3] += gv[3];
+    g[4] += gv[4];
   }
-  __syncthreads();
-  const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
-  const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
-  if (gx >= c.nx || gy >= c.ny || gz >= c.nz) return;
-  const int p = (tz + 1) * Bx::SZ + (ty + 1) * Bx::SY + (tx + HX);
-  const long long gi = ((long long)gz * c.ny + gy) * c.nx + gx;
-  const T ri = T(1) / W[gi];
-  const T uc[3] = {W[N + gi] * ri, W[2 * N + gi] * ri, W[3 * N + gi] * ri};
-  const T e = W[4 * N + gi] * ri - T(0.5) * (uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
-  T g[5];
-  adj_cell<T, NB, Bx::SY, Bx::SZ, LNU>(sm, p, c, gx, e, ri, g);
-  if (WALL) {
-    // contributions through the mirror ghost of a wall-adjacent cell: g += M^T gather(ghost)
-    if (gx == 0 || gx == c.nx - 1) {
-      T gv[5];
-      adj_cell<T, NB, Bx::SY, Bx::SZ, 0>(sm, gx == 0 ? p - 1 : p + 1, c, gx, e, ri, gv);
-      g[0] += gv[0];
-      g[1] -= gv[1];
-      g[2] += gv[2];
-      g[3] += gv[3];
-      g[4] += gv[4];
-    }
-  }
-  __builtin_amdgcn_sched_barrier(0);
   if (MODE == STAGE_VJP) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[v * N + gi] = g[v];
@@ -393,9 +521,8 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const long long q = v * N + gi;
-      const T av = a[q], g2v = gnext[q], g3v = g3[q], g4v = g4[q];
-      out[q] = av + g[v] + g2v + g3v + g4v;
-      if (grad_s) grad_s[q] += dt * av + dt * g4v + h2 * (g3v + g2v);
+      out[q] = fa[v] + g[v] + f2[v] + f3[v] + f4[v];
+      if (grad_s) grad_s[q] += dt * fa[v] + dt * f4[v] + h2 * (f3[v] + f2[v]);
     }
   }
 }
@@ -446,14 +573,36 @@ static void adjoint_tile(int mode, const Consts<T>& c, const T* W, const T* a, c
                        cg, g3, g4, out, grad_s);
 }
 
+// LDS bytes of one work-group of the reverse-stage kernel (box fields + face records + work terms)
+template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
+constexpr int adjoint_lds_bytes() {
+  constexpr int HX = WALL ? 2 : 1;
+  using B = TBox<TX, TY, TZ, HX, 1>;
+  using F0 = FaceSet<TX, TY, TZ, HX, 0>;
+  using F1 = FaceSet<TX, TY, TZ, HX, 1>;
+  using F2 = FaceSet<TX, TY, TZ, HX, 2>;
+  return (int)sizeof(T) * ((LNU ? A_NU + 1 : A_NU) * B::NB + 4 * Max3<F0::N, F1::N, F2::N>::v +
+                           3 * Max3<F0::NQ, F1::NQ, F2::NQ>::v);
+}
+
+// Tile dispatch; a shape whose LDS footprint exceeds the 160 KB of a CU runs as 16x4x4.
+template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
+static void adjoint_fit(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu, T ca, T cg,
+                        const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
+  if constexpr (adjoint_lds_bytes<T, WALL, LNU, TX, TY, TZ>() <= 160 * 1024)
+    adjoint_tile<T, WALL, LNU, TX, TY, TZ>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
+  else
+    adjoint_tile<T, WALL, LNU, 16, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
+}
+
 template <typename T, int WALL, int LNU>
 static void adjoint_variant(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu, T ca,
                             T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
   switch (tile_choice(ADJ_PROF_ADJOINT_STAGE, sizeof(T) == 8)) {
-    case TILE_16x4x4: adjoint_tile<T, WALL, LNU, 16, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
-    case TILE_32x4x2: adjoint_tile<T, WALL, LNU, 32, 4, 2>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
-    case TILE_32x4x4: adjoint_tile<T, WALL, LNU, 32, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
-    default: adjoint_tile<T, WALL, LNU, 32, 8, 2>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
+    case TILE_16x4x4: adjoint_fit<T, WALL, LNU, 16, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
+    case TILE_32x4x2: adjoint_fit<T, WALL, LNU, 32, 4, 2>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
+    case TILE_32x4x4: adjoint_fit<T, WALL, LNU, 32, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
+    default: adjoint_fit<T, WALL, LNU, 32, 8, 2>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
   }
 }
 
