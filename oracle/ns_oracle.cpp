@@ -14,7 +14,15 @@
 //
 // What is computed (paper section / equation in brackets):
 //   * residual  R(w; s) = -div_h F(w) + div_h F^v(w) + s          [Physics, Eq. (navier); vector form; index form with s_i]
-//       - convective face flux  0.5 (F_d(w_L) + F_d(w_R))          (central finite volume)
+//       - convective face flux  (split central form of Kennedy & Gruber, JCP 227, 2008):
+//         with face means  r = <rho>, v = <u>, H = <E/rho>, P = <p>  (<q> = (q_L + q_R)/2)
+//           F~ = r v_d (1, v, H) + P (0, e_d, v_d)
+//         The paper's solver relied on the numerical dissipation of its upwind flux and adds no
+//         subgrid model (section "Large Eddy Simulation"); a plain average of the two cell
+//         fluxes has neither, and on the under-resolved wake box (Re 5e4 on the wake width,
+//         512x256x32 cells) it diverged within 1700 steps, so the convective terms use this
+//         kinetic-energy-preserving product of means instead (still conservative, second order,
+//         and identical to the cell-flux average to first order about a uniform state).
 //       - viscous face flux     (0, sigma_d., u_f . sigma_d. + alpha d_d e) with face gradients:
 //         normal (phi_R - phi_L)/dx_d, tangential = mean of the two cells' central differences
 //       - sigma = mu (grad u + grad u^T) - (2 mu / 3) (div u) I,  p = (gamma-1) rho e,
@@ -162,14 +170,22 @@ Prim<T> prim(const G& g, const T w[5]) {
   return q;
 }
 
-// Convective flux in direction d   [vector form: F = (rho u, rho u u + p I, (rho E + p) u)]
+// Convective face flux in direction d between cells L and R   [vector form: F = (rho u,
+// rho u u + p I, (rho E + p) u)], each product of cell fields replaced by the product of the
+// face means of its factors (Kennedy & Gruber):  mass r v_d, momentum r v_d v + P e_d,
+// energy r v_d H + P v_d, with H the mean of the specific total energy E/rho.
 template <class T>
-void conv_flux(int d, const Prim<T>& q, T F[5]) {
-  T m = q.rho * q.u[d];
+void conv_face_flux(int d, const Prim<T>& L, const Prim<T>& R, T F[5]) {
+  T r = 0.5 * (L.rho + R.rho);
+  T v[3];
+  for (int k = 0; k < 3; ++k) v[k] = 0.5 * (L.u[k] + R.u[k]);
+  T H = 0.5 * (L.E / L.rho + R.E / R.rho);
+  T P = 0.5 * (L.p + R.p);
+  T m = r * v[d];
   F[0] = m;
-  for (int k = 0; k < 3; ++k) F[1 + k] = m * q.u[k];
-  F[1 + d] = F[1 + d] + q.p;
-  F[4] = (q.E + q.p) * q.u[d];
+  for (int k = 0; k < 3; ++k) F[1 + k] = m * v[k];
+  F[1 + d] = F[1 + d] + P;
+  F[4] = m * H + P * v[d];
 }
 
 inline void tangents(int d, int& t1, int& t2) { t1 = (d == 0) ? 1 : 0; t2 = (d == 2) ? 1 : 2; }
@@ -192,7 +208,7 @@ void face_slots(const G& g, int d, long i, long j, long k, Slot st[10]) {
 }
 
 // Total face flux H = F~ - F~^v on the face between slot 0 (L) and slot 1 (R) in direction d.
-//   F~   = 0.5 (F_d(w_L) + F_d(w_R))
+//   F~   = split-form convective face flux (conv_face_flux)
 //   F~^v = (0, sigma_d., u_f . sigma_d. + alpha d_d e), u_f = 0.5 (u_L + u_R)
 //   face gradient d_l u_k: l == d -> (u_R - u_L)/dx_d ; l != d -> mean of the central
 //   differences of cells L and R in direction l.
@@ -200,9 +216,8 @@ template <class T>
 void face_flux(const G& g, int d, const T st[10][5], T H[5]) {
   Prim<T> q[10];
   for (int s = 0; s < 10; ++s) q[s] = prim(g, st[s]);
-  T FL[5], FR[5];
-  conv_flux(d, q[0], FL);
-  conv_flux(d, q[1], FR);
+  T Fc[5];
+  conv_face_flux(d, q[0], q[1], Fc);
   int t[2]; tangents(d, t[0], t[1]);
   T gu[3][3];  // gu[l][k] = d_l u_k at the face
   for (int k = 0; k < 3; ++k) {
@@ -223,9 +238,9 @@ void face_flux(const G& g, int d, const T st[10][5], T H[5]) {
   }
   T work = 0.0;
   for (int k = 0; k < 3; ++k) work = work + 0.5 * (q[0].u[k] + q[1].u[k]) * sig[k];
-  H[0] = 0.5 * (FL[0] + FR[0]);
-  for (int k = 0; k < 3; ++k) H[1 + k] = 0.5 * (FL[1 + k] + FR[1 + k]) - sig[k];
-  H[4] = 0.5 * (FL[4] + FR[4]) - (work + g.alpha * de);
+  H[0] = Fc[0];
+  for (int k = 0; k < 3; ++k) H[1 + k] = Fc[1 + k] - sig[k];
+  H[4] = Fc[4] - (work + g.alpha * de);
 }
 
 // Face ranges: in x with walls the faces run from the wall face (ghost -1 | 0) to (nx-1 | ghost nx).

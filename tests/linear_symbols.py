@@ -7,7 +7,8 @@ the oracle's code:
 * Euler flux Jacobian A_d = dF_d/dw written in the textbook (u, H, phi) form.
 * Symbol of the semi-discrete operator at a uniform base state, acting on a Fourier mode
   w' = w^ exp(i k.x):
-    convective  -i sum_d A_d sin(k_d dx_d)/dx_d             (central flux average)
+    convective  -i sum_d A_d sin(k_d dx_d)/dx_d             (any consistent central face flux built
+                from face means, the split product form included, linearises to this)
     viscous     momentum_k = mu sum_d D_dd u'_k + mu sum_d D_dk u'_d - (2 mu/3) sum_l D_kl u'_l
                 energy     = u0 . momentum + alpha sum_d D_dd e'
     with D_dd = -4 sin^2(k_d dx_d / 2)/dx_d^2 (normal face gradient) and

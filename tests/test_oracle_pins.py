@@ -4,6 +4,10 @@ Each test is chosen so that a plausible slip in the oracle (a dropped term, a wr
 index or stencil coefficient, a transposed operand, a wrong RK4 weight) fails at least one:
 
   freestream / conservation      invariants of the conservative central finite-volume residual
+  split-form identity            the face flux of means equals Kennedy & Gruber's split
+                                 derivative (1/4)[d(ruf) + r d(uf) + u d(rf) + f d(ru) + ru df
+                                 + rf du + uf dr] with plain central differences d
+  kinetic energy                 at uniform pressure the inviscid terms leave sum rho|u|^2/2 fixed
   Fourier symbol (J and J^T)     closed-form linearised operator at a uniform state
   RK4 polynomial                 one tangent step equals G(dt L) = 1 + Z + Z^2/2 + Z^3/6 + Z^4/24
   complex step                   dual-number tangent vs complex-step derivative of the primal
@@ -82,6 +86,64 @@ def test_wall_conserves_mass_and_energy(orc):
     assert abs(R[0].sum()) <= 1e-13 * scale[0]
     assert abs(R[4].sum()) <= 1e-13 * scale[4]
     assert abs(R[2].sum()) <= 1e-13 * scale[2]  # tangential momentum
+
+
+def _central(q, d, dx):
+    # plain second-order central difference along grid axis d (x = last numpy axis), periodic
+    ax = 2 - d
+    return (np.roll(q, -1, axis=ax) - np.roll(q, 1, axis=ax)) / (2.0 * dx)
+
+
+def test_split_form_identity(orc):
+    # Inviscid residual on a rough periodic state against the split derivative forms written with
+    # central differences only: cubic split for rho u_d phi (phi = 1, u_k, E/rho), quadratic split
+    # (1/2)[d(pu) + p du + u dp] for the pressure work and d p for the momentum pressure term.
+    n = (6, 5, 7)
+    L = (1.3, 2.0, 0.9)
+    gam = 1.4
+    g = _grid(orc, n, L=L, mu=0.0, gamma=gam)
+    rng = np.random.default_rng(11)
+    shp = (n[2], n[1], n[0])
+    rho = 1.0 + 0.3 * rng.random(shp)
+    u = [0.4 * rng.standard_normal(shp) for _ in range(3)]
+    p = 0.7 + 0.2 * rng.random(shp)
+    w = W.conservative(rho, u[0], u[1], u[2], p, gamma=gam)
+    Es = w.reshape(5, *shp)[4] / rho
+    dx = [L[d] / n[d] for d in range(3)]
+
+    def cubic(a, b, c, d):
+        D = lambda q: _central(q, d, dx[d])
+        return 0.25 * (D(a * b * c) + a * D(b * c) + b * D(a * c) + c * D(a * b)
+                       + a * b * D(c) + a * c * D(b) + b * c * D(a))
+
+    one = np.ones(shp)
+    expect = np.zeros((5,) + shp)
+    for d in range(3):
+        expect[0] -= cubic(rho, u[d], one, d)
+        for k in range(3):
+            expect[1 + k] -= cubic(rho, u[d], u[k], d)
+        expect[1 + d] -= _central(p, d, dx[d])
+        expect[4] -= cubic(rho, u[d], Es, d)
+        expect[4] -= 0.5 * (_central(p * u[d], d, dx[d]) + p * _central(u[d], d, dx[d])
+                            + u[d] * _central(p, d, dx[d]))
+    R = orc.residual(g, w).reshape(5, *shp)
+    assert np.abs(R - expect).max() <= 1e-13 * np.abs(expect).max()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_kinetic_energy_preserved_by_convection(orc, seed):
+    # d/dt sum rho|u|^2/2 = sum (u . R_m - |u|^2/2 R_rho): zero when only convection acts and the
+    # pressure is uniform (the momentum flux is the mass flux times the face-mean velocity)
+    n = (6, 7, 5)
+    g = _grid(orc, n, L=(1.0, 1.4, 0.8), mu=0.0)
+    rng = np.random.default_rng(40 + seed)
+    shp = (n[2], n[1], n[0])
+    rho = 1.0 + 0.5 * rng.random(shp)
+    u = [rng.standard_normal(shp) for _ in range(3)]
+    w = W.conservative(rho, u[0], u[1], u[2], np.full(shp, 0.8))
+    R = orc.residual(g, w).reshape(5, *shp)
+    terms = sum(u[k] * R[1 + k] for k in range(3)) - 0.5 * sum(uk * uk for uk in u) * R[0]
+    assert abs(terms.sum()) <= 1e-13 * np.abs(terms).sum()
 
 
 # ------------------------------------------------------------------------------ Fourier symbols
