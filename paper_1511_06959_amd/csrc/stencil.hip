@@ -10,27 +10,29 @@
 namespace adjns {
 
 // ------------------------------------------------------------------------------------------
-// Primal residual  R = -sum_d (F~_{d,+} - F~_{d,-})/dx_d + s  with
-//   F~ = 0.5 (F(w_L) + F(w_R)) - (0, sigma_d., u_f . sigma_d. + alpha d_d e)
-// [Physics, Eq. navier; Unsteady adjoint, vector form with source].
+// Primal residual  R = -sum_d (F~_{d,+} - F~_{d,-})/dx_d + s  with the face flux
+//   F~ = r v_d (1, v, H) + P (0, e_d, v_d) - (0, sigma_d., u_f . sigma_d. + alpha d_d e)
+// where r, v, H, P are the face means of rho, u, E/rho and p (split product form of Kennedy &
+// Gruber, which conserves kinetic energy under convection; the paper's LES instead leans on the
+// dissipation of its upwind flux) [Physics, Eq. navier; Unsteady adjoint, vector form with source].
 // ------------------------------------------------------------------------------------------
 namespace {
 
-// LDS field order of the primal box
-enum { P_RHO = 0, P_U1, P_U2, P_U3, P_E, P_P, P_ET, P_NF };
+// LDS field order of the primal box (P_H: specific total energy E/rho)
+enum { P_RHO = 0, P_U1, P_U2, P_U3, P_E, P_P, P_H, P_NF };
 
-template <typename T, int NB>
-__device__ __forceinline__ void conv_flux(const T (*sm)[NB], int d, int q, T gm1, T F[5]) {
-  const T r = sm[P_RHO][q], u1 = sm[P_U1][q], u2 = sm[P_U2][q], u3 = sm[P_U3][q];
-  const T p = sm[P_P][q];
-  const T ud = d == 0 ? u1 : (d == 1 ? u2 : u3);
-  const T m = r * ud;
+// Convective flux through the direction-D face between box cells a (lower) and b.
+template <typename T, int NB, int D>
+__device__ __forceinline__ void conv_face(const T (*sm)[NB], int a, int b, T F[5]) {
+  const T r2 = sm[P_RHO][a] + sm[P_RHO][b];
+  const T v[3] = {T(0.5) * (sm[P_U1][a] + sm[P_U1][b]), T(0.5) * (sm[P_U2][a] + sm[P_U2][b]),
+                  T(0.5) * (sm[P_U3][a] + sm[P_U3][b])};
+  const T H2 = sm[P_H][a] + sm[P_H][b], P2 = sm[P_P][a] + sm[P_P][b];
+  const T m = T(0.5) * r2 * v[D];
   F[0] = m;
-  F[1] = m * u1 + (d == 0 ? p : T(0));
-  F[2] = m * u2 + (d == 1 ? p : T(0));
-  F[3] = m * u3 + (d == 2 ? p : T(0));
-  F[4] = (sm[P_ET][q] + p) * ud;
-  (void)gm1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) F[1 + k] = m * v[k] + (k == D ? T(0.5) * P2 : T(0));
+  F[4] = T(0.5) * (m * H2 + P2 * v[D]);
 }
 
 // Forward viscous stress row sigma_d. on the face between box cells A and A + e_d.
@@ -76,9 +78,9 @@ template <typename T, int NB, int D>
 __device__ __forceinline__ void residual_dir(const T (*sm)[NB], const int st[3], int p, const Consts<T>& c,
                                              T R[5]) {
   T Fp[5], Fm[5];
-  conv_flux<T, NB>(sm, D, p + st[D], c.gamma - T(1), Fp);
-  conv_flux<T, NB>(sm, D, p - st[D], c.gamma - T(1), Fm);
-  const T h = T(0.5) * c.idx[D];
+  conv_face<T, NB, D>(sm, p, p + st[D], Fp);
+  conv_face<T, NB, D>(sm, p - st[D], p, Fm);
+  const T h = c.idx[D];
 #pragma unroll
   for (int v = 0; v < 5; ++v) R[v] -= (Fp[v] - Fm[v]) * h;
   T Gp[4], Gm[4];
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, cons
       sm[P_U3][b] = u3;
       sm[P_E][b] = e;
       sm[P_P][b] = gm1 * r * e;
-      sm[P_ET][b] = Et;
+      sm[P_H][b] = Et * ri;
     }
   }
   const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
@@ -195,7 +197,11 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, cons
 // adjoint; Stabilizing adjoint equations: lambda sigma_1 delta_ki delta_jl term].
 //
 // Gather form for output cell j (all terms are the exact transpose of the primal residual):
-//   convective  sum_d A_d(W_j)^T (kh_{j+e_d} - kh_{j-e_d}) / (2 dx_d), A_d = dF_d/dw
+//   convective  each face f of j (direction d, cells L|R) with face means r, v, H, P and
+//               G = (kh_R - kh_L)/dx_d, phi = G_0 + v.G_m + H G_E, m = r v_d hands j half of
+//                 r^ = v_d phi,  v^ = m G_m + (r phi + P G_E) e_d,  H^ = m G_E,  P^ = G_m,d + v_d G_E
+//               (the adjoints of the face means; each mean is half of each cell's value);
+//               H^ and P^ then move to (rho, u, e) through E/rho = e + |u|^2/2, p = (gamma-1) rho e
 //   viscous     adjoint of the primitive fields (u^, e^) at j collected from
 //               - its six faces f (direction d, cells L|R):  G^ = (kh_L - kh_R)/dx_d,
 //                 sigma^_k = G^_mk + G^_E u_f,k,
@@ -204,16 +210,19 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, cons
 //                 heat part alpha G^_E / dx_d (to R with +, to L with -);
 //               - the tangential-gradient chain:  u^_j += sum_l (C_l(j-e_l) - C_l(j+e_l))/(2 dx_l)
 //                 with C_l(c) = 0.5 sum_{d != l} sum_{faces of c in d} (mu sigma^_l e_d - (2mu/3) sigma^_d e_l);
-//               then (u^, e^) -> conservative adjoint through u = m/rho, e = E/rho - |u|^2/2.
+//               then (rho^, u^, e^) -> conservative adjoint through u = m/rho, e = E/rho - |u|^2/2.
 //   L_nu        sum_d sum_{+-} nu_f (kh_nb - kh_j)/dx_d^2, nu_f = (nu_j + nu_nb)/2, no wall faces.
 // Slip walls: ghost cells carry mirrored primitives and kh = 0 (they own no residual); a cell
-// next to a wall adds M^T times the gather evaluated at its ghost image (M flips x-momentum).
+// next to a wall adds what its ghost image receives, mapped back through the mirror (u_x odd).
+// For the convective part that is the wall face's second half-share; the viscous part gathers
+// at the ghost image.
 //
-// Every face adjoint sigma^ is shared by six cells (the two it separates and four tangential
-// neighbours), so the kernel evaluates the faces once per work-group, one direction at a
-// time: a face-record buffer in LDS receives s~ = dx_d sigma^ and dK_E = kh_E,L - kh_E,R of all
-// direction-d faces of the box, plus the work term 0.5 G^_E sigma_d. of the faces bounding the
-// tile; the cells then gather from the records.  Three record phases reuse one buffer.
+// Every viscous face adjoint sigma^ is shared by six cells (the two it separates and four
+// tangential neighbours), so the kernel evaluates those faces once per work-group, one direction
+// at a time: a face-record buffer in LDS receives s~ = dx_d sigma^ and dK_E = kh_E,L - kh_E,R of
+// all direction-d faces of the box, plus the work term 0.5 G^_E sigma_d. of the faces bounding
+// the tile; the cells then gather from the records.  Three record phases reuse one buffer, which
+// before them holds rho, E/rho and p of the box for the convective gather.
 // ------------------------------------------------------------------------------------------
 namespace {
 
@@ -333,37 +342,42 @@ __device__ __forceinline__ void face_gather(const T (*fr)[NF], const T (*fq)[NQF
   }
 }
 
-template <typename T, int NB, int D>
-__device__ __forceinline__ void adj_conv_dir(const T (*sm)[NB], const int st[3], int p, const Consts<T>& c,
-                                             const T u[3], T H, T phi, T acc[5]) {
-  const T h = T(0.5) * c.idx[D];
-  T v[5];
+// Convective transpose at box cell p (own fields r0, u, H0, P0): half of the adjoint of every
+// face mean, accumulated as (rho^, u^, H^, P^).  The fields of the neighbours come from the LDS
+// planes K (kh), U (u) and Q (rho, E/rho, p).  wallside: the direction-0 face on this side is a
+// slip wall, whose ghost-image share (u^_x odd) folds into the cell as well.
+template <typename T, int NB, int NBQ, int D>
+__device__ __forceinline__ void adj_conv_dir(const T (*K)[NB], const T (*U)[NB], const T (*Q)[NBQ], int p, int sd,
+                                             const Consts<T>& c, T r0, const T u[3], T H0, T P0, const T k0[5],
+                                             bool wall_lo, bool wall_hi, T& rh, T uh[3], T& Hh, T& Ph) {
 #pragma unroll
-  for (int q = 0; q < 5; ++q) v[q] = (sm[A_K0 + q][p + st[D]] - sm[A_K0 + q][p - st[D]]) * h;
-  const T gm1 = c.gamma - T(1);
-  const T um = u[0] * v[1] + u[1] * v[2] + u[2] * v[3];
-  const T ud = u[D];
-  acc[0] += -ud * um + phi * v[1 + D] + ud * (phi - H) * v[4];
-  const T common = v[0] + um + H * v[4];
-  const T mdp = v[1 + D] + ud * v[4];
+  for (int side = 0; side < 2; ++side) {
+    const int q = side ? p + sd : p - sd;
+    const T sg = side ? c.idx[D] : -c.idx[D];
+    T G[5];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) acc[1 + j] += (j == D ? common : T(0)) + ud * v[1 + j] - gm1 * u[j] * mdp;
-  acc[4] += gm1 * v[1 + D] + c.gamma * ud * v[4];
+    for (int v = 0; v < 5; ++v) G[v] = sg * (K[v][q] - k0[v]);
+    const T r = T(0.5) * (r0 + Q[0][q]);
+    const T v[3] = {T(0.5) * (u[0] + U[0][q]), T(0.5) * (u[1] + U[1][q]), T(0.5) * (u[2] + U[2][q])};
+    const T H = T(0.5) * (H0 + Q[1][q]), P = T(0.5) * (P0 + Q[2][q]);
+    const T m = r * v[D];
+    const T phi = G[0] + v[0] * G[1] + v[1] * G[2] + v[2] * G[3] + H * G[4];
+    // own half-share, plus the ghost's half-share at a wall face (u^_x flips, the rest adds)
+    const bool wl = D == 0 && (side ? wall_hi : wall_lo);
+    const T h = wl ? T(1) : T(0.5), hx = wl ? T(0) : T(0.5);
+    rh += h * (v[D] * phi);
+    Hh += h * (m * G[4]);
+    Ph += h * (G[1 + D] + v[D] * G[4]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T t = m * G[1 + k] + (k == D ? r * phi + P * G[4] : T(0));
+      uh[k] += (k == 0 ? hx : h) * t;
+    }
+  }
 }
 
-// Convective transpose at box cell p with primitive velocity u and internal energy e.
-template <typename T, int NB>
-__device__ __forceinline__ void adj_conv(const T (*sm)[NB], const int st[3], int p, const Consts<T>& c, const T u[3],
-                                         T e, T acc[5]) {
-  const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  const T H = c.gamma * e + T(0.5) * usq;
-  const T phi = T(0.5) * (c.gamma - T(1)) * usq;
-  adj_conv_dir<T, NB, 0>(sm, st, p, c, u, H, phi, acc);
-  adj_conv_dir<T, NB, 1>(sm, st, p, c, u, H, phi, acc);
-  adj_conv_dir<T, NB, 2>(sm, st, p, c, u, H, phi, acc);
-}
-
-// (u^, e^) -> conservative adjoint at a cell with velocity u, internal energy e, 1/rho = ri.
+// (u^, e^) -> conservative adjoint at a cell with velocity u, internal energy e, 1/rho = ri
+// (the direct rho^ is added by the caller).
 template <typename T>
 __device__ __forceinline__ void prim_to_cons(const T u[3], T e, T ri, const T uh[3], T eh, T acc[5]) {
   const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -394,19 +408,24 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
   using F2 = FaceSet<TX, TY, TZ, HX, 2>;
   constexpr int NF = Max3<F0::N, F1::N, F2::N>::v;
   constexpr int NQF = Max3<F0::NQ, F1::NQ, F2::NQ>::v;
+  // one LDS region serves first as the (rho, E/rho, p) planes of the box, then as the face records
+  constexpr int NUN = 4 * NF + 3 * NQF > 3 * NB ? 4 * NF + 3 * NQF : 3 * NB;
   __shared__ T sm[LNU ? A_NU + 1 : A_NU][NB];
-  __shared__ T fr[4][NF];
-  __shared__ T fq[3][NQF];
+  __shared__ T un[NUN];
+  T (*fr)[NF] = reinterpret_cast<T (*)[NF]>(un);
+  T (*fq)[NQF] = reinterpret_cast<T (*)[NQF]>(un + 4 * NF);
+  T (*Q)[NB] = reinterpret_cast<T (*)[NB]>(un);
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
   const long long N = c.N;
+  const T gm1 = c.gamma - T(1);
   // all of this thread's box loads are issued before any is used: one memory latency, not NIT
   // (branch-free: the tail iteration re-reads the last box cell and does not store it; a missing
   // g_next is read as a with weight 0)
   constexpr int NIT = (NB + NT - 1) / NT;
   const T* __restrict__ gn = gnext ? gnext : a;
   const T cgn = gnext ? cg : T(0);
-  T wv[NIT][4], av[NIT][5], gv[NIT][5], nv[NIT];
+  T wv[NIT][5], av[NIT][5], gv[NIT][5], nv[NIT];
   int mir[NIT], rl[NIT];
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
@@ -414,7 +433,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
     const int bx = b % Bx::BX, by = (b / Bx::BX) % Bx::BY, bz = b / (Bx::BX * Bx::BY);
     const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - HX, y0 + by - 1, z0 + bz - 1, mir[it], rl[it]);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) wv[it][v] = W[v * N + gi];
+    for (int v = 0; v < 5; ++v) wv[it][v] = W[v * N + gi];
 #pragma unroll
     for (int v = 0; v < 5; ++v) av[it][v] = a[v * N + gi];
 #pragma unroll
@@ -425,10 +444,14 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
   for (int it = 0; it < NIT; ++it) {
     const int b = tid + it * NT;
     if (it + 1 < NIT || b < NB) {
-      const T ri = T(1) / wv[it][0];
-      sm[A_U1][b] = (mir[it] ? -wv[it][1] : wv[it][1]) * ri;
-      sm[A_U2][b] = wv[it][2] * ri;
-      sm[A_U3][b] = wv[it][3] * ri;
+      const T r = wv[it][0], ri = T(1) / r;
+      const T u1 = (mir[it] ? -wv[it][1] : wv[it][1]) * ri, u2 = wv[it][2] * ri, u3 = wv[it][3] * ri;
+      sm[A_U1][b] = u1;
+      sm[A_U2][b] = u2;
+      sm[A_U3][b] = u3;
+      Q[0][b] = r;
+      Q[1][b] = wv[it][4] * ri;
+      Q[2][b] = gm1 * (wv[it][4] - T(0.5) * r * (u1 * u1 + u2 * u2 + u3 * u3));
 #pragma unroll
       for (int v = 0; v < 5; ++v) sm[A_K0 + v][b] = rl[it] ? ca * av[it][v] + cgn * gv[it][v] : T(0);
       if (LNU) sm[LNU ? A_NU : 0][b] = rl[it] ? nv[it] : T(0);
@@ -443,9 +466,10 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
   const int st[3] = {1, Bx::SY, Bx::SZ};
   const int p = qz * Bx::SZ + qy * Bx::SY + qx;
   const long long gi = ((long long)(active ? gz : 0) * c.ny + (active ? gy : 0)) * c.nx + (active ? gx : 0);
-  T ri = T(0), e = T(0), uc[3] = {T(0), T(0), T(0)};
+  T r0 = T(1), ri = T(0), e = T(0), uc[3] = {T(0), T(0), T(0)};
   if (active) {
-    ri = T(1) / W[gi];
+    r0 = W[gi];
+    ri = T(1) / r0;
     uc[0] = W[N + gi] * ri;
     uc[1] = W[2 * N + gi] * ri;
     uc[2] = W[3 * N + gi] * ri;
@@ -464,8 +488,25 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
       f4[v] = g4[q];
     }
   }
-  T uh[3] = {T(0), T(0), T(0)}, eh = T(0);
+  T uh[3] = {T(0), T(0), T(0)}, eh = T(0), rh = T(0);
   T uhv[3] = {T(0), T(0), T(0)}, ehv = T(0);
+  __syncthreads();
+  if (active) {
+    // convective transpose, in (rho, u, E/rho, p), then moved to (rho, u, e)
+    const T H0 = e + T(0.5) * (uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]), P0 = gm1 * r0 * e;
+    T k0[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) k0[v] = sm[A_K0 + v][p];
+    const bool wlo = WALL && gx == 0, whi = WALL && gx == c.nx - 1;
+    T Hh = T(0), Ph = T(0);
+    adj_conv_dir<T, NB, NB, 0>(&sm[A_K0], &sm[A_U1], Q, p, st[0], c, r0, uc, H0, P0, k0, wlo, whi, rh, uh, Hh, Ph);
+    adj_conv_dir<T, NB, NB, 1>(&sm[A_K0], &sm[A_U1], Q, p, st[1], c, r0, uc, H0, P0, k0, false, false, rh, uh, Hh, Ph);
+    adj_conv_dir<T, NB, NB, 2>(&sm[A_K0], &sm[A_U1], Q, p, st[2], c, r0, uc, H0, P0, k0, false, false, rh, uh, Hh, Ph);
+    rh += gm1 * e * Ph;
+    eh += Hh + gm1 * r0 * Ph;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) uh[k] += Hh * uc[k];
+  }
   __syncthreads();
   face_records<T, TX, TY, TZ, HX, 0, NB, NF, NQF>(sm, fr, fq, st, c);
   __syncthreads();
@@ -482,8 +523,15 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
   if (active) face_gather<T, TX, TY, TZ, HX, 2, NF, NQF, false>(fr, fq, qx, qy, qz, c, uh, eh);
   if (virt) face_gather<T, TX, TY, TZ, HX, 2, NF, NQF, true>(fr, fq, vx, qy, qz, c, uhv, ehv);
   if (!active) return;
-  T g[5] = {T(0), T(0), T(0), T(0), T(0)};
-  adj_conv<T, NB>(sm, st, p, c, uc, e, g);
+  if (virt) {
+    // what the ghost image gathered from the viscous faces folds back through the mirror: the
+    // ghost carries the cell's rho and e and the velocity (-u_x, u_y, u_z)
+    uh[0] -= uhv[0];
+    uh[1] += uhv[1];
+    uh[2] += uhv[2];
+    eh += ehv;
+  }
+  T g[5] = {rh, T(0), T(0), T(0), T(0)};
   prim_to_cons(uc, e, ri, uh, eh, g);
   if (LNU) {
 #pragma unroll
@@ -498,20 +546,6 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
         for (int v = 0; v < 5; ++v) g[v] += nf * (sm[A_K0 + v][q] - sm[A_K0 + v][p]);
       }
     }
-  }
-  if (virt) {
-    // contributions through the mirror ghost of a wall cell: g += M^T gather(ghost); the ghost has
-    // the cell's rho and e and the mirrored velocity (-u_x, u_y, u_z)
-    const int pv = qz * Bx::SZ + qy * Bx::SY + vx;
-    const T um[3] = {-uc[0], uc[1], uc[2]};
-    T gv[5] = {T(0), T(0), T(0), T(0), T(0)};
-    adj_conv<T, NB>(sm, st, pv, c, um, e, gv);
-    prim_to_cons(um, e, ri, uhv, ehv, gv);
-    g[0] += gv[0];
-    g[1] -= gv[1];
-    g[2] += gv[2];
-    g[3] += gv[3];
-    g[4] += gv[4];
   }
   if (MODE == STAGE_VJP) {
 #pragma unroll
@@ -573,7 +607,8 @@ static void adjoint_tile(int mode, const Consts<T>& c, const T* W, const T* a, c
                        cg, g3, g4, out, grad_s);
 }
 
-// LDS bytes of one work-group of the reverse-stage kernel (box fields + face records + work terms)
+// LDS bytes of one work-group of the reverse-stage kernel (box fields + the region shared by the
+// convective planes and the face records / work terms)
 template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
 constexpr int adjoint_lds_bytes() {
   constexpr int HX = WALL ? 2 : 1;
@@ -581,8 +616,8 @@ constexpr int adjoint_lds_bytes() {
   using F0 = FaceSet<TX, TY, TZ, HX, 0>;
   using F1 = FaceSet<TX, TY, TZ, HX, 1>;
   using F2 = FaceSet<TX, TY, TZ, HX, 2>;
-  return (int)sizeof(T) * ((LNU ? A_NU + 1 : A_NU) * B::NB + 4 * Max3<F0::N, F1::N, F2::N>::v +
-                           3 * Max3<F0::NQ, F1::NQ, F2::NQ>::v);
+  constexpr int rec = 4 * Max3<F0::N, F1::N, F2::N>::v + 3 * Max3<F0::NQ, F1::NQ, F2::NQ>::v;
+  return (int)sizeof(T) * ((LNU ? A_NU + 1 : A_NU) * B::NB + (rec > 3 * B::NB ? rec : 3 * B::NB));
 }
 
 // Tile dispatch; a shape whose LDS footprint exceeds the 160 KB of a CU runs as 16x4x4.

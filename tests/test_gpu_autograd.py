@@ -119,7 +119,8 @@ def test_window_gradient_finite_differences_turbulence():
     J = CheckpointedWindow.apply(w0, st, spec)
     J.backward()
     grad = host(st.grad)
-    eps = 1e-5
+    # J carries ~1e-15 of rounding: eps = 1e-5 would leave ~3e-6 of noise in the quotient
+    eps = 1e-4
     for seed in range(10, 14):
         d = np.random.default_rng(seed).standard_normal(w0.numel())
         with torch.no_grad():
