@@ -13,8 +13,12 @@
  * Discretisation (identical in every entry point):
  *   - uniform Cartesian cells, n[d] cells over length L[d], dx_d = L[d]/n[d]; periodic in y, z;
  *     x periodic or slip walls (mirror ghost cell, x-momentum odd);
- *   - residual R(w; s) = -sum_d (F~_{d,+} - F~_{d,-})/dx_d + s, with F~ = 0.5 (F(w_L) + F(w_R))
- *     minus the viscous face flux (0, sigma_d., u_f . sigma_d. + alpha d_d e): normal face
+ *   - residual R(w; s) = -sum_d (F~_{d,+} - F~_{d,-})/dx_d + s, with the convective face flux
+ *     r v_d (1, v, H) + P (0, e_d, v_d) built from the face means r, v, H, P of rho, u, E/rho
+ *     and p (the kinetic-energy-preserving split form of Kennedy & Gruber, JCP 227, 2008: the
+ *     paper's own LES leans on the dissipation of its upwind flux, and a plain average of the two
+ *     cell fluxes diverges on under-resolved flows), minus the viscous face flux
+ *     (0, sigma_d., u_f . sigma_d. + alpha d_d e): normal face
  *     gradients (phi_R - phi_L)/dx_d, tangential ones the mean of the two cells' central
  *     differences; sigma = mu (grad u + grad u^T) - (2/3) mu (div u) I; alpha = gamma mu / Pr;
  *   - classical RK4 with fixed dt.
@@ -185,6 +189,60 @@ int adj_profile_read(int kernel_class, double* total_ms, long long* launches);
 enum { ADJ_TILE_16x4x4 = 0, ADJ_TILE_32x4x2 = 1, ADJ_TILE_32x4x4 = 2, ADJ_TILE_32x8x2 = 3, ADJ_NTILES = 4 };
 int adj_set_tile(int kernel_class, int precision, int tile);
 int adj_get_tile(int kernel_class, int precision);
+
+/* ---------------------------------------------------------------------------------------------
+ * Ensembles: many independent boxes (each its own adj_grid: size, dt, viscosity) and many adjoint
+ * sweeps ("members") in one launch per RK stage, the batched form of the calls above.  A member
+ * is one reverse sweep over the trajectory of its box with its own lambda, so several members of
+ * one box form a lambda sweep that recomputes the box's stage states once.
+ *
+ * Packed layout: ensemble arrays hold box after box (member after member), each in the
+ * single-box layout above.  State arrays (w, s) are packed over boxes: box b occupies elements
+ * [5 o_b, 5 o_{b+1}) with o_b = adj_batch_offset(batch, 0, b); adjoint arrays (w^, grad_s, dJ/dw)
+ * are packed over members with offsets adj_batch_offset(batch, 1, m).  A call that names
+ * `nbox` / `nmem` covers boxes [0, nbox) / members [0, nmem) only (ordering boxes by decreasing
+ * window length makes the live part of a window of uneven lengths such a prefix), so arrays need
+ * only hold that prefix.  Per-member FP64 scalars (weights, J, E) are device arrays indexed by
+ * member.  Every box shares precision and x boundary; states are stored natively.  The tile
+ * shapes in force when the ensemble is created (adj_set_tile) are the ones its launches use.
+ *
+ *   adj_batch_table_bytes : device bytes of the ensemble's descriptor table
+ *   adj_batch_create      : validates, writes the table into the caller's device memory `table`
+ *                           (256-byte aligned, blocking copy: call outside graph capture) and
+ *                           returns a host handle; member_box non-decreasing; obj NULL, NONE or
+ *                           MEAN_PRESSURE.  The table must outlive the handle.
+ *   adj_batch_destroy     : frees the host handle
+ *   adj_batch_offset      : which = 0 boxes, 1 members; index in [0, count] (count = the total)
+ *   adj_batch_workspace_bytes : scratch for every ensemble call (stage states of all boxes, stage
+ *                           adjoints of all members, sigma_1, partial sums)
+ *   adj_batch_primal_step : one RK4 step of boxes [0, nbox)                (adj_primal_step)
+ *   adj_batch_adjoint_step: one reverse RK4 step of members [0, nmem), recomputing the stage
+ *                           states of their boxes; nu = lambda_m sigma_1(w_n); then
+ *                           w^_n += c_n[m] dj/dw(w_n) when c_n (device double, per member) is
+ *                           non-NULL; grad_s (member-packed) += the source gradient if non-NULL
+ *                           (adj_adjoint_step, member by member)
+ *   adj_batch_objective_and_grad : members [first, first + count): J_accum[m] += weights[m] j(w of
+ *                           the member's box), dJ/dw (member-packed) += weights[m] dj/dw; either
+ *                           output may be NULL                             (adj_objective_and_grad)
+ *   adj_batch_energy_vhat : E[m] = adjoint energy of member m's w^ at its box's state w, members
+ *                           [0, nmem)                                      (adj_energy_vhat)
+ * Each member's fields equal those of the single-box calls bit for bit; FP64 scalars agree to
+ * rounding (the partial sums run in another order). */
+typedef struct adj_batch adj_batch;
+size_t adj_batch_table_bytes(int nbox, int nmem, int precision);
+int adj_batch_create(adj_batch** out, int nbox, const adj_grid* grids, const adj_objective* obj, int nmem,
+                     const int* member_box, const double* member_lambda, void* table, size_t table_bytes);
+void adj_batch_destroy(adj_batch* batch);
+long long adj_batch_offset(const adj_batch* batch, int which, int index);
+size_t adj_batch_workspace_bytes(const adj_batch* batch);
+int adj_batch_primal_step(const adj_batch* batch, int nbox, const void* w_n, const void* s, void* w_np1, void* ws,
+                          size_t ws_bytes, void* stream);
+int adj_batch_adjoint_step(const adj_batch* batch, int nmem, const void* w_n, const void* s, const void* wh_np1,
+                           const double* c_n, void* wh_n, void* grad_s, void* ws, size_t ws_bytes, void* stream);
+int adj_batch_objective_and_grad(const adj_batch* batch, int first, int count, const void* w, const double* weights,
+                                 double* J_accum, void* djdw, void* ws, size_t ws_bytes, void* stream);
+int adj_batch_energy_vhat(const adj_batch* batch, int nmem, const void* w, const void* wh, double* E, void* ws,
+                          size_t ws_bytes, void* stream);
 
 const char* adj_last_error(void);
 const char* adj_version(void);

@@ -85,6 +85,9 @@ EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjo
            "adj_adjoint_step_stages", "adj_growth_sigma1",
            "adj_objective_and_grad", "adj_energy_vhat", "adj_dot", "adj_ckpt_encode", "adj_ckpt_decode",
            "adj_residual", "adj_vjp", "adj_profile_enable", "adj_profile_read", "adj_set_tile", "adj_get_tile",
+           "adj_batch_table_bytes", "adj_batch_create", "adj_batch_destroy", "adj_batch_offset",
+           "adj_batch_workspace_bytes", "adj_batch_primal_step", "adj_batch_adjoint_step",
+           "adj_batch_objective_and_grad", "adj_batch_energy_vhat",
            "adj_last_error", "adj_version")
 
 
@@ -118,6 +121,16 @@ def lib():
                              ctypes.c_int),
         "adj_set_tile": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "adj_get_tile": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "adj_batch_table_bytes": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], sz),
+        "adj_batch_create": ([ctypes.POINTER(vp), ctypes.c_int, gp, op, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(dbl), vp, sz], ctypes.c_int),
+        "adj_batch_destroy": ([vp], None),
+        "adj_batch_offset": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_longlong),
+        "adj_batch_workspace_bytes": ([vp], sz),
+        "adj_batch_primal_step": ([vp, ctypes.c_int, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_batch_adjoint_step": ([vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_batch_objective_and_grad": ([vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_batch_energy_vhat": ([vp, ctypes.c_int, vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "adj_last_error": ([], ctypes.c_char_p),
         "adj_version": ([], ctypes.c_char_p),
     }
@@ -284,3 +297,94 @@ def get_tile(kernel_class, precision):
     if t < 0:
         _check(t)
     return t
+
+
+class Ensemble:
+    """Many boxes and adjoint members in one launch per stage (adj_batch_*).
+
+    grids: one Grid per box (same precision and x boundary); member_box: the box of each member
+    (non-decreasing); member_lam: lambda (L^2 units) of each member.  State arrays are packed
+    over boxes and adjoint arrays over members (see offset()); a call covering boxes [0, nbox)
+    or members [0, nmem) reads and writes only that prefix.
+    """
+
+    def __init__(self, grids, member_box, member_lam, obj=None, device="cuda"):
+        self.grids = list(grids)
+        self.member_box = [int(b) for b in member_box]
+        self.member_lam = [float(x) for x in member_lam]
+        nb, nm = len(self.grids), len(self.member_box)
+        if nm != len(self.member_lam):
+            raise ValueError("member_box and member_lam differ in length")
+        self.precision = self.grids[0].precision if nb else F64
+        self.dtype = torch.float64 if self.precision == F64 else torch.float32
+        L = lib()
+        tb = L.adj_batch_table_bytes(nb, nm, self.precision)
+        if tb == 0:
+            raise AdjError(-1, "an ensemble needs at least one box and one member")
+        self.table = torch.empty(tb, dtype=torch.uint8, device=device)
+        garr = (Grid * nb)(*self.grids)
+        marr = (ctypes.c_int * nm)(*self.member_box)
+        larr = (ctypes.c_double * nm)(*self.member_lam)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(L.adj_batch_create(ctypes.byref(h), nb, garr, ctypes.byref(obj) if obj is not None else None, nm,
+                                  marr, larr, _ptr(self.table, torch.uint8), ctypes.c_size_t(tb)))
+        self._h = h
+        self.nbox, self.nmem = nb, nm
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.adj_batch_destroy(h)
+            self._h = None
+
+    def offset(self, which, index):
+        """Cell offset of box (which = 0) or member (which = 1) `index`; index = count gives the total."""
+        o = lib().adj_batch_offset(self._h, int(which), int(index))
+        if o < 0:
+            raise AdjError(-1, f"offset({which}, {index}) out of range")
+        return o
+
+    def box_slice(self, t, b):
+        """View of box b's five fields in a box-packed tensor."""
+        return t[5 * self.offset(0, b):5 * self.offset(0, b + 1)]
+
+    def member_slice(self, t, m):
+        return t[5 * self.offset(1, m):5 * self.offset(1, m + 1)]
+
+    def workspace(self, device="cuda"):
+        return torch.empty(lib().adj_batch_workspace_bytes(self._h), dtype=torch.uint8, device=device)
+
+    def _packed(self, t, which, count):
+        if t is None:
+            return None
+        p = _ptr(t, self.dtype)
+        if t.numel() < 5 * self.offset(which, count):
+            raise ValueError(f"packed tensor holds {t.numel()} values, needs {5 * self.offset(which, count)}")
+        return p
+
+    def primal_step(self, nbox, w_n, s, w_np1, ws):
+        wp, wb = _ws(ws)
+        _check(lib().adj_batch_primal_step(self._h, int(nbox), self._packed(w_n, 0, nbox), self._packed(s, 0, nbox),
+                                           self._packed(w_np1, 0, nbox), wp, wb, _stream()))
+
+    def adjoint_step(self, nmem, w_n, s, wh_np1, wh_n, ws, c_n=None, grad_s=None):
+        nb = self.member_box[nmem - 1] + 1 if 0 < nmem <= self.nmem else 1
+        wp, wb = _ws(ws)
+        _check(lib().adj_batch_adjoint_step(self._h, int(nmem), self._packed(w_n, 0, nb), self._packed(s, 0, nb),
+                                            self._packed(wh_np1, 1, nmem), _ptr(c_n, torch.float64),
+                                            self._packed(wh_n, 1, nmem), self._packed(grad_s, 1, nmem), wp, wb,
+                                            _stream()))
+
+    def objective_and_grad(self, first, count, w, weights, ws, J_accum=None, djdw=None):
+        nb = self.member_box[first + count - 1] + 1 if 0 < count and first + count <= self.nmem else 1
+        wp, wb = _ws(ws)
+        _check(lib().adj_batch_objective_and_grad(self._h, int(first), int(count), self._packed(w, 0, nb),
+                                                  _ptr(weights, torch.float64), _ptr(J_accum, torch.float64),
+                                                  self._packed(djdw, 1, first + count), wp, wb, _stream()))
+
+    def energy_vhat(self, nmem, w, wh, E, ws):
+        nb = self.member_box[nmem - 1] + 1 if 0 < nmem <= self.nmem else 1
+        wp, wb = _ws(ws)
+        _check(lib().adj_batch_energy_vhat(self._h, int(nmem), self._packed(w, 0, nb), self._packed(wh, 1, nmem),
+                                           _ptr(E, torch.float64), wp, wb, _stream()))

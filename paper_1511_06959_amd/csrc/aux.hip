@@ -83,6 +83,30 @@ __device__ __forceinline__ Q64 load_q64(const Consts<T>& c, const T* __restrict_
 // [Symmetrization: S, V, T = S V, w^ = T^T v^; Energy Analysis: E_v^]
 // ------------------------------------------------------------------------------------------
 template <typename T>
+__device__ __forceinline__ double vhat_sq(const Consts<T>& c, const T* __restrict__ w, const T* __restrict__ wh,
+                                          const long long i, const double g, const double sa, const double sb) {
+  const long long N = c.N;
+  const Q64 q = load_q64(c, w, i, 0, g);
+  const double cs = sqrt(g * q.p * q.ri);
+  const double a = sa * cs, b = sb * cs;
+  double h[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) h[k] = (double)wh[k * N + i];
+  const double usq = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+  const double qr = h[0] + q.u[0] * h[1] + q.u[1] * h[2] + q.u[2] * h[3] + 0.5 * usq * h[4];
+  const double qp = h[4] / (g - 1.0);
+  const double v1 = (q.rho / b) * qr + q.rho * b * qp;
+  const double v5 = q.rho * a * qp;
+  double s = v1 * v1 + v5 * v5;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double qu = q.rho * (h[1 + k] + q.u[k] * h[4]);
+    s += qu * qu;
+  }
+  return s;
+}
+
+template <typename T>
 __global__ __launch_bounds__(RB) void k_energy_partial(Consts<T> c, const T* __restrict__ w,
                                                        const T* __restrict__ wh, double* __restrict__ partials) {
   __shared__ double sh[RB];
@@ -90,26 +114,8 @@ __global__ __launch_bounds__(RB) void k_energy_partial(Consts<T> c, const T* __r
   const double sa = sqrt((g - 1.0) / g), sb = 1.0 / sqrt(g);
   const long long N = c.N;
   double v = 0.0;
-  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < N; i += (long long)gridDim.x * RB) {
-    const Q64 q = load_q64(c, w, i, 0, g);
-    const double cs = sqrt(g * q.p * q.ri);
-    const double a = sa * cs, b = sb * cs;
-    double h[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) h[k] = (double)wh[k * N + i];
-    const double usq = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
-    const double qr = h[0] + q.u[0] * h[1] + q.u[1] * h[2] + q.u[2] * h[3] + 0.5 * usq * h[4];
-    const double qp = h[4] / (g - 1.0);
-    const double v1 = (q.rho / b) * qr + q.rho * b * qp;
-    const double v5 = q.rho * a * qp;
-    double s = v1 * v1 + v5 * v5;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double qu = q.rho * (h[1 + k] + q.u[k] * h[4]);
-      s += qu * qu;
-    }
-    v += s;
-  }
+  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < N; i += (long long)gridDim.x * RB)
+    v += vhat_sq(c, w, wh, i, g, sa, sb);
   const double tot = block_sum(v, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
@@ -185,10 +191,9 @@ __device__ __forceinline__ void jrot(T (&A)[5][5], int p, int q) {
   }
 }
 
+// sigma_1 of cell i (0 <= i < N)
 template <typename T>
-__global__ __launch_bounds__(RB) void k_sigma1(Consts<T> c, const T* __restrict__ w, T scale, T* __restrict__ out) {
-  const long long i = (long long)blockIdx.x * RB + threadIdx.x;
-  if (i >= c.N) return;
+__device__ __forceinline__ T sigma1_cell(const Consts<T>& c, const T* __restrict__ w, const long long i) {
   const int gx = (int)(i % c.nx);
   const int gy = (int)((i / c.nx) % c.ny);
   const int gz = (int)(i / ((long long)c.nx * c.ny));
@@ -254,7 +259,26 @@ __global__ __launch_bounds__(RB) void k_sigma1(Consts<T> c, const T* __restrict_
   T lm = A[0][0];
 #pragma unroll
   for (int r = 1; r < 5; ++r) lm = fmax(lm, A[r][r]);
-  out[i] = scale * sqrt(fmax(lm, T(0)));
+  return sqrt(fmax(lm, T(0)));
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_sigma1(Consts<T> c, const T* __restrict__ w, T scale, T* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * RB + threadIdx.x;
+  if (i >= c.N) return;
+  out[i] = scale * sigma1_cell(c, w, i);
+}
+
+// Ensemble form: RB cells of one box per work-group (offsets `start`), unscaled sigma_1.
+template <typename T>
+__global__ __launch_bounds__(RB) void k_sigma1_batch(const BoxDesc<T>* __restrict__ boxes,
+                                                     const int* __restrict__ start, int nbox, const T* __restrict__ w,
+                                                     T* __restrict__ out) {
+  const int b = find_box(start, nbox, blockIdx.x);
+  const Consts<T> c = boxes[b].c;
+  const long long i = (long long)(blockIdx.x - start[b]) * RB + threadIdx.x;
+  if (i >= c.N) return;
+  out[boxes[b].off + i] = sigma1_cell(c, w + 5 * boxes[b].off, i);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -284,6 +308,82 @@ __global__ __launch_bounds__(RB) void k_meanp(Consts<T> c, const T* __restrict__
   if (partials) {
     const double tot = block_sum(v, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  }
+}
+
+// Ensemble forms over members [first, first + count): RB cells of one member per work-group
+// (offsets `start`, block blk = blockIdx.x + start[first]); one FP64 partial per work-group, folded
+// per member by k_fold_members.  The per-cell gradient is the single-box formula with the
+// member's own weight and size.
+template <typename T>
+__global__ __launch_bounds__(RB) void k_meanp_batch(const BoxDesc<T>* __restrict__ mems,
+                                                    const int* __restrict__ start, int first, int count,
+                                                    const T* __restrict__ w, const double* __restrict__ wgt,
+                                                    double* __restrict__ partials, T* __restrict__ djdw) {
+  __shared__ double sh[RB];
+  const int blk = blockIdx.x + start[first];
+  const int m = find_box(start, first + count, blk);
+  const Consts<T> c = mems[m].c;
+  const double g = (double)c.gamma;
+  const long long N = c.N;
+  const long long i = (long long)(blk - start[m]) * RB + threadIdx.x;
+  double v = 0.0;
+  if (i < N) {
+    const Q64 q = load_q64(c, w + 5 * mems[m].off, i, 0, g);
+    v = q.p;
+    if (djdw) {
+      T* d = djdw + 5 * mems[m].aoff;
+      const double f = wgt[m] * (g - 1.0) / (double)N;
+      const double usq = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+      d[i] += (T)(f * 0.5 * usq);
+      d[N + i] += (T)(-f * q.u[0]);
+      d[2 * N + i] += (T)(-f * q.u[1]);
+      d[3 * N + i] += (T)(-f * q.u[2]);
+      d[4 * N + i] += (T)f;
+    }
+  }
+  if (partials) {
+    const double tot = block_sum(v, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_energy_batch(const BoxDesc<T>* __restrict__ mems,
+                                                     const int* __restrict__ start, int count,
+                                                     const T* __restrict__ w, const T* __restrict__ wh,
+                                                     double* __restrict__ partials) {
+  __shared__ double sh[RB];
+  const int m = find_box(start, count, blockIdx.x);
+  const Consts<T> c = mems[m].c;
+  const double g = (double)c.gamma;
+  const double sa = sqrt((g - 1.0) / g), sb = 1.0 / sqrt(g);
+  const long long N = c.N;
+  const long long i = (long long)(blockIdx.x - start[m]) * RB + threadIdx.x;
+  double v = 0.0;
+  if (i < N) v = vhat_sq(c, w + 5 * mems[m].off, wh + 5 * mems[m].aoff, i, g, sa, sb);
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// One work-group per member m = first + blockIdx.x: its partials in block order, then
+// dst[m] = dst[m] + (wgt[m] / N) sum   (objective)   or   dst[m] = sum / dV   (energy, wgt NULL).
+template <typename T>
+__global__ __launch_bounds__(RB) void k_fold_members(const double* __restrict__ partials, const int* __restrict__ start,
+                                                     int first, const BoxDesc<T>* __restrict__ mems,
+                                                     const double* __restrict__ wgt, double* __restrict__ dst) {
+  __shared__ double sh[RB];
+  const int m = first + blockIdx.x;
+  const int b0 = start[m] - start[first], b1 = start[m + 1] - start[first];
+  double v = 0.0;
+  for (int i = b0 + threadIdx.x; i < b1; i += RB) v += partials[i];
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    const Consts<T>& c = mems[m].c;
+    if (wgt)
+      dst[m] = dst[m] + (wgt[m] / (double)c.N) * tot;
+    else
+      dst[m] = (1.0 / ((double)c.dx[0] * (double)c.dx[1] * (double)c.dx[2])) * tot;
   }
 }
 
@@ -696,13 +796,49 @@ hipError_t launch_ckpt_decode(const Consts<float>& c, const float* header, const
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_sigma1_batch(const BoxDesc<T>* boxes, const int* start, int nbox, int nblocks, const T* w, T* out,
+                               hipStream_t st) {
+  ProfScope ps(ADJ_PROF_SIGMA1, st);
+  hipLaunchKernelGGL((k_sigma1_batch<T>), dim3(nblocks), dim3(RB), 0, st, boxes, start, nbox, w, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_meanp_batch(const BoxDesc<T>* mems, const int* start, const int* start_host, int first, int count,
+                              const T* w, const double* wgt, double* J_accum, T* djdw, double* partials,
+                              hipStream_t st) {
+  ProfScope ps(ADJ_PROF_OBJECTIVE, st);
+  const int nb = start_host[first + count] - start_host[first];
+  hipLaunchKernelGGL((k_meanp_batch<T>), dim3(nb), dim3(RB), 0, st, mems, start, first, count, w, wgt,
+                     J_accum ? partials : nullptr, djdw);
+  if (J_accum)
+    hipLaunchKernelGGL((k_fold_members<T>), dim3(count), dim3(RB), 0, st, partials, start, first, mems, wgt, J_accum);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_energy_batch(const BoxDesc<T>* mems, const int* start, const int* start_host, int count, const T* w,
+                               const T* wh, double* partials, double* E, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_REDUCE, st);
+  const int nb = start_host[count];
+  hipLaunchKernelGGL((k_energy_batch<T>), dim3(nb), dim3(RB), 0, st, mems, start, count, w, wh, partials);
+  hipLaunchKernelGGL((k_fold_members<T>), dim3(count), dim3(RB), 0, st, partials, start, 0, mems, nullptr, E);
+  return hipGetLastError();
+}
+
 #define ADJNS_INST(T)                                                                                          \
   template hipError_t launch_sigma1<T>(const Consts<T>&, const T*, T, T*, hipStream_t);                        \
   template hipError_t launch_dot<T>(const Consts<T>&, const T*, const T*, double*, double*, double, double,    \
                                     hipStream_t);                                                              \
   template hipError_t launch_energy_vhat<T>(const Consts<T>&, const T*, const T*, double*, double*, hipStream_t); \
   template hipError_t launch_objective<T>(const Consts<T>&, int, int, double, const T*, double, double*, T*,   \
-                                          double*, double*, hipStream_t);
+                                          double*, double*, hipStream_t);                                      \
+  template hipError_t launch_sigma1_batch<T>(const BoxDesc<T>*, const int*, int, int, const T*, T*, hipStream_t); \
+  template hipError_t launch_meanp_batch<T>(const BoxDesc<T>*, const int*, const int*, int, int, const T*,     \
+                                            const double*, double*, T*, double*, hipStream_t);                 \
+  template hipError_t launch_energy_batch<T>(const BoxDesc<T>*, const int*, const int*, int, const T*, const T*, \
+                                             double*, double*, hipStream_t);
 ADJNS_INST(float)
 ADJNS_INST(double)
 #undef ADJNS_INST

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/adjns.h"
 #include "kernels.hpp"
@@ -456,6 +457,360 @@ int adj_get_tile(int kernel_class, int precision) {
   if (kernel_class != ADJ_PROF_ADJOINT_STAGE && kernel_class != ADJ_PROF_PRIMAL_STAGE) return fail(ADJ_EINVAL, "bad class");
   if (precision != ADJ_F64 && precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", precision);
   return tile_choice(kernel_class, precision == ADJ_F64);
+}
+
+// ------------------------------------------------------------------------------------------
+// Ensembles
+// ------------------------------------------------------------------------------------------
+}  // extern "C"
+
+// Host side of an ensemble; the device table it points into belongs to the caller.
+struct adj_batch {
+  int nbox = 0, nmem = 0, fp64 = 0, wall = 0, lnu = 0, obj = ADJ_OBJ_NONE;
+  int tile_p = 0, tile_a = 0;
+  std::vector<long long> boff, moff;    // cell offsets of boxes / members (n + 1 entries)
+  std::vector<int> sp, sa, slb, slm;    // work-group offsets: primal tiles, adjoint tiles, RB cells
+  std::vector<int> mem_box;
+  const void *dbox = nullptr, *dmem = nullptr;
+  const int *dsp = nullptr, *dsa = nullptr, *dslb = nullptr, *dslm = nullptr;
+};
+
+namespace {
+
+struct BatchTable {
+  size_t box, mem, sp, sa, slb, slm, total;
+};
+
+BatchTable batch_table(int nbox, int nmem, int fp64) {
+  const size_t d = fp64 ? sizeof(BoxDesc<double>) : sizeof(BoxDesc<float>);
+  BatchTable t;
+  t.box = 0;
+  t.mem = t.box + up(nbox * d);
+  t.sp = t.mem + up(nmem * d);
+  t.sa = t.sp + up((nbox + 1) * sizeof(int));
+  t.slb = t.sa + up((nmem + 1) * sizeof(int));
+  t.slm = t.slb + up((nbox + 1) * sizeof(int));
+  t.total = t.slm + up((nmem + 1) * sizeof(int));
+  return t;
+}
+
+struct BatchWs {
+  size_t W2, W3, W4, sig, g4, g3, g2, partials, total;
+};
+
+BatchWs batch_ws(const adj_batch* b) {
+  const size_t e = b->fp64 ? sizeof(double) : sizeof(float);
+  const size_t P = (size_t)b->boff[b->nbox], Q = (size_t)b->moff[b->nmem];
+  BatchWs L;
+  L.W2 = 0;
+  L.W3 = L.W2 + up(5 * P * e);
+  L.W4 = L.W3 + up(5 * P * e);
+  L.sig = L.W4 + up(5 * P * e);
+  L.g4 = L.sig + up(P * e);
+  L.g3 = L.g4 + up(5 * Q * e);
+  L.g2 = L.g3 + up(5 * Q * e);
+  L.partials = L.g2 + up(5 * Q * e);
+  L.total = L.partials + up((size_t)b->slm[b->nmem] * sizeof(double));
+  return L;
+}
+
+template <typename T>
+BoxDesc<T> box_desc(const adj_grid* g, long long off, long long aoff, double lam) {
+  BoxDesc<T> d;
+  std::memset(&d, 0, sizeof d);
+  d.c = consts<T>(g);
+  d.off = off;
+  d.aoff = aoff;
+  d.lam = (T)lam;
+  return d;
+}
+
+int check_batch_ws(const adj_batch* b, const void* ws, size_t ws_bytes) {
+  if (!ws) return fail(ADJ_EWORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % ALIGN) return fail(ADJ_EWORKSPACE, "workspace must be 256-byte aligned");
+  const size_t need = batch_ws(b).total;
+  if (ws_bytes < need) return fail(ADJ_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  return ADJ_OK;
+}
+
+template <typename T>
+int batch_primal(const adj_batch* b, int nb, const T* wn, const T* s, T* out, void* ws, hipStream_t st) {
+  const BatchWs L = batch_ws(b);
+  T* W2 = (T*)at(ws, L.W2);
+  T* W3 = (T*)at(ws, L.W3);
+  T* W4 = (T*)at(ws, L.W4);
+  const auto* bx = (const BoxDesc<T>*)b->dbox;
+  const int nblk = b->sp[nb];
+  hipError_t e;
+  if ((e = launch_primal_stage_batch<T>(STAGE_LIN, b->tile_p, bx, b->dsp, nb, nblk, wn, wn, s, nullptr, nullptr,
+                                        T(0.5), W2, st)))
+    return hip_fail(e, "ensemble primal stage 1");
+  if ((e = launch_primal_stage_batch<T>(STAGE_LIN, b->tile_p, bx, b->dsp, nb, nblk, W2, wn, s, nullptr, nullptr,
+                                        T(0.5), W3, st)))
+    return hip_fail(e, "ensemble primal stage 2");
+  if ((e = launch_primal_stage_batch<T>(STAGE_LIN, b->tile_p, bx, b->dsp, nb, nblk, W3, wn, s, nullptr, nullptr,
+                                        T(1), W4, st)))
+    return hip_fail(e, "ensemble primal stage 3");
+  if ((e = launch_primal_stage_batch<T>(STAGE_FIN, b->tile_p, bx, b->dsp, nb, nblk, W4, wn, s, W2, W3, T(0), out, st)))
+    return hip_fail(e, "ensemble primal stage 4");
+  return ADJ_OK;
+}
+
+template <typename T>
+int batch_adjoint(const adj_batch* b, int nm, const T* wn, const T* s, const T* a, const double* c_n, T* wh,
+                  T* grad_s, void* ws, hipStream_t st) {
+  const BatchWs L = batch_ws(b);
+  T* W2 = (T*)at(ws, L.W2);
+  T* W3 = (T*)at(ws, L.W3);
+  T* W4 = (T*)at(ws, L.W4);
+  T* sig = (T*)at(ws, L.sig);
+  T* g4 = (T*)at(ws, L.g4);
+  T* g3 = (T*)at(ws, L.g3);
+  T* g2 = (T*)at(ws, L.g2);
+  const auto* bx = (const BoxDesc<T>*)b->dbox;
+  const auto* mm = (const BoxDesc<T>*)b->dmem;
+  const int nb = b->mem_box[nm - 1] + 1;  // boxes whose trajectory an active member reads
+  const int pblk = b->sp[nb];
+  hipError_t e;
+  if ((e = launch_primal_stage_batch<T>(STAGE_LIN, b->tile_p, bx, b->dsp, nb, pblk, wn, wn, s, nullptr, nullptr,
+                                        T(0.5), W2, st)))
+    return hip_fail(e, "ensemble recompute W2");
+  if ((e = launch_primal_stage_batch<T>(STAGE_LIN, b->tile_p, bx, b->dsp, nb, pblk, W2, wn, s, nullptr, nullptr,
+                                        T(0.5), W3, st)))
+    return hip_fail(e, "ensemble recompute W3");
+  if ((e = launch_primal_stage_batch<T>(STAGE_LIN, b->tile_p, bx, b->dsp, nb, pblk, W3, wn, s, nullptr, nullptr,
+                                        T(1), W4, st)))
+    return hip_fail(e, "ensemble recompute W4");
+  if (b->lnu && (e = launch_sigma1_batch<T>(bx, b->dslb, nb, b->slb[nb], wn, sig, st)))
+    return hip_fail(e, "ensemble sigma_1");
+  const int ablk = b->sa[nm];
+  const int tl = b->tile_a, wl = b->wall, ln = b->lnu;
+  if ((e = launch_adjoint_stage_batch<T>(STAGE_VJP, tl, wl, ln, mm, b->dsa, nm, ablk, W4, a, nullptr, sig, T(6), T(0),
+                                         nullptr, nullptr, g4, nullptr, st)))
+    return hip_fail(e, "ensemble adjoint stage 4");
+  if ((e = launch_adjoint_stage_batch<T>(STAGE_VJP, tl, wl, ln, mm, b->dsa, nm, ablk, W3, a, g4, sig, T(3), T(1),
+                                         nullptr, nullptr, g3, nullptr, st)))
+    return hip_fail(e, "ensemble adjoint stage 3");
+  if ((e = launch_adjoint_stage_batch<T>(STAGE_VJP, tl, wl, ln, mm, b->dsa, nm, ablk, W2, a, g3, sig, T(3), T(0.5),
+                                         nullptr, nullptr, g2, nullptr, st)))
+    return hip_fail(e, "ensemble adjoint stage 2");
+  if ((e = launch_adjoint_stage_batch<T>(STAGE_FIN, tl, wl, ln, mm, b->dsa, nm, ablk, wn, a, g2, sig, T(6), T(0.5), g3,
+                                         g4, wh, grad_s, st)))
+    return hip_fail(e, "ensemble adjoint stage 1");
+  if (c_n && b->obj == ADJ_OBJ_MEAN_PRESSURE) {
+    if ((e = launch_meanp_batch<T>(mm, b->dslm, b->slm.data(), 0, nm, wn, c_n, nullptr, wh,
+                                   (double*)at(ws, L.partials), st)))
+      return hip_fail(e, "ensemble objective gradient");
+  }
+  return ADJ_OK;
+}
+
+int check_batch(const adj_batch* b) {
+  if (!b) return fail(ADJ_EINVAL, "ensemble handle is NULL");
+  return ADJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t adj_batch_table_bytes(int nbox, int nmem, int precision) {
+  if (nbox < 1 || nmem < 1 || (precision != ADJ_F64 && precision != ADJ_F32)) return 0;
+  return batch_table(nbox, nmem, precision == ADJ_F64).total;
+}
+
+int adj_batch_create(adj_batch** out, int nbox, const adj_grid* grids, const adj_objective* obj, int nmem,
+                     const int* member_box, const double* member_lambda, void* table, size_t table_bytes) {
+  if (!out) return fail(ADJ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nbox < 1 || nmem < 1) return fail(ADJ_EINVAL, "an ensemble needs at least one box and one member");
+  if (!grids || !member_box || !member_lambda) return fail(ADJ_EINVAL, "grids, member_box and member_lambda must be non-NULL");
+  int r;
+  for (int i = 0; i < nbox; ++i) {
+    if ((r = check_grid(&grids[i], true))) return fail(r, "box %d: %s", i, g_err.c_str());
+    if (grids[i].precision != grids[0].precision) return fail(ADJ_EINVAL, "box %d: every box needs one precision", i);
+    if (grids[i].bc_x != grids[0].bc_x) return fail(ADJ_EINVAL, "box %d: every box needs one x boundary", i);
+    if (grids[i].ckpt_format != ADJ_CKPT_NATIVE) return fail(ADJ_EINVAL, "box %d: ensembles keep native states", i);
+  }
+  const int kind = obj ? obj->kind : ADJ_OBJ_NONE;
+  if (kind != ADJ_OBJ_NONE && kind != ADJ_OBJ_MEAN_PRESSURE)
+    return fail(ADJ_EINVAL, "ensembles support the mean-pressure objective (kind %d given)", kind);
+  for (int m = 0; m < nmem; ++m) {
+    if (member_box[m] < 0 || member_box[m] >= nbox) return fail(ADJ_EINVAL, "member %d: box %d out of range", m, member_box[m]);
+    if (m && member_box[m] < member_box[m - 1]) return fail(ADJ_EINVAL, "member boxes must be non-decreasing");
+    if (!(member_lambda[m] >= 0.0) || !std::isfinite(member_lambda[m]))
+      return fail(ADJ_EINVAL, "member %d: lambda must be finite and >= 0", m);
+  }
+  const int fp64 = grids[0].precision == ADJ_F64;
+  const BatchTable tb = batch_table(nbox, nmem, fp64);
+  if (!table || (uintptr_t)table % ALIGN) return fail(ADJ_EWORKSPACE, "table must be non-NULL and 256-byte aligned");
+  if (table_bytes < tb.total) return fail(ADJ_EWORKSPACE, "table has %zu bytes, needs %zu", table_bytes, tb.total);
+
+  adj_batch* b = new adj_batch;
+  b->nbox = nbox;
+  b->nmem = nmem;
+  b->fp64 = fp64;
+  b->wall = grids[0].bc_x == ADJ_BC_SLIP_WALLS;
+  b->obj = kind;
+  for (int m = 0; m < nmem; ++m) b->lnu |= member_lambda[m] > 0.0;
+  b->tile_p = tile_choice(ADJ_PROF_PRIMAL_STAGE, fp64);
+  b->tile_a = adjoint_tile_used(fp64, b->wall, b->lnu, tile_choice(ADJ_PROF_ADJOINT_STAGE, fp64));
+  int ptx, pty, ptz, atx, aty, atz;
+  tile_dims(b->tile_p, ptx, pty, ptz);
+  tile_dims(b->tile_a, atx, aty, atz);
+  auto tiles = [](const adj_grid& g, int tx, int ty, int tz) {
+    return (long long)((g.n[0] + tx - 1) / tx) * ((g.n[1] + ty - 1) / ty) * ((g.n[2] + tz - 1) / tz);
+  };
+  b->boff.assign(nbox + 1, 0);
+  b->sp.assign(nbox + 1, 0);
+  b->slb.assign(nbox + 1, 0);
+  long long sp = 0, slb = 0;
+  for (int i = 0; i < nbox; ++i) {
+    const long long N = ncells(&grids[i]);
+    b->boff[i + 1] = b->boff[i] + N;
+    sp += tiles(grids[i], ptx, pty, ptz);
+    slb += (N + RB - 1) / RB;
+    b->sp[i + 1] = (int)sp;
+    b->slb[i + 1] = (int)slb;
+  }
+  b->moff.assign(nmem + 1, 0);
+  b->sa.assign(nmem + 1, 0);
+  b->slm.assign(nmem + 1, 0);
+  b->mem_box.assign(member_box, member_box + nmem);
+  long long sa = 0, slm = 0;
+  for (int m = 0; m < nmem; ++m) {
+    const adj_grid& g = grids[member_box[m]];
+    const long long N = ncells(&g);
+    b->moff[m + 1] = b->moff[m] + N;
+    sa += tiles(g, atx, aty, atz);
+    slm += (N + RB - 1) / RB;
+    b->sa[m + 1] = (int)sa;
+    b->slm[m + 1] = (int)slm;
+  }
+  if (sp > INT32_MAX / 2 || sa > INT32_MAX / 2 || slb > INT32_MAX / 2 || slm > INT32_MAX / 2) {
+    delete b;
+    return fail(ADJ_ESHAPE, "ensemble too large for one launch");
+  }
+  // descriptors, written to the caller's device table with blocking copies
+  std::vector<char> hb(tb.total, 0);
+  for (int i = 0; i < nbox; ++i) {
+    if (fp64) {
+      const BoxDesc<double> d = box_desc<double>(&grids[i], b->boff[i], b->boff[i], 0.0);
+      std::memcpy(hb.data() + tb.box + i * sizeof d, &d, sizeof d);
+    } else {
+      const BoxDesc<float> d = box_desc<float>(&grids[i], b->boff[i], b->boff[i], 0.0);
+      std::memcpy(hb.data() + tb.box + i * sizeof d, &d, sizeof d);
+    }
+  }
+  for (int m = 0; m < nmem; ++m) {
+    const int i = member_box[m];
+    if (fp64) {
+      const BoxDesc<double> d = box_desc<double>(&grids[i], b->boff[i], b->moff[m], member_lambda[m]);
+      std::memcpy(hb.data() + tb.mem + m * sizeof d, &d, sizeof d);
+    } else {
+      const BoxDesc<float> d = box_desc<float>(&grids[i], b->boff[i], b->moff[m], member_lambda[m]);
+      std::memcpy(hb.data() + tb.mem + m * sizeof d, &d, sizeof d);
+    }
+  }
+  std::memcpy(hb.data() + tb.sp, b->sp.data(), (nbox + 1) * sizeof(int));
+  std::memcpy(hb.data() + tb.sa, b->sa.data(), (nmem + 1) * sizeof(int));
+  std::memcpy(hb.data() + tb.slb, b->slb.data(), (nbox + 1) * sizeof(int));
+  std::memcpy(hb.data() + tb.slm, b->slm.data(), (nmem + 1) * sizeof(int));
+  hipError_t e = hipMemcpy(table, hb.data(), tb.total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "ensemble table upload");
+  }
+  char* t = (char*)table;
+  b->dbox = t + tb.box;
+  b->dmem = t + tb.mem;
+  b->dsp = (const int*)(t + tb.sp);
+  b->dsa = (const int*)(t + tb.sa);
+  b->dslb = (const int*)(t + tb.slb);
+  b->dslm = (const int*)(t + tb.slm);
+  *out = b;
+  return ADJ_OK;
+}
+
+void adj_batch_destroy(adj_batch* batch) { delete batch; }
+
+long long adj_batch_offset(const adj_batch* batch, int which, int index) {
+  if (!batch) return -1;
+  if (which == 0) return (index < 0 || index > batch->nbox) ? -1 : batch->boff[index];
+  if (which == 1) return (index < 0 || index > batch->nmem) ? -1 : batch->moff[index];
+  return -1;
+}
+
+size_t adj_batch_workspace_bytes(const adj_batch* batch) { return batch ? batch_ws(batch).total : 0; }
+
+int adj_batch_primal_step(const adj_batch* batch, int nbox, const void* w_n, const void* s, void* w_np1, void* ws,
+                          size_t ws_bytes, void* stream) {
+  int r;
+  if ((r = check_batch(batch))) return r;
+  if (nbox < 1 || nbox > batch->nbox) return fail(ADJ_EINVAL, "nbox = %d outside [1, %d]", nbox, batch->nbox);
+  if ((r = check_batch_ws(batch, ws, ws_bytes))) return r;
+  if (!w_n || !w_np1) return fail(ADJ_EINVAL, "w_n and w_np1 must be non-NULL");
+  if (w_n == w_np1) return fail(ADJ_EINVAL, "w_np1 must not alias w_n");
+  hipStream_t st = (hipStream_t)stream;
+  if (batch->fp64)
+    return batch_primal<double>(batch, nbox, (const double*)w_n, (const double*)s, (double*)w_np1, ws, st);
+  return batch_primal<float>(batch, nbox, (const float*)w_n, (const float*)s, (float*)w_np1, ws, st);
+}
+
+int adj_batch_adjoint_step(const adj_batch* batch, int nmem, const void* w_n, const void* s, const void* wh_np1,
+                           const double* c_n, void* wh_n, void* grad_s, void* ws, size_t ws_bytes, void* stream) {
+  int r;
+  if ((r = check_batch(batch))) return r;
+  if (nmem < 1 || nmem > batch->nmem) return fail(ADJ_EINVAL, "nmem = %d outside [1, %d]", nmem, batch->nmem);
+  if ((r = check_batch_ws(batch, ws, ws_bytes))) return r;
+  if (!w_n || !wh_np1 || !wh_n) return fail(ADJ_EINVAL, "w_n, wh_np1 and wh_n must be non-NULL");
+  if (wh_n == wh_np1) return fail(ADJ_EINVAL, "wh_n must not alias wh_np1");
+  hipStream_t st = (hipStream_t)stream;
+  if (batch->fp64)
+    return batch_adjoint<double>(batch, nmem, (const double*)w_n, (const double*)s, (const double*)wh_np1, c_n,
+                                 (double*)wh_n, (double*)grad_s, ws, st);
+  return batch_adjoint<float>(batch, nmem, (const float*)w_n, (const float*)s, (const float*)wh_np1, c_n,
+                              (float*)wh_n, (float*)grad_s, ws, st);
+}
+
+int adj_batch_objective_and_grad(const adj_batch* batch, int first, int count, const void* w, const double* weights,
+                                 double* J_accum, void* djdw, void* ws, size_t ws_bytes, void* stream) {
+  int r;
+  if ((r = check_batch(batch))) return r;
+  if (first < 0 || count < 1 || first + count > batch->nmem)
+    return fail(ADJ_EINVAL, "members [%d, %d) outside [0, %d)", first, first + count, batch->nmem);
+  if ((r = check_batch_ws(batch, ws, ws_bytes))) return r;
+  if (!w || !weights) return fail(ADJ_EINVAL, "w and weights must be non-NULL");
+  if (batch->obj == ADJ_OBJ_NONE) return ADJ_OK;
+  const BatchWs L = batch_ws(batch);
+  hipError_t e;
+  hipStream_t st = (hipStream_t)stream;
+  if (batch->fp64)
+    e = launch_meanp_batch<double>((const BoxDesc<double>*)batch->dmem, batch->dslm, batch->slm.data(), first, count,
+                                   (const double*)w, weights, J_accum, (double*)djdw, (double*)at(ws, L.partials), st);
+  else
+    e = launch_meanp_batch<float>((const BoxDesc<float>*)batch->dmem, batch->dslm, batch->slm.data(), first, count,
+                                  (const float*)w, weights, J_accum, (float*)djdw, (double*)at(ws, L.partials), st);
+  return e ? hip_fail(e, "ensemble objective") : ADJ_OK;
+}
+
+int adj_batch_energy_vhat(const adj_batch* batch, int nmem, const void* w, const void* wh, double* E, void* ws,
+                          size_t ws_bytes, void* stream) {
+  int r;
+  if ((r = check_batch(batch))) return r;
+  if (nmem < 1 || nmem > batch->nmem) return fail(ADJ_EINVAL, "nmem = %d outside [1, %d]", nmem, batch->nmem);
+  if ((r = check_batch_ws(batch, ws, ws_bytes))) return r;
+  if (!w || !wh || !E) return fail(ADJ_EINVAL, "w, wh and E must be non-NULL");
+  const BatchWs L = batch_ws(batch);
+  hipError_t e;
+  hipStream_t st = (hipStream_t)stream;
+  if (batch->fp64)
+    e = launch_energy_batch<double>((const BoxDesc<double>*)batch->dmem, batch->dslm, batch->slm.data(), nmem,
+                                    (const double*)w, (const double*)wh, (double*)at(ws, L.partials), E, st);
+  else
+    e = launch_energy_batch<float>((const BoxDesc<float>*)batch->dmem, batch->dslm, batch->slm.data(), nmem,
+                                   (const float*)w, (const float*)wh, (double*)at(ws, L.partials), E, st);
+  return e ? hip_fail(e, "ensemble energy") : ADJ_OK;
 }
 
 const char* adj_last_error(void) { return g_err.c_str(); }

@@ -38,6 +38,31 @@ struct Consts {
   T gamma, mu, alpha, dt;
 };
 
+// One box of an ensemble (batched launches).  Ensemble arrays are packed box after box: the
+// fields of a box start at element 5 * off (state arrays of the boxes) or 5 * aoff (adjoint
+// arrays of the members), scalar fields at off; inside a box the layout is the single-box one.
+// A member is one adjoint sweep over the trajectory of its box (several members of one box form
+// a lambda sweep); for a box entry aoff = off and lam = 0.
+template <typename T>
+struct BoxDesc {
+  Consts<T> c;
+  long long off, aoff;
+  T lam;  // artificial viscosity coefficient: nu = lam * sigma_1
+};
+
+// Index of the box that owns work-group `blk` of a batched launch, given the non-decreasing work
+// offsets start[0..n] (start[b] = first work-group of box b).  Every wavefront computes it with
+// one vector load and a ballot per 64 boxes; the result is wavefront-uniform.
+__device__ __forceinline__ int find_box(const int* __restrict__ start, int n, int blk) {
+  int b = 0;
+  for (int base = 0; base < n; base += 64) {
+    const int i = base + (int)__lane_id();
+    const bool before = i < n && start[i + 1] <= blk;
+    b += __popcll(__ballot(before));
+  }
+  return __builtin_amdgcn_readfirstlane(b);
+}
+
 __device__ __forceinline__ int wrap_index(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;

@@ -33,6 +33,30 @@ template <typename T>
 hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt_ref, const T* w, double weight,
                             double* J_accum, T* djdw, double* partials, double* scratch, hipStream_t st);
 
+// Ensemble launchers (packed arrays, work-group offsets `start` on the device; see BoxDesc).
+// The stencil launches cover boxes / members [0, n) in nblocks work-groups of the given tile.
+void tile_dims(int tile, int& tx, int& ty, int& tz);
+int adjoint_tile_used(int fp64, int wall, int lnu, int tile);  // tile after the LDS fit
+template <typename T>
+hipError_t launch_primal_stage_batch(int mode, int tile, const BoxDesc<T>* boxes, const int* start, int nbox,
+                                     int nblocks, const T* W, const T* wn, const T* s, const T* W2, const T* W3,
+                                     T cfac, T* out, hipStream_t st);
+template <typename T>
+hipError_t launch_adjoint_stage_batch(int mode, int tile, int wall, int lnu, const BoxDesc<T>* mems, const int* start,
+                                      int nmem, int nblocks, const T* W, const T* a, const T* gnext, const T* sigma1,
+                                      T da, T mg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st);
+template <typename T>
+hipError_t launch_sigma1_batch(const BoxDesc<T>* boxes, const int* start, int nbox, int nblocks, const T* w, T* out,
+                               hipStream_t st);
+// members [first, first + count); start_host mirrors start on the host
+template <typename T>
+hipError_t launch_meanp_batch(const BoxDesc<T>* mems, const int* start, const int* start_host, int first, int count,
+                              const T* w, const double* wgt, double* J_accum, T* djdw, double* partials,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_energy_batch(const BoxDesc<T>* mems, const int* start, const int* start_host, int count, const T* w,
+                               const T* wh, double* partials, double* E, hipStream_t st);
+
 // BF16 checkpoint codec; header = 10 floats (mean, scale) x 5 at the start of the record
 hipError_t launch_ckpt_encode(const Consts<float>& c, const float* w, float* header, uint16_t* codes,
                               float* partials, hipStream_t st);

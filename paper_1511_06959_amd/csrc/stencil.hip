@@ -97,17 +97,17 @@ __device__ __forceinline__ void residual_dir(const T (*sm)[NB], const int st[3],
 //       FIN  out = (W2 + 2 W3 + W - wn)/3 + (dt/6) R(W; s)      (stage 4, W = W4;
 //            equals wn + dt/6 (k1 + 2 k2 + 2 k3 + k4) since k1 = 2(W2-wn)/dt, k2 = 2(W3-wn)/dt,
 //            k3 = (W4-wn)/dt)
+// One work-group: the tile with origin (x0, y0, z0).
 template <typename T, int MODE, int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, const T* __restrict__ W,
-                                                               const T* __restrict__ wn, const T* __restrict__ s,
-                                                               const T* __restrict__ W2, const T* __restrict__ W3,
-                                                               T cR, T* __restrict__ out) {
+__device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x0, const int y0, const int z0,
+                                                 const T* __restrict__ W, const T* __restrict__ wn,
+                                                 const T* __restrict__ s, const T* __restrict__ W2,
+                                                 const T* __restrict__ W3, const T cR, T* __restrict__ out) {
   constexpr int NT = TX * TY * TZ;
   using Bx = TBox<TX, TY, TZ, 1, 1>;
   constexpr int NB = Bx::NB;
   __shared__ T sm[P_NF][NB];
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
   const long long N = c.N;
   const T gm1 = c.gamma - T(1);
   // all of this thread's box loads are issued before any is used: one memory latency, not NIT
@@ -189,6 +189,34 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, cons
       out[q] = (base[v] + W[q]) * third + h6 * R[v];
     }
   }
+}
+
+template <typename T, int MODE, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, const T* __restrict__ W,
+                                                               const T* __restrict__ wn, const T* __restrict__ s,
+                                                               const T* __restrict__ W2, const T* __restrict__ W3,
+                                                               T cR, T* __restrict__ out) {
+  primal_tile_body<T, MODE, TX, TY, TZ>(c, blockIdx.x * TX, blockIdx.y * TY, blockIdx.z * TZ, W, wn, s, W2, W3, cR,
+                                        out);
+}
+
+// Ensemble form: work-group -> (box, tile) through the tile offsets `start`; every array is
+// packed box after box.  cfac scales the box's own dt into the stage coefficient.
+template <typename T, int MODE, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage_batch(const BoxDesc<T>* __restrict__ boxes,
+                                                                     const int* __restrict__ start, int nbox,
+                                                                     const T* __restrict__ W, const T* __restrict__ wn,
+                                                                     const T* __restrict__ s, const T* __restrict__ W2,
+                                                                     const T* __restrict__ W3, T cfac,
+                                                                     T* __restrict__ out) {
+  const int b = find_box(start, nbox, blockIdx.x);
+  const Consts<T> c = boxes[b].c;
+  const long long o = 5 * boxes[b].off;
+  const int t = blockIdx.x - start[b];
+  const int ntx = (c.nx + TX - 1) / TX, nty = (c.ny + TY - 1) / TY;
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  primal_tile_body<T, MODE, TX, TY, TZ>(c, tx * TX, ty * TY, tz * TZ, W + o, wn + o, s ? s + o : nullptr,
+                                        W2 ? W2 + o : nullptr, W3 ? W3 + o : nullptr, c.dt * cfac, out + o);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -393,12 +421,14 @@ __device__ __forceinline__ void prim_to_cons(const T u[3], T e, T ri, const T uh
 // MODE: STAGE_VJP  out = g = J^T kh (+ L_nu kh)
 //       STAGE_FIN  (RK4 stage 1) g1 = J(w_n)^T kh + ...; out = w^_n = a + g1 + gnext + g3 + g4;
 //                  grad_s += dt a + dt g4 + dt/2 (g3 + gnext)   (= k^1 + k^2 + k^3 + k^4)
+// One work-group: the tile with origin (x0, y0, z0); the artificial viscosity is nscale * nu.
 template <typename T, int MODE, int WALL, int LNU, int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, const T* __restrict__ W,
-                                                                const T* __restrict__ a, const T* __restrict__ gnext,
-                                                                const T* __restrict__ nu, T ca, T cg,
-                                                                const T* __restrict__ g3, const T* __restrict__ g4,
-                                                                T* __restrict__ out, T* __restrict__ grad_s) {
+__device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int x0, const int y0, const int z0,
+                                                  const T* __restrict__ W, const T* __restrict__ a,
+                                                  const T* __restrict__ gnext, const T* __restrict__ nu,
+                                                  const T nscale, const T ca, const T cg, const T* __restrict__ g3,
+                                                  const T* __restrict__ g4, T* __restrict__ out,
+                                                  T* __restrict__ grad_s) {
   constexpr int NT = TX * TY * TZ;
   constexpr int HX = WALL ? 2 : 1;
   using Bx = TBox<TX, TY, TZ, HX, 1>;
@@ -416,7 +446,6 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
   T (*fq)[NQF] = reinterpret_cast<T (*)[NQF]>(un + 4 * NF);
   T (*Q)[NB] = reinterpret_cast<T (*)[NB]>(un);
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
   const long long N = c.N;
   const T gm1 = c.gamma - T(1);
   // all of this thread's box loads are issued before any is used: one memory latency, not NIT
@@ -438,7 +467,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
     for (int v = 0; v < 5; ++v) av[it][v] = a[v * N + gi];
 #pragma unroll
     for (int v = 0; v < 5; ++v) gv[it][v] = gn[v * N + gi];
-    nv[it] = LNU ? nu[gi] : T(0);
+    nv[it] = LNU ? nscale * nu[gi] : T(0);
   }
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
@@ -556,9 +585,40 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
     for (int v = 0; v < 5; ++v) {
       const long long q = v * N + gi;
       out[q] = fa[v] + g[v] + f2[v] + f3[v] + f4[v];
-      if (grad_s) grad_s[q] += dt * fa[v] + dt * f4[v] + h2 * (f3[v] + f2[v]);
+      // explicit fused order: every instantiation (and the ensemble form) rounds identically
+      if (grad_s) grad_s[q] = fma(dt, fa[v], fma(dt, f4[v], fma(h2, f3[v] + f2[v], grad_s[q])));
     }
   }
+}
+
+template <typename T, int MODE, int WALL, int LNU, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, const T* __restrict__ W,
+                                                                const T* __restrict__ a, const T* __restrict__ gnext,
+                                                                const T* __restrict__ nu, T ca, T cg,
+                                                                const T* __restrict__ g3, const T* __restrict__ g4,
+                                                                T* __restrict__ out, T* __restrict__ grad_s) {
+  adjoint_tile_body<T, MODE, WALL, LNU, TX, TY, TZ>(c, blockIdx.x * TX, blockIdx.y * TY, blockIdx.z * TZ, W, a,
+                                                    gnext, nu, T(1), ca, cg, g3, g4, out, grad_s);
+}
+
+// Ensemble form over the members: state arrays (W, the sigma_1 field) at the member's box,
+// adjoint arrays at the member itself; nu = lam * sigma_1; ca = dt / da, cg = dt * mg with the
+// member's own dt (the same operations the single-box launch performs on the host).
+template <typename T, int MODE, int WALL, int LNU, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage_batch(
+    const BoxDesc<T>* __restrict__ mems, const int* __restrict__ start, int nmem, const T* __restrict__ W,
+    const T* __restrict__ a, const T* __restrict__ gnext, const T* __restrict__ sigma1, T da, T mg,
+    const T* __restrict__ g3, const T* __restrict__ g4, T* __restrict__ out, T* __restrict__ grad_s) {
+  const int m = find_box(start, nmem, blockIdx.x);
+  const Consts<T> c = mems[m].c;
+  const long long o = 5 * mems[m].off, ao = 5 * mems[m].aoff;
+  const int t = blockIdx.x - start[m];
+  const int ntx = (c.nx + TX - 1) / TX, nty = (c.ny + TY - 1) / TY;
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  adjoint_tile_body<T, MODE, WALL, LNU, TX, TY, TZ>(
+      c, tx * TX, ty * TY, tz * TZ, W + o, a + ao, gnext ? gnext + ao : nullptr, LNU ? sigma1 + mems[m].off : nullptr,
+      mems[m].lam, c.dt / da, c.dt * mg, g3 ? g3 + ao : nullptr, g4 ? g4 + ao : nullptr, out + ao,
+      grad_s ? grad_s + ao : nullptr);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -658,6 +718,139 @@ hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const 
   }
   return hipGetLastError();
 }
+
+// ------------------------------------------------------------------------------------------
+// Ensemble launchers: one launch covers the first nbox boxes (or members) of the packed arrays;
+// the tile shape is fixed when the ensemble is set up, so that `start` matches it.
+// ------------------------------------------------------------------------------------------
+void tile_dims(int tile, int& tx, int& ty, int& tz) {
+  switch (tile) {
+    case TILE_16x4x4: tx = 16; ty = 4; tz = 4; break;
+    case TILE_32x4x2: tx = 32; ty = 4; tz = 2; break;
+    case TILE_32x4x4: tx = 32; ty = 4; tz = 4; break;
+    default: tx = 32; ty = 8; tz = 2; break;
+  }
+}
+
+template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
+static int fit_tile(int tile) {
+  return adjoint_lds_bytes<T, WALL, LNU, TX, TY, TZ>() <= 160 * 1024 ? tile : (int)TILE_16x4x4;
+}
+
+template <typename T, int WALL, int LNU>
+static int fit_variant(int tile) {
+  switch (tile) {
+    case TILE_16x4x4: return fit_tile<T, WALL, LNU, 16, 4, 4>(tile);
+    case TILE_32x4x2: return fit_tile<T, WALL, LNU, 32, 4, 2>(tile);
+    case TILE_32x4x4: return fit_tile<T, WALL, LNU, 32, 4, 4>(tile);
+    default: return fit_tile<T, WALL, LNU, 32, 8, 2>(TILE_32x8x2);
+  }
+}
+
+int adjoint_tile_used(int fp64, int wall, int lnu, int tile) {
+  if (fp64) {
+    if (wall) return lnu ? fit_variant<double, 1, 1>(tile) : fit_variant<double, 1, 0>(tile);
+    return lnu ? fit_variant<double, 0, 1>(tile) : fit_variant<double, 0, 0>(tile);
+  }
+  if (wall) return lnu ? fit_variant<float, 1, 1>(tile) : fit_variant<float, 1, 0>(tile);
+  return lnu ? fit_variant<float, 0, 1>(tile) : fit_variant<float, 0, 0>(tile);
+}
+
+template <typename T, int TX, int TY, int TZ>
+static void primal_batch_tile(int mode, const BoxDesc<T>* boxes, const int* start, int nbox, int nblocks, const T* W,
+                              const T* wn, const T* s, const T* W2, const T* W3, T cfac, T* out, hipStream_t st) {
+  const dim3 grid(nblocks), blk(TX * TY * TZ);
+  if (mode == STAGE_RES)
+    hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_RES, TX, TY, TZ>), grid, blk, 0, st, boxes, start, nbox, W, wn,
+                       s, W2, W3, cfac, out);
+  else if (mode == STAGE_LIN)
+    hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_LIN, TX, TY, TZ>), grid, blk, 0, st, boxes, start, nbox, W, wn,
+                       s, W2, W3, cfac, out);
+  else
+    hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_FIN, TX, TY, TZ>), grid, blk, 0, st, boxes, start, nbox, W, wn,
+                       s, W2, W3, cfac, out);
+}
+
+template <typename T>
+hipError_t launch_primal_stage_batch(int mode, int tile, const BoxDesc<T>* boxes, const int* start, int nbox,
+                                     int nblocks, const T* W, const T* wn, const T* s, const T* W2, const T* W3,
+                                     T cfac, T* out, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st);
+  switch (tile) {
+    case TILE_16x4x4: primal_batch_tile<T, 16, 4, 4>(mode, boxes, start, nbox, nblocks, W, wn, s, W2, W3, cfac, out, st); break;
+    case TILE_32x4x2: primal_batch_tile<T, 32, 4, 2>(mode, boxes, start, nbox, nblocks, W, wn, s, W2, W3, cfac, out, st); break;
+    case TILE_32x4x4: primal_batch_tile<T, 32, 4, 4>(mode, boxes, start, nbox, nblocks, W, wn, s, W2, W3, cfac, out, st); break;
+    default: primal_batch_tile<T, 32, 8, 2>(mode, boxes, start, nbox, nblocks, W, wn, s, W2, W3, cfac, out, st); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
+static void adjoint_batch_tile(int mode, const BoxDesc<T>* mems, const int* start, int nmem, int nblocks, const T* W,
+                               const T* a, const T* gnext, const T* sigma1, T da, T mg, const T* g3, const T* g4,
+                               T* out, T* grad_s, hipStream_t st) {
+  if constexpr (adjoint_lds_bytes<T, WALL, LNU, TX, TY, TZ>() <= 160 * 1024) {
+    const dim3 grid(nblocks), blk(TX * TY * TZ);
+    if (mode == STAGE_VJP)
+      hipLaunchKernelGGL((k_adjoint_stage_batch<T, STAGE_VJP, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, mems, start,
+                         nmem, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s);
+    else
+      hipLaunchKernelGGL((k_adjoint_stage_batch<T, STAGE_FIN, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, mems, start,
+                         nmem, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s);
+  } else {
+    adjoint_batch_tile<T, WALL, LNU, 16, 4, 4>(mode, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4,
+                                               out, grad_s, st);
+  }
+}
+
+template <typename T, int WALL, int LNU>
+static void adjoint_batch_variant(int mode, int tile, const BoxDesc<T>* mems, const int* start, int nmem, int nblocks,
+                                  const T* W, const T* a, const T* gnext, const T* sigma1, T da, T mg, const T* g3,
+                                  const T* g4, T* out, T* grad_s, hipStream_t st) {
+  switch (tile) {
+    case TILE_16x4x4:
+      adjoint_batch_tile<T, WALL, LNU, 16, 4, 4>(mode, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
+      break;
+    case TILE_32x4x2:
+      adjoint_batch_tile<T, WALL, LNU, 32, 4, 2>(mode, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
+      break;
+    case TILE_32x4x4:
+      adjoint_batch_tile<T, WALL, LNU, 32, 4, 4>(mode, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
+      break;
+    default:
+      adjoint_batch_tile<T, WALL, LNU, 32, 8, 2>(mode, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
+      break;
+  }
+}
+
+template <typename T>
+hipError_t launch_adjoint_stage_batch(int mode, int tile, int wall, int lnu, const BoxDesc<T>* mems, const int* start,
+                                      int nmem, int nblocks, const T* W, const T* a, const T* gnext, const T* sigma1,
+                                      T da, T mg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st);
+  if (wall) {
+    if (lnu)
+      adjoint_batch_variant<T, 1, 1>(mode, tile, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
+    else
+      adjoint_batch_variant<T, 1, 0>(mode, tile, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
+  } else {
+    if (lnu)
+      adjoint_batch_variant<T, 0, 1>(mode, tile, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
+    else
+      adjoint_batch_variant<T, 0, 0>(mode, tile, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
+  }
+  return hipGetLastError();
+}
+
+#define ADJNS_BATCH_INST(T)                                                                                        \
+  template hipError_t launch_primal_stage_batch<T>(int, int, const BoxDesc<T>*, const int*, int, int, const T*,   \
+                                                   const T*, const T*, const T*, const T*, T, T*, hipStream_t);  \
+  template hipError_t launch_adjoint_stage_batch<T>(int, int, int, int, const BoxDesc<T>*, const int*, int, int,  \
+                                                    const T*, const T*, const T*, const T*, T, T, const T*,       \
+                                                    const T*, T*, T*, hipStream_t);
+ADJNS_BATCH_INST(float)
+ADJNS_BATCH_INST(double)
+#undef ADJNS_BATCH_INST
 
 template hipError_t launch_primal_stage<float>(int, const Consts<float>&, const float*, const float*, const float*,
                                                const float*, const float*, float, float*, hipStream_t);

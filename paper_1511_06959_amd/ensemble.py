@@ -1,0 +1,156 @@
+"""Ensembles of uneven adjoint windows and lambda sweeps, batched through the adj_batch_* calls.
+
+Each box runs its own window of T_b RK4 steps from w_0 with the time-averaged objective
+J_b = (1/T_b) sum_{n=1..T_b} j(w_n) (the rectangle rule of the averaged objectives of the paper,
+Eqs. (1)-(3)); each member is one reverse sweep over its box's trajectory with its own lambda
+("Stabilizing adjoint equations").  Boxes are ordered by non-increasing window length, so at
+step t the boxes still running form a prefix of the packed arrays and one launch per RK stage
+covers all of them; the whole ensemble window is then captured as two HIP graphs.
+
+The trajectory of the ensemble is stored whole: slot t keeps w_t of the boxes with T_b >= t
+(natively, in the state precision), so it holds sum_b 5 N_b (T_b + 1) values.  The reverse sweep
+recomputes the inner RK4 stage states of each step inside the batched adjoint step.
+
+Only scheduling happens here; all arithmetic runs in the library's kernels.
+"""
+import bisect
+
+import torch
+
+from . import F64, OBJ_MEAN_PRESSURE, Ensemble, Objective
+
+
+class EnsembleWindow:
+    """Forward and reverse sweep of an ensemble.
+
+    grids:      one Grid per box (same precision and x boundary), ordered by non-increasing window
+    windows:    T_b per box (>= 1)
+    w0, s:      lists of per-box initial states / sources (s may be None, or a list with Nones
+                replaced by zeros)
+    member_box: box of each member (non-decreasing); member_lam: lambda (L^2) of each member
+    energy:     also record the adjoint energy of every member after every reverse step
+    """
+
+    def __init__(self, grids, windows, w0, s=None, member_box=None, member_lam=None, obj_kind=OBJ_MEAN_PRESSURE,
+                 energy=False, device="cuda"):
+        nb = len(grids)
+        self.windows = [int(t) for t in windows]
+        if len(self.windows) != nb or any(t < 1 for t in self.windows):
+            raise ValueError("one window length >= 1 per box")
+        if any(self.windows[i] < self.windows[i + 1] for i in range(nb - 1)):
+            raise ValueError("boxes must be ordered by non-increasing window length")
+        member_box = list(range(nb)) if member_box is None else [int(b) for b in member_box]
+        member_lam = [0.0] * len(member_box) if member_lam is None else [float(x) for x in member_lam]
+        self.obj = Objective.make(obj_kind)
+        self.ens = Ensemble(grids, member_box, member_lam, self.obj, device)
+        self.nbox, self.nmem = nb, len(member_box)
+        self.member_box = member_box
+        self.dtype = torch.float64 if grids[0].precision == F64 else torch.float32
+        dt = self.dtype
+        ens = self.ens
+        self.Tmax = self.windows[0]
+        # boxes with T_b >= t, as a count (windows are non-increasing): nbox_ge(t)
+        neg = [-t for t in self.windows]
+        self._nbox_ge = [bisect.bisect_right(neg, -t) for t in range(self.Tmax + 2)]
+        self._nmem_of_nbox = [bisect.bisect_left(member_box, b) for b in range(nb + 1)]
+        P = ens.offset(0, nb)
+        Q = ens.offset(1, self.nmem)
+        self.slots = [torch.empty(5 * ens.offset(0, self._nbox_ge[t]), dtype=dt, device=device)
+                      for t in range(self.Tmax + 1)]
+        self.w0 = torch.empty(5 * P, dtype=dt, device=device)
+        for b in range(nb):
+            ens.box_slice(self.w0, b).copy_(torch.as_tensor(w0[b]).to(device=device, dtype=dt).reshape(-1))
+        self.s = None
+        if s is not None:
+            self.s = torch.zeros(5 * P, dtype=dt, device=device)
+            for b in range(nb):
+                if s[b] is not None:
+                    ens.box_slice(self.s, b).copy_(torch.as_tensor(s[b]).to(device=device, dtype=dt).reshape(-1))
+        self.wmem = torch.tensor([1.0 / self.windows[b] for b in member_box], dtype=torch.float64, device=device)
+        self.J = torch.zeros(self.nmem, dtype=torch.float64, device=device)
+        self.a = torch.zeros(5 * Q, dtype=dt, device=device)
+        self.b = torch.zeros(5 * Q, dtype=dt, device=device)
+        self.grad_s = torch.zeros(5 * Q, dtype=dt, device=device)
+        self.wh0 = self.a
+        self.E = torch.zeros((self.Tmax + 1, self.nmem), dtype=torch.float64, device=device) if energy else None
+        self.ws = ens.workspace(device)
+
+    def cell_steps(self):
+        """Primal cell-steps of one window: sum_b N_b T_b."""
+        return sum((self.ens.offset(0, b + 1) - self.ens.offset(0, b)) * self.windows[b] for b in range(self.nbox))
+
+    def adjoint_cell_steps(self):
+        return sum((self.ens.offset(1, m + 1) - self.ens.offset(1, m)) * self.windows[self.member_box[m]]
+                   for m in range(self.nmem))
+
+    def _nmem_running(self, t):
+        """Members whose box runs step t (T_b > t)."""
+        return self._nmem_of_nbox[self._nbox_ge[t + 1]]
+
+    def forward(self):
+        ens, ws = self.ens, self.ws
+        self.J.zero_()
+        self.slots[0].copy_(self.w0)
+        for t in range(self.Tmax):
+            nb = self._nbox_ge[t + 1]
+            ens.primal_step(nb, self.slots[t], self.s, self.slots[t + 1], ws)
+            nm = self._nmem_of_nbox[nb]
+            if nm:
+                ens.objective_and_grad(0, nm, self.slots[t + 1], self.wmem, ws, J_accum=self.J)
+        return self.J
+
+    def backward(self):
+        ens, ws = self.ens, self.ws
+        a, b = self.a, self.b
+        self.grad_s.zero_()
+        for n in range(self.Tmax - 1, -1, -1):
+            nm = self._nmem_running(n)
+            m0 = self._nmem_running(n + 1) if n + 1 < self.Tmax else 0
+            if nm > m0:
+                # members whose window ends at w_{n+1}: terminal adjoint c_T dj/dw(w_T)
+                lo, hi = 5 * ens.offset(1, m0), 5 * ens.offset(1, nm)
+                a[lo:hi].zero_()
+                ens.objective_and_grad(m0, nm - m0, self.slots[n + 1], self.wmem, ws, djdw=a)
+                if self.E is not None:
+                    ens.energy_vhat(nm, self.slots[n + 1], a, self.E[n + 1], ws)
+            if nm:
+                ens.adjoint_step(nm, self.slots[n], self.s, a, b, ws, c_n=self.wmem if n >= 1 else None,
+                                 grad_s=self.grad_s)
+                a, b = b, a
+                if self.E is not None:
+                    ens.energy_vhat(nm, self.slots[n], a, self.E[n], ws)
+        self.wh0 = a
+        return a, self.grad_s
+
+    def member(self, t, m):
+        """Member m's part of a member-packed tensor."""
+        return self.ens.member_slice(t, m)
+
+
+class CapturedEnsemble:
+    """An EnsembleWindow captured once as two HIP graphs (forward sweep, reverse sweep)."""
+
+    def __init__(self, window):
+        self.win = window
+        self._fwd = torch.cuda.CUDAGraph()
+        self._bwd = torch.cuda.CUDAGraph()
+        window.forward()
+        window.backward()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(self._fwd):
+            window.forward()
+        with torch.cuda.graph(self._bwd):
+            window.backward()
+        torch.cuda.synchronize()
+
+    def run_forward(self):
+        self._fwd.replay()
+
+    def run_backward(self):
+        self._bwd.replay()
+
+    def run(self):
+        """Replay both sweeps; returns (J per member, packed w^_0, packed grad_s)."""
+        self._fwd.replay()
+        self._bwd.replay()
+        return self.win.J, self.win.wh0, self.win.grad_s

@@ -97,3 +97,63 @@ def test_binding_refuses_host_tensors():
     w = torch.zeros(5 * g.ncells, dtype=torch.float64)
     with pytest.raises(ValueError):
         adj.residual(g, w, None, w.clone())
+
+
+def _create(grids, member_box, member_lam, obj=None, table_bytes=None):
+    L = adj.lib()
+    nb, nm = len(grids), len(member_box)
+    tb = L.adj_batch_table_bytes(nb, nm, grids[0].precision) if table_bytes is None else table_bytes
+    buf = ctypes.create_string_buffer(max(tb, 1) + 256)
+    addr = (ctypes.addressof(buf) + 255) // 256 * 256
+    h = ctypes.c_void_p()
+    rc = L.adj_batch_create(ctypes.byref(h), nb, (adj.Grid * nb)(*grids),
+                            ctypes.byref(obj) if obj is not None else None, nm, (ctypes.c_int * nm)(*member_box),
+                            (ctypes.c_double * nm)(*member_lam), ctypes.c_void_p(addr), ctypes.c_size_t(tb))
+    return rc
+
+
+def test_ensemble_table_size_grows_with_members():
+    L = adj.lib()
+    assert L.adj_batch_table_bytes(0, 1, adj.F64) == 0
+    assert L.adj_batch_table_bytes(2, 3, 9) == 0
+    assert L.adj_batch_table_bytes(4, 8, adj.F64) > L.adj_batch_table_bytes(4, 4, adj.F64)
+    assert L.adj_batch_table_bytes(4, 16, adj.F64) > L.adj_batch_table_bytes(4, 16, adj.F32)
+
+
+@pytest.mark.parametrize("case,code", [
+    ("members_decreasing", -1), ("member_box_range", -1), ("negative_lambda", -1), ("mixed_precision", -1),
+    ("mixed_boundary", -1), ("bf16_states", -1), ("objective_kind", -1), ("small_table", -6), ("bad_grid", -1),
+])
+def test_ensemble_create_rejects(case, code):
+    g = [_grid(), _grid(n=(8, 8, 8))]
+    mb, ml, obj, tb = [0, 1], [0.0, 0.1], None, None
+    if case == "members_decreasing":
+        mb = [1, 0]
+    elif case == "member_box_range":
+        mb = [0, 2]
+    elif case == "negative_lambda":
+        ml = [0.0, -1.0]
+    elif case == "mixed_precision":
+        g[1] = _grid(n=(8, 8, 8), precision=adj.F32)
+    elif case == "mixed_boundary":
+        g[1] = _grid(n=(8, 8, 8), bc_x=adj.BC_SLIP_WALLS)
+    elif case == "bf16_states":
+        g = [_grid(precision=adj.F32, ckpt_format=adj.CKPT_BF16), _grid(n=(8, 8, 8), precision=adj.F32)]
+    elif case == "objective_kind":
+        obj = adj.Objective.make(adj.OBJ_KE_DISSIPATION)
+    elif case == "small_table":
+        tb = 64
+    elif case == "bad_grid":
+        g[1] = _grid(n=(8, 0, 8))
+    assert _create(g, mb, ml, obj, tb) == code
+    assert adj.lib().adj_last_error()
+
+
+def test_ensemble_calls_reject_null_handle():
+    L = adj.lib()
+    buf = ctypes.create_string_buffer(1024)
+    p = ctypes.c_void_p(ctypes.addressof(buf))
+    assert L.adj_batch_primal_step(None, 1, p, None, p, p, 1024, None) == -1
+    assert L.adj_batch_adjoint_step(None, 1, p, None, p, None, p, None, p, 1024, None) == -1
+    assert L.adj_batch_offset(None, 0, 0) == -1
+    assert L.adj_batch_workspace_bytes(None) == 0
