@@ -162,6 +162,94 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     return out
 
 
+def make_ensemble():
+    """The batched-ensemble configuration: 64 periodic decaying-turbulence boxes, sizes drawn from
+    {32, 48, 64, 96}^3, windows of 50-400 steps and lambda factors from {0, 0.03, 0.1, 0.3, 1}
+    (seeded draws), Mach_rms 0.3, nu 0.0175; ordered by decreasing window for the batched sweep."""
+    import workloads as W
+    sizes, windows, lams = W.ensemble_draws()
+    order = sorted(range(len(sizes)), key=lambda i: -windows[i])
+    return [W.turbulence(sizes[i], mach_rms=0.3, nu=0.0175, seed=4 + i, nsteps=windows[i], lam_factor=lams[i])
+            for i in order]
+
+
+def run_ensemble(boxes, precision, steps, warmup, tune=True):
+    import torch
+
+    import paper_1511_06959_amd as adj
+    from paper_1511_06959_amd import autotune
+    from paper_1511_06959_amd.ensemble import CapturedEnsemble, EnsembleWindow
+
+    grids = [adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision) for wl in boxes]
+    tiles = {}
+    if tune:
+        # tile shapes tuned on the largest box; the ensemble launches use the same kernel bodies
+        big = max(grids, key=lambda g: g.ncells)
+        res = autotune.tune(big, use_cache=False)
+        for kc, name in ((adj.PROF_ADJOINT_STAGE, "adjoint_stage"), (adj.PROF_PRIMAL_STAGE, "primal_stage")):
+            best, times = res[kc]
+            tiles[name] = {"tile": "x".join(map(str, adj.TILES[best])), "tuned_on": "x".join(map(str, big.n)),
+                           "us": {"x".join(map(str, adj.TILES[t])): round(ms * 1e3, 2) for t, ms in times.items()}}
+    win = EnsembleWindow(grids, [wl.nsteps for wl in boxes], [wl.w0 for wl in boxes], None,
+                         list(range(len(boxes))), [wl.lam for wl in boxes])
+    out = {"tiles": tiles}
+    adj.profile_enable(True)
+    win.forward()
+    win.backward()
+    torch.cuda.synchronize()
+    adj.profile_enable(True)
+    t0 = time.perf_counter()
+    win.forward()
+    win.backward()
+    torch.cuda.synchronize()
+    out["eager_ms_per_step"] = (time.perf_counter() - t0) * 1e3
+    adj.profile_enable(False)
+    prof = {}
+    for name, cls in (("adjoint_stage", adj.PROF_ADJOINT_STAGE), ("primal_stage", adj.PROF_PRIMAL_STAGE),
+                      ("objective", adj.PROF_OBJECTIVE), ("sigma1", adj.PROF_SIGMA1), ("reduce", adj.PROF_REDUCE)):
+        prof[name] = adj.profile_read(cls)
+    print("[bench] ensemble eager window done", file=sys.stderr, flush=True)
+    cap = CapturedEnsemble(win)
+    for _ in range(warmup):
+        cap.run()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    mids = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record()
+        cap.run_forward()
+        mids[k].record()
+        cap.run_backward()
+        ends[k].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cs = win.cell_steps()
+    acs = win.adjoint_cell_steps()
+    fwd = sum(starts[k].elapsed_time(mids[k]) for k in range(steps)) / steps
+    bwd = sum(mids[k].elapsed_time(ends[k]) for k in range(steps)) / steps
+    out["ms_per_step"] = wall * 1e3 / steps
+    out["value"] = cs / (out["ms_per_step"] / 1e3)
+    out["adjoint_sweep_cell_steps_per_s"] = acs / (bwd / 1e3)
+    out["primal_cell_steps_per_s"] = cs / (fwd / 1e3)
+    out["prof"] = prof
+    esz = 8 if precision == adj.F64 else 4
+    ms, n = prof["adjoint_stage"]
+    # every reverse step launches the four stages over the members still running
+    alg = VALUES_PER_STAGE_LAUNCH * esz * 4 * acs
+    out["stage_achieved_gbs"] = alg / (ms / 1e3) / 1e9
+    out["stage_avg_us"] = ms / n * 1e3
+    out["stage_launches"] = n
+    out["cells"] = win.ens.offset(0, win.nbox)
+    out["cell_steps"] = cs
+    out["trajectory_gb"] = sum(t.numel() for t in win.slots) * esz / 1e9
+    out["J_mean"] = float(win.J.mean().cpu())
+    del cap, win
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle as it stands, on the host cores: whole primal + reverse steps of the
     same 64^3 field, repeated until about budget_s seconds have been spent."""
@@ -208,6 +296,9 @@ WORKLOADS = {
                "{n}-step window sample of the 5000-step case, lambda 0.1 dx^2 sigma_1, mean pressure",
     "wake": "temporally developing wake 512x256x32 (slip walls in x, free stream Mach 0.85, centre 0.5, Re 5e4), "
             "{n}-step window sample of the 4000-step case, lambda 0.1 dx^2 sigma_1, stagnation-pressure loss",
+    "ensemble": "batched ensemble of 64 periodic decaying-turbulence boxes (sizes from {32,48,64,96}^3, Mach_rms "
+                "0.3, nu 0.0175), windows of 50-400 RK4 steps, lambda from {0,0.03,0.1,0.3,1} dx^2 sigma_1, "
+                "time-averaged mean pressure per box; one launch per RK stage covers every running box",
 }
 
 
@@ -248,6 +339,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     adj.lib()
+    if args.workload == "ensemble":
+        main_ensemble(args)
+        return
     wl = make_workload(args.workload, args.window)
     big = args.workload != "tgv64"
     stages = args.schedule == "stages" and not big
@@ -335,6 +429,56 @@ def main():
         }
     if not args.no_cpu_baseline and not big:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def main_ensemble(args):
+    import paper_1511_06959_amd as adj
+    boxes = make_ensemble()
+    print(f"[bench] ensemble: {len(boxes)} boxes, {sum(w.ncells for w in boxes)} cells, windows "
+          f"{boxes[-1].nsteps}-{boxes[0].nsteps}", file=sys.stderr, flush=True)
+    r = run_ensemble(boxes, adj.F32, args.steps, args.warmup, not args.no_autotune)
+    print(f"[bench] ensemble f32 window {r['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
+    line = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOADS["ensemble"],
+            "cells": r["cells"],
+            "cell_steps_per_window": r["cell_steps"],
+            "step": "one whole ensemble window: forward sweep + reverse sweep of every box",
+            "schedule": "every state of every box kept in HBM (native FP32); the reverse step recomputes the "
+                        "stage states",
+            "trajectory_gb": r["trajectory_gb"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": r["stage_achieved_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": r["stage_achieved_gbs"] / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_adjoint_stage_batch (reverse-stage gather over all running members)",
+            "avg_launch_us": r["stage_avg_us"],
+            "launches": r["stage_launches"],
+        },
+        "adjoint_sweep_cell_steps_per_s": r["adjoint_sweep_cell_steps_per_s"],
+        "primal_cell_steps_per_s": r["primal_cell_steps_per_s"],
+        "kernel_ms_per_window": {k: v[0] for k, v in r["prof"].items()},
+        "eager_ms_per_step": r["eager_ms_per_step"],
+        "launch": "the ensemble window replayed as two captured HIP graphs (forward sweep, reverse sweep)",
+        "tiles": r["tiles"],
+    }
     print(json.dumps(line), flush=True)
 
 
