@@ -121,8 +121,8 @@ __global__ __launch_bounds__(RB) void k_energy_partial(Consts<T> c, const T* __r
 }
 
 // ------------------------------------------------------------------------------------------
-// sigma_1: M = M1 - M2 from central differences [Energy Analysis, printed M1 and M2], then the
-// largest eigenvalue of M^T M by cyclic Jacobi rotations.
+// sigma_1: M = M1 - M2 from central differences [Energy Analysis, printed M1 and M2], then
+// sigma_1 = sqrt(lambda_max(M^T M)).
 // ------------------------------------------------------------------------------------------
 template <typename T>
 struct QS {
@@ -151,44 +151,93 @@ __device__ __forceinline__ QS<T> load_qs(const Consts<T>& c, const T* __restrict
   return q;
 }
 
+// Largest eigenvalue of a symmetric positive semidefinite 5x5 matrix A (destroyed): Householder
+// reduction to tridiagonal form T (Golub & Van Loan, section 8.3.1), then bisection on
+// [max_i T_ii, Gershgorin bound] with the leading principal minors of x I - T, which are all
+// positive exactly when x exceeds every eigenvalue.  The iteration count is fixed (the bracket
+// starts no wider than 2 lambda_max), so every lane of a wavefront runs the same instructions.
 template <typename T>
-struct JacobiTol;
+struct Bisect;
 template <>
-struct JacobiTol<double> {
-  static constexpr double rel = 1e-30;
-  static constexpr int sweeps = 12;
+struct Bisect<double> {
+  static constexpr int iters = 54;
 };
 template <>
-struct JacobiTol<float> {
-  static constexpr float rel = 1e-14f;
-  static constexpr int sweeps = 8;
+struct Bisect<float> {
+  static constexpr int iters = 25;
 };
 
 template <typename T>
-__device__ __forceinline__ void jrot(T (&A)[5][5], int p, int q) {
-  const T apq = A[p][q];
-  if (apq == T(0)) return;
-  const T theta = (A[q][q] - A[p][p]) / (T(2) * apq);
-  const T at = fabs(theta);
-  T t;
-  if (at > T(1e15))
-    t = T(0.5) / theta;
-  else
-    t = (theta >= T(0) ? T(1) : T(-1)) / (at + sqrt(theta * theta + T(1)));
-  const T cs = T(1) / sqrt(t * t + T(1));
-  const T sn = t * cs;
+__device__ __forceinline__ T sym5_lambda_max(T (&A)[5][5]) {
 #pragma unroll
-  for (int r = 0; r < 5; ++r) {
-    const T arp = A[r][p], arq = A[r][q];
-    A[r][p] = cs * arp - sn * arq;
-    A[r][q] = sn * arp + cs * arq;
+  for (int k = 0; k < 3; ++k) {
+    T ss = T(0);
+#pragma unroll
+    for (int i = k + 1; i < 5; ++i) ss += A[i][k] * A[i][k];
+    const T x0 = A[k + 1][k];
+    const T nrm = sqrt(ss);
+    const T alpha = x0 >= T(0) ? -nrm : nrm;
+    const T h = ss - x0 * alpha;  // |v|^2 / 2
+    const T hi = h > T(0) ? T(1) / h : T(0);
+    T v[5], p[5];
+#pragma unroll
+    for (int i = k + 1; i < 5; ++i) v[i] = i == k + 1 ? x0 - alpha : A[i][k];
+#pragma unroll
+    for (int r = k + 1; r < 5; ++r) {
+      T acc = T(0);
+#pragma unroll
+      for (int c = k + 1; c < 5; ++c) acc += A[r][c] * v[c];
+      p[r] = acc * hi;
+    }
+    T K = T(0);
+#pragma unroll
+    for (int i = k + 1; i < 5; ++i) K += v[i] * p[i];
+    K *= T(0.5) * hi;
+#pragma unroll
+    for (int i = k + 1; i < 5; ++i) p[i] -= K * v[i];  // p := q
+#pragma unroll
+    for (int r = k + 1; r < 5; ++r)
+#pragma unroll
+      for (int c = k + 1; c < 5; ++c) A[r][c] -= v[r] * p[c] + p[r] * v[c];
+    // a vanishing column (h = 0) needs no reflection and keeps its sub-diagonal entry
+    A[k + 1][k] = h > T(0) ? alpha : x0;
+  }
+  T d[5], e[4];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) d[i] = A[i][i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) e[i] = A[i + 1][i];
+  T sc = T(0);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) sc = fmax(sc, fabs(d[i]));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) sc = fmax(sc, fabs(e[i]));
+  const T inv = sc > T(0) ? T(1) / sc : T(0);
+  T e2[4], lo = T(0), hi = T(0);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) d[i] *= inv;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    e[i] = fabs(e[i] * inv);
+    e2[i] = e[i] * e[i];
   }
 #pragma unroll
-  for (int r = 0; r < 5; ++r) {
-    const T apr = A[p][r], aqr = A[q][r];
-    A[p][r] = cs * apr - sn * aqr;
-    A[q][r] = sn * apr + cs * aqr;
+  for (int i = 0; i < 5; ++i) {
+    lo = fmax(lo, d[i]);
+    hi = fmax(hi, d[i] + (i > 0 ? e[i - 1] : T(0)) + (i < 4 ? e[i] : T(0)));
   }
+  for (int it = 0; it < Bisect<T>::iters; ++it) {
+    const T x = T(0.5) * (lo + hi);
+    const T m1 = x - d[0];
+    const T m2 = (x - d[1]) * m1 - e2[0];
+    const T m3 = (x - d[2]) * m2 - e2[1] * m1;
+    const T m4 = (x - d[3]) * m3 - e2[2] * m2;
+    const T m5 = (x - d[4]) * m4 - e2[3] * m3;
+    const bool above = m1 > T(0) && m2 > T(0) && m3 > T(0) && m4 > T(0) && m5 > T(0);
+    hi = above ? x : hi;
+    lo = above ? lo : x;
+  }
+  return T(0.5) * (lo + hi) * sc;
 }
 
 // sigma_1 of cell i (0 <= i < N)
@@ -229,36 +278,17 @@ __device__ __forceinline__ T sigma1_cell(const Consts<T>& c, const T* __restrict
   Mx[0][4] = -T(0.5) * sqrt(g - T(1)) * div;
   Mx[4][4] = T(0.5) * div - T(0.5) * (g - T(1)) * div;
   T A[5][5];
-  T tot = T(0);
 #pragma unroll
   for (int r = 0; r < 5; ++r)
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
+    for (int s = r; s < 5; ++s) {
       T acc = T(0);
 #pragma unroll
       for (int k = 0; k < 5; ++k) acc += Mx[k][r] * Mx[k][s];
       A[r][s] = acc;
+      A[s][r] = acc;
     }
-#pragma unroll
-  for (int r = 0; r < 5; ++r)
-#pragma unroll
-    for (int s = 0; s < 5; ++s) tot += A[r][s] * A[r][s];
-  for (int sweep = 0; sweep < JacobiTol<T>::sweeps; ++sweep) {
-    T off = T(0);
-#pragma unroll
-    for (int r = 0; r < 5; ++r)
-#pragma unroll
-      for (int s = 0; s < 5; ++s)
-        if (r != s) off += A[r][s] * A[r][s];
-    if (off <= JacobiTol<T>::rel * tot) break;
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int qq = p + 1; qq < 5; ++qq) jrot(A, p, qq);
-  }
-  T lm = A[0][0];
-#pragma unroll
-  for (int r = 1; r < 5; ++r) lm = fmax(lm, A[r][r]);
+  const T lm = sym5_lambda_max(A);
   return sqrt(fmax(lm, T(0)));
 }
 

@@ -167,6 +167,29 @@ def test_adjoint_step_deterministic():
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("bc_x", [0, 1], ids=["periodic", "walls"])
+def test_sigma1_parity_f32(orc, bc_x):
+    g, og, w = _setup(orc, (19, 6, 9), bc_x, precision=adj.F32, seed=18)
+    w32 = w.astype(np.float32).astype(np.float64)
+    out = torch.empty(w.size // 5, dtype=torch.float32, device="cuda")
+    adj.growth_sigma1(g, dev(w32, torch.float32), out)
+    assert relerr(host(out), orc.sigma1(og, w32)) <= 2e-5
+
+
+def test_sigma1_repeated_singular_values(orc):
+    # uniform state plus a pure shear in one velocity component: M has a single non-zero entry, so
+    # M^T M has a four-fold zero eigenvalue below lambda_max (the bracket must not stall)
+    n = (8, 8, 8)
+    g, og, _ = _setup(orc, n, 0, seed=19)
+    x, y, z = W.cell_centres(n, (2.0, 1.3, 1.7))
+    rho = np.ones_like(x)
+    w = W.conservative(rho, 0.3 * np.sin(2 * math.pi * y / 1.3), np.zeros_like(x), np.zeros_like(x),
+                       np.full_like(x, 0.8))
+    out = torch.empty(w.size // 5, dtype=torch.float64, device="cuda")
+    adj.growth_sigma1(g, dev(w), out)
+    assert relerr(host(out), orc.sigma1(og, w)) <= 1e-13
+
+
 def test_fp32_operators(orc):
     shape = (19, 6, 9)
     g, og, w = _setup(orc, shape, 0, precision=adj.F32, seed=14)
