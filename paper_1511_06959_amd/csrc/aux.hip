@@ -294,7 +294,7 @@ __device__ __forceinline__ T sigma1_cell(const Consts<T>& c, const T* __restrict
 
 template <typename T>
 __global__ __launch_bounds__(RB) void k_sigma1(Consts<T> c, const T* __restrict__ w, T scale, T* __restrict__ out) {
-  const long long i = (long long)blockIdx.x * RB + threadIdx.x;
+  const long long i = (long long)xcd_tile(blockIdx.x, gridDim.x) * RB + threadIdx.x;
   if (i >= c.N) return;
   out[i] = scale * sigma1_cell(c, w, i);
 }
@@ -304,9 +304,10 @@ template <typename T>
 __global__ __launch_bounds__(RB) void k_sigma1_batch(const BoxDesc<T>* __restrict__ boxes,
                                                      const int* __restrict__ start, int nbox, const T* __restrict__ w,
                                                      T* __restrict__ out) {
-  const int b = find_box(start, nbox, blockIdx.x);
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int b = find_box(start, nbox, blk);
   const Consts<T> c = boxes[b].c;
-  const long long i = (long long)(blockIdx.x - start[b]) * RB + threadIdx.x;
+  const long long i = (long long)(blk - start[b]) * RB + threadIdx.x;
   if (i >= c.N) return;
   out[boxes[b].off + i] = sigma1_cell(c, w + 5 * boxes[b].off, i);
 }
@@ -451,7 +452,9 @@ __global__ __launch_bounds__(NT) void k_ked_tile(Consts<T> c, const T* __restric
   using B = Box<1, 1>;
   __shared__ T su[3][B::NB];
   __shared__ double sh[NT];
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  int x0, y0, z0;
+  tile_origin<TX, TY, TZ>(t, c.nx, c.ny, x0, y0, z0);
   load_box_u<T, 1, 1>(c, w, x0, y0, z0, su);
   __syncthreads();
   const int tid = threadIdx.x;
@@ -475,7 +478,7 @@ __global__ __launch_bounds__(NT) void k_ked_tile(Consts<T> c, const T* __restric
     phi = (double)acc;
   }
   const double tot = block_sum(phi, sh);
-  if (tid == 0) partials[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+  if (tid == 0) partials[t] = tot;
 }
 
 // Gradient: u^_k(j) = (wgt/N) sum_l (sigma_lk(j - e_l) - sigma_lk(j + e_l)) / dx_l (since
@@ -489,7 +492,8 @@ __global__ __launch_bounds__(NT) void k_ked_grad_tile(Consts<T> c, const T* __re
   using I = Box<1, 1>;
   __shared__ T su[3][O::NB];
   __shared__ T ss[6][I::NB];  // sigma xx, yy, zz, xy, xz, yz on the inner box
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+  int x0, y0, z0;
+  tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
   load_box_u<T, 2, 2>(c, w, x0, y0, z0, su);
   __syncthreads();
   const int sto[3] = {1, O::SY, O::SZ};
@@ -787,9 +791,9 @@ hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt
     if (J_accum)
       hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 1, J_accum, weight / (double)c.N, 1.0);
   } else if (kind == 2) {
-    const dim3 grid((c.nx + TX - 1) / TX, (c.ny + TY - 1) / TY, (c.nz + TZ - 1) / TZ);
+    const dim3 grid(((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY) * ((c.nz + TZ - 1) / TZ));
     if (J_accum) {
-      const int nb = (int)(grid.x * grid.y * grid.z);
+      const int nb = (int)grid.x;
       // one partial per tile: the workspace partial region holds max(10 * MAX_PARTIALS, tiles) values
       hipLaunchKernelGGL((k_ked_tile<T>), grid, dim3(NT), 0, st, c, w, partials);
       hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 1, J_accum, weight / (double)c.N, 1.0);

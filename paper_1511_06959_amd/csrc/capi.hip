@@ -80,8 +80,8 @@ int check_grid(const adj_grid* g, bool need_dt) {
     if (g->n[d] < 1) return fail(ADJ_EINVAL, "n[%d] = %d must be >= 1", d, g->n[d]);
     if (!(g->L[d] > 0.0) || !std::isfinite(g->L[d])) return fail(ADJ_EINVAL, "L[%d] must be positive", d);
   }
-  if ((g->n[1] + TY - 1) / TY > 65535 || (g->n[2] + TZ - 1) / TZ > 65535)
-    return fail(ADJ_ESHAPE, "grid too large in y or z for the tile launch");
+  if ((long long)((g->n[0] + 15) / 16) * ((g->n[1] + 3) / 4) * ((g->n[2] + 3) / 4) > 0x7fffffffLL)
+    return fail(ADJ_ESHAPE, "grid too large for one tile launch");
   if (g->bc_x != ADJ_BC_PERIODIC && g->bc_x != ADJ_BC_SLIP_WALLS) return fail(ADJ_EINVAL, "bad bc_x %d", g->bc_x);
   if (g->bc_x == ADJ_BC_SLIP_WALLS && g->n[0] < 2) return fail(ADJ_ESHAPE, "slip walls need n[0] >= 2");
   if (!(g->gamma > 1.0) || !std::isfinite(g->gamma)) return fail(ADJ_EINVAL, "gamma must be > 1");

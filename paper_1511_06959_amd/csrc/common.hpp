@@ -38,6 +38,25 @@ struct Consts {
   T gamma, mu, alpha, dt;
 };
 
+// Work-groups of a 1-D launch are dispatched to the eight XCDs round-robin (work-group b on XCD
+// b mod 8), and each XCD has its own L2.  xcd_tile turns the dispatch index into a logical tile
+// index such that every XCD walks one contiguous run of tiles: tiles that share halo lines (the
+// x and y neighbours) then run on the same XCD, close in time, and the lines hit in its L2.
+// It is a bijection of [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Origin of logical tile t of a TX x TY x TZ tiling of an nx x ny x nz grid (x fastest).
+template <int TX_, int TY_, int TZ_>
+__device__ __forceinline__ void tile_origin(int t, int nx, int ny, int& x0, int& y0, int& z0) {
+  const int ntx = (nx + TX_ - 1) / TX_, nty = (ny + TY_ - 1) / TY_;
+  x0 = (t % ntx) * TX_;
+  y0 = ((t / ntx) % nty) * TY_;
+  z0 = (t / (ntx * nty)) * TZ_;
+}
+
 // One box of an ensemble (batched launches).  Ensemble arrays are packed box after box: the
 // fields of a box start at element 5 * off (state arrays of the boxes) or 5 * aoff (adjoint
 // arrays of the members), scalar fields at off; inside a box the layout is the single-box one.

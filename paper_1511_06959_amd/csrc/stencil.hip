@@ -196,8 +196,9 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, cons
                                                                const T* __restrict__ wn, const T* __restrict__ s,
                                                                const T* __restrict__ W2, const T* __restrict__ W3,
                                                                T cR, T* __restrict__ out) {
-  primal_tile_body<T, MODE, TX, TY, TZ>(c, blockIdx.x * TX, blockIdx.y * TY, blockIdx.z * TZ, W, wn, s, W2, W3, cR,
-                                        out);
+  int x0, y0, z0;
+  tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
+  primal_tile_body<T, MODE, TX, TY, TZ>(c, x0, y0, z0, W, wn, s, W2, W3, cR, out);
 }
 
 // Ensemble form: work-group -> (box, tile) through the tile offsets `start`; every array is
@@ -209,13 +210,13 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage_batch(const BoxDe
                                                                      const T* __restrict__ s, const T* __restrict__ W2,
                                                                      const T* __restrict__ W3, T cfac,
                                                                      T* __restrict__ out) {
-  const int b = find_box(start, nbox, blockIdx.x);
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int b = find_box(start, nbox, blk);
   const Consts<T> c = boxes[b].c;
   const long long o = 5 * boxes[b].off;
-  const int t = blockIdx.x - start[b];
-  const int ntx = (c.nx + TX - 1) / TX, nty = (c.ny + TY - 1) / TY;
-  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-  primal_tile_body<T, MODE, TX, TY, TZ>(c, tx * TX, ty * TY, tz * TZ, W + o, wn + o, s ? s + o : nullptr,
+  int x0, y0, z0;
+  tile_origin<TX, TY, TZ>(blk - start[b], c.nx, c.ny, x0, y0, z0);
+  primal_tile_body<T, MODE, TX, TY, TZ>(c, x0, y0, z0, W + o, wn + o, s ? s + o : nullptr,
                                         W2 ? W2 + o : nullptr, W3 ? W3 + o : nullptr, c.dt * cfac, out + o);
 }
 
@@ -597,8 +598,10 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
                                                                 const T* __restrict__ nu, T ca, T cg,
                                                                 const T* __restrict__ g3, const T* __restrict__ g4,
                                                                 T* __restrict__ out, T* __restrict__ grad_s) {
-  adjoint_tile_body<T, MODE, WALL, LNU, TX, TY, TZ>(c, blockIdx.x * TX, blockIdx.y * TY, blockIdx.z * TZ, W, a,
-                                                    gnext, nu, T(1), ca, cg, g3, g4, out, grad_s);
+  int x0, y0, z0;
+  tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
+  adjoint_tile_body<T, MODE, WALL, LNU, TX, TY, TZ>(c, x0, y0, z0, W, a, gnext, nu, T(1), ca, cg, g3, g4, out,
+                                                    grad_s);
 }
 
 // Ensemble form over the members: state arrays (W, the sigma_1 field) at the member's box,
@@ -609,14 +612,14 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage_batch(
     const BoxDesc<T>* __restrict__ mems, const int* __restrict__ start, int nmem, const T* __restrict__ W,
     const T* __restrict__ a, const T* __restrict__ gnext, const T* __restrict__ sigma1, T da, T mg,
     const T* __restrict__ g3, const T* __restrict__ g4, T* __restrict__ out, T* __restrict__ grad_s) {
-  const int m = find_box(start, nmem, blockIdx.x);
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int m = find_box(start, nmem, blk);
   const Consts<T> c = mems[m].c;
   const long long o = 5 * mems[m].off, ao = 5 * mems[m].aoff;
-  const int t = blockIdx.x - start[m];
-  const int ntx = (c.nx + TX - 1) / TX, nty = (c.ny + TY - 1) / TY;
-  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  int x0, y0, z0;
+  tile_origin<TX, TY, TZ>(blk - start[m], c.nx, c.ny, x0, y0, z0);
   adjoint_tile_body<T, MODE, WALL, LNU, TX, TY, TZ>(
-      c, tx * TX, ty * TY, tz * TZ, W + o, a + ao, gnext ? gnext + ao : nullptr, LNU ? sigma1 + mems[m].off : nullptr,
+      c, x0, y0, z0, W + o, a + ao, gnext ? gnext + ao : nullptr, LNU ? sigma1 + mems[m].off : nullptr,
       mems[m].lam, c.dt / da, c.dt * mg, g3 ? g3 + ao : nullptr, g4 ? g4 + ao : nullptr, out + ao,
       grad_s ? grad_s + ao : nullptr);
 }
@@ -627,7 +630,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage_batch(
 // ------------------------------------------------------------------------------------------
 template <int TX, int TY, int TZ>
 static dim3 tile_grid(int nx, int ny, int nz) {
-  return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY, (nz + TZ - 1) / TZ);
+  return dim3(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + TZ - 1) / TZ));
 }
 
 template <typename T, int TX, int TY, int TZ>
