@@ -186,7 +186,15 @@ int adj_profile_read(int kernel_class, double* total_ms, long long* launches);
  * ADJ_PROF_PRIMAL_STAGE), per precision: the output tile each work-group covers.  Process-wide;
  * set it before enqueuing work that should use it (the autotuner does).  adj_get_tile returns
  * the tile id or a negative status. */
-enum { ADJ_TILE_16x4x4 = 0, ADJ_TILE_32x4x2 = 1, ADJ_TILE_32x4x4 = 2, ADJ_TILE_32x8x2 = 3, ADJ_NTILES = 4 };
+enum {
+  ADJ_TILE_16x4x4 = 0,
+  ADJ_TILE_32x4x2 = 1,
+  ADJ_TILE_32x4x4 = 2,
+  ADJ_TILE_32x8x2 = 3,
+  ADJ_TILE_32x8x4 = 4,
+  ADJ_TILE_16x8x8 = 5,
+  ADJ_NTILES = 6
+};
 int adj_set_tile(int kernel_class, int precision, int tile);
 int adj_get_tile(int kernel_class, int precision);
 

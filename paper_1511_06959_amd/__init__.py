@@ -23,7 +23,7 @@ CKPT_NATIVE, CKPT_BF16 = 0, 1
 BC_PERIODIC, BC_SLIP_WALLS = 0, 1
 OBJ_NONE, OBJ_MEAN_PRESSURE, OBJ_KE_DISSIPATION, OBJ_PT_LOSS_PLANE = 0, 1, 2, 3
 PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, PROF_SIGMA1, PROF_OBJECTIVE, PROF_CODEC, PROF_REDUCE = range(6)
-TILES = {0: (16, 4, 4), 1: (32, 4, 2), 2: (32, 4, 4), 3: (32, 8, 2)}
+TILES = {0: (16, 4, 4), 1: (32, 4, 2), 2: (32, 4, 4), 3: (32, 8, 2), 4: (32, 8, 4), 5: (16, 8, 8)}
 
 STATUS = {0: "ADJ_OK", -1: "ADJ_EINVAL", -2: "ADJ_ESHAPE", -3: "ADJ_EUNSTABLE", -4: "ADJ_ENONFINITE",
           -5: "ADJ_EHIP", -6: "ADJ_EWORKSPACE"}

@@ -27,7 +27,7 @@ using Box = TBox<TX, TY, TZ, HX, HY>;
 // Tile shapes the stencil kernels are compiled for (index = adj_set_tile's tile id).  A
 // wavefront covers 64 consecutive threads, x fastest: rows of 32 let each half-wavefront read 32
 // consecutive LDS words (conflict-free) and 128-byte global segments.
-enum { TILE_16x4x4 = 0, TILE_32x4x2 = 1, TILE_32x4x4 = 2, TILE_32x8x2 = 3, NTILES = 4 };
+enum { TILE_16x4x4 = 0, TILE_32x4x2 = 1, TILE_32x4x4 = 2, TILE_32x8x2 = 3, TILE_32x8x4 = 4, TILE_16x8x8 = 5, NTILES = 6 };
 int& tile_choice(int kernel_class, int fp64);
 
 template <typename T>

@@ -5,6 +5,8 @@
 // LDS, derive the primitive variables once per box cell, and then evaluate each output cell's
 // 19-point stencil from LDS.  SoA var-major global layout; every global access of a wavefront is
 // to consecutive x addresses.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace adjns {
@@ -628,46 +630,43 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage_batch(
 // Host-side launchers: the tile shape of each kernel class and precision is a process-wide
 // setting (adj_set_tile), dispatched here to the matching instantiation.
 // ------------------------------------------------------------------------------------------
+template <int X, int Y, int Z>
+struct Shape {
+  static constexpr int tx = X, ty = Y, tz = Z;
+};
+
+// Calls f(Shape<...>{}) for tile id `tile`.
+template <class F>
+static void with_tile(int tile, F&& f) {
+  switch (tile) {
+    case TILE_16x4x4: f(Shape<16, 4, 4>{}); break;
+    case TILE_32x4x2: f(Shape<32, 4, 2>{}); break;
+    case TILE_32x4x4: f(Shape<32, 4, 4>{}); break;
+    case TILE_32x8x2: f(Shape<32, 8, 2>{}); break;
+    case TILE_32x8x4: f(Shape<32, 8, 4>{}); break;
+    default: f(Shape<16, 8, 8>{}); break;
+  }
+}
+
+// Calls f(integral WALL, integral LNU) for the boundary / artificial-viscosity variant.
+template <class F>
+static void with_variant(int wall, int lnu, F&& f) {
+  if (wall) {
+    if (lnu)
+      f(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{});
+    else
+      f(std::integral_constant<int, 1>{}, std::integral_constant<int, 0>{});
+  } else {
+    if (lnu)
+      f(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
+    else
+      f(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+  }
+}
+
 template <int TX, int TY, int TZ>
 static dim3 tile_grid(int nx, int ny, int nz) {
   return dim3(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + TZ - 1) / TZ));
-}
-
-template <typename T, int TX, int TY, int TZ>
-static void primal_tile(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2, const T* W3,
-                        T cR, T* out, hipStream_t st) {
-  const dim3 grid = tile_grid<TX, TY, TZ>(c.nx, c.ny, c.nz), blk(TX * TY * TZ);
-  if (mode == STAGE_RES)
-    hipLaunchKernelGGL((k_primal_stage<T, STAGE_RES, TX, TY, TZ>), grid, blk, 0, st, c, W, wn, s, W2, W3, cR, out);
-  else if (mode == STAGE_LIN)
-    hipLaunchKernelGGL((k_primal_stage<T, STAGE_LIN, TX, TY, TZ>), grid, blk, 0, st, c, W, wn, s, W2, W3, cR, out);
-  else
-    hipLaunchKernelGGL((k_primal_stage<T, STAGE_FIN, TX, TY, TZ>), grid, blk, 0, st, c, W, wn, s, W2, W3, cR, out);
-}
-
-template <typename T>
-hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
-                               const T* W3, T cR, T* out, hipStream_t st) {
-  ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st);
-  switch (tile_choice(ADJ_PROF_PRIMAL_STAGE, sizeof(T) == 8)) {
-    case TILE_16x4x4: primal_tile<T, 16, 4, 4>(mode, c, W, wn, s, W2, W3, cR, out, st); break;
-    case TILE_32x4x2: primal_tile<T, 32, 4, 2>(mode, c, W, wn, s, W2, W3, cR, out, st); break;
-    case TILE_32x4x4: primal_tile<T, 32, 4, 4>(mode, c, W, wn, s, W2, W3, cR, out, st); break;
-    default: primal_tile<T, 32, 8, 2>(mode, c, W, wn, s, W2, W3, cR, out, st); break;
-  }
-  return hipGetLastError();
-}
-
-template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
-static void adjoint_tile(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu, T ca, T cg,
-                         const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
-  const dim3 grid = tile_grid<TX, TY, TZ>(c.nx, c.ny, c.nz), blk(TX * TY * TZ);
-  if (mode == STAGE_VJP)
-    hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_VJP, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, c, W, a, gnext, nu, ca,
-                       cg, g3, g4, out, grad_s);
-  else
-    hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_FIN, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, c, W, a, gnext, nu, ca,
-                       cg, g3, g4, out, grad_s);
 }
 
 // LDS bytes of one work-group of the reverse-stage kernel (box fields + the region shared by the
@@ -683,42 +682,59 @@ constexpr int adjoint_lds_bytes() {
   return (int)sizeof(T) * ((LNU ? A_NU + 1 : A_NU) * B::NB + (rec > 3 * B::NB ? rec : 3 * B::NB));
 }
 
-// Tile dispatch; a shape whose LDS footprint exceeds the 160 KB of a CU runs as 16x4x4.
-template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
-static void adjoint_fit(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu, T ca, T cg,
-                        const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
-  if constexpr (adjoint_lds_bytes<T, WALL, LNU, TX, TY, TZ>() <= 160 * 1024)
-    adjoint_tile<T, WALL, LNU, TX, TY, TZ>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
-  else
-    adjoint_tile<T, WALL, LNU, 16, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
+// A tile shape whose reverse-stage LDS footprint exceeds the 160 KB of a CU runs as 16x4x4.
+template <typename T, int WALL, int LNU, class S>
+constexpr bool adjoint_fits() {
+  return adjoint_lds_bytes<T, WALL, LNU, S::tx, S::ty, S::tz>() <= 160 * 1024;
 }
 
-template <typename T, int WALL, int LNU>
-static void adjoint_variant(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu, T ca,
-                            T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
-  switch (tile_choice(ADJ_PROF_ADJOINT_STAGE, sizeof(T) == 8)) {
-    case TILE_16x4x4: adjoint_fit<T, WALL, LNU, 16, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
-    case TILE_32x4x2: adjoint_fit<T, WALL, LNU, 32, 4, 2>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
-    case TILE_32x4x4: adjoint_fit<T, WALL, LNU, 32, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
-    default: adjoint_fit<T, WALL, LNU, 32, 8, 2>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st); break;
-  }
+template <typename T>
+hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
+                               const T* W3, T cR, T* out, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st);
+  with_tile(tile_choice(ADJ_PROF_PRIMAL_STAGE, sizeof(T) == 8), [&](auto S) {
+    using Sh = decltype(S);
+    const dim3 grid = tile_grid<Sh::tx, Sh::ty, Sh::tz>(c.nx, c.ny, c.nz), blk(Sh::tx * Sh::ty * Sh::tz);
+    if (mode == STAGE_RES)
+      hipLaunchKernelGGL((k_primal_stage<T, STAGE_RES, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, c, W, wn, s, W2, W3,
+                         cR, out);
+    else if (mode == STAGE_LIN)
+      hipLaunchKernelGGL((k_primal_stage<T, STAGE_LIN, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, c, W, wn, s, W2, W3,
+                         cR, out);
+    else
+      hipLaunchKernelGGL((k_primal_stage<T, STAGE_FIN, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, c, W, wn, s, W2, W3,
+                         cR, out);
+  });
+  return hipGetLastError();
+}
+
+template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
+static void adjoint_launch(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu, T ca,
+                           T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
+  const dim3 grid = tile_grid<TX, TY, TZ>(c.nx, c.ny, c.nz), blk(TX * TY * TZ);
+  if (mode == STAGE_VJP)
+    hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_VJP, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, c, W, a, gnext, nu, ca,
+                       cg, g3, g4, out, grad_s);
+  else
+    hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_FIN, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, c, W, a, gnext, nu, ca,
+                       cg, g3, g4, out, grad_s);
 }
 
 template <typename T>
 hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,
                                 T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
   ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st);
-  if (c.wall) {
-    if (nu)
-      adjoint_variant<T, 1, 1>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
-    else
-      adjoint_variant<T, 1, 0>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
-  } else {
-    if (nu)
-      adjoint_variant<T, 0, 1>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
-    else
-      adjoint_variant<T, 0, 0>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
-  }
+  with_variant(c.wall, nu != nullptr, [&](auto WL, auto LN) {
+    constexpr int WALL = decltype(WL)::value, LNU = decltype(LN)::value;
+    with_tile(tile_choice(ADJ_PROF_ADJOINT_STAGE, sizeof(T) == 8), [&](auto S) {
+      using Sh = decltype(S);
+      if constexpr (adjoint_fits<T, WALL, LNU, Sh>())
+        adjoint_launch<T, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s,
+                                                             st);
+      else
+        adjoint_launch<T, WALL, LNU, 16, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
+    });
+  });
   return hipGetLastError();
 }
 
@@ -727,51 +743,25 @@ hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const 
 // the tile shape is fixed when the ensemble is set up, so that `start` matches it.
 // ------------------------------------------------------------------------------------------
 void tile_dims(int tile, int& tx, int& ty, int& tz) {
-  switch (tile) {
-    case TILE_16x4x4: tx = 16; ty = 4; tz = 4; break;
-    case TILE_32x4x2: tx = 32; ty = 4; tz = 2; break;
-    case TILE_32x4x4: tx = 32; ty = 4; tz = 4; break;
-    default: tx = 32; ty = 8; tz = 2; break;
-  }
-}
-
-template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
-static int fit_tile(int tile) {
-  return adjoint_lds_bytes<T, WALL, LNU, TX, TY, TZ>() <= 160 * 1024 ? tile : (int)TILE_16x4x4;
-}
-
-template <typename T, int WALL, int LNU>
-static int fit_variant(int tile) {
-  switch (tile) {
-    case TILE_16x4x4: return fit_tile<T, WALL, LNU, 16, 4, 4>(tile);
-    case TILE_32x4x2: return fit_tile<T, WALL, LNU, 32, 4, 2>(tile);
-    case TILE_32x4x4: return fit_tile<T, WALL, LNU, 32, 4, 4>(tile);
-    default: return fit_tile<T, WALL, LNU, 32, 8, 2>(TILE_32x8x2);
-  }
+  with_tile(tile, [&](auto S) {
+    using Sh = decltype(S);
+    tx = Sh::tx;
+    ty = Sh::ty;
+    tz = Sh::tz;
+  });
 }
 
 int adjoint_tile_used(int fp64, int wall, int lnu, int tile) {
-  if (fp64) {
-    if (wall) return lnu ? fit_variant<double, 1, 1>(tile) : fit_variant<double, 1, 0>(tile);
-    return lnu ? fit_variant<double, 0, 1>(tile) : fit_variant<double, 0, 0>(tile);
-  }
-  if (wall) return lnu ? fit_variant<float, 1, 1>(tile) : fit_variant<float, 1, 0>(tile);
-  return lnu ? fit_variant<float, 0, 1>(tile) : fit_variant<float, 0, 0>(tile);
-}
-
-template <typename T, int TX, int TY, int TZ>
-static void primal_batch_tile(int mode, const BoxDesc<T>* boxes, const int* start, int nbox, int nblocks, const T* W,
-                              const T* wn, const T* s, const T* W2, const T* W3, T cfac, T* out, hipStream_t st) {
-  const dim3 grid(nblocks), blk(TX * TY * TZ);
-  if (mode == STAGE_RES)
-    hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_RES, TX, TY, TZ>), grid, blk, 0, st, boxes, start, nbox, W, wn,
-                       s, W2, W3, cfac, out);
-  else if (mode == STAGE_LIN)
-    hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_LIN, TX, TY, TZ>), grid, blk, 0, st, boxes, start, nbox, W, wn,
-                       s, W2, W3, cfac, out);
-  else
-    hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_FIN, TX, TY, TZ>), grid, blk, 0, st, boxes, start, nbox, W, wn,
-                       s, W2, W3, cfac, out);
+  int used = tile;
+  with_variant(wall, lnu, [&](auto WL, auto LN) {
+    constexpr int WALL = decltype(WL)::value, LNU = decltype(LN)::value;
+    with_tile(tile, [&](auto S) {
+      using Sh = decltype(S);
+      const bool fits = fp64 ? adjoint_fits<double, WALL, LNU, Sh>() : adjoint_fits<float, WALL, LNU, Sh>();
+      used = fits ? tile : (int)TILE_16x4x4;
+    });
+  });
+  return used;
 }
 
 template <typename T>
@@ -779,69 +769,43 @@ hipError_t launch_primal_stage_batch(int mode, int tile, const BoxDesc<T>* boxes
                                      int nblocks, const T* W, const T* wn, const T* s, const T* W2, const T* W3,
                                      T cfac, T* out, hipStream_t st) {
   ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st);
-  switch (tile) {
-    case TILE_16x4x4: primal_batch_tile<T, 16, 4, 4>(mode, boxes, start, nbox, nblocks, W, wn, s, W2, W3, cfac, out, st); break;
-    case TILE_32x4x2: primal_batch_tile<T, 32, 4, 2>(mode, boxes, start, nbox, nblocks, W, wn, s, W2, W3, cfac, out, st); break;
-    case TILE_32x4x4: primal_batch_tile<T, 32, 4, 4>(mode, boxes, start, nbox, nblocks, W, wn, s, W2, W3, cfac, out, st); break;
-    default: primal_batch_tile<T, 32, 8, 2>(mode, boxes, start, nbox, nblocks, W, wn, s, W2, W3, cfac, out, st); break;
-  }
+  with_tile(tile, [&](auto S) {
+    using Sh = decltype(S);
+    const dim3 grid(nblocks), blk(Sh::tx * Sh::ty * Sh::tz);
+    if (mode == STAGE_RES)
+      hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_RES, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, boxes, start,
+                         nbox, W, wn, s, W2, W3, cfac, out);
+    else if (mode == STAGE_LIN)
+      hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_LIN, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, boxes, start,
+                         nbox, W, wn, s, W2, W3, cfac, out);
+    else
+      hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_FIN, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, boxes, start,
+                         nbox, W, wn, s, W2, W3, cfac, out);
+  });
   return hipGetLastError();
 }
 
-template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
-static void adjoint_batch_tile(int mode, const BoxDesc<T>* mems, const int* start, int nmem, int nblocks, const T* W,
-                               const T* a, const T* gnext, const T* sigma1, T da, T mg, const T* g3, const T* g4,
-                               T* out, T* grad_s, hipStream_t st) {
-  if constexpr (adjoint_lds_bytes<T, WALL, LNU, TX, TY, TZ>() <= 160 * 1024) {
-    const dim3 grid(nblocks), blk(TX * TY * TZ);
-    if (mode == STAGE_VJP)
-      hipLaunchKernelGGL((k_adjoint_stage_batch<T, STAGE_VJP, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, mems, start,
-                         nmem, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s);
-    else
-      hipLaunchKernelGGL((k_adjoint_stage_batch<T, STAGE_FIN, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, mems, start,
-                         nmem, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s);
-  } else {
-    adjoint_batch_tile<T, WALL, LNU, 16, 4, 4>(mode, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4,
-                                               out, grad_s, st);
-  }
-}
-
-template <typename T, int WALL, int LNU>
-static void adjoint_batch_variant(int mode, int tile, const BoxDesc<T>* mems, const int* start, int nmem, int nblocks,
-                                  const T* W, const T* a, const T* gnext, const T* sigma1, T da, T mg, const T* g3,
-                                  const T* g4, T* out, T* grad_s, hipStream_t st) {
-  switch (tile) {
-    case TILE_16x4x4:
-      adjoint_batch_tile<T, WALL, LNU, 16, 4, 4>(mode, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
-      break;
-    case TILE_32x4x2:
-      adjoint_batch_tile<T, WALL, LNU, 32, 4, 2>(mode, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
-      break;
-    case TILE_32x4x4:
-      adjoint_batch_tile<T, WALL, LNU, 32, 4, 4>(mode, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
-      break;
-    default:
-      adjoint_batch_tile<T, WALL, LNU, 32, 8, 2>(mode, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
-      break;
-  }
-}
-
+// `tile` is the shape after the LDS fit (adjoint_tile_used), so no fallback happens here
 template <typename T>
 hipError_t launch_adjoint_stage_batch(int mode, int tile, int wall, int lnu, const BoxDesc<T>* mems, const int* start,
                                       int nmem, int nblocks, const T* W, const T* a, const T* gnext, const T* sigma1,
                                       T da, T mg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
   ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st);
-  if (wall) {
-    if (lnu)
-      adjoint_batch_variant<T, 1, 1>(mode, tile, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
-    else
-      adjoint_batch_variant<T, 1, 0>(mode, tile, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
-  } else {
-    if (lnu)
-      adjoint_batch_variant<T, 0, 1>(mode, tile, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
-    else
-      adjoint_batch_variant<T, 0, 0>(mode, tile, mems, start, nmem, nblocks, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, st);
-  }
+  with_variant(wall, lnu, [&](auto WL, auto LN) {
+    constexpr int WALL = decltype(WL)::value, LNU = decltype(LN)::value;
+    with_tile(tile, [&](auto S) {
+      using Sh = decltype(S);
+      if constexpr (adjoint_fits<T, WALL, LNU, Sh>()) {
+        const dim3 grid(nblocks), blk(Sh::tx * Sh::ty * Sh::tz);
+        if (mode == STAGE_VJP)
+          hipLaunchKernelGGL((k_adjoint_stage_batch<T, STAGE_VJP, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st,
+                             mems, start, nmem, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s);
+        else
+          hipLaunchKernelGGL((k_adjoint_stage_batch<T, STAGE_FIN, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st,
+                             mems, start, nmem, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s);
+      }
+    });
+  });
   return hipGetLastError();
 }
 
