@@ -23,6 +23,9 @@
  *     differences; sigma = mu (grad u + grad u^T) - (2/3) mu (div u) I; alpha = gamma mu / Pr;
  *   - classical RK4 with fixed dt.
  *
+ * Size limit: a state array (5 N values) must span less than 4 GiB (N < 2^28 / 1.25 cells in FP32,
+ * half that in FP64); larger grids are rejected with ADJ_ESHAPE.
+ *
  * Memory: every state-sized array is a DEVICE pointer owned by the caller, structure-of-arrays,
  * var-major: a[v*N + (k*ny + j)*nx + i], v = 0..4, N = nx*ny*nz, element type double when
  * grid->precision == ADJ_F64 and float when ADJ_F32.  Scalars marked "device double" are FP64 in

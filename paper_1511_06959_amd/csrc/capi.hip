@@ -89,6 +89,8 @@ int check_grid(const adj_grid* g, bool need_dt) {
   if (!(g->mu >= 0.0) || !std::isfinite(g->mu)) return fail(ADJ_EINVAL, "mu must be >= 0");
   if (need_dt && (!(g->dt > 0.0) || !std::isfinite(g->dt))) return fail(ADJ_EINVAL, "dt must be > 0");
   if (g->precision != ADJ_F64 && g->precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", g->precision);
+  if (5 * (double)ncells(g) * (g->precision == ADJ_F64 ? 8.0 : 4.0) >= 4294967296.0)
+    return fail(ADJ_ESHAPE, "state arrays must span less than 4 GiB (%lld cells)", ncells(g));
   if (g->ckpt_format != ADJ_CKPT_NATIVE && g->ckpt_format != ADJ_CKPT_BF16)
     return fail(ADJ_EINVAL, "bad ckpt_format %d", g->ckpt_format);
   if (g->ckpt_format == ADJ_CKPT_BF16 && g->precision != ADJ_F32)

@@ -38,6 +38,27 @@ struct Consts {
   T gamma, mu, alpha, dt;
 };
 
+// Buffer loads: a 128-bit resource (base, byte size) in scalar registers plus a 32-bit per-lane
+// byte offset and a scalar offset.  One offset per cell then serves every field of every array
+// (the scalar offset selects the field), instead of a 64-bit address per load; a read outside
+// the resource returns zero.  Arrays must span less than 4 GiB.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const T* p, long long n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, (int)(unsigned)(n * (long long)sizeof(T)),
+                                           0x00020000);
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// 1/x: the hardware reciprocal in FP32 (within 1 ulp, instead of the ten-instruction correctly
+// rounded division), a division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // Work-groups of a 1-D launch are dispatched to the eight XCDs round-robin (work-group b on XCD
 // b mod 8), and each XCD has its own L2.  xcd_tile turns the dispatch index into a logical tile
 // index such that every XCD walks one contiguous run of tiles: tiles that share halo lines (the
@@ -82,9 +103,15 @@ __device__ __forceinline__ int find_box(const int* __restrict__ start, int n, in
   return __builtin_amdgcn_readfirstlane(b);
 }
 
+// Periodic index.  Halo indices are at most a tile away from [0, n): one conditional shift covers
+// them unless the grid is smaller than the tile, which takes the remainder.
 __device__ __forceinline__ int wrap_index(int i, int n) {
-  i %= n;
-  return i < 0 ? i + n : i;
+  int r = i < 0 ? i + n : (i >= n ? i - n : i);
+  if (r < 0 || r >= n) {
+    r = i % n;
+    r = r < 0 ? r + n : r;
+  }
+  return r;
 }
 
 // x index of a cell or ghost: periodic wrap, or the mirror image across a slip wall.  Ghosts
@@ -100,6 +127,24 @@ __device__ __forceinline__ int map_x(int i, int nx, int wall, int& mirror) {
     i = 2 * nx - 1 - i;
   }
   return i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+}
+
+// 32-bit form of box_cell for grids of fewer than 2^31 cells, with the x boundary known at compile
+// time (WALL = 1: slip walls, 0: periodic).
+template <int WALL>
+__device__ __forceinline__ int box_cell32(const int nx, const int ny, const int nz, int gx, int gy, int gz,
+                                          int& mirror, int& real) {
+  if (WALL) {
+    real = gx >= 0 && gx < nx;
+    gx = map_x(gx, nx, 1, mirror);
+  } else {
+    real = 1;
+    mirror = 0;
+    gx = wrap_index(gx, nx);
+  }
+  gy = wrap_index(gy, ny);
+  gz = wrap_index(gz, nz);
+  return (gz * ny + gy) * nx + gx;
 }
 
 // Linear cell index of tile-box position (bx, by, bz) for a box whose origin (halo included) is

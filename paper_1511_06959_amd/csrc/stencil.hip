@@ -20,36 +20,37 @@ namespace adjns {
 // ------------------------------------------------------------------------------------------
 namespace {
 
-// LDS field order of the primal box (P_H: specific total energy E/rho)
+// LDS field order of the primal box (P_H: specific total energy E/rho).  The planes hold HALF of
+// each field, so that a face mean is one addition (halving is exact: the sums round exactly as
+// the halved sums of the full values would).
 enum { P_RHO = 0, P_U1, P_U2, P_U3, P_E, P_P, P_H, P_NF };
 
 // Convective flux through the direction-D face between box cells a (lower) and b.
 template <typename T, int NB, int D>
 __device__ __forceinline__ void conv_face(const T (*sm)[NB], int a, int b, T F[5]) {
-  const T r2 = sm[P_RHO][a] + sm[P_RHO][b];
-  const T v[3] = {T(0.5) * (sm[P_U1][a] + sm[P_U1][b]), T(0.5) * (sm[P_U2][a] + sm[P_U2][b]),
-                  T(0.5) * (sm[P_U3][a] + sm[P_U3][b])};
-  const T H2 = sm[P_H][a] + sm[P_H][b], P2 = sm[P_P][a] + sm[P_P][b];
-  const T m = T(0.5) * r2 * v[D];
+  const T r = sm[P_RHO][a] + sm[P_RHO][b];
+  const T v[3] = {sm[P_U1][a] + sm[P_U1][b], sm[P_U2][a] + sm[P_U2][b], sm[P_U3][a] + sm[P_U3][b]};
+  const T H = sm[P_H][a] + sm[P_H][b], P = sm[P_P][a] + sm[P_P][b];
+  const T m = r * v[D];
   F[0] = m;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) F[1 + k] = m * v[k] + (k == D ? T(0.5) * P2 : T(0));
-  F[4] = T(0.5) * (m * H2 + P2 * v[D]);
+  for (int k = 0; k < 3; ++k) F[1 + k] = m * v[k] + (k == D ? P : T(0));
+  F[4] = m * H + P * v[D];
 }
 
 // Forward viscous stress row sigma_d. on the face between box cells A and A + e_d.
-// Velocity fields are read from `U` (three LDS planes of NB values).
+// Velocity fields are read from `U` (three LDS planes of NB values holding u/2).
 template <typename T, int NB, int D>
 __device__ __forceinline__ void face_stress(const T* __restrict__ U, const int st[3], int A, T mu,
                                             const T idx[3], T sig[3]) {
   constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
   const int B = A + st[D];
-  const T in = idx[D];
+  const T in = T(2) * idx[D];
   T gn[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) gn[k] = (U[k * NB + B] - U[k * NB + A]) * in;
   // tangential gradients d_t u_D and d_t u_t at the face: mean of the two cells' central differences
-  const T q1 = T(0.25) * idx[t1], q2 = T(0.25) * idx[t2];
+  const T q1 = T(0.5) * idx[t1], q2 = T(0.5) * idx[t2];
   const int s1 = st[t1], s2 = st[t2];
   const T g1D = (U[D * NB + A + s1] - U[D * NB + A - s1] + U[D * NB + B + s1] - U[D * NB + B - s1]) * q1;
   const T g11 = (U[t1 * NB + A + s1] - U[t1 * NB + A - s1] + U[t1 * NB + B + s1] - U[t1 * NB + B - s1]) * q1;
@@ -69,11 +70,11 @@ __device__ __forceinline__ void visc_flux(const T (*sm)[NB], const int st[3], in
   const int B = A + st[D];
   T work = T(0);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) work += T(0.5) * (sm[P_U1 + k][A] + sm[P_U1 + k][B]) * sig[k];
+  for (int k = 0; k < 3; ++k) work += (sm[P_U1 + k][A] + sm[P_U1 + k][B]) * sig[k];
   G[0] = sig[0];
   G[1] = sig[1];
   G[2] = sig[2];
-  G[3] = work + c.alpha * (sm[P_E][B] - sm[P_E][A]) * c.idx[D];
+  G[3] = work + (T(2) * c.alpha) * (sm[P_E][B] - sm[P_E][A]) * c.idx[D];
 }
 
 template <typename T, int NB, int D>
@@ -117,14 +118,19 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
   constexpr int NIT = (NB + NT - 1) / NT;
   T wv[NIT][5];
   int mir[NIT];
+  const auto rW = buf_rsrc(W, 5 * N);
+  const unsigned fb = (unsigned)(N * (long long)sizeof(T));  // bytes per field
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int b = min(tid + it * NT, NB - 1);
     const int bx = b % Bx::BX, by = (b / Bx::BX) % Bx::BY, bz = b / (Bx::BX * Bx::BY);
     int real;
-    const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - 1, y0 + by - 1, z0 + bz - 1, mir[it], real);
+    const int gx = x0 + bx - 1, gy = y0 + by - 1, gz = z0 + bz - 1;
+    const unsigned off = (unsigned)(c.wall ? box_cell32<1>(c.nx, c.ny, c.nz, gx, gy, gz, mir[it], real)
+                                           : box_cell32<0>(c.nx, c.ny, c.nz, gx, gy, gz, mir[it], real)) *
+                         (unsigned)sizeof(T);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) wv[it][v] = W[v * N + gi];
+    for (int v = 0; v < 5; ++v) wv[it][v] = buf_load(rW, off, v * fb, T());
   }
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
@@ -132,16 +138,17 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
     if (it + 1 < NIT || b < NB) {
       const T r = wv[it][0], Et = wv[it][4];
       const T m1 = mir[it] ? -wv[it][1] : wv[it][1];
-      const T ri = T(1) / r;
-      const T u1 = m1 * ri, u2 = wv[it][2] * ri, u3 = wv[it][3] * ri;
-      const T e = Et * ri - T(0.5) * (u1 * u1 + u2 * u2 + u3 * u3);
-      sm[P_RHO][b] = r;
-      sm[P_U1][b] = u1;
-      sm[P_U2][b] = u2;
-      sm[P_U3][b] = u3;
-      sm[P_E][b] = e;
-      sm[P_P][b] = gm1 * r * e;
-      sm[P_H][b] = Et * ri;
+      const T ri = recip(r), hri = T(0.5) * ri;
+      const T h1 = m1 * hri, h2 = wv[it][2] * hri, h3 = wv[it][3] * hri;  // u/2
+      const T hH = Et * hri;                                               // (E/rho)/2
+      const T he = hH - (h1 * h1 + h2 * h2 + h3 * h3);                     // e/2
+      sm[P_RHO][b] = T(0.5) * r;
+      sm[P_U1][b] = h1;
+      sm[P_U2][b] = h2;
+      sm[P_U3][b] = h3;
+      sm[P_E][b] = he;
+      sm[P_P][b] = gm1 * r * he;
+      sm[P_H][b] = hH;
     }
   }
   const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
@@ -299,10 +306,9 @@ __device__ __forceinline__ void face_records(const T (*sm)[NB], T (*fr)[NF], T (
     const int ax = F::X0 + f % F::NX, ay = (f / F::NX) % F::NY, az = f / (F::NX * F::NY);
     const int A = az * B::SZ + ay * B::SY + ax, Bc = A + st[D];
     const T dK4 = sm[A_K4][A] - sm[A_K4][Bc];
-    const T hd = T(0.5) * dK4;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      fr[k][f] = (sm[A_K1 + k][A] - sm[A_K1 + k][Bc]) + hd * (sm[A_U1 + k][A] + sm[A_U1 + k][Bc]);
+      fr[k][f] = (sm[A_K1 + k][A] - sm[A_K1 + k][Bc]) + dK4 * (sm[A_U1 + k][A] + sm[A_U1 + k][Bc]);
     fr[3][f] = dK4;
   }
   const T qs = T(0.5) * c.idx[D];
@@ -373,7 +379,8 @@ __device__ __forceinline__ void face_gather(const T (*fr)[NF], const T (*fq)[NQF
   }
 }
 
-// Convective transpose at box cell p (own fields r0, u, H0, P0): half of the adjoint of every
+// Convective transpose at box cell p (own fields r0, u, H0, P0, all halved like the LDS planes):
+// half of the adjoint of every
 // face mean, accumulated as (rho^, u^, H^, P^).  The fields of the neighbours come from the LDS
 // planes K (kh), U (u) and Q (rho, E/rho, p).  wallside: the direction-0 face on this side is a
 // slip wall, whose ghost-image share (u^_x odd) folds into the cell as well.
@@ -388,9 +395,9 @@ __device__ __forceinline__ void adj_conv_dir(const T (*K)[NB], const T (*U)[NB],
     T G[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) G[v] = sg * (K[v][q] - k0[v]);
-    const T r = T(0.5) * (r0 + Q[0][q]);
-    const T v[3] = {T(0.5) * (u[0] + U[0][q]), T(0.5) * (u[1] + U[1][q]), T(0.5) * (u[2] + U[2][q])};
-    const T H = T(0.5) * (H0 + Q[1][q]), P = T(0.5) * (P0 + Q[2][q]);
+    const T r = r0 + Q[0][q];
+    const T v[3] = {u[0] + U[0][q], u[1] + U[1][q], u[2] + U[2][q]};
+    const T H = H0 + Q[1][q], P = P0 + Q[2][q];
     const T m = r * v[D];
     const T phi = G[0] + v[0] * G[1] + v[1] * G[2] + v[2] * G[3] + H * G[4];
     // own half-share, plus the ghost's half-share at a wall face (u^_x flips, the rest adds)
@@ -459,31 +466,37 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
   const T cgn = gnext ? cg : T(0);
   T wv[NIT][5], av[NIT][5], gv[NIT][5], nv[NIT];
   int mir[NIT], rl[NIT];
+  const auto rW = buf_rsrc(W, 5 * N), rA = buf_rsrc(a, 5 * N), rG = buf_rsrc(gn, 5 * N);
+  const auto rN = buf_rsrc(LNU ? nu : W, N);
+  const unsigned fb = (unsigned)(N * (long long)sizeof(T));  // bytes per field
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int b = min(tid + it * NT, NB - 1);
     const int bx = b % Bx::BX, by = (b / Bx::BX) % Bx::BY, bz = b / (Bx::BX * Bx::BY);
-    const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - HX, y0 + by - 1, z0 + bz - 1, mir[it], rl[it]);
+    const unsigned off =
+        (unsigned)box_cell32<WALL>(c.nx, c.ny, c.nz, x0 + bx - HX, y0 + by - 1, z0 + bz - 1, mir[it], rl[it]) *
+        (unsigned)sizeof(T);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) wv[it][v] = W[v * N + gi];
+    for (int v = 0; v < 5; ++v) wv[it][v] = buf_load(rW, off, v * fb, T());
 #pragma unroll
-    for (int v = 0; v < 5; ++v) av[it][v] = a[v * N + gi];
+    for (int v = 0; v < 5; ++v) av[it][v] = buf_load(rA, off, v * fb, T());
 #pragma unroll
-    for (int v = 0; v < 5; ++v) gv[it][v] = gn[v * N + gi];
-    nv[it] = LNU ? nscale * nu[gi] : T(0);
+    for (int v = 0; v < 5; ++v) gv[it][v] = buf_load(rG, off, v * fb, T());
+    nv[it] = LNU ? nscale * buf_load(rN, off, 0, T()) : T(0);
   }
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int b = tid + it * NT;
     if (it + 1 < NIT || b < NB) {
-      const T r = wv[it][0], ri = T(1) / r;
-      const T u1 = (mir[it] ? -wv[it][1] : wv[it][1]) * ri, u2 = wv[it][2] * ri, u3 = wv[it][3] * ri;
-      sm[A_U1][b] = u1;
-      sm[A_U2][b] = u2;
-      sm[A_U3][b] = u3;
-      Q[0][b] = r;
-      Q[1][b] = wv[it][4] * ri;
-      Q[2][b] = gm1 * (wv[it][4] - T(0.5) * r * (u1 * u1 + u2 * u2 + u3 * u3));
+      const T r = wv[it][0], ri = recip(r);
+      const T hri = T(0.5) * ri;
+      const T h1 = (mir[it] ? -wv[it][1] : wv[it][1]) * hri, h2 = wv[it][2] * hri, h3 = wv[it][3] * hri;
+      sm[A_U1][b] = h1;
+      sm[A_U2][b] = h2;
+      sm[A_U3][b] = h3;
+      Q[0][b] = T(0.5) * r;
+      Q[1][b] = wv[it][4] * hri;
+      Q[2][b] = gm1 * (T(0.5) * wv[it][4] - r * (h1 * h1 + h2 * h2 + h3 * h3));
 #pragma unroll
       for (int v = 0; v < 5; ++v) sm[A_K0 + v][b] = rl[it] ? ca * av[it][v] + cgn * gv[it][v] : T(0);
       if (LNU) sm[LNU ? A_NU : 0][b] = rl[it] ? nv[it] : T(0);
@@ -499,14 +512,6 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
   const int p = qz * Bx::SZ + qy * Bx::SY + qx;
   const long long gi = ((long long)(active ? gz : 0) * c.ny + (active ? gy : 0)) * c.nx + (active ? gx : 0);
   T r0 = T(1), ri = T(0), e = T(0), uc[3] = {T(0), T(0), T(0)};
-  if (active) {
-    r0 = W[gi];
-    ri = T(1) / r0;
-    uc[0] = W[N + gi] * ri;
-    uc[1] = W[2 * N + gi] * ri;
-    uc[2] = W[3 * N + gi] * ri;
-    e = W[4 * N + gi] * ri - T(0.5) * (uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
-  }
   // stage-1 operands at the cell itself, fetched now so that their latency hides behind the
   // face phases
   T fa[5], f2[5], f3[5], f4[5];
@@ -524,16 +529,23 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
   T uhv[3] = {T(0), T(0), T(0)}, ehv = T(0);
   __syncthreads();
   if (active) {
+    // the cell's own fields, halved as in the LDS planes
+    const T hr0 = Q[0][p], hu[3] = {sm[A_U1][p], sm[A_U2][p], sm[A_U3][p]};
+    const T H0 = Q[1][p], P0 = Q[2][p];
+    r0 = T(2) * hr0;
+    ri = recip(r0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) uc[k] = T(2) * hu[k];
+    e = T(2) * (H0 - (hu[0] * hu[0] + hu[1] * hu[1] + hu[2] * hu[2]));
     // convective transpose, in (rho, u, E/rho, p), then moved to (rho, u, e)
-    const T H0 = e + T(0.5) * (uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]), P0 = gm1 * r0 * e;
     T k0[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) k0[v] = sm[A_K0 + v][p];
     const bool wlo = WALL && gx == 0, whi = WALL && gx == c.nx - 1;
     T Hh = T(0), Ph = T(0);
-    adj_conv_dir<T, NB, NB, 0>(&sm[A_K0], &sm[A_U1], Q, p, st[0], c, r0, uc, H0, P0, k0, wlo, whi, rh, uh, Hh, Ph);
-    adj_conv_dir<T, NB, NB, 1>(&sm[A_K0], &sm[A_U1], Q, p, st[1], c, r0, uc, H0, P0, k0, false, false, rh, uh, Hh, Ph);
-    adj_conv_dir<T, NB, NB, 2>(&sm[A_K0], &sm[A_U1], Q, p, st[2], c, r0, uc, H0, P0, k0, false, false, rh, uh, Hh, Ph);
+    adj_conv_dir<T, NB, NB, 0>(&sm[A_K0], &sm[A_U1], Q, p, st[0], c, hr0, hu, H0, P0, k0, wlo, whi, rh, uh, Hh, Ph);
+    adj_conv_dir<T, NB, NB, 1>(&sm[A_K0], &sm[A_U1], Q, p, st[1], c, hr0, hu, H0, P0, k0, false, false, rh, uh, Hh, Ph);
+    adj_conv_dir<T, NB, NB, 2>(&sm[A_K0], &sm[A_U1], Q, p, st[2], c, hr0, hu, H0, P0, k0, false, false, rh, uh, Hh, Ph);
     rh += gm1 * e * Ph;
     eh += Hh + gm1 * r0 * Ph;
 #pragma unroll
