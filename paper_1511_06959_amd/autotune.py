@@ -65,9 +65,11 @@ def _time(fn, reps):
     return a.elapsed_time(b) / reps
 
 
-def tune(g, reps=20, use_cache=True, verbose=False):
+def tune(g, reps=20, use_cache=True, verbose=False, rounds=3, margin=0.03):
     """Pick and install the fastest tile of both kernel classes for grid g; returns
-    {kernel_class: (tile_id, {tile_id: ms})}."""
+    {kernel_class: (tile_id, {tile_id: ms})}.  Every tile is timed in `rounds` interleaved rounds
+    (best round kept); the tile installed before tuning stays unless another is faster by more
+    than `margin`, so that near-ties do not flip between runs."""
     db = _load() if use_cache else {}
     out = {}
     w, kh = _state(g, 0)
@@ -80,13 +82,17 @@ def tune(g, reps=20, use_cache=True, verbose=False):
             continue
         prev = get_tile(kclass, g.precision)
         times = {}
-        for t in TILES:
-            set_tile(kclass, g.precision, t)
-            if kclass == PROF_ADJOINT_STAGE:
-                times[t] = _time(lambda: vjp(g, w, kh, buf), reps)
-            else:
-                times[t] = _time(lambda: residual(g, w, None, buf), reps)
+        for _ in range(rounds):
+            for t in TILES:
+                set_tile(kclass, g.precision, t)
+                if kclass == PROF_ADJOINT_STAGE:
+                    ms = _time(lambda: vjp(g, w, kh, buf), reps)
+                else:
+                    ms = _time(lambda: residual(g, w, None, buf), reps)
+                times[t] = min(times.get(t, ms), ms)
         best = min(times, key=times.get) if times else prev
+        if prev in times and times[prev] <= (1.0 + margin) * times[best]:
+            best = prev
         set_tile(kclass, g.precision, best)
         out[kclass] = (best, times)
         db[key] = {"tile": best, "ms": times}

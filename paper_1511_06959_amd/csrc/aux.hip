@@ -753,9 +753,9 @@ inline int ew_blocks(long long n) {
 // ------------------------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_sigma1(const Consts<T>& c, const T* w, T scale, T* out, hipStream_t st) {
-  ProfScope ps(ADJ_PROF_SIGMA1, st);
+  ProfScope ps(ADJ_PROF_SIGMA1, st, true);
   const int nb = (int)((c.N + RB - 1) / RB);
-  hipLaunchKernelGGL((k_sigma1<T>), dim3(nb), dim3(RB), 0, st, c, w, scale, out);
+  timed_launch(ps, k_sigma1<T>, dim3(nb), dim3(RB), st, c, w, scale, out);
   return hipGetLastError();
 }
 
@@ -833,8 +833,8 @@ hipError_t launch_ckpt_decode(const Consts<float>& c, const float* header, const
 template <typename T>
 hipError_t launch_sigma1_batch(const BoxDesc<T>* boxes, const int* start, int nbox, int nblocks, const T* w, T* out,
                                hipStream_t st) {
-  ProfScope ps(ADJ_PROF_SIGMA1, st);
-  hipLaunchKernelGGL((k_sigma1_batch<T>), dim3(nblocks), dim3(RB), 0, st, boxes, start, nbox, w, out);
+  ProfScope ps(ADJ_PROF_SIGMA1, st, true);
+  timed_launch(ps, k_sigma1_batch<T>, dim3(nblocks), dim3(RB), st, boxes, start, nbox, w, out);
   return hipGetLastError();
 }
 

@@ -703,48 +703,45 @@ constexpr bool adjoint_fits() {
 template <typename T>
 hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
                                const T* W3, T cR, T* out, hipStream_t st) {
-  ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st);
+  ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st, true);
   with_tile(tile_choice(ADJ_PROF_PRIMAL_STAGE, sizeof(T) == 8), [&](auto S) {
     using Sh = decltype(S);
     const dim3 grid = tile_grid<Sh::tx, Sh::ty, Sh::tz>(c.nx, c.ny, c.nz), blk(Sh::tx * Sh::ty * Sh::tz);
     if (mode == STAGE_RES)
-      hipLaunchKernelGGL((k_primal_stage<T, STAGE_RES, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, c, W, wn, s, W2, W3,
-                         cR, out);
+      timed_launch(ps, k_primal_stage<T, STAGE_RES, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out);
     else if (mode == STAGE_LIN)
-      hipLaunchKernelGGL((k_primal_stage<T, STAGE_LIN, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, c, W, wn, s, W2, W3,
-                         cR, out);
+      timed_launch(ps, k_primal_stage<T, STAGE_LIN, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out);
     else
-      hipLaunchKernelGGL((k_primal_stage<T, STAGE_FIN, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, c, W, wn, s, W2, W3,
-                         cR, out);
+      timed_launch(ps, k_primal_stage<T, STAGE_FIN, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out);
   });
   return hipGetLastError();
 }
 
 template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
-static void adjoint_launch(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu, T ca,
-                           T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
+static void adjoint_launch(ProfScope& ps, int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext,
+                           const T* nu, T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
   const dim3 grid = tile_grid<TX, TY, TZ>(c.nx, c.ny, c.nz), blk(TX * TY * TZ);
   if (mode == STAGE_VJP)
-    hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_VJP, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, c, W, a, gnext, nu, ca,
-                       cg, g3, g4, out, grad_s);
+    timed_launch(ps, k_adjoint_stage<T, STAGE_VJP, WALL, LNU, TX, TY, TZ>, grid, blk, st, c, W, a, gnext, nu, ca, cg,
+                 g3, g4, out, grad_s);
   else
-    hipLaunchKernelGGL((k_adjoint_stage<T, STAGE_FIN, WALL, LNU, TX, TY, TZ>), grid, blk, 0, st, c, W, a, gnext, nu, ca,
-                       cg, g3, g4, out, grad_s);
+    timed_launch(ps, k_adjoint_stage<T, STAGE_FIN, WALL, LNU, TX, TY, TZ>, grid, blk, st, c, W, a, gnext, nu, ca, cg,
+                 g3, g4, out, grad_s);
 }
 
 template <typename T>
 hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,
                                 T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
-  ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st);
+  ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st, true);
   with_variant(c.wall, nu != nullptr, [&](auto WL, auto LN) {
     constexpr int WALL = decltype(WL)::value, LNU = decltype(LN)::value;
     with_tile(tile_choice(ADJ_PROF_ADJOINT_STAGE, sizeof(T) == 8), [&](auto S) {
       using Sh = decltype(S);
       if constexpr (adjoint_fits<T, WALL, LNU, Sh>())
-        adjoint_launch<T, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s,
-                                                             st);
+        adjoint_launch<T, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>(ps, mode, c, W, a, gnext, nu, ca, cg, g3, g4, out,
+                                                             grad_s, st);
       else
-        adjoint_launch<T, WALL, LNU, 16, 4, 4>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
+        adjoint_launch<T, WALL, LNU, 16, 4, 4>(ps, mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
     });
   });
   return hipGetLastError();
@@ -780,19 +777,16 @@ template <typename T>
 hipError_t launch_primal_stage_batch(int mode, int tile, const BoxDesc<T>* boxes, const int* start, int nbox,
                                      int nblocks, const T* W, const T* wn, const T* s, const T* W2, const T* W3,
                                      T cfac, T* out, hipStream_t st) {
-  ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st);
+  ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st, true);
   with_tile(tile, [&](auto S) {
     using Sh = decltype(S);
     const dim3 grid(nblocks), blk(Sh::tx * Sh::ty * Sh::tz);
     if (mode == STAGE_RES)
-      hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_RES, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, boxes, start,
-                         nbox, W, wn, s, W2, W3, cfac, out);
+      timed_launch(ps, k_primal_stage_batch<T, STAGE_RES, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, boxes, start, nbox, W, wn, s, W2, W3, cfac, out);
     else if (mode == STAGE_LIN)
-      hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_LIN, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, boxes, start,
-                         nbox, W, wn, s, W2, W3, cfac, out);
+      timed_launch(ps, k_primal_stage_batch<T, STAGE_LIN, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, boxes, start, nbox, W, wn, s, W2, W3, cfac, out);
     else
-      hipLaunchKernelGGL((k_primal_stage_batch<T, STAGE_FIN, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st, boxes, start,
-                         nbox, W, wn, s, W2, W3, cfac, out);
+      timed_launch(ps, k_primal_stage_batch<T, STAGE_FIN, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, boxes, start, nbox, W, wn, s, W2, W3, cfac, out);
   });
   return hipGetLastError();
 }
@@ -802,7 +796,7 @@ template <typename T>
 hipError_t launch_adjoint_stage_batch(int mode, int tile, int wall, int lnu, const BoxDesc<T>* mems, const int* start,
                                       int nmem, int nblocks, const T* W, const T* a, const T* gnext, const T* sigma1,
                                       T da, T mg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
-  ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st);
+  ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st, true);
   with_variant(wall, lnu, [&](auto WL, auto LN) {
     constexpr int WALL = decltype(WL)::value, LNU = decltype(LN)::value;
     with_tile(tile, [&](auto S) {
@@ -810,11 +804,11 @@ hipError_t launch_adjoint_stage_batch(int mode, int tile, int wall, int lnu, con
       if constexpr (adjoint_fits<T, WALL, LNU, Sh>()) {
         const dim3 grid(nblocks), blk(Sh::tx * Sh::ty * Sh::tz);
         if (mode == STAGE_VJP)
-          hipLaunchKernelGGL((k_adjoint_stage_batch<T, STAGE_VJP, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st,
-                             mems, start, nmem, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s);
+          timed_launch(ps, k_adjoint_stage_batch<T, STAGE_VJP, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, mems, start, nmem, W, a, gnext, sigma1, da, mg, g3, g4,
+                       out, grad_s);
         else
-          hipLaunchKernelGGL((k_adjoint_stage_batch<T, STAGE_FIN, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>), grid, blk, 0, st,
-                             mems, start, nmem, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s);
+          timed_launch(ps, k_adjoint_stage_batch<T, STAGE_FIN, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, mems, start, nmem, W, a, gnext, sigma1, da, mg, g3, g4,
+                       out, grad_s);
       }
     });
   });

@@ -9,6 +9,11 @@
     python -m paper_1511_06959_amd.profile_run summarize <rocprofv3 output dir> [--kernel SUBSTR]
         mean value per dispatch of every counter, per kernel, from the *_counter_collection.csv
         files under the directory
+    python -m paper_1511_06959_amd.profile_run traffic --fetch D --write D --copy-fetch D --copy-write D
+        --cells N [--kernel k_adjoint_stage]
+        HBM bytes per launch of a kernel from FETCH_SIZE / WRITE_SIZE runs, calibrated on the copy runs
+    python -m paper_1511_06959_amd.profile_run trace <dir> --title T --command C
+        markdown table of a --kernel-trace --stats run
 
 Run the first two under rocprofv3, e.g.
     rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o run --output-format csv -- \
@@ -102,6 +107,74 @@ def summarize(outdir, kernel=None):
         print(f"| `{k}` | {nd} | " + " | ".join(f"{v:.6g}" for v in vals) + " |")
 
 
+def _counter_means(outdir, kernel):
+    """{kernel name: (dispatches, mean value)} of the single counter in a rocprofv3 output dir."""
+    acc, disp = defaultdict(float), defaultdict(set)
+    for f in glob.glob(os.path.join(outdir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                k = short_name(row.get("Kernel_Name", ""))
+                if kernel in k:
+                    acc[k] += float(row["Counter_Value"])
+                    disp[k].add(row.get("Dispatch_Id"))
+    return {k: (len(disp[k]), acc[k] / max(1, len(disp[k]))) for k in acc}
+
+
+def traffic(fetch, write, copy_fetch, copy_write, mib, cells, kernel, commands):
+    """key = value file of HBM bytes per cell and launch of `kernel` (all its instantiations,
+    weighted by dispatch count), FETCH_SIZE / WRITE_SIZE scaled by what they read for a copy of
+    mib MiB (which reads and writes exactly that much)."""
+    import hashlib
+    cf = _counter_means(copy_fetch, "copyBuffer")
+    cw = _counter_means(copy_write, "copyBuffer")
+    (_, cfv), = cf.values()
+    (_, cwv), = cw.values()
+    sf, sw = mib * 1024.0 / cfv, mib * 1024.0 / cwv
+    fm, wm = _counter_means(fetch, kernel), _counter_means(write, kernel)
+    nd = sum(n for n, _ in fm.values())
+    fkib = sum(n * v for n, v in fm.values()) / nd
+    wkib = sum(n * v for n, v in wm.values()) / sum(n for n, _ in wm.values())
+    byts = (fkib * sf + wkib * sw) * 1024.0
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for name in ("stencil.hip", "common.hpp", "kernels.hpp"):
+        h.update(open(os.path.join(here, "csrc", name), "rb").read())
+    print(f"# HBM traffic of {kernel} (rocprofv3 FETCH_SIZE and WRITE_SIZE, separate runs), {cells} cells")
+    for c in commands:
+        print(f"# command: {c}")
+    print(f"# calibration: copy of {mib} MiB reads FETCH_SIZE {cfv:.0f} KiB, WRITE_SIZE {cwv:.0f} KiB per dispatch")
+    print(f"# scale factors (true / counter): fetch {sf:.4f}, write {sw:.4f}")
+    for k in sorted(fm):
+        print(f"# {k}: {fm[k][0]} dispatches, FETCH_SIZE {fm[k][1]:.1f} KiB, WRITE_SIZE {wm.get(k, (0, 0))[1]:.1f} KiB")
+    print(f"kernel_source_sha256 = {h.hexdigest()}")
+    print(f"fetch_bytes_per_launch = {fkib * sf * 1024.0:.6g}")
+    print(f"write_bytes_per_launch = {wkib * sw * 1024.0:.6g}")
+    print(f"bytes_per_cell_launch_f32 = {byts / cells:.6g}")
+
+
+def trace_summary(outdir, title, command):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (*_kernel_stats.csv)."""
+    files = glob.glob(os.path.join(outdir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        sys.exit(f"no kernel_stats.csv under {outdir}")
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    print(f"# {title}\n")
+    print("Command (from the repository root):\n")
+    print("```\n" + command + "\n```\n")
+    print("rocprofv3 kernel-trace statistics:\n")
+    print("| kernel | calls | total (ms) | average (us) | % |")
+    print("|---|---:|---:|---:|---:|")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        pct = float(r.get("Percentage", 0.0))
+        if pct < 0.05:
+            continue
+        print(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+              f"{float(r['AverageNs']) / 1e3:.2f} | {pct:.1f} |")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -116,7 +189,25 @@ def main():
     s = sub.add_parser("summarize")
     s.add_argument("outdir")
     s.add_argument("--kernel", default=None)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        t.add_argument("--" + k.replace("_", "-"), required=True)
+    t.add_argument("--mib", type=int, default=1024)
+    t.add_argument("--cells", type=int, required=True)
+    t.add_argument("--kernel", default="k_adjoint_stage")
+    t.add_argument("--command", action="append", default=[])
+    r = sub.add_parser("trace")
+    r.add_argument("outdir")
+    r.add_argument("--title", required=True)
+    r.add_argument("--command", required=True)
     args = ap.parse_args()
+    if args.cmd == "traffic":
+        traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.mib, args.cells, args.kernel,
+                args.command)
+        return
+    if args.cmd == "trace":
+        trace_summary(args.outdir, args.title, args.command)
+        return
     if args.cmd == "adjoint":
         run_adjoint(args.n, args.precision, args.reps, args.stages)
     elif args.cmd == "copy":
