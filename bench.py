@@ -77,7 +77,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
                       adj.CKPT_BF16 if ckpt_bf16 else adj.CKPT_NATIVE)
     tiles = {}
     if tune:
-        res = autotune.tune(g, use_cache=False)
+        res = autotune.tune(g)
         for kc, name in ((adj.PROF_ADJOINT_STAGE, "adjoint_stage"), (adj.PROF_PRIMAL_STAGE, "primal_stage")):
             best, times = res[kc]
             tiles[name] = {"tile": "x".join(map(str, adj.TILES[best])),
@@ -185,7 +185,7 @@ def run_ensemble(boxes, precision, steps, warmup, tune=True):
     if tune:
         # tile shapes tuned on the largest box; the ensemble launches use the same kernel bodies
         big = max(grids, key=lambda g: g.ncells)
-        res = autotune.tune(big, use_cache=False)
+        res = autotune.tune(big)
         for kc, name in ((adj.PROF_ADJOINT_STAGE, "adjoint_stage"), (adj.PROF_PRIMAL_STAGE, "primal_stage")):
             best, times = res[kc]
             tiles[name] = {"tile": "x".join(map(str, adj.TILES[best])), "tuned_on": "x".join(map(str, big.n)),

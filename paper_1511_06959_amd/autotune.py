@@ -3,7 +3,7 @@
 For a grid and precision, every compiled tile shape of the reverse-stage kernel (timed through
 ``vjp``) and of the RK4-stage kernel (timed through ``residual``) is run on the device with
 HIP events, and the fastest is installed with ``set_tile``.  Results are cached in a JSON file
-keyed by device name, kernel class, precision, grid shape and boundary type, so a process pays
+keyed by library build, kernel class, precision, grid shape and boundary type, so a process pays
 for the search once per configuration.
 """
 import json
@@ -16,10 +16,17 @@ from . import (F64, PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, TILES, get_tile, resi
 CACHE = os.environ.get("ADJNS_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "adjns_tiles.json"))
 
 
+def _build_id():
+    """Size and modification time of the loaded library: a rebuilt library re-tunes."""
+    from . import LIB_PATH
+    st = os.stat(LIB_PATH)
+    return f"{st.st_size}-{int(st.st_mtime)}"
+
+
 def _key(g, kclass):
-    dev = torch.cuda.get_device_name()
-    return f"{dev}|{'adjoint' if kclass == PROF_ADJOINT_STAGE else 'primal'}|{'f64' if g.precision == F64 else 'f32'}|" \
-           f"{g.n[0]}x{g.n[1]}x{g.n[2]}|bc{g.bc_x}"
+    # the cache is per machine: no device name (a profiler-wrapped process may not see it)
+    return f"{_build_id()}|{'adjoint' if kclass == PROF_ADJOINT_STAGE else 'primal'}|" \
+           f"{'f64' if g.precision == F64 else 'f32'}|{g.n[0]}x{g.n[1]}x{g.n[2]}|bc{g.bc_x}"
 
 
 def _load():

@@ -1,8 +1,9 @@
 """Fixed launch sequences for hardware-counter and kernel-trace profiles, and their summaries.
 
-    python -m paper_1511_06959_amd.profile_run adjoint --n 64 --precision f32 --reps 5 [--stages]
+    python -m paper_1511_06959_amd.profile_run adjoint --n 64 --precision f32 --reps 5 [--stages] [--tune]
         reverse steps (adjoint_step / adjoint_step_stages) on an n^3 Taylor-Green state, Mach 0.1,
-        lambda 0: the reverse-stage kernel as the benchmark launches it
+        lambda 0: the reverse-stage kernel as the benchmark launches it (with --tune, in the tile
+        shapes of the tuning cache that a preceding bench.py run filled)
     python -m paper_1511_06959_amd.profile_run copy --mib 1024 --reps 5
         torch's device-to-device copy of a buffer of known size, the calibration of the byte
         counters (it reads and writes exactly mib MiB per launch)
@@ -29,7 +30,7 @@ import sys
 from collections import defaultdict
 
 
-def run_adjoint(n, precision, reps, stages):
+def run_adjoint(n, precision, reps, stages, tune=False):
     import torch
 
     import paper_1511_06959_amd as adj
@@ -44,6 +45,10 @@ def run_adjoint(n, precision, reps, stages):
     g = adj.Grid.make(nn, L, 1.0 / 1600.0, W.cfl_dt(rho, u, v, w, p, dx), precision=prec)
     w0 = torch.from_numpy(W.conservative(rho, u, v, w, p)).to("cuda", dt)
     ws = adj.workspace(g)
+    if tune:
+        # the tile shapes the benchmark runs (from the tuning cache when it holds this grid)
+        from . import autotune
+        autotune.tune(g)
     obj = adj.Objective.make(adj.OBJ_KE_DISSIPATION)
     w1 = torch.empty_like(w0)
     st = torch.empty(3 * w0.numel(), dtype=dt, device="cuda") if stages else None
@@ -183,6 +188,7 @@ def main():
     a.add_argument("--precision", choices=("f32", "f64"), default="f32")
     a.add_argument("--reps", type=int, default=5)
     a.add_argument("--stages", action="store_true")
+    a.add_argument("--tune", action="store_true", help="install the autotuned tiles (tuning cache) first")
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=1024)
     c.add_argument("--reps", type=int, default=5)
@@ -209,7 +215,7 @@ def main():
         trace_summary(args.outdir, args.title, args.command)
         return
     if args.cmd == "adjoint":
-        run_adjoint(args.n, args.precision, args.reps, args.stages)
+        run_adjoint(args.n, args.precision, args.reps, args.stages, args.tune)
     elif args.cmd == "copy":
         run_copy(args.mib, args.reps)
     else:
