@@ -83,6 +83,14 @@ typedef struct adj_grid {
   int32_t precision;   /* ADJ_F64 or ADJ_F32: element type of states and stencil arithmetic  */
   int32_t ckpt_format; /* ADJ_CKPT_NATIVE or ADJ_CKPT_BF16 (ADJ_F32 only): form of w_n handed
                           to adj_adjoint_step and of ckpt_out written by adj_primal_step       */
+  double w_ref[5];     /* reference state: every state array holds w - w_ref (all zero = the
+                          plain state).  A constant near the mean state keeps FP32 states
+                          accurate at low Mach number, where rho E is dominated by the internal
+                          energy and rho by its mean: the stored deviations are O(the flow's
+                          fluctuations) and lose no digits to the offset, and pressures are
+                          formed from them.  The scheme is unchanged; adjoint fields are
+                          gradients with respect to the stored variables, the same as those
+                          with respect to w.                                                   */
 } adj_grid;
 
 typedef struct adj_objective {

@@ -47,10 +47,13 @@ class Grid(ctypes.Structure):
         ("dt", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("ckpt_format", ctypes.c_int32),
+        ("w_ref", ctypes.c_double * 5),
     ]
 
     @classmethod
-    def make(cls, n, L, mu, dt, gamma=1.4, prandtl=0.72, bc_x=0, precision=F64, ckpt_format=CKPT_NATIVE):
+    def make(cls, n, L, mu, dt, gamma=1.4, prandtl=0.72, bc_x=0, precision=F64, ckpt_format=CKPT_NATIVE,
+             w_ref=None):
+        """w_ref: five reference values; state arrays then hold w - w_ref (see to_stored)."""
         g = cls()
         for d in range(3):
             g.n[d] = int(n[d])
@@ -58,7 +61,23 @@ class Grid(ctypes.Structure):
         g.bc_x = int(bc_x)
         g.gamma, g.prandtl, g.mu, g.dt = float(gamma), float(prandtl), float(mu), float(dt)
         g.precision, g.ckpt_format = int(precision), int(ckpt_format)
+        for v in range(5):
+            g.w_ref[v] = 0.0 if w_ref is None else float(w_ref[v])
         return g
+
+    def to_stored(self, w):
+        """A full state (numpy or torch, (rho, rho u, rho E)) as the library stores it for this
+        grid: w - w_ref field by field, in the input's precision (form it in FP64, then cast)."""
+        w = w.clone() if hasattr(w, "clone") else w.copy()
+        for v in range(5):
+            w.reshape(5, -1)[v] -= self.w_ref[v]
+        return w
+
+    def from_stored(self, w):
+        w = w.clone() if hasattr(w, "clone") else w.copy()
+        for v in range(5):
+            w.reshape(5, -1)[v] += self.w_ref[v]
+        return w
 
     @property
     def ncells(self):
@@ -67,6 +86,13 @@ class Grid(ctypes.Structure):
     @property
     def dtype(self):
         return torch.float64 if self.precision == F64 else torch.float32
+
+
+def reference_state(w):
+    """Field means of a full state: a w_ref for Grid.make that keeps the stored deviations small."""
+    import numpy as np
+    a = np.asarray(w.detach().cpu() if hasattr(w, "detach") else w, dtype=np.float64).reshape(5, -1)
+    return tuple(float(x) for x in a.mean(axis=1))
 
 
 class Objective(ctypes.Structure):

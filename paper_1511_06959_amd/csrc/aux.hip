@@ -63,10 +63,12 @@ __device__ __forceinline__ Q64 load_q64(const Consts<T>& c, const T* __restrict_
                                         double gamma) {
   const long long N = c.N;
   Q64 q;
-  q.rho = (double)w[gi];
-  double m1 = (double)w[N + gi];
+  // stored deviations w - wref, restored in FP64
+  q.rho = (double)w[gi] + (double)c.wref[0];
+  double m1 = (double)w[N + gi] + (double)c.wref[1];
   if (mirror) m1 = -m1;
-  const double m2 = (double)w[2 * N + gi], m3 = (double)w[3 * N + gi], Et = (double)w[4 * N + gi];
+  const double m2 = (double)w[2 * N + gi] + (double)c.wref[2], m3 = (double)w[3 * N + gi] + (double)c.wref[3];
+  const double Et = (double)w[4 * N + gi] + (double)c.wref[4];
   q.ri = 1.0 / q.rho;
   q.u[0] = m1 * q.ri;
   q.u[1] = m2 * q.ri;
@@ -135,16 +137,18 @@ __device__ __forceinline__ QS<T> load_qs(const Consts<T>& c, const T* __restrict
   const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, gx, gy, gz, mirror, real);
   const long long N = c.N;
   QS<T> q;
-  q.rho = w[gi];
-  T m1 = w[N + gi];
+  // stored deviations w - wref
+  q.rho = w[gi] + c.wref[0];
+  T m1 = w[N + gi] + c.wref[1];
   if (mirror) m1 = -m1;
-  const T ri = T(1) / q.rho;
+  const T ri = recip(q.rho);
   q.u[0] = m1 * ri;
-  q.u[1] = w[2 * N + gi] * ri;
-  q.u[2] = w[3 * N + gi] * ri;
-  const T e = w[4 * N + gi] * ri - T(0.5) * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
+  q.u[1] = (w[2 * N + gi] + c.wref[2]) * ri;
+  q.u[2] = (w[3 * N + gi] + c.wref[3]) * ri;
   const T g = c.gamma;
-  q.p = (g - T(1)) * q.rho * e;
+  // p = (gamma-1)((Ed - K) + wref_E), Ed = rho E - wref_E the stored deviation
+  q.p = (g - T(1)) * ((w[4 * N + gi] - T(0.5) * q.rho * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2])) +
+                      c.wref[4]);
   const T cs = sqrt(g * q.p * ri);
   q.a = sqrt((g - T(1)) / g) * cs;
   q.b = cs / sqrt(g);
@@ -438,12 +442,13 @@ __device__ __forceinline__ void load_box_u(const Consts<T>& c, const T* __restri
     const int bx = b % B::BX, by = (b / B::BX) % B::BY, bz = b / (B::BX * B::BY);
     int mirror, real;
     const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - HX, y0 + by - HY, z0 + bz - HY, mirror, real);
-    const T ri = T(1) / w[gi];
-    T m1 = w[N + gi];
+    // stored deviations w - wref
+    const T ri = recip(w[gi] + c.wref[0]);
+    T m1 = w[N + gi] + c.wref[1];
     if (mirror) m1 = -m1;
     su[0][b] = m1 * ri;
-    su[1][b] = w[2 * N + gi] * ri;
-    su[2][b] = w[3 * N + gi] * ri;
+    su[1][b] = (w[2 * N + gi] + c.wref[2]) * ri;
+    su[2][b] = (w[3 * N + gi] + c.wref[3]) * ri;
   }
 }
 
@@ -533,8 +538,8 @@ __global__ __launch_bounds__(NT) void k_ked_grad_tile(Consts<T> c, const T* __re
   }
   const long long N = c.N;
   const long long gi = ((long long)gz * c.ny + gy) * c.nx + gx;
-  const T ri = T(1) / w[gi];
-  const T u[3] = {w[N + gi] * ri, w[2 * N + gi] * ri, w[3 * N + gi] * ri};
+  const T ri = recip(w[gi] + c.wref[0]);  // stored deviations w - wref
+  const T u[3] = {(w[N + gi] + c.wref[1]) * ri, (w[2 * N + gi] + c.wref[2]) * ri, (w[3 * N + gi] + c.wref[3]) * ri};
   const T f = (T)(wgt / (double)N);
   T o0 = -f * ri * (u[0] * uh[0] + u[1] * uh[1] + u[2] * uh[2]);
   T o[3] = {f * ri * uh[0], f * ri * uh[1], f * ri * uh[2]};
@@ -600,7 +605,8 @@ __device__ __forceinline__ void plane_face(const Consts<T>& c, const T* __restri
   ir = il + 1;
   const long long N = c.N;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) wf[v] = 0.5 * ((double)w[v * N + il] + (double)w[v * N + ir]);
+  // stored deviations w - wref, restored in FP64
+  for (int v = 0; v < 5; ++v) wf[v] = 0.5 * ((double)w[v * N + il] + (double)w[v * N + ir]) + (double)c.wref[v];
 }
 
 template <typename T>

@@ -88,6 +88,8 @@ int check_grid(const adj_grid* g, bool need_dt) {
   if (!(g->prandtl > 0.0)) return fail(ADJ_EINVAL, "prandtl must be > 0");
   if (!(g->mu >= 0.0) || !std::isfinite(g->mu)) return fail(ADJ_EINVAL, "mu must be >= 0");
   if (need_dt && (!(g->dt > 0.0) || !std::isfinite(g->dt))) return fail(ADJ_EINVAL, "dt must be > 0");
+  for (int v = 0; v < 5; ++v)
+    if (!std::isfinite(g->w_ref[v])) return fail(ADJ_EINVAL, "w_ref[%d] must be finite", v);
   if (g->precision != ADJ_F64 && g->precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", g->precision);
   if (5 * (double)ncells(g) * (g->precision == ADJ_F64 ? 8.0 : 4.0) >= 4294967296.0)
     return fail(ADJ_ESHAPE, "state arrays must span less than 4 GiB (%lld cells)", ncells(g));
@@ -134,6 +136,7 @@ Consts<T> consts(const adj_grid* g) {
   c.mu = (T)g->mu;
   c.alpha = (T)(g->gamma * g->mu / g->prandtl);
   c.dt = (T)g->dt;
+  for (int v = 0; v < 5; ++v) c.wref[v] = (T)g->w_ref[v];
   return c;
 }
 

@@ -25,17 +25,20 @@ namespace {
 // the halved sums of the full values would).
 enum { P_RHO = 0, P_U1, P_U2, P_U3, P_E, P_P, P_H, P_NF };
 
-// Convective flux through the direction-D face between box cells a (lower) and b.
+// Convective flux through the direction-D face between box cells a (lower) and b.  The P_P planes
+// hold p - p0 (p0 = (gamma-1) wref_E, the pressure of the reference state): the momentum flux
+// carries that deviation, since a uniform pressure has no divergence, and keeps its low-order
+// digits in FP32 at low Mach number; the energy flux takes the full mean pressure.
 template <typename T, int NB, int D>
-__device__ __forceinline__ void conv_face(const T (*sm)[NB], int a, int b, T F[5]) {
+__device__ __forceinline__ void conv_face(const T (*sm)[NB], int a, int b, T p0, T F[5]) {
   const T r = sm[P_RHO][a] + sm[P_RHO][b];
   const T v[3] = {sm[P_U1][a] + sm[P_U1][b], sm[P_U2][a] + sm[P_U2][b], sm[P_U3][a] + sm[P_U3][b]};
-  const T H = sm[P_H][a] + sm[P_H][b], P = sm[P_P][a] + sm[P_P][b];
+  const T H = sm[P_H][a] + sm[P_H][b], Pd = sm[P_P][a] + sm[P_P][b];
   const T m = r * v[D];
   F[0] = m;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) F[1 + k] = m * v[k] + (k == D ? P : T(0));
-  F[4] = m * H + P * v[D];
+  for (int k = 0; k < 3; ++k) F[1 + k] = m * v[k] + (k == D ? Pd : T(0));
+  F[4] = m * H + (Pd + p0) * v[D];
 }
 
 // Forward viscous stress row sigma_d. on the face between box cells A and A + e_d.
@@ -81,8 +84,9 @@ template <typename T, int NB, int D>
 __device__ __forceinline__ void residual_dir(const T (*sm)[NB], const int st[3], int p, const Consts<T>& c,
                                              T R[5]) {
   T Fp[5], Fm[5];
-  conv_face<T, NB, D>(sm, p, p + st[D], Fp);
-  conv_face<T, NB, D>(sm, p - st[D], p, Fm);
+  const T p0 = (c.gamma - T(1)) * c.wref[4];
+  conv_face<T, NB, D>(sm, p, p + st[D], p0, Fp);
+  conv_face<T, NB, D>(sm, p - st[D], p, p0, Fm);
   const T h = c.idx[D];
 #pragma unroll
   for (int v = 0; v < 5; ++v) R[v] -= (Fp[v] - Fm[v]) * h;
@@ -136,19 +140,23 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
   for (int it = 0; it < NIT; ++it) {
     const int b = tid + it * NT;
     if (it + 1 < NIT || b < NB) {
-      const T r = wv[it][0], Et = wv[it][4];
-      const T m1 = mir[it] ? -wv[it][1] : wv[it][1];
+      // stored deviations w - wref; Ed = rho E - wref_E stays a deviation
+      const T r = wv[it][0] + c.wref[0], Ed = wv[it][4];
+      const T mx = wv[it][1] + c.wref[1], m1 = mir[it] ? -mx : mx;
       const T ri = recip(r), hri = T(0.5) * ri;
-      const T h1 = m1 * hri, h2 = wv[it][2] * hri, h3 = wv[it][3] * hri;  // u/2
-      const T hH = Et * hri;                                               // (E/rho)/2
-      const T he = hH - (h1 * h1 + h2 * h2 + h3 * h3);                     // e/2
+      const T h1 = m1 * hri, h2 = (wv[it][2] + c.wref[2]) * hri, h3 = (wv[it][3] + c.wref[3]) * hri;  // u/2
+      const T hk = r * (h1 * h1 + h2 * h2 + h3 * h3);                      // kinetic energy / 2
+      // pressure deviation from the small stored deviation: p - p0 = (gamma-1)(Ed - K)
+      const T hp = gm1 * (T(0.5) * Ed - hk);                               // (p - p0)/2
       sm[P_RHO][b] = T(0.5) * r;
       sm[P_U1][b] = h1;
       sm[P_U2][b] = h2;
       sm[P_U3][b] = h3;
-      sm[P_E][b] = he;
-      sm[P_P][b] = gm1 * r * he;
+      const T hH = (Ed + c.wref[4]) * hri;                                 // (E/rho)/2
+      sm[P_E][b] = hH - (h1 * h1 + h2 * h2 + h3 * h3);                     // e/2
+      sm[P_P][b] = hp;
       sm[P_H][b] = hH;
+
     }
   }
   const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
@@ -388,30 +396,55 @@ template <typename T, int NB, int NBQ, int D>
 __device__ __forceinline__ void adj_conv_dir(const T (*K)[NB], const T (*U)[NB], const T (*Q)[NBQ], int p, int sd,
                                              const Consts<T>& c, T r0, const T u[3], T H0, T P0, const T k0[5],
                                              bool wall_lo, bool wall_hi, T& rh, T uh[3], T& Hh, T& Ph) {
+  // Both faces of direction D, accumulated with the unscaled kh differences dk = kh_nb - kh_j
+  // (G = +-dk/dx_d) and the face sign applied by addition or subtraction; the common factor
+  // 0.5/dx_d (the half-share of the face means) is applied once per direction.
+  T ar = T(0), aH = T(0), aP = T(0), au[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     const int q = side ? p + sd : p - sd;
-    const T sg = side ? c.idx[D] : -c.idx[D];
-    T G[5];
+    T dk[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) G[v] = sg * (K[v][q] - k0[v]);
+    for (int v = 0; v < 5; ++v) dk[v] = K[v][q] - k0[v];
     const T r = r0 + Q[0][q];
     const T v[3] = {u[0] + U[0][q], u[1] + U[1][q], u[2] + U[2][q]};
     const T H = H0 + Q[1][q], P = P0 + Q[2][q];
     const T m = r * v[D];
-    const T phi = G[0] + v[0] * G[1] + v[1] * G[2] + v[2] * G[3] + H * G[4];
-    // own half-share, plus the ghost's half-share at a wall face (u^_x flips, the rest adds)
-    const bool wl = D == 0 && (side ? wall_hi : wall_lo);
-    const T h = wl ? T(1) : T(0.5), hx = wl ? T(0) : T(0.5);
-    rh += h * (v[D] * phi);
-    Hh += h * (m * G[4]);
-    Ph += h * (G[1 + D] + v[D] * G[4]);
+    const T phi = dk[0] + v[0] * dk[1] + v[1] * dk[2] + v[2] * dk[3] + H * dk[4];
+    T tr = v[D] * phi, tH = m * dk[4], tP = dk[1 + D] + v[D] * dk[4], tu[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const T t = m * G[1 + k] + (k == D ? r * phi + P * G[4] : T(0));
-      uh[k] += (k == 0 ? hx : h) * t;
+    for (int k = 0; k < 3; ++k) tu[k] = m * dk[1 + k] + (k == D ? r * phi + P * dk[4] : T(0));
+    // at a slip wall the ghost image's half-share folds back through the mirror: u^_x cancels,
+    // the rest doubles
+    const bool wl = D == 0 && (side ? wall_hi : wall_lo);
+    if (wl) {
+      tr *= T(2);
+      tH *= T(2);
+      tP *= T(2);
+      tu[0] = T(0);
+      tu[1] *= T(2);
+      tu[2] *= T(2);
+    }
+    if (side) {
+      ar += tr;
+      aH += tH;
+      aP += tP;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) au[k] += tu[k];
+    } else {
+      ar -= tr;
+      aH -= tH;
+      aP -= tP;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) au[k] -= tu[k];
     }
   }
+  const T s = T(0.5) * c.idx[D];
+  rh += s * ar;
+  Hh += s * aH;
+  Ph += s * aP;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) uh[k] += s * au[k];
 }
 
 // (u^, e^) -> conservative adjoint at a cell with velocity u, internal energy e, 1/rho = ri
@@ -488,15 +521,16 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
   for (int it = 0; it < NIT; ++it) {
     const int b = tid + it * NT;
     if (it + 1 < NIT || b < NB) {
-      const T r = wv[it][0], ri = recip(r);
+      const T r = wv[it][0] + c.wref[0], ri = recip(r);  // stored deviations w - wref
       const T hri = T(0.5) * ri;
-      const T h1 = (mir[it] ? -wv[it][1] : wv[it][1]) * hri, h2 = wv[it][2] * hri, h3 = wv[it][3] * hri;
+      const T mx = wv[it][1] + c.wref[1];
+      const T h1 = (mir[it] ? -mx : mx) * hri, h2 = (wv[it][2] + c.wref[2]) * hri, h3 = (wv[it][3] + c.wref[3]) * hri;
       sm[A_U1][b] = h1;
       sm[A_U2][b] = h2;
       sm[A_U3][b] = h3;
       Q[0][b] = T(0.5) * r;
-      Q[1][b] = wv[it][4] * hri;
-      Q[2][b] = gm1 * (T(0.5) * wv[it][4] - r * (h1 * h1 + h2 * h2 + h3 * h3));
+      Q[1][b] = (wv[it][4] + c.wref[4]) * hri;
+      Q[2][b] = gm1 * (T(0.5) * wv[it][4] - r * (h1 * h1 + h2 * h2 + h3 * h3)) + T(0.5) * gm1 * c.wref[4];
 #pragma unroll
       for (int v = 0; v < 5; ++v) sm[A_K0 + v][b] = rl[it] ? ca * av[it][v] + cgn * gv[it][v] : T(0);
       if (LNU) sm[LNU ? A_NU : 0][b] = rl[it] ? nv[it] : T(0);

@@ -234,3 +234,47 @@ def test_every_tile_shape_f64(orc, restore_tiles, tile, bc_x):
     ref = orc.adjoint_step(og, w, s, a, 2e-3, orc.make_obj(W.OBJ_KE_DISSIPATION), 0.2, gref)
     assert relerr(host(wh) - a, ref - a) <= 1e-12
     assert relerr(host(gs), gref) <= 1e-12
+
+
+# ------------------------------------------------------------------------------ reference state
+@pytest.mark.parametrize("bc_x", [0, 1], ids=["periodic", "walls"])
+def test_reference_state_offset_f64(orc, bc_x):
+    # states stored as w - w_ref: every operator acts on the full state (the oracle's), so the
+    # rates, the adjoint fields and the scalars are unchanged and the stored outputs are offset
+    shape = (19, 6, 9)
+    g0, og, w = _setup(orc, shape, bc_x, seed=21)
+    w_ref = (1.02, 0.0 if bc_x else 0.13, -0.07, 0.05, 2.31)
+    g = adj.Grid.make(shape, (2.0, 1.3, 1.7), 0.02, 0.004, bc_x=bc_x, w_ref=w_ref)
+    ws = adj.workspace(g)
+    wd = dev(g.to_stored(w))
+    rng = np.random.default_rng(22)
+    s = 1e-2 * rng.standard_normal(w.size)
+    a = rng.standard_normal(w.size)
+    R = torch.empty(w.size, dtype=torch.float64, device="cuda")
+    adj.residual(g, wd, dev(s), R)
+    assert relerr(host(R), orc.residual(og, w, s)) <= 1e-12
+    out = torch.empty_like(R)
+    adj.vjp(g, wd, dev(a), out)
+    assert relerr(host(out), orc.vjp(og, w, a)) <= 1e-12
+    adj.primal_step(g, wd, dev(s), out, ws)
+    ref = orc.primal_step(og, w, s)
+    assert relerr(g.from_stored(host(out)) - w, ref - w) <= 1e-12
+    obj = adj.Objective.make(W.OBJ_PT_LOSS_PLANE if bc_x else W.OBJ_MEAN_PRESSURE, 7, 1.1)
+    oobj = orc.make_obj(W.OBJ_PT_LOSS_PLANE if bc_x else W.OBJ_MEAN_PRESSURE, 7, 1.1)
+    gs = torch.zeros_like(R)
+    adj.adjoint_step(g, wd, dev(s), dev(a), out, ws, lam=3e-3, obj=obj, c_n=0.37, grad_s=gs)
+    gref = np.zeros_like(w)
+    ref = orc.adjoint_step(og, w, s, a, 3e-3, oobj, 0.37, gref)
+    assert relerr(host(out) - a, ref - a) <= 1e-12
+    assert relerr(host(gs), gref) <= 1e-12
+    sig = torch.empty(w.size // 5, dtype=torch.float64, device="cuda")
+    adj.growth_sigma1(g, wd, sig)
+    assert relerr(host(sig), orc.sigma1(og, w)) <= 1e-12
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    adj.objective_and_grad(g, obj, wd, ws, weight=1.0, J_accum=J)
+    jr, _ = orc.objective(og, oobj, w)
+    assert abs(host(J)[0] - jr) <= 1e-13 * abs(jr)
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    adj.energy_vhat(g, wd, dev(a), E, ws)
+    Er, _ = orc.energy_vhat(og, w, a)
+    assert abs(host(E)[0] - Er) <= 1e-12 * abs(Er)
