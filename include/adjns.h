@@ -164,9 +164,13 @@ int adj_energy_vhat(const adj_grid* grid, const void* w, const void* wh, double*
 int adj_dot(const adj_grid* grid, const void* a, const void* b, double* out, void* ws, size_t ws_bytes,
             void* stream);
 
-/* BF16 checkpoint codec (ADJ_F32 states): per variable v, m_v = (max+min)/2, s_v = (max-min)/2
- * (1 when the range is empty), code = bf16_round_nearest_even((w - m_v)/s_v) in FP32; decode
- * w' = fma(s_v, code, m_v).  ckpt is an adj_ckpt_bytes() record. */
+/* BF16 checkpoint codec (ADJ_F32 states), block-scaled: the grid is cut into 4x4x4 blocks of
+ * cells (ragged at the far ends), block b = (bz*nby + by)*nbx + bx, nbd = ceil(n[d]/4).  Per block
+ * and variable v, m = (max+min)/2, s = (max-min)/2 over the block's cells (1 when the range is
+ * empty), code = bf16_round_nearest_even((w - m)/s) in FP32 with IEEE division; decode
+ * w' = fma(s, code, m).  Record (adj_ckpt_bytes): header of 10 floats per block,
+ * header[b*10 + 2v] = m, header[b*10 + 2v + 1] = s, padded to a multiple of 256 bytes, then the
+ * 5N codes in the state layout.  Records must be 64-byte aligned. */
 int adj_ckpt_encode(const adj_grid* grid, const float* w, void* ckpt, void* ws, size_t ws_bytes, void* stream);
 int adj_ckpt_decode(const adj_grid* grid, const void* ckpt, float* w, void* stream);
 

@@ -75,8 +75,9 @@ def lib():
             "orc_growth_matrix_field": [gp, dp, dp],
             "orc_cell_growth_matrix": [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp],
             "orc_energy_vhat": [gp, dp, dp, dp, dp],
-            "orc_ckpt_encode": [ctypes.c_long, P(ctypes.c_float), P(ctypes.c_uint16), P(ctypes.c_float)],
-            "orc_ckpt_decode": [ctypes.c_long, P(ctypes.c_uint16), P(ctypes.c_float), P(ctypes.c_float)],
+            "orc_ckpt_blocks": [ctypes.POINTER(OrcGrid)],
+            "orc_ckpt_encode": [ctypes.POINTER(OrcGrid), P(ctypes.c_float), P(ctypes.c_uint16), P(ctypes.c_float)],
+            "orc_ckpt_decode": [ctypes.POINTER(OrcGrid), P(ctypes.c_uint16), P(ctypes.c_float), P(ctypes.c_float)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -84,6 +85,7 @@ def lib():
             f.restype = ctypes.c_int
         L.orc_matrix_sigma1.argtypes = [dp]
         L.orc_matrix_sigma1.restype = ctypes.c_double
+        L.orc_ckpt_blocks.restype = ctypes.c_long
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -276,24 +278,24 @@ def energy_vhat(g, w, wh):
     return E.value, vhat
 
 
-def ckpt_encode(w32):
+def ckpt_encode(g, w32):
+    """Block-scaled BF16 encoding of an FP32 state: (codes, header[blocks, 10])."""
     w32 = np.ascontiguousarray(w32, dtype=np.float32)
-    N = w32.size // 5
-    q = np.zeros(5 * N, dtype=np.uint16)
-    ms = np.zeros(10, dtype=np.float32)
-    lib().orc_ckpt_encode(N, w32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+    nb = lib().orc_ckpt_blocks(ctypes.byref(g))
+    q = np.zeros(w32.size, dtype=np.uint16)
+    hdr = np.zeros((nb, 10), dtype=np.float32)
+    lib().orc_ckpt_encode(ctypes.byref(g), w32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                           q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
-                          ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
-    return q, ms
+                          hdr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    return q, hdr
 
 
-def ckpt_decode(q, ms):
+def ckpt_decode(g, q, hdr):
     q = np.ascontiguousarray(q, dtype=np.uint16)
-    ms = np.ascontiguousarray(ms, dtype=np.float32)
-    N = q.size // 5
-    out = np.zeros(5 * N, dtype=np.float32)
-    lib().orc_ckpt_decode(N, q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
-                          ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+    hdr = np.ascontiguousarray(hdr, dtype=np.float32)
+    out = np.zeros(q.size, dtype=np.float32)
+    lib().orc_ckpt_decode(ctypes.byref(g), q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                          hdr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
     return out
 

@@ -880,9 +880,11 @@ int orc_energy_vhat(const orc_grid* gr, const double* w, const double* wh, doubl
 }
 
 // ------------------------------------------------------------------------------------------
-// BF16 checkpoint codec (per-snapshot, per-variable affine scaling), FP32 arithmetic:
-//   m_v = (max_v + min_v)/2, s_v = (max_v - min_v)/2 (1 if the range is 0),
-//   q = bf16_round_nearest_even((w - m_v) / s_v),   decode w' = fma(s_v, q, m_v).
+// BF16 checkpoint codec, block-scaled, FP32 arithmetic.  The grid is cut into 4 x 4 x 4 blocks of
+// cells (ragged at the far ends); block b = (bz * nby + by) * nbx + bx holds, per variable v,
+//   m = (max + min)/2, s = (max - min)/2 (1 if the range is 0) over the block's cells,
+//   q = bf16_round_nearest_even((w - m) / s),   decode w' = fma(s, q, m);
+// header[b * 10 + 2 v] = m, header[b * 10 + 2 v + 1] = s.  Codes keep the state layout.
 // ------------------------------------------------------------------------------------------
 static uint16_t f32_to_bf16_rne(float f) {
   uint32_t u; std::memcpy(&u, &f, 4);
@@ -893,25 +895,54 @@ static uint16_t f32_to_bf16_rne(float f) {
 }
 static float bf16_to_f32(uint16_t h) { uint32_t u = (uint32_t)h << 16; float f; std::memcpy(&f, &u, 4); return f; }
 
-int orc_ckpt_encode(long N, const float* w, uint16_t* q, float* meanscale) {
-  for (int v = 0; v < 5; ++v) {
-    float mn = w[v * N], mx = w[v * N];
-    for (long c = 1; c < N; ++c) { mn = std::min(mn, w[v * N + c]); mx = std::max(mx, w[v * N + c]); }
-    float m = 0.5f * (mx + mn), s = 0.5f * (mx - mn);
-    if (!(s > 0.0f)) s = 1.0f;
-    meanscale[2 * v] = m; meanscale[2 * v + 1] = s;
-    for (long c = 0; c < N; ++c) {
-      float t = (w[v * N + c] - m) / s;
-      q[v * N + c] = f32_to_bf16_rne(t);
-    }
-  }
+static void codec_blocks(const orc_grid* g, long& nbx, long& nby, long& nbz) {
+  nbx = (g->n[0] + 3) / 4; nby = (g->n[1] + 3) / 4; nbz = (g->n[2] + 3) / 4;
+}
+
+long orc_ckpt_blocks(const orc_grid* g) {
+  long a, b, c; codec_blocks(g, a, b, c);
+  return a * b * c;
+}
+
+int orc_ckpt_encode(const orc_grid* g, const float* w, uint16_t* q, float* header) {
+  const long nx = g->n[0], ny = g->n[1], nz = g->n[2], N = nx * ny * nz;
+  long nbx, nby, nbz; codec_blocks(g, nbx, nby, nbz);
+  for (long bz = 0; bz < nbz; ++bz)
+    for (long by = 0; by < nby; ++by)
+      for (long bx = 0; bx < nbx; ++bx) {
+        const long b = (bz * nby + by) * nbx + bx;
+        for (int v = 0; v < 5; ++v) {
+          float mn = INFINITY, mx = -INFINITY;
+          for (long k = 4 * bz; k < std::min(nz, 4 * bz + 4); ++k)
+            for (long j = 4 * by; j < std::min(ny, 4 * by + 4); ++j)
+              for (long i = 4 * bx; i < std::min(nx, 4 * bx + 4); ++i) {
+                const float x = w[v * N + (k * ny + j) * nx + i];
+                mn = std::min(mn, x); mx = std::max(mx, x);
+              }
+          float m = 0.5f * (mx + mn), s = 0.5f * (mx - mn);
+          if (!(s > 0.0f)) s = 1.0f;
+          header[b * 10 + 2 * v] = m; header[b * 10 + 2 * v + 1] = s;
+          for (long k = 4 * bz; k < std::min(nz, 4 * bz + 4); ++k)
+            for (long j = 4 * by; j < std::min(ny, 4 * by + 4); ++j)
+              for (long i = 4 * bx; i < std::min(nx, 4 * bx + 4); ++i) {
+                const long c = v * N + (k * ny + j) * nx + i;
+                q[c] = f32_to_bf16_rne((w[c] - m) / s);
+              }
+        }
+      }
   return 0;
 }
 
-int orc_ckpt_decode(long N, const uint16_t* q, const float* meanscale, float* w) {
+int orc_ckpt_decode(const orc_grid* g, const uint16_t* q, const float* header, float* w) {
+  const long nx = g->n[0], ny = g->n[1], nz = g->n[2], N = nx * ny * nz;
+  long nbx, nby, nbz; codec_blocks(g, nbx, nby, nbz);
   for (int v = 0; v < 5; ++v)
-    for (long c = 0; c < N; ++c)
-      w[v * N + c] = std::fma(meanscale[2 * v + 1], bf16_to_f32(q[v * N + c]), meanscale[2 * v]);
+    for (long k = 0; k < nz; ++k)
+      for (long j = 0; j < ny; ++j)
+        for (long i = 0; i < nx; ++i) {
+          const long b = ((k / 4) * nby + j / 4) * nbx + i / 4, c = v * N + (k * ny + j) * nx + i;
+          w[c] = std::fma(header[b * 10 + 2 * v + 1], bf16_to_f32(q[c]), header[b * 10 + 2 * v]);
+        }
   return 0;
 }
 

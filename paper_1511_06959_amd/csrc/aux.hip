@@ -668,88 +668,68 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
-__global__ __launch_bounds__(RB) void k_minmax_partial(Consts<float> c, const float* __restrict__ w,
-                                                       float* __restrict__ partials) {
-  __shared__ float smn[RB], smx[RB];
+// Block-scaled BF16 codec: 4 x 4 x 4 cell blocks, one wavefront each (lane = cell), four blocks
+// consecutive in x per work-group.  Per block and variable m = (max+min)/2, s = (max-min)/2 (1 for
+// an empty range); code = RNE_bf16((w - m)/s) with IEEE division; decode fma(s, code, m).
+// header[b * 10 + 2 v] = m, [b * 10 + 2 v + 1] = s; codes keep the state layout.
+struct CodecBlock {
+  long long i;  // cell index (valid when act)
+  int b;        // block index
+  bool act, live;
+};
+
+__device__ __forceinline__ CodecBlock codec_block(const Consts<float>& c) {
+  const int lane = threadIdx.x & 63;
+  const int nbx = (c.nx + 3) >> 2, nby = (c.ny + 3) >> 2, nbz = (c.nz + 3) >> 2;
+  CodecBlock q;
+  q.b = blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
+  q.live = q.b < nbx * nby * nbz;
+  const int bx = q.b % nbx, by = (q.b / nbx) % nby, bz = q.b / (nbx * nby);
+  const int x = 4 * bx + (lane & 3), y = 4 * by + ((lane >> 2) & 3), z = 4 * bz + (lane >> 4);
+  q.act = q.live && x < c.nx && y < c.ny && z < c.nz;
+  q.i = q.act ? ((long long)z * c.ny + y) * c.nx + x : 0;
+  return q;
+}
+
+__global__ __launch_bounds__(RB) void k_encode(Consts<float> c, const float* __restrict__ w, float* __restrict__ header,
+                                               uint16_t* __restrict__ codes) {
+  const CodecBlock q = codec_block(c);
+  if (!q.live) return;  // whole wavefronts only: no lane of a live block leaves early
   const long long N = c.N;
+#pragma unroll
   for (int v = 0; v < 5; ++v) {
-    float mn = INFINITY, mx = -INFINITY;
-    for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < N; i += (long long)gridDim.x * RB) {
-      const float x = w[v * N + i];
-      mn = fminf(mn, x);
-      mx = fmaxf(mx, x);
+    const float x = q.act ? w[v * N + q.i] : 0.0f;
+    float mn = q.act ? x : INFINITY, mx = q.act ? x : -INFINITY;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      mn = fminf(mn, __shfl_xor(mn, o));
+      mx = fmaxf(mx, __shfl_xor(mx, o));
     }
-    smn[threadIdx.x] = mn;
-    smx[threadIdx.x] = mx;
-    for (int o = RB / 2; o > 0; o >>= 1) {
-      __syncthreads();
-      if (threadIdx.x < o) {
-        smn[threadIdx.x] = fminf(smn[threadIdx.x], smn[threadIdx.x + o]);
-        smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + o]);
-      }
+    const float m = 0.5f * (mx + mn);
+    float s = 0.5f * (mx - mn);
+    if (!(s > 0.0f)) s = 1.0f;
+    if ((threadIdx.x & 63) == 0) {
+      header[q.b * 10 + 2 * v] = m;
+      header[q.b * 10 + 2 * v + 1] = s;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      partials[(2 * v) * gridDim.x + blockIdx.x] = smn[0];
-      partials[(2 * v + 1) * gridDim.x + blockIdx.x] = smx[0];
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(RB) void k_minmax_fold(const float* __restrict__ partials, int nblk,
-                                                    float* __restrict__ header) {
-  __shared__ float smn[RB], smx[RB];
-  for (int v = 0; v < 5; ++v) {
-    float mn = INFINITY, mx = -INFINITY;
-    for (int i = threadIdx.x; i < nblk; i += RB) {
-      mn = fminf(mn, partials[(2 * v) * nblk + i]);
-      mx = fmaxf(mx, partials[(2 * v + 1) * nblk + i]);
-    }
-    smn[threadIdx.x] = mn;
-    smx[threadIdx.x] = mx;
-    for (int o = RB / 2; o > 0; o >>= 1) {
-      __syncthreads();
-      if (threadIdx.x < o) {
-        smn[threadIdx.x] = fminf(smn[threadIdx.x], smn[threadIdx.x + o]);
-        smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + o]);
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const float m = 0.5f * (smx[0] + smn[0]);
-      float s = 0.5f * (smx[0] - smn[0]);
-      if (!(s > 0.0f)) s = 1.0f;
-      header[2 * v] = m;
-      header[2 * v + 1] = s;
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(RB) void k_encode(Consts<float> c, const float* __restrict__ w,
-                                               const float* __restrict__ header, uint16_t* __restrict__ codes) {
-  const long long n = 5 * c.N;
-  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
-    const int v = (int)(i / c.N);
-    const float t = __fdiv_rn(w[i] - header[2 * v], header[2 * v + 1]);
-    codes[i] = bf16_rne(t);
+    if (q.act) codes[v * N + q.i] = bf16_rne(__fdiv_rn(x - m, s));
   }
 }
 
 __global__ __launch_bounds__(RB) void k_decode(Consts<float> c, const float* __restrict__ header,
                                                const uint16_t* __restrict__ codes, float* __restrict__ w) {
-  const long long n = 5 * c.N;
-  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < n; i += (long long)gridDim.x * RB) {
-    const int v = (int)(i / c.N);
-    w[i] = fmaf(header[2 * v + 1], __uint_as_float((uint32_t)codes[i] << 16), header[2 * v]);
-  }
+  const CodecBlock q = codec_block(c);
+  if (!q.act) return;
+  const long long N = c.N;
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+    w[v * N + q.i] = fmaf(header[q.b * 10 + 2 * v + 1], __uint_as_float((uint32_t)codes[v * N + q.i] << 16),
+                          header[q.b * 10 + 2 * v]);
 }
 
-inline int ew_blocks(long long n) {
-  long long b = (n + RB - 1) / RB;
-  const long long cap = 256 * 64;
-  return (int)(b > cap ? cap : (b < 1 ? 1 : b));
+inline int codec_groups(const Consts<float>& c) {
+  const long long nb = (long long)((c.nx + 3) >> 2) * ((c.ny + 3) >> 2) * ((c.nz + 3) >> 2);
+  return (int)((nb + RB / 64 - 1) / (RB / 64));
 }
 
 }  // namespace
@@ -820,19 +800,16 @@ hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt
 }
 
 hipError_t launch_ckpt_encode(const Consts<float>& c, const float* w, float* header, uint16_t* codes,
-                              float* partials, hipStream_t st) {
-  ProfScope ps(ADJ_PROF_CODEC, st);
-  const int nb = reduce_blocks(c.N);
-  hipLaunchKernelGGL(k_minmax_partial, dim3(nb), dim3(RB), 0, st, c, w, partials);
-  hipLaunchKernelGGL(k_minmax_fold, dim3(1), dim3(RB), 0, st, partials, nb, header);
-  hipLaunchKernelGGL(k_encode, dim3(ew_blocks(5 * c.N)), dim3(RB), 0, st, c, w, header, codes);
+                              hipStream_t st) {
+  ProfScope ps(ADJ_PROF_CODEC, st, true);
+  timed_launch(ps, k_encode, dim3(codec_groups(c)), dim3(RB), st, c, w, header, codes);
   return hipGetLastError();
 }
 
 hipError_t launch_ckpt_decode(const Consts<float>& c, const float* header, const uint16_t* codes, float* w,
                               hipStream_t st) {
-  ProfScope ps(ADJ_PROF_CODEC, st);
-  hipLaunchKernelGGL(k_decode, dim3(ew_blocks(5 * c.N)), dim3(RB), 0, st, c, header, codes, w);
+  ProfScope ps(ADJ_PROF_CODEC, st, true);
+  timed_launch(ps, k_decode, dim3(codec_groups(c)), dim3(RB), st, c, header, codes, w);
   return hipGetLastError();
 }
 

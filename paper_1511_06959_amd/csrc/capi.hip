@@ -142,6 +142,12 @@ Consts<T> consts(const adj_grid* g) {
 
 inline char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
+// A BF16 record: the block header (10 floats per 4x4x4 block), 256-byte aligned, then 5N codes.
+size_t ckpt_header_bytes(const adj_grid* g) {
+  const size_t nb = (size_t)((g->n[0] + 3) / 4) * ((g->n[1] + 3) / 4) * ((g->n[2] + 3) / 4);
+  return up(nb * 10 * sizeof(float));
+}
+
 template <typename T>
 int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, T* stages, void* ws, hipStream_t st) {
   const Consts<T> c = consts<T>(g);
@@ -159,8 +165,8 @@ int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, 
   if (ckpt) {
     if constexpr (sizeof(T) == sizeof(float)) {
       float* hdr = (float*)ckpt;
-      uint16_t* codes = (uint16_t*)at(ckpt, 64);
-      if ((e = launch_ckpt_encode(c, (const float*)out, hdr, codes, (float*)at(ws, L.partials), st)))
+      uint16_t* codes = (uint16_t*)at(ckpt, ckpt_header_bytes(g));
+      if ((e = launch_ckpt_encode(c, (const float*)out, hdr, codes, st)))
         return hip_fail(e, "checkpoint encode");
     }
   }
@@ -185,7 +191,8 @@ int adjoint_step(const adj_grid* g, const void* wn_in, const T* stages, const T*
   if (g->ckpt_format == ADJ_CKPT_BF16) {
     if constexpr (sizeof(T) == sizeof(float)) {
       float* dec = (float*)at(ws, L.wdec);
-      if ((e = launch_ckpt_decode(c, (const float*)wn_in, (const uint16_t*)((const char*)wn_in + 64), dec, st)))
+      if ((e = launch_ckpt_decode(c, (const float*)wn_in,
+                                  (const uint16_t*)((const char*)wn_in + ckpt_header_bytes(g)), dec, st)))
         return hip_fail(e, "checkpoint decode");
       wn = (const T*)dec;
     }
@@ -236,7 +243,7 @@ size_t adj_workspace_bytes(const adj_grid* grid) {
 
 size_t adj_ckpt_bytes(const adj_grid* grid) {
   if (check_grid(grid, false)) return 0;
-  return 64 + 5 * (size_t)ncells(grid) * sizeof(uint16_t);
+  return ckpt_header_bytes(grid) + 5 * (size_t)ncells(grid) * sizeof(uint16_t);
 }
 
 static int primal_entry(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out,
@@ -373,9 +380,8 @@ int adj_ckpt_encode(const adj_grid* grid, const float* w, void* ckpt, void* ws, 
   if ((r = check_ws(grid, ws, ws_bytes))) return r;
   if (!w || !ckpt) return fail(ADJ_EINVAL, "w and ckpt must be non-NULL");
   if ((uintptr_t)ckpt % 64) return fail(ADJ_EINVAL, "ckpt must be 64-byte aligned");
-  const WsLayout L = layout(grid);
-  hipError_t e = launch_ckpt_encode(consts<float>(grid), w, (float*)ckpt, (uint16_t*)at(ckpt, 64),
-                                    (float*)at(ws, L.partials), (hipStream_t)stream);
+  hipError_t e = launch_ckpt_encode(consts<float>(grid), w, (float*)ckpt, (uint16_t*)at(ckpt, ckpt_header_bytes(grid)),
+                                    (hipStream_t)stream);
   return e ? hip_fail(e, "encode") : ADJ_OK;
 }
 
@@ -386,7 +392,8 @@ int adj_ckpt_decode(const adj_grid* grid, const void* ckpt, float* w, void* stre
   if (!w || !ckpt) return fail(ADJ_EINVAL, "w and ckpt must be non-NULL");
   if ((uintptr_t)ckpt % 64) return fail(ADJ_EINVAL, "ckpt must be 64-byte aligned");
   hipError_t e = launch_ckpt_decode(consts<float>(grid), (const float*)ckpt,
-                                    (const uint16_t*)((const char*)ckpt + 64), w, (hipStream_t)stream);
+                                    (const uint16_t*)((const char*)ckpt + ckpt_header_bytes(grid)), w,
+                                    (hipStream_t)stream);
   return e ? hip_fail(e, "decode") : ADJ_OK;
 }
 

@@ -137,15 +137,18 @@ def test_codec_bitwise(orc):
     adj.ckpt_encode(g, dev(w, torch.float32), rec, ws)
     torch.cuda.synchronize()
     raw = rec.cpu().numpy()
-    hdr = raw[:40].view(np.float32)
-    codes = raw[64:].view(np.uint16)
-    q, ms = orc.ckpt_encode(w)
-    assert np.array_equal(hdr, ms)
+    og = orc.make_grid(shape, (1, 1, 1), 1.4, 0.72, 0.01, 0.01, 0)
+    q, hdr_ref = orc.ckpt_encode(og, w)
+    hb = raw.size - 2 * w.size  # header bytes (block headers, padded)
+    hdr = raw[:hdr_ref.size * 4].view(np.float32).reshape(hdr_ref.shape)
+    codes = raw[hb:].view(np.uint16)
+    assert hb % 256 == 0 and hb >= hdr_ref.size * 4
+    assert np.array_equal(hdr, hdr_ref)
     assert np.array_equal(codes, q)
     out = torch.empty(w.size, dtype=torch.float32, device="cuda")
     adj.ckpt_decode(g, rec, out)
     torch.cuda.synchronize()
-    assert np.array_equal(out.cpu().numpy(), orc.ckpt_decode(q, ms))
+    assert np.array_equal(out.cpu().numpy(), orc.ckpt_decode(og, q, hdr_ref))
 
 
 def test_adjoint_step_deterministic():

@@ -236,17 +236,41 @@ def test_objective_gradient_finite_difference(orc, kind, bc_x):
 
 # ------------------------------------------------------------------------------ codec
 def test_bf16_rounding_matches_torch(orc):
+    # block-scaled codec on a ragged grid: the header is each 4x4x4 block's (max+min)/2 and
+    # (max-min)/2 (written here with numpy), and the codes are torch's round-to-nearest-even
+    # bfloat16 of (w - m)/s
     torch = pytest.importorskip("torch")
+    n = (9, 6, 5)
+    N = n[0] * n[1] * n[2]
+    g = orc.make_grid(n, (1.0, 1.0, 1.0), 1.4, 0.72, 0.01, 0.01, 0)
     rng = np.random.default_rng(6)
-    w = (rng.standard_normal(5 * 1000) * 0.3 + 1.0).astype(np.float32)
+    w = (rng.standard_normal(5 * N) * 0.3 + 1.0).astype(np.float32)
     w[:5] = [1.0, -1.0, 0.0, 1e-30, 3.0]
-    q, ms = orc.ckpt_encode(w)
-    t = np.empty_like(w)
-    for v in range(5):
-        t[v * 1000:(v + 1) * 1000] = (w[v * 1000:(v + 1) * 1000] - ms[2 * v]) / ms[2 * v + 1]
-    ref = torch.from_numpy(t).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    w[N:2 * N] = 0.25  # a constant field: s = 1
+    q, hdr = orc.ckpt_encode(g, w)
+    W5 = w.reshape(5, n[2], n[1], n[0])
+    nb = [(n[d] + 3) // 4 for d in range(3)]
+    assert hdr.shape == (nb[0] * nb[1] * nb[2], 10)
+    t = np.empty_like(W5)
+    for bz in range(nb[2]):
+        for by in range(nb[1]):
+            for bx in range(nb[0]):
+                b = (bz * nb[1] + by) * nb[0] + bx
+                sl = (slice(4 * bz, 4 * bz + 4), slice(4 * by, 4 * by + 4), slice(4 * bx, 4 * bx + 4))
+                for v in range(5):
+                    blk = W5[v][sl]
+                    m = np.float32(0.5) * (blk.max() + blk.min())
+                    sc = np.float32(0.5) * (blk.max() - blk.min())
+                    sc = sc if sc > 0 else np.float32(1.0)
+                    assert hdr[b, 2 * v] == m and hdr[b, 2 * v + 1] == sc
+                    t[v][sl] = (blk - m) / sc
+    ref = torch.from_numpy(t.reshape(-1)).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
     assert np.array_equal(q, ref)
-    dec = orc.ckpt_decode(q, ms)
-    for v in range(5):
-        sl = slice(v * 1000, (v + 1) * 1000)
-        assert np.abs(dec[sl] - w[sl]).max() <= 2.0 ** -8 * ms[2 * v + 1]
+    dec = orc.ckpt_decode(g, q, hdr).reshape(5, n[2], n[1], n[0])
+    for bz in range(nb[2]):
+        for by in range(nb[1]):
+            for bx in range(nb[0]):
+                b = (bz * nb[1] + by) * nb[0] + bx
+                sl = (slice(4 * bz, 4 * bz + 4), slice(4 * by, 4 * by + 4), slice(4 * bx, 4 * bx + 4))
+                for v in range(5):
+                    assert np.abs(dec[v][sl] - W5[v][sl]).max() <= 2.0 ** -8 * hdr[b, 2 * v + 1]
