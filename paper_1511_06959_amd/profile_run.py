@@ -142,7 +142,7 @@ def traffic(fetch, write, copy_fetch, copy_write, mib, cells, kernel, commands):
     byts = (fkib * sf + wkib * sw) * 1024.0
     h = hashlib.sha256()
     here = os.path.dirname(os.path.abspath(__file__))
-    for name in ("stencil.hip", "common.hpp", "kernels.hpp"):
+    for name in ("stencil.hip", "common.hpp"):
         h.update(open(os.path.join(here, "csrc", name), "rb").read())
     print(f"# HBM traffic of {kernel} (rocprofv3 FETCH_SIZE and WRITE_SIZE, separate runs), {cells} cells")
     for c in commands:
