@@ -66,6 +66,20 @@ def kernel_hash():
     return h.hexdigest()
 
 
+def _tile_report(res, g, lnu):
+    """Autotuner result as bench fields: the selected tile, the tile the launches of this
+    workload really use (lnu: a lambda term is applied) and the timed candidates (us)."""
+    import paper_1511_06959_amd as adj
+
+    name = lambda t: "x".join(map(str, adj.TILES[t]))
+    out = {}
+    for kc, key in ((adj.PROF_ADJOINT_STAGE, "adjoint_stage"), (adj.PROF_PRIMAL_STAGE, "primal_stage")):
+        best, times = res[kc]
+        out[key] = {"tile": name(best), "launched": name(adj.tile_launched(kc, g.precision, g.bc_x, lnu, best)),
+                    "us": {name(t): round(ms * 1e3, 2) for t, ms in times.items()}}
+    return out
+
+
 def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=False):
     import torch
 
@@ -79,11 +93,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
                       adj.CKPT_BF16 if ckpt_bf16 else adj.CKPT_NATIVE, w_ref)
     tiles = {}
     if tune:
-        res = autotune.tune(g)
-        for kc, name in ((adj.PROF_ADJOINT_STAGE, "adjoint_stage"), (adj.PROF_PRIMAL_STAGE, "primal_stage")):
-            best, times = res[kc]
-            tiles[name] = {"tile": "x".join(map(str, adj.TILES[best])),
-                           "us": {"x".join(map(str, adj.TILES[t])): round(ms * 1e3, 2) for t, ms in times.items()}}
+        tiles = _tile_report(autotune.tune(g), g, wl.lam > 0.0)
     obj = adj.Objective.make(wl.obj_kind, wl.plane_i, wl.pt_ref)
     w0 = torch.from_numpy(g.to_stored(wl.w0)).to("cuda", dt)
     s = torch.from_numpy(wl.s).to("cuda", dt)
@@ -189,11 +199,9 @@ def run_ensemble(boxes, precision, steps, warmup, tune=True):
     if tune:
         # tile shapes tuned on the largest box; the ensemble launches use the same kernel bodies
         big = max(grids, key=lambda g: g.ncells)
-        res = autotune.tune(big)
-        for kc, name in ((adj.PROF_ADJOINT_STAGE, "adjoint_stage"), (adj.PROF_PRIMAL_STAGE, "primal_stage")):
-            best, times = res[kc]
-            tiles[name] = {"tile": "x".join(map(str, adj.TILES[best])), "tuned_on": "x".join(map(str, big.n)),
-                           "us": {"x".join(map(str, adj.TILES[t])): round(ms * 1e3, 2) for t, ms in times.items()}}
+        tiles = _tile_report(autotune.tune(big), big, any(wl.lam > 0.0 for wl in boxes))
+        for v in tiles.values():
+            v["tuned_on"] = "x".join(map(str, big.n))
     win = EnsembleWindow(grids, [wl.nsteps for wl in boxes], [g.to_stored(wl.w0) for g, wl in zip(grids, boxes)], None,
                          list(range(len(boxes))), [wl.lam for wl in boxes])
     out = {"tiles": tiles}

@@ -212,6 +212,11 @@ enum {
 };
 int adj_set_tile(int kernel_class, int precision, int tile);
 int adj_get_tile(int kernel_class, int precision);
+/* The tile a launch of `kernel_class` actually uses when `tile` is selected, for the boundary
+ * (bc_x, ADJ_BC_*) and lambda variant (lnu: 1 when a lambda term is applied): a reverse-stage
+ * tile whose shared-memory footprint exceeds a work-group's 160 KiB (the largest FP64 tiles)
+ * runs as ADJ_TILE_16x4x4 instead.  Returns the tile id or a negative status. */
+int adj_tile_launched(int kernel_class, int precision, int bc_x, int lnu, int tile);
 
 /* ---------------------------------------------------------------------------------------------
  * Ensembles: many independent boxes (each its own adj_grid: size, dt, viscosity) and many adjoint

@@ -24,6 +24,7 @@ BC_PERIODIC, BC_SLIP_WALLS = 0, 1
 OBJ_NONE, OBJ_MEAN_PRESSURE, OBJ_KE_DISSIPATION, OBJ_PT_LOSS_PLANE = 0, 1, 2, 3
 PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, PROF_SIGMA1, PROF_OBJECTIVE, PROF_CODEC, PROF_REDUCE = range(6)
 TILES = {0: (16, 4, 4), 1: (32, 4, 2), 2: (32, 4, 4), 3: (32, 8, 2), 4: (32, 8, 4), 5: (16, 8, 8)}
+TILE_16x4x4, TILE_32x4x2, TILE_32x4x4, TILE_32x8x2, TILE_32x8x4, TILE_16x8x8 = range(6)
 
 STATUS = {0: "ADJ_OK", -1: "ADJ_EINVAL", -2: "ADJ_ESHAPE", -3: "ADJ_EUNSTABLE", -4: "ADJ_ENONFINITE",
           -5: "ADJ_EHIP", -6: "ADJ_EWORKSPACE"}
@@ -111,7 +112,7 @@ EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjo
            "adj_adjoint_step_stages", "adj_growth_sigma1",
            "adj_objective_and_grad", "adj_energy_vhat", "adj_dot", "adj_ckpt_encode", "adj_ckpt_decode",
            "adj_residual", "adj_vjp", "adj_profile_enable", "adj_profile_read", "adj_set_tile", "adj_get_tile",
-           "adj_batch_table_bytes", "adj_batch_create", "adj_batch_destroy", "adj_batch_offset",
+           "adj_tile_launched", "adj_batch_table_bytes", "adj_batch_create", "adj_batch_destroy", "adj_batch_offset",
            "adj_batch_workspace_bytes", "adj_batch_primal_step", "adj_batch_adjoint_step",
            "adj_batch_objective_and_grad", "adj_batch_energy_vhat",
            "adj_last_error", "adj_version")
@@ -147,6 +148,7 @@ def lib():
                              ctypes.c_int),
         "adj_set_tile": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "adj_get_tile": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "adj_tile_launched": ([ctypes.c_int] * 5, ctypes.c_int),
         "adj_batch_table_bytes": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], sz),
         "adj_batch_create": ([ctypes.POINTER(vp), ctypes.c_int, gp, op, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                               ctypes.POINTER(dbl), vp, sz], ctypes.c_int),
@@ -320,6 +322,15 @@ def set_tile(kernel_class, precision, tile):
 
 def get_tile(kernel_class, precision):
     t = lib().adj_get_tile(int(kernel_class), int(precision))
+    if t < 0:
+        _check(t)
+    return t
+
+
+def tile_launched(kernel_class, precision, bc_x, lnu, tile):
+    """The tile a launch really uses when `tile` is selected (reverse-stage tiles too large for a
+    work-group's shared memory run as 16x4x4)."""
+    t = lib().adj_tile_launched(int(kernel_class), int(precision), int(bc_x), int(bool(lnu)), int(tile))
     if t < 0:
         _check(t)
     return t

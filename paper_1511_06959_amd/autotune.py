@@ -11,7 +11,8 @@ import os
 
 import torch
 
-from . import (F64, PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, TILES, get_tile, residual, set_tile, vjp)
+from . import (F64, PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, TILES, get_tile, residual, set_tile, tile_launched,
+               vjp)
 
 CACHE = os.environ.get("ADJNS_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "adjns_tiles.json"))
 
@@ -88,9 +89,11 @@ def tune(g, reps=20, use_cache=True, verbose=False, rounds=3, margin=0.03):
             out[kclass] = (db[key]["tile"], {int(k): v for k, v in db[key]["ms"].items()})
             continue
         prev = get_tile(kclass, g.precision)
+        # only tiles that launch as themselves (the others run as a smaller tile already timed)
+        cands = [t for t in TILES if tile_launched(kclass, g.precision, g.bc_x, False, t) == t]
         times = {}
         for _ in range(rounds):
-            for t in TILES:
+            for t in cands:
                 set_tile(kclass, g.precision, t)
                 if kclass == PROF_ADJOINT_STAGE:
                     ms = _time(lambda: vjp(g, w, kh, buf), reps)

@@ -471,6 +471,15 @@ int adj_get_tile(int kernel_class, int precision) {
   return tile_choice(kernel_class, precision == ADJ_F64);
 }
 
+int adj_tile_launched(int kernel_class, int precision, int bc_x, int lnu, int tile) {
+  if (kernel_class != ADJ_PROF_ADJOINT_STAGE && kernel_class != ADJ_PROF_PRIMAL_STAGE) return fail(ADJ_EINVAL, "bad class");
+  if (precision != ADJ_F64 && precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", precision);
+  if (bc_x != ADJ_BC_PERIODIC && bc_x != ADJ_BC_SLIP_WALLS) return fail(ADJ_EINVAL, "bad bc_x %d", bc_x);
+  if (tile < 0 || tile >= NTILES) return fail(ADJ_EINVAL, "bad tile id %d", tile);
+  if (kernel_class == ADJ_PROF_PRIMAL_STAGE) return tile;  // every primal tile fits
+  return adjoint_tile_used(precision == ADJ_F64, bc_x == ADJ_BC_SLIP_WALLS, lnu != 0, tile);
+}
+
 // ------------------------------------------------------------------------------------------
 // Ensembles
 // ------------------------------------------------------------------------------------------

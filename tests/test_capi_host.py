@@ -158,3 +158,19 @@ def test_ensemble_calls_reject_null_handle():
     assert L.adj_batch_adjoint_step(None, 1, p, None, p, None, p, None, p, 1024, None) == -1
     assert L.adj_batch_offset(None, 0, 0) == -1
     assert L.adj_batch_workspace_bytes(None) == 0
+
+
+def test_tile_launched():
+    # reverse-stage LDS per work-group: 8 B x (8 box planes + max(4 record planes + 3 work-term
+    # planes, 3 staging planes)); the FP64 32x8x4 box (34 x 10 x 6 cells) needs 226560 B > 160 KiB
+    A, P = adj.PROF_ADJOINT_STAGE, adj.PROF_PRIMAL_STAGE
+    for t in adj.TILES:
+        assert adj.tile_launched(A, adj.F32, adj.BC_PERIODIC, False, t) == t
+        assert adj.tile_launched(P, adj.F64, adj.BC_SLIP_WALLS, True, t) == t
+    assert adj.tile_launched(A, adj.F64, adj.BC_PERIODIC, False, adj.TILE_32x8x4) == adj.TILE_16x4x4
+    assert adj.tile_launched(A, adj.F64, adj.BC_PERIODIC, False, adj.TILE_32x4x4) == adj.TILE_32x4x4
+    assert adj.tile_launched(A, adj.F64, adj.BC_SLIP_WALLS, True, adj.TILE_16x4x4) == adj.TILE_16x4x4
+    with pytest.raises(adj.AdjError):
+        adj.tile_launched(A, adj.F64, 3, False, 0)
+    with pytest.raises(adj.AdjError):
+        adj.tile_launched(A, adj.F64, adj.BC_PERIODIC, False, len(adj.TILES))
