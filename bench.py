@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = 157.3  # FP32 vector, 256 CUs x 2.4 GHz x 256 operations per clock
 METRIC = "adjoint cell-steps/s + % HBM roofline, FP32/BF16-ckpt vs FP64 at stated rel err"
 
 # Algorithmic values moved per cell by the four reverse-stage launches of one adjoint step
@@ -42,10 +43,10 @@ METRIC = "adjoint cell-steps/s + % HBM roofline, FP32/BF16-ckpt vs FP64 at state
 VALUES_PER_STAGE_LAUNCH = 95.0 / 4.0
 
 
-def traffic_from_profiles(kernel_src_hash, precision):
-    """HBM bytes per cell and launch of the reverse-stage kernel from the committed rocprofv3
-    counter summary, or None when it was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_adjoint_stage_tgv64.txt")
+def profile_values(name, kernel_src_hash, tile):
+    """key = value pairs of a committed rocprofv3 summary of the reverse-stage kernel
+    (profiles/<name>), or None when it was taken on a different kernel source or tile."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -53,10 +54,24 @@ def traffic_from_profiles(kernel_src_hash, precision):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != kernel_src_hash:
+    if vals.get("kernel_source_sha256") != kernel_src_hash or vals.get("tile_f32") != tile:
         return None
-    key = f"bytes_per_cell_launch_{precision}"
-    return float(vals[key]) if key in vals else None
+    return vals
+
+
+def valu_roofline(valu, cells, avg_us):
+    """The reverse-stage kernel against the vector ALU: FP32 operations it issues per launch
+    (committed SQ counter summary) / its live average launch duration, against 157.3 TFLOP/s;
+    issue_frac = wave-level VALU instructions x 4 cycles (a wave64 instruction on a 16-lane SIMD)
+    / (1024 SIMDs x 2.4 GHz x duration)."""
+    if valu is None:
+        return None
+    s = avg_us * 1e-6
+    flops = float(valu["fp32_ops_per_cell_launch_f32"]) * cells
+    insts = float(valu["valu_insts_per_cell_launch_f32"]) * cells
+    return {"bound": "alu", "achieved": flops / s / 1e12, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": flops / s / 1e12 / VALU_PEAK_TFLOPS, "issue_frac": insts * 4.0 / (1024 * 2.4e9 * s),
+            "fp32_ops_per_launch": flops, "valu_insts_per_launch": insts}
 
 
 def kernel_hash():
@@ -98,7 +113,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     w0 = torch.from_numpy(g.to_stored(wl.w0)).to("cuda", dt)
     s = torch.from_numpy(wl.s).to("cuda", dt)
     ws = adj.workspace(g)
-    traj = sweep.Trajectory(g, wl.nsteps)
+    traj = sweep.Trajectory(g, wl.nsteps, stages=stages)  # the schedule the graphs replay
     J = torch.zeros(1, dtype=torch.float64, device="cuda")
     gs = torch.zeros(5 * g.ncells, dtype=dt, device="cuda")
     out = {}
@@ -375,7 +390,11 @@ def main():
         return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
     khash = kernel_hash()
-    traffic = traffic_from_profiles(khash, "f32")
+    tile32 = r32["tiles"].get("adjoint_stage", {}).get("launched")
+    traffic = profile_values("traffic_adjoint_stage_tgv64.txt", khash, tile32)
+    valu = profile_values("valu_adjoint_stage_tgv64.txt", khash, tile32)
+    if big:
+        traffic = valu = None
     line = {
         "metric": METRIC,
         "value": r32["value"],
@@ -397,7 +416,7 @@ def main():
             "step": "one whole window: forward sweep + reverse sweep",
             "schedule": ("stage states of every step kept in HBM by the forward sweep" if stages else
                          "reverse step recomputes the stage states from the stored w_n"),
-            "checkpoints": "BF16 records (per-variable affine)" if big else "native FP32 / FP64 states",
+            "checkpoints": "BF16 records (block-scaled, one affine map per variable and 4x4x4 block)" if big else "native FP32 / FP64 states",
         },
         "roofline": {
             "bound": "hbm",
@@ -405,11 +424,12 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": r32["stage_achieved_gbs"] / HBM_PEAK_GBS,
-            "traffic": None if (traffic is None or big) else traffic * wl.ncells,
+            "traffic": None if traffic is None else float(traffic["bytes_per_cell_launch_f32"]) * wl.ncells,
             "kernel": "k_adjoint_stage (reverse-stage gather)",
             "avg_launch_us": r32["stage_avg_us"],
             "alg_bytes_per_launch": r32["stage_alg_bytes"],
         },
+        "roofline_valu": valu_roofline(valu, wl.ncells, r32["stage_avg_us"]),
         "adjoint_sweep_cell_steps_per_s": r32["adjoint_sweep_cell_steps_per_s"],
         "primal_cell_steps_per_s": r32["primal_cell_steps_per_s"],
         "kernel_ms_per_window": {k: v[0] / args.steps for k, v in r32["prof"].items()},

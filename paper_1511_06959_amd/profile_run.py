@@ -13,6 +13,9 @@
     python -m paper_1511_06959_amd.profile_run traffic --fetch D --write D --copy-fetch D --copy-write D
         --cells N [--kernel k_adjoint_stage]
         HBM bytes per launch of a kernel from FETCH_SIZE / WRITE_SIZE runs, calibrated on the copy runs
+    python -m paper_1511_06959_amd.profile_run valu <dir> --cells N [--kernel k_adjoint_stage]
+        vector-ALU instructions and FP32 operations per launch from one run with the SQ counters
+        of VALU_COUNTERS
     python -m paper_1511_06959_amd.profile_run trace <dir> --title T --command C
         markdown table of a --kernel-trace --stats run
 
@@ -129,7 +132,6 @@ def traffic(fetch, write, copy_fetch, copy_write, mib, cells, kernel, commands):
     """key = value file of HBM bytes per cell and launch of `kernel` (all its instantiations,
     weighted by dispatch count), FETCH_SIZE / WRITE_SIZE scaled by what they read for a copy of
     mib MiB (which reads and writes exactly that much)."""
-    import hashlib
     cf = _counter_means(copy_fetch, "copyBuffer")
     cw = _counter_means(copy_write, "copyBuffer")
     (_, cfv), = cf.values()
@@ -140,10 +142,6 @@ def traffic(fetch, write, copy_fetch, copy_write, mib, cells, kernel, commands):
     fkib = sum(n * v for n, v in fm.values()) / nd
     wkib = sum(n * v for n, v in wm.values()) / sum(n for n, _ in wm.values())
     byts = (fkib * sf + wkib * sw) * 1024.0
-    h = hashlib.sha256()
-    here = os.path.dirname(os.path.abspath(__file__))
-    for name in ("stencil.hip", "common.hpp"):
-        h.update(open(os.path.join(here, "csrc", name), "rb").read())
     print(f"# HBM traffic of {kernel} (rocprofv3 FETCH_SIZE and WRITE_SIZE, separate runs), {cells} cells")
     for c in commands:
         print(f"# command: {c}")
@@ -151,10 +149,71 @@ def traffic(fetch, write, copy_fetch, copy_write, mib, cells, kernel, commands):
     print(f"# scale factors (true / counter): fetch {sf:.4f}, write {sw:.4f}")
     for k in sorted(fm):
         print(f"# {k}: {fm[k][0]} dispatches, FETCH_SIZE {fm[k][1]:.1f} KiB, WRITE_SIZE {wm.get(k, (0, 0))[1]:.1f} KiB")
-    print(f"kernel_source_sha256 = {h.hexdigest()}")
+    print(f"kernel_source_sha256 = {_src_hash()}")
+    print(f"tile_f32 = {_tiles(fm)}")
     print(f"fetch_bytes_per_launch = {fkib * sf * 1024.0:.6g}")
     print(f"write_bytes_per_launch = {wkib * sw * 1024.0:.6g}")
     print(f"bytes_per_cell_launch_f32 = {byts / cells:.6g}")
+
+
+def _tiles(names):
+    """Tile shapes ("32x8x4") in the template arguments of k_*_stage kernel names."""
+    out = set()
+    for k in names:
+        m = re.search(r"<[^<>]*?(\d+), (\d+), (\d+)>$", k)
+        if m:
+            out.add("x".join(m.groups()))
+    return ",".join(sorted(out))
+
+
+def _src_hash():
+    import hashlib
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for name in ("stencil.hip", "common.hpp"):
+        h.update(open(os.path.join(here, "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+VALU_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32",
+                 "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_TRANS_F32")
+
+
+def valu(outdir, cells, kernel, commands):
+    """key = value file of vector-ALU work per cell and launch of `kernel` (all its
+    instantiations, weighted by dispatch count) from one run with VALU_COUNTERS: wave-level VALU
+    instructions, and FP32 operations issued (64 lanes per wave instruction; an FMA counts 2)."""
+    acc, disp = defaultdict(lambda: defaultdict(float)), defaultdict(set)
+    for f in glob.glob(os.path.join(outdir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                k = short_name(row.get("Kernel_Name", ""))
+                if kernel in k:
+                    acc[k][row["Counter_Name"]] += float(row["Counter_Value"])
+                    disp[k].add(row.get("Dispatch_Id"))
+    if not acc:
+        sys.exit(f"no {kernel} dispatches under {outdir}")
+    nd = sum(len(disp[k]) for k in acc)
+    tot = defaultdict(float)
+    for k in acc:
+        for c, v in acc[k].items():
+            tot[c] += v
+    per = {c: tot[c] / nd for c in tot}  # per dispatch
+    flops = 64.0 * (per.get("SQ_INSTS_VALU_ADD_F32", 0.0) + per.get("SQ_INSTS_VALU_MUL_F32", 0.0)
+                    + 2.0 * per.get("SQ_INSTS_VALU_FMA_F32", 0.0) + per.get("SQ_INSTS_VALU_TRANS_F32", 0.0))
+    print(f"# vector-ALU work of {kernel} (rocprofv3 SQ counters, one run), {cells} cells")
+    for c in commands:
+        print(f"# command: {c}")
+    for k in sorted(acc):
+        print(f"# {k}: {len(disp[k])} dispatches, " +
+              ", ".join(f"{c} {acc[k][c] / len(disp[k]):.6g}" for c in VALU_COUNTERS if c in acc[k]))
+    print("# FP32 operations = 64 x (ADD + MUL + TRANS + 2 FMA) wave instructions")
+    print(f"kernel_source_sha256 = {_src_hash()}")
+    print(f"tile_f32 = {_tiles(acc)}")
+    print(f"waves_per_launch = {per.get('SQ_WAVES', 0.0):.6g}")
+    print(f"valu_insts_per_launch = {per.get('SQ_INSTS_VALU', 0.0):.6g}")
+    print(f"valu_insts_per_cell_launch_f32 = {per.get('SQ_INSTS_VALU', 0.0) / cells:.6g}")
+    print(f"fp32_ops_per_cell_launch_f32 = {flops / cells:.6g}")
 
 
 def trace_summary(outdir, title, command):
@@ -202,6 +261,11 @@ def main():
     t.add_argument("--cells", type=int, required=True)
     t.add_argument("--kernel", default="k_adjoint_stage")
     t.add_argument("--command", action="append", default=[])
+    v = sub.add_parser("valu")
+    v.add_argument("outdir")
+    v.add_argument("--cells", type=int, required=True)
+    v.add_argument("--kernel", default="k_adjoint_stage")
+    v.add_argument("--command", action="append", default=[])
     r = sub.add_parser("trace")
     r.add_argument("outdir")
     r.add_argument("--title", required=True)
@@ -210,6 +274,9 @@ def main():
     if args.cmd == "traffic":
         traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.mib, args.cells, args.kernel,
                 args.command)
+        return
+    if args.cmd == "valu":
+        valu(args.outdir, args.cells, args.kernel, args.command)
         return
     if args.cmd == "trace":
         trace_summary(args.outdir, args.title, args.command)
