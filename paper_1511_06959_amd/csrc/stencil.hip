@@ -274,16 +274,18 @@ namespace {
 
 enum { A_K0 = 0, A_K1, A_K2, A_K3, A_K4, A_U1, A_U2, A_U3, A_NU };
 
-// Direction-D faces of the box, indexed by their lower cell in box coordinates.  Records cover
-// every box cell (those a tile cell or a tangential neighbour reads among them); work terms (Q)
-// cover the faces bounding tile cells.
+// Direction-D faces of the box, indexed by their lower cell (ax, ay, az) in box coordinates.
+// Records cover every lower cell that a tile cell or a tangential neighbour needs, in a compact
+// array (rows of NX lower cells); work terms (Q) cover the faces bounding tile cells.
 template <int TX, int TY, int TZ, int HX, int D>
 struct FaceSet {
   using B = TBox<TX, TY, TZ, HX, 1>;
-  // records are indexed by the box index of the lower cell; every box cell whose +D neighbour is
-  // in the box gets one (a few are never read), so no index decomposition is needed
-  static constexpr int STEP = D == 0 ? 1 : (D == 1 ? B::SY : B::SZ);
-  static constexpr int N = B::NB - STEP;
+  static constexpr int X0 = D == 0 ? HX - 1 : 0;
+  static constexpr int NX = D == 0 ? TX + 1 : B::BX;
+  static constexpr int NY = D == 1 ? TY + 1 : B::BY;
+  static constexpr int NZ = D == 2 ? TZ + 1 : B::BZ;
+  static constexpr int N = NX * NY * NZ;
+  static constexpr int STEP = D == 0 ? 1 : (D == 1 ? B::SY : B::SZ);  // box-index step to the upper cell
   static constexpr int QX0 = D == 0 ? HX - 1 : HX;
   static constexpr int QY0 = D == 1 ? 0 : 1;
   static constexpr int QZ0 = D == 2 ? 0 : 1;
@@ -291,8 +293,16 @@ struct FaceSet {
   static constexpr int NQY = D == 1 ? TY + 1 : TY;
   static constexpr int NQZ = D == 2 ? TZ + 1 : TZ;
   static constexpr int NQ = NQX * NQY * NQZ;
-  __device__ static int idx(int ax, int ay, int az) { return az * B::SZ + ay * B::SY + ax; }
+  __device__ static int idx(int ax, int ay, int az) { return (ax - X0) + NX * (ay + NY * az); }
+  // box index of the lower cell of record f: the records skip BX - NX box cells per row (D = 0)
+  // or BX per z-layer (D = 1) and none for D = 2, so one constant division finds it
+  __device__ static int box(int f) {
+    if constexpr (D == 0) return f + (f / NX) * (B::BX - NX) + X0;
+    else if constexpr (D == 1) return f + (f / (NX * NY)) * (B::SZ - NX * NY);
+    else return f;
+  }
   __device__ static int qidx(int ax, int ay, int az) { return (ax - QX0) + NQX * ((ay - QY0) + NQY * (az - QZ0)); }
+  __device__ static bool has(int ax) { return ax >= X0 && ax < X0 + NX; }
   __device__ static bool hasq(int ax) { return ax >= QX0 && ax < QX0 + NQX; }
 };
 
@@ -308,13 +318,13 @@ __device__ __forceinline__ void face_records(const T (*sm)[NB], T (*fr)[NF], T (
   using F = FaceSet<TX, TY, TZ, HX, D>;
   using B = TBox<TX, TY, TZ, HX, 1>;
   constexpr int NT = TX * TY * TZ;
-  for (int A = threadIdx.x; A < F::N; A += NT) {
-    const int Bc = A + F::STEP;
+  for (int f = threadIdx.x; f < F::N; f += NT) {
+    const int A = F::box(f), Bc = A + F::STEP;
     const T dK4 = sm[A_K4][A] - sm[A_K4][Bc];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      fr[k][A] = (sm[A_K1 + k][A] - sm[A_K1 + k][Bc]) + dK4 * (sm[A_U1 + k][A] + sm[A_U1 + k][Bc]);
-    fr[3][A] = dK4;
+      fr[k][f] = (sm[A_K1 + k][A] - sm[A_K1 + k][Bc]) + dK4 * (sm[A_U1 + k][A] + sm[A_U1 + k][Bc]);
+    fr[3][f] = dK4;
   }
   const T qs = T(0.5) * c.idx[D];
   for (int q = threadIdx.x; q < F::NQ; q += NT) {
@@ -329,8 +339,8 @@ __device__ __forceinline__ void face_records(const T (*sm)[NB], T (*fr)[NF], T (
 }
 
 // Gather of the direction-D records at box cell (qx, qy, qz).  VIRT: the cell is the ghost image
-// of a wall cell (only faces with a real cell contribute; the records of faces between two
-// ghosts are zero, since ghosts carry kh = 0).
+// of a wall cell (only faces with a real cell contribute; lower cells outside the record set
+// are faces between two ghosts and count as zero).
 template <typename T, int TX, int TY, int TZ, int HX, int D, int NF, int NQF, bool VIRT>
 __device__ __forceinline__ void face_gather(const T (*fr)[NF], const T (*fq)[NQF], int qx, int qy, int qz,
                                             const Consts<T>& c, T uh[3], T& eh) {
@@ -342,6 +352,7 @@ __device__ __forceinline__ void face_gather(const T (*fr)[NF], const T (*fq)[NQF
   for (int side = 0; side < 2; ++side) {
     const int ax = qx - (D == 0 && side == 0), ay = qy - (D == 1 && side == 0), az = qz - (D == 2 && side == 0);
     if (VIRT && D != 0) continue;
+    if (VIRT && !F::has(ax)) continue;
     const int f = F::idx(ax, ay, az);
     const T sg = side == 0 ? T(1) : T(-1);
     const T sD = fr[D][f];
@@ -371,6 +382,7 @@ __device__ __forceinline__ void face_gather(const T (*fr)[NF], const T (*fq)[NQF
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         const int ax = cx - (D == 0 && side == 0), ay = cy - (D == 1 && side == 0), az = cz - (D == 2 && side == 0);
+        if (VIRT && D == 0 && !F::has(ax)) continue;
         const int f = F::idx(ax, ay, az);
         tl += sgn * fr[l][f];
         tD += sgn * fr[D][f];
@@ -474,7 +486,7 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
   using F0 = FaceSet<TX, TY, TZ, HX, 0>;
   using F1 = FaceSet<TX, TY, TZ, HX, 1>;
   using F2 = FaceSet<TX, TY, TZ, HX, 2>;
-  constexpr int NF = NB;  // face records indexed by box cell
+  constexpr int NF = Max3<F0::N, F1::N, F2::N>::v;
   constexpr int NQF = Max3<F0::NQ, F1::NQ, F2::NQ>::v;
   // one LDS region serves first as the (rho, E/rho, p) planes of the box, then as the face records
   constexpr int NUN = 4 * NF + 3 * NQF > 3 * NB ? 4 * NF + 3 * NQF : 3 * NB;
@@ -719,7 +731,7 @@ constexpr int adjoint_lds_bytes() {
   using F0 = FaceSet<TX, TY, TZ, HX, 0>;
   using F1 = FaceSet<TX, TY, TZ, HX, 1>;
   using F2 = FaceSet<TX, TY, TZ, HX, 2>;
-  constexpr int rec = 4 * B::NB + 3 * Max3<F0::NQ, F1::NQ, F2::NQ>::v;
+  constexpr int rec = 4 * Max3<F0::N, F1::N, F2::N>::v + 3 * Max3<F0::NQ, F1::NQ, F2::NQ>::v;
   return (int)sizeof(T) * ((LNU ? A_NU + 1 : A_NU) * B::NB + (rec > 3 * B::NB ? rec : 3 * B::NB));
 }
 
