@@ -91,6 +91,11 @@ typedef struct adj_grid {
                           formed from them.  The scheme is unchanged; adjoint fields are
                           gradients with respect to the stored variables, the same as those
                           with respect to w.                                                   */
+  double nu_weight[3]; /* artificial-viscosity weights of the variable groups (rho, rho u,
+                          rho E): the adjoint components of group g are diffused with
+                          nu_g = lambda nu_weight[g] sigma_1 (each >= 0; all three 0 means
+                          1, 1, 1, the single viscosity of the paper)  [Conclusion: separate
+                          adjoint viscosities for rho, rho U, rho E]                           */
 } adj_grid;
 
 typedef struct adj_objective {
@@ -122,7 +127,8 @@ int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* 
  *   k^2 = dt/3 a + dt/2 g3, g2 = ...; k^1 = dt/6 a + dt/2 g2, g1 = ...;
  *   w^_n = a + g1 + g2 + g3 + g4 + c_n dj/dw(w_n);  grad_s += k^1 + k^2 + k^3 + k^4,
  * where a = w^_{n+1} and (L_nu q)_i = sum_d [nu_{i+1/2}(q_{i+1}-q_i) - nu_{i-1/2}(q_i-q_{i-1})]/dx_d^2
- * with face nu the mean of its cells (no artificial flux through slip walls).
+ * with face nu the mean of its cells (no artificial flux through slip walls), applied to each
+ * component with the nu of its variable group (grid->nu_weight).
  *   w_n     in : primal state at step n (state-sized), or a BF16 record when ckpt_format says so
  *   s       in : source field or NULL
  *   wh_np1  in : adjoint at step n+1 (state-sized)

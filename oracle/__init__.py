@@ -68,8 +68,9 @@ def lib():
             "orc_lnu_apply": [gp, dp, dp, dp],
             "orc_primal_step": [gp, dp, dp, dp],
             "orc_primal_step_complex": [gp, dp, dp, dp, dp, dp, dp],
-            "orc_tlm_step": [gp, dp, dp, dp, dp, ctypes.c_double, dp, dp],
-            "orc_adjoint_step": [gp, dp, dp, dp, ctypes.c_double, op, ctypes.c_double, dp, dp],
+            "orc_tlm_step": [gp, dp, dp, dp, dp, dp, dp, dp],
+            "orc_lnu_apply_groups": [gp, dp, dp, dp, dp],
+            "orc_adjoint_step": [gp, dp, dp, dp, dp, op, ctypes.c_double, dp, dp],
             "orc_objective": [gp, op, dp, dp, dp],
             "orc_sigma1": [gp, dp, dp],
             "orc_growth_matrix_field": [gp, dp, dp],
@@ -198,6 +199,22 @@ def primal_step_complex(g, w, s=None):
     return outr + 1j * outi
 
 
+def _lam3(lam):
+    """lambda per variable group (rho, rho u, rho E): a scalar applies to all three."""
+    v = np.broadcast_to(np.asarray(lam, dtype=np.float64), (3,)).copy()
+    return v, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def lnu_apply_groups(g, w, lam, q):
+    """L_nu q with nu_g = lam_g sigma_1(w) on the components of group g (rho, rho u, rho E)."""
+    w, wp = _d(w)
+    q, qp = _d(q)
+    lam, lp = _lam3(lam)
+    out = np.zeros(5 * _ncells(g))
+    _chk(lib().orc_lnu_apply_groups(ctypes.byref(g), wp, lp, qp, _d(out)[1]), "lnu_apply_groups")
+    return out
+
+
 def tlm_step(g, w, s, dw, ds=None, lam=0.0):
     w, wp = _d(w)
     sp = _null()
@@ -209,13 +226,15 @@ def tlm_step(g, w, s, dw, ds=None, lam=0.0):
         ds, dsp = _d(ds)
     wn = np.zeros_like(w)
     dwn = np.zeros_like(w)
-    _chk(lib().orc_tlm_step(ctypes.byref(g), wp, sp, dwp, dsp, float(lam), _d(wn)[1], _d(dwn)[1]),
+    lam, lp = _lam3(lam)
+    _chk(lib().orc_tlm_step(ctypes.byref(g), wp, sp, dwp, dsp, lp, _d(wn)[1], _d(dwn)[1]),
          "tlm_step")
     return wn, dwn
 
 
 def adjoint_step(g, w, s, a, lam=0.0, obj=None, c_n=0.0, grad_s=None):
-    """Returns w^_n; accumulates into grad_s (FP64 array, modified in place) when given."""
+    """Returns w^_n; accumulates into grad_s (FP64 array, modified in place) when given.
+    lam: one lambda for all components, or three (rho, rho u, rho E groups)."""
     w, wp = _d(w)
     sp = _null()
     if s is not None:
@@ -227,7 +246,8 @@ def adjoint_step(g, w, s, a, lam=0.0, obj=None, c_n=0.0, grad_s=None):
         assert grad_s.dtype == np.float64 and grad_s.flags.c_contiguous
         gsp = grad_s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     op = ctypes.byref(obj) if obj is not None else ctypes.POINTER(OrcObj)()
-    _chk(lib().orc_adjoint_step(ctypes.byref(g), wp, sp, ap, float(lam), op, float(c_n), _d(wh)[1], gsp),
+    lam, lp = _lam3(lam)
+    _chk(lib().orc_adjoint_step(ctypes.byref(g), wp, sp, ap, lp, op, float(c_n), _d(wh)[1], gsp),
          "adjoint_step")
     return wh
 

@@ -31,7 +31,9 @@
 //   * discrete adjoint of the RK4 step [Implementation; terminal condition and backward solve]:
 //       the transposed Jacobian of every face flux is assembled from dual-number local Jacobians
 //   * artificial adjoint viscosity  d_l( lambda sigma_1 delta_ki delta_jl d_j w^_k )  [Stabilizing
-//     adjoint equations, last equation], discretised as a symmetric face-based Laplacian
+//     adjoint equations, last equation], discretised as a symmetric face-based Laplacian; with
+//     one lambda per variable group (rho, rho u, rho E), the separate adjoint viscosities the
+//     Conclusion proposes
 //   * growth matrix M = M1 - M2 and its largest singular value sigma_1 [Energy Analysis, M1/M2]
 //   * adjoint energy E = int |v^|^2 dV with v^ = T^{-T} w^ [Symmetrization, Energy Analysis]
 //   * objectives: volume-mean pressure, volume-mean viscous dissipation sigma:grad u, and the
@@ -347,15 +349,15 @@ void jvp(const G& g, const double* W, const double* v, double* out) {
 
 // ------------------------------------------------------------------------------------------
 // Artificial adjoint viscosity  (L_nu q)_i = sum_d [nu_{i+1/2}(q_{i+1}-q_i) - nu_{i-1/2}(q_i-q_{i-1})]/dx_d^2
-// with nu_f = (nu_L + nu_R)/2, applied to each of the 5 components (delta_ki delta_jl).  Wall faces
-// carry no artificial flux.  Accumulates into out.
+// with nu_f = (nu_L + nu_R)/2, applied to each of the 5 components (delta_ki delta_jl); component
+// v uses the cell field nu[v].  Wall faces carry no artificial flux.  Accumulates into out.
 // ------------------------------------------------------------------------------------------
-void lnu_apply(const G& g, const double* nu, const double* q, double* out) {
+void lnu_apply(const G& g, const double* const nu[5], const double* q, double* out) {
   face_scatter<double>(g, 5 * g.N, out, [&](int d, long i, long j, long k, double* acc) {
     Slot sl[10]; face_slots(g, d, i, j, k, sl);
     if (!sl[0].real || !sl[1].real) return;
-    double nf = 0.5 * (nu[sl[0].c] + nu[sl[1].c]);
     for (int v = 0; v < 5; ++v) {
+      double nf = 0.5 * (nu[v][sl[0].c] + nu[v][sl[1].c]);
       double flux = nf * (q[v * g.N + sl[1].c] - q[v * g.N + sl[0].c]) / (g.dx[d] * g.dx[d]);
       acc[v * g.N + sl[0].c] += flux;
       acc[v * g.N + sl[1].c] -= flux;
@@ -690,7 +692,8 @@ int orc_vjp(const orc_grid* gr, const double* W, const double* kh, double* out) 
 int orc_lnu_apply(const orc_grid* gr, const double* nu, const double* q, double* out) {
   if (check(gr)) return -1;
   G g(gr);
-  lnu_apply(g, nu, q, out);
+  const double* const nus[5] = {nu, nu, nu, nu, nu};
+  lnu_apply(g, nus, q, out);
   return 0;
 }
 
@@ -718,21 +721,46 @@ int orc_primal_step_complex(const orc_grid* gr, const double* w_re, const double
   return 0;
 }
 
+// Cell fields nu_g = lambda_g sigma_1(w) of the three variable groups (rho), (rho u), (rho E) and
+// the field each component uses.
+struct NuFields {
+  std::vector<double> f[3];
+  const double* comp[5];
+  bool any = false;
+  NuFields(const G& g, const double* w, const double lam[3]) {
+    any = lam[0] != 0.0 || lam[1] != 0.0 || lam[2] != 0.0;
+    if (!any) return;
+    std::vector<double> sig(g.N);
+    sigma1_field(g, w, sig.data());
+    for (int k = 0; k < 3; ++k) {
+      f[k].resize(g.N);
+      for (long c = 0; c < g.N; ++c) f[k][c] = lam[k] * sig[c];
+    }
+    const int group[5] = {0, 1, 1, 1, 2};
+    for (int v = 0; v < 5; ++v) comp[v] = f[group[v]].data();
+  }
+};
+
+// out += L_nu q with the group fields nu_g = lambda_g sigma_1(w) (lambda: 3 values)
+int orc_lnu_apply_groups(const orc_grid* gr, const double* w, const double* lambda, const double* q,
+                         double* out) {
+  if (check(gr)) return -1;
+  G g(gr);
+  const NuFields nu(g, w, lambda);
+  if (nu.any) lnu_apply(g, nu.comp, q, out);
+  return 0;
+}
+
 // Tangent-linear RK4 step: (w, dw) -> (w_next, dw_next) for perturbations dw of the state and ds
 // of the source.  With lambda > 0 the tangent of every stage also carries L_nu dW with
-// nu = lambda sigma_1(w) frozen over the step (the operator whose transpose the stabilised
-// adjoint applies).
+// nu_g = lambda_g sigma_1(w) frozen over the step (the operator whose transpose the stabilised
+// adjoint applies); lambda holds one value per variable group (rho, rho u, rho E).
 int orc_tlm_step(const orc_grid* gr, const double* w, const double* s, const double* dw,
-                 const double* ds, double lambda, double* wn, double* dwn) {
+                 const double* ds, const double* lambda, double* wn, double* dwn) {
   if (check(gr)) return -1;
   G g(gr);
   const long M = 5 * g.N;
-  std::vector<double> nu;
-  if (lambda != 0.0) {
-    nu.resize(g.N);
-    sigma1_field(g, w, nu.data());
-    for (auto& x : nu) x *= lambda;
-  }
+  const NuFields nu(g, w, lambda);
   std::vector<double> Ws[4];
   rk4_stage_states(g, w, s, Ws);
   std::vector<double> dW(dw, dw + M), dk[4];
@@ -740,7 +768,7 @@ int orc_tlm_step(const orc_grid* gr, const double* w, const double* s, const dou
   for (int m = 0; m < 4; ++m) {
     dk[m].assign(M, 0.0);
     jvp(g, Ws[m].data(), dW.data(), dk[m].data());
-    if (lambda != 0.0) lnu_apply(g, nu.data(), dW.data(), dk[m].data());
+    if (nu.any) lnu_apply(g, nu.comp, dW.data(), dk[m].data());
     if (ds)
       for (long x = 0; x < M; ++x) dk[m][x] += ds[x];
     if (m < 3)
@@ -754,7 +782,7 @@ int orc_tlm_step(const orc_grid* gr, const double* w, const double* s, const dou
 
 // One reverse RK4 step of the discrete adjoint   [Implementation; adjoint terminal condition and
 // backward integration; stabilised adjoint equation]:
-//   recompute W1..W4 from w_n;  nu = lambda sigma_1(w_n)
+//   recompute W1..W4 from w_n;  nu_g = lambda_g sigma_1(w_n) per variable group
 //   k^4 = dt/6 a;           g4 = (J(W4)^T + L_nu) k^4
 //   k^3 = dt/3 a + dt g4;   g3 = (J(W3)^T + L_nu) k^3
 //   k^2 = dt/3 a + dt/2 g3; g2 = (J(W2)^T + L_nu) k^2
@@ -762,18 +790,13 @@ int orc_tlm_step(const orc_grid* gr, const double* w, const double* s, const dou
 //   w^_n = a + g1 + g2 + g3 + g4 + c_n dj/dw(w_n);   grad_s += k^1 + k^2 + k^3 + k^4
 // where a = w^_{n+1}.  grad_s may be NULL; obj may be NULL (no injection).
 int orc_adjoint_step(const orc_grid* gr, const double* w, const double* s, const double* a,
-                     double lambda, const orc_obj* ob, double c_n, double* wh, double* grad_s) {
+                     const double* lambda, const orc_obj* ob, double c_n, double* wh, double* grad_s) {
   if (check(gr)) return -1;
   G g(gr);
   const long M = 5 * g.N;
   std::vector<double> Ws[4];
   rk4_stage_states(g, w, s, Ws);
-  std::vector<double> nu;
-  if (lambda != 0.0) {
-    nu.resize(g.N);
-    sigma1_field(g, w, nu.data());
-    for (auto& x : nu) x *= lambda;
-  }
+  const NuFields nu(g, w, lambda);
   const double dt = g.dt;
   const double ca[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};  // weight of a in k^m, m = 1..4
   const double cg[4] = {dt / 2.0, dt / 2.0, dt, 0.0};             // weight of g_{m+1} in k^m
@@ -781,7 +804,7 @@ int orc_adjoint_step(const orc_grid* gr, const double* w, const double* s, const
   for (int m = 3; m >= 0; --m) {
     for (long x = 0; x < M; ++x) kh[x] = ca[m] * a[x] + cg[m] * gnext[x];
     vjp(g, Ws[m].data(), kh.data(), gm.data());
-    if (lambda != 0.0) lnu_apply(g, nu.data(), kh.data(), gm.data());
+    if (nu.any) lnu_apply(g, nu.comp, kh.data(), gm.data());
     for (long x = 0; x < M; ++x) { sum_g[x] += gm[x]; sum_k[x] += kh[x]; }
     gnext = gm;
   }

@@ -49,12 +49,15 @@ class Grid(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("ckpt_format", ctypes.c_int32),
         ("w_ref", ctypes.c_double * 5),
+        ("nu_weight", ctypes.c_double * 3),
     ]
 
     @classmethod
     def make(cls, n, L, mu, dt, gamma=1.4, prandtl=0.72, bc_x=0, precision=F64, ckpt_format=CKPT_NATIVE,
-             w_ref=None):
-        """w_ref: five reference values; state arrays then hold w - w_ref (see to_stored)."""
+             w_ref=None, nu_weight=None):
+        """w_ref: five reference values; state arrays then hold w - w_ref (see to_stored).
+        nu_weight: artificial-viscosity weights of the groups (rho, rho u, rho E), the adjoint
+        components of group g diffused with nu_g = lambda nu_weight[g] sigma_1 (None: 1, 1, 1)."""
         g = cls()
         for d in range(3):
             g.n[d] = int(n[d])
@@ -64,6 +67,8 @@ class Grid(ctypes.Structure):
         g.precision, g.ckpt_format = int(precision), int(ckpt_format)
         for v in range(5):
             g.w_ref[v] = 0.0 if w_ref is None else float(w_ref[v])
+        for k in range(3):
+            g.nu_weight[k] = 1.0 if nu_weight is None else float(nu_weight[k])
         return g
 
     def to_stored(self, w):

@@ -90,6 +90,9 @@ int check_grid(const adj_grid* g, bool need_dt) {
   if (need_dt && (!(g->dt > 0.0) || !std::isfinite(g->dt))) return fail(ADJ_EINVAL, "dt must be > 0");
   for (int v = 0; v < 5; ++v)
     if (!std::isfinite(g->w_ref[v])) return fail(ADJ_EINVAL, "w_ref[%d] must be finite", v);
+  for (int k = 0; k < 3; ++k)
+    if (!(g->nu_weight[k] >= 0.0) || !std::isfinite(g->nu_weight[k]))
+      return fail(ADJ_EINVAL, "nu_weight[%d] must be finite and >= 0", k);
   if (g->precision != ADJ_F64 && g->precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", g->precision);
   if (5 * (double)ncells(g) * (g->precision == ADJ_F64 ? 8.0 : 4.0) >= 4294967296.0)
     return fail(ADJ_ESHAPE, "state arrays must span less than 4 GiB (%lld cells)", ncells(g));
@@ -137,6 +140,10 @@ Consts<T> consts(const adj_grid* g) {
   c.alpha = (T)(g->gamma * g->mu / g->prandtl);
   c.dt = (T)g->dt;
   for (int v = 0; v < 5; ++v) c.wref[v] = (T)g->w_ref[v];
+  // per-component weight of the artificial viscosity: groups (rho), (rho u_1..3), (rho E)
+  const bool unit = g->nu_weight[0] == 0.0 && g->nu_weight[1] == 0.0 && g->nu_weight[2] == 0.0;
+  static constexpr int group[5] = {0, 1, 1, 1, 2};
+  for (int v = 0; v < 5; ++v) c.nuw[v] = unit ? T(1) : (T)g->nu_weight[group[v]];
   return c;
 }
 

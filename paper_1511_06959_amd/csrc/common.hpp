@@ -37,6 +37,7 @@ struct Consts {
   T dx[3], idx[3];       // cell size and its inverse
   T gamma, mu, alpha, dt;
   T wref[5];  // reference state: state arrays hold w - wref
+  T nuw[5];   // weight of the artificial viscosity on each adjoint component
 };
 
 // Buffer loads: a 128-bit resource (base, byte size) in scalar registers plus a 32-bit per-lane

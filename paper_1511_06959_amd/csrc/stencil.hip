@@ -619,6 +619,8 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
   T g[5] = {rh, T(0), T(0), T(0), T(0)};
   prim_to_cons(uc, e, ri, uh, eh, g);
   if (LNU) {
+    // L_nu k^ with the face nu the mean of its cells, weighted per component (variable group)
+    T lv[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
       const T i2 = c.idx[D] * c.idx[D];
@@ -628,9 +630,11 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
         const int q = side ? p + st[D] : p - st[D];
         const T nf = T(0.5) * (sm[LNU ? A_NU : 0][p] + sm[LNU ? A_NU : 0][q]) * i2;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) g[v] += nf * (sm[A_K0 + v][q] - sm[A_K0 + v][p]);
+        for (int v = 0; v < 5; ++v) lv[v] = fma(nf, sm[A_K0 + v][q] - sm[A_K0 + v][p], lv[v]);
       }
     }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) g[v] = fma(c.nuw[v], lv[v], g[v]);
   }
   if (MODE == STAGE_VJP) {
 #pragma unroll

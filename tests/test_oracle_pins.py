@@ -11,7 +11,10 @@ index or stencil coefficient, a transposed operand, a wrong RK4 weight) fails at
   Fourier symbol (J and J^T)     closed-form linearised operator at a uniform state
   RK4 polynomial                 one tangent step equals G(dt L) = 1 + Z + Z^2/2 + Z^3/6 + Z^4/24
   complex step                   dual-number tangent vs complex-step derivative of the primal
-  duality                        <w^_N, dw_N> = <w^_0, dw_0> + <g_s, ds> over whole windows
+  duality                        <w^_N, dw_N> = <w^_0, dw_0> + <g_s, ds> over whole windows,
+                                 also with one artificial viscosity per variable group
+  variable groups                nu_g acts on exactly the components of its group (rho; rho u;
+                                 rho E) and equals the single-viscosity operator there
   Taylor / finite differences    gradient of the time-averaged objective vs J(s + eps d)
   constant adjoint               J_R^T const = 0 (dual of conservation), L_nu const = 0
 """
@@ -224,7 +227,8 @@ def _duality_window(orc, g, w0, s, lam, nsteps, seed):
     return lhs, rhs
 
 
-@pytest.mark.parametrize("bc_x,lam", [(0, 0.0), (0, 0.01), (1, 0.0), (1, 0.01)])
+@pytest.mark.parametrize("bc_x,lam", [(0, 0.0), (0, 0.01), (1, 0.0), (1, 0.01), (0, (0.004, 0.01, 0.025)),
+                                      (1, (0.02, 0.0, 0.006))])
 def test_window_duality(orc, bc_x, lam):
     n = (6, 6, 4)
     g = _grid(orc, n, bc_x=bc_x, dt=0.02, mu=0.02)
@@ -334,3 +338,26 @@ def test_taylor_plane_loss_with_walls(orc):
     eps = 1e-4
     fd = (J(s0 + eps * d) - J(s0 - eps * d)) / (2 * eps)
     assert abs(fd - gs @ d) <= 1e-7 * abs(gs @ d)
+
+
+@pytest.mark.parametrize("bc_x", [0, 1])
+def test_group_viscosity_acts_on_its_components(orc, bc_x):
+    n = (6, 5, 4)
+    g = _grid(orc, n, bc_x=bc_x)
+    w = _smooth_state(n, 15)
+    q = np.random.default_rng(16).standard_normal(w.size)
+    lam = 0.03
+    one = orc.lnu_apply(g, lam * orc.sigma1(g, w), q).reshape(5, -1)  # one nu on every component
+    assert np.abs(one).max() > 0.0
+    total = np.zeros_like(one)
+    for grp, comps in ((0, [0]), (1, [1, 2, 3]), (2, [4])):
+        lv = [0.0, 0.0, 0.0]
+        lv[grp] = lam
+        out = orc.lnu_apply_groups(g, w, lv, q).reshape(5, -1)
+        for v in range(5):
+            if v in comps:
+                assert np.allclose(out[v], one[v], rtol=1e-14, atol=0.0), (grp, v)
+            else:
+                assert not out[v].any(), (grp, v)
+        total += out
+    assert np.allclose(total, orc.lnu_apply_groups(g, w, lam, q).reshape(5, -1), rtol=1e-14, atol=0.0)
