@@ -24,6 +24,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// block_sum for a work-group of NTH threads (a power of two)
+template <int NTH>
+__device__ __forceinline__ double block_sum_n(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+#pragma unroll
+  for (int o = NTH / 2; o > 0; o >>= 1) {
+    __syncthreads();
+    if (t < o) sh[t] += sh[t + o];
+  }
+  __syncthreads();
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
 inline int reduce_blocks(long long n) {
   long long b = (n + RB - 1) / RB;
   if (b > MAX_PARTIALS) b = MAX_PARTIALS;
@@ -433,12 +449,13 @@ __device__ __forceinline__ void tile_grad(const T (*su)[NB], int p, const int st
 }
 
 // Loads velocities of the box whose origin is (x0 - hx, y0 - hy, z0 - hy) into su.
-template <typename T, int HX, int HY>
+template <typename T, int KX, int KY, int KZ, int HX, int HY>
 __device__ __forceinline__ void load_box_u(const Consts<T>& c, const T* __restrict__ w, int x0, int y0, int z0,
-                                           T (*su)[Box<HX, HY>::NB]) {
-  using B = Box<HX, HY>;
+                                           T (*su)[TBox<KX, KY, KZ, HX, HY>::NB]) {
+  using B = TBox<KX, KY, KZ, HX, HY>;
+  constexpr int NTH = KX * KY * KZ;
   const long long N = c.N;
-  for (int b = threadIdx.x; b < B::NB; b += NT) {
+  for (int b = threadIdx.x; b < B::NB; b += NTH) {
     const int bx = b % B::BX, by = (b / B::BX) % B::BY, bz = b / (B::BX * B::BY);
     int mirror, real;
     const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - HX, y0 + by - HY, z0 + bz - HY, mirror, real);
@@ -452,18 +469,21 @@ __device__ __forceinline__ void load_box_u(const Consts<T>& c, const T* __restri
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_ked_tile(Consts<T> c, const T* __restrict__ w, double* __restrict__ partials) {
-  using B = Box<1, 1>;
+// One work-group of KX x KY x KZ threads per tile of as many cells.
+template <typename T, int KX, int KY, int KZ>
+__global__ __launch_bounds__(KX * KY * KZ) void k_ked_tile(Consts<T> c, const T* __restrict__ w,
+                                                           double* __restrict__ partials) {
+  constexpr int NTH = KX * KY * KZ;
+  using B = TBox<KX, KY, KZ, 1, 1>;
   __shared__ T su[3][B::NB];
-  __shared__ double sh[NT];
+  __shared__ double sh[NTH];
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   int x0, y0, z0;
-  tile_origin<TX, TY, TZ>(t, c.nx, c.ny, x0, y0, z0);
-  load_box_u<T, 1, 1>(c, w, x0, y0, z0, su);
+  tile_origin<KX, KY, KZ>(t, c.nx, c.ny, x0, y0, z0);
+  load_box_u<T, KX, KY, KZ, 1, 1>(c, w, x0, y0, z0, su);
   __syncthreads();
   const int tid = threadIdx.x;
-  const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
+  const int tx = tid % KX, ty = (tid / KX) % KY, tz = tid / (KX * KY);
   double phi = 0.0;
   if (x0 + tx < c.nx && y0 + ty < c.ny && z0 + tz < c.nz) {
     const int st[3] = {1, B::SY, B::SZ};
@@ -482,7 +502,7 @@ __global__ __launch_bounds__(NT) void k_ked_tile(Consts<T> c, const T* __restric
       }
     phi = (double)acc;
   }
-  const double tot = block_sum(phi, sh);
+  const double tot = block_sum_n<NTH>(phi, sh);
   if (tid == 0) partials[t] = tot;
 }
 
@@ -490,19 +510,20 @@ __global__ __launch_bounds__(NT) void k_ked_tile(Consts<T> c, const T* __restric
 // d Phi / d G_lk = 2 sigma_lk); a ghost cell beyond a slip wall owns no dissipation term (sigma = 0),
 // so the gather at the ghost image of a wall cell reduces to -+ sigma_xk(cell)/dx and is folded
 // back through the mirror.  Then to conservative variables via u = m / rho.
-template <typename T>
-__global__ __launch_bounds__(NT) void k_ked_grad_tile(Consts<T> c, const T* __restrict__ w, double wgt,
-                                                      T* __restrict__ djdw) {
-  using O = Box<2, 2>;
-  using I = Box<1, 1>;
+template <typename T, int KX, int KY, int KZ>
+__global__ __launch_bounds__(KX * KY * KZ) void k_ked_grad_tile(Consts<T> c, const T* __restrict__ w, double wgt,
+                                                                T* __restrict__ djdw) {
+  constexpr int NTH = KX * KY * KZ;
+  using O = TBox<KX, KY, KZ, 2, 2>;
+  using I = TBox<KX, KY, KZ, 1, 1>;
   __shared__ T su[3][O::NB];
   __shared__ T ss[6][I::NB];  // sigma xx, yy, zz, xy, xz, yz on the inner box
   int x0, y0, z0;
-  tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
-  load_box_u<T, 2, 2>(c, w, x0, y0, z0, su);
+  tile_origin<KX, KY, KZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
+  load_box_u<T, KX, KY, KZ, 2, 2>(c, w, x0, y0, z0, su);
   __syncthreads();
   const int sto[3] = {1, O::SY, O::SZ};
-  for (int b = threadIdx.x; b < I::NB; b += NT) {
+  for (int b = threadIdx.x; b < I::NB; b += NTH) {
     const int bx = b % I::BX, by = (b / I::BX) % I::BY, bz = b / (I::BX * I::BY);
     const int gx = x0 + bx - 1;
     const bool real = !c.wall || (gx >= 0 && gx < c.nx);
@@ -521,7 +542,7 @@ __global__ __launch_bounds__(NT) void k_ked_grad_tile(Consts<T> c, const T* __re
   }
   __syncthreads();
   const int tid = threadIdx.x;
-  const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
+  const int tx = tid % KX, ty = (tid / KX) % KY, tz = tid / (KX * KY);
   const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
   if (gx >= c.nx || gy >= c.ny || gz >= c.nz) return;
   const int sti[3] = {1, I::SY, I::SZ};
@@ -777,14 +798,20 @@ hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt
     if (J_accum)
       hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 1, J_accum, weight / (double)c.N, 1.0);
   } else if (kind == 2) {
-    const dim3 grid(((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY) * ((c.nz + TZ - 1) / TZ));
+    // tiles of 32x8x4 cells (FP32) / 32x4x4 (FP64): the halo-2 box of the gradient kernel then
+    // holds 3.4 / 4.5 cells per output cell instead of 5 for 16x4x4, within the shared memory of
+    // one work-group
+    constexpr int KX = 32, KY = sizeof(T) == 8 ? 4 : 8, KZ = 4;
+    const dim3 grid(((c.nx + KX - 1) / KX) * ((c.ny + KY - 1) / KY) * ((c.nz + KZ - 1) / KZ));
     if (J_accum) {
       const int nb = (int)grid.x;
-      // one partial per tile: the workspace partial region holds max(10 * MAX_PARTIALS, tiles) values
-      hipLaunchKernelGGL((k_ked_tile<T>), grid, dim3(NT), 0, st, c, w, partials);
+      // one partial per tile: the workspace partial region holds max(10 * MAX_PARTIALS, tiles of
+      // 16x4x4 cells) values
+      hipLaunchKernelGGL((k_ked_tile<T, KX, KY, KZ>), grid, dim3(KX * KY * KZ), 0, st, c, w, partials);
       hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, nb, 1, J_accum, weight / (double)c.N, 1.0);
     }
-    if (djdw) hipLaunchKernelGGL((k_ked_grad_tile<T>), grid, dim3(NT), 0, st, c, w, weight, djdw);
+    if (djdw)
+      hipLaunchKernelGGL((k_ked_grad_tile<T, KX, KY, KZ>), grid, dim3(KX * KY * KZ), 0, st, c, w, weight, djdw);
   } else if (kind == 3) {
     const long long nf = (long long)c.ny * c.nz;
     const int nb = reduce_blocks(nf);
