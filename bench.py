@@ -326,6 +326,9 @@ WORKLOADS = {
     "ensemble": "batched ensemble of 64 periodic decaying-turbulence boxes (sizes from {32,48,64,96}^3, Mach_rms "
                 "0.3, nu 0.0175), windows of 50-400 RK4 steps, lambda from {0,0.03,0.1,0.3,1} dx^2 sigma_1, "
                 "time-averaged mean pressure per box; one launch per RK stage covers every running box",
+    "lamest": "choice of lambda for decaying turbulence 128^3 periodic (Mach_rms 0.4, nu 2.887e-3): {n}-step window, "
+              "6 candidate scales {{0,0.01,0.03,0.1,0.3,1}} dx^2 swept backward together as one batched ensemble "
+              "from a white-noise terminal adjoint, adjoint energy after every reverse step",
 }
 
 
@@ -368,6 +371,9 @@ def main():
     adj.lib()
     if args.workload == "ensemble":
         main_ensemble(args)
+        return
+    if args.workload == "lamest":
+        main_lamest(args)
         return
     wl = make_workload(args.workload, args.window)
     big = args.workload != "tgv64"
@@ -511,6 +517,76 @@ def main_ensemble(args):
         "eager_ms_per_step": r["eager_ms_per_step"],
         "launch": "the ensemble window replayed as two captured HIP graphs (forward sweep, reverse sweep)",
         "tiles": r["tiles"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def main_lamest(args):
+    """The batched reverse sweeps of the lambda estimate (paper_1511_06959_amd.lamest): one
+    ensemble of 6 members over one stored 128^3 window, timed per sweep; value = member
+    cell-steps per second of the sweep."""
+    import torch
+
+    import paper_1511_06959_amd as adj
+    import workloads as W
+    from paper_1511_06959_amd import autotune, lamest
+
+    T = args.window or 50
+    wl = W.turbulence(128, mach_rms=0.4, nu=2.887e-3, seed=4, nsteps=T)
+    ref = adj.reference_state(wl.w0)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F32, w_ref=ref)
+    tiles = {}
+    if not args.no_autotune:
+        tiles = _tile_report(autotune.tune(g), g, True)
+    factors = [0.0, 0.01, 0.03, 0.1, 0.3, 1.0]
+    dx2 = (wl.L[0] / 128) ** 2
+    lams = [f * dx2 for f in factors]
+    aT = np.random.default_rng(0).standard_normal(5 * g.ncells)
+    print(f"[bench] lamest: 128^3, {T} steps, {len(factors)} candidates", file=sys.stderr, flush=True)
+    sw = lamest.EnergySweeps(g, g.to_stored(wl.w0), None, T, "cuda")
+    for _ in range(args.warmup):
+        sw.energies(lams, aT)
+    adj.profile_enable(True)
+    Es = sw.energies(lams, aT)
+    torch.cuda.synchronize()
+    adj.profile_enable(False)
+    ms, n = adj.profile_read(adj.PROF_ADJOINT_STAGE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Es = sw.energies(lams, aT)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    rates = [lamest.growth_rate(E, g.dt) for E in Es]
+    k = lamest.choose(factors, rates, [True] * len(factors), 0.0)
+    cells = g.ncells * len(factors) * T
+    avg_s = ms / n / 1e3
+    alg = VALUES_PER_STAGE_LAUNCH * 4 * g.ncells * len(factors)
+    print(f"[bench] lamest sweep {sec * 1e3:.1f} ms, chosen factor {factors[k] if k is not None else None}",
+          file=sys.stderr, flush=True)
+    line = {
+        "metric": METRIC,
+        "value": cells / sec,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["lamest"].format(n=T), "cells": g.ncells, "members": len(factors),
+                   "window_steps": T, "step": "the batched homogeneous reverse sweep of all candidates over the "
+                   "stored window (one estimate without refinement)"},
+        "roofline": {"bound": "hbm", "achieved": alg / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_adjoint_stage_batch (reverse-stage gather over all members)",
+                     "avg_launch_us": avg_s * 1e6},
+        "estimate": {"factors": factors, "growth_rates": rates,
+                     "chosen_factor": factors[k] if k is not None else None},
+        "tiles": tiles,
     }
     print(json.dumps(line), flush=True)
 

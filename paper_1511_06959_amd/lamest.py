@@ -80,7 +80,7 @@ class Estimate:
     lam_max: float = None          # the RK4 diffusion bound of lambda on this window
 
 
-class _Sweeps:
+class EnergySweeps:
     """The stored window of one box and batched homogeneous reverse sweeps over it."""
 
     def __init__(self, g, w0, s, nsteps, device):
@@ -126,7 +126,7 @@ def estimate_lambda(g, w0, s, nsteps, factors=(0.0, 0.01, 0.03, 0.1, 0.3, 1.0), 
     dx2 = min(g.L[d] / g.n[d] for d in range(3)) ** 2
     if aT is None:
         aT = np.random.default_rng(seed).standard_normal(5 * g.ncells)
-    sw = _Sweeps(g, w0, s, nsteps, device)
+    sw = EnergySweeps(g, w0, s, nsteps, device)
     # sigma_1 at the first and last state of the window bounds the candidates
     sig = torch.empty(g.ncells, dtype=g.dtype, device=device)
     smax = 0.0
