@@ -326,6 +326,10 @@ WORKLOADS = {
     "ensemble": "batched ensemble of 64 periodic decaying-turbulence boxes (sizes from {32,48,64,96}^3, Mach_rms "
                 "0.3, nu 0.0175), windows of 50-400 RK4 steps, lambda from {0,0.03,0.1,0.3,1} dx^2 sigma_1, "
                 "time-averaged mean pressure per box; one launch per RK stage covers every running box",
+    "offload": "decaying turbulence 384^3 periodic (Mach_rms 0.4, nu 2.887e-3), {n}-step window sample, lambda 0.1 "
+               "dx^2 sigma_1, mean pressure; the window's BF16 records kept in pinned host memory and streamed "
+               "over PCIe (device-to-host after each primal step, host-to-device one step ahead of the reverse "
+               "sweep), against the same sweeps with the records in HBM",
     "lamest": "choice of lambda for decaying turbulence 128^3 periodic (Mach_rms 0.4, nu 2.887e-3): {n}-step window, "
               "6 candidate scales {{0,0.01,0.03,0.1,0.3,1}} dx^2 swept backward together as one batched ensemble "
               "from a white-noise terminal adjoint, adjoint energy after every reverse step",
@@ -374,6 +378,9 @@ def main():
         return
     if args.workload == "lamest":
         main_lamest(args)
+        return
+    if args.workload == "offload":
+        main_offload(args)
         return
     wl = make_workload(args.workload, args.window)
     big = args.workload != "tgv64"
@@ -586,6 +593,84 @@ def main_lamest(args):
                      "avg_launch_us": avg_s * 1e6},
         "estimate": {"factors": factors, "growth_rates": rates,
                      "chosen_factor": factors[k] if k is not None else None},
+        "tiles": tiles,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def main_offload(args):
+    """Eager windows with the trajectory in pinned host memory (offload) and in HBM (sweep);
+    value = cell-steps/s of the host-memory window, PCIe transfers included."""
+    import torch
+
+    import paper_1511_06959_amd as adj
+    import workloads as W
+    from paper_1511_06959_amd import autotune, offload, sweep
+
+    wl = make_workload("turb384", args.window)
+    T = wl.nsteps
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F32, adj.CKPT_BF16,
+                      adj.reference_state(wl.w0))
+    tiles = _tile_report(autotune.tune(g), g, True) if not args.no_autotune else {}
+    obj = adj.Objective.make(wl.obj_kind, wl.plane_i, wl.pt_ref)
+    w0 = torch.from_numpy(g.to_stored(wl.w0)).to("cuda", torch.float32)
+    s = torch.from_numpy(wl.s).to("cuda", torch.float32)
+    ws = adj.workspace(g)
+    ht = offload.HostTrajectory(g, T)
+    hh = offload.HostTrajectory(g, T, device_tail=(T + 1) // 2)
+    traj = sweep.Trajectory(g, T)
+
+    def timed(fwd, bwd):
+        out = []
+        for k in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fwd()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            bwd()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if k >= args.warmup:
+                out.append((t1 - t0, t2 - t1))
+        f = sum(x for x, _ in out) / len(out)
+        b = sum(y for _, y in out) / len(out)
+        return f, b
+
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fh, bh = timed(lambda: offload.forward(g, w0, s, T, obj, wl.weights, ws, traj=ht, J=J.zero_()),
+                   lambda: offload.backward(g, ht, s, obj, wl.weights, wl.lam, ws))
+    ft, bt = timed(lambda: offload.forward(g, w0, s, T, obj, wl.weights, ws, traj=hh, J=J.zero_()),
+                   lambda: offload.backward(g, hh, s, obj, wl.weights, wl.lam, ws))
+    fd, bd = timed(lambda: sweep.forward(g, w0, s, T, obj, wl.weights, ws, traj=traj, J=J.zero_()),
+                   lambda: sweep.backward(g, traj, s, obj, wl.weights, wl.lam, ws))
+    cells = g.ncells * T
+    rec_gb = ht.rec_len / 1e9
+    print(f"[bench] offload window {1e3 * (fh + bh):.1f} ms (HBM {1e3 * (fd + bd):.1f} ms)", file=sys.stderr,
+          flush=True)
+    line = {
+        "metric": METRIC,
+        "value": cells / (fh + bh),
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * (fh + bh),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["offload"].format(n=T), "cells": g.ncells, "window_steps": T,
+                   "step": "one whole eager window: forward sweep + reverse sweep",
+                   "record_gb": rec_gb, "host_trajectory_gb": ht.nbytes / 1e9},
+        "pcie_inclusive": True,
+        "forward_ms": 1e3 * fh, "reverse_ms": 1e3 * bh,
+        "half_in_hbm": {"device_tail": hh.tail, "value": cells / (ft + bt), "ms_per_step": 1e3 * (ft + bt),
+                        "forward_ms": 1e3 * ft, "reverse_ms": 1e3 * bt},
+        "hbm_trajectory": {"value": cells / (fd + bd), "ms_per_step": 1e3 * (fd + bd), "forward_ms": 1e3 * fd,
+                           "reverse_ms": 1e3 * bd},
+        "host_copy_gbs": {"device_to_host": (T + 1) * rec_gb / fh, "host_to_device": (T + 1) * rec_gb / bh},
         "tiles": tiles,
     }
     print(json.dumps(line), flush=True)
