@@ -224,6 +224,28 @@ int adj_get_tile(int kernel_class, int precision);
  * runs as ADJ_TILE_16x4x4 instead.  Returns the tile id or a negative status. */
 int adj_tile_launched(int kernel_class, int precision, int bc_x, int lnu, int tile);
 
+/* Explicit stability of a step from state w, three numbers written to out (device FP64[3]):
+ *   out[0] = dt max_cells sum_d (|u_d| + c)/dx_d                       convective
+ *   out[1] = dt max_cells max(4 mu/3, alpha)/rho sum_d 4/dx_d^2         viscous and heat conduction
+ *   out[2] = dt lambda max_g w_g max_cells sigma_1 sum_d 4/dx_d^2       artificial viscosity
+ * (w_g: grid->nu_weight).  The central scheme's convective eigenvalues lie on the imaginary axis
+ * and its diffusive ones on the negative real axis; classical RK4 is stable there for |z| up to
+ * ADJ_RK4_IMAG_BOUND and ADJ_RK4_REAL_BOUND.  Each number bounds its part of the spectrum alone
+ * (a necessary condition)  [Numerical methods: explicit Runge-Kutta time marching].  Uses the
+ * workspace; asynchronous. */
+#define ADJ_RK4_IMAG_BOUND 2.8284
+#define ADJ_RK4_REAL_BOUND 2.7853
+int adj_stability(const adj_grid* grid, const void* w, double lambda, double* out, void* ws, size_t ws_bytes,
+                  void* stream);
+/* adj_stability, then waits for the stream: ADJ_EUNSTABLE when a number exceeds its bound,
+ * ADJ_OK otherwise; out_host (NULL or host FP64[3]) receives the numbers. */
+int adj_check_stable(const adj_grid* grid, const void* w, double lambda, double* out_host, void* ws,
+                     size_t ws_bytes, void* stream);
+/* Waits for the stream, then ADJ_ENONFINITE when a reduction on the current device (J, E_v^, inner
+ * products, plane sums) produced NaN or Inf since the previous call, ADJ_OK otherwise; clears the
+ * indication. */
+int adj_check_status(void* stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Ensembles: many independent boxes (each its own adj_grid: size, dt, viscosity) and many adjoint
  * sweeps ("members") in one launch per RK stage, the batched form of the calls above.  A member

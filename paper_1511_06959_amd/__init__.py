@@ -117,7 +117,7 @@ EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjo
            "adj_adjoint_step_stages", "adj_growth_sigma1",
            "adj_objective_and_grad", "adj_energy_vhat", "adj_dot", "adj_ckpt_encode", "adj_ckpt_decode",
            "adj_residual", "adj_vjp", "adj_profile_enable", "adj_profile_read", "adj_set_tile", "adj_get_tile",
-           "adj_tile_launched", "adj_batch_table_bytes", "adj_batch_create", "adj_batch_destroy", "adj_batch_offset",
+           "adj_tile_launched", "adj_stability", "adj_check_stable", "adj_check_status", "adj_batch_table_bytes", "adj_batch_create", "adj_batch_destroy", "adj_batch_offset",
            "adj_batch_workspace_bytes", "adj_batch_primal_step", "adj_batch_adjoint_step",
            "adj_batch_objective_and_grad", "adj_batch_energy_vhat",
            "adj_last_error", "adj_version")
@@ -154,6 +154,9 @@ def lib():
         "adj_set_tile": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "adj_get_tile": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "adj_tile_launched": ([ctypes.c_int] * 5, ctypes.c_int),
+        "adj_stability": ([gp, vp, dbl, vp, vp, sz, vp], ctypes.c_int),
+        "adj_check_stable": ([gp, vp, dbl, ctypes.POINTER(dbl), vp, sz, vp], ctypes.c_int),
+        "adj_check_status": ([vp], ctypes.c_int),
         "adj_batch_table_bytes": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], sz),
         "adj_batch_create": ([ctypes.POINTER(vp), ctypes.c_int, gp, op, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                               ctypes.POINTER(dbl), vp, sz], ctypes.c_int),
@@ -282,6 +285,32 @@ def energy_vhat(g, w, wh, E, ws):
     wp, wb = _ws(ws)
     _check(lib().adj_energy_vhat(ctypes.byref(g), _state(g, w), _state(g, wh), _ptr(E, torch.float64), wp, wb,
                                  _stream()))
+
+
+RK4_IMAG_BOUND, RK4_REAL_BOUND = 2.8284, 2.7853
+
+
+def stability(g, w, out, ws, lam=0.0):
+    """Explicit-stability numbers (convective, viscous, artificial viscosity) of a step from w
+    into out (device FP64[3]); bounds RK4_IMAG_BOUND, RK4_REAL_BOUND, RK4_REAL_BOUND."""
+    wp, wb = _ws(ws)
+    _check(lib().adj_stability(ctypes.byref(g), _state(g, w), float(lam), _ptr(out, torch.float64), wp, wb,
+                               _stream()))
+
+
+def check_stable(g, w, ws, lam=0.0):
+    """Waits for the stream; raises AdjError (ADJ_EUNSTABLE) when a number exceeds its bound,
+    else returns the three numbers."""
+    h = (ctypes.c_double * 3)()
+    wp, wb = _ws(ws)
+    _check(lib().adj_check_stable(ctypes.byref(g), _state(g, w), float(lam), h, wp, wb, _stream()))
+    return tuple(h)
+
+
+def check_status():
+    """Waits for the stream; raises AdjError (ADJ_ENONFINITE) when a reduction produced NaN or Inf
+    since the previous check (the indication is cleared)."""
+    _check(lib().adj_check_status(_stream()))
 
 
 def dot(g, a, b, out, ws):

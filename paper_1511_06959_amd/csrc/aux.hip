@@ -46,6 +46,14 @@ inline int reduce_blocks(long long n) {
   return (int)(b < 1 ? 1 : b);
 }
 
+// Set (never cleared by a kernel) when a reduction's result is NaN or Inf; per device, zero when
+// the library is loaded; read and cleared by read_clear_nonfinite (adj_check_status).
+__device__ unsigned int g_nonfinite = 0;
+
+__device__ __forceinline__ void note_nonfinite(double x) {
+  if (!isfinite(x)) __hip_atomic_fetch_or(&g_nonfinite, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // partials has `nsets` consecutive arrays of `nblk` values; dst[s] = beta dst[s] + alpha[s] sum_s
 __global__ __launch_bounds__(RB) void k_fold(const double* __restrict__ partials, int nblk, int nsets,
                                              double* __restrict__ dst, double alpha, double beta) {
@@ -54,7 +62,10 @@ __global__ __launch_bounds__(RB) void k_fold(const double* __restrict__ partials
     double v = 0.0;
     for (int i = threadIdx.x; i < nblk; i += RB) v += partials[s * nblk + i];
     const double tot = block_sum(v, sh);
-    if (threadIdx.x == 0) dst[s] = beta * dst[s] + alpha * tot;
+    if (threadIdx.x == 0) {
+      dst[s] = beta * dst[s] + alpha * tot;
+      note_nonfinite(dst[s]);
+    }
   }
 }
 
@@ -435,6 +446,7 @@ __global__ __launch_bounds__(RB) void k_fold_members(const double* __restrict__ 
       dst[m] = dst[m] + (wgt[m] / (double)c.N) * tot;
     else
       dst[m] = (1.0 / ((double)c.dx[0] * (double)c.dx[1] * (double)c.dx[2])) * tot;
+    note_nonfinite(dst[m]);
   }
 }
 
@@ -654,7 +666,10 @@ __global__ __launch_bounds__(RB) void k_ptloss_partial(Consts<T> c, const T* __r
 
 // scratch[0] = num, scratch[1] = den (already folded); J_accum += wgt num/(den pt_ref)
 __global__ void k_ptloss_value(const double* __restrict__ scratch, double pt_ref, double wgt, double* J_accum) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *J_accum += wgt * scratch[0] / (scratch[1] * pt_ref);
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *J_accum += wgt * scratch[0] / (scratch[1] * pt_ref);
+    note_nonfinite(*J_accum);
+  }
 }
 
 // dj/dw_L = dj/dw_R = 0.5 (dnum_f - (num/den) dden_f) / (den pt_ref)
@@ -871,7 +886,86 @@ hipError_t launch_energy_batch(const BoxDesc<T>* mems, const int* start, const i
   return hipGetLastError();
 }
 
+// Per-block maxima of the explicit-stability rates of a state: convective
+// sum_d (|u_d| + c)/dx_d and viscous max(4/3, gamma/Pr) (mu/rho) sum_d 4/dx_d^2; set 2 of the
+// partials takes the maximum of x (the sigma_1 field) when given.
+template <typename T>
+__global__ __launch_bounds__(RB) void k_stab_partial(Consts<T> c, const T* __restrict__ w, const T* __restrict__ x,
+                                                     double* __restrict__ partials) {
+  __shared__ double sh[3][RB];
+  const long long N = c.N;
+  double cv = 0.0, vv = 0.0, xv = 0.0;
+  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < N; i += (long long)gridDim.x * RB) {
+    const double r = (double)w[i] + (double)c.wref[0];
+    const double u[3] = {((double)w[N + i] + (double)c.wref[1]) / r, ((double)w[2 * N + i] + (double)c.wref[2]) / r,
+                         ((double)w[3 * N + i] + (double)c.wref[3]) / r};
+    const double g = (double)c.gamma;
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double p = (g - 1.0) * (((double)w[4 * N + i] + (double)c.wref[4]) - 0.5 * r * usq);
+    const double snd = sqrt(fmax(g * p / r, 0.0));
+    double s4 = 0.0, ci = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double h = (double)c.idx[d];
+      ci += (fabs(u[d]) + snd) * h;
+      s4 += 4.0 * h * h;
+    }
+    cv = fmax(cv, ci);
+    // largest diffusivity: (4/3) mu / rho (normal stress) or alpha / rho = gamma mu / (Pr rho) (heat)
+    vv = fmax(vv, fmax(4.0 / 3.0 * (double)c.mu, (double)c.alpha) / r * s4);
+    if (x) xv = fmax(xv, (double)x[i]);
+  }
+  sh[0][threadIdx.x] = cv;
+  sh[1][threadIdx.x] = vv;
+  sh[2][threadIdx.x] = xv;
+  for (int o = RB / 2; o > 0; o >>= 1) {
+    __syncthreads();
+    if (threadIdx.x < o)
+      for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + o]);
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) partials[k * gridDim.x + blockIdx.x] = sh[k][0];
+}
+
+// dst[k] = scale[k] * max over the nblk partials of set k, k = 0, 1, 2
+__global__ __launch_bounds__(RB) void k_fold_max(const double* __restrict__ partials, int nblk, double s0, double s1,
+                                                 double s2, double* __restrict__ dst) {
+  __shared__ double sh[RB];
+  const double sc[3] = {s0, s1, s2};
+  for (int k = 0; k < 3; ++k) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += RB) v = fmax(v, partials[k * nblk + i]);
+    sh[threadIdx.x] = v;
+    for (int o = RB / 2; o > 0; o >>= 1) {
+      __syncthreads();
+      if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) dst[k] = sc[k] * sh[0];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_stability(const Consts<T>& c, const T* w, const T* sigma1, double s_conv, double s_visc,
+                            double s_art, double* partials, double* dst, hipStream_t st) {
+  const int nb = reduce_blocks(c.N);
+  hipLaunchKernelGGL((k_stab_partial<T>), dim3(nb), dim3(RB), 0, st, c, w, sigma1, partials);
+  hipLaunchKernelGGL(k_fold_max, dim3(1), dim3(RB), 0, st, partials, nb, s_conv, s_visc, s_art, dst);
+  return hipGetLastError();
+}
+
+hipError_t read_clear_nonfinite(unsigned int* flag) {
+  hipError_t e;
+  if ((e = hipMemcpyFromSymbol(flag, HIP_SYMBOL(g_nonfinite), sizeof(unsigned int), 0, hipMemcpyDeviceToHost)))
+    return e;
+  const unsigned int zero = 0;
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_nonfinite), &zero, sizeof(unsigned int), 0, hipMemcpyHostToDevice);
+}
+
 #define ADJNS_INST(T)                                                                                          \
+  template hipError_t launch_stability<T>(const Consts<T>&, const T*, const T*, double, double, double, double*, \
+                                          double*, hipStream_t);                                               \
   template hipError_t launch_sigma1<T>(const Consts<T>&, const T*, T, T*, hipStream_t);                        \
   template hipError_t launch_dot<T>(const Consts<T>&, const T*, const T*, double*, double*, double, double,    \
                                     hipStream_t);                                                              \

@@ -1,5 +1,6 @@
 // capi.hip -- the C ABI declared in include/adjns.h: host-side validation, workspace layout and
 // the launch sequences of one primal step and one reverse step.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -325,6 +326,67 @@ int adj_growth_sigma1(const adj_grid* grid, const void* w, double scale, void* o
   else
     e = launch_sigma1<float>(consts<float>(grid), (const float*)w, (float)scale, (float*)out, st);
   return e ? hip_fail(e, "sigma_1") : ADJ_OK;
+}
+
+int adj_stability(const adj_grid* grid, const void* w, double lambda, double* out, void* ws, size_t ws_bytes,
+                  void* stream) {
+  int r;
+  if ((r = check_grid(grid, true))) return r;
+  if ((r = check_ws(grid, ws, ws_bytes))) return r;
+  if (!w || !out) return fail(ADJ_EINVAL, "w and out must be non-NULL");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(ADJ_EINVAL, "lambda must be finite and >= 0");
+  const WsLayout L = layout(grid);
+  hipStream_t st = (hipStream_t)stream;
+  double s4 = 0.0;
+  for (int d = 0; d < 3; ++d) s4 += 4.0 * (grid->n[d] / grid->L[d]) * (grid->n[d] / grid->L[d]);
+  const bool unit = grid->nu_weight[0] == 0.0 && grid->nu_weight[1] == 0.0 && grid->nu_weight[2] == 0.0;
+  const double wmax = unit ? 1.0 : std::max(grid->nu_weight[0], std::max(grid->nu_weight[1], grid->nu_weight[2]));
+  const double s_art = grid->dt * lambda * wmax * s4;
+  hipError_t e;
+  if (grid->precision == ADJ_F64) {
+    const Consts<double> c = consts<double>(grid);
+    double* sig = (double*)at(ws, L.nu);
+    if (lambda > 0.0 && (e = launch_sigma1<double>(c, (const double*)w, 1.0, sig, st))) return hip_fail(e, "sigma_1");
+    e = launch_stability<double>(c, (const double*)w, lambda > 0.0 ? sig : nullptr, grid->dt, grid->dt, s_art,
+                                 (double*)at(ws, L.partials), out, st);
+  } else {
+    const Consts<float> c = consts<float>(grid);
+    float* sig = (float*)at(ws, L.nu);
+    if (lambda > 0.0 && (e = launch_sigma1<float>(c, (const float*)w, 1.0f, sig, st))) return hip_fail(e, "sigma_1");
+    e = launch_stability<float>(c, (const float*)w, lambda > 0.0 ? sig : nullptr, grid->dt, grid->dt, s_art,
+                                (double*)at(ws, L.partials), out, st);
+  }
+  return e ? hip_fail(e, "stability") : ADJ_OK;
+}
+
+int adj_check_stable(const adj_grid* grid, const void* w, double lambda, double* out_host, void* ws,
+                     size_t ws_bytes, void* stream) {
+  int r;
+  if ((r = check_grid(grid, true))) return r;
+  if ((r = check_ws(grid, ws, ws_bytes))) return r;
+  double* dev = (double*)at(ws, layout(grid).scratch);
+  if ((r = adj_stability(grid, w, lambda, dev, ws, ws_bytes, stream))) return r;
+  double h[3];
+  hipError_t e;
+  if ((e = hipMemcpyAsync(h, dev, sizeof h, hipMemcpyDeviceToHost, (hipStream_t)stream)) ||
+      (e = hipStreamSynchronize((hipStream_t)stream)))
+    return hip_fail(e, "stability read-back");
+  if (out_host) std::memcpy(out_host, h, sizeof h);
+  const double bound[3] = {ADJ_RK4_IMAG_BOUND, ADJ_RK4_REAL_BOUND, ADJ_RK4_REAL_BOUND};
+  const char* what[3] = {"convective", "viscous", "artificial-viscosity"};
+  for (int k = 0; k < 3; ++k)
+    if (!(h[k] <= bound[k]))
+      return fail(ADJ_EUNSTABLE, "%s stability number %.4g exceeds the RK4 bound %.4g", what[k], h[k], bound[k]);
+  return ADJ_OK;
+}
+
+int adj_check_status(void* stream) {
+  hipError_t e;
+  if ((e = hipStreamSynchronize((hipStream_t)stream))) return hip_fail(e, "status: stream");
+  unsigned int flag = 0;
+  if ((e = read_clear_nonfinite(&flag))) return hip_fail(e, "status: flag");
+  if (flag) return fail(ADJ_ENONFINITE, "a reduction met NaN or Inf since the last status check");
+  return ADJ_OK;
 }
 
 int adj_objective_and_grad(const adj_grid* grid, const adj_objective* obj, const void* w, double weight,

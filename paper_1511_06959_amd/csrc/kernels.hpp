@@ -28,6 +28,15 @@ hipError_t launch_dot(const Consts<T>& c, const T* a, const T* b, double* partia
 template <typename T>
 hipError_t launch_energy_vhat(const Consts<T>& c, const T* w, const T* wh, double* partials, double* dst,
                               hipStream_t st);
+// dst[0..2] = (s_conv, s_visc, s_art) x the maxima over cells of the convective rate
+// sum_d (|u_d| + c)/dx_d, the viscous rate max(4/3, gamma/Pr)(mu/rho) sum_d 4/dx_d^2 and sigma1
+// (sigma1 may be NULL: 0); partials holds 3 MAX_PARTIALS values
+template <typename T>
+hipError_t launch_stability(const Consts<T>& c, const T* w, const T* sigma1, double s_conv, double s_visc,
+                            double s_art, double* partials, double* dst, hipStream_t st);
+// copies the device's non-finite indication of the reductions to *flag and clears it (synchronous)
+hipError_t read_clear_nonfinite(unsigned int* flag);
+
 // objective kinds follow adjns.h; scratch holds 4 doubles of intermediate plane sums
 template <typename T>
 hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt_ref, const T* w, double weight,

@@ -175,3 +175,16 @@ def test_tile_launched():
         adj.tile_launched(A, adj.F64, 3, False, 0)
     with pytest.raises(adj.AdjError):
         adj.tile_launched(A, adj.F64, adj.BC_PERIODIC, False, len(adj.TILES))
+
+
+def test_stability_argument_errors():
+    L = adj.lib()
+    g = _grid()
+    fake = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
+    wsp = ctypes.c_void_p(1 << 20)
+    nb = ctypes.c_size_t(1 << 30)
+    assert L.adj_stability(ctypes.byref(g), None, ctypes.c_double(0.0), fake, wsp, nb, None) == -1
+    assert L.adj_stability(ctypes.byref(g), fake, ctypes.c_double(-1.0), fake, wsp, nb, None) == -1
+    assert L.adj_stability(ctypes.byref(g), fake, ctypes.c_double(0.0), fake, None, nb, None) == -6
+    bad = _grid(dt=0.0)
+    assert L.adj_check_stable(ctypes.byref(bad), fake, ctypes.c_double(0.0), None, wsp, nb, None) == -1
