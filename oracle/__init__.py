@@ -28,6 +28,7 @@ class OrcGrid(ctypes.Structure):
         ("prandtl", ctypes.c_double),
         ("mu", ctypes.c_double),
         ("dt", ctypes.c_double),
+        ("scheme", ctypes.c_int32),
     ]
 
 
@@ -97,20 +98,25 @@ def num_threads():
 
 
 # ---------------------------------------------------------------------------------------------
-def make_grid(n, L, gamma=1.4, prandtl=0.72, mu=0.01, dt=0.0, bc_x=0):
+SCHEME_RK4, SCHEME_SSPRK3 = 0, 1
+
+
+def make_grid(n, L, gamma=1.4, prandtl=0.72, mu=0.01, dt=0.0, bc_x=0, scheme=SCHEME_RK4):
+    """scheme: time marching, SCHEME_RK4 (classical RK4) or SCHEME_SSPRK3 (Shu-Osher SSP-RK3)."""
     g = OrcGrid()
     for d in range(3):
         g.n[d] = int(n[d])
         g.L[d] = float(L[d])
     g.bc_x = int(bc_x)
     g.gamma, g.prandtl, g.mu, g.dt = float(gamma), float(prandtl), float(mu), float(dt)
+    g.scheme = int(scheme)
     return g
 
 
 def grid_from(p):
-    """Oracle grid from a plain parameter mapping (keys n, L, gamma, prandtl, mu, dt, bc_x)."""
+    """Oracle grid from a plain parameter mapping (keys n, L, gamma, prandtl, mu, dt, bc_x[, scheme])."""
     return make_grid(p["n"], p["L"], p.get("gamma", 1.4), p.get("prandtl", 0.72), p["mu"],
-                     p.get("dt", 0.0), p.get("bc_x", 0))
+                     p.get("dt", 0.0), p.get("bc_x", 0), p.get("scheme", SCHEME_RK4))
 
 
 def make_obj(kind=0, plane_i=0, pt_ref=0.0):

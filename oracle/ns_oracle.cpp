@@ -58,6 +58,7 @@ typedef struct orc_grid {
   int32_t bc_x;  // 0: periodic in x, 1: slip walls at x = 0 and x = L_x
   double L[3];
   double gamma, prandtl, mu, dt;
+  int32_t scheme;  // time marching: 0 classical RK4, 1 strong-stability-preserving RK3
 } orc_grid;
 
 typedef struct orc_obj {
@@ -118,12 +119,13 @@ using std::pow;
 struct G {
   long nx, ny, nz, N;
   double dx[3];
-  int wall;
+  int wall, scheme;
   double gamma, pr, mu, alpha, dt;
   explicit G(const orc_grid* g) {
     nx = g->n[0]; ny = g->n[1]; nz = g->n[2]; N = nx * ny * nz;
     for (int d = 0; d < 3; ++d) dx[d] = g->L[d] / (double)g->n[d];
     wall = g->bc_x;
+    scheme = g->scheme;
     gamma = g->gamma; pr = g->prandtl; mu = g->mu; dt = g->dt;
     alpha = gamma * mu / pr;  // heat flux alpha grad e == (mu c_p / Pr) grad T, since e = c_v T
   }
@@ -634,6 +636,42 @@ void rk4_step(const G& g, const T* w, const T* s, T* wn) {
     wn[x] = w[x] + (g.dt / 6.0) * (k1[x] + 2.0 * k2[x] + 2.0 * k3[x] + k4[x]);
 }
 
+// Strong-stability-preserving third-order Runge-Kutta step in Shu-Osher form [Numerical methods]:
+//   u1 = w + dt R(w);  u2 = 3/4 w + 1/4 (u1 + dt R(u1));  w_next = 1/3 w + 2/3 (u2 + dt R(u2)).
+template <class T>
+void ssprk3_step(const G& g, const T* w, const T* s, T* wn) {
+  const long M = 5 * g.N;
+  std::vector<T> k(M), u1(M), u2(M);
+  residual<T>(g, w, s, k.data());
+  for (long x = 0; x < M; ++x) u1[x] = w[x] + g.dt * k[x];
+  residual<T>(g, u1.data(), s, k.data());
+  for (long x = 0; x < M; ++x) u2[x] = 0.75 * w[x] + 0.25 * (u1[x] + g.dt * k[x]);
+  residual<T>(g, u2.data(), s, k.data());
+  for (long x = 0; x < M; ++x) wn[x] = (1.0 / 3.0) * w[x] + (2.0 / 3.0) * (u2[x] + g.dt * k[x]);
+}
+
+// One step of the grid's time scheme.
+template <class T>
+void time_step(const G& g, const T* w, const T* s, T* wn) {
+  if (g.scheme == 1)
+    ssprk3_step<T>(g, w, s, wn);
+  else
+    rk4_step<T>(g, w, s, wn);
+}
+
+// The SSP-RK3 stage states u0 = w, u1, u2 of one step.
+void ssprk3_stage_states(const G& g, const double* w, const double* s, std::vector<double> U[3]) {
+  const long M = 5 * g.N;
+  std::vector<double> k(M);
+  U[0].assign(w, w + M);
+  residual<double>(g, w, s, k.data());
+  U[1].resize(M);
+  for (long x = 0; x < M; ++x) U[1][x] = w[x] + g.dt * k[x];
+  residual<double>(g, U[1].data(), s, k.data());
+  U[2].resize(M);
+  for (long x = 0; x < M; ++x) U[2][x] = 0.75 * w[x] + 0.25 * (U[1][x] + g.dt * k[x]);
+}
+
 // The four RK4 stage states W1 = w, W2, W3, W4 of one step.
 void rk4_stage_states(const G& g, const double* w, const double* s, std::vector<double> Ws[4]) {
   const long M = 5 * g.N;
@@ -661,6 +699,7 @@ static int check(const orc_grid* g) {
   for (int d = 0; d < 3; ++d)
     if (g->n[d] < 1 || !(g->L[d] > 0)) return -1;
   if (g->bc_x == 1 && g->n[0] < 2) return -1;
+  if (g->scheme != 0 && g->scheme != 1) return -1;
   return 0;
 }
 
@@ -697,11 +736,11 @@ int orc_lnu_apply(const orc_grid* gr, const double* nu, const double* q, double*
   return 0;
 }
 
-// w_next = RK4 step of w with source s (s may be NULL)
+// w_next = one step (RK4 or SSP-RK3) of w with source s (s may be NULL)
 int orc_primal_step(const orc_grid* gr, const double* w, const double* s, double* wn) {
   if (check(gr)) return -1;
   G g(gr);
-  rk4_step<double>(g, w, s, wn);
+  time_step<double>(g, w, s, wn);
   return 0;
 }
 
@@ -716,7 +755,7 @@ int orc_primal_step_complex(const orc_grid* gr, const double* w_re, const double
     w[x] = {w_re[x], w_im ? w_im[x] : 0.0};
     s[x] = {s_re ? s_re[x] : 0.0, s_im ? s_im[x] : 0.0};
   }
-  rk4_step<std::complex<double>>(g, w.data(), s.data(), wn.data());
+  time_step<std::complex<double>>(g, w.data(), s.data(), wn.data());
   for (long x = 0; x < M; ++x) { out_re[x] = wn[x].real(); out_im[x] = wn[x].imag(); }
   return 0;
 }
@@ -761,6 +800,27 @@ int orc_tlm_step(const orc_grid* gr, const double* w, const double* s, const dou
   G g(gr);
   const long M = 5 * g.N;
   const NuFields nu(g, w, lambda);
+  // tangent of one stage: (J_R(W) + L_nu) dW + ds
+  auto stage_tangent = [&](const std::vector<double>& W, const std::vector<double>& dW, std::vector<double>& dk) {
+    dk.assign(M, 0.0);
+    jvp(g, W.data(), dW.data(), dk.data());
+    if (nu.any) lnu_apply(g, nu.comp, dW.data(), dk.data());
+    if (ds)
+      for (long x = 0; x < M; ++x) dk[x] += ds[x];
+  };
+  if (g.scheme == 1) {
+    // SSP-RK3, the Shu-Osher stages differentiated one by one
+    std::vector<double> U[3], du1(M), du2(M), dk;
+    ssprk3_stage_states(g, w, s, U);
+    stage_tangent(U[0], std::vector<double>(dw, dw + M), dk);
+    for (long x = 0; x < M; ++x) du1[x] = dw[x] + g.dt * dk[x];
+    stage_tangent(U[1], du1, dk);
+    for (long x = 0; x < M; ++x) du2[x] = 0.75 * dw[x] + 0.25 * (du1[x] + g.dt * dk[x]);
+    stage_tangent(U[2], du2, dk);
+    for (long x = 0; x < M; ++x) dwn[x] = (1.0 / 3.0) * dw[x] + (2.0 / 3.0) * (du2[x] + g.dt * dk[x]);
+    if (wn) ssprk3_step<double>(g, w, s, wn);
+    return 0;
+  }
   std::vector<double> Ws[4];
   rk4_stage_states(g, w, s, Ws);
   std::vector<double> dW(dw, dw + M), dk[4];
@@ -794,10 +854,50 @@ int orc_adjoint_step(const orc_grid* gr, const double* w, const double* s, const
   if (check(gr)) return -1;
   G g(gr);
   const long M = 5 * g.N;
-  std::vector<double> Ws[4];
-  rk4_stage_states(g, w, s, Ws);
   const NuFields nu(g, w, lambda);
   const double dt = g.dt;
+  std::vector<double> dj(M, 0.0);
+  if (ob && ob->kind != 0 && c_n != 0.0) {
+    double jv;
+    if (objective(g, ob, w, &jv, dj.data())) return -1;
+  }
+  if (g.scheme == 1) {
+    // SSP-RK3 reversed stage by stage: each stage u_i = sum_k alpha_ik u_k + beta_i dt R(u_{i-1})
+    // hands u^_i to its inputs: alpha_ik u^_i to u_k and beta_i dt (J_R(u_{i-1})^T + L_nu) u^_i
+    // to u_{i-1}, and beta_i dt u^_i to s^
+    std::vector<double> U[3], r(M), u0(M, 0.0), u1(M, 0.0), u2(M, 0.0), sh(M, 0.0);
+    ssprk3_stage_states(g, w, s, U);
+    auto stage_adjoint = [&](const std::vector<double>& W, const double* q, std::vector<double>& out) {
+      vjp(g, W.data(), q, out.data());
+      if (nu.any) lnu_apply(g, nu.comp, q, out.data());
+    };
+    // w_next = 1/3 u0 + 2/3 u2 + 2/3 dt R(u2)
+    stage_adjoint(U[2], a, r);
+    for (long x = 0; x < M; ++x) {
+      u2[x] = (2.0 / 3.0) * a[x] + (2.0 / 3.0) * dt * r[x];
+      u0[x] = (1.0 / 3.0) * a[x];
+      sh[x] = (2.0 / 3.0) * dt * a[x];
+    }
+    // u2 = 3/4 u0 + 1/4 u1 + 1/4 dt R(u1)
+    stage_adjoint(U[1], u2.data(), r);
+    for (long x = 0; x < M; ++x) {
+      u1[x] = 0.25 * u2[x] + 0.25 * dt * r[x];
+      u0[x] += 0.75 * u2[x];
+      sh[x] += 0.25 * dt * u2[x];
+    }
+    // u1 = u0 + dt R(u0)
+    stage_adjoint(U[0], u1.data(), r);
+    for (long x = 0; x < M; ++x) {
+      u0[x] += u1[x] + dt * r[x];
+      sh[x] += dt * u1[x];
+    }
+    for (long x = 0; x < M; ++x) wh[x] = u0[x] + c_n * dj[x];
+    if (grad_s)
+      for (long x = 0; x < M; ++x) grad_s[x] += sh[x];
+    return 0;
+  }
+  std::vector<double> Ws[4];
+  rk4_stage_states(g, w, s, Ws);
   const double ca[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};  // weight of a in k^m, m = 1..4
   const double cg[4] = {dt / 2.0, dt / 2.0, dt, 0.0};             // weight of g_{m+1} in k^m
   std::vector<double> gnext(M, 0.0), gm(M), kh(M), sum_g(M, 0.0), sum_k(M, 0.0);
@@ -807,11 +907,6 @@ int orc_adjoint_step(const orc_grid* gr, const double* w, const double* s, const
     if (nu.any) lnu_apply(g, nu.comp, kh.data(), gm.data());
     for (long x = 0; x < M; ++x) { sum_g[x] += gm[x]; sum_k[x] += kh[x]; }
     gnext = gm;
-  }
-  std::vector<double> dj(M, 0.0);
-  if (ob && ob->kind != 0 && c_n != 0.0) {
-    double jv;
-    if (objective(g, ob, w, &jv, dj.data())) return -1;
   }
   for (long x = 0; x < M; ++x) wh[x] = a[x] + sum_g[x] + c_n * dj[x];
   if (grad_s)

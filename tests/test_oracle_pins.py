@@ -10,6 +10,7 @@ index or stencil coefficient, a transposed operand, a wrong RK4 weight) fails at
   kinetic energy                 at uniform pressure the inviscid terms leave sum rho|u|^2/2 fixed
   Fourier symbol (J and J^T)     closed-form linearised operator at a uniform state
   RK4 polynomial                 one tangent step equals G(dt L) = 1 + Z + Z^2/2 + Z^3/6 + Z^4/24
+                                 (SSP-RK3: 1 + Z + Z^2/2 + Z^3/6)
   complex step                   dual-number tangent vs complex-step derivative of the primal
   duality                        <w^_N, dw_N> = <w^_0, dw_0> + <g_s, ds> over whole windows,
                                  also with one artificial viscosity per variable group
@@ -27,8 +28,12 @@ import workloads as W
 from tests import linear_symbols as LS
 
 
-def _grid(orc, n, L=(2 * math.pi,) * 3, mu=0.02, dt=0.01, bc_x=0, gamma=1.4, prandtl=0.72):
-    return orc.make_grid(n, L, gamma, prandtl, mu, dt, bc_x)
+def _grid(orc, n, L=(2 * math.pi,) * 3, mu=0.02, dt=0.01, bc_x=0, gamma=1.4, prandtl=0.72, scheme=0):
+    return orc.make_grid(n, L, gamma, prandtl, mu, dt, bc_x, scheme)
+
+
+SCHEMES = [0, 1]
+SCHEME_IDS = ["rk4", "ssprk3"]
 
 
 def _uniform(n, rho, u, p):
@@ -62,9 +67,10 @@ def test_freestream_preserved_exactly(orc, bc_x):
     assert np.abs(R).max() <= 1e-14
 
 
-def test_conservation_periodic(orc):
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
+def test_conservation_periodic(orc, scheme):
     n = (7, 6, 5)
-    g = _grid(orc, n)
+    g = _grid(orc, n, scheme=scheme)
     w = _smooth_state(n, 1)
     s = np.random.default_rng(2).standard_normal(w.size)
     R = orc.residual(g, w, s).reshape(5, -1)
@@ -190,11 +196,36 @@ def test_rk4_amplification_polynomial(orc):
     assert np.abs(dwn - expect).max() <= 1e-13 * np.abs(expect).max()
 
 
+def test_ssprk3_amplification_polynomial(orc):
+    # a three-stage third-order method is exact to third order on a linear system:
+    # G(Z) = I + Z + Z^2/2 + Z^3/6 (no Z^4 term, which RK4 has)
+    n = (8, 6, 4)
+    L = (2.0, 1.5, 1.0)
+    mu, pr, gam = 0.01, 0.72, 1.4
+    dt = 0.01
+    g = _grid(orc, n, L=L, mu=mu, prandtl=pr, gamma=gam, dt=dt, scheme=1)
+    dx = [L[d] / n[d] for d in range(3)]
+    rho, u, p = 0.9, np.array([0.5, 0.1, -0.2]), 1.1
+    W0 = _uniform(n, rho, u, p)
+    k = [2 * math.pi * 1 / L[0], 2 * math.pi * 2 / L[1], 2 * math.pi * 1 / L[2]]
+    what = np.array([1.0 + 0.5j, -0.3j, 0.2, 0.7 - 0.1j, 0.4j])
+    v = LS.fourier_mode(n, dx, k, what)
+    _, dwn = orc.tlm_step(g, W0, None, v)
+    Z = dt * LS.semi_discrete_symbol(k, dx, rho, u, p, gam, mu, pr)
+    Gk = np.eye(5) + Z + Z @ Z / 2.0 + Z @ Z @ Z / 6.0
+    expect = LS.fourier_mode(n, dx, k, Gk @ what)
+    assert np.abs(dwn - expect).max() <= 1e-13 * np.abs(expect).max()
+    # and it differs from the RK4 step by the Z^4/24 term (far above rounding)
+    _, dw4 = orc.tlm_step(_grid(orc, n, L=L, mu=mu, prandtl=pr, gamma=gam, dt=dt), W0, None, v)
+    assert np.abs(dw4 - dwn).max() > 1e3 * 1e-13 * np.abs(expect).max()
+
+
 # ------------------------------------------------------------------------------ AD machinery
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
 @pytest.mark.parametrize("bc_x", [0, 1])
-def test_tangent_matches_complex_step(orc, bc_x):
+def test_tangent_matches_complex_step(orc, bc_x, scheme):
     n = (6, 5, 4)
-    g = _grid(orc, n, bc_x=bc_x, dt=0.02)
+    g = _grid(orc, n, bc_x=bc_x, dt=0.02, scheme=scheme)
     w = _smooth_state(n, 4)
     rng = np.random.default_rng(5)
     s = 1e-2 * rng.standard_normal(w.size)
@@ -227,11 +258,12 @@ def _duality_window(orc, g, w0, s, lam, nsteps, seed):
     return lhs, rhs
 
 
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
 @pytest.mark.parametrize("bc_x,lam", [(0, 0.0), (0, 0.01), (1, 0.0), (1, 0.01), (0, (0.004, 0.01, 0.025)),
                                       (1, (0.02, 0.0, 0.006))])
-def test_window_duality(orc, bc_x, lam):
+def test_window_duality(orc, bc_x, lam, scheme):
     n = (6, 6, 4)
-    g = _grid(orc, n, bc_x=bc_x, dt=0.02, mu=0.02)
+    g = _grid(orc, n, bc_x=bc_x, dt=0.02, mu=0.02, scheme=scheme)
     w0 = _smooth_state(n, 6)
     s = 1e-3 * np.random.default_rng(8).standard_normal(w0.size)
     lhs, rhs = _duality_window(orc, g, w0, s, lam, 4, 9)
@@ -285,11 +317,13 @@ def test_artificial_viscosity_closed_form(orc):
 
 
 # ------------------------------------------------------------------------------ Taylor tests
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
 @pytest.mark.parametrize("kind", [W.OBJ_MEAN_PRESSURE, W.OBJ_KE_DISSIPATION])
-def test_taylor_gradient_wrt_source(orc, kind):
+def test_taylor_gradient_wrt_source(orc, kind, scheme):
     wl = W.tgv_small(n=6, nsteps=4)
     p = wl.params()
     p["mu"] = 0.05
+    p["scheme"] = scheme
     g = orc.grid_from(p)
     obj = orc.make_obj(kind)
     weights = W.window_weights(wl.nsteps, 1, wl.nsteps)
