@@ -41,6 +41,9 @@ METRIC = "adjoint cell-steps/s + % HBM roofline, FP32/BF16-ckpt vs FP64 at state
 # stage 1: W, a, g2, g3, g4 in, w^_n out, grad_s read+write = 40), i.e. 95 values per
 # adjoint cell-step, 23.75 per launch and cell.
 VALUES_PER_STAGE_LAUNCH = 95.0 / 4.0
+# SSP-RK3: stage 3 (W, a in, g3 out) 15, stage 2 (W, a, g3 in, g2 out) 20, stage 1 (W, a, g2 + g3/4
+# in, g1 out) 20 values per cell; the combination of the stages is a separate elementwise pass
+VALUES_PER_STAGE_LAUNCH_RK3 = 55.0 / 3.0
 
 
 def profile_values(name, kernel_src_hash, tile):
@@ -95,7 +98,7 @@ def _tile_report(res, g, lnu):
     return out
 
 
-def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=False):
+def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=False, time_scheme=0):
     import torch
 
     import paper_1511_06959_amd as adj
@@ -105,7 +108,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     # FP32 states are stored as deviations from the mean initial state (see adj_grid.w_ref)
     w_ref = adj.reference_state(wl.w0) if precision == adj.F32 else None
     g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision,
-                      adj.CKPT_BF16 if ckpt_bf16 else adj.CKPT_NATIVE, w_ref)
+                      adj.CKPT_BF16 if ckpt_bf16 else adj.CKPT_NATIVE, w_ref, time_scheme=time_scheme)
     tiles = {}
     if tune:
         tiles = _tile_report(autotune.tune(g), g, wl.lam > 0.0)
@@ -175,7 +178,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     esz = 8 if precision == adj.F64 else 4
     ms, n = prof["adjoint_stage"]
     avg_s = ms / n / 1e3
-    alg_bytes = VALUES_PER_STAGE_LAUNCH * esz * cells
+    alg_bytes = (VALUES_PER_STAGE_LAUNCH_RK3 if time_scheme == 1 else VALUES_PER_STAGE_LAUNCH) * esz * cells
     out["stage_avg_us"] = avg_s * 1e6
     out["stage_alg_bytes"] = alg_bytes
     out["stage_achieved_gbs"] = alg_bytes / avg_s / 1e9
@@ -361,7 +364,10 @@ def main():
     ap.add_argument("--schedule", default="stages", choices=("stages", "recompute"),
                     help="stages: the forward sweep keeps the RK4 stage states in HBM; recompute: the reverse "
                          "step recomputes them from w_n")
+    ap.add_argument("--time-scheme", default="rk4", choices=("rk4", "ssprk3"),
+                    help="time marching: classical RK4, or the strong-stability-preserving RK3 of the paper")
     args = ap.parse_args()
+    args.ts = 1 if args.time_scheme == "ssprk3" else 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
               "design note, not part of this build)", file=sys.stderr)
@@ -388,15 +394,17 @@ def main():
     print(f"[bench] workload {wl.name}: {wl.n} cells, {wl.nsteps} steps, dt {wl.dt:.4e}, lambda {wl.lam:.3e}",
           file=sys.stderr, flush=True)
     # the large configurations keep BF16 checkpoint records on the FP32 path
-    r32 = run_gpu(wl, adj.F32, args.steps, args.warmup, not args.no_autotune, stages=stages, ckpt_bf16=big)
+    r32 = run_gpu(wl, adj.F32, args.steps, args.warmup, not args.no_autotune, stages=stages, ckpt_bf16=big,
+                  time_scheme=args.ts)
     print(f"[bench] f32 window {r32['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
     r32b = None
     if stages:
-        r32b = run_gpu(wl, adj.F32, args.steps, args.warmup, False, stages=False)
+        r32b = run_gpu(wl, adj.F32, args.steps, args.warmup, False, stages=False, time_scheme=args.ts)
         print(f"[bench] f32 window, recompute schedule {r32b['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_f64:
-        r64 = run_gpu(wl, adj.F64, args.steps, args.warmup, not args.no_autotune, stages=stages)
+        r64 = run_gpu(wl, adj.F64, args.steps, args.warmup, not args.no_autotune, stages=stages,
+                      time_scheme=args.ts)
         print(f"[bench] f64 window {r64['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
 
     def rel(a, b):
@@ -422,7 +430,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": WORKLOADS[args.workload].format(n=wl.nsteps),
+            "workload": WORKLOADS[args.workload].format(n=wl.nsteps).replace(
+                "RK4 steps", "SSP-RK3 steps" if args.ts == 1 else "RK4 steps"),
+            "time_scheme": args.time_scheme,
             "cells": wl.ncells,
             "window_steps": wl.nsteps,
             "dt": wl.dt,

@@ -61,6 +61,7 @@ typedef enum adj_status {
 enum { ADJ_BC_PERIODIC = 0, ADJ_BC_SLIP_WALLS = 1 };
 enum { ADJ_F64 = 0, ADJ_F32 = 1 };
 enum { ADJ_CKPT_NATIVE = 0, ADJ_CKPT_BF16 = 1 };
+enum { ADJ_RK4 = 0, ADJ_SSPRK3 = 1 };
 enum {
   ADJ_OBJ_NONE = 0,
   ADJ_OBJ_MEAN_PRESSURE = 1,  /* j = (1/N) sum_cells p                                         */
@@ -96,6 +97,12 @@ typedef struct adj_grid {
                           nu_g = lambda nu_weight[g] sigma_1 (each >= 0; all three 0 means
                           1, 1, 1, the single viscosity of the paper)  [Conclusion: separate
                           adjoint viscosities for rho, rho U, rho E]                           */
+  int32_t time_scheme; /* ADJ_RK4 (classical four-stage, the default) or ADJ_SSPRK3, the
+                          paper's strong-stability-preserving third-order Runge-Kutta in
+                          Shu-Osher form: u1 = w + dt R(w), u2 = 3/4 w + 1/4 (u1 + dt R(u1)),
+                          w_next = 1/3 w + 2/3 (u2 + dt R(u2))  [Numerical methods].  Every
+                          single-box call follows it, with the exact discrete adjoint of the
+                          chosen scheme; ensembles (adj_batch_*) take ADJ_RK4 grids only.       */
 } adj_grid;
 
 typedef struct adj_objective {

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libadjns.so")
 F64, F32 = 0, 1
 CKPT_NATIVE, CKPT_BF16 = 0, 1
 BC_PERIODIC, BC_SLIP_WALLS = 0, 1
+RK4, SSPRK3 = 0, 1
 OBJ_NONE, OBJ_MEAN_PRESSURE, OBJ_KE_DISSIPATION, OBJ_PT_LOSS_PLANE = 0, 1, 2, 3
 PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, PROF_SIGMA1, PROF_OBJECTIVE, PROF_CODEC, PROF_REDUCE = range(6)
 TILES = {0: (16, 4, 4), 1: (32, 4, 2), 2: (32, 4, 4), 3: (32, 8, 2), 4: (32, 8, 4), 5: (16, 8, 8)}
@@ -50,14 +51,16 @@ class Grid(ctypes.Structure):
         ("ckpt_format", ctypes.c_int32),
         ("w_ref", ctypes.c_double * 5),
         ("nu_weight", ctypes.c_double * 3),
+        ("time_scheme", ctypes.c_int32),
     ]
 
     @classmethod
     def make(cls, n, L, mu, dt, gamma=1.4, prandtl=0.72, bc_x=0, precision=F64, ckpt_format=CKPT_NATIVE,
-             w_ref=None, nu_weight=None):
+             w_ref=None, nu_weight=None, time_scheme=0):
         """w_ref: five reference values; state arrays then hold w - w_ref (see to_stored).
         nu_weight: artificial-viscosity weights of the groups (rho, rho u, rho E), the adjoint
-        components of group g diffused with nu_g = lambda nu_weight[g] sigma_1 (None: 1, 1, 1)."""
+        components of group g diffused with nu_g = lambda nu_weight[g] sigma_1 (None: 1, 1, 1).
+        time_scheme: RK4 (classical) or SSPRK3 (strong-stability-preserving third order)."""
         g = cls()
         for d in range(3):
             g.n[d] = int(n[d])
@@ -69,6 +72,7 @@ class Grid(ctypes.Structure):
             g.w_ref[v] = 0.0 if w_ref is None else float(w_ref[v])
         for k in range(3):
             g.nu_weight[k] = 1.0 if nu_weight is None else float(nu_weight[k])
+        g.time_scheme = int(time_scheme)
         return g
 
     def to_stored(self, w):

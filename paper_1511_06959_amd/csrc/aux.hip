@@ -963,7 +963,41 @@ hipError_t read_clear_nonfinite(unsigned int* flag) {
   return hipMemcpyToSymbol(HIP_SYMBOL(g_nonfinite), &zero, sizeof(unsigned int), 0, hipMemcpyHostToDevice);
 }
 
+template <typename T>
+__global__ __launch_bounds__(RB) void k_rk3_mid(T* __restrict__ g2, const T* __restrict__ g3, long long n) {
+  const long long i = (long long)blockIdx.x * RB + threadIdx.x;
+  if (i < n) g2[i] = g2[i] + T(0.25) * g3[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_rk3_combine(const T* __restrict__ a, const T* __restrict__ g1,
+                                                    const T* __restrict__ h, const T* __restrict__ g3, T dt,
+                                                    T* __restrict__ wh, T* __restrict__ grad_s, long long n) {
+  const long long i = (long long)blockIdx.x * RB + threadIdx.x;
+  if (i >= n) return;
+  const T av = a[i], hv = h[i], g3v = g3[i];
+  wh[i] = av + g1[i] + hv + T(0.75) * g3v;
+  if (grad_s) grad_s[i] = fma(dt, av, fma(dt, hv, fma(T(0.25) * dt, g3v, grad_s[i])));
+}
+
+template <typename T>
+hipError_t launch_rk3_mid(T* g2, const T* g3, long long n, hipStream_t st) {
+  hipLaunchKernelGGL((k_rk3_mid<T>), dim3((unsigned)((n + RB - 1) / RB)), dim3(RB), 0, st, g2, g3, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rk3_combine(const T* a, const T* g1, const T* h, const T* g3, T dt, T* wh, T* grad_s, long long n,
+                              hipStream_t st) {
+  hipLaunchKernelGGL((k_rk3_combine<T>), dim3((unsigned)((n + RB - 1) / RB)), dim3(RB), 0, st, a, g1, h, g3, dt, wh,
+                     grad_s, n);
+  return hipGetLastError();
+}
+
 #define ADJNS_INST(T)                                                                                          \
+  template hipError_t launch_rk3_mid<T>(T*, const T*, long long, hipStream_t);                                  \
+  template hipError_t launch_rk3_combine<T>(const T*, const T*, const T*, const T*, T, T*, T*, long long,       \
+                                            hipStream_t);                                                      \
   template hipError_t launch_stability<T>(const Consts<T>&, const T*, const T*, double, double, double, double*, \
                                           double*, hipStream_t);                                               \
   template hipError_t launch_sigma1<T>(const Consts<T>&, const T*, T, T*, hipStream_t);                        \

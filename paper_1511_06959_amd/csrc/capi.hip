@@ -95,6 +95,8 @@ int check_grid(const adj_grid* g, bool need_dt) {
     if (!(g->nu_weight[k] >= 0.0) || !std::isfinite(g->nu_weight[k]))
       return fail(ADJ_EINVAL, "nu_weight[%d] must be finite and >= 0", k);
   if (g->precision != ADJ_F64 && g->precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", g->precision);
+  if (g->time_scheme != ADJ_RK4 && g->time_scheme != ADJ_SSPRK3)
+    return fail(ADJ_EINVAL, "bad time_scheme %d", g->time_scheme);
   if (5 * (double)ncells(g) * (g->precision == ADJ_F64 ? 8.0 : 4.0) >= 4294967296.0)
     return fail(ADJ_ESHAPE, "state arrays must span less than 4 GiB (%lld cells)", ncells(g));
   if (g->ckpt_format != ADJ_CKPT_NATIVE && g->ckpt_format != ADJ_CKPT_BF16)
@@ -166,10 +168,23 @@ int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, 
   T* W4 = stages ? stages + 2 * S5 : (T*)at(ws, L.W4);
   const T h = c.dt * T(0.5);
   hipError_t e;
-  if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st))) return hip_fail(e, "primal stage 1");
-  if ((e = launch_primal_stage<T>(STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st))) return hip_fail(e, "primal stage 2");
-  if ((e = launch_primal_stage<T>(STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st))) return hip_fail(e, "primal stage 3");
-  if ((e = launch_primal_stage<T>(STAGE_FIN, c, W4, wn, s, W2, W3, T(0), out, st))) return hip_fail(e, "primal stage 4");
+  if (g->time_scheme == ADJ_SSPRK3) {
+    // u1 = w + dt R(w) (in W2), u2 = 3/4 w + 1/4 u1 + dt/4 R(u1) (in W3), w_next = 1/3 w + 2/3 u2 +
+    // 2 dt/3 R(u2); the affine weights sum to one, so stored deviations w - w_ref combine alike
+    if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, c.dt, W2, st)))
+      return hip_fail(e, "primal stage 1");
+    if ((e = launch_primal_stage<T>(STAGE_AFF, c, W2, wn, s, nullptr, nullptr, c.dt * T(0.25), W3, st, T(0.75),
+                                    T(0.25))))
+      return hip_fail(e, "primal stage 2");
+    if ((e = launch_primal_stage<T>(STAGE_AFF, c, W3, wn, s, nullptr, nullptr, c.dt * T(2.0 / 3.0), out, st,
+                                    T(1.0 / 3.0), T(2.0 / 3.0))))
+      return hip_fail(e, "primal stage 3");
+  } else {
+    if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st))) return hip_fail(e, "primal stage 1");
+    if ((e = launch_primal_stage<T>(STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st))) return hip_fail(e, "primal stage 2");
+    if ((e = launch_primal_stage<T>(STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st))) return hip_fail(e, "primal stage 3");
+    if ((e = launch_primal_stage<T>(STAGE_FIN, c, W4, wn, s, W2, W3, T(0), out, st))) return hip_fail(e, "primal stage 4");
+  }
   if (ckpt) {
     if constexpr (sizeof(T) == sizeof(float)) {
       float* hdr = (float*)ckpt;
@@ -177,6 +192,56 @@ int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, 
       if ((e = launch_ckpt_encode(c, (const float*)out, hdr, codes, st)))
         return hip_fail(e, "checkpoint encode");
     }
+  }
+  return ADJ_OK;
+}
+
+// SSP-RK3 reverse step: with a = w^_{n+1}, the stage transposes
+//   g3 = (J(u2)^T + L_nu) k3, k3 = 2dt/3 a;   g2 = (J(u1)^T + L_nu) k2, k2 = dt/6 a + dt/4 g3;
+//   g1 = (J(w_n)^T + L_nu) k1, k1 = dt/6 a + dt (g2 + g3/4);
+//   w^_n = a + g1 + g2 + g3 (+ c_n dj/dw),  grad_s += k1 + k2 + k3 = dt a + dt (g2 + g3/4) + dt/4 g3
+// (the Shu-Osher stages reversed one by one and summed; wn is the decoded state).
+template <typename T>
+int adjoint_step_rk3(const adj_grid* g, const Consts<T>& c, const WsLayout& L, const T* wn, const T* stages,
+                     const T* s, const T* a, double lambda, const adj_objective* o, double c_n, T* wh, T* grad_s,
+                     void* ws, hipStream_t st) {
+  const long long S5 = 5 * c.N;
+  const T dt = c.dt;
+  hipError_t e;
+  const T *u1 = (T*)at(ws, L.W2), *u2 = (T*)at(ws, L.W3);
+  if (stages) {
+    u1 = stages;
+    u2 = stages + S5;
+  } else {
+    if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, dt, (T*)at(ws, L.W2), st)))
+      return hip_fail(e, "recompute u1");
+    if ((e = launch_primal_stage<T>(STAGE_AFF, c, (T*)at(ws, L.W2), wn, s, nullptr, nullptr, dt * T(0.25),
+                                    (T*)at(ws, L.W3), st, T(0.75), T(0.25))))
+      return hip_fail(e, "recompute u2");
+  }
+  T* nu = (T*)at(ws, L.nu);
+  const T* nup = nullptr;
+  if (lambda > 0.0) {
+    if ((e = launch_sigma1<T>(c, wn, (T)lambda, nu, st))) return hip_fail(e, "sigma_1");
+    nup = nu;
+  }
+  T* g3 = (T*)at(ws, L.g3);
+  T* g2 = (T*)at(ws, L.g4);
+  T* g1 = (T*)at(ws, L.W4);
+  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, u2, a, nullptr, nup, dt * T(2.0 / 3.0), T(0), nullptr, nullptr, g3,
+                                   nullptr, st)))
+    return hip_fail(e, "adjoint stage 3");
+  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, u1, a, g3, nup, dt / T(6), dt * T(0.25), nullptr, nullptr, g2, nullptr,
+                                   st)))
+    return hip_fail(e, "adjoint stage 2");
+  if ((e = launch_rk3_mid<T>(g2, g3, S5, st))) return hip_fail(e, "adjoint stage combination");
+  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, wn, a, g2, nup, dt / T(6), dt, nullptr, nullptr, g1, nullptr, st)))
+    return hip_fail(e, "adjoint stage 1");
+  if ((e = launch_rk3_combine<T>(a, g1, g2, g3, dt, wh, grad_s, S5, st))) return hip_fail(e, "adjoint combination");
+  if (o && o->kind != ADJ_OBJ_NONE && c_n != 0.0) {
+    if ((e = launch_objective<T>(c, o->kind, o->plane_i, o->pt_ref, wn, c_n, nullptr, wh,
+                                 (double*)at(ws, L.partials), (double*)at(ws, L.scratch), st)))
+      return hip_fail(e, "objective gradient");
   }
   return ADJ_OK;
 }
@@ -205,6 +270,8 @@ int adjoint_step(const adj_grid* g, const void* wn_in, const T* stages, const T*
       wn = (const T*)dec;
     }
   }
+  if (g->time_scheme == ADJ_SSPRK3) return adjoint_step_rk3<T>(g, c, L, wn, stages, s, a, lambda, o, c_n, wh, grad_s,
+                                                              ws, st);
   const T *sW2 = W2, *sW3 = W3, *sW4 = W4;
   if (stages) {
     // stage states stored by the forward sweep (adj_primal_step_stages)
@@ -721,6 +788,7 @@ int adj_batch_create(adj_batch** out, int nbox, const adj_grid* grids, const adj
     if (grids[i].precision != grids[0].precision) return fail(ADJ_EINVAL, "box %d: every box needs one precision", i);
     if (grids[i].bc_x != grids[0].bc_x) return fail(ADJ_EINVAL, "box %d: every box needs one x boundary", i);
     if (grids[i].ckpt_format != ADJ_CKPT_NATIVE) return fail(ADJ_EINVAL, "box %d: ensembles keep native states", i);
+    if (grids[i].time_scheme != ADJ_RK4) return fail(ADJ_EINVAL, "box %d: ensembles march with RK4", i);
   }
   const int kind = obj ? obj->kind : ADJ_OBJ_NONE;
   if (kind != ADJ_OBJ_NONE && kind != ADJ_OBJ_MEAN_PRESSURE)

@@ -5,12 +5,22 @@
 
 namespace adjns {
 
-enum { STAGE_RES = 0, STAGE_LIN = 1, STAGE_FIN = 2 };  // primal stage modes
+enum { STAGE_RES = 0, STAGE_LIN = 1, STAGE_FIN = 2, STAGE_AFF = 3 };  // primal stage modes
 enum { STAGE_VJP = 0 };                                  // adjoint stage modes (STAGE_FIN shared)
 
+// STAGE_AFF: out = ca * wn + cb * W + cR * R(W; s)  (the SSP-RK3 stages)
 template <typename T>
 hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
-                               const T* W3, T cR, T* out, hipStream_t st);
+                               const T* W3, T cR, T* out, hipStream_t st, T ca = T(0), T cb = T(0));
+
+// SSP-RK3 reverse step, after the three stage transposes g3 (at u2), g2 (at u1), g1 (at w_n):
+// rk3_mid:     h = g2 + g3/4                               (in place of g2; k^1 = dt/6 a + dt h)
+// rk3_combine: w^_n = a + g1 + h + 3/4 g3,  grad_s += dt a + dt h + dt/4 g3 (grad_s may be NULL)
+template <typename T>
+hipError_t launch_rk3_mid(T* g2, const T* g3, long long n, hipStream_t st);
+template <typename T>
+hipError_t launch_rk3_combine(const T* a, const T* g1, const T* h, const T* g3, T dt, T* wh, T* grad_s, long long n,
+                              hipStream_t st);
 
 template <typename T>
 hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,

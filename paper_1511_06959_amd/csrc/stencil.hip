@@ -101,6 +101,7 @@ __device__ __forceinline__ void residual_dir(const T (*sm)[NB], const int st[3],
 
 // MODE: RES  out = R(W; s)
 //       LIN  out = wn + cR * R(W; s)                           (RK4 stages 1-3)
+//       AFF  out = ca wn + cb W + cR * R(W; s)                 (SSP-RK3 stages)
 //       FIN  out = (W2 + 2 W3 + W - wn)/3 + (dt/6) R(W; s)      (stage 4, W = W4;
 //            equals wn + dt/6 (k1 + 2 k2 + 2 k3 + k4) since k1 = 2(W2-wn)/dt, k2 = 2(W3-wn)/dt,
 //            k3 = (W4-wn)/dt)
@@ -109,7 +110,8 @@ template <typename T, int MODE, int TX, int TY, int TZ>
 __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x0, const int y0, const int z0,
                                                  const T* __restrict__ W, const T* __restrict__ wn,
                                                  const T* __restrict__ s, const T* __restrict__ W2,
-                                                 const T* __restrict__ W3, const T cR, T* __restrict__ out) {
+                                                 const T* __restrict__ W3, const T cR, T* __restrict__ out,
+                                                 const T ca = T(0), const T cb = T(0)) {
   constexpr int NT = TX * TY * TZ;
   using Bx = TBox<TX, TY, TZ, 1, 1>;
   constexpr int NB = Bx::NB;
@@ -173,6 +175,9 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
     if (MODE == STAGE_LIN) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) base[v] = wn[v * N + gi];
+    } else if (MODE == STAGE_AFF) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) base[v] = ca * wn[v * N + gi] + cb * W[v * N + gi];
     } else if (MODE == STAGE_FIN) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -195,7 +200,7 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
   if (MODE == STAGE_RES) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[v * N + gi] = R[v];
-  } else if (MODE == STAGE_LIN) {
+  } else if (MODE == STAGE_LIN || MODE == STAGE_AFF) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[v * N + gi] = base[v] + cR * R[v];
   } else {
@@ -212,10 +217,10 @@ template <typename T, int MODE, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, const T* __restrict__ W,
                                                                const T* __restrict__ wn, const T* __restrict__ s,
                                                                const T* __restrict__ W2, const T* __restrict__ W3,
-                                                               T cR, T* __restrict__ out) {
+                                                               T cR, T* __restrict__ out, T ca, T cb) {
   int x0, y0, z0;
   tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
-  primal_tile_body<T, MODE, TX, TY, TZ>(c, x0, y0, z0, W, wn, s, W2, W3, cR, out);
+  primal_tile_body<T, MODE, TX, TY, TZ>(c, x0, y0, z0, W, wn, s, W2, W3, cR, out, ca, cb);
 }
 
 // Ensemble form: work-group -> (box, tile) through the tile offsets `start`; every array is
@@ -747,17 +752,23 @@ constexpr bool adjoint_fits() {
 
 template <typename T>
 hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
-                               const T* W3, T cR, T* out, hipStream_t st) {
+                               const T* W3, T cR, T* out, hipStream_t st, T ca, T cb) {
   ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st, true);
   with_tile(tile_choice(ADJ_PROF_PRIMAL_STAGE, sizeof(T) == 8), [&](auto S) {
     using Sh = decltype(S);
     const dim3 grid = tile_grid<Sh::tx, Sh::ty, Sh::tz>(c.nx, c.ny, c.nz), blk(Sh::tx * Sh::ty * Sh::tz);
     if (mode == STAGE_RES)
-      timed_launch(ps, k_primal_stage<T, STAGE_RES, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out);
+      timed_launch(ps, k_primal_stage<T, STAGE_RES, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out,
+                   ca, cb);
     else if (mode == STAGE_LIN)
-      timed_launch(ps, k_primal_stage<T, STAGE_LIN, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out);
+      timed_launch(ps, k_primal_stage<T, STAGE_LIN, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out,
+                   ca, cb);
+    else if (mode == STAGE_AFF)
+      timed_launch(ps, k_primal_stage<T, STAGE_AFF, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out,
+                   ca, cb);
     else
-      timed_launch(ps, k_primal_stage<T, STAGE_FIN, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out);
+      timed_launch(ps, k_primal_stage<T, STAGE_FIN, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out,
+                   ca, cb);
   });
   return hipGetLastError();
 }
@@ -871,9 +882,10 @@ ADJNS_BATCH_INST(double)
 #undef ADJNS_BATCH_INST
 
 template hipError_t launch_primal_stage<float>(int, const Consts<float>&, const float*, const float*, const float*,
-                                               const float*, const float*, float, float*, hipStream_t);
+                                               const float*, const float*, float, float*, hipStream_t, float, float);
 template hipError_t launch_primal_stage<double>(int, const Consts<double>&, const double*, const double*, const double*,
-                                                const double*, const double*, double, double*, hipStream_t);
+                                                const double*, const double*, double, double*, hipStream_t, double,
+                                                double);
 template hipError_t launch_adjoint_stage<float>(int, const Consts<float>&, const float*, const float*, const float*,
                                                 const float*, float, float, const float*, const float*, float*,
                                                 float*, hipStream_t);
