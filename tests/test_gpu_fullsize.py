@@ -1,0 +1,129 @@
+"""Parity at the full benchmark sizes, in the benchmark's launch configuration (autotuned tiles).
+
+64^3 Taylor-Green (the default benchmark line, Mach 0.1, Re 1600): one primal step and one
+reverse step (dissipation objective injected, body force) on the whole grid against the oracle's
+whole-grid steps, FP64 and FP32 (states stored as deviations from the mean state).
+
+384^3 decaying turbulence and the 512x256x32 wake (FP32, lambda = 0.1 dx^2 sigma_1): one reverse
+step on the whole grid; 4x4x4 cell samples against the oracle's step on a 36^3 block around each
+sample.  An output cell of a reverse step depends on w_n within 14 cells and on w^_{n+1} within
+8 (four stages of the radius-2 stencil, each stage state recomputed from w_n), so the sampled
+cells, 16 or more cells from every block face that is not the true boundary, are exact although
+the oracle treats the block as periodic (or, for the wake, as walled in x where the real wall is).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1511_06959_amd as adj
+import workloads as W
+from paper_1511_06959_amd import autotune
+from tests.gpu_helpers import dev, host, relerr
+
+pytestmark = pytest.mark.gpu
+
+BLOCK, SAMPLE = 36, 4
+OFF = (BLOCK - SAMPLE) // 2  # 16: sampled cells sit at block positions 16..19
+
+
+@pytest.fixture(scope="module")
+def tgv64():
+    return W.tgv_64(nsteps=2)
+
+
+@pytest.mark.parametrize("precision", [adj.F64, adj.F32], ids=["f64", "f32"])
+def test_tgv64_steps_whole_grid(orc, tgv64, precision):
+    wl = tgv64
+    ref = adj.reference_state(wl.w0) if precision == adj.F32 else None
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision, w_ref=ref)
+    autotune.tune(g)
+    dt = g.dtype
+    # the states the GPU holds, as the oracle sees them
+    stored = g.to_stored(wl.w0).astype(np.float32 if precision == adj.F32 else np.float64)
+    w = g.from_stored(stored.astype(np.float64))
+    s = wl.s.astype(np.float32 if precision == adj.F32 else np.float64).astype(np.float64)
+    rng = np.random.default_rng(60)
+    a = rng.standard_normal(w.size).astype(np.float32 if precision == adj.F32 else np.float64).astype(np.float64)
+    og = orc.grid_from(wl.params())
+    ws = adj.workspace(g)
+    out = torch.empty(w.size, dtype=dt, device="cuda")
+    adj.primal_step(g, dev(stored, dt), dev(s, dt), out, ws)
+    ref_p = orc.primal_step(og, w, s)
+    # At Mach 0.1 the energy flux (rho E + p) u ~ 250 while its face differences are a few units:
+    # summation order alone moves the FP64 increments by ~1e-11 of their largest value (the FP64
+    # target of 1e-10 applies), and FP32 fluxes (6e-8 relative) move them by up to ~1e-3.  The
+    # FP32 states themselves (stored deviations from the mean state) agree to FP32 rounding; the
+    # 1000-step FP32 window stays within 1e-4 of FP64 (test_fp32_window_accuracy_64cubed).
+    tol = 1e-10 if precision == adj.F64 else 2e-3
+    assert relerr(g.from_stored(host(out)) - w, ref_p - w) <= tol
+    if precision == adj.F32:
+        assert relerr(host(out), g.to_stored(ref_p)) <= 1e-6
+    obj = adj.Objective.make(W.OBJ_KE_DISSIPATION)
+    gs = torch.zeros(w.size, dtype=dt, device="cuda")
+    adj.adjoint_step(g, dev(stored, dt), dev(s, dt), dev(a, dt), out, ws, obj=obj, c_n=0.5, grad_s=gs)
+    gref = np.zeros(w.size)
+    ref_a = orc.adjoint_step(og, w, s, a, 0.0, orc.make_obj(W.OBJ_KE_DISSIPATION), 0.5, gref)
+    assert relerr(host(out) - a, ref_a - a) <= tol
+    assert relerr(host(gs), gref) <= tol
+
+
+def _axis(n, s0, walled):
+    """Block cell indices along one axis for a sample starting at s0, and whether the block ends
+    at a real wall: the whole axis if it is short, a walled block from the wall for samples near a
+    slip wall, a wrapped (periodic) block centred on the sample otherwise."""
+    if n <= BLOCK:
+        return np.arange(n), walled
+    if walled and s0 < OFF:
+        return np.arange(BLOCK), True
+    if walled and s0 + SAMPLE > n - OFF:
+        return np.arange(n - BLOCK, n), True
+    return (s0 - OFF + np.arange(BLOCK)) % n, False
+
+
+def _sampled_parity(orc, wl, starts, seed):
+    """One FP32 reverse step (lambda = 0.1 dx^2 sigma_1) on the whole grid; each 4^3 sample at
+    `starts` (x, y, z) against the oracle step on its block.  Returns the largest relative error of
+    the increments w^_n - w^_{n+1}."""
+    ref = adj.reference_state(wl.w0)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F32, w_ref=ref)
+    autotune.tune(g)
+    lam = 0.1 * min(wl.L[d] / wl.n[d] for d in range(3)) ** 2
+    nx, ny, nz = wl.n
+    stored = g.to_stored(wl.w0).astype(np.float32)
+    a = np.random.default_rng(seed).standard_normal(stored.size).astype(np.float32)
+    out = torch.empty(stored.size, dtype=torch.float32, device="cuda")
+    adj.adjoint_step(g, torch.from_numpy(stored).to("cuda"), None, torch.from_numpy(a).to("cuda"), out,
+                     adj.workspace(g), lam=lam)
+    out5 = host(out).reshape(5, nz, ny, nx)
+    st5, a5 = stored.reshape(5, nz, ny, nx), a.reshape(5, nz, ny, nx)
+    worst = 0.0
+    for start in starts:
+        (ix, wall), (iy, _), (iz, _) = (_axis(wl.n[d], start[d], d == 0 and wl.bc_x == 1) for d in range(3))
+        blk = np.ix_(np.arange(5), iz, iy, ix)
+        wb = st5[blk].astype(np.float64) + np.asarray(ref).reshape(5, 1, 1, 1)
+        ab = a5[blk].astype(np.float64)
+        bn = (len(ix), len(iy), len(iz))
+        og = orc.make_grid(bn, tuple(bn[d] * wl.L[d] / wl.n[d] for d in range(3)), wl.gamma, wl.prandtl, wl.mu,
+                           wl.dt, 1 if wall else 0)
+        rb = orc.adjoint_step(og, wb.ravel(), None, ab.ravel(), lam, None, 0.0, None).reshape(5, *bn[::-1])
+        pos = [int(np.nonzero(ii == s0)[0][0]) for ii, s0 in zip((ix, iy, iz), start)]
+        sl = (slice(None), slice(pos[2], pos[2] + SAMPLE), slice(pos[1], pos[1] + SAMPLE),
+              slice(pos[0], pos[0] + SAMPLE))
+        got = out5[np.ix_(np.arange(5), iz[sl[1]], iy[sl[2]], ix[sl[3]])] - ab[sl]
+        worst = max(worst, relerr(got, rb[sl] - ab[sl]))
+    return worst
+
+
+def test_turb384_reverse_step_sampled(orc):
+    wl = W.turb_384(nsteps=1)
+    n = wl.n[0]
+    starts = [(0, 0, 0), (100, 200, 300), (n - 2, 17, n - 3), (191, n - 1, 64)]
+    assert _sampled_parity(orc, wl, starts, 61) <= 5e-5
+
+
+def test_wake_reverse_step_sampled(orc):
+    wl = W.wake(nsteps=1)
+    nx = wl.n[0]
+    # at both slip walls, in the shear layer and in the free stream; the span (32 cells) is whole
+    starts = [(0, 10, 0), (nx - SAMPLE, 250, 8), (254, 100, 20), (380, 3, 28)]
+    assert _sampled_parity(orc, wl, starts, 62) <= 5e-5
