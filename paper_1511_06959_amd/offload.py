@@ -1,32 +1,138 @@
-"""Window trajectories kept in pinned host memory, streamed over PCIe while the kernels run.
+"""Window trajectories kept in pinned host memory or in a file, streamed while the kernels run.
 
 The paper writes its primal snapshots to disk and reads them back during the adjoint sweep
-("Implementation").  Here the states of a window (native states or BF16 records) go to pinned
-host memory instead of HBM when the window does not fit on the GPU: after each primal step the
-new state is copied device-to-host on a copy stream while the next step computes, and the
-reverse sweep prefetches w_{n-1} host-to-device while step n runs.  A small ring of device
-slots holds the states in flight; events order every reuse of a slot after the copy or the
-kernel that last touched it.  The last states of the window may stay in HBM (`device_tail`):
-the reverse sweep consumes them first, while the first host states are already on their way.
+("Implementation").  Here the states of a window (native states or BF16 records) that do not fit
+in HBM go to pinned host memory, or through pinned staging buffers to a file (an NVMe scratch
+file, say): after each primal step the new state is copied device-to-host on a copy stream while
+the next step computes, and the reverse sweep fetches w_{n-1} while step n runs.  A small ring of
+device slots holds the states in flight; events order every reuse of a slot after the copy or the
+kernel that last touched it, and file reads and writes run on a worker thread.  The last states of
+the window may stay in HBM (`device_tail`): the reverse sweep consumes them first, while the first
+stored states are already on their way.
 
 The kernels and their inputs are those of the HBM sweeps (sweep.forward / sweep.backward), so
 the results are identical bit for bit; only where the states wait between the sweeps differs.
 Only scheduling and copies happen here.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
 import torch
 
 from . import (CKPT_BF16, OBJ_NONE, adjoint_step, ckpt_bytes, ckpt_decode, ckpt_encode, objective_and_grad,
                primal_step, workspace)
 
 
+class _PinnedStore:
+    """Stored states in one pinned host tensor."""
+
+    def __init__(self, n, rec_len, dtype):
+        self.host = torch.empty((max(n, 1), rec_len), dtype=dtype, pin_memory=True)
+
+    def put(self, n, src, copy):
+        with torch.cuda.stream(copy):
+            self.host[n].copy_(src, non_blocking=True)
+        return copy.record_event()
+
+    def prefetch(self, n):
+        pass
+
+    def get(self, n, dst, copy):
+        with torch.cuda.stream(copy):
+            dst.copy_(self.host[n], non_blocking=True)
+        return copy.record_event()
+
+    def finish(self):
+        pass
+
+    def read(self, n):
+        return self.host[n]
+
+
+class _FileStore:
+    """Stored states in a file, moved through `nstage` pinned staging buffers by one worker
+    thread (file writes after the device-to-host copy has landed, file reads ahead of the
+    host-to-device copy)."""
+
+    def __init__(self, n, rec_len, dtype, path, nstage=3):
+        np_dtype = torch.empty(0, dtype=dtype).numpy().dtype
+        self.mm = np.memmap(path, dtype=np_dtype, mode="w+", shape=(max(n, 1), rec_len))
+        self.path = path
+        self.stage = [torch.empty(rec_len, dtype=dtype, pin_memory=True) for _ in range(nstage)]
+        self.busy = [None] * nstage     # pending worker job on each staging buffer
+        self.h2d = [None] * nstage      # host-to-device copy out of each staging buffer
+        self.reads = {}
+        self.pool = ThreadPoolExecutor(max_workers=1)
+
+    def _slot(self, n):
+        return n % len(self.stage)
+
+    def _write(self, n, j, ev):
+        ev.synchronize()
+        self.mm[n] = self.stage[j].numpy()
+
+    def _read(self, n, j, prior):
+        if prior is not None:
+            prior.synchronize()
+        self.stage[j].numpy()[:] = self.mm[n]
+
+    def _claim(self, j):
+        if self.busy[j] is not None:
+            self.busy[j].result()
+            self.busy[j] = None
+
+    def put(self, n, src, copy):
+        j = self._slot(n)
+        self._claim(j)
+        with torch.cuda.stream(copy):
+            self.stage[j].copy_(src, non_blocking=True)
+        ev = copy.record_event()
+        self.busy[j] = self.pool.submit(self._write, n, j, ev)
+        return ev
+
+    def prefetch(self, n):
+        if n < 0 or n in self.reads:
+            return
+        j = self._slot(n)
+        self._claim(j)
+        self.reads[n] = self.busy[j] = self.pool.submit(self._read, n, j, self.h2d[j])
+
+    def get(self, n, dst, copy):
+        j = self._slot(n)
+        self.prefetch(n)
+        self.reads.pop(n).result()
+        self.busy[j] = None
+        with torch.cuda.stream(copy):
+            dst.copy_(self.stage[j], non_blocking=True)
+        self.h2d[j] = copy.record_event()
+        return self.h2d[j]
+
+    def finish(self):
+        for j in range(len(self.stage)):
+            self._claim(j)
+        self.mm.flush()
+
+    def read(self, n):
+        return torch.from_numpy(np.array(self.mm[n]))
+
+    def close(self):
+        for j in range(len(self.stage)):
+            self._claim(j)
+        self.pool.shutdown()
+        del self.mm
+        if os.path.exists(self.path):
+            os.remove(self.path)
+
+
 class HostTrajectory:
     """States w_0..w_N of one window: the last `device_tail` of them in HBM, the others in pinned
-    host memory (full-precision states, or BF16 records when g.ckpt_format says so).  A ring of
-    `slots` device buffers holds the host states in flight; a copy stream of its own (default
-    priority) moves them.  The reverse sweep starts with the states kept in HBM and in the ring,
-    so its first host fetches overlap computation."""
+    host memory, or in the file `path` when given (full-precision states, or BF16 records when
+    g.ckpt_format says so).  A ring of `slots` device buffers holds the stored states in flight; a
+    copy stream of its own (default priority) moves them.  The reverse sweep starts with the states
+    kept in HBM and in the ring, so its first fetches overlap computation."""
 
-    def __init__(self, g, nsteps, device="cuda", slots=2, device_tail=0):
+    def __init__(self, g, nsteps, device="cuda", slots=2, device_tail=0, path=None):
         if slots < 2:
             raise ValueError("at least two device slots")
         self.g, self.nsteps = g, nsteps
@@ -35,28 +141,47 @@ class HostTrajectory:
             self.rec_len, dt = ckpt_bytes(g), torch.uint8
         else:
             self.rec_len, dt = 5 * g.ncells, g.dtype
+        self.elem = torch.empty(0, dtype=dt).element_size()
         self.tail = max(0, min(int(device_tail), nsteps + 1))
-        self.nhost = nsteps + 1 - self.tail  # states 0 .. nhost-1 live in host memory
-        self.host = torch.empty((max(self.nhost, 1), self.rec_len), dtype=dt, pin_memory=True)
+        self.nhost = nsteps + 1 - self.tail  # states 0 .. nhost-1 live in host memory or the file
+        if path:
+            self.store = _FileStore(self.nhost, self.rec_len, dt, path)
+        else:
+            self.store = _PinnedStore(self.nhost, self.rec_len, dt)
         self.dev_tail = [torch.empty(self.rec_len, dtype=dt, device=device) for _ in range(self.tail)]
         self.ring = [torch.empty(self.rec_len, dtype=dt, device=device) for _ in range(slots)]
-        self.in_ring = [None] * slots  # host state that each ring slot holds, as the forward sweep left it
+        self.in_ring = [None] * slots  # stored state that each ring slot holds, as the last sweep left it
         self.copy = torch.cuda.Stream(device=device)
         self.device = device
 
     @property
     def nbytes(self):
-        return self.nhost * self.rec_len * self.host.element_size()
+        return self.nhost * self.rec_len * self.elem
+
+    @property
+    def host(self):
+        """The pinned host tensor of the stored states (pinned-memory trajectories)."""
+        return self.store.host
+
+    def stored(self, n):
+        """State or record n as stored (a host tensor; complete once the forward sweep's stream
+        has finished)."""
+        return self.store.read(n) if n < self.nhost else self.dev_tail[n - self.nhost].cpu()
 
     def buffer(self, n):
         """Device buffer of state n during the forward sweep."""
         return self.dev_tail[n - self.nhost] if n >= self.nhost else self.ring[n % len(self.ring)]
 
+    def close(self):
+        if isinstance(self.store, _FileStore):
+            self.store.close()
+
 
 def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None):
-    """Primal sweep w_0 -> w_N storing every state (host memory or the HBM tail); J (device
+    """Primal sweep w_0 -> w_N storing every state (host memory, file or the HBM tail); J (device
     FP64) += sum_n c_n j(w_n).  Same kernels and order as sweep.forward.  Returns (trajectory,
-    w_N, J); the host copies are complete when the caller's stream reaches the end of the sweep."""
+    w_N, J); the stored copies are complete when the caller's stream reaches the end of the sweep
+    (and, for a file, when this call returns)."""
     dev = w0.device
     ws = workspace(g) if ws is None else ws
     traj = HostTrajectory(g, nsteps, dev) if traj is None else traj
@@ -74,11 +199,8 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
         if n >= traj.nhost:
             return
         k = n % K
-        ev = main.record_event()
-        traj.copy.wait_event(ev)
-        with torch.cuda.stream(traj.copy):
-            traj.host[n].copy_(traj.ring[k], non_blocking=True)
-        done[k] = traj.copy.record_event()
+        traj.copy.wait_event(main.record_event())
+        done[k] = traj.store.put(n, traj.ring[k], traj.copy)
         traj.in_ring[k] = n
 
     use_obj = obj is not None and obj.kind != OBJ_NONE and weights is not None
@@ -111,11 +233,12 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
     for ev in done:
         if ev is not None:
             main.wait_event(ev)
+    traj.store.finish()
     return traj, wN, J
 
 
 def backward(g, traj, s, obj=None, weights=None, lam=0.0, ws=None, grad_s=None):
-    """Reverse sweep over a host trajectory, the next host state fetched while a step runs.
+    """Reverse sweep over a stored trajectory, the next stored state fetched while a step runs.
     Same kernels and order as sweep.backward.  Returns (w^_0, grad_s)."""
     dev = traj.ring[0].device
     ws = workspace(g) if ws is None else ws
@@ -129,21 +252,23 @@ def backward(g, traj, s, obj=None, weights=None, lam=0.0, ws=None, grad_s=None):
     use_obj = obj is not None and obj.kind != OBJ_NONE and weights is not None
     dec = torch.empty(N5, dtype=g.dtype, device=dev) if traj.bf16 else None
     free = [None] * K   # last kernel reading each ring slot finished
-    ready = {}          # host state n has arrived in its ring slot (None: it was there already)
+    ready = {}          # stored state n has arrived in its ring slot (None: it was there already)
     held = list(traj.in_ring)
 
     def fetch(n):
         if n < 0 or n >= traj.nhost:
             return
         k = n % K
-        if held[k] == n:  # left in the ring by the forward sweep
+        if held[k] == n:  # left in the ring by the last sweep
             ready[n] = None
             return
         held[k] = n
         traj.copy.wait_stream(main) if free[k] is None else traj.copy.wait_event(free[k])
-        with torch.cuda.stream(traj.copy):
-            traj.ring[k].copy_(traj.host[n], non_blocking=True)
-        ready[n] = traj.copy.record_event()
+        ready[n] = traj.store.get(n, traj.ring[k], traj.copy)
+
+    def prefetch(n):
+        if 0 <= n < traj.nhost and held[n % K] != n:
+            traj.store.prefetch(n)
 
     def state(n):
         if n >= traj.nhost:
@@ -163,8 +288,10 @@ def backward(g, traj, s, obj=None, weights=None, lam=0.0, ws=None, grad_s=None):
         ckpt_decode(g, rec, dec)
         return dec
 
-    # the first host states are on their way while the HBM tail is processed
+    # the first stored states are on their way while the HBM tail is processed
     top = traj.nhost - 1
+    for n in (top, top - 1, top - 2):
+        prefetch(n)
     fetch(top)
     if top == N:
         fetch(N - 1)
@@ -176,6 +303,7 @@ def backward(g, traj, s, obj=None, weights=None, lam=0.0, ws=None, grad_s=None):
         w = state(n)
         if n <= top:
             fetch(n - 1)
+            prefetch(n - 2)
         c_n = float(weights[n]) if use_obj else 0.0
         adjoint_step(g, w, s, a, b, ws, lam=lam, obj=obj if use_obj else None, c_n=c_n, grad_s=grad_s)
         release(n)

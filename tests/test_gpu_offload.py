@@ -1,6 +1,6 @@
-"""Window trajectories in pinned host memory (paper_1511_06959_amd.offload): the same sweeps as
-with the trajectory in HBM, so J, dJ/dw_0 and dJ/ds agree bit for bit, and every stored state
-(or BF16 record) in host memory equals the one the HBM sweep stores."""
+"""Window trajectories in pinned host memory or in a file (paper_1511_06959_amd.offload): the
+same sweeps as with the trajectory in HBM, so J, dJ/dw_0 and dJ/ds agree bit for bit, and every
+stored state (or BF16 record) equals the one the HBM sweep stores."""
 import numpy as np
 import pytest
 import torch
@@ -12,14 +12,17 @@ from tests.gpu_helpers import host
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(adj.F64, adj.CKPT_NATIVE, 2, 0), (adj.F32, adj.CKPT_NATIVE, 3, 0), (adj.F32, adj.CKPT_BF16, 2, 0),
-         (adj.F64, adj.CKPT_NATIVE, 2, 4), (adj.F32, adj.CKPT_BF16, 3, 1), (adj.F32, adj.CKPT_BF16, 2, 10)]
-IDS = ["f64", "f32-3slots", "f32-bf16", "f64-tail4", "f32-bf16-3slots-tail1", "f32-bf16-all-in-hbm"]
+CASES = [(adj.F64, adj.CKPT_NATIVE, 2, 0, False), (adj.F32, adj.CKPT_NATIVE, 3, 0, False),
+         (adj.F32, adj.CKPT_BF16, 2, 0, False), (adj.F64, adj.CKPT_NATIVE, 2, 4, False),
+         (adj.F32, adj.CKPT_BF16, 3, 1, False), (adj.F32, adj.CKPT_BF16, 2, 10, False),
+         (adj.F64, adj.CKPT_NATIVE, 2, 0, True), (adj.F32, adj.CKPT_BF16, 3, 3, True)]
+IDS = ["f64", "f32-3slots", "f32-bf16", "f64-tail4", "f32-bf16-3slots-tail1", "f32-bf16-all-in-hbm",
+       "f64-file", "f32-bf16-file-3slots-tail3"]
 
 
-@pytest.mark.parametrize("precision,ckpt,slots,tail", CASES, ids=IDS)
+@pytest.mark.parametrize("precision,ckpt,slots,tail,to_file", CASES, ids=IDS)
 @pytest.mark.parametrize("lam_factor", [0.0, 0.3], ids=["lam0", "lam"])
-def test_host_trajectory_matches_hbm(precision, ckpt, slots, tail, lam_factor):
+def test_host_trajectory_matches_hbm(tmp_path, precision, ckpt, slots, tail, to_file, lam_factor):
     T = 9
     wl = W.turbulence((12, 10, 8), mach_rms=0.3, nu=0.02, seed=31, nsteps=T)
     ref = adj.reference_state(wl.w0) if precision == adj.F32 else None
@@ -34,8 +37,11 @@ def test_host_trajectory_matches_hbm(precision, ckpt, slots, tail, lam_factor):
     traj, _, J1 = sweep.forward(g, w0, s, T, obj, weights, ws)
     wh1, gs1, _ = sweep.backward(g, traj, s, obj, weights, lam, ws)
     J1, wh1, gs1 = host(J1), host(wh1), host(gs1)
-    ht = offload.HostTrajectory(g, T, slots=slots, device_tail=tail)
-    assert ht.host.is_pinned() and ht.nhost == T + 1 - tail
+    ht = offload.HostTrajectory(g, T, slots=slots, device_tail=tail,
+                                path=str(tmp_path / "traj.bin") if to_file else None)
+    assert ht.nhost == T + 1 - tail
+    if not to_file:
+        assert ht.host.is_pinned()
     ht, _, J2 = offload.forward(g, w0, s, T, obj, weights, ws, traj=ht)
     wh2, gs2 = offload.backward(g, ht, s, obj, weights, lam, ws)
     # a second reverse sweep over the same trajectory (the ring now holds other states)
@@ -47,10 +53,11 @@ def test_host_trajectory_matches_hbm(precision, ckpt, slots, tail, lam_factor):
     nbl = -(-wl.n[0] // 4) * -(-wl.n[1] // 4) * -(-wl.n[2] // 4)
     used = [slice(0, 40 * nbl), slice(adj.ckpt_bytes(g) - 10 * N, None)] if ckpt == adj.CKPT_BF16 else [slice(None)]
     for n in range(T + 1):
-        stored = ht.host[n] if n < ht.nhost else ht.dev_tail[n - ht.nhost].cpu()
+        stored = ht.stored(n)
         for u in used:
             assert torch.equal(stored[u], traj.slot(n).cpu()[u]), f"state {n}"
     assert np.array_equal(host(J2), J1)
     for wh, gs in ((wh2, gs2), (wh3, gs3)):
         assert np.array_equal(host(wh), wh1)
         assert np.array_equal(host(gs), gs1)
+    ht.close()
