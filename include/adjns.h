@@ -114,11 +114,13 @@ typedef struct adj_objective {
 /* Bytes of scratch the caller must pass as `ws` to any call on this grid. */
 size_t adj_workspace_bytes(const adj_grid* grid);
 
-/* Bytes of one BF16 checkpoint record: a 64-byte header of 5 (mean, scale) FP32 pairs followed
- * by 5N bfloat16 codes in the state layout. */
+/* Bytes of one BF16 checkpoint record: the block header (10 FP32 values per 4x4x4 block of
+ * cells, padded to a multiple of 256 bytes) followed by 5N bfloat16 codes in the state layout
+ * (see adj_ckpt_encode). */
 size_t adj_ckpt_bytes(const adj_grid* grid);
 
-/* One RK4 step of the primal  [Physics; Numerical methods (time marching)].
+/* One time step of the primal (classical RK4, or SSP-RK3 when grid->time_scheme says so)
+ * [Physics; Numerical methods (time marching)].
  *   w_n   in : state at step n                     (state-sized)
  *   s     in : source field, or NULL for s = 0      (state-sized)
  *   w_np1 out: state at step n+1 (must not alias w_n)
@@ -127,7 +129,8 @@ size_t adj_ckpt_bytes(const adj_grid* grid);
 int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out,
                     void* ws, size_t ws_bytes, void* stream);
 
-/* One reverse RK4 step of the discrete adjoint with artificial viscosity  [Unsteady adjoint:
+/* One reverse step of the discrete adjoint with artificial viscosity (below for RK4; an
+ * ADJ_SSPRK3 grid reverses its three Shu-Osher stages the same way, see time_scheme)  [Unsteady adjoint:
  * terminal condition and backward integration; Implementation; Stabilizing adjoint equations]:
  *   recompute the stage states W1 = w_n, W2, W3, W4; nu = lambda sigma_1(w_n) held over the step;
  *   k^4 = dt/6 a, g4 = (J_R(W4)^T + L_nu) k^4; k^3 = dt/3 a + dt g4, g3 = ...;
@@ -148,9 +151,10 @@ int adj_adjoint_step(const adj_grid* grid, const void* w_n, const void* s, const
                      void* ws, size_t ws_bytes, void* stream);
 
 /* Store-stages schedule (for windows whose stage states fit in memory): adj_primal_step_stages
- * is adj_primal_step that also writes the RK4 stage states W2, W3, W4 of the step into
- * stages_out (3 consecutive state-sized arrays); adj_adjoint_step_stages is adj_adjoint_step
- * that reads them from `stages` instead of recomputing them from w_n.  Native states only. */
+ * is adj_primal_step that also writes the stage states of the step into stages_out (3
+ * consecutive state-sized arrays: W2, W3, W4 for RK4; u1, u2 and an unused third for SSP-RK3);
+ * adj_adjoint_step_stages is adj_adjoint_step that reads them from `stages` instead of
+ * recomputing them from w_n.  Native states only. */
 int adj_primal_step_stages(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* stages_out,
                            void* ws, size_t ws_bytes, void* stream);
 int adj_adjoint_step_stages(const adj_grid* grid, const void* w_n, const void* stages, const void* s,
