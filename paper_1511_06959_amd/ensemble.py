@@ -11,6 +11,9 @@ The trajectory of the ensemble is stored whole: slot t keeps w_t of the boxes wi
 (natively, in the state precision), so it holds sum_b 5 N_b (T_b + 1) values.  The reverse sweep
 recomputes the inner RK4 stage states of each step inside the batched adjoint step.
 
+When the stored trajectory of a whole ensemble exceeds the memory at hand, PlannedEnsemble runs
+it in consecutive groups of boxes, each within a byte budget.
+
 Only scheduling happens here; all arithmetic runs in the library's kernels.
 """
 import bisect
@@ -154,3 +157,69 @@ class CapturedEnsemble:
         self._fwd.replay()
         self._bwd.replay()
         return self.win.J, self.win.wh0, self.win.grad_s
+
+
+def trajectory_bytes(grids, windows):
+    """HBM held by an EnsembleWindow's stored trajectory: 5 N_b (T_b + 1) state values per box."""
+    return sum(5 * g.ncells * (int(t) + 1) * (8 if g.precision == F64 else 4) for g, t in zip(grids, windows))
+
+
+def plan(grids, windows, member_box, budget_bytes):
+    """Split an ensemble (boxes ordered by non-increasing window) into consecutive groups of boxes
+    whose stored trajectories each fit in `budget_bytes`; a box that alone exceeds the budget
+    forms a group of its own.  Returns [(first_box, end_box, first_member, end_member)]."""
+    groups, start, used = [], 0, 0
+    for b in range(len(grids)):
+        need = trajectory_bytes([grids[b]], [windows[b]])
+        if b > start and used + need > budget_bytes:
+            groups.append((start, b))
+            start, used = b, 0
+        used += need
+    groups.append((start, len(grids)))
+    out = []
+    for b0, b1 in groups:
+        m0 = bisect.bisect_left(member_box, b0)
+        m1 = bisect.bisect_left(member_box, b1)
+        out.append((b0, b1, m0, m1))
+    return out
+
+
+class PlannedEnsemble:
+    """An ensemble run group by group when its whole trajectory exceeds a memory budget (the
+    worst-case draws of the batched configuration need more than one GPU's HBM): each group of
+    consecutive boxes is one EnsembleWindow, built, swept forward and backward, and released
+    before the next.  Every member's results equal those of the single ensemble bit for bit (the
+    kernels see the same boxes and members, only fewer of them per launch).
+
+    results(m) -> (J_m, w^_0 of member m, dJ/ds of member m) as host copies after run()."""
+
+    def __init__(self, grids, windows, w0, s=None, member_box=None, member_lam=None, obj_kind=OBJ_MEAN_PRESSURE,
+                 budget_bytes=None, device="cuda"):
+        self.grids, self.windows, self.w0, self.s = list(grids), [int(t) for t in windows], list(w0), s
+        nb = len(self.grids)
+        self.member_box = list(range(nb)) if member_box is None else [int(b) for b in member_box]
+        self.member_lam = [0.0] * len(self.member_box) if member_lam is None else [float(x) for x in member_lam]
+        self.obj_kind, self.device = obj_kind, device
+        if budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info()
+            budget_bytes = int(0.5 * free)
+        self.groups = plan(self.grids, self.windows, self.member_box, budget_bytes)
+        self._res = {}
+
+    def run(self):
+        for b0, b1, m0, m1 in self.groups:
+            win = EnsembleWindow(self.grids[b0:b1], self.windows[b0:b1], self.w0[b0:b1],
+                                 None if self.s is None else self.s[b0:b1],
+                                 [b - b0 for b in self.member_box[m0:m1]], self.member_lam[m0:m1],
+                                 obj_kind=self.obj_kind, device=self.device)
+            win.forward()
+            wh0, gs = win.backward()
+            J = win.J.cpu()
+            for k in range(m1 - m0):
+                self._res[m0 + k] = (float(J[k]), win.member(wh0, k).cpu().clone(), win.member(gs, k).cpu().clone())
+            del win
+            torch.cuda.empty_cache()
+        return self
+
+    def results(self, m):
+        return self._res[m]

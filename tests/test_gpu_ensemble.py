@@ -9,7 +9,7 @@ import torch
 
 import paper_1511_06959_amd as adj
 from paper_1511_06959_amd import sweep
-from paper_1511_06959_amd.ensemble import CapturedEnsemble, EnsembleWindow
+from paper_1511_06959_amd.ensemble import CapturedEnsemble, EnsembleWindow, PlannedEnsemble, trajectory_bytes
 import workloads as W
 from tests.gpu_helpers import host, smooth_state
 
@@ -113,3 +113,25 @@ def test_ensemble_rejects_bad_orderings():
     mixed = grids[:1] + [_grid(wls[1], adj.F32)]
     with pytest.raises(adj.AdjError):
         adj.Ensemble(mixed, [0, 1], [0.0, 0.0])
+
+
+def test_planned_groups_equal_single_ensemble():
+    wls, windows, member_box, factors = _periodic_boxes()
+    grids = [_grid(wl, adj.F64) for wl in wls]
+    lams = [f * (2 * math.pi / wls[b].n[0]) ** 2 for f, b in zip(factors, member_box)]
+    s = _sources(wls, 72)
+    win = EnsembleWindow(grids, windows, [wl.w0 for wl in wls], s, member_box, lams)
+    win.forward()
+    wh, gs = win.backward()
+    J, wh, gs = host(win.J), host(wh), host(gs)
+    # a budget that holds the first box's trajectory but not the first two
+    budget = trajectory_bytes(grids[:1], windows[:1]) + 1
+    pe = PlannedEnsemble(grids, windows, [wl.w0 for wl in wls], s, member_box, lams, budget_bytes=budget)
+    assert len(pe.groups) >= 3 and pe.groups[0][:2] == (0, 1)
+    pe.run()
+    for m in range(len(member_box)):
+        Jm, whm, gsm = pe.results(m)
+        lo, hi = 5 * win.ens.offset(1, m), 5 * win.ens.offset(1, m + 1)
+        assert Jm == J[m], f"member {m}: J"
+        assert np.array_equal(whm.double().numpy(), wh[lo:hi]), f"member {m}: w^_0"
+        assert np.array_equal(gsm.double().numpy(), gs[lo:hi]), f"member {m}: grad_s"

@@ -50,3 +50,22 @@ def test_lambda_bound_is_the_rk4_diffusion_limit():
     # nu_max = lam * max weight * sigma; explicit RK4 needs nu_max dt sum_d 4/dx^2 <= 2.785,
     # i.e. nu_max dt / dx^2 <= 0.232 on a cube
     assert abs(lam * 2.0 * sig * g.dt / dx ** 2 - 2.785 / 12.0) <= 1e-12
+
+
+def test_ensemble_plan_groups():
+    from paper_1511_06959_amd.ensemble import plan, trajectory_bytes
+    grids = [adj.Grid.make((n, n, n), (1.0, 1.0, 1.0), 0.01, 0.01, precision=adj.F32) for n in (16, 8, 8, 4)]
+    windows = [10, 10, 5, 2]
+    member_box = [0, 0, 1, 2, 3, 3]
+    per = [trajectory_bytes([g], [t]) for g, t in zip(grids, windows)]
+    assert per[0] == 5 * 16 ** 3 * 11 * 4
+    assert plan(grids, windows, member_box, sum(per)) == [(0, 4, 0, 6)]
+    groups = plan(grids, windows, member_box, per[0])
+    assert groups[0] == (0, 1, 0, 2)
+    assert [g[:2] for g in groups] == [(0, 1), (1, 4)]  # the three smaller boxes fit together
+    assert [g[:2] for g in plan(grids, windows, member_box, per[1] + per[2])] == [(0, 1), (1, 3), (3, 4)]
+    # every box and member exactly once, in order
+    assert groups[-1][1] == 4 and groups[-1][3] == 6
+    assert all(a[1] == b[0] and a[3] == b[2] for a, b in zip(groups, groups[1:]))
+    # a box larger than the budget alone
+    assert plan(grids, windows, member_box, 1)[0] == (0, 1, 0, 2)
