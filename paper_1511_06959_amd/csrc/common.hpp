@@ -5,9 +5,9 @@
 
 namespace adjns {
 
-// Work-group tile of output cells for the stencil kernels: 16 x 4 x 4 = 256 threads (four
-// 64-wide wavefronts).  x is the unit-stride direction, so each wavefront reads 16-element
-// contiguous rows (128 B in FP64, 64 B in FP32) of every plane it touches.
+// Reference tiling of 16 x 4 x 4 cells: an upper bound on the number of tiles of any kernel that
+// writes one partial sum per tile (the workspace's partial-sum region is sized with it).  The
+// stencil kernels take their own tile shape (TILE_* below).
 constexpr int TX = 16, TY = 4, TZ = 4, NT = TX * TY * TZ;
 
 // Block size of the 1-D element-wise and reduction kernels.
@@ -21,8 +21,6 @@ struct TBox {
   static constexpr int BX = TX_ + 2 * HX, BY = TY_ + 2 * HY, BZ = TZ_ + 2 * HY;
   static constexpr int SY = BX, SZ = BX * BY, NB = BX * BY * BZ;
 };
-template <int HX, int HY = 1>
-using Box = TBox<TX, TY, TZ, HX, HY>;
 
 // Tile shapes the stencil kernels are compiled for (index = adj_set_tile's tile id).  A
 // wavefront covers 64 consecutive threads, x fastest: rows of 32 let each half-wavefront read 32

@@ -1,10 +1,10 @@
-// stencil.hip -- gfx950 kernels for one RK4 stage of the primal residual and one reverse stage of
-// the discrete adjoint (transposed convective, viscous and artificial-viscosity operators).
+// stencil.hip -- gfx950 kernels for one Runge-Kutta stage of the primal residual and one reverse
+// stage of the discrete adjoint (transposed convective, viscous and artificial-viscosity operators).
 //
-// Both kernels stage a (16+2h) x 6 x 6 box of cells (the 16x4x4 output tile plus its halo) in
-// LDS, derive the primitive variables once per box cell, and then evaluate each output cell's
-// 19-point stencil from LDS.  SoA var-major global layout; every global access of a wavefront is
-// to consecutive x addresses.
+// Both kernels stage a box of cells (the work-group's output tile, one of the TILE_* shapes, plus
+// a halo of one cell, two in x beside slip walls) in LDS, derive the primitive variables once per
+// box cell, and then evaluate each output cell's 19-point stencil from LDS.  SoA var-major global
+// layout; every global access of a wavefront is to consecutive x addresses.
 #include <type_traits>
 
 #include "kernels.hpp"
