@@ -1,7 +1,7 @@
 """Tile-shape autotuner for the two stencil kernel classes.
 
 For a grid and precision, every compiled tile shape of the reverse-stage kernel (timed through
-``vjp``) and of the RK4-stage kernel (timed through ``residual``) is run on the device with
+``vjp``) and of the primal-stage kernel (timed through ``residual``) is run on the device with
 HIP events, and the fastest is installed with ``set_tile``.  Results are cached in a JSON file
 keyed by library build, kernel class, precision, grid shape and boundary type, so a process pays
 for the search once per configuration.
