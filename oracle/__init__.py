@@ -29,6 +29,8 @@ class OrcGrid(ctypes.Structure):
         ("mu", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("scheme", ctypes.c_int32),
+        ("flux", ctypes.c_int32),
+        ("roe_delta", ctypes.c_double),
     ]
 
 
@@ -65,6 +67,7 @@ def lib():
         sig = {
             "orc_residual": [gp, dp, dp, dp],
             "orc_jvp": [gp, dp, dp, dp],
+            "orc_roe_flux": [gp, ctypes.c_int, dp, dp, dp],
             "orc_vjp": [gp, dp, dp, dp],
             "orc_lnu_apply": [gp, dp, dp, dp],
             "orc_primal_step": [gp, dp, dp, dp],
@@ -99,10 +102,15 @@ def num_threads():
 
 # ---------------------------------------------------------------------------------------------
 SCHEME_RK4, SCHEME_SSPRK3 = 0, 1
+FLUX_SPLIT, FLUX_ROE = 0, 1
 
 
-def make_grid(n, L, gamma=1.4, prandtl=0.72, mu=0.01, dt=0.0, bc_x=0, scheme=SCHEME_RK4):
-    """scheme: time marching, SCHEME_RK4 (classical RK4) or SCHEME_SSPRK3 (Shu-Osher SSP-RK3)."""
+def make_grid(n, L, gamma=1.4, prandtl=0.72, mu=0.01, dt=0.0, bc_x=0, scheme=SCHEME_RK4, flux=FLUX_SPLIT,
+              roe_delta=0.1):
+    """scheme: time marching, SCHEME_RK4 (classical RK4) or SCHEME_SSPRK3 (Shu-Osher SSP-RK3).
+    flux: convective face flux, FLUX_SPLIT (split central form) or FLUX_ROE (Roe's approximate
+    Riemann solver on linearly reconstructed face states, wave speeds |lam| smoothed within
+    roe_delta times the Roe sound speed)."""
     g = OrcGrid()
     for d in range(3):
         g.n[d] = int(n[d])
@@ -110,13 +118,17 @@ def make_grid(n, L, gamma=1.4, prandtl=0.72, mu=0.01, dt=0.0, bc_x=0, scheme=SCH
     g.bc_x = int(bc_x)
     g.gamma, g.prandtl, g.mu, g.dt = float(gamma), float(prandtl), float(mu), float(dt)
     g.scheme = int(scheme)
+    g.flux = int(flux)
+    g.roe_delta = float(roe_delta)
     return g
 
 
 def grid_from(p):
-    """Oracle grid from a plain parameter mapping (keys n, L, gamma, prandtl, mu, dt, bc_x[, scheme])."""
+    """Oracle grid from a plain parameter mapping (keys n, L, gamma, prandtl, mu, dt, bc_x[, scheme,
+    flux, roe_delta])."""
     return make_grid(p["n"], p["L"], p.get("gamma", 1.4), p.get("prandtl", 0.72), p["mu"],
-                     p.get("dt", 0.0), p.get("bc_x", 0), p.get("scheme", SCHEME_RK4))
+                     p.get("dt", 0.0), p.get("bc_x", 0), p.get("scheme", SCHEME_RK4), p.get("flux", FLUX_SPLIT),
+                     p.get("roe_delta", 0.1))
 
 
 def make_obj(kind=0, plane_i=0, pt_ref=0.0):
@@ -152,6 +164,15 @@ def residual(g, w, s=None):
     out = np.zeros(5 * N)
     _chk(lib().orc_residual(ctypes.byref(g), wp, sp, _d(out)[1]), "residual")
     return out
+
+
+def roe_flux(g, d, wl, wr):
+    """Roe flux between two face states (5 conservative values each) in direction d."""
+    wl, pl = _d(wl)
+    wr, pr = _d(wr)
+    F, pF = _d(np.zeros(5))
+    _chk(lib().orc_roe_flux(ctypes.byref(g), int(d), pl, pr, pF), "roe_flux")
+    return F
 
 
 def jvp(g, W, v):

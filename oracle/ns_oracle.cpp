@@ -59,6 +59,8 @@ typedef struct orc_grid {
   double L[3];
   double gamma, prandtl, mu, dt;
   int32_t scheme;  // time marching: 0 classical RK4, 1 strong-stability-preserving RK3
+  int32_t flux;    // convective face flux: 0 split central form, 1 Roe upwind flux
+  double roe_delta;  // flux 1: width of the smoothing of |wave speed|, as a fraction of the Roe sound speed
 } orc_grid;
 
 typedef struct orc_obj {
@@ -113,19 +115,26 @@ template <int N> Dual<N> pow(const Dual<N>& a, double e) {
 using std::sqrt;
 using std::pow;
 
+// Value of a plain or dual number, for branch decisions.
+inline double val(double x) { return x; }
+inline double val(const std::complex<double>& x) { return x.real(); }
+template <int N> double val(const Dual<N>& x) { return x.v; }
+
 // ------------------------------------------------------------------------------------------
 // Grid helpers
 // ------------------------------------------------------------------------------------------
 struct G {
   long nx, ny, nz, N;
   double dx[3];
-  int wall, scheme;
-  double gamma, pr, mu, alpha, dt;
+  int wall, scheme, flux;
+  double gamma, pr, mu, alpha, dt, roe_delta;
   explicit G(const orc_grid* g) {
     nx = g->n[0]; ny = g->n[1]; nz = g->n[2]; N = nx * ny * nz;
     for (int d = 0; d < 3; ++d) dx[d] = g->L[d] / (double)g->n[d];
     wall = g->bc_x;
     scheme = g->scheme;
+    flux = g->flux;
+    roe_delta = g->roe_delta;
     gamma = g->gamma; pr = g->prandtl; mu = g->mu; dt = g->dt;
     alpha = gamma * mu / pr;  // heat flux alpha grad e == (mu c_p / Pr) grad T, since e = c_v T
   }
@@ -192,11 +201,78 @@ void conv_face_flux(int d, const Prim<T>& L, const Prim<T>& R, T F[5]) {
   F[4] = m * H + P * v[d];
 }
 
+// |lam| smoothed inside |lam| < delta (Harten's entropy fix): (lam^2 + delta^2) / (2 delta) there.
+// Value and slope match |lam| at |lam| = delta, so the flux is differentiable everywhere and its
+// discrete adjoint exists (plain |lam| has no derivative where a wave speed is zero).
+template <class T>
+T smooth_abs(const T& lam, const T& delta) {
+  if (val(lam) >= val(delta)) return lam;
+  if (val(lam) <= -val(delta)) return -lam;
+  return (lam * lam + delta * delta) / (2.0 * delta);
+}
+
+// Roe's approximate Riemann solver between face states wl and wr in direction d [Numerical
+// methods: approximate Roe solver]:  F = (F_d(wl) + F_d(wr))/2 - (1/2) sum_k |lam_k| a_k r_k, with
+// the Roe averages (weights sqrt(rho)) u~, H~ (H = (rho E + p)/rho), rho~ = sqrt(rho_l rho_r),
+// c~^2 = (gamma-1)(H~ - |u~|^2/2), and the jumps d(.) = (.)_r - (.)_l of rho, u and p:
+//   acoustic waves  lam = u~_d -+ c~,  a = (dp -+ rho~ c~ du_d) / (2 c~^2),  r = (1, u~ -+ c~ e_d, H~ -+ u~_d c~)
+//   entropy wave    lam = u~_d,        a = drho - dp / c~^2,                r = (1, u~, |u~|^2/2)
+//   shear waves     lam = u~_d,        a r = rho~ (0, du - du_d e_d, u~.du - u~_d du_d)
+// Every |lam| is smoothed with delta = roe_delta c~ (smooth_abs).
+template <class T>
+void roe_face_flux(const G& g, int d, const T wl[5], const T wr[5], T F[5]) {
+  const Prim<T> L = prim(g, wl), R = prim(g, wr);
+  const T HL = (L.E + L.p) / L.rho, HR = (R.E + R.p) / R.rho;
+  const T sl = sqrt(L.rho), sr = sqrt(R.rho);
+  const T fl = sl / (sl + sr), fr = sr / (sl + sr);
+  T u[3], du[3];
+  for (int k = 0; k < 3; ++k) {
+    u[k] = fl * L.u[k] + fr * R.u[k];
+    du[k] = R.u[k] - L.u[k];
+  }
+  const T H = fl * HL + fr * HR;
+  const T q2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const T c2 = (g.gamma - 1.0) * (H - 0.5 * q2);
+  const T c = sqrt(c2);
+  const T rt = sl * sr;
+  const T un = u[d], dun = du[d];
+  const T drho = R.rho - L.rho, dp = R.p - L.p;
+  const T delta = g.roe_delta * c;
+  const T l1 = smooth_abs(un - c, delta), l2 = smooth_abs(un, delta), l5 = smooth_abs(un + c, delta);
+  const T s1 = l1 * (dp - rt * c * dun) / (2.0 * c2);  // |lam| a of the acoustic waves
+  const T s5 = l5 * (dp + rt * c * dun) / (2.0 * c2);
+  const T s2 = l2 * (drho - dp / c2);                    // |lam| a of the entropy wave
+  const T udu = u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
+  T D[5];
+  D[0] = s1 + s5 + s2;
+  for (int k = 0; k < 3; ++k) {
+    D[1 + k] = (s1 + s5 + s2) * u[k] + l2 * rt * du[k];
+    if (k == d) D[1 + k] = D[1 + k] + (s5 - s1) * c - l2 * rt * dun;
+  }
+  D[4] = s1 * (H - un * c) + s5 * (H + un * c) + s2 * (0.5 * q2) + l2 * rt * (udu - un * dun);
+  // cell fluxes F_d(w) = (rho u_d, rho u_d u + p e_d, (rho E + p) u_d)
+  T FL[5], FR[5];
+  FL[0] = wl[1 + d];
+  FR[0] = wr[1 + d];
+  for (int k = 0; k < 3; ++k) {
+    FL[1 + k] = wl[1 + d] * L.u[k];
+    FR[1 + k] = wr[1 + d] * R.u[k];
+  }
+  FL[1 + d] = FL[1 + d] + L.p;
+  FR[1 + d] = FR[1 + d] + R.p;
+  FL[4] = (L.E + L.p) * L.u[d];
+  FR[4] = (R.E + R.p) * R.u[d];
+  for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * D[v];
+}
+
 inline void tangents(int d, int& t1, int& t2) { t1 = (d == 0) ? 1 : 0; t2 = (d == 2) ? 1 : 2; }
 
 // Stencil of the face between cell L=(i,j,k) and R=L+e_d: slots
-//   0 L, 1 R, 2 L+e_t1, 3 L-e_t1, 4 L+e_t2, 5 L-e_t2, 6 R+e_t1, 7 R-e_t1, 8 R+e_t2, 9 R-e_t2
-void face_slots(const G& g, int d, long i, long j, long k, Slot st[10]) {
+//   0 L, 1 R, 2 L+e_t1, 3 L-e_t1, 4 L+e_t2, 5 L-e_t2, 6 R+e_t1, 7 R-e_t1, 8 R+e_t2, 9 R-e_t2,
+//   and with the Roe flux 10 L-e_d, 11 R+e_d (the reconstruction stencil)
+constexpr int NSLOT = 12;
+inline int nslots(const G& g) { return g.flux == 1 ? 12 : 10; }
+void face_slots(const G& g, int d, long i, long j, long k, Slot st[NSLOT]) {
   long L[3] = {i, j, k};
   long R[3] = {i, j, k};
   R[d] += 1;
@@ -209,19 +285,31 @@ void face_slots(const G& g, int d, long i, long j, long k, Slot st[10]) {
   st[0] = sl(L, -1, 0); st[1] = sl(R, -1, 0);
   st[2] = sl(L, t1, +1); st[3] = sl(L, t1, -1); st[4] = sl(L, t2, +1); st[5] = sl(L, t2, -1);
   st[6] = sl(R, t1, +1); st[7] = sl(R, t1, -1); st[8] = sl(R, t2, +1); st[9] = sl(R, t2, -1);
+  st[10] = sl(L, d, -1); st[11] = sl(R, d, +1);
 }
 
 // Total face flux H = F~ - F~^v on the face between slot 0 (L) and slot 1 (R) in direction d.
-//   F~   = split-form convective face flux (conv_face_flux)
+//   F~   = split-form convective face flux (conv_face_flux), or with the Roe flux roe_face_flux of
+//          the face states reconstructed linearly with central cell gradients (second order):
+//          w_l = w_L + (w_R - w_{L-e_d})/4,  w_r = w_R - (w_{R+e_d} - w_L)/4
 //   F~^v = (0, sigma_d., u_f . sigma_d. + alpha d_d e), u_f = 0.5 (u_L + u_R)
 //   face gradient d_l u_k: l == d -> (u_R - u_L)/dx_d ; l != d -> mean of the central
 //   differences of cells L and R in direction l.
 template <class T>
-void face_flux(const G& g, int d, const T st[10][5], T H[5]) {
+void face_flux(const G& g, int d, const T (*st)[5], T H[5]) {
   Prim<T> q[10];
   for (int s = 0; s < 10; ++s) q[s] = prim(g, st[s]);
   T Fc[5];
-  conv_face_flux(d, q[0], q[1], Fc);
+  if (g.flux == 1) {
+    T wl[5], wr[5];
+    for (int v = 0; v < 5; ++v) {
+      wl[v] = st[0][v] + 0.25 * (st[1][v] - st[10][v]);
+      wr[v] = st[1][v] - 0.25 * (st[11][v] - st[0][v]);
+    }
+    roe_face_flux(g, d, wl, wr, Fc);
+  } else {
+    conv_face_flux(d, q[0], q[1], Fc);
+  }
   int t[2]; tangents(d, t[0], t[1]);
   T gu[3][3];  // gu[l][k] = d_l u_k at the face
   for (int k = 0; k < 3; ++k) {
@@ -298,9 +386,9 @@ template <class T>
 void residual(const G& g, const T* w, const T* s, T* R) {
   for (long x = 0; x < 5 * g.N; ++x) R[x] = T(0.0);
   face_scatter<T>(g, 5 * g.N, R, [&](int d, long i, long j, long k, T* acc) {
-    Slot sl[10]; face_slots(g, d, i, j, k, sl);
-    T st[10][5];
-    for (int a = 0; a < 10; ++a) load_slot(g, w, sl[a], st[a]);
+    Slot sl[NSLOT]; face_slots(g, d, i, j, k, sl);
+    T st[NSLOT][5];
+    for (int a = 0; a < nslots(g); ++a) load_slot(g, w, sl[a], st[a]);
     T H[5]; face_flux(g, d, st, H);
     for (int v = 0; v < 5; ++v) {
       if (sl[0].real) acc[v * g.N + sl[0].c] -= H[v] / g.dx[d];
@@ -311,15 +399,17 @@ void residual(const G& g, const T* w, const T* s, T* R) {
     for (long x = 0; x < 5 * g.N; ++x) R[x] += s[x];
 }
 
-// out = J_R(W)^T kh : for every face, the 5 x 50 local Jacobian dH/d(stencil) from dual numbers,
-// contracted with the adjoint weights (kh_R - kh_L)/dx_d and scattered to the stencil cells.
-void vjp(const G& g, const double* W, const double* kh, double* out) {
-  constexpr int ND = 50;
+// out = J_R(W)^T kh : for every face, the local Jacobian dH/d(stencil) (5 x 5NS, NS slots) from
+// dual numbers, contracted with the adjoint weights (kh_R - kh_L)/dx_d and scattered to the
+// stencil cells.
+template <int NS>
+void vjp_slots(const G& g, const double* W, const double* kh, double* out) {
+  constexpr int ND = 5 * NS;
   for (long x = 0; x < 5 * g.N; ++x) out[x] = 0.0;
   face_scatter<double>(g, 5 * g.N, out, [&](int d, long i, long j, long k, double* acc) {
-    Slot sl[10]; face_slots(g, d, i, j, k, sl);
-    Dual<ND> st[10][5];
-    for (int a = 0; a < 10; ++a)
+    Slot sl[NSLOT]; face_slots(g, d, i, j, k, sl);
+    Dual<ND> st[NSLOT][5];
+    for (int a = 0; a < NS; ++a)
       for (int v = 0; v < 5; ++v) {
         double sg = mirror_sign(sl[a].mirror, v);
         st[a][v] = Dual<ND>(sg * W[v * g.N + sl[a].c]);
@@ -332,13 +422,20 @@ void vjp(const G& g, const double* W, const double* kh, double* out) {
       double l = sl[0].real ? kh[o * g.N + sl[0].c] : 0.0;
       om[o] = (r - l) / g.dx[d];
     }
-    for (int a = 0; a < 10; ++a)
+    for (int a = 0; a < NS; ++a)
       for (int v = 0; v < 5; ++v) {
         double sum = 0.0;
         for (int o = 0; o < 5; ++o) sum += om[o] * H[o].d[a * 5 + v];
         acc[v * g.N + sl[a].c] += sum;
       }
   });
+}
+
+void vjp(const G& g, const double* W, const double* kh, double* out) {
+  if (nslots(g) == 12)
+    vjp_slots<12>(g, W, kh, out);
+  else
+    vjp_slots<10>(g, W, kh, out);
 }
 
 // out = J_R(W) v  (tangent), by evaluating the residual on single-direction dual numbers.
@@ -356,7 +453,7 @@ void jvp(const G& g, const double* W, const double* v, double* out) {
 // ------------------------------------------------------------------------------------------
 void lnu_apply(const G& g, const double* const nu[5], const double* q, double* out) {
   face_scatter<double>(g, 5 * g.N, out, [&](int d, long i, long j, long k, double* acc) {
-    Slot sl[10]; face_slots(g, d, i, j, k, sl);
+    Slot sl[NSLOT]; face_slots(g, d, i, j, k, sl);
     if (!sl[0].real || !sl[1].real) return;
     for (int v = 0; v < 5; ++v) {
       double nf = 0.5 * (nu[v][sl[0].c] + nu[v][sl[1].c]);
@@ -700,6 +797,16 @@ static int check(const orc_grid* g) {
     if (g->n[d] < 1 || !(g->L[d] > 0)) return -1;
   if (g->bc_x == 1 && g->n[0] < 2) return -1;
   if (g->scheme != 0 && g->scheme != 1) return -1;
+  if (g->flux != 0 && g->flux != 1) return -1;
+  if (g->flux == 1 && !(g->roe_delta > 0.0)) return -1;
+  return 0;
+}
+
+// F = Roe flux between the face states wl and wr in direction d (no reconstruction)
+int orc_roe_flux(const orc_grid* gr, int d, const double* wl, const double* wr, double* F) {
+  if (check(gr) || d < 0 || d > 2) return -1;
+  G g(gr);
+  roe_face_flux<double>(g, d, wl, wr, F);
   return 0;
 }
 

@@ -13,6 +13,13 @@ the oracle's code:
                 energy     = u0 . momentum + alpha sum_d D_dd e'
     with D_dd = -4 sin^2(k_d dx_d / 2)/dx_d^2 (normal face gradient) and
     D_dt = -sin(k_d dx_d) sin(k_t dx_t)/(dx_d dx_t) (face-averaged central tangential gradient).
+    Roe upwind flux on linearly reconstructed face states, at theta = k_d dx_d:
+      face states  w_l = a_l w', w_r = a_r w' with a_l = 1 + i sin(theta)/2,
+                   a_r = e^{i theta} (1 - i sin(theta)/2)   (w_l = w_i + (w_{i+1}-w_{i-1})/4, ...)
+      face flux    A_d (a_l + a_r)/2 - |A_d| (a_r - a_l)/2, |A_d| = R diag(|lam|_s) R^-1 from the
+                   eigen-decomposition of A_d (the Roe matrix of two equal states is A_d), |lam|_s
+                   = |lam| outside |lam| < delta, (lam^2 + delta^2)/(2 delta) inside
+      residual     -(1 - e^{-i theta}) face flux / dx_d
 * Symmetriser S (printed), V = dq/dw (printed, with the sign of the u_j/rho entries corrected),
   T = S V, and the printed symmetrised flux matrices A^_d.
 """
@@ -53,13 +60,33 @@ def prim_linearisation(rho, u, p, gamma):
     return P
 
 
-def semi_discrete_symbol(k, dx, rho, u, p, gamma, mu, prandtl):
-    """5x5 complex symbol L(k) of the linearised residual at a uniform state."""
+def smoothed_abs(lam, delta):
+    lam = np.asarray(lam)
+    return np.where(np.abs(lam) >= delta, np.abs(lam), (lam * lam + delta * delta) / (2.0 * delta))
+
+
+def abs_matrix(A, delta):
+    """R diag(|lam|_s) R^-1 of a matrix with real eigenvalues (numpy's eigen-decomposition)."""
+    lam, R = np.linalg.eig(A)
+    return np.real(R @ np.diag(smoothed_abs(np.real(lam), delta)) @ np.linalg.inv(R))
+
+
+def semi_discrete_symbol(k, dx, rho, u, p, gamma, mu, prandtl, roe_delta=None):
+    """5x5 complex symbol L(k) of the linearised residual at a uniform state (convective part of
+    the central flux, or of the Roe flux when roe_delta is given)."""
     u = np.asarray(u, dtype=float)
     alpha = gamma * mu / prandtl
     Lk = np.zeros((5, 5), dtype=complex)
     for d in range(3):
-        Lk += -1j * euler_jacobian(d, rho, u, p, gamma) * np.sin(k[d] * dx[d]) / dx[d]
+        A = euler_jacobian(d, rho, u, p, gamma)
+        th = k[d] * dx[d]
+        if roe_delta is None:
+            Lk += -1j * A * np.sin(th) / dx[d]
+        else:
+            al = 1.0 + 0.5j * np.sin(th)
+            ar = np.exp(1j * th) * (1.0 - 0.5j * np.sin(th))
+            absA = abs_matrix(A, roe_delta * np.sqrt(gamma * p / rho))
+            Lk += -(1.0 - np.exp(-1j * th)) / dx[d] * (0.5 * (al + ar) * A - 0.5 * (ar - al) * absA)
     D = np.zeros((3, 3))
     for a in range(3):
         for b in range(3):
