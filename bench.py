@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ROE_DELTA = 0.1  # Roe flux option: |lam| smoothed within 0.1 c~ of zero
 VALU_PEAK_TFLOPS = 157.3  # FP32 vector, 256 CUs x 2.4 GHz x 256 operations per clock
 METRIC = "adjoint cell-steps/s + % HBM roofline, FP32/BF16-ckpt vs FP64 at stated rel err"
 
@@ -98,7 +99,7 @@ def _tile_report(res, g, lnu):
     return out
 
 
-def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=False, time_scheme=0):
+def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=False, time_scheme=0, flux=0):
     import torch
 
     import paper_1511_06959_amd as adj
@@ -108,7 +109,8 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     # FP32 states are stored as deviations from the mean initial state (see adj_grid.w_ref)
     w_ref = adj.reference_state(wl.w0) if precision == adj.F32 else None
     g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision,
-                      adj.CKPT_BF16 if ckpt_bf16 else adj.CKPT_NATIVE, w_ref, time_scheme=time_scheme)
+                      adj.CKPT_BF16 if ckpt_bf16 else adj.CKPT_NATIVE, w_ref, time_scheme=time_scheme, flux=flux,
+                      roe_delta=ROE_DELTA)
     tiles = {}
     if tune:
         tiles = _tile_report(autotune.tune(g), g, wl.lam > 0.0)
@@ -144,7 +146,8 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     prof = {}
     for name, cls in (("adjoint_stage", adj.PROF_ADJOINT_STAGE), ("primal_stage", adj.PROF_PRIMAL_STAGE),
                       ("objective", adj.PROF_OBJECTIVE), ("sigma1", adj.PROF_SIGMA1), ("codec", adj.PROF_CODEC),
-                      ("reduce", adj.PROF_REDUCE)):
+                      ("reduce", adj.PROF_REDUCE), ("roe_primal", adj.PROF_ROE_PRIMAL),
+                      ("roe_adjoint", adj.PROF_ROE_ADJOINT)):
         prof[name] = adj.profile_read(cls)
     del traj, ws
     torch.cuda.empty_cache()
@@ -182,6 +185,16 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     out["stage_avg_us"] = avg_s * 1e6
     out["stage_alg_bytes"] = alg_bytes
     out["stage_achieved_gbs"] = alg_bytes / avg_s / 1e9
+    if flux == 1:
+        # Roe corrections: the primal kernel reads W and updates out (15 values per cell), the
+        # reverse kernel reads W, a, gnext and updates out (25 values per cell)
+        out["roe"] = {}
+        for name, vals in (("roe_primal", 15), ("roe_adjoint", 25)):
+            ms_k, n_k = prof[name]
+            us = ms_k / n_k * 1e3
+            byts = vals * esz * cells
+            out["roe"][name] = {"avg_launch_us": us, "alg_bytes_per_launch": byts,
+                                "achieved_gbs": byts / us / 1e3, "frac_hbm": byts / us / 1e3 / HBM_PEAK_GBS}
     Jt, wh0, gs = cw.J, cw.wh0, cw.grad_s
     out["tiles"] = tiles
     out["J"] = float(Jt.cpu()[0])
@@ -280,12 +293,14 @@ def run_ensemble(boxes, precision, steps, warmup, tune=True):
     return out
 
 
-def cpu_baseline(wl, budget_s):
+def cpu_baseline(wl, budget_s, flux=0):
     """The FP64 oracle as it stands, on the host cores: whole primal + reverse steps of the
     same 64^3 field, repeated until about budget_s seconds have been spent."""
     import oracle
 
-    og = oracle.grid_from(wl.params())
+    p = wl.params()
+    p["flux"], p["roe_delta"] = flux, ROE_DELTA
+    og = oracle.grid_from(p)
     obj = oracle.make_obj(wl.obj_kind)
     w = wl.w0
     a = np.random.default_rng(0).standard_normal(w.size) * 1e-3
@@ -366,8 +381,11 @@ def main():
                          "step recomputes them from w_n")
     ap.add_argument("--time-scheme", default="rk4", choices=("rk4", "ssprk3"),
                     help="time marching: classical RK4, or the strong-stability-preserving RK3 of the paper")
+    ap.add_argument("--flux", default="split", choices=("split", "roe"),
+                    help="convective flux: split central form, or the paper's Roe upwind flux")
     args = ap.parse_args()
     args.ts = 1 if args.time_scheme == "ssprk3" else 0
+    args.fl = 1 if args.flux == "roe" else 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
               "design note, not part of this build)", file=sys.stderr)
@@ -395,16 +413,16 @@ def main():
           file=sys.stderr, flush=True)
     # the large configurations keep BF16 checkpoint records on the FP32 path
     r32 = run_gpu(wl, adj.F32, args.steps, args.warmup, not args.no_autotune, stages=stages, ckpt_bf16=big,
-                  time_scheme=args.ts)
+                  time_scheme=args.ts, flux=args.fl)
     print(f"[bench] f32 window {r32['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
     r32b = None
     if stages:
-        r32b = run_gpu(wl, adj.F32, args.steps, args.warmup, False, stages=False, time_scheme=args.ts)
+        r32b = run_gpu(wl, adj.F32, args.steps, args.warmup, False, stages=False, time_scheme=args.ts, flux=args.fl)
         print(f"[bench] f32 window, recompute schedule {r32b['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_f64:
         r64 = run_gpu(wl, adj.F64, args.steps, args.warmup, not args.no_autotune, stages=stages,
-                      time_scheme=args.ts)
+                      time_scheme=args.ts, flux=args.fl)
         print(f"[bench] f64 window {r64['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
 
     def rel(a, b):
@@ -433,6 +451,8 @@ def main():
             "workload": WORKLOADS[args.workload].format(n=wl.nsteps).replace(
                 "RK4 steps", "SSP-RK3 steps" if args.ts == 1 else "RK4 steps"),
             "time_scheme": args.time_scheme,
+            "flux": ("Roe upwind flux (linear reconstruction, |lam| smoothed within %g c~)" % ROE_DELTA
+                     if args.fl else "split central form (Kennedy-Gruber)"),
             "cells": wl.ncells,
             "window_steps": wl.nsteps,
             "dt": wl.dt,
@@ -460,6 +480,8 @@ def main():
         "launch": "each window replayed as two captured HIP graphs (forward sweep, reverse sweep)",
         "tiles": r32["tiles"],
     }
+    if "roe" in r32:
+        line["roe_kernels"] = r32["roe"]
     if r32b is not None:
         line["f32_recompute_schedule"] = {"value": r32b["value"], "ms_per_step": r32b["ms_per_step"],
                                           "adjoint_sweep_cell_steps_per_s": r32b["adjoint_sweep_cell_steps_per_s"]}
@@ -484,7 +506,7 @@ def main():
                     "path matches the FP64 oracle to 1e-10 on the 16^3 window in the test suite",
         }
     if not args.no_cpu_baseline and not big:
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.fl)
     print(json.dumps(line), flush=True)
 
 

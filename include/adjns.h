@@ -62,6 +62,7 @@ enum { ADJ_BC_PERIODIC = 0, ADJ_BC_SLIP_WALLS = 1 };
 enum { ADJ_F64 = 0, ADJ_F32 = 1 };
 enum { ADJ_CKPT_NATIVE = 0, ADJ_CKPT_BF16 = 1 };
 enum { ADJ_RK4 = 0, ADJ_SSPRK3 = 1 };
+enum { ADJ_FLUX_SPLIT = 0, ADJ_FLUX_ROE = 1 };
 enum {
   ADJ_OBJ_NONE = 0,
   ADJ_OBJ_MEAN_PRESSURE = 1,  /* j = (1/N) sum_cells p                                         */
@@ -103,6 +104,18 @@ typedef struct adj_grid {
                           w_next = 1/3 w + 2/3 (u2 + dt R(u2))  [Numerical methods].  Every
                           single-box call follows it, with the exact discrete adjoint of the
                           chosen scheme; ensembles (adj_batch_*) take ADJ_RK4 grids only.       */
+  int32_t flux;        /* convective face flux: ADJ_FLUX_SPLIT (the default) takes the face means
+                          of rho, u, E/rho and p in the split product form of Kennedy & Gruber,
+                          F = r v_d (1, v, H) + P (0, e_d, v_d); ADJ_FLUX_ROE is Roe's
+                          approximate Riemann solver, the paper's flux [Numerical methods], on
+                          face states reconstructed linearly with central cell gradients,
+                          w_l = w_L + (w_R - w_{L-e_d})/4, w_r = w_R - (w_{R+e_d} - w_L)/4:
+                          F = (F_d(w_l) + F_d(w_r))/2 - (1/2) sum_k |lam_k| a_k r_k over the
+                          acoustic, entropy and shear waves of the Roe average (weights
+                          sqrt(rho)).  Ensembles take ADJ_FLUX_SPLIT grids only.                */
+  double roe_delta;    /* ADJ_FLUX_ROE: every |lam| is smoothed within delta = roe_delta c~ of
+                          zero (Harten: (lam^2 + delta^2)/(2 delta) there), so that the flux is
+                          differentiable and its discrete adjoint exists; finite and > 0       */
 } adj_grid;
 
 typedef struct adj_objective {
@@ -204,12 +217,14 @@ int adj_vjp(const adj_grid* grid, const void* W, const void* kh, const void* nu,
  * stops recording and keeps the records; not thread-safe (one host thread). */
 enum {
   ADJ_PROF_ADJOINT_STAGE = 0, /* reverse-stage gather kernels                   */
-  ADJ_PROF_PRIMAL_STAGE = 1,  /* RK4 stage kernels (primal and recomputation)   */
+  ADJ_PROF_PRIMAL_STAGE = 1,  /* primal stage kernels (also recomputation)      */
   ADJ_PROF_SIGMA1 = 2,        /* growth-matrix singular value                   */
   ADJ_PROF_OBJECTIVE = 3,     /* objective values and gradients                 */
   ADJ_PROF_CODEC = 4,         /* checkpoint encode / decode                     */
   ADJ_PROF_REDUCE = 5,        /* energy and inner products                      */
-  ADJ_PROF_NCLASS = 6
+  ADJ_PROF_ROE_PRIMAL = 6,    /* Roe flux correction of primal stages           */
+  ADJ_PROF_ROE_ADJOINT = 7,   /* its transpose in reverse stages                */
+  ADJ_PROF_NCLASS = 8
 };
 int adj_profile_enable(int on);
 int adj_profile_read(int kernel_class, double* total_ms, long long* launches);

@@ -97,6 +97,9 @@ int check_grid(const adj_grid* g, bool need_dt) {
   if (g->precision != ADJ_F64 && g->precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", g->precision);
   if (g->time_scheme != ADJ_RK4 && g->time_scheme != ADJ_SSPRK3)
     return fail(ADJ_EINVAL, "bad time_scheme %d", g->time_scheme);
+  if (g->flux != ADJ_FLUX_SPLIT && g->flux != ADJ_FLUX_ROE) return fail(ADJ_EINVAL, "bad flux %d", g->flux);
+  if (g->flux == ADJ_FLUX_ROE && (!(g->roe_delta > 0.0) || !std::isfinite(g->roe_delta)))
+    return fail(ADJ_EINVAL, "roe_delta must be finite and > 0");
   if (5 * (double)ncells(g) * (g->precision == ADJ_F64 ? 8.0 : 4.0) >= 4294967296.0)
     return fail(ADJ_ESHAPE, "state arrays must span less than 4 GiB (%lld cells)", ncells(g));
   if (g->ckpt_format != ADJ_CKPT_NATIVE && g->ckpt_format != ADJ_CKPT_BF16)
@@ -158,6 +161,34 @@ size_t ckpt_header_bytes(const adj_grid* g) {
   return up(nb * 10 * sizeof(float));
 }
 
+// One primal stage (launch_primal_stage) and, on a Roe-flux grid, the correction of its residual
+// to the Roe flux, weighted like R in the stage (cR; dt/6 in stage 4; 1 for the plain residual).
+template <typename T>
+int primal_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
+                 const T* W3, T cR, T* out, hipStream_t st, const char* what, T ca = T(0), T cb = T(0)) {
+  hipError_t e;
+  if ((e = launch_primal_stage<T>(mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb))) return hip_fail(e, what);
+  if (g->flux == ADJ_FLUX_ROE) {
+    const T coef = mode == STAGE_FIN ? c.dt / T(6) : (mode == STAGE_RES ? T(1) : cR);
+    if ((e = launch_roe_primal<T>(c, (T)g->roe_delta, W, coef, out, st))) return hip_fail(e, what);
+  }
+  return ADJ_OK;
+}
+
+// One reverse stage (launch_adjoint_stage) and, on a Roe-flux grid, the transpose of the
+// correction applied to the same kh = ca a + cg gnext, added into `out` (g, or w^_n in stage 1).
+template <typename T>
+int adjoint_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext,
+                  const T* nu, T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st,
+                  const char* what) {
+  hipError_t e;
+  if ((e = launch_adjoint_stage<T>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st))) return hip_fail(e, what);
+  if (g->flux == ADJ_FLUX_ROE) {
+    if ((e = launch_roe_adjoint<T>(c, (T)g->roe_delta, W, a, gnext, ca, cg, out, st))) return hip_fail(e, what);
+  }
+  return ADJ_OK;
+}
+
 template <typename T>
 int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, T* stages, void* ws, hipStream_t st) {
   const Consts<T> c = consts<T>(g);
@@ -168,22 +199,22 @@ int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, 
   T* W4 = stages ? stages + 2 * S5 : (T*)at(ws, L.W4);
   const T h = c.dt * T(0.5);
   hipError_t e;
+  int r;
   if (g->time_scheme == ADJ_SSPRK3) {
     // u1 = w + dt R(w) (in W2), u2 = 3/4 w + 1/4 u1 + dt/4 R(u1) (in W3), w_next = 1/3 w + 2/3 u2 +
     // 2 dt/3 R(u2); the affine weights sum to one, so stored deviations w - w_ref combine alike
-    if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, c.dt, W2, st)))
-      return hip_fail(e, "primal stage 1");
-    if ((e = launch_primal_stage<T>(STAGE_AFF, c, W2, wn, s, nullptr, nullptr, c.dt * T(0.25), W3, st, T(0.75),
-                                    T(0.25))))
-      return hip_fail(e, "primal stage 2");
-    if ((e = launch_primal_stage<T>(STAGE_AFF, c, W3, wn, s, nullptr, nullptr, c.dt * T(2.0 / 3.0), out, st,
-                                    T(1.0 / 3.0), T(2.0 / 3.0))))
-      return hip_fail(e, "primal stage 3");
+    if ((r = primal_stage<T>(g, STAGE_LIN, c, wn, wn, s, nullptr, nullptr, c.dt, W2, st, "primal stage 1"))) return r;
+    if ((r = primal_stage<T>(g, STAGE_AFF, c, W2, wn, s, nullptr, nullptr, c.dt * T(0.25), W3, st, "primal stage 2",
+                             T(0.75), T(0.25))))
+      return r;
+    if ((r = primal_stage<T>(g, STAGE_AFF, c, W3, wn, s, nullptr, nullptr, c.dt * T(2.0 / 3.0), out, st,
+                             "primal stage 3", T(1.0 / 3.0), T(2.0 / 3.0))))
+      return r;
   } else {
-    if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st))) return hip_fail(e, "primal stage 1");
-    if ((e = launch_primal_stage<T>(STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st))) return hip_fail(e, "primal stage 2");
-    if ((e = launch_primal_stage<T>(STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st))) return hip_fail(e, "primal stage 3");
-    if ((e = launch_primal_stage<T>(STAGE_FIN, c, W4, wn, s, W2, W3, T(0), out, st))) return hip_fail(e, "primal stage 4");
+    if ((r = primal_stage<T>(g, STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st, "primal stage 1"))) return r;
+    if ((r = primal_stage<T>(g, STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st, "primal stage 2"))) return r;
+    if ((r = primal_stage<T>(g, STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st, "primal stage 3"))) return r;
+    if ((r = primal_stage<T>(g, STAGE_FIN, c, W4, wn, s, W2, W3, T(0), out, st, "primal stage 4"))) return r;
   }
   if (ckpt) {
     if constexpr (sizeof(T) == sizeof(float)) {
@@ -208,16 +239,17 @@ int adjoint_step_rk3(const adj_grid* g, const Consts<T>& c, const WsLayout& L, c
   const long long S5 = 5 * c.N;
   const T dt = c.dt;
   hipError_t e;
+  int r;
   const T *u1 = (T*)at(ws, L.W2), *u2 = (T*)at(ws, L.W3);
   if (stages) {
     u1 = stages;
     u2 = stages + S5;
   } else {
-    if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, dt, (T*)at(ws, L.W2), st)))
-      return hip_fail(e, "recompute u1");
-    if ((e = launch_primal_stage<T>(STAGE_AFF, c, (T*)at(ws, L.W2), wn, s, nullptr, nullptr, dt * T(0.25),
-                                    (T*)at(ws, L.W3), st, T(0.75), T(0.25))))
-      return hip_fail(e, "recompute u2");
+    if ((r = primal_stage<T>(g, STAGE_LIN, c, wn, wn, s, nullptr, nullptr, dt, (T*)at(ws, L.W2), st, "recompute u1")))
+      return r;
+    if ((r = primal_stage<T>(g, STAGE_AFF, c, (T*)at(ws, L.W2), wn, s, nullptr, nullptr, dt * T(0.25),
+                             (T*)at(ws, L.W3), st, "recompute u2", T(0.75), T(0.25))))
+      return r;
   }
   T* nu = (T*)at(ws, L.nu);
   const T* nup = nullptr;
@@ -228,15 +260,16 @@ int adjoint_step_rk3(const adj_grid* g, const Consts<T>& c, const WsLayout& L, c
   T* g3 = (T*)at(ws, L.g3);
   T* g2 = (T*)at(ws, L.g4);
   T* g1 = (T*)at(ws, L.W4);
-  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, u2, a, nullptr, nup, dt * T(2.0 / 3.0), T(0), nullptr, nullptr, g3,
-                                   nullptr, st)))
-    return hip_fail(e, "adjoint stage 3");
-  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, u1, a, g3, nup, dt / T(6), dt * T(0.25), nullptr, nullptr, g2, nullptr,
-                                   st)))
-    return hip_fail(e, "adjoint stage 2");
+  if ((r = adjoint_stage<T>(g, STAGE_VJP, c, u2, a, nullptr, nup, dt * T(2.0 / 3.0), T(0), nullptr, nullptr, g3,
+                            nullptr, st, "adjoint stage 3")))
+    return r;
+  if ((r = adjoint_stage<T>(g, STAGE_VJP, c, u1, a, g3, nup, dt / T(6), dt * T(0.25), nullptr, nullptr, g2, nullptr,
+                            st, "adjoint stage 2")))
+    return r;
   if ((e = launch_rk3_mid<T>(g2, g3, S5, st))) return hip_fail(e, "adjoint stage combination");
-  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, wn, a, g2, nup, dt / T(6), dt, nullptr, nullptr, g1, nullptr, st)))
-    return hip_fail(e, "adjoint stage 1");
+  if ((r = adjoint_stage<T>(g, STAGE_VJP, c, wn, a, g2, nup, dt / T(6), dt, nullptr, nullptr, g1, nullptr, st,
+                            "adjoint stage 1")))
+    return r;
   if ((e = launch_rk3_combine<T>(a, g1, g2, g3, dt, wh, grad_s, S5, st))) return hip_fail(e, "adjoint combination");
   if (o && o->kind != ADJ_OBJ_NONE && c_n != 0.0) {
     if ((e = launch_objective<T>(c, o->kind, o->plane_i, o->pt_ref, wn, c_n, nullptr, wh,
@@ -281,9 +314,10 @@ int adjoint_step(const adj_grid* g, const void* wn_in, const T* stages, const T*
   } else {
     // forward recompute of the stage states
     const T h = c.dt * T(0.5);
-    if ((e = launch_primal_stage<T>(STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st))) return hip_fail(e, "recompute W2");
-    if ((e = launch_primal_stage<T>(STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st))) return hip_fail(e, "recompute W3");
-    if ((e = launch_primal_stage<T>(STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st))) return hip_fail(e, "recompute W4");
+    int r;
+    if ((r = primal_stage<T>(g, STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st, "recompute W2"))) return r;
+    if ((r = primal_stage<T>(g, STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st, "recompute W3"))) return r;
+    if ((r = primal_stage<T>(g, STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st, "recompute W4"))) return r;
   }
   const T* nup = nullptr;
   if (lambda > 0.0) {
@@ -291,14 +325,19 @@ int adjoint_step(const adj_grid* g, const void* wn_in, const T* stages, const T*
     nup = nu;
   }
   const T dt = c.dt;
-  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, sW4, a, nullptr, nup, dt / T(6), T(0), nullptr, nullptr, g4, nullptr, st)))
-    return hip_fail(e, "adjoint stage 4");
-  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, sW3, a, g4, nup, dt / T(3), dt, nullptr, nullptr, g3, nullptr, st)))
-    return hip_fail(e, "adjoint stage 3");
-  if ((e = launch_adjoint_stage<T>(STAGE_VJP, c, sW2, a, g3, nup, dt / T(3), dt * T(0.5), nullptr, nullptr, g2, nullptr, st)))
-    return hip_fail(e, "adjoint stage 2");
-  if ((e = launch_adjoint_stage<T>(STAGE_FIN, c, wn, a, g2, nup, dt / T(6), dt * T(0.5), g3, g4, wh, grad_s, st)))
-    return hip_fail(e, "adjoint stage 1");
+  int r;
+  if ((r = adjoint_stage<T>(g, STAGE_VJP, c, sW4, a, nullptr, nup, dt / T(6), T(0), nullptr, nullptr, g4, nullptr, st,
+                            "adjoint stage 4")))
+    return r;
+  if ((r = adjoint_stage<T>(g, STAGE_VJP, c, sW3, a, g4, nup, dt / T(3), dt, nullptr, nullptr, g3, nullptr, st,
+                            "adjoint stage 3")))
+    return r;
+  if ((r = adjoint_stage<T>(g, STAGE_VJP, c, sW2, a, g3, nup, dt / T(3), dt * T(0.5), nullptr, nullptr, g2, nullptr, st,
+                            "adjoint stage 2")))
+    return r;
+  if ((r = adjoint_stage<T>(g, STAGE_FIN, c, wn, a, g2, nup, dt / T(6), dt * T(0.5), g3, g4, wh, grad_s, st,
+                            "adjoint stage 1")))
+    return r;
   if (o && o->kind != ADJ_OBJ_NONE && c_n != 0.0) {
     if ((e = launch_objective<T>(c, o->kind, o->plane_i, o->pt_ref, wn, c_n, nullptr, wh,
                                  (double*)at(ws, L.partials), (double*)at(ws, L.scratch), st)))
@@ -538,15 +577,12 @@ int adj_residual(const adj_grid* grid, const void* w, const void* s, void* R, vo
   if ((r = check_grid(grid, false))) return r;
   if (!w || !R) return fail(ADJ_EINVAL, "w and R must be non-NULL");
   if (w == R) return fail(ADJ_EINVAL, "R must not alias w");
-  hipError_t e;
   hipStream_t st = (hipStream_t)stream;
   if (grid->precision == ADJ_F64)
-    e = launch_primal_stage<double>(STAGE_RES, consts<double>(grid), (const double*)w, nullptr, (const double*)s,
-                                    nullptr, nullptr, 0.0, (double*)R, st);
-  else
-    e = launch_primal_stage<float>(STAGE_RES, consts<float>(grid), (const float*)w, nullptr, (const float*)s, nullptr,
-                                   nullptr, 0.0f, (float*)R, st);
-  return e ? hip_fail(e, "residual") : ADJ_OK;
+    return primal_stage<double>(grid, STAGE_RES, consts<double>(grid), (const double*)w, nullptr, (const double*)s,
+                                nullptr, nullptr, 0.0, (double*)R, st, "residual");
+  return primal_stage<float>(grid, STAGE_RES, consts<float>(grid), (const float*)w, nullptr, (const float*)s, nullptr,
+                             nullptr, 0.0f, (float*)R, st, "residual");
 }
 
 int adj_vjp(const adj_grid* grid, const void* W, const void* kh, const void* nu, void* out, void* stream) {
@@ -554,15 +590,12 @@ int adj_vjp(const adj_grid* grid, const void* W, const void* kh, const void* nu,
   if ((r = check_grid(grid, false))) return r;
   if (!W || !kh || !out) return fail(ADJ_EINVAL, "W, kh and out must be non-NULL");
   if (out == kh || out == W) return fail(ADJ_EINVAL, "out must not alias its inputs");
-  hipError_t e;
   hipStream_t st = (hipStream_t)stream;
   if (grid->precision == ADJ_F64)
-    e = launch_adjoint_stage<double>(STAGE_VJP, consts<double>(grid), (const double*)W, (const double*)kh, nullptr,
-                                     (const double*)nu, 1.0, 0.0, nullptr, nullptr, (double*)out, nullptr, st);
-  else
-    e = launch_adjoint_stage<float>(STAGE_VJP, consts<float>(grid), (const float*)W, (const float*)kh, nullptr,
-                                    (const float*)nu, 1.0f, 0.0f, nullptr, nullptr, (float*)out, nullptr, st);
-  return e ? hip_fail(e, "vjp") : ADJ_OK;
+    return adjoint_stage<double>(grid, STAGE_VJP, consts<double>(grid), (const double*)W, (const double*)kh, nullptr,
+                                 (const double*)nu, 1.0, 0.0, nullptr, nullptr, (double*)out, nullptr, st, "vjp");
+  return adjoint_stage<float>(grid, STAGE_VJP, consts<float>(grid), (const float*)W, (const float*)kh, nullptr,
+                              (const float*)nu, 1.0f, 0.0f, nullptr, nullptr, (float*)out, nullptr, st, "vjp");
 }
 
 int adj_profile_enable(int on) {
@@ -789,6 +822,7 @@ int adj_batch_create(adj_batch** out, int nbox, const adj_grid* grids, const adj
     if (grids[i].bc_x != grids[0].bc_x) return fail(ADJ_EINVAL, "box %d: every box needs one x boundary", i);
     if (grids[i].ckpt_format != ADJ_CKPT_NATIVE) return fail(ADJ_EINVAL, "box %d: ensembles keep native states", i);
     if (grids[i].time_scheme != ADJ_RK4) return fail(ADJ_EINVAL, "box %d: ensembles march with RK4", i);
+    if (grids[i].flux != ADJ_FLUX_SPLIT) return fail(ADJ_EINVAL, "box %d: ensembles take the split-form flux", i);
   }
   const int kind = obj ? obj->kind : ADJ_OBJ_NONE;
   if (kind != ADJ_OBJ_NONE && kind != ADJ_OBJ_MEAN_PRESSURE)

@@ -26,6 +26,16 @@ template <typename T>
 hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,
                                 T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st);
 
+// Roe flux option: the difference dF = F_roe - F_split of every face flux (roe.hip), added after
+// the stage kernel that wrote `out` from the same W:
+//   roe_primal:  out += coef * (-sum_d (dF_{d,+} - dF_{d,-}) / dx_d)
+//   roe_adjoint: out += J_dF(W)^T kh,  kh = ca a + cg gnext (gnext may be NULL)
+template <typename T>
+hipError_t launch_roe_primal(const Consts<T>& c, T roe_delta, const T* W, T coef, T* out, hipStream_t st);
+template <typename T>
+hipError_t launch_roe_adjoint(const Consts<T>& c, T roe_delta, const T* W, const T* a, const T* gnext, T ca, T cg,
+                              T* out, hipStream_t st);
+
 // out[c] = scale * sigma_1(w) at every cell
 template <typename T>
 hipError_t launch_sigma1(const Consts<T>& c, const T* w, T scale, T* out, hipStream_t st);

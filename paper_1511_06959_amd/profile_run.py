@@ -1,9 +1,11 @@
 """Fixed launch sequences for hardware-counter and kernel-trace profiles, and their summaries.
 
     python -m paper_1511_06959_amd.profile_run adjoint --n 64 --precision f32 --reps 5 [--stages] [--tune]
+        [--flux roe]
         reverse steps (adjoint_step / adjoint_step_stages) on an n^3 Taylor-Green state, Mach 0.1,
         lambda 0: the reverse-stage kernel as the benchmark launches it (with --tune, in the tile
-        shapes of the tuning cache that a preceding bench.py run filled)
+        shapes of the tuning cache that a preceding bench.py run filled; with --flux roe, followed
+        by the Roe correction kernels)
     python -m paper_1511_06959_amd.profile_run copy --mib 1024 --reps 5
         torch's device-to-device copy of a buffer of known size, the calibration of the byte
         counters (it reads and writes exactly mib MiB per launch)
@@ -33,7 +35,7 @@ import sys
 from collections import defaultdict
 
 
-def run_adjoint(n, precision, reps, stages, tune=False):
+def run_adjoint(n, precision, reps, stages, tune=False, flux="split"):
     import torch
 
     import paper_1511_06959_amd as adj
@@ -45,7 +47,8 @@ def run_adjoint(n, precision, reps, stages, tune=False):
     nn = (n, n, n)
     rho, u, v, w, p = W.tgv_fields(nn, L, 0.1)
     dx = [L[d] / n for d in range(3)]
-    g = adj.Grid.make(nn, L, 1.0 / 1600.0, W.cfl_dt(rho, u, v, w, p, dx), precision=prec)
+    g = adj.Grid.make(nn, L, 1.0 / 1600.0, W.cfl_dt(rho, u, v, w, p, dx), precision=prec,
+                      flux=adj.FLUX_ROE if flux == "roe" else adj.FLUX_SPLIT, roe_delta=0.1)
     w0 = torch.from_numpy(W.conservative(rho, u, v, w, p)).to("cuda", dt)
     ws = adj.workspace(g)
     if tune:
@@ -69,8 +72,8 @@ def run_adjoint(n, precision, reps, stages, tune=False):
             adj.adjoint_step(g, w0, None, a, b, ws, obj=obj, c_n=1e-3, grad_s=gs)
         a, b = b, a
     torch.cuda.synchronize()
-    print(f"adjoint: {reps} reverse steps on {n}^3 ({precision}, {'stored' if stages else 'recomputed'} stages)",
-          flush=True)
+    print(f"adjoint: {reps} reverse steps on {n}^3 ({precision}, {'stored' if stages else 'recomputed'} stages, "
+          f"{flux} flux)", flush=True)
 
 
 def run_copy(mib, reps):
@@ -248,6 +251,8 @@ def main():
     a.add_argument("--reps", type=int, default=5)
     a.add_argument("--stages", action="store_true")
     a.add_argument("--tune", action="store_true", help="install the autotuned tiles (tuning cache) first")
+    a.add_argument("--flux", choices=("split", "roe"), default="split",
+                   help="roe: the Roe flux option (its correction kernels run after each stage kernel)")
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=1024)
     c.add_argument("--reps", type=int, default=5)
@@ -282,7 +287,7 @@ def main():
         trace_summary(args.outdir, args.title, args.command)
         return
     if args.cmd == "adjoint":
-        run_adjoint(args.n, args.precision, args.reps, args.stages, args.tune)
+        run_adjoint(args.n, args.precision, args.reps, args.stages, args.tune, args.flux)
     elif args.cmd == "copy":
         run_copy(args.mib, args.reps)
     else:

@@ -53,6 +53,8 @@ def test_workspace_and_record_sizes():
     (dict(mu=-1.0), -1), (dict(precision=7), -1), (dict(ckpt_format=adj.CKPT_BF16), -1),
     (dict(n=(1, 8, 4), bc_x=adj.BC_SLIP_WALLS), -2), (dict(bc_x=5), -1), (dict(dt=0.0), -1),
     (dict(nu_weight=(1.0, -0.5, 1.0)), -1), (dict(nu_weight=(1.0, 1.0, float("nan"))), -1), (dict(time_scheme=2), -1),
+    (dict(flux=2), -1), (dict(flux=adj.FLUX_ROE, roe_delta=0.0), -1),
+    (dict(flux=adj.FLUX_ROE, roe_delta=float("inf")), -1),
 ])
 def test_bad_grid_rejected(bad, code):
     g = _grid(**bad)
@@ -125,7 +127,7 @@ def test_ensemble_table_size_grows_with_members():
 @pytest.mark.parametrize("case,code", [
     ("members_decreasing", -1), ("member_box_range", -1), ("negative_lambda", -1), ("mixed_precision", -1),
     ("mixed_boundary", -1), ("bf16_states", -1), ("objective_kind", -1), ("small_table", -6), ("bad_grid", -1),
-    ("ssprk3", -1),
+    ("ssprk3", -1), ("roe", -1),
 ])
 def test_ensemble_create_rejects(case, code):
     g = [_grid(), _grid(n=(8, 8, 8))]
@@ -150,6 +152,8 @@ def test_ensemble_create_rejects(case, code):
         g[1] = _grid(n=(8, 0, 8))
     elif case == "ssprk3":
         g[1] = _grid(n=(8, 8, 8), time_scheme=adj.SSPRK3)
+    elif case == "roe":
+        g[1] = _grid(n=(8, 8, 8), flux=adj.FLUX_ROE)
     assert _create(g, mb, ml, obj, tb) == code
     assert adj.lib().adj_last_error()
 
