@@ -64,8 +64,8 @@ def profile_values(name, kernel_src_hash, tile):
 
 
 def valu_roofline(valu, cells, avg_us):
-    """The reverse-stage kernel against the vector ALU: FP32 operations it issues per launch
-    (committed SQ counter summary) / its live average launch duration, against 157.3 TFLOP/s;
+    """A reverse kernel against the vector ALU: FP32 operations it issues per launch (committed
+    SQ counter summary) / its live average launch duration, against 157.3 TFLOP/s;
     issue_frac = wave-level VALU instructions x 4 cycles (a wave64 instruction on a 16-lane SIMD)
     / (1024 SIMDs x 2.4 GHz x duration)."""
     if valu is None:
@@ -78,9 +78,11 @@ def valu_roofline(valu, cells, avg_us):
             "fp32_ops_per_launch": flops, "valu_insts_per_launch": insts}
 
 
-def kernel_hash():
+def kernel_hash(source="stencil.hip"):
+    """sha256 of a kernel family's sources (stencil.hip: the stage kernels, roe.hip: the Roe
+    corrections), as the committed counter summaries record it."""
     h = hashlib.sha256()
-    for name in ("stencil.hip", "common.hpp"):
+    for name in (source, "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1511_06959_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
@@ -434,6 +436,41 @@ def main():
     valu = profile_values("valu_adjoint_stage_tgv64.txt", khash, tile32)
     if big:
         traffic = valu = None
+    roof = {
+        "bound": "hbm",
+        "achieved": r32["stage_achieved_gbs"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": r32["stage_achieved_gbs"] / HBM_PEAK_GBS,
+        "traffic": None if traffic is None else float(traffic["bytes_per_cell_launch_f32"]) * wl.ncells,
+        "kernel": "k_adjoint_stage (reverse-stage gather)",
+        "avg_launch_us": r32["stage_avg_us"],
+        "alg_bytes_per_launch": r32["stage_alg_bytes"],
+    }
+    roof_valu = valu_roofline(valu, wl.ncells, r32["stage_avg_us"])
+    if "roe" in r32:
+        # with the Roe flux the transpose of its correction takes the largest share of the window
+        rk = r32["roe"]["roe_adjoint"]
+        rhash = kernel_hash("roe.hip")
+        rtraffic = profile_values("traffic_roe_adjoint_tgv64.txt", rhash, "")
+        rvalu = profile_values("valu_roe_adjoint_tgv64.txt", rhash, "")
+        if big:
+            rtraffic = rvalu = None
+        line_stage = dict(roof, traffic=roof["traffic"])
+        roof = {
+            "bound": "hbm",
+            "achieved": rk["achieved_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": rk["frac_hbm"],
+            "traffic": None if rtraffic is None else float(rtraffic["bytes_per_cell_launch_f32"]) * wl.ncells,
+            "kernel": "k_roe_adjoint (transpose of the Roe flux correction)",
+            "avg_launch_us": rk["avg_launch_us"],
+            "alg_bytes_per_launch": rk["alg_bytes_per_launch"],
+        }
+        r32["roe"]["adjoint_stage_roofline"] = line_stage
+        r32["roe"]["adjoint_stage_roofline_valu"] = roof_valu
+        roof_valu = valu_roofline(rvalu, wl.ncells, rk["avg_launch_us"])
     line = {
         "metric": METRIC,
         "value": r32["value"],
@@ -461,18 +498,8 @@ def main():
                          "reverse step recomputes the stage states from the stored w_n"),
             "checkpoints": "BF16 records (block-scaled, one affine map per variable and 4x4x4 block)" if big else "native FP32 / FP64 states",
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": r32["stage_achieved_gbs"],
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": r32["stage_achieved_gbs"] / HBM_PEAK_GBS,
-            "traffic": None if traffic is None else float(traffic["bytes_per_cell_launch_f32"]) * wl.ncells,
-            "kernel": "k_adjoint_stage (reverse-stage gather)",
-            "avg_launch_us": r32["stage_avg_us"],
-            "alg_bytes_per_launch": r32["stage_alg_bytes"],
-        },
-        "roofline_valu": valu_roofline(valu, wl.ncells, r32["stage_avg_us"]),
+        "roofline": roof,
+        "roofline_valu": roof_valu,
         "adjoint_sweep_cell_steps_per_s": r32["adjoint_sweep_cell_steps_per_s"],
         "primal_cell_steps_per_s": r32["primal_cell_steps_per_s"],
         "kernel_ms_per_window": {k: v[0] / args.steps for k, v in r32["prof"].items()},

@@ -30,6 +30,10 @@ namespace {
 // Output tile of both kernels: rows of 16 cells (x), 4 x 4 rows, one cell per thread.
 constexpr int RX = 16, RY = 4, RZ = 4, RNT = RX * RY * RZ;
 
+// 1/sqrt(x): the hardware approximation in FP32 (about 1 ulp), exact operations in FP64.
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
 template <typename T>
 struct RoeC {
   T gm1, eref, p0, dfrac;  // gamma - 1, wref_E, (gamma - 1) wref_E, roe_delta
@@ -44,7 +48,7 @@ struct Pr {
 template <typename T>
 __device__ __forceinline__ Pr<T> prim_of(const T w[5], const RoeC<T>& k) {
   Pr<T> q;
-  q.ir = T(1) / w[0];
+  q.ir = recip(w[0]);
 #pragma unroll
   for (int j = 0; j < 3; ++j) q.u[j] = w[1 + j] * q.ir;
   q.pd = k.gm1 * (w[4] - T(0.5) * (w[1] * q.u[0] + w[2] * q.u[1] + w[3] * q.u[2]));
@@ -70,9 +74,9 @@ __device__ __forceinline__ void prim_of_vjp(const T w[5], const Pr<T>& q, const 
   wb[0] -= irb * q.ir * q.ir;
 }
 
-// |x| smoothed within del of zero; dx, dd: its derivatives with respect to x and del.
+// |x| smoothed within del of zero (id = 1/del); dx, dd: its derivatives with respect to x and del.
 template <typename T>
-__device__ __forceinline__ T sabs(T x, T del, T& dx, T& dd) {
+__device__ __forceinline__ T sabs(T x, T del, T id, T& dx, T& dd) {
   if (x >= del) {
     dx = T(1);
     dd = T(0);
@@ -83,7 +87,6 @@ __device__ __forceinline__ T sabs(T x, T del, T& dx, T& dd) {
     dd = T(0);
     return -x;
   }
-  const T id = T(1) / del;
   dx = x * id;
   dd = T(0.5) * (T(1) - x * x * id * id);
   return T(0.5) * (x * x + del * del) * id;
@@ -103,8 +106,8 @@ __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5
   }
   const Pr<T> L = prim_of(wl, k), R = prim_of(wr, k);
   const T Hl = L.Ep * L.ir, Hr = R.Ep * R.ir;
-  const T sl = sqrt(wl[0]), sr = sqrt(wr[0]);
-  const T is = T(1) / (sl + sr), fl = sl * is, fr = sr * is;
+  const T isl = rsq(wl[0]), isr = rsq(wr[0]), sl = wl[0] * isl, sr = wr[0] * isr;
+  const T is = recip(sl + sr), fl = sl * is, fr = sr * is;
   T ut[3], du[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -114,12 +117,13 @@ __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5
   const T Ht = fl * Hl + fr * Hr;
   const T q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
   const T c2 = k.gm1 * (Ht - T(0.5) * q2);
-  const T cs = sqrt(c2), ic2 = T(1) / c2;
+  const T ics = rsq(c2), cs = c2 * ics, ic2 = ics * ics;
   const T rt = sl * sr, un = ut[D], dun = du[D];
   const T drho = wr[0] - wl[0], dp = R.pd - L.pd;
-  const T del = k.dfrac * cs;
+  const T del = k.dfrac * cs, idel = recip(del);
   T d1x, d1d, d2x, d2d, d5x, d5d;
-  const T l1 = sabs(un - cs, del, d1x, d1d), l2 = sabs(un, del, d2x, d2d), l5 = sabs(un + cs, del, d5x, d5d);
+  const T l1 = sabs(un - cs, del, idel, d1x, d1d), l2 = sabs(un, del, idel, d2x, d2d),
+          l5 = sabs(un + cs, del, idel, d5x, d5d);
   const T rcd = rt * cs * dun;
   const T t1 = dp - rcd, t5 = dp + rcd, hi = T(0.5) * ic2;
   const T s1 = l1 * t1 * hi, s5 = l5 * t5 * hi;  // |lam| a of the acoustic waves
@@ -217,7 +221,7 @@ __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5
     csb += l5b * d5x - l1b * d1x + (l1b * d1d + l2b * d2d + l5b * d5d) * k.dfrac;
     utb[D] += unb;
     dub[D] += dunb;
-    const T c2b = csb * T(0.5) / cs - ic2b * ic2 * ic2;
+    const T c2b = csb * T(0.5) * ics - ic2b * ic2 * ic2;
     Htb += c2b * k.gm1;
     q2b -= c2b * k.gm1 * T(0.5);
     T flb = Htb * Hl, frb = Htb * Hr;
@@ -233,8 +237,8 @@ __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5
     }
     const T slb = (flb - frb) * fr * is + rtb * sr;
     const T srb = (frb - flb) * fl * is + rtb * sl;
-    T wlb[5] = {-drhob + slb * T(0.5) / sl, T(0), T(0), T(0), T(0)};
-    T wrb[5] = {drhob + srb * T(0.5) / sr, T(0), T(0), T(0), T(0)};
+    T wlb[5] = {-drhob + slb * T(0.5) * isl, T(0), T(0), T(0), T(0)};
+    T wrb[5] = {drhob + srb * T(0.5) * isr, T(0), T(0), T(0), T(0)};
     // ---- reverse of the mean of the cell fluxes (weight G)
     T pdlb = -dpb + T(0.5) * G[1 + D], pdrb = dpb + T(0.5) * G[1 + D];
     wlb[1 + D] += T(0.5) * G[0];
@@ -489,8 +493,11 @@ __device__ __forceinline__ void adjoint_dir(const Consts<T>& c, const RoeC<T>& k
   __syncthreads();
 }
 
+// FP32: at most 128 registers, so that four work-groups (16 wavefronts) share a compute unit and
+// a 64^3 grid (1024 work-groups) runs in one round; FP64 holds two (LDS and registers).
 template <typename T>
-__global__ __launch_bounds__(RNT) void k_roe_adjoint(Consts<T> c, RoeC<T> k, const T* __restrict__ W,
+__global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+void k_roe_adjoint(Consts<T> c, RoeC<T> k, const T* __restrict__ W,
                                                      const T* __restrict__ a, const T* __restrict__ gnext, T ca, T cg,
                                                      T* __restrict__ out) {
   __shared__ T lds[NLA];

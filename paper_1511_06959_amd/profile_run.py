@@ -152,7 +152,7 @@ def traffic(fetch, write, copy_fetch, copy_write, mib, cells, kernel, commands):
     print(f"# scale factors (true / counter): fetch {sf:.4f}, write {sw:.4f}")
     for k in sorted(fm):
         print(f"# {k}: {fm[k][0]} dispatches, FETCH_SIZE {fm[k][1]:.1f} KiB, WRITE_SIZE {wm.get(k, (0, 0))[1]:.1f} KiB")
-    print(f"kernel_source_sha256 = {_src_hash()}")
+    print(f"kernel_source_sha256 = {_src_hash(kernel)}")
     print(f"tile_f32 = {_tiles(fm)}")
     print(f"fetch_bytes_per_launch = {fkib * sf * 1024.0:.6g}")
     print(f"write_bytes_per_launch = {wkib * sw * 1024.0:.6g}")
@@ -169,11 +169,13 @@ def _tiles(names):
     return ",".join(sorted(out))
 
 
-def _src_hash():
+def _src_hash(kernel="k_adjoint_stage"):
+    """sha256 of the sources of a kernel family: the Roe kernels (k_roe_*) live in roe.hip, the
+    stage kernels in stencil.hip; both include common.hpp."""
     import hashlib
     h = hashlib.sha256()
     here = os.path.dirname(os.path.abspath(__file__))
-    for name in ("stencil.hip", "common.hpp"):
+    for name in (("roe.hip" if kernel.startswith("k_roe") else "stencil.hip"), "common.hpp"):
         h.update(open(os.path.join(here, "csrc", name), "rb").read())
     return h.hexdigest()
 
@@ -211,7 +213,7 @@ def valu(outdir, cells, kernel, commands):
         print(f"# {k}: {len(disp[k])} dispatches, " +
               ", ".join(f"{c} {acc[k][c] / len(disp[k]):.6g}" for c in VALU_COUNTERS if c in acc[k]))
     print("# FP32 operations = 64 x (ADD + MUL + TRANS + 2 FMA) wave instructions")
-    print(f"kernel_source_sha256 = {_src_hash()}")
+    print(f"kernel_source_sha256 = {_src_hash(kernel)}")
     print(f"tile_f32 = {_tiles(acc)}")
     print(f"waves_per_launch = {per.get('SQ_WAVES', 0.0):.6g}")
     print(f"valu_insts_per_launch = {per.get('SQ_INSTS_VALU', 0.0):.6g}")
