@@ -31,6 +31,7 @@ class OrcGrid(ctypes.Structure):
         ("scheme", ctypes.c_int32),
         ("flux", ctypes.c_int32),
         ("roe_delta", ctypes.c_double),
+        ("w_far", ctypes.c_double * 10),
     ]
 
 
@@ -68,6 +69,7 @@ def lib():
             "orc_residual": [gp, dp, dp, dp],
             "orc_jvp": [gp, dp, dp, dp],
             "orc_roe_flux": [gp, ctypes.c_int, dp, dp, dp],
+            "orc_char_flux": [gp, ctypes.c_int, dp, dp],
             "orc_vjp": [gp, dp, dp, dp],
             "orc_lnu_apply": [gp, dp, dp, dp],
             "orc_primal_step": [gp, dp, dp, dp],
@@ -102,15 +104,18 @@ def num_threads():
 
 # ---------------------------------------------------------------------------------------------
 SCHEME_RK4, SCHEME_SSPRK3 = 0, 1
+BC_PERIODIC, BC_SLIP_WALLS, BC_CHARACTERISTIC = 0, 1, 2
 FLUX_SPLIT, FLUX_ROE = 0, 1
 
 
 def make_grid(n, L, gamma=1.4, prandtl=0.72, mu=0.01, dt=0.0, bc_x=0, scheme=SCHEME_RK4, flux=FLUX_SPLIT,
-              roe_delta=0.1):
+              roe_delta=0.1, w_far=None):
     """scheme: time marching, SCHEME_RK4 (classical RK4) or SCHEME_SSPRK3 (Shu-Osher SSP-RK3).
     flux: convective face flux, FLUX_SPLIT (split central form) or FLUX_ROE (Roe's approximate
     Riemann solver on linearly reconstructed face states, wave speeds |lam| smoothed within
-    roe_delta times the Roe sound speed)."""
+    roe_delta times the Roe sound speed).
+    bc_x 2 (characteristic inflow/outflow in x): w_far = two far-field conservative states (beyond
+    x = 0, beyond x = L_x)."""
     g = OrcGrid()
     for d in range(3):
         g.n[d] = int(n[d])
@@ -120,6 +125,10 @@ def make_grid(n, L, gamma=1.4, prandtl=0.72, mu=0.01, dt=0.0, bc_x=0, scheme=SCH
     g.scheme = int(scheme)
     g.flux = int(flux)
     g.roe_delta = float(roe_delta)
+    if w_far is not None:
+        far = np.asarray(w_far, dtype=np.float64).reshape(10)
+        for i in range(10):
+            g.w_far[i] = float(far[i])
     return g
 
 
@@ -128,7 +137,7 @@ def grid_from(p):
     flux, roe_delta])."""
     return make_grid(p["n"], p["L"], p.get("gamma", 1.4), p.get("prandtl", 0.72), p["mu"],
                      p.get("dt", 0.0), p.get("bc_x", 0), p.get("scheme", SCHEME_RK4), p.get("flux", FLUX_SPLIT),
-                     p.get("roe_delta", 0.1))
+                     p.get("roe_delta", 0.1), p.get("w_far"))
 
 
 def make_obj(kind=0, plane_i=0, pt_ref=0.0):
@@ -172,6 +181,15 @@ def roe_flux(g, d, wl, wr):
     wr, pr = _d(wr)
     F, pF = _d(np.zeros(5))
     _chk(lib().orc_roe_flux(ctypes.byref(g), int(d), pl, pr, pF), "roe_flux")
+    return F
+
+
+def char_flux(g, side, w):
+    """Flux through the characteristic boundary face of side 0 (x = 0) or 1 (x = L_x) next to the
+    boundary cell state w."""
+    w, pw = _d(w)
+    F, pF = _d(np.zeros(5))
+    _chk(lib().orc_char_flux(ctypes.byref(g), int(side), pw, pF), "char_flux")
     return F
 
 

@@ -27,7 +27,9 @@
 //         normal (phi_R - phi_L)/dx_d, tangential = mean of the two cells' central differences
 //       - sigma = mu (grad u + grad u^T) - (2 mu / 3) (div u) I,  p = (gamma-1) rho e,
 //         e = E - |u|^2/2,  alpha = gamma mu / Pr  (heat flux alpha grad e = k grad T)
-//   * classical RK4 in time with fixed dt
+//       - or (option) Roe's approximate Riemann solver on linearly reconstructed face states
+//         [Numerical methods], every |wave speed| smoothed near zero (Harten)
+//   * classical RK4 in time with fixed dt (or the strong-stability-preserving RK3)
 //   * discrete adjoint of the RK4 step [Implementation; terminal condition and backward solve]:
 //       the transposed Jacobian of every face flux is assembled from dual-number local Jacobians
 //   * artificial adjoint viscosity  d_l( lambda sigma_1 delta_ki delta_jl d_j w^_k )  [Stabilizing
@@ -40,8 +42,10 @@
 //     density-weighted stagnation-pressure loss on a plane [Eqs. (1)-(3), pressure loss]
 //
 // Layout: SoA, var-major, w[v*N + (k*ny + j)*nx + i], v = (rho, rho u1, rho u2, rho u3, rho E).
-// Boundaries: periodic in y and z; x either periodic or inviscid-mirror slip walls (ghost cell
-// mirrors the first interior cell with the x-momentum sign flipped).
+// Boundaries: periodic in y and z; x either periodic, inviscid-mirror slip walls (ghost cell
+// mirrors the first interior cell with the x-momentum sign flipped), or characteristic inflow /
+// outflow boundaries: the same mirror ghosts in every stencil, and through the two boundary faces
+// the inviscid upwind (Roe) flux between the boundary cell and a far-field state.
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -55,12 +59,14 @@
 extern "C" {
 typedef struct orc_grid {
   int32_t n[3];
-  int32_t bc_x;  // 0: periodic in x, 1: slip walls at x = 0 and x = L_x
+  int32_t bc_x;  // 0: periodic in x, 1: slip walls at x = 0 and x = L_x, 2: characteristic
+                 //    inflow/outflow boundaries there (far-field states w_far)
   double L[3];
   double gamma, prandtl, mu, dt;
   int32_t scheme;  // time marching: 0 classical RK4, 1 strong-stability-preserving RK3
   int32_t flux;    // convective face flux: 0 split central form, 1 Roe upwind flux
   double roe_delta;  // flux 1: width of the smoothing of |wave speed|, as a fraction of the Roe sound speed
+  double w_far[2][5];  // bc_x 2: far-field conservative states beyond x = 0 and beyond x = L_x
 } orc_grid;
 
 typedef struct orc_obj {
@@ -126,12 +132,16 @@ template <int N> double val(const Dual<N>& x) { return x.v; }
 struct G {
   long nx, ny, nz, N;
   double dx[3];
-  int wall, scheme, flux;
+  int wall, bc, scheme, flux;
   double gamma, pr, mu, alpha, dt, roe_delta;
+  double wfar[2][5];
   explicit G(const orc_grid* g) {
     nx = g->n[0]; ny = g->n[1]; nz = g->n[2]; N = nx * ny * nz;
     for (int d = 0; d < 3; ++d) dx[d] = g->L[d] / (double)g->n[d];
-    wall = g->bc_x;
+    wall = g->bc_x != 0;  // walls and open boundaries both keep mirror ghosts in every stencil
+    bc = g->bc_x;
+    for (int s = 0; s < 2; ++s)
+      for (int v = 0; v < 5; ++v) wfar[s][v] = g->w_far[s][v];
     scheme = g->scheme;
     flux = g->flux;
     roe_delta = g->roe_delta;
@@ -295,16 +305,47 @@ void face_slots(const G& g, int d, long i, long j, long k, Slot st[NSLOT]) {
 //   F~^v = (0, sigma_d., u_f . sigma_d. + alpha d_d e), u_f = 0.5 (u_L + u_R)
 //   face gradient d_l u_k: l == d -> (u_R - u_L)/dx_d ; l != d -> mean of the central
 //   differences of cells L and R in direction l.
+// Characteristic boundary face (side 0: x = 0, side 1: x = L_x): the inviscid upwind flux between
+// the boundary cell and the far-field state (Roe's solver, first order), which takes the waves
+// entering the box from the far field and those leaving it from the interior [Boundary
+// conditions: characteristic inlet and outlet].
 template <class T>
-void face_flux(const G& g, int d, const T (*st)[5], T H[5]) {
+void char_face_flux(const G& g, int side, const T (*st)[5], T H[5]) {
+  T far[5];
+  for (int v = 0; v < 5; ++v) far[v] = T(g.wfar[side][v]);
+  if (side == 0)
+    roe_face_flux(g, 0, far, st[1], H);
+  else
+    roe_face_flux(g, 0, st[0], far, H);
+}
+
+// Whether a Roe reconstruction may use the cell of slot s (not a ghost beyond an open boundary).
+inline bool recon_ok(const G& g, const Slot& s) { return g.bc != 2 || s.real; }
+
+// Which characteristic boundary face (0 or 1) the direction-d face with lower cell i is, or -1.
+inline int open_side(const G& g, int d, long i) {
+  if (d != 0 || g.bc != 2) return -1;
+  return i == -1 ? 0 : (i == g.nx - 1 ? 1 : -1);
+}
+
+// rl, rr: whether the Roe face states are reconstructed on the left / right; next to a
+// characteristic boundary a reconstruction that would reach the ghost cell is dropped (the face
+// state is the cell value there), since a mirror image is no estimate of the flow beyond an
+// open boundary.
+template <class T>
+void face_flux(const G& g, int d, const T (*st)[5], T H[5], int side = -1, bool rl = true, bool rr = true) {
+  if (side >= 0) {
+    char_face_flux(g, side, st, H);
+    return;
+  }
   Prim<T> q[10];
   for (int s = 0; s < 10; ++s) q[s] = prim(g, st[s]);
   T Fc[5];
   if (g.flux == 1) {
     T wl[5], wr[5];
     for (int v = 0; v < 5; ++v) {
-      wl[v] = st[0][v] + 0.25 * (st[1][v] - st[10][v]);
-      wr[v] = st[1][v] - 0.25 * (st[11][v] - st[0][v]);
+      wl[v] = rl ? st[0][v] + 0.25 * (st[1][v] - st[10][v]) : st[0][v];
+      wr[v] = rr ? st[1][v] - 0.25 * (st[11][v] - st[0][v]) : st[1][v];
     }
     roe_face_flux(g, d, wl, wr, Fc);
   } else {
@@ -389,7 +430,7 @@ void residual(const G& g, const T* w, const T* s, T* R) {
     Slot sl[NSLOT]; face_slots(g, d, i, j, k, sl);
     T st[NSLOT][5];
     for (int a = 0; a < nslots(g); ++a) load_slot(g, w, sl[a], st[a]);
-    T H[5]; face_flux(g, d, st, H);
+    T H[5]; face_flux(g, d, st, H, open_side(g, d, i), recon_ok(g, sl[10]), recon_ok(g, sl[11]));
     for (int v = 0; v < 5; ++v) {
       if (sl[0].real) acc[v * g.N + sl[0].c] -= H[v] / g.dx[d];
       if (sl[1].real) acc[v * g.N + sl[1].c] += H[v] / g.dx[d];
@@ -415,7 +456,7 @@ void vjp_slots(const G& g, const double* W, const double* kh, double* out) {
         st[a][v] = Dual<ND>(sg * W[v * g.N + sl[a].c]);
         st[a][v].d[a * 5 + v] = sg;
       }
-    Dual<ND> H[5]; face_flux(g, d, st, H);
+    Dual<ND> H[5]; face_flux(g, d, st, H, open_side(g, d, i), recon_ok(g, sl[10]), recon_ok(g, sl[11]));
     double om[5];
     for (int o = 0; o < 5; ++o) {
       double r = sl[1].real ? kh[o * g.N + sl[1].c] : 0.0;
@@ -795,10 +836,23 @@ static int check(const orc_grid* g) {
   if (!g) return -1;
   for (int d = 0; d < 3; ++d)
     if (g->n[d] < 1 || !(g->L[d] > 0)) return -1;
-  if (g->bc_x == 1 && g->n[0] < 2) return -1;
+  if (g->bc_x < 0 || g->bc_x > 2) return -1;
+  if (g->bc_x != 0 && g->n[0] < 2) return -1;
+  if (g->bc_x == 2 && !(g->w_far[0][0] > 0.0 && g->w_far[1][0] > 0.0)) return -1;
   if (g->scheme != 0 && g->scheme != 1) return -1;
   if (g->flux != 0 && g->flux != 1) return -1;
   if (g->flux == 1 && !(g->roe_delta > 0.0)) return -1;
+  return 0;
+}
+
+// F = flux through the characteristic boundary face of `side` (0: x = 0, 1: x = L_x) next to the
+// boundary cell state w
+int orc_char_flux(const orc_grid* gr, int side, const double* w, double* F) {
+  if (check(gr) || gr->bc_x != 2 || side < 0 || side > 1) return -1;
+  G g(gr);
+  double st[2][5];
+  for (int v = 0; v < 5; ++v) st[0][v] = st[1][v] = w[v];
+  char_face_flux<double>(g, side, st, F);
   return 0;
 }
 
