@@ -58,7 +58,7 @@ typedef enum adj_status {
   ADJ_EWORKSPACE = -6  /* workspace missing, too small or misaligned */
 } adj_status;
 
-enum { ADJ_BC_PERIODIC = 0, ADJ_BC_SLIP_WALLS = 1 };
+enum { ADJ_BC_PERIODIC = 0, ADJ_BC_SLIP_WALLS = 1, ADJ_BC_CHARACTERISTIC = 2 };
 enum { ADJ_F64 = 0, ADJ_F32 = 1 };
 enum { ADJ_CKPT_NATIVE = 0, ADJ_CKPT_BF16 = 1 };
 enum { ADJ_RK4 = 0, ADJ_SSPRK3 = 1 };
@@ -76,7 +76,8 @@ enum {
 /* Grid, gas and scheme.  dt is fixed over a window. */
 typedef struct adj_grid {
   int32_t n[3];        /* cells in x, y, z (each >= 1; >= 2 in x with slip walls)           */
-  int32_t bc_x;        /* ADJ_BC_PERIODIC or ADJ_BC_SLIP_WALLS                               */
+  int32_t bc_x;        /* ADJ_BC_PERIODIC, ADJ_BC_SLIP_WALLS, or ADJ_BC_CHARACTERISTIC: open
+                          inflow/outflow boundaries at x = 0 and x = L_x (see w_far)           */
   double L[3];         /* box lengths                                                        */
   double gamma;        /* ratio of specific heats                                            */
   double prandtl;      /* Prandtl number; heat conduction coefficient alpha = gamma mu / Pr  */
@@ -115,7 +116,18 @@ typedef struct adj_grid {
                           sqrt(rho)).  Ensembles take ADJ_FLUX_SPLIT grids only.                */
   double roe_delta;    /* ADJ_FLUX_ROE: every |lam| is smoothed within delta = roe_delta c~ of
                           zero (Harten: (lam^2 + delta^2)/(2 delta) there), so that the flux is
-                          differentiable and its discrete adjoint exists; finite and > 0       */
+                          differentiable and its discrete adjoint exists; finite and > 0.  The
+                          characteristic boundaries use it too.                                */
+  double w_far[2][5];  /* ADJ_BC_CHARACTERISTIC: the far-field conservative states beyond x = 0
+                          and beyond x = L_x (rho > 0, p > 0).  Through each boundary face the
+                          flux is Roe's inviscid flux between the far-field state and the
+                          boundary cell (first order): the characteristics that enter the box
+                          carry far-field data and those that leave it interior data, the
+                          non-reflecting inlet and outlet of the paper's solver [Numerical
+                          methods; Boundary conditions of the adjoint: characteristic
+                          boundaries].  Every other stencil sees mirror ghosts beyond x = 0
+                          and x = L_x, as with slip walls, except that a Roe reconstruction does
+                          not reach into them.  Ensembles take no characteristic grids.        */
 } adj_grid;
 
 typedef struct adj_objective {
@@ -224,7 +236,8 @@ enum {
   ADJ_PROF_REDUCE = 5,        /* energy and inner products                      */
   ADJ_PROF_ROE_PRIMAL = 6,    /* Roe flux correction of primal stages           */
   ADJ_PROF_ROE_ADJOINT = 7,   /* its transpose in reverse stages                */
-  ADJ_PROF_NCLASS = 8
+  ADJ_PROF_BOUNDARY = 8,      /* characteristic boundary fluxes and transposes  */
+  ADJ_PROF_NCLASS = 9
 };
 int adj_profile_enable(int on);
 int adj_profile_read(int kernel_class, double* total_ms, long long* launches);

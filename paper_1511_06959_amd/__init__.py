@@ -20,12 +20,12 @@ LIB_PATH = os.path.join(_HERE, "libadjns.so")
 
 F64, F32 = 0, 1
 CKPT_NATIVE, CKPT_BF16 = 0, 1
-BC_PERIODIC, BC_SLIP_WALLS = 0, 1
+BC_PERIODIC, BC_SLIP_WALLS, BC_CHARACTERISTIC = 0, 1, 2
 RK4, SSPRK3 = 0, 1
 FLUX_SPLIT, FLUX_ROE = 0, 1
 OBJ_NONE, OBJ_MEAN_PRESSURE, OBJ_KE_DISSIPATION, OBJ_PT_LOSS_PLANE = 0, 1, 2, 3
 (PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, PROF_SIGMA1, PROF_OBJECTIVE, PROF_CODEC, PROF_REDUCE, PROF_ROE_PRIMAL,
- PROF_ROE_ADJOINT) = range(8)
+ PROF_ROE_ADJOINT, PROF_BOUNDARY) = range(9)
 TILES = {0: (16, 4, 4), 1: (32, 4, 2), 2: (32, 4, 4), 3: (32, 8, 2), 4: (32, 8, 4), 5: (16, 8, 8)}
 TILE_16x4x4, TILE_32x4x2, TILE_32x4x4, TILE_32x8x2, TILE_32x8x4, TILE_16x8x8 = range(6)
 
@@ -56,17 +56,20 @@ class Grid(ctypes.Structure):
         ("time_scheme", ctypes.c_int32),
         ("flux", ctypes.c_int32),
         ("roe_delta", ctypes.c_double),
+        ("w_far", ctypes.c_double * 10),
     ]
 
     @classmethod
     def make(cls, n, L, mu, dt, gamma=1.4, prandtl=0.72, bc_x=0, precision=F64, ckpt_format=CKPT_NATIVE,
-             w_ref=None, nu_weight=None, time_scheme=0, flux=FLUX_SPLIT, roe_delta=0.1):
+             w_ref=None, nu_weight=None, time_scheme=0, flux=FLUX_SPLIT, roe_delta=0.1, w_far=None):
         """w_ref: five reference values; state arrays then hold w - w_ref (see to_stored).
         nu_weight: artificial-viscosity weights of the groups (rho, rho u, rho E), the adjoint
         components of group g diffused with nu_g = lambda nu_weight[g] sigma_1 (None: 1, 1, 1).
         time_scheme: RK4 (classical) or SSPRK3 (strong-stability-preserving third order).
         flux: FLUX_SPLIT (split central form) or FLUX_ROE (Roe's flux on linearly reconstructed
-        face states, wave speeds smoothed within roe_delta times the Roe sound speed)."""
+        face states, wave speeds smoothed within roe_delta times the Roe sound speed).
+        w_far: with bc_x = BC_CHARACTERISTIC, the far-field conservative states beyond x = 0 and
+        beyond x = L_x (two sequences of five values)."""
         g = cls()
         for d in range(3):
             g.n[d] = int(n[d])
@@ -81,6 +84,10 @@ class Grid(ctypes.Structure):
         g.time_scheme = int(time_scheme)
         g.flux = int(flux)
         g.roe_delta = float(roe_delta)
+        if w_far is not None:
+            far = [float(x) for pair in w_far for x in pair]
+            for i in range(10):
+                g.w_far[i] = far[i]
         return g
 
     def to_stored(self, w):

@@ -83,8 +83,9 @@ int check_grid(const adj_grid* g, bool need_dt) {
   }
   if ((long long)((g->n[0] + 15) / 16) * ((g->n[1] + 3) / 4) * ((g->n[2] + 3) / 4) > 0x7fffffffLL)
     return fail(ADJ_ESHAPE, "grid too large for one tile launch");
-  if (g->bc_x != ADJ_BC_PERIODIC && g->bc_x != ADJ_BC_SLIP_WALLS) return fail(ADJ_EINVAL, "bad bc_x %d", g->bc_x);
-  if (g->bc_x == ADJ_BC_SLIP_WALLS && g->n[0] < 2) return fail(ADJ_ESHAPE, "slip walls need n[0] >= 2");
+  if (g->bc_x != ADJ_BC_PERIODIC && g->bc_x != ADJ_BC_SLIP_WALLS && g->bc_x != ADJ_BC_CHARACTERISTIC)
+    return fail(ADJ_EINVAL, "bad bc_x %d", g->bc_x);
+  if (g->bc_x != ADJ_BC_PERIODIC && g->n[0] < 2) return fail(ADJ_ESHAPE, "x boundaries need n[0] >= 2");
   if (!(g->gamma > 1.0) || !std::isfinite(g->gamma)) return fail(ADJ_EINVAL, "gamma must be > 1");
   if (!(g->prandtl > 0.0)) return fail(ADJ_EINVAL, "prandtl must be > 0");
   if (!(g->mu >= 0.0) || !std::isfinite(g->mu)) return fail(ADJ_EINVAL, "mu must be >= 0");
@@ -98,8 +99,18 @@ int check_grid(const adj_grid* g, bool need_dt) {
   if (g->time_scheme != ADJ_RK4 && g->time_scheme != ADJ_SSPRK3)
     return fail(ADJ_EINVAL, "bad time_scheme %d", g->time_scheme);
   if (g->flux != ADJ_FLUX_SPLIT && g->flux != ADJ_FLUX_ROE) return fail(ADJ_EINVAL, "bad flux %d", g->flux);
-  if (g->flux == ADJ_FLUX_ROE && (!(g->roe_delta > 0.0) || !std::isfinite(g->roe_delta)))
+  if ((g->flux == ADJ_FLUX_ROE || g->bc_x == ADJ_BC_CHARACTERISTIC) &&
+      (!(g->roe_delta > 0.0) || !std::isfinite(g->roe_delta)))
     return fail(ADJ_EINVAL, "roe_delta must be finite and > 0");
+  if (g->bc_x == ADJ_BC_CHARACTERISTIC) {
+    for (int s = 0; s < 2; ++s) {
+      const double* f = g->w_far[s];
+      for (int v = 0; v < 5; ++v)
+        if (!std::isfinite(f[v])) return fail(ADJ_EINVAL, "w_far[%d][%d] must be finite", s, v);
+      const double p = (g->gamma - 1.0) * (f[4] - 0.5 * (f[1] * f[1] + f[2] * f[2] + f[3] * f[3]) / f[0]);
+      if (!(f[0] > 0.0) || !(p > 0.0)) return fail(ADJ_EINVAL, "w_far[%d] needs rho > 0 and p > 0", s);
+    }
+  }
   if (5 * (double)ncells(g) * (g->precision == ADJ_F64 ? 8.0 : 4.0) >= 4294967296.0)
     return fail(ADJ_ESHAPE, "state arrays must span less than 4 GiB (%lld cells)", ncells(g));
   if (g->ckpt_format != ADJ_CKPT_NATIVE && g->ckpt_format != ADJ_CKPT_BF16)
@@ -134,7 +145,7 @@ Consts<T> consts(const adj_grid* g) {
   c.nx = g->n[0];
   c.ny = g->n[1];
   c.nz = g->n[2];
-  c.wall = g->bc_x == ADJ_BC_SLIP_WALLS;
+  c.wall = g->bc_x != ADJ_BC_PERIODIC;  // characteristic boundaries keep the mirror ghosts
   c.N = ncells(g);
   for (int d = 0; d < 3; ++d) {
     const double h = g->L[d] / g->n[d];
@@ -162,29 +173,39 @@ size_t ckpt_header_bytes(const adj_grid* g) {
 }
 
 // One primal stage (launch_primal_stage) and, on a Roe-flux grid, the correction of its residual
-// to the Roe flux, weighted like R in the stage (cR; dt/6 in stage 4; 1 for the plain residual).
+// to the Roe flux, on a grid with characteristic boundaries the correction of the boundary faces,
+// each weighted like R in the stage (cR; dt/6 in stage 4; 1 for the plain residual).
 template <typename T>
 int primal_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
                  const T* W3, T cR, T* out, hipStream_t st, const char* what, T ca = T(0), T cb = T(0)) {
   hipError_t e;
   if ((e = launch_primal_stage<T>(mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb))) return hip_fail(e, what);
+  const T coef = mode == STAGE_FIN ? c.dt / T(6) : (mode == STAGE_RES ? T(1) : cR);
+  const int open = g->bc_x == ADJ_BC_CHARACTERISTIC;
   if (g->flux == ADJ_FLUX_ROE) {
-    const T coef = mode == STAGE_FIN ? c.dt / T(6) : (mode == STAGE_RES ? T(1) : cR);
-    if ((e = launch_roe_primal<T>(c, (T)g->roe_delta, W, coef, out, st))) return hip_fail(e, what);
+    if ((e = launch_roe_primal<T>(c, (T)g->roe_delta, open, W, coef, out, st))) return hip_fail(e, what);
+  }
+  if (open) {
+    if ((e = launch_char_primal<T>(c, (T)g->roe_delta, &g->w_far[0][0], W, coef, out, st))) return hip_fail(e, what);
   }
   return ADJ_OK;
 }
 
-// One reverse stage (launch_adjoint_stage) and, on a Roe-flux grid, the transpose of the
-// correction applied to the same kh = ca a + cg gnext, added into `out` (g, or w^_n in stage 1).
+// One reverse stage (launch_adjoint_stage) and the transposes of the Roe-flux and boundary
+// corrections applied to the same kh = ca a + cg gnext, added into `out` (g, or w^_n in stage 1).
 template <typename T>
 int adjoint_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext,
                   const T* nu, T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st,
                   const char* what) {
   hipError_t e;
   if ((e = launch_adjoint_stage<T>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st))) return hip_fail(e, what);
+  const int open = g->bc_x == ADJ_BC_CHARACTERISTIC;
   if (g->flux == ADJ_FLUX_ROE) {
-    if ((e = launch_roe_adjoint<T>(c, (T)g->roe_delta, W, a, gnext, ca, cg, out, st))) return hip_fail(e, what);
+    if ((e = launch_roe_adjoint<T>(c, (T)g->roe_delta, open, W, a, gnext, ca, cg, out, st))) return hip_fail(e, what);
+  }
+  if (open) {
+    if ((e = launch_char_adjoint<T>(c, (T)g->roe_delta, &g->w_far[0][0], W, a, gnext, ca, cg, out, st)))
+      return hip_fail(e, what);
   }
   return ADJ_OK;
 }
@@ -643,10 +664,11 @@ int adj_get_tile(int kernel_class, int precision) {
 int adj_tile_launched(int kernel_class, int precision, int bc_x, int lnu, int tile) {
   if (kernel_class != ADJ_PROF_ADJOINT_STAGE && kernel_class != ADJ_PROF_PRIMAL_STAGE) return fail(ADJ_EINVAL, "bad class");
   if (precision != ADJ_F64 && precision != ADJ_F32) return fail(ADJ_EINVAL, "bad precision %d", precision);
-  if (bc_x != ADJ_BC_PERIODIC && bc_x != ADJ_BC_SLIP_WALLS) return fail(ADJ_EINVAL, "bad bc_x %d", bc_x);
+  if (bc_x != ADJ_BC_PERIODIC && bc_x != ADJ_BC_SLIP_WALLS && bc_x != ADJ_BC_CHARACTERISTIC)
+    return fail(ADJ_EINVAL, "bad bc_x %d", bc_x);
   if (tile < 0 || tile >= NTILES) return fail(ADJ_EINVAL, "bad tile id %d", tile);
   if (kernel_class == ADJ_PROF_PRIMAL_STAGE) return tile;  // every primal tile fits
-  return adjoint_tile_used(precision == ADJ_F64, bc_x == ADJ_BC_SLIP_WALLS, lnu != 0, tile);
+  return adjoint_tile_used(precision == ADJ_F64, bc_x != ADJ_BC_PERIODIC, lnu != 0, tile);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -823,6 +845,8 @@ int adj_batch_create(adj_batch** out, int nbox, const adj_grid* grids, const adj
     if (grids[i].ckpt_format != ADJ_CKPT_NATIVE) return fail(ADJ_EINVAL, "box %d: ensembles keep native states", i);
     if (grids[i].time_scheme != ADJ_RK4) return fail(ADJ_EINVAL, "box %d: ensembles march with RK4", i);
     if (grids[i].flux != ADJ_FLUX_SPLIT) return fail(ADJ_EINVAL, "box %d: ensembles take the split-form flux", i);
+    if (grids[i].bc_x == ADJ_BC_CHARACTERISTIC)
+      return fail(ADJ_EINVAL, "box %d: ensembles take periodic or walled boxes", i);
   }
   const int kind = obj ? obj->kind : ADJ_OBJ_NONE;
   if (kind != ADJ_OBJ_NONE && kind != ADJ_OBJ_MEAN_PRESSURE)

@@ -30,11 +30,23 @@ hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const 
 // the stage kernel that wrote `out` from the same W:
 //   roe_primal:  out += coef * (-sum_d (dF_{d,+} - dF_{d,-}) / dx_d)
 //   roe_adjoint: out += J_dF(W)^T kh,  kh = ca a + cg gnext (gnext may be NULL)
+// (open: characteristic boundaries in x, whose faces these kernels leave alone)
 template <typename T>
-hipError_t launch_roe_primal(const Consts<T>& c, T roe_delta, const T* W, T coef, T* out, hipStream_t st);
+hipError_t launch_roe_primal(const Consts<T>& c, T roe_delta, int open, const T* W, T coef, T* out, hipStream_t st);
 template <typename T>
-hipError_t launch_roe_adjoint(const Consts<T>& c, T roe_delta, const T* W, const T* a, const T* gnext, T ca, T cg,
-                              T* out, hipStream_t st);
+hipError_t launch_roe_adjoint(const Consts<T>& c, T roe_delta, int open, const T* W, const T* a, const T* gnext, T ca,
+                              T cg, T* out, hipStream_t st);
+// Characteristic boundaries in x: the flux the stage kernels evaluated through the two boundary
+// faces (a slip-wall mirror pair) replaced by Roe's flux against the far-field states w_far
+// (2 x 5 conservative values), after the stage kernel (and Roe correction) that wrote `out`:
+//   char_primal:  out += coef * (boundary-face flux difference) / dx at the boundary cells
+//   char_adjoint: out += its transpose applied to kh = ca a + cg gnext
+template <typename T>
+hipError_t launch_char_primal(const Consts<T>& c, T roe_delta, const double* w_far, const T* W, T coef, T* out,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_char_adjoint(const Consts<T>& c, T roe_delta, const double* w_far, const T* W, const T* a,
+                               const T* gnext, T ca, T cg, T* out, hipStream_t st);
 
 // out[c] = scale * sigma_1(w) at every cell
 template <typename T>

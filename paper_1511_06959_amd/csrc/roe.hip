@@ -37,6 +37,7 @@ __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 template <typename T>
 struct RoeC {
   T gm1, eref, p0, dfrac;  // gamma - 1, wref_E, (gamma - 1) wref_E, roe_delta
+  int open;                // characteristic boundaries in x (their faces are not corrected here)
 };
 
 // Cell and face values are held as (rho, rho u (full values), rho E - wref_E).  Primitive form:
@@ -92,18 +93,12 @@ __device__ __forceinline__ T sabs(T x, T del, T id, T& dx, T& dd) {
   return T(0.5) * (x * x + del * del) * id;
 }
 
-// dF = F_roe(w_l, w_r) - F_s(b, c) through the direction-D face between cells b and c; a and e are
-// the next cells outward.  REV = false: out[0] = dF.  REV = true: out[j] = d(G . dF)/d(cell j)
-// for the cells (a, b, c, e).
+// Roe's flux between the face states wl and wr in direction D (momentum flux with p - p0).
+// REV = false: F = the flux.  REV = true: the adjoints of G . F with respect to wl and wr are
+// added to wlb and wrb.
 template <typename T, int D, bool REV>
-__device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5], const T e[5], const RoeC<T>& k,
-                                         const T G[5], T out[4][5]) {
-  T wl[5], wr[5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    wl[v] = b[v] + T(0.25) * (c[v] - a[v]);
-    wr[v] = c[v] - T(0.25) * (e[v] - b[v]);
-  }
+__device__ __forceinline__ void roe_flux2(const T wl[5], const T wr[5], const RoeC<T>& k, const T G[5], T F[5],
+                                          T wlb[5], T wrb[5]) {
   const Pr<T> L = prim_of(wl, k), R = prim_of(wr, k);
   const T Hl = L.Ep * L.ir, Hr = R.Ep * R.ir;
   const T isl = rsq(wl[0]), isr = rsq(wr[0]), sl = wl[0] * isl, sr = wr[0] * isr;
@@ -130,37 +125,20 @@ __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5
   const T e2 = drho - dp * ic2, s2 = l2 * e2;    // |lam| a of the entropy wave
   const T S = s1 + s5 + s2, Ls = l2 * rt, dif = s5 - s1;
   const T udu = ut[0] * du[0] + ut[1] * du[1] + ut[2] * du[2];
-  // split form of the two cells: face means r, v, Hs (of E/rho), Pd (of p - p0); mK = r v_D
-  const Pr<T> Pb = prim_of(b, k), Pc = prim_of(c, k);
-  const T hb = (b[4] + k.eref) * Pb.ir, hc = (c[4] + k.eref) * Pc.ir;
-  const T r = T(0.5) * (b[0] + c[0]);
-  T v[3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) v[j] = T(0.5) * (Pb.u[j] + Pc.u[j]);
-  const T Hs = T(0.5) * (hb + hc), Pd = T(0.5) * (Pb.pd + Pc.pd);
-  const T mK = r * v[D];
   if constexpr (!REV) {
-    // dissipation sum_k |lam_k| a_k r_k
+    // F = mean of the cell fluxes of the face states - (1/2) sum_k |lam_k| a_k r_k
     T Dv[5];
     Dv[0] = S;
 #pragma unroll
     for (int j = 0; j < 3; ++j) Dv[1 + j] = j == D ? S * un + dif * cs : S * ut[j] + Ls * du[j];
     Dv[4] = (s1 + s5) * Ht + dif * un * cs + s2 * T(0.5) * q2 + Ls * (udu - un * dun);
-    // mean of the cell fluxes of the face states (momentum with p - p0)
-    T Fc[5];
-    Fc[0] = T(0.5) * (wl[1 + D] + wr[1 + D]);
+    F[0] = T(0.5) * (wl[1 + D] + wr[1 + D]);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Fc[1 + j] = T(0.5) * (wl[1 + D] * L.u[j] + wr[1 + D] * R.u[j]);
-    Fc[1 + D] += T(0.5) * (L.pd + R.pd);
-    Fc[4] = T(0.5) * (L.Ep * L.u[D] + R.Ep * R.u[D]);
-    T Fs[5];
-    Fs[0] = mK;
+    for (int j = 0; j < 3; ++j) F[1 + j] = T(0.5) * (wl[1 + D] * L.u[j] + wr[1 + D] * R.u[j]);
+    F[1 + D] += T(0.5) * (L.pd + R.pd);
+    F[4] = T(0.5) * (L.Ep * L.u[D] + R.Ep * R.u[D]);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Fs[1 + j] = mK * v[j];
-    Fs[1 + D] += Pd;
-    Fs[4] = mK * Hs + (Pd + k.p0) * v[D];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) out[0][q] = Fc[q] - T(0.5) * Dv[q] - Fs[q];
+    for (int q = 0; q < 5; ++q) F[q] -= T(0.5) * Dv[q];
   } else {
     // ---- reverse of the dissipation term (weight -G/2)
     T gD[5];
@@ -237,8 +215,8 @@ __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5
     }
     const T slb = (flb - frb) * fr * is + rtb * sr;
     const T srb = (frb - flb) * fl * is + rtb * sl;
-    T wlb[5] = {-drhob + slb * T(0.5) * isl, T(0), T(0), T(0), T(0)};
-    T wrb[5] = {drhob + srb * T(0.5) * isr, T(0), T(0), T(0), T(0)};
+    wlb[0] += -drhob + slb * T(0.5) * isl;
+    wrb[0] += drhob + srb * T(0.5) * isr;
     // ---- reverse of the mean of the cell fluxes (weight G)
     T pdlb = -dpb + T(0.5) * G[1 + D], pdrb = dpb + T(0.5) * G[1 + D];
     wlb[1 + D] += T(0.5) * G[0];
@@ -255,6 +233,45 @@ __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5
     const T Eplb = T(0.5) * G[4] * L.u[D] + Hlb * L.ir, Eprb = T(0.5) * G[4] * R.u[D] + Hrb * R.ir;
     prim_of_vjp(wl, L, k, ulb, pdlb, Eplb, Hlb * L.Ep, wlb);
     prim_of_vjp(wr, R, k, urb, pdrb, Eprb, Hrb * R.Ep, wrb);
+  }
+}
+
+// dF = F_roe(w_l, w_r) - F_s(b, c) through the direction-D face between cells b and c; a and e are
+// the next cells outward, w_l = b + ql (c - a), w_r = c - qr (e - b) with ql, qr = 1/4 (0 where the
+// reconstruction would reach beyond an open boundary).  REV = false: out[0] = dF.  REV = true:
+// out[j] = d(G . dF)/d(cell j) for the cells (a, b, c, e).
+template <typename T, int D, bool REV>
+__device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5], const T e[5], const RoeC<T>& k,
+                                         T ql, T qr, const T G[5], T out[4][5]) {
+  T wl[5], wr[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    wl[v] = b[v] + ql * (c[v] - a[v]);
+    wr[v] = c[v] - qr * (e[v] - b[v]);
+  }
+  // split form of the two cells: face means r, v, Hs (of E/rho), Pd (of p - p0); mK = r v_D
+  const Pr<T> Pb = prim_of(b, k), Pc = prim_of(c, k);
+  const T hb = (b[4] + k.eref) * Pb.ir, hc = (c[4] + k.eref) * Pc.ir;
+  const T r = T(0.5) * (b[0] + c[0]);
+  T v[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) v[j] = T(0.5) * (Pb.u[j] + Pc.u[j]);
+  const T Hs = T(0.5) * (hb + hc), Pd = T(0.5) * (Pb.pd + Pc.pd);
+  const T mK = r * v[D];
+  if constexpr (!REV) {
+    T F[5];
+    roe_flux2<T, D, false>(wl, wr, k, G, F, nullptr, nullptr);
+    T Fs[5];
+    Fs[0] = mK;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Fs[1 + j] = mK * v[j];
+    Fs[1 + D] += Pd;
+    Fs[4] = mK * Hs + (Pd + k.p0) * v[D];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[0][q] = F[q] - Fs[q];
+  } else {
+    T wlb[5] = {T(0), T(0), T(0), T(0), T(0)}, wrb[5] = {T(0), T(0), T(0), T(0), T(0)};
+    roe_flux2<T, D, true>(wl, wr, k, G, nullptr, wlb, wrb);
     // ---- reverse of the split form (weight -G)
     const T mKb = G[0] + G[1] * v[0] + G[2] * v[1] + G[3] * v[2] + G[4] * Hs;
     T vb[3];
@@ -266,13 +283,13 @@ __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5
     T bb[5] = {rb, T(0), T(0), T(0), Hsb * Pb.ir}, cb[5] = {rb, T(0), T(0), T(0), Hsb * Pc.ir};
     prim_of_vjp(b, Pb, k, vb, Pdb, T(0), Hsb * (b[4] + k.eref), bb);
     prim_of_vjp(c, Pc, k, vb, Pdb, T(0), Hsb * (c[4] + k.eref), cb);
-    // ---- reconstruction: w_l = b + (c - a)/4, w_r = c - (e - b)/4
+    // ---- reconstruction
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      out[0][q] = T(-0.25) * wlb[q];
-      out[1][q] = wlb[q] + T(0.25) * wrb[q] - bb[q];
-      out[2][q] = T(0.25) * wlb[q] + wrb[q] - cb[q];
-      out[3][q] = T(-0.25) * wrb[q];
+      out[0][q] = -ql * wlb[q];
+      out[1][q] = wlb[q] + qr * wrb[q] - bb[q];
+      out[2][q] = ql * wlb[q] + wrb[q] - cb[q];
+      out[3][q] = -qr * wrb[q];
     }
   }
 }
@@ -375,9 +392,21 @@ __device__ __forceinline__ void primal_dir(const Consts<T>& c, const RoeC<T>& k,
   for (int f = threadIdx.x; f < F::N; f += RNT) {
     int p, x, y, z;
     F::coords(f, p, x, y, z);
-    T w[4][5], o[4][5];
-    load4<T, D>(sw, NSP, E::at(p, x, y, z), w);
-    roe_face<T, D, false>(w[0], w[1], w[2], w[3], k, nullptr, o);
+    T w[4][5], o[4][5] = {};
+    T ql = T(0.25), qr = T(0.25);
+    bool live = true;
+    if (D == 0 && k.open) {
+      // the boundary faces carry the characteristic flux (boundary kernels); next to them the
+      // reconstruction does not reach into the ghost cells
+      const int gl = x0 + p - 1;
+      live = gl >= 0 && gl <= c.nx - 2;
+      ql = gl >= 1 ? T(0.25) : T(0);
+      qr = gl + 2 <= c.nx - 1 ? T(0.25) : T(0);
+    }
+    if (live) {
+      load4<T, D>(sw, NSP, E::at(p, x, y, z), w);
+      roe_face<T, D, false>(w[0], w[1], w[2], w[3], k, ql, qr, nullptr, o);
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v) sf[v * NFP + f] = o[0][v];
   }
@@ -450,9 +479,16 @@ __device__ __forceinline__ void adjoint_dir(const Consts<T>& c, const RoeC<T>& k
     bool live = f < F::N;
     int p = 0, x = 0, y = 0, z = 0;
     if (live) F::coords(f, p, x, y, z);
+    T ql = T(0.25), qr = T(0.25);
     if (live && D == 0 && c.wall) {
-      const int gl = x0 + p - 2;  // a face needs a real cell on at least one side
-      live = gl >= -1 && gl <= c.nx - 1;
+      const int gl = x0 + p - 2;
+      if (k.open) {  // as in the forward kernel
+        live = gl >= 0 && gl <= c.nx - 2;
+        ql = gl >= 1 ? T(0.25) : T(0);
+        qr = gl + 2 <= c.nx - 1 ? T(0.25) : T(0);
+      } else {  // slip walls: a face needs a real cell on at least one side
+        live = gl >= -1 && gl <= c.nx - 1;
+      }
     }
     if (live) {
       const int e0 = E::at(p, x, y, z);
@@ -460,7 +496,7 @@ __device__ __forceinline__ void adjoint_dir(const Consts<T>& c, const RoeC<T>& k
       load4<T, D>(lds, NSA, e0, w);
 #pragma unroll
       for (int v = 0; v < 5; ++v) G[v] = (lds[(5 + v) * NSA + e0 + 2 * E::S] - lds[(5 + v) * NSA + e0 + E::S]) * c.idx[D];
-      roe_face<T, D, true>(w[0], w[1], w[2], w[3], k, G, rec[i]);
+      roe_face<T, D, true>(w[0], w[1], w[2], w[3], k, ql, qr, G, rec[i]);
     } else {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -519,13 +555,115 @@ void k_roe_adjoint(Consts<T> c, RoeC<T> k, const T* __restrict__ W,
   for (int v = 0; v < 5; ++v) out[v * c.N + gi] += acc[v];
 }
 
+// ------------------------------------------------------------------------ open boundaries in x
+// Characteristic inflow/outflow boundaries (bc_x = ADJ_BC_CHARACTERISTIC).  The stage kernels
+// treat them as slip walls (mirror ghosts), so through each boundary face they evaluate the
+// mirror-pair flux H_w = (0, p - p0 - s_xx, 0, 0, 0): the mirror pair carries no mass, energy,
+// tangential stress or heat, and s_xx = (4/3) mu g_n - (2/3) mu (d_y u_y + d_z u_z) with the
+// normal gradient g_n = +-2 u_x/dx of the pair and the boundary cell's central tangential
+// divergence.  The kernels here replace H_w by the characteristic flux F_c, Roe's flux between the
+// far-field state and the boundary cell (x = 0) or the boundary cell and the far-field state
+// (x = L_x), which takes the entering waves from the far field and the leaving ones from inside:
+//   char_primal:  out += coef * (+-)(F_c - H_w)/dx at the boundary cells (+ at x = 0)
+//   char_adjoint: out += (its Jacobian)^T kh, gathered per boundary cell (s_xx also reaches the
+//                 y and z neighbours of a boundary cell through the tangential divergence)
+// One thread per boundary cell of either side.
 template <typename T>
-RoeC<T> roe_consts(const Consts<T>& c, T roe_delta) {
+struct Far {
+  T w[2][5];  // held far-field states beyond x = 0 and beyond x = L_x
+};
+
+constexpr int CB = 256;
+
+template <typename T>
+struct BCell {
+  int side;
+  long long q, jm, jp, km, kp;  // the cell and its y and z neighbours (periodic)
+};
+
+template <typename T>
+__device__ __forceinline__ bool bcell(const Consts<T>& c, int t, BCell<T>& b) {
+  const int ncol = c.ny * c.nz;
+  if (t >= 2 * ncol) return false;
+  b.side = t >= ncol;
+  const int r = t - b.side * ncol, j = r % c.ny, kz = r / c.ny, i = b.side ? c.nx - 1 : 0;
+  const int jp = j + 1 < c.ny ? j + 1 : 0, jm = j > 0 ? j - 1 : c.ny - 1;
+  const int kp = kz + 1 < c.nz ? kz + 1 : 0, km = kz > 0 ? kz - 1 : c.nz - 1;
+  auto at = [&](int jj, int kk) { return ((long long)kk * c.ny + jj) * c.nx + i; };
+  b.q = at(j, kz);
+  b.jm = at(jm, kz);
+  b.jp = at(jp, kz);
+  b.km = at(j, km);
+  b.kp = at(j, kp);
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ void held(const Consts<T>& c, const T* __restrict__ W, long long q, T w[5]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) w[v] = W[v * c.N + q] + c.wref[v];
+  w[4] = W[4 * c.N + q];
+}
+
+template <typename T>
+__global__ __launch_bounds__(CB) void k_char_primal(Consts<T> c, RoeC<T> k, Far<T> far, const T* __restrict__ W,
+                                                    T coef, T* __restrict__ out) {
+  BCell<T> b;
+  if (!bcell(c, (int)(blockIdx.x * CB + threadIdx.x), b)) return;
+  T w[5];
+  held(c, W, b.q, w);
+  auto uy = [&](long long q) { return (W[2 * c.N + q] + c.wref[2]) / (W[q] + c.wref[0]); };
+  auto uz = [&](long long q) { return (W[3 * c.N + q] + c.wref[3]) / (W[q] + c.wref[0]); };
+  const T div_t = (uy(b.jp) - uy(b.jm)) * (T(0.5) * c.idx[1]) + (uz(b.kp) - uz(b.km)) * (T(0.5) * c.idx[2]);
+  const T gn = (b.side ? T(-2) : T(2)) * (w[1] / w[0]) * c.idx[0];
+  const T sxx = (T(4) / T(3)) * c.mu * gn - (T(2) / T(3)) * c.mu * div_t;
+  T F[5];
+  if (b.side)
+    roe_flux2<T, 0, false>(w, far.w[1], k, nullptr, F, nullptr, nullptr);
+  else
+    roe_flux2<T, 0, false>(far.w[0], w, k, nullptr, F, nullptr, nullptr);
+  F[1] -= prim_of(w, k).pd - sxx;
+  const T f = coef * (b.side ? -c.idx[0] : c.idx[0]);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) out[v * c.N + b.q] += f * F[v];
+}
+
+template <typename T>
+__global__ __launch_bounds__(CB) void k_char_adjoint(Consts<T> c, RoeC<T> k, Far<T> far, const T* __restrict__ W,
+                                                     const T* __restrict__ a, const T* __restrict__ gnext, T ca, T cg,
+                                                     T* __restrict__ out) {
+  BCell<T> b;
+  if (!bcell(c, (int)(blockIdx.x * CB + threadIdx.x), b)) return;
+  auto kh = [&](int v, long long q) { return ca * a[v * c.N + q] + (gnext ? cg * gnext[v * c.N + q] : T(0)); };
+  const T sg = b.side ? -c.idx[0] : c.idx[0];
+  T w[5], G[5];
+  held(c, W, b.q, w);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) G[v] = sg * kh(v, b.q);
+  T wb[5] = {T(0), T(0), T(0), T(0), T(0)}, fb[5] = {T(0), T(0), T(0), T(0), T(0)};
+  if (b.side)
+    roe_flux2<T, 0, true>(w, far.w[1], k, G, nullptr, wb, fb);
+  else
+    roe_flux2<T, 0, true>(far.w[0], w, k, G, nullptr, fb, wb);
+  // - G_1 (p - p0 - s_xx) of this cell and of its y / z neighbours (through their divergence)
+  const T m23 = (T(2) / T(3)) * c.mu;
+  T ub[3];
+  ub[0] = G[1] * (T(4) / T(3)) * c.mu * (b.side ? T(-2) : T(2)) * c.idx[0];
+  ub[1] = -m23 * (T(0.5) * c.idx[1]) * sg * (kh(1, b.jm) - kh(1, b.jp));
+  ub[2] = -m23 * (T(0.5) * c.idx[2]) * sg * (kh(1, b.km) - kh(1, b.kp));
+  prim_of_vjp(w, prim_of(w, k), k, ub, -G[1], T(0), T(0), wb);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) out[v * c.N + b.q] += wb[v];
+}
+
+template <typename T>
+RoeC<T> roe_consts(const Consts<T>& c, T roe_delta, int open) {
   RoeC<T> k;
   k.gm1 = c.gamma - T(1);
   k.eref = c.wref[4];
   k.p0 = k.gm1 * c.wref[4];
   k.dfrac = roe_delta;
+  k.open = open;
   return k;
 }
 
@@ -537,27 +675,59 @@ int roe_tiles(const Consts<T>& c) {
 }  // namespace
 
 template <typename T>
-hipError_t launch_roe_primal(const Consts<T>& c, T roe_delta, const T* W, T coef, T* out, hipStream_t st) {
+hipError_t launch_roe_primal(const Consts<T>& c, T roe_delta, int open, const T* W, T coef, T* out, hipStream_t st) {
   ProfScope ps(ADJ_PROF_ROE_PRIMAL, st, true);
-  timed_launch(ps, k_roe_primal<T>, dim3(roe_tiles(c)), dim3(RNT), st, c, roe_consts(c, roe_delta), W, coef, out);
+  timed_launch(ps, k_roe_primal<T>, dim3(roe_tiles(c)), dim3(RNT), st, c, roe_consts(c, roe_delta, open), W, coef,
+               out);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_roe_adjoint(const Consts<T>& c, T roe_delta, const T* W, const T* a, const T* gnext, T ca, T cg,
-                              T* out, hipStream_t st) {
+hipError_t launch_roe_adjoint(const Consts<T>& c, T roe_delta, int open, const T* W, const T* a, const T* gnext, T ca,
+                              T cg, T* out, hipStream_t st) {
   ProfScope ps(ADJ_PROF_ROE_ADJOINT, st, true);
-  timed_launch(ps, k_roe_adjoint<T>, dim3(roe_tiles(c)), dim3(RNT), st, c, roe_consts(c, roe_delta), W, a, gnext, ca,
-               cg, out);
+  timed_launch(ps, k_roe_adjoint<T>, dim3(roe_tiles(c)), dim3(RNT), st, c, roe_consts(c, roe_delta, open), W, a,
+               gnext, ca, cg, out);
   return hipGetLastError();
 }
 
-template hipError_t launch_roe_primal<float>(const Consts<float>&, float, const float*, float, float*, hipStream_t);
-template hipError_t launch_roe_primal<double>(const Consts<double>&, double, const double*, double, double*,
-                                              hipStream_t);
-template hipError_t launch_roe_adjoint<float>(const Consts<float>&, float, const float*, const float*, const float*,
-                                              float, float, float*, hipStream_t);
-template hipError_t launch_roe_adjoint<double>(const Consts<double>&, double, const double*, const double*,
-                                               const double*, double, double, double*, hipStream_t);
+template <typename T>
+static Far<T> far_held(const Consts<T>& c, const double* w_far) {
+  Far<T> f;
+  for (int s = 0; s < 2; ++s)
+    for (int v = 0; v < 5; ++v) f.w[s][v] = (T)(v == 4 ? w_far[5 * s + 4] - (double)c.wref[4] : w_far[5 * s + v]);
+  return f;
+}
+
+template <typename T>
+hipError_t launch_char_primal(const Consts<T>& c, T roe_delta, const double* w_far, const T* W, T coef, T* out,
+                              hipStream_t st) {
+  ProfScope ps(ADJ_PROF_BOUNDARY, st, true);
+  const int n = 2 * c.ny * c.nz;
+  timed_launch(ps, k_char_primal<T>, dim3((n + CB - 1) / CB), dim3(CB), st, c, roe_consts(c, roe_delta, 1),
+               far_held(c, w_far), W, coef, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_char_adjoint(const Consts<T>& c, T roe_delta, const double* w_far, const T* W, const T* a,
+                               const T* gnext, T ca, T cg, T* out, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_BOUNDARY, st, true);
+  const int n = 2 * c.ny * c.nz;
+  timed_launch(ps, k_char_adjoint<T>, dim3((n + CB - 1) / CB), dim3(CB), st, c, roe_consts(c, roe_delta, 1),
+               far_held(c, w_far), W, a, gnext, ca, cg, out);
+  return hipGetLastError();
+}
+
+#define ADJNS_ROE_INST(T)                                                                                          \
+  template hipError_t launch_roe_primal<T>(const Consts<T>&, T, int, const T*, T, T*, hipStream_t);                \
+  template hipError_t launch_roe_adjoint<T>(const Consts<T>&, T, int, const T*, const T*, const T*, T, T, T*,       \
+                                            hipStream_t);                                                          \
+  template hipError_t launch_char_primal<T>(const Consts<T>&, T, const double*, const T*, T, T*, hipStream_t);     \
+  template hipError_t launch_char_adjoint<T>(const Consts<T>&, T, const double*, const T*, const T*, const T*, T, T, \
+                                             T*, hipStream_t);
+ADJNS_ROE_INST(float)
+ADJNS_ROE_INST(double)
+#undef ADJNS_ROE_INST
 
 }  // namespace adjns

@@ -186,7 +186,8 @@ class RevolveSweep:
         self.g = g
         self.bf16 = g.ckpt_format == CKPT_BF16
         self.gn = Grid.make(tuple(g.n), tuple(g.L), g.mu, g.dt, g.gamma, g.prandtl, g.bc_x, g.precision, 0,
-                            tuple(g.w_ref), tuple(g.nu_weight), g.time_scheme, g.flux, g.roe_delta)
+                            tuple(g.w_ref), tuple(g.nu_weight), g.time_scheme, g.flux, g.roe_delta,
+                            (tuple(g.w_far[0:5]), tuple(g.w_far[5:10])))
         self.nsteps, self.slots = nsteps, int(slots)
         self.s, self.obj, self.weights, self.lam = s, obj, weights, lam
         self.ws = workspace(g, device) if ws is None else ws

@@ -55,6 +55,11 @@ def test_workspace_and_record_sizes():
     (dict(nu_weight=(1.0, -0.5, 1.0)), -1), (dict(nu_weight=(1.0, 1.0, float("nan"))), -1), (dict(time_scheme=2), -1),
     (dict(flux=2), -1), (dict(flux=adj.FLUX_ROE, roe_delta=0.0), -1),
     (dict(flux=adj.FLUX_ROE, roe_delta=float("inf")), -1),
+    (dict(bc_x=adj.BC_CHARACTERISTIC), -1),  # no far-field states
+    (dict(bc_x=adj.BC_CHARACTERISTIC, w_far=((1.0, 0.3, 0, 0, 1.8), (1.0, 0.3, 0, 0, 0.01))), -1),  # p < 0
+    (dict(bc_x=adj.BC_CHARACTERISTIC, w_far=((1.0, 0.3, 0, 0, 1.8), (1.0, 0.3, 0, 0, 1.8)), roe_delta=0.0), -1),
+    (dict(bc_x=adj.BC_CHARACTERISTIC, n=(1, 8, 4), w_far=((1.0, 0.3, 0, 0, 1.8), (1.0, 0.3, 0, 0, 1.8))), -2),
+    (dict(bc_x=3), -1),
 ])
 def test_bad_grid_rejected(bad, code):
     g = _grid(**bad)
@@ -127,7 +132,7 @@ def test_ensemble_table_size_grows_with_members():
 @pytest.mark.parametrize("case,code", [
     ("members_decreasing", -1), ("member_box_range", -1), ("negative_lambda", -1), ("mixed_precision", -1),
     ("mixed_boundary", -1), ("bf16_states", -1), ("objective_kind", -1), ("small_table", -6), ("bad_grid", -1),
-    ("ssprk3", -1), ("roe", -1),
+    ("ssprk3", -1), ("roe", -1), ("characteristic", -1),
 ])
 def test_ensemble_create_rejects(case, code):
     g = [_grid(), _grid(n=(8, 8, 8))]
@@ -154,6 +159,9 @@ def test_ensemble_create_rejects(case, code):
         g[1] = _grid(n=(8, 8, 8), time_scheme=adj.SSPRK3)
     elif case == "roe":
         g[1] = _grid(n=(8, 8, 8), flux=adj.FLUX_ROE)
+    elif case == "characteristic":
+        far = ((1.0, 0.3, 0, 0, 1.8), (1.0, 0.3, 0, 0, 1.8))
+        g = [_grid(bc_x=adj.BC_CHARACTERISTIC, w_far=far), _grid(n=(8, 8, 8), bc_x=adj.BC_CHARACTERISTIC, w_far=far)]
     assert _create(g, mb, ml, obj, tb) == code
     assert adj.lib().adj_last_error()
 
