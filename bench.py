@@ -112,7 +112,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     w_ref = adj.reference_state(wl.w0) if precision == adj.F32 else None
     g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision,
                       adj.CKPT_BF16 if ckpt_bf16 else adj.CKPT_NATIVE, w_ref, time_scheme=time_scheme, flux=flux,
-                      roe_delta=ROE_DELTA)
+                      roe_delta=ROE_DELTA, w_far=wl.extra.get("w_far"))
     tiles = {}
     if tune:
         tiles = _tile_report(autotune.tune(g), g, wl.lam > 0.0)
@@ -149,7 +149,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     for name, cls in (("adjoint_stage", adj.PROF_ADJOINT_STAGE), ("primal_stage", adj.PROF_PRIMAL_STAGE),
                       ("objective", adj.PROF_OBJECTIVE), ("sigma1", adj.PROF_SIGMA1), ("codec", adj.PROF_CODEC),
                       ("reduce", adj.PROF_REDUCE), ("roe_primal", adj.PROF_ROE_PRIMAL),
-                      ("roe_adjoint", adj.PROF_ROE_ADJOINT)):
+                      ("roe_adjoint", adj.PROF_ROE_ADJOINT), ("boundary", adj.PROF_BOUNDARY)):
         prof[name] = adj.profile_read(cls)
     del traj, ws
     torch.cuda.empty_cache()
@@ -346,6 +346,10 @@ WORKLOADS = {
     "ensemble": "batched ensemble of 64 periodic decaying-turbulence boxes (sizes from {32,48,64,96}^3, Mach_rms "
                 "0.3, nu 0.0175), windows of 50-400 RK4 steps, lambda from {0,0.03,0.1,0.3,1} dx^2 sigma_1, "
                 "time-averaged mean pressure per box; one launch per RK stage covers every running box",
+    "spatial_wake": "spatially developing wake 512x256x32 (characteristic inlet and outlet in x, uniform free "
+                    "stream Mach 0.85, drag strip at 0.1 L_x holding the deficit, Re 5e4), {n}-step window "
+                    "sample, lambda 0.1 dx^2 sigma_1, stagnation-pressure loss on the plane x = 0.75 L_x, "
+                    "gradient wrt the body force",
     "offload": "decaying turbulence 384^3 periodic (Mach_rms 0.4, nu 2.887e-3), {n}-step window sample, lambda 0.1 "
                "dx^2 sigma_1, mean pressure; the window's BF16 records kept in pinned host memory and streamed "
                "over PCIe (device-to-host after each primal step, host-to-device one step ahead of the reverse "
@@ -364,6 +368,8 @@ def make_workload(name, window):
         return W.turb_384(nsteps=window or 10, lam_factor=0.1)
     if name == "wake":
         return W.wake(nsteps=window or 20, lam_factor=0.1)
+    if name == "spatial_wake":
+        return W.spatial_wake(nsteps=window or 20, lam_factor=0.1)
     raise SystemExit(f"unknown workload {name}")
 
 

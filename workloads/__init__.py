@@ -62,8 +62,11 @@ class Workload:
         return int(self.n[0] * self.n[1] * self.n[2])
 
     def params(self):
-        return dict(n=self.n, L=self.L, gamma=self.gamma, prandtl=self.prandtl, mu=self.mu,
-                    dt=self.dt, bc_x=self.bc_x)
+        p = dict(n=self.n, L=self.L, gamma=self.gamma, prandtl=self.prandtl, mu=self.mu, dt=self.dt,
+                 bc_x=self.bc_x)
+        if "w_far" in self.extra:
+            p["w_far"] = np.concatenate([np.asarray(f, dtype=np.float64) for f in self.extra["w_far"]])
+        return p
 
 
 def cell_centres(n, L):
@@ -214,6 +217,50 @@ def wake(n=(512, 256, 32), nsteps=4000, lam_factor=0.0, seed=2, delta=1.0):
     return Workload(f"wake_{nn[0]}x{nn[1]}x{nn[2]}", nn, L, mu, dt, w0, np.zeros_like(w0), nsteps,
                     OBJ_PT_LOSS_PLANE, window_weights(nsteps, 1, nsteps), lam=lam_factor * dx0 * dx0,
                     lam_factor=lam_factor, bc_x=1, plane_i=int(round(0.75 * nn[0])), pt_ref=pt_ref)
+
+
+def spatial_wake(n=(512, 256, 32), nsteps=4000, lam_factor=0.0, seed=7, delta=1.0, mach=0.85, drag=0.05):
+    """Spatially developing wake: x streamwise between a characteristic inlet (uniform free stream
+    at Mach `mach`) and a characteristic outlet (the same far-field state), y cross-stream and z
+    span periodic.  A streamwise body-force sink (peak `drag` U^2/delta, Gaussian of width delta
+    across the stream and 2 cells along it, at x = 0.1 L_x) holds a wake deficit; the initial field
+    carries that deficit downstream of the strip plus a 2 % solenoidal perturbation.  Objective: the density-
+    weighted stagnation-pressure loss on the cross-stream plane at x = 0.75 L_x; the gradient is
+    with respect to the body force (the source field)."""
+    nn = tuple(n)
+    dx0 = delta / 16.0
+    L = tuple(nn[d] * dx0 for d in range(3))
+    rng = np.random.default_rng(seed)
+    cinf = 1.0
+    Uinf, Uc = mach * cinf, 0.6 * mach * cinf
+    x, y, z = cell_centres(nn, L)
+    prof = np.exp(-(((y - 0.5 * L[1]) / delta) ** 2))
+    ramp = 0.5 * (1.0 + np.tanh((x - 0.1 * L[0]) / (4.0 * dx0)))  # the deficit starts at the strip
+    ux = Uinf - (Uinf - Uc) * prof * ramp
+    kmax = math.pi / dx0
+    pu, pv, pw = solenoidal_field(nn, L, rng, lambda k: np.where(k <= 0.5 * kmax, 1.0, 0.0))
+    rms = math.sqrt(float(np.mean(pu * pu + pv * pv + pw * pw)) / 3.0)
+    sc = 0.02 * Uinf / rms
+    u, v, w = ux + pu * sc, pv * sc, pw * sc
+    rho = np.ones_like(u)
+    pinf = cinf * cinf / GAMMA
+    p = np.full_like(u, pinf)
+    mu = 1.0 * Uinf * delta / 5e4
+    dx = [L[d] / nn[d] for d in range(3)]
+    dt = cfl_dt(rho, u, v, w, p, dx)
+    w0 = conservative(rho, u, v, w, p)
+    # drag strip: momentum sink f_x and the work it does on the free stream, U_inf f_x
+    fx = -drag * Uinf * Uinf / delta * prof * np.exp(-(((x - 0.1 * L[0]) / (2.0 * dx0)) ** 2))
+    s = np.zeros_like(w0).reshape(5, -1)
+    s[1] = fx.ravel()
+    s[4] = Uinf * fx.ravel()
+    far = conservative(np.ones(1), np.full(1, Uinf), np.zeros(1), np.zeros(1), np.full(1, pinf))
+    minf = Uinf / cinf
+    pt_ref = pinf * (1.0 + 0.5 * (GAMMA - 1.0) * minf * minf) ** (GAMMA / (GAMMA - 1.0))
+    return Workload(f"spatial_wake_{nn[0]}x{nn[1]}x{nn[2]}", nn, L, mu, dt, w0, s.reshape(-1), nsteps,
+                    OBJ_PT_LOSS_PLANE, window_weights(nsteps, 1, nsteps), lam=lam_factor * dx0 * dx0,
+                    lam_factor=lam_factor, bc_x=2, plane_i=int(round(0.75 * nn[0])), pt_ref=pt_ref,
+                    extra={"w_far": (tuple(far), tuple(far))})
 
 
 def ensemble_draws(nboxes=64, seed_sizes=3, seed_windows=5, seed_lams=6):
