@@ -80,7 +80,7 @@ def valu_roofline(valu, cells, avg_us):
 
 def kernel_hash(source="stencil.hip"):
     """sha256 of a kernel family's sources (stencil.hip: the stage kernels, roe.hip: the Roe
-    corrections), as the committed counter summaries record it."""
+    flux kernels), as the committed counter summaries record it."""
     h = hashlib.sha256()
     for name in (source, "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1511_06959_amd", "csrc", name), "rb").read())
@@ -188,7 +188,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     out["stage_alg_bytes"] = alg_bytes
     out["stage_achieved_gbs"] = alg_bytes / avg_s / 1e9
     if flux == 1:
-        # Roe corrections: the primal kernel reads W and updates out (15 values per cell), the
+        # Roe flux kernels: the primal kernel reads W and updates out (15 values per cell), the
         # reverse kernel reads W, a, gnext and updates out (25 values per cell)
         out["roe"] = {}
         for name, vals in (("roe_primal", 15), ("roe_adjoint", 25)):
@@ -455,7 +455,7 @@ def main():
     }
     roof_valu = valu_roofline(valu, wl.ncells, r32["stage_avg_us"])
     if "roe" in r32:
-        # with the Roe flux the transpose of its correction takes the largest share of the window
+        # with the Roe flux the transpose of its flux terms takes the largest share of the window
         rk = r32["roe"]["roe_adjoint"]
         rhash = kernel_hash("roe.hip")
         rtraffic = profile_values("traffic_roe_adjoint_tgv64.txt", rhash, "")
@@ -470,7 +470,7 @@ def main():
             "unit": "GB/s",
             "frac": rk["frac_hbm"],
             "traffic": None if rtraffic is None else float(rtraffic["bytes_per_cell_launch_f32"]) * wl.ncells,
-            "kernel": "k_roe_adjoint (transpose of the Roe flux correction)",
+            "kernel": "k_roe_adjoint (transpose of the Roe convective terms)",
             "avg_launch_us": rk["avg_launch_us"],
             "alg_bytes_per_launch": rk["alg_bytes_per_launch"],
         }

@@ -234,7 +234,7 @@ enum {
   ADJ_PROF_OBJECTIVE = 3,     /* objective values and gradients                 */
   ADJ_PROF_CODEC = 4,         /* checkpoint encode / decode                     */
   ADJ_PROF_REDUCE = 5,        /* energy and inner products                      */
-  ADJ_PROF_ROE_PRIMAL = 6,    /* Roe flux correction of primal stages           */
+  ADJ_PROF_ROE_PRIMAL = 6,    /* Roe convective terms of primal stages          */
   ADJ_PROF_ROE_ADJOINT = 7,   /* its transpose in reverse stages                */
   ADJ_PROF_BOUNDARY = 8,      /* characteristic boundary fluxes and transposes  */
   ADJ_PROF_NCLASS = 9

@@ -172,39 +172,45 @@ size_t ckpt_header_bytes(const adj_grid* g) {
   return up(nb * 10 * sizeof(float));
 }
 
-// One primal stage (launch_primal_stage) and, on a Roe-flux grid, the correction of its residual
-// to the Roe flux, on a grid with characteristic boundaries the correction of the boundary faces,
-// each weighted like R in the stage (cR; dt/6 in stage 4; 1 for the plain residual).
+// One primal stage (launch_primal_stage; on a Roe-flux grid without its split-form convective
+// flux) and, on a Roe-flux grid, the Roe convective terms, on a grid with characteristic
+// boundaries the correction of the boundary faces, each weighted like R in the stage (cR; dt/6 in
+// stage 4; 1 for the plain residual).
 template <typename T>
 int primal_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
                  const T* W3, T cR, T* out, hipStream_t st, const char* what, T ca = T(0), T cb = T(0)) {
   hipError_t e;
-  if ((e = launch_primal_stage<T>(mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb))) return hip_fail(e, what);
+  const int split = g->flux == ADJ_FLUX_SPLIT;
+  if ((e = launch_primal_stage<T>(mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb, split))) return hip_fail(e, what);
   const T coef = mode == STAGE_FIN ? c.dt / T(6) : (mode == STAGE_RES ? T(1) : cR);
   const int open = g->bc_x == ADJ_BC_CHARACTERISTIC;
-  if (g->flux == ADJ_FLUX_ROE) {
+  if (!split) {
     if ((e = launch_roe_primal<T>(c, (T)g->roe_delta, open, W, coef, out, st))) return hip_fail(e, what);
   }
   if (open) {
-    if ((e = launch_char_primal<T>(c, (T)g->roe_delta, &g->w_far[0][0], W, coef, out, st))) return hip_fail(e, what);
+    if ((e = launch_char_primal<T>(c, (T)g->roe_delta, split, &g->w_far[0][0], W, coef, out, st)))
+      return hip_fail(e, what);
   }
   return ADJ_OK;
 }
 
-// One reverse stage (launch_adjoint_stage) and the transposes of the Roe-flux and boundary
-// corrections applied to the same kh = ca a + cg gnext, added into `out` (g, or w^_n in stage 1).
+// One reverse stage (launch_adjoint_stage, as the primal stage) and the transposes of the Roe
+// terms and boundary corrections applied to the same kh = ca a + cg gnext, added into `out` (g, or
+// w^_n in stage 1).
 template <typename T>
 int adjoint_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext,
                   const T* nu, T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st,
                   const char* what) {
   hipError_t e;
-  if ((e = launch_adjoint_stage<T>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st))) return hip_fail(e, what);
+  const int split = g->flux == ADJ_FLUX_SPLIT;
+  if ((e = launch_adjoint_stage<T>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st, split)))
+    return hip_fail(e, what);
   const int open = g->bc_x == ADJ_BC_CHARACTERISTIC;
-  if (g->flux == ADJ_FLUX_ROE) {
+  if (!split) {
     if ((e = launch_roe_adjoint<T>(c, (T)g->roe_delta, open, W, a, gnext, ca, cg, out, st))) return hip_fail(e, what);
   }
   if (open) {
-    if ((e = launch_char_adjoint<T>(c, (T)g->roe_delta, &g->w_far[0][0], W, a, gnext, ca, cg, out, st)))
+    if ((e = launch_char_adjoint<T>(c, (T)g->roe_delta, split, &g->w_far[0][0], W, a, gnext, ca, cg, out, st)))
       return hip_fail(e, what);
   }
   return ADJ_OK;

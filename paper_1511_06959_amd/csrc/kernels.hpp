@@ -9,9 +9,10 @@ enum { STAGE_RES = 0, STAGE_LIN = 1, STAGE_FIN = 2, STAGE_AFF = 3 };  // primal 
 enum { STAGE_VJP = 0 };                                  // adjoint stage modes (STAGE_FIN shared)
 
 // STAGE_AFF: out = ca * wn + cb * W + cR * R(W; s)  (the SSP-RK3 stages)
+// conv = 0: R without the split-form convective flux (the Roe option adds its own afterwards)
 template <typename T>
 hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
-                               const T* W3, T cR, T* out, hipStream_t st, T ca = T(0), T cb = T(0));
+                               const T* W3, T cR, T* out, hipStream_t st, T ca = T(0), T cb = T(0), int conv = 1);
 
 // SSP-RK3 reverse step, after the three stage transposes g3 (at u2), g2 (at u1), g1 (at w_n):
 // rk3_mid:     h = g2 + g3/4                               (in place of g2; k^1 = dt/6 a + dt h)
@@ -22,14 +23,15 @@ template <typename T>
 hipError_t launch_rk3_combine(const T* a, const T* g1, const T* h, const T* g3, T dt, T* wh, T* grad_s, long long n,
                               hipStream_t st);
 
+// conv = 0: without the transpose of the split-form convective flux
 template <typename T>
 hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,
-                                T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st);
+                                T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st, int conv = 1);
 
-// Roe flux option: the difference dF = F_roe - F_split of every face flux (roe.hip), added after
-// the stage kernel that wrote `out` from the same W:
-//   roe_primal:  out += coef * (-sum_d (dF_{d,+} - dF_{d,-}) / dx_d)
-//   roe_adjoint: out += J_dF(W)^T kh,  kh = ca a + cg gnext (gnext may be NULL)
+// Roe flux option: the Roe convective flux F of every face (roe.hip), added after the stage
+// kernel (launched with conv = 0) that wrote `out` from the same W:
+//   roe_primal:  out += coef * (-sum_d (F_{d,+} - F_{d,-}) / dx_d)
+//   roe_adjoint: out += J_F(W)^T kh,  kh = ca a + cg gnext (gnext may be NULL)
 // (open: characteristic boundaries in x, whose faces these kernels leave alone)
 template <typename T>
 hipError_t launch_roe_primal(const Consts<T>& c, T roe_delta, int open, const T* W, T coef, T* out, hipStream_t st);
@@ -37,16 +39,17 @@ template <typename T>
 hipError_t launch_roe_adjoint(const Consts<T>& c, T roe_delta, int open, const T* W, const T* a, const T* gnext, T ca,
                               T cg, T* out, hipStream_t st);
 // Characteristic boundaries in x: the flux the stage kernels evaluated through the two boundary
-// faces (a slip-wall mirror pair) replaced by Roe's flux against the far-field states w_far
-// (2 x 5 conservative values), after the stage kernel (and Roe correction) that wrote `out`:
+// faces (a slip-wall mirror pair; split: whether they included the split-form convective flux)
+// replaced by Roe's flux against the far-field states w_far (2 x 5 conservative values), after
+// the stage kernel (and Roe kernel) that wrote `out`:
 //   char_primal:  out += coef * (boundary-face flux difference) / dx at the boundary cells
 //   char_adjoint: out += its transpose applied to kh = ca a + cg gnext
 template <typename T>
-hipError_t launch_char_primal(const Consts<T>& c, T roe_delta, const double* w_far, const T* W, T coef, T* out,
-                              hipStream_t st);
+hipError_t launch_char_primal(const Consts<T>& c, T roe_delta, int split, const double* w_far, const T* W, T coef,
+                              T* out, hipStream_t st);
 template <typename T>
-hipError_t launch_char_adjoint(const Consts<T>& c, T roe_delta, const double* w_far, const T* W, const T* a,
-                               const T* gnext, T ca, T cg, T* out, hipStream_t st);
+hipError_t launch_char_adjoint(const Consts<T>& c, T roe_delta, int split, const double* w_far, const T* W,
+                               const T* a, const T* gnext, T ca, T cg, T* out, hipStream_t st);
 
 // out[c] = scale * sigma_1(w) at every cell
 template <typename T>

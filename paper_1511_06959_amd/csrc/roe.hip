@@ -9,13 +9,14 @@
 // |lam| smoothed within delta = roe_delta c~ of zero ((lam^2 + delta^2)/(2 delta) there), so that
 // the flux has a derivative everywhere.
 //
-// The stage kernels (stencil.hip) evaluate the split-form flux F_s of the two cells of each face;
-// the kernels here add the difference dF = F - F_s, which keeps the stage kernels unchanged:
-//   roe_primal:  out += coef * (-sum_d (dF_{d,i+1/2} - dF_{d,i-1/2}) / dx_d)
-//   roe_adjoint: out += J_dF(W)^T kh,  kh = ca a + cg gnext
-// (added after the stage kernel that wrote `out` with the same W, coefficients and kh).  The
-// reverse kernel is the exact transpose: per face, the hand-written reverse of dF's evaluation
-// turns G = (kh_R - kh_L)/dx_d into adjoint shares of the four cells of the face's stencil.
+// On such grids the stage kernels (stencil.hip) run without their split-form convective flux and
+// evaluate the viscous terms, the source and the stage update; the kernels here add the Roe
+// convective terms to their output:
+//   roe_primal:  out += coef * (-sum_d (F_{d,i+1/2} - F_{d,i-1/2}) / dx_d)
+//   roe_adjoint: out += J_F(W)^T kh,  kh = ca a + cg gnext
+// (after the stage kernel that wrote `out` with the same W, coefficients and kh).  The reverse
+// kernel is the exact transpose: per face, the hand-written reverse of F's evaluation turns
+// G = (kh_R - kh_L)/dx_d into adjoint shares of the four cells of the face's stencil.
 //
 // Both kernels treat one direction at a time: the tile's cells plus a halo along that direction
 // only (2 cells forward, 3 in reverse) are staged in LDS, every face of the direction that the
@@ -37,7 +38,8 @@ __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 template <typename T>
 struct RoeC {
   T gm1, eref, p0, dfrac;  // gamma - 1, wref_E, (gamma - 1) wref_E, roe_delta
-  int open;                // characteristic boundaries in x (their faces are not corrected here)
+  int open;                // characteristic boundaries in x (the Roe kernels leave their faces alone)
+  int split;               // boundary kernels: the stage kernels included the split-form flux
 };
 
 // Cell and face values are held as (rho, rho u (full values), rho E - wref_E).  Primitive form:
@@ -236,10 +238,10 @@ __device__ __forceinline__ void roe_flux2(const T wl[5], const T wr[5], const Ro
   }
 }
 
-// dF = F_roe(w_l, w_r) - F_s(b, c) through the direction-D face between cells b and c; a and e are
-// the next cells outward, w_l = b + ql (c - a), w_r = c - qr (e - b) with ql, qr = 1/4 (0 where the
-// reconstruction would reach beyond an open boundary).  REV = false: out[0] = dF.  REV = true:
-// out[j] = d(G . dF)/d(cell j) for the cells (a, b, c, e).
+// Roe's flux through the direction-D face between cells b and c; a and e are the next cells
+// outward, the face states w_l = b + ql (c - a), w_r = c - qr (e - b) with ql, qr = 1/4 (0 where
+// the reconstruction would reach beyond an open boundary).  REV = false: out[0] = F.  REV = true:
+// out[j] = d(G . F)/d(cell j) for the cells (a, b, c, e).
 template <typename T, int D, bool REV>
 __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5], const T e[5], const RoeC<T>& k,
                                          T ql, T qr, const T G[5], T out[4][5]) {
@@ -249,46 +251,16 @@ __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5
     wl[v] = b[v] + ql * (c[v] - a[v]);
     wr[v] = c[v] - qr * (e[v] - b[v]);
   }
-  // split form of the two cells: face means r, v, Hs (of E/rho), Pd (of p - p0); mK = r v_D
-  const Pr<T> Pb = prim_of(b, k), Pc = prim_of(c, k);
-  const T hb = (b[4] + k.eref) * Pb.ir, hc = (c[4] + k.eref) * Pc.ir;
-  const T r = T(0.5) * (b[0] + c[0]);
-  T v[3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) v[j] = T(0.5) * (Pb.u[j] + Pc.u[j]);
-  const T Hs = T(0.5) * (hb + hc), Pd = T(0.5) * (Pb.pd + Pc.pd);
-  const T mK = r * v[D];
   if constexpr (!REV) {
-    T F[5];
-    roe_flux2<T, D, false>(wl, wr, k, G, F, nullptr, nullptr);
-    T Fs[5];
-    Fs[0] = mK;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) Fs[1 + j] = mK * v[j];
-    Fs[1 + D] += Pd;
-    Fs[4] = mK * Hs + (Pd + k.p0) * v[D];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) out[0][q] = F[q] - Fs[q];
+    roe_flux2<T, D, false>(wl, wr, k, G, out[0], nullptr, nullptr);
   } else {
     T wlb[5] = {T(0), T(0), T(0), T(0), T(0)}, wrb[5] = {T(0), T(0), T(0), T(0), T(0)};
     roe_flux2<T, D, true>(wl, wr, k, G, nullptr, wlb, wrb);
-    // ---- reverse of the split form (weight -G)
-    const T mKb = G[0] + G[1] * v[0] + G[2] * v[1] + G[3] * v[2] + G[4] * Hs;
-    T vb[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) vb[j] = T(0.5) * G[1 + j] * mK;  // halves: each mean splits equally
-    vb[D] += T(0.5) * (G[4] * (Pd + k.p0) + mKb * r);
-    const T Pdb = T(0.5) * (G[1 + D] + G[4] * v[D]);
-    const T rb = T(0.5) * mKb * v[D], Hsb = T(0.5) * G[4] * mK;
-    T bb[5] = {rb, T(0), T(0), T(0), Hsb * Pb.ir}, cb[5] = {rb, T(0), T(0), T(0), Hsb * Pc.ir};
-    prim_of_vjp(b, Pb, k, vb, Pdb, T(0), Hsb * (b[4] + k.eref), bb);
-    prim_of_vjp(c, Pc, k, vb, Pdb, T(0), Hsb * (c[4] + k.eref), cb);
-    // ---- reconstruction
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       out[0][q] = -ql * wlb[q];
-      out[1][q] = wlb[q] + qr * wrb[q] - bb[q];
-      out[2][q] = ql * wlb[q] + wrb[q] - cb[q];
+      out[1][q] = wlb[q] + qr * wrb[q];
+      out[2][q] = ql * wlb[q] + wrb[q];
       out[3][q] = -qr * wrb[q];
     }
   }
@@ -558,10 +530,11 @@ void k_roe_adjoint(Consts<T> c, RoeC<T> k, const T* __restrict__ W,
 // ------------------------------------------------------------------------ open boundaries in x
 // Characteristic inflow/outflow boundaries (bc_x = ADJ_BC_CHARACTERISTIC).  The stage kernels
 // treat them as slip walls (mirror ghosts), so through each boundary face they evaluate the
-// mirror-pair flux H_w = (0, p - p0 - s_xx, 0, 0, 0): the mirror pair carries no mass, energy,
-// tangential stress or heat, and s_xx = (4/3) mu g_n - (2/3) mu (d_y u_y + d_z u_z) with the
-// normal gradient g_n = +-2 u_x/dx of the pair and the boundary cell's central tangential
-// divergence.  The kernels here replace H_w by the characteristic flux F_c, Roe's flux between the
+// mirror-pair flux H_w = (0, p - p0 - s_xx, 0, 0, 0), or (0, -s_xx, 0, 0, 0) when they run
+// without the split-form convective flux (Roe grids, whose Roe kernels skip the boundary faces):
+// the mirror pair carries no mass, energy, tangential stress or heat, and
+// s_xx = (4/3) mu g_n - (2/3) mu (d_y u_y + d_z u_z) with the normal gradient g_n = +-2 u_x/dx of
+// the pair and the boundary cell's central tangential divergence.  The kernels here replace H_w by the characteristic flux F_c, Roe's flux between the
 // far-field state and the boundary cell (x = 0) or the boundary cell and the far-field state
 // (x = L_x), which takes the entering waves from the far field and the leaving ones from inside:
 //   char_primal:  out += coef * (+-)(F_c - H_w)/dx at the boundary cells (+ at x = 0)
@@ -622,7 +595,7 @@ __global__ __launch_bounds__(CB) void k_char_primal(Consts<T> c, RoeC<T> k, Far<
     roe_flux2<T, 0, false>(w, far.w[1], k, nullptr, F, nullptr, nullptr);
   else
     roe_flux2<T, 0, false>(far.w[0], w, k, nullptr, F, nullptr, nullptr);
-  F[1] -= prim_of(w, k).pd - sxx;
+  F[1] -= (k.split ? prim_of(w, k).pd : T(0)) - sxx;
   const T f = coef * (b.side ? -c.idx[0] : c.idx[0]);
 #pragma unroll
   for (int v = 0; v < 5; ++v) out[v * c.N + b.q] += f * F[v];
@@ -651,19 +624,20 @@ __global__ __launch_bounds__(CB) void k_char_adjoint(Consts<T> c, RoeC<T> k, Far
   ub[0] = G[1] * (T(4) / T(3)) * c.mu * (b.side ? T(-2) : T(2)) * c.idx[0];
   ub[1] = -m23 * (T(0.5) * c.idx[1]) * sg * (kh(1, b.jm) - kh(1, b.jp));
   ub[2] = -m23 * (T(0.5) * c.idx[2]) * sg * (kh(1, b.km) - kh(1, b.kp));
-  prim_of_vjp(w, prim_of(w, k), k, ub, -G[1], T(0), T(0), wb);
+  prim_of_vjp(w, prim_of(w, k), k, ub, k.split ? -G[1] : T(0), T(0), T(0), wb);
 #pragma unroll
   for (int v = 0; v < 5; ++v) out[v * c.N + b.q] += wb[v];
 }
 
 template <typename T>
-RoeC<T> roe_consts(const Consts<T>& c, T roe_delta, int open) {
+RoeC<T> roe_consts(const Consts<T>& c, T roe_delta, int open, int split = 0) {
   RoeC<T> k;
   k.gm1 = c.gamma - T(1);
   k.eref = c.wref[4];
   k.p0 = k.gm1 * c.wref[4];
   k.dfrac = roe_delta;
   k.open = open;
+  k.split = split;
   return k;
 }
 
@@ -700,21 +674,21 @@ static Far<T> far_held(const Consts<T>& c, const double* w_far) {
 }
 
 template <typename T>
-hipError_t launch_char_primal(const Consts<T>& c, T roe_delta, const double* w_far, const T* W, T coef, T* out,
-                              hipStream_t st) {
+hipError_t launch_char_primal(const Consts<T>& c, T roe_delta, int split, const double* w_far, const T* W, T coef,
+                              T* out, hipStream_t st) {
   ProfScope ps(ADJ_PROF_BOUNDARY, st, true);
   const int n = 2 * c.ny * c.nz;
-  timed_launch(ps, k_char_primal<T>, dim3((n + CB - 1) / CB), dim3(CB), st, c, roe_consts(c, roe_delta, 1),
+  timed_launch(ps, k_char_primal<T>, dim3((n + CB - 1) / CB), dim3(CB), st, c, roe_consts(c, roe_delta, 1, split),
                far_held(c, w_far), W, coef, out);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_char_adjoint(const Consts<T>& c, T roe_delta, const double* w_far, const T* W, const T* a,
-                               const T* gnext, T ca, T cg, T* out, hipStream_t st) {
+hipError_t launch_char_adjoint(const Consts<T>& c, T roe_delta, int split, const double* w_far, const T* W,
+                               const T* a, const T* gnext, T ca, T cg, T* out, hipStream_t st) {
   ProfScope ps(ADJ_PROF_BOUNDARY, st, true);
   const int n = 2 * c.ny * c.nz;
-  timed_launch(ps, k_char_adjoint<T>, dim3((n + CB - 1) / CB), dim3(CB), st, c, roe_consts(c, roe_delta, 1),
+  timed_launch(ps, k_char_adjoint<T>, dim3((n + CB - 1) / CB), dim3(CB), st, c, roe_consts(c, roe_delta, 1, split),
                far_held(c, w_far), W, a, gnext, ca, cg, out);
   return hipGetLastError();
 }
@@ -723,9 +697,9 @@ hipError_t launch_char_adjoint(const Consts<T>& c, T roe_delta, const double* w_
   template hipError_t launch_roe_primal<T>(const Consts<T>&, T, int, const T*, T, T*, hipStream_t);                \
   template hipError_t launch_roe_adjoint<T>(const Consts<T>&, T, int, const T*, const T*, const T*, T, T, T*,       \
                                             hipStream_t);                                                          \
-  template hipError_t launch_char_primal<T>(const Consts<T>&, T, const double*, const T*, T, T*, hipStream_t);     \
-  template hipError_t launch_char_adjoint<T>(const Consts<T>&, T, const double*, const T*, const T*, const T*, T, T, \
-                                             T*, hipStream_t);
+  template hipError_t launch_char_primal<T>(const Consts<T>&, T, int, const double*, const T*, T, T*, hipStream_t); \
+  template hipError_t launch_char_adjoint<T>(const Consts<T>&, T, int, const double*, const T*, const T*, const T*, \
+                                             T, T, T*, hipStream_t);
 ADJNS_ROE_INST(float)
 ADJNS_ROE_INST(double)
 #undef ADJNS_ROE_INST

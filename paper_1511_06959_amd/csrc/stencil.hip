@@ -4,7 +4,9 @@
 // Both kernels stage a box of cells (the work-group's output tile, one of the TILE_* shapes, plus
 // a halo of one cell, two in x beside slip walls) in LDS, derive the primitive variables once per
 // box cell, and then evaluate each output cell's 19-point stencil from LDS.  SoA var-major global
-// layout; every global access of a wavefront is to consecutive x addresses.
+// layout; every global access of a wavefront is to consecutive x addresses.  A CONV = 0
+// instantiation leaves the split-form convective terms out, for grids whose convective flux the
+// Roe kernels (roe.hip) add.
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -80,16 +82,19 @@ __device__ __forceinline__ void visc_flux(const T (*sm)[NB], const int st[3], in
   G[3] = work + (T(2) * c.alpha) * (sm[P_E][B] - sm[P_E][A]) * c.idx[D];
 }
 
-template <typename T, int NB, int D>
+// CONV = 0: the viscous terms only (grids whose convective flux another kernel adds).
+template <typename T, int NB, int D, int CONV>
 __device__ __forceinline__ void residual_dir(const T (*sm)[NB], const int st[3], int p, const Consts<T>& c,
                                              T R[5]) {
-  T Fp[5], Fm[5];
-  const T p0 = (c.gamma - T(1)) * c.wref[4];
-  conv_face<T, NB, D>(sm, p, p + st[D], p0, Fp);
-  conv_face<T, NB, D>(sm, p - st[D], p, p0, Fm);
-  const T h = c.idx[D];
+  if constexpr (CONV) {
+    T Fp[5], Fm[5];
+    const T p0 = (c.gamma - T(1)) * c.wref[4];
+    conv_face<T, NB, D>(sm, p, p + st[D], p0, Fp);
+    conv_face<T, NB, D>(sm, p - st[D], p, p0, Fm);
+    const T h = c.idx[D];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) R[v] -= (Fp[v] - Fm[v]) * h;
+    for (int v = 0; v < 5; ++v) R[v] -= (Fp[v] - Fm[v]) * h;
+  }
   T Gp[4], Gm[4];
   visc_flux<T, NB, D>(sm, st, p, c, Gp);
   visc_flux<T, NB, D>(sm, st, p - st[D], c, Gm);
@@ -105,8 +110,9 @@ __device__ __forceinline__ void residual_dir(const T (*sm)[NB], const int st[3],
 //       FIN  out = (W2 + 2 W3 + W - wn)/3 + (dt/6) R(W; s)      (stage 4, W = W4;
 //            equals wn + dt/6 (k1 + 2 k2 + 2 k3 + k4) since k1 = 2(W2-wn)/dt, k2 = 2(W3-wn)/dt,
 //            k3 = (W4-wn)/dt)
+// CONV = 0 leaves out the split-form convective flux (the Roe option adds its own).
 // One work-group: the tile with origin (x0, y0, z0).
-template <typename T, int MODE, int TX, int TY, int TZ>
+template <typename T, int MODE, int CONV, int TX, int TY, int TZ>
 __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x0, const int y0, const int z0,
                                                  const T* __restrict__ W, const T* __restrict__ wn,
                                                  const T* __restrict__ s, const T* __restrict__ W2,
@@ -191,11 +197,11 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
   const int st[3] = {1, Bx::SY, Bx::SZ};
   const int p = (tz + 1) * Bx::SZ + (ty + 1) * Bx::SY + (tx + 1);
   T R[5] = {sv[0], sv[1], sv[2], sv[3], sv[4]};
-  residual_dir<T, NB, 0>(sm, st, p, c, R);
+  residual_dir<T, NB, 0, CONV>(sm, st, p, c, R);
   __builtin_amdgcn_sched_barrier(0);
-  residual_dir<T, NB, 1>(sm, st, p, c, R);
+  residual_dir<T, NB, 1, CONV>(sm, st, p, c, R);
   __builtin_amdgcn_sched_barrier(0);
-  residual_dir<T, NB, 2>(sm, st, p, c, R);
+  residual_dir<T, NB, 2, CONV>(sm, st, p, c, R);
   __builtin_amdgcn_sched_barrier(0);
   if (MODE == STAGE_RES) {
 #pragma unroll
@@ -213,14 +219,14 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
   }
 }
 
-template <typename T, int MODE, int TX, int TY, int TZ>
+template <typename T, int MODE, int CONV, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, const T* __restrict__ W,
                                                                const T* __restrict__ wn, const T* __restrict__ s,
                                                                const T* __restrict__ W2, const T* __restrict__ W3,
                                                                T cR, T* __restrict__ out, T ca, T cb) {
   int x0, y0, z0;
   tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
-  primal_tile_body<T, MODE, TX, TY, TZ>(c, x0, y0, z0, W, wn, s, W2, W3, cR, out, ca, cb);
+  primal_tile_body<T, MODE, CONV, TX, TY, TZ>(c, x0, y0, z0, W, wn, s, W2, W3, cR, out, ca, cb);
 }
 
 // Ensemble form: work-group -> (box, tile) through the tile offsets `start`; every array is
@@ -238,7 +244,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage_batch(const BoxDe
   const long long o = 5 * boxes[b].off;
   int x0, y0, z0;
   tile_origin<TX, TY, TZ>(blk - start[b], c.nx, c.ny, x0, y0, z0);
-  primal_tile_body<T, MODE, TX, TY, TZ>(c, x0, y0, z0, W + o, wn + o, s ? s + o : nullptr,
+  primal_tile_body<T, MODE, 1, TX, TY, TZ>(c, x0, y0, z0, W + o, wn + o, s ? s + o : nullptr,
                                         W2 ? W2 + o : nullptr, W3 ? W3 + o : nullptr, c.dt * cfac, out + o);
 }
 
@@ -476,8 +482,9 @@ __device__ __forceinline__ void prim_to_cons(const T u[3], T e, T ri, const T uh
 // MODE: STAGE_VJP  out = g = J^T kh (+ L_nu kh)
 //       STAGE_FIN  (RK4 stage 1) g1 = J(w_n)^T kh + ...; out = w^_n = a + g1 + gnext + g3 + g4;
 //                  grad_s += dt a + dt g4 + dt/2 (g3 + gnext)   (= k^1 + k^2 + k^3 + k^4)
+// CONV = 0 leaves out the transpose of the split-form convective flux (the Roe option adds its own).
 // One work-group: the tile with origin (x0, y0, z0); the artificial viscosity is nscale * nu.
-template <typename T, int MODE, int WALL, int LNU, int TX, int TY, int TZ>
+template <typename T, int MODE, int WALL, int LNU, int CONV, int TX, int TY, int TZ>
 __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int x0, const int y0, const int z0,
                                                   const T* __restrict__ W, const T* __restrict__ a,
                                                   const T* __restrict__ gnext, const T* __restrict__ nu,
@@ -588,14 +595,18 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
 #pragma unroll
     for (int v = 0; v < 5; ++v) k0[v] = sm[A_K0 + v][p];
     const bool wlo = WALL && gx == 0, whi = WALL && gx == c.nx - 1;
-    T Hh = T(0), Ph = T(0);
-    adj_conv_dir<T, NB, NB, 0>(&sm[A_K0], &sm[A_U1], Q, p, st[0], c, hr0, hu, H0, P0, k0, wlo, whi, rh, uh, Hh, Ph);
-    adj_conv_dir<T, NB, NB, 1>(&sm[A_K0], &sm[A_U1], Q, p, st[1], c, hr0, hu, H0, P0, k0, false, false, rh, uh, Hh, Ph);
-    adj_conv_dir<T, NB, NB, 2>(&sm[A_K0], &sm[A_U1], Q, p, st[2], c, hr0, hu, H0, P0, k0, false, false, rh, uh, Hh, Ph);
-    rh += gm1 * e * Ph;
-    eh += Hh + gm1 * r0 * Ph;
+    if constexpr (CONV) {
+      T Hh = T(0), Ph = T(0);
+      adj_conv_dir<T, NB, NB, 0>(&sm[A_K0], &sm[A_U1], Q, p, st[0], c, hr0, hu, H0, P0, k0, wlo, whi, rh, uh, Hh, Ph);
+      adj_conv_dir<T, NB, NB, 1>(&sm[A_K0], &sm[A_U1], Q, p, st[1], c, hr0, hu, H0, P0, k0, false, false, rh, uh, Hh,
+                                 Ph);
+      adj_conv_dir<T, NB, NB, 2>(&sm[A_K0], &sm[A_U1], Q, p, st[2], c, hr0, hu, H0, P0, k0, false, false, rh, uh, Hh,
+                                 Ph);
+      rh += gm1 * e * Ph;
+      eh += Hh + gm1 * r0 * Ph;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) uh[k] += Hh * uc[k];
+      for (int k = 0; k < 3; ++k) uh[k] += Hh * uc[k];
+    }
   }
   __syncthreads();
   face_records<T, TX, TY, TZ, HX, 0, NB, NF, NQF>(sm, fr, fq, st, c);
@@ -656,7 +667,7 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
   }
 }
 
-template <typename T, int MODE, int WALL, int LNU, int TX, int TY, int TZ>
+template <typename T, int MODE, int WALL, int LNU, int CONV, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, const T* __restrict__ W,
                                                                 const T* __restrict__ a, const T* __restrict__ gnext,
                                                                 const T* __restrict__ nu, T ca, T cg,
@@ -664,8 +675,8 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
                                                                 T* __restrict__ out, T* __restrict__ grad_s) {
   int x0, y0, z0;
   tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
-  adjoint_tile_body<T, MODE, WALL, LNU, TX, TY, TZ>(c, x0, y0, z0, W, a, gnext, nu, T(1), ca, cg, g3, g4, out,
-                                                    grad_s);
+  adjoint_tile_body<T, MODE, WALL, LNU, CONV, TX, TY, TZ>(c, x0, y0, z0, W, a, gnext, nu, T(1), ca, cg, g3, g4, out,
+                                                          grad_s);
 }
 
 // Ensemble form over the members: state arrays (W, the sigma_1 field) at the member's box,
@@ -682,7 +693,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage_batch(
   const long long o = 5 * mems[m].off, ao = 5 * mems[m].aoff;
   int x0, y0, z0;
   tile_origin<TX, TY, TZ>(blk - start[m], c.nx, c.ny, x0, y0, z0);
-  adjoint_tile_body<T, MODE, WALL, LNU, TX, TY, TZ>(
+  adjoint_tile_body<T, MODE, WALL, LNU, 1, TX, TY, TZ>(
       c, x0, y0, z0, W + o, a + ao, gnext ? gnext + ao : nullptr, LNU ? sigma1 + mems[m].off : nullptr,
       mems[m].lam, c.dt / da, c.dt * mg, g3 ? g3 + ao : nullptr, g4 ? g4 + ao : nullptr, out + ao,
       grad_s ? grad_s + ao : nullptr);
@@ -750,54 +761,74 @@ constexpr bool adjoint_fits() {
   return adjoint_lds_bytes<T, WALL, LNU, S::tx, S::ty, S::tz>() <= 160 * 1024;
 }
 
+template <typename T, int CONV, int TX, int TY, int TZ>
+static void primal_launch(ProfScope& ps, int mode, const Consts<T>& c, const T* W, const T* wn, const T* s,
+                          const T* W2, const T* W3, T cR, T* out, hipStream_t st, T ca, T cb) {
+  const dim3 grid = tile_grid<TX, TY, TZ>(c.nx, c.ny, c.nz), blk(TX * TY * TZ);
+  if (mode == STAGE_RES)
+    timed_launch(ps, k_primal_stage<T, STAGE_RES, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
+                 cb);
+  else if (mode == STAGE_LIN)
+    timed_launch(ps, k_primal_stage<T, STAGE_LIN, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
+                 cb);
+  else if (mode == STAGE_AFF)
+    timed_launch(ps, k_primal_stage<T, STAGE_AFF, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
+                 cb);
+  else
+    timed_launch(ps, k_primal_stage<T, STAGE_FIN, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
+                 cb);
+}
+
 template <typename T>
 hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
-                               const T* W3, T cR, T* out, hipStream_t st, T ca, T cb) {
+                               const T* W3, T cR, T* out, hipStream_t st, T ca, T cb, int conv) {
   ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st, true);
   with_tile(tile_choice(ADJ_PROF_PRIMAL_STAGE, sizeof(T) == 8), [&](auto S) {
     using Sh = decltype(S);
-    const dim3 grid = tile_grid<Sh::tx, Sh::ty, Sh::tz>(c.nx, c.ny, c.nz), blk(Sh::tx * Sh::ty * Sh::tz);
-    if (mode == STAGE_RES)
-      timed_launch(ps, k_primal_stage<T, STAGE_RES, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out,
-                   ca, cb);
-    else if (mode == STAGE_LIN)
-      timed_launch(ps, k_primal_stage<T, STAGE_LIN, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out,
-                   ca, cb);
-    else if (mode == STAGE_AFF)
-      timed_launch(ps, k_primal_stage<T, STAGE_AFF, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out,
-                   ca, cb);
+    if (conv)
+      primal_launch<T, 1, Sh::tx, Sh::ty, Sh::tz>(ps, mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb);
     else
-      timed_launch(ps, k_primal_stage<T, STAGE_FIN, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, c, W, wn, s, W2, W3, cR, out,
-                   ca, cb);
+      primal_launch<T, 0, Sh::tx, Sh::ty, Sh::tz>(ps, mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb);
   });
   return hipGetLastError();
 }
 
-template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
-static void adjoint_launch(ProfScope& ps, int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext,
-                           const T* nu, T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
+template <typename T, int WALL, int LNU, int CONV, int TX, int TY, int TZ>
+static void adjoint_launch_conv(ProfScope& ps, int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext,
+                                const T* nu, T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s,
+                                hipStream_t st) {
   const dim3 grid = tile_grid<TX, TY, TZ>(c.nx, c.ny, c.nz), blk(TX * TY * TZ);
   if (mode == STAGE_VJP)
-    timed_launch(ps, k_adjoint_stage<T, STAGE_VJP, WALL, LNU, TX, TY, TZ>, grid, blk, st, c, W, a, gnext, nu, ca, cg,
-                 g3, g4, out, grad_s);
+    timed_launch(ps, k_adjoint_stage<T, STAGE_VJP, WALL, LNU, CONV, TX, TY, TZ>, grid, blk, st, c, W, a, gnext, nu, ca,
+                 cg, g3, g4, out, grad_s);
   else
-    timed_launch(ps, k_adjoint_stage<T, STAGE_FIN, WALL, LNU, TX, TY, TZ>, grid, blk, st, c, W, a, gnext, nu, ca, cg,
-                 g3, g4, out, grad_s);
+    timed_launch(ps, k_adjoint_stage<T, STAGE_FIN, WALL, LNU, CONV, TX, TY, TZ>, grid, blk, st, c, W, a, gnext, nu, ca,
+                 cg, g3, g4, out, grad_s);
+}
+
+template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
+static void adjoint_launch(ProfScope& ps, int mode, int conv, const Consts<T>& c, const T* W, const T* a,
+                           const T* gnext, const T* nu, T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s,
+                           hipStream_t st) {
+  if (conv)
+    adjoint_launch_conv<T, WALL, LNU, 1, TX, TY, TZ>(ps, mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
+  else
+    adjoint_launch_conv<T, WALL, LNU, 0, TX, TY, TZ>(ps, mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
 }
 
 template <typename T>
 hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,
-                                T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
+                                T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st, int conv) {
   ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st, true);
   with_variant(c.wall, nu != nullptr, [&](auto WL, auto LN) {
     constexpr int WALL = decltype(WL)::value, LNU = decltype(LN)::value;
     with_tile(tile_choice(ADJ_PROF_ADJOINT_STAGE, sizeof(T) == 8), [&](auto S) {
       using Sh = decltype(S);
       if constexpr (adjoint_fits<T, WALL, LNU, Sh>())
-        adjoint_launch<T, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>(ps, mode, c, W, a, gnext, nu, ca, cg, g3, g4, out,
+        adjoint_launch<T, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>(ps, mode, conv, c, W, a, gnext, nu, ca, cg, g3, g4, out,
                                                              grad_s, st);
       else
-        adjoint_launch<T, WALL, LNU, 16, 4, 4>(ps, mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
+        adjoint_launch<T, WALL, LNU, 16, 4, 4>(ps, mode, conv, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
     });
   });
   return hipGetLastError();
@@ -882,15 +913,16 @@ ADJNS_BATCH_INST(double)
 #undef ADJNS_BATCH_INST
 
 template hipError_t launch_primal_stage<float>(int, const Consts<float>&, const float*, const float*, const float*,
-                                               const float*, const float*, float, float*, hipStream_t, float, float);
+                                               const float*, const float*, float, float*, hipStream_t, float, float,
+                                               int);
 template hipError_t launch_primal_stage<double>(int, const Consts<double>&, const double*, const double*, const double*,
                                                 const double*, const double*, double, double*, hipStream_t, double,
-                                                double);
+                                                double, int);
 template hipError_t launch_adjoint_stage<float>(int, const Consts<float>&, const float*, const float*, const float*,
                                                 const float*, float, float, const float*, const float*, float*,
-                                                float*, hipStream_t);
+                                                float*, hipStream_t, int);
 template hipError_t launch_adjoint_stage<double>(int, const Consts<double>&, const double*, const double*,
                                                  const double*, const double*, double, double, const double*,
-                                                 const double*, double*, double*, hipStream_t);
+                                                 const double*, double*, double*, hipStream_t, int);
 
 }  // namespace adjns

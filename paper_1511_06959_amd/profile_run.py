@@ -5,7 +5,7 @@
         reverse steps (adjoint_step / adjoint_step_stages) on an n^3 Taylor-Green state, Mach 0.1,
         lambda 0: the reverse-stage kernel as the benchmark launches it (with --tune, in the tile
         shapes of the tuning cache that a preceding bench.py run filled; with --flux roe, followed
-        by the Roe correction kernels)
+        by the Roe flux kernels)
     python -m paper_1511_06959_amd.profile_run copy --mib 1024 --reps 5
         torch's device-to-device copy of a buffer of known size, the calibration of the byte
         counters (it reads and writes exactly mib MiB per launch)
@@ -254,7 +254,7 @@ def main():
     a.add_argument("--stages", action="store_true")
     a.add_argument("--tune", action="store_true", help="install the autotuned tiles (tuning cache) first")
     a.add_argument("--flux", choices=("split", "roe"), default="split",
-                   help="roe: the Roe flux option (its correction kernels run after each stage kernel)")
+                   help="roe: the Roe flux option (its kernels run after each stage kernel)")
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=1024)
     c.add_argument("--reps", type=int, default=5)
