@@ -10,9 +10,10 @@
  * largest singular value of the adjoint-energy growth matrix M = M1 - M2 ("Stabilizing adjoint
  * equations": Energy Analysis, last equation).
  *
- * Discretisation (identical in every entry point):
+ * Discretisation (identical in every entry point; the defaults below, the options of adj_grid
+ * flux, time_scheme and bc_x replace the flux, the time marching or the x boundaries):
  *   - uniform Cartesian cells, n[d] cells over length L[d], dx_d = L[d]/n[d]; periodic in y, z;
- *     x periodic or slip walls (mirror ghost cell, x-momentum odd);
+ *     x periodic, slip walls (mirror ghost cell, x-momentum odd) or characteristic inlet/outlet;
  *   - residual R(w; s) = -sum_d (F~_{d,+} - F~_{d,-})/dx_d + s, with the convective face flux
  *     r v_d (1, v, H) + P (0, e_d, v_d) built from the face means r, v, H, P of rho, u, E/rho
  *     and p (the kinetic-energy-preserving split form of Kennedy & Gruber, JCP 227, 2008: the
@@ -21,7 +22,9 @@
  *     (0, sigma_d., u_f . sigma_d. + alpha d_d e): normal face
  *     gradients (phi_R - phi_L)/dx_d, tangential ones the mean of the two cells' central
  *     differences; sigma = mu (grad u + grad u^T) - (2/3) mu (div u) I; alpha = gamma mu / Pr;
- *   - classical RK4 with fixed dt.
+ *   - classical RK4 with fixed dt (or the paper's SSP-RK3);
+ *   - options: the paper's Roe upwind flux on reconstructed face states (adj_grid.flux) and its
+ *     characteristic inlet and outlet (adj_grid.bc_x, w_far).
  *
  * Size limit: a state array (5 N values) must span less than 4 GiB (N < 2^28 / 1.25 cells in FP32,
  * half that in FP64); larger grids are rejected with ADJ_ESHAPE.
