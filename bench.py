@@ -101,7 +101,8 @@ def _tile_report(res, g, lnu):
     return out
 
 
-def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=False, time_scheme=0, flux=0):
+def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=False, time_scheme=0, flux=0,
+            nu_weight=None):
     import torch
 
     import paper_1511_06959_amd as adj
@@ -112,7 +113,7 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     w_ref = adj.reference_state(wl.w0) if precision == adj.F32 else None
     g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision,
                       adj.CKPT_BF16 if ckpt_bf16 else adj.CKPT_NATIVE, w_ref, time_scheme=time_scheme, flux=flux,
-                      roe_delta=ROE_DELTA, w_far=wl.extra.get("w_far"))
+                      roe_delta=ROE_DELTA, w_far=wl.extra.get("w_far"), nu_weight=nu_weight)
     tiles = {}
     if tune:
         tiles = _tile_report(autotune.tune(g), g, wl.lam > 0.0)
@@ -391,9 +392,12 @@ def main():
                     help="time marching: classical RK4, or the strong-stability-preserving RK3 of the paper")
     ap.add_argument("--flux", default="split", choices=("split", "roe"),
                     help="convective flux: split central form, or the paper's Roe upwind flux")
+    ap.add_argument("--nu-weight", default=None,
+                    help="artificial-viscosity weights of the variable groups rho, rho u, rho E (e.g. 0.3,1,2.5)")
     args = ap.parse_args()
     args.ts = 1 if args.time_scheme == "ssprk3" else 0
     args.fl = 1 if args.flux == "roe" else 0
+    args.nw = tuple(float(x) for x in args.nu_weight.split(",")) if args.nu_weight else None
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
               "design note, not part of this build)", file=sys.stderr)
@@ -421,16 +425,17 @@ def main():
           file=sys.stderr, flush=True)
     # the large configurations keep BF16 checkpoint records on the FP32 path
     r32 = run_gpu(wl, adj.F32, args.steps, args.warmup, not args.no_autotune, stages=stages, ckpt_bf16=big,
-                  time_scheme=args.ts, flux=args.fl)
+                  time_scheme=args.ts, flux=args.fl, nu_weight=args.nw)
     print(f"[bench] f32 window {r32['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
     r32b = None
     if stages:
-        r32b = run_gpu(wl, adj.F32, args.steps, args.warmup, False, stages=False, time_scheme=args.ts, flux=args.fl)
+        r32b = run_gpu(wl, adj.F32, args.steps, args.warmup, False, stages=False, time_scheme=args.ts, flux=args.fl,
+                       nu_weight=args.nw)
         print(f"[bench] f32 window, recompute schedule {r32b['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_f64:
         r64 = run_gpu(wl, adj.F64, args.steps, args.warmup, not args.no_autotune, stages=stages,
-                      time_scheme=args.ts, flux=args.fl)
+                      time_scheme=args.ts, flux=args.fl, nu_weight=args.nw)
         print(f"[bench] f64 window {r64['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
 
     def rel(a, b):
@@ -496,6 +501,7 @@ def main():
             "time_scheme": args.time_scheme,
             "flux": ("Roe upwind flux (linear reconstruction, |lam| smoothed within %g c~)" % ROE_DELTA
                      if args.fl else "split central form (Kennedy-Gruber)"),
+            "nu_weight": list(args.nw) if args.nw else "one artificial viscosity for every variable",
             "cells": wl.ncells,
             "window_steps": wl.nsteps,
             "dt": wl.dt,
