@@ -78,11 +78,12 @@ def valu_roofline(valu, cells, avg_us):
             "fp32_ops_per_launch": flops, "valu_insts_per_launch": insts}
 
 
-def kernel_hash(source="stencil.hip"):
-    """sha256 of a kernel family's sources (stencil.hip: the stage kernels, roe.hip: the Roe
-    flux kernels), as the committed counter summaries record it."""
+def kernel_hash(family="stage"):
+    """sha256 of a kernel family's sources ("stage": the stage kernels, "roe": the Roe flux
+    kernels), as the committed counter summaries record it."""
+    from paper_1511_06959_amd.profile_run import SOURCES
     h = hashlib.sha256()
-    for name in (source, "common.hpp"):
+    for name in SOURCES[family]:
         h.update(open(os.path.join(ROOT, "paper_1511_06959_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
@@ -462,7 +463,7 @@ def main():
     if "roe" in r32:
         # with the Roe flux the transpose of its flux terms takes the largest share of the window
         rk = r32["roe"]["roe_adjoint"]
-        rhash = kernel_hash("roe.hip")
+        rhash = kernel_hash("roe")
         rtraffic = profile_values("traffic_roe_adjoint_tgv64.txt", rhash, "")
         rvalu = profile_values("valu_roe_adjoint_tgv64.txt", rhash, "")
         if big:

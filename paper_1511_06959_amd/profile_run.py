@@ -169,13 +169,16 @@ def _tiles(names):
     return ",".join(sorted(out))
 
 
+SOURCES = {"stage": ("stencil.hip", "common.hpp"), "roe": ("roe.hip", "roe_flux.hpp", "common.hpp")}
+
+
 def _src_hash(kernel="k_adjoint_stage"):
-    """sha256 of the sources of a kernel family: the Roe kernels (k_roe_*) live in roe.hip, the
-    stage kernels in stencil.hip; both include common.hpp."""
+    """sha256 of the sources of a kernel family: the Roe kernels (k_roe_*) are roe.hip with the
+    flux core roe_flux.hpp, the stage kernels stencil.hip; all include common.hpp."""
     import hashlib
     h = hashlib.sha256()
     here = os.path.dirname(os.path.abspath(__file__))
-    for name in (("roe.hip" if kernel.startswith("k_roe") else "stencil.hip"), "common.hpp"):
+    for name in SOURCES["roe" if kernel.startswith("k_roe") else "stage"]:
         h.update(open(os.path.join(here, "csrc", name), "rb").read())
     return h.hexdigest()
 
