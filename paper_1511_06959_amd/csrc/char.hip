@@ -8,16 +8,16 @@ namespace adjns {
 namespace {
 using namespace roeflux;
 
-// ------------------------------------------------------------------------ open boundaries in x
-// Characteristic inflow/outflow boundaries (bc_x = ADJ_BC_CHARACTERISTIC).  The stage kernels
-// treat them as slip walls (mirror ghosts), so through each boundary face they evaluate the
-// mirror-pair flux H_w = (0, p - p0 - s_xx, 0, 0, 0), or (0, -s_xx, 0, 0, 0) when they run
-// without the split-form convective flux (Roe grids, whose Roe kernels skip the boundary faces):
-// the mirror pair carries no mass, energy, tangential stress or heat, and
-// s_xx = (4/3) mu g_n - (2/3) mu (d_y u_y + d_z u_z) with the normal gradient g_n = +-2 u_x/dx of
-// the pair and the boundary cell's central tangential divergence.  The kernels here replace H_w by the characteristic flux F_c, Roe's flux between the
-// far-field state and the boundary cell (x = 0) or the boundary cell and the far-field state
-// (x = L_x), which takes the entering waves from the far field and the leaving ones from inside:
+// The stage kernels treat the open boundaries as slip walls (mirror ghosts), so through each
+// boundary face they evaluate the mirror-pair flux H_w = (0, p - p0 - s_xx, 0, 0, 0), or
+// (0, -s_xx, 0, 0, 0) when they run without the split-form convective flux (Roe grids, whose Roe
+// kernels skip the boundary faces): the mirror pair carries no mass, energy, tangential stress or
+// heat, and s_xx = (4/3) mu g_n - (2/3) mu (d_y u_y + d_z u_z) with the normal gradient
+// g_n = +-2 u_x/dx of the pair and the boundary cell's central tangential divergence.  The
+// kernels here replace H_w by the characteristic flux F_c, Roe's flux between the far-field state
+// and the boundary cell (x = 0) or the boundary cell and the far-field state (x = L_x), which
+// takes the entering waves from the far field and the leaving ones from inside
+// [Numerical methods; Boundary conditions of the adjoint]:
 //   char_primal:  out += coef * (+-)(F_c - H_w)/dx at the boundary cells (+ at x = 0)
 //   char_adjoint: out += (its Jacobian)^T kh, gathered per boundary cell (s_xx also reaches the
 //                 y and z neighbours of a boundary cell through the tangential divergence)
