@@ -20,7 +20,8 @@
 //
 // Both kernels treat one direction at a time: the tile's cells plus a halo along that direction
 // only (2 cells forward, 3 in reverse) are staged in LDS, every face of the direction that the
-// tile needs is evaluated once into LDS, and each cell then gathers from its faces.  Slip walls:
+// tile needs is evaluated once into LDS (in reverse: the adjoints of its two face states), and
+// each cell then gathers from its faces.  Slip walls:
 // ghost cells hold mirrored states and kh = 0; faces between two ghosts do not exist; a wall
 // cell adds the shares its ghost images receive, mapped back through the mirror (rho u_x odd).
 #include "kernels.hpp"
@@ -131,7 +132,7 @@ __device__ __forceinline__ void primal_dir(const Consts<T>& c, const RoeC<T>& k,
   for (int f = threadIdx.x; f < F::N; f += RNT) {
     int p, x, y, z;
     F::coords(f, p, x, y, z);
-    T w[4][5], o[4][5] = {};
+    T w[4][5], o[1][5] = {};
     T ql = T(0.25), qr = T(0.25);
     bool live = true;
     if (D == 0 && k.open) {
@@ -180,12 +181,25 @@ __global__ __launch_bounds__(RNT) void k_roe_primal(Consts<T> c, RoeC<T> k, cons
 // ---------------------------------------------------------------------------------- reverse
 constexpr int NSA = Max3c<Ext<0, 3>::N, Ext<1, 3>::N, Ext<2, 3>::N>::v;
 constexpr int NFA = Max3c<Faces<0, RX + 3>::N, Faces<1, RY + 3>::N, Faces<2, RZ + 3>::N>::v;
-constexpr int NLA = 10 * NSA > 20 * NFA ? 10 * NSA : 20 * NFA;
+constexpr int NLA = 10 * NSA > 10 * NFA ? 10 * NSA : 10 * NFA;
 
-// Shares that the direction-D faces hand to the cell at tile position t along D (cross
-// coordinates x, y, z): face p (lower cell p - 2) gives share 3 - (p - t) for p = t .. t + 3.
+// Reconstruction weights (ql, qr) of the direction-D face with lower cell gl (global index along
+// D): 1/4, or 0 where the reconstruction would reach beyond an open boundary.
 template <typename T, int D>
-__device__ __forceinline__ void gather(const T* fr, int t, int x, int y, int z, T sgn1, T acc[5]) {
+__device__ __forceinline__ void face_q(const Consts<T>& c, const RoeC<T>& k, int gl, T& ql, T& qr) {
+  ql = qr = T(0.25);
+  if (D == 0 && k.open) {
+    ql = gl >= 1 ? T(0.25) : T(0);
+    qr = gl + 2 <= c.nx - 1 ? T(0.25) : T(0);
+  }
+}
+
+// Adjoint shares gathered by the cell at tile position t along D (cross coordinates x, y, z)
+// from the records (w_l^, w_r^) of the faces p = t .. t + 3 (lower cells t - 2 .. t + 1):
+// -qr w_r^ (p = t), ql w_l^ + w_r^ (p = t + 1), w_l^ + qr w_r^ (p = t + 2), -ql w_l^ (p = t + 3).
+template <typename T, int D>
+__device__ __forceinline__ void gather(const Consts<T>& c, const RoeC<T>& k, const T* fr, int x0, int t, int x, int y,
+                                       int z, T sgn1, T acc[5]) {
   constexpr int TD = D == 0 ? RX : (D == 1 ? RY : RZ);
   using F = Faces<D, TD + 3>;
 #pragma unroll
@@ -193,9 +207,17 @@ __device__ __forceinline__ void gather(const T* fr, int t, int x, int y, int z, 
     const int p = t + q;
     if (p < 0 || p >= TD + 3) continue;
     const int f = F::at(p, x, y, z);
-    const int j = 3 - q;
+    T ql, qr;
+    face_q<T, D>(c, k, x0 + p - 2, ql, qr);
+    const T cl = q == 3 ? -ql : (q == 2 ? T(1) : (q == 1 ? ql : T(0)));
+    const T cr = q == 0 ? -qr : (q == 1 ? T(1) : (q == 2 ? qr : T(0)));
 #pragma unroll
-    for (int v = 0; v < 5; ++v) acc[v] += (v == 1 ? sgn1 : T(1)) * fr[(j * 5 + v) * NFA + f];
+    for (int v = 0; v < 5; ++v) {
+      T sh = T(0);
+      if (q >= 1) sh += cl * fr[v * NFA + f];
+      if (q <= 2) sh += cr * fr[(5 + v) * NFA + f];
+      acc[v] += (v == 1 ? sgn1 : T(1)) * sh;
+    }
   }
 }
 
@@ -211,23 +233,20 @@ __device__ __forceinline__ void adjoint_dir(const Consts<T>& c, const RoeC<T>& k
   stage<T, D, 3, true>(c, x0, y0, z0, rW, ra, rg, has_g, ca, cg, lds, NSA);
   __syncthreads();
   // face p lies between tile cells p - 3 and p - 2 (lower cell p - 2); stencil: extended p .. p + 3
-  T rec[NPT][4][5];
+  T rec[NPT][2][5];
 #pragma unroll
   for (int i = 0; i < NPT; ++i) {
     const int f = threadIdx.x + i * RNT;
     bool live = f < F::N;
     int p = 0, x = 0, y = 0, z = 0;
     if (live) F::coords(f, p, x, y, z);
-    T ql = T(0.25), qr = T(0.25);
+    T ql, qr;
+    face_q<T, D>(c, k, x0 + p - 2, ql, qr);
     if (live && D == 0 && c.wall) {
       const int gl = x0 + p - 2;
-      if (k.open) {  // as in the forward kernel
-        live = gl >= 0 && gl <= c.nx - 2;
-        ql = gl >= 1 ? T(0.25) : T(0);
-        qr = gl + 2 <= c.nx - 1 ? T(0.25) : T(0);
-      } else {  // slip walls: a face needs a real cell on at least one side
-        live = gl >= -1 && gl <= c.nx - 1;
-      }
+      // open boundaries: the boundary faces carry the characteristic flux (boundary kernels);
+      // slip walls: a face needs a real cell on at least one side
+      live = k.open ? (gl >= 0 && gl <= c.nx - 2) : (gl >= -1 && gl <= c.nx - 1);
     }
     if (live) {
       const int e0 = E::at(p, x, y, z);
@@ -238,7 +257,7 @@ __device__ __forceinline__ void adjoint_dir(const Consts<T>& c, const RoeC<T>& k
       roe_face<T, D, true>(w[0], w[1], w[2], w[3], k, ql, qr, G, rec[i]);
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 5; ++v) rec[i][j][v] = T(0);
     }
@@ -249,7 +268,7 @@ __device__ __forceinline__ void adjoint_dir(const Consts<T>& c, const RoeC<T>& k
     const int f = threadIdx.x + i * RNT;
     if (f < F::N) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 5; ++v) lds[(j * 5 + v) * NFA + f] = rec[i][j][v];
     }
@@ -257,19 +276,19 @@ __device__ __forceinline__ void adjoint_dir(const Consts<T>& c, const RoeC<T>& k
   __syncthreads();
   if (active) {
     const int t = D == 0 ? tx : (D == 1 ? ty : tz);
-    gather<T, D>(lds, t, tx, ty, tz, T(1), acc);
+    gather<T, D>(c, k, lds, x0, t, tx, ty, tz, T(1), acc);
     if (D == 0 && c.wall) {
       // shares of the ghost images of this cell (x <= 1: left wall, x >= nx - 2: right wall)
       const int gx = x0 + tx;
-      if (gx <= 1) gather<T, D>(lds, -1 - gx - x0, tx, ty, tz, T(-1), acc);
-      if (gx >= c.nx - 2) gather<T, D>(lds, 2 * c.nx - 1 - gx - x0, tx, ty, tz, T(-1), acc);
+      if (gx <= 1) gather<T, D>(c, k, lds, x0, -1 - gx - x0, tx, ty, tz, T(-1), acc);
+      if (gx >= c.nx - 2) gather<T, D>(c, k, lds, x0, 2 * c.nx - 1 - gx - x0, tx, ty, tz, T(-1), acc);
     }
   }
   __syncthreads();
 }
 
 // FP32: at most 128 registers, so that four work-groups (16 wavefronts) share a compute unit and
-// a 64^3 grid (1024 work-groups) runs in one round; FP64 holds two (LDS and registers).
+// a 64^3 grid (1024 work-groups) runs in one round; FP64 holds two (registers).
 template <typename T>
 __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 void k_roe_adjoint(Consts<T> c, RoeC<T> k, const T* __restrict__ W,

@@ -224,10 +224,11 @@ __device__ __forceinline__ void roe_flux2(const T wl[5], const T wr[5], const Ro
 // Roe's flux through the direction-D face between cells b and c; a and e are the next cells
 // outward, the face states w_l = b + ql (c - a), w_r = c - qr (e - b) with ql, qr = 1/4 (0 where
 // the reconstruction would reach beyond an open boundary).  REV = false: out[0] = F.  REV = true:
-// out[j] = d(G . F)/d(cell j) for the cells (a, b, c, e).
+// out[0], out[1] = d(G . F)/d(w_l), d(G . F)/d(w_r); the cells (a, b, c, e) then receive
+// (-ql out[0], out[0] + qr out[1], ql out[0] + out[1], -qr out[1]).
 template <typename T, int D, bool REV>
 __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5], const T e[5], const RoeC<T>& k,
-                                         T ql, T qr, const T G[5], T out[4][5]) {
+                                         T ql, T qr, const T G[5], T out[][5]) {
   T wl[5], wr[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
@@ -237,15 +238,9 @@ __device__ __forceinline__ void roe_face(const T a[5], const T b[5], const T c[5
   if constexpr (!REV) {
     roe_flux2<T, D, false>(wl, wr, k, G, out[0], nullptr, nullptr);
   } else {
-    T wlb[5] = {T(0), T(0), T(0), T(0), T(0)}, wrb[5] = {T(0), T(0), T(0), T(0), T(0)};
-    roe_flux2<T, D, true>(wl, wr, k, G, nullptr, wlb, wrb);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      out[0][q] = -ql * wlb[q];
-      out[1][q] = wlb[q] + qr * wrb[q];
-      out[2][q] = ql * wlb[q] + wrb[q];
-      out[3][q] = -qr * wrb[q];
-    }
+    for (int q = 0; q < 5; ++q) out[0][q] = out[1][q] = T(0);
+    roe_flux2<T, D, true>(wl, wr, k, G, nullptr, out[0], out[1]);
   }
 }
 
