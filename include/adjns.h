@@ -272,15 +272,19 @@ int adj_tile_launched(int kernel_class, int precision, int bc_x, int lnu, int ti
  *   out[2] = dt lambda max_g w_g max_cells sigma_1 sum_d 4/dx_d^2       artificial viscosity
  * (w_g: grid->nu_weight).  The central scheme's convective eigenvalues lie on the imaginary axis
  * and its diffusive ones on the negative real axis; classical RK4 is stable there for |z| up to
- * ADJ_RK4_IMAG_BOUND and ADJ_RK4_REAL_BOUND.  Each number bounds its part of the spectrum alone
- * (a necessary condition)  [Numerical methods: explicit Runge-Kutta time marching].  Uses the
- * workspace; asynchronous. */
+ * ADJ_RK4_IMAG_BOUND and ADJ_RK4_REAL_BOUND, SSP-RK3 (amplification 1 + z + z^2/2 + z^3/6) up to
+ * ADJ_SSPRK3_IMAG_BOUND (sqrt 3) and ADJ_SSPRK3_REAL_BOUND.  Each number bounds its part of the
+ * spectrum alone (a necessary condition; the Roe flux's dissipation moves its convective
+ * eigenvalues into the left half-plane)  [Numerical methods: explicit Runge-Kutta time marching].
+ * Uses the workspace; asynchronous. */
 #define ADJ_RK4_IMAG_BOUND 2.8284
 #define ADJ_RK4_REAL_BOUND 2.7853
+#define ADJ_SSPRK3_IMAG_BOUND 1.7320
+#define ADJ_SSPRK3_REAL_BOUND 2.5127
 int adj_stability(const adj_grid* grid, const void* w, double lambda, double* out, void* ws, size_t ws_bytes,
                   void* stream);
-/* adj_stability, then waits for the stream: ADJ_EUNSTABLE when a number exceeds its bound,
- * ADJ_OK otherwise; out_host (NULL or host FP64[3]) receives the numbers. */
+/* adj_stability, then waits for the stream: ADJ_EUNSTABLE when a number exceeds the bound of the
+ * grid's time scheme, ADJ_OK otherwise; out_host (NULL or host FP64[3]) receives the numbers. */
 int adj_check_stable(const adj_grid* grid, const void* w, double lambda, double* out_host, void* ws,
                      size_t ws_bytes, void* stream);
 /* Waits for the stream, then ADJ_ENONFINITE when a reduction on the current device (J, E_v^, inner

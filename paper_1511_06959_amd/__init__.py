@@ -307,11 +307,17 @@ def energy_vhat(g, w, wh, E, ws):
 
 
 RK4_IMAG_BOUND, RK4_REAL_BOUND = 2.8284, 2.7853
+SSPRK3_IMAG_BOUND, SSPRK3_REAL_BOUND = 1.7320, 2.5127
+
+
+def stability_bounds(g):
+    """(imaginary-axis, real-axis) stability bounds of the grid's time scheme."""
+    return (SSPRK3_IMAG_BOUND, SSPRK3_REAL_BOUND) if g.time_scheme == SSPRK3 else (RK4_IMAG_BOUND, RK4_REAL_BOUND)
 
 
 def stability(g, w, out, ws, lam=0.0):
     """Explicit-stability numbers (convective, viscous, artificial viscosity) of a step from w
-    into out (device FP64[3]); bounds RK4_IMAG_BOUND, RK4_REAL_BOUND, RK4_REAL_BOUND."""
+    into out (device FP64[3]); bounds (imaginary, real, real) of stability_bounds(g)."""
     wp, wb = _ws(ws)
     _check(lib().adj_stability(ctypes.byref(g), _state(g, w), float(lam), _ptr(out, torch.float64), wp, wb,
                                _stream()))

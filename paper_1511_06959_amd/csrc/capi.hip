@@ -505,11 +505,14 @@ int adj_check_stable(const adj_grid* grid, const void* w, double lambda, double*
       (e = hipStreamSynchronize((hipStream_t)stream)))
     return hip_fail(e, "stability read-back");
   if (out_host) std::memcpy(out_host, h, sizeof h);
-  const double bound[3] = {ADJ_RK4_IMAG_BOUND, ADJ_RK4_REAL_BOUND, ADJ_RK4_REAL_BOUND};
+  const bool rk3 = grid->time_scheme == ADJ_SSPRK3;
+  const double im = rk3 ? ADJ_SSPRK3_IMAG_BOUND : ADJ_RK4_IMAG_BOUND, re = rk3 ? ADJ_SSPRK3_REAL_BOUND : ADJ_RK4_REAL_BOUND;
+  const double bound[3] = {im, re, re};
   const char* what[3] = {"convective", "viscous", "artificial-viscosity"};
   for (int k = 0; k < 3; ++k)
     if (!(h[k] <= bound[k]))
-      return fail(ADJ_EUNSTABLE, "%s stability number %.4g exceeds the RK4 bound %.4g", what[k], h[k], bound[k]);
+      return fail(ADJ_EUNSTABLE, "%s stability number %.4g exceeds the %s bound %.4g", what[k], h[k],
+                  rk3 ? "SSP-RK3" : "RK4", bound[k]);
   return ADJ_OK;
 }
 

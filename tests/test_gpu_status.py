@@ -13,9 +13,9 @@ from tests.gpu_helpers import dev, host, smooth_state
 pytestmark = pytest.mark.gpu
 
 
-def _case(orc, precision=adj.F64, weights=(0.5, 2.0, 1.0), bc_x=0, dt=0.004):
+def _case(orc, precision=adj.F64, weights=(0.5, 2.0, 1.0), bc_x=0, dt=0.004, scheme=adj.RK4):
     shape, L = (19, 6, 9), (2.0, 1.3, 1.7)
-    g = adj.Grid.make(shape, L, 0.02, dt, bc_x=bc_x, precision=precision, nu_weight=weights)
+    g = adj.Grid.make(shape, L, 0.02, dt, bc_x=bc_x, precision=precision, nu_weight=weights, time_scheme=scheme)
     og = orc.make_grid(shape, L, 1.4, 0.72, 0.02, dt, bc_x)
     return g, og, smooth_state(shape, L, seed=40)
 
@@ -56,16 +56,22 @@ def test_stability_numbers(orc, precision, bc_x):
     assert host(out)[2] == 0.0
 
 
-def test_check_stable_bounds(orc):
-    g, og, w = _case(orc)
+@pytest.mark.parametrize("scheme", [adj.RK4, adj.SSPRK3], ids=["rk4", "ssprk3"])
+def test_check_stable_bounds(orc, scheme):
+    g, og, w = _case(orc, scheme=scheme)
+    im, re = adj.stability_bounds(g)
     ws = adj.workspace(g)
     nums = adj.check_stable(g, dev(w), ws, lam=1e-3)
-    assert max(nums[0] / adj.RK4_IMAG_BOUND, nums[1] / adj.RK4_REAL_BOUND, nums[2] / adj.RK4_REAL_BOUND) < 1.0
-    big_dt, *_ = _case(orc, dt=g.dt * 1.05 * adj.RK4_IMAG_BOUND / nums[0])
+    assert max(nums[0] / im, nums[1] / re, nums[2] / re) < 1.0
+    big_dt, *_ = _case(orc, dt=g.dt * 1.05 * im / nums[0], scheme=scheme)
     with pytest.raises(adj.AdjError) as e:
         adj.check_stable(big_dt, dev(w), ws)
     assert e.value.code == -3 and "convective" in str(e.value)
-    lam_big = 1e-3 * 1.05 * adj.RK4_REAL_BOUND / nums[2]
+    if scheme == adj.SSPRK3:  # between the SSP-RK3 and the RK4 bound: RK4 would pass it
+        mid_dt, *_ = _case(orc, dt=g.dt * 0.5 * (im + adj.RK4_IMAG_BOUND) / nums[0], scheme=scheme)
+        with pytest.raises(adj.AdjError):
+            adj.check_stable(mid_dt, dev(w), ws)
+    lam_big = 1e-3 * 1.05 * re / nums[2]
     with pytest.raises(adj.AdjError) as e:
         adj.check_stable(g, dev(w), ws, lam=lam_big)
     assert e.value.code == -3 and "artificial" in str(e.value)
