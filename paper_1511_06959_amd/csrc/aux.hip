@@ -24,19 +24,25 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// block_sum for a work-group of NTH threads (a power of two)
+// Sum over a work-group of NTH threads (a multiple of 64, at most 64 wavefronts), valid in thread
+// 0 only: a butterfly within each 64-lane wavefront, then the wavefront sums, in wavefront order,
+// by the same butterfly in wavefront 0.  A fixed order: the result does not depend on timing.  sh
+// holds NTH / 64 values.
 template <int NTH>
 __device__ __forceinline__ double block_sum_n(double v, double* sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
+  static_assert(NTH % 64 == 0 && NTH <= 64 * 64, "block_sum_n: whole wavefronts, at most 64");
+  constexpr int NW = NTH / 64;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 #pragma unroll
-  for (int o = NTH / 2; o > 0; o >>= 1) {
-    __syncthreads();
-    if (t < o) sh[t] += sh[t + o];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (wv == 0) {
+    r = lane < NW ? sh[lane] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
   }
-  __syncthreads();
-  const double r = sh[0];
-  __syncthreads();
   return r;
 }
 
@@ -466,18 +472,33 @@ __device__ __forceinline__ void load_box_u(const Consts<T>& c, const T* __restri
                                            T (*su)[TBox<KX, KY, KZ, HX, HY>::NB]) {
   using B = TBox<KX, KY, KZ, HX, HY>;
   constexpr int NTH = KX * KY * KZ;
+  constexpr int NIT = (B::NB + NTH - 1) / NTH;
   const long long N = c.N;
-  for (int b = threadIdx.x; b < B::NB; b += NTH) {
+  // every load of this thread is issued before any is used (one memory latency, not NIT); the
+  // tail iteration re-reads the last box cell and does not store it
+  T wv[NIT][4];
+  int mir[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int b = min((int)threadIdx.x + it * NTH, B::NB - 1);
     const int bx = b % B::BX, by = (b / B::BX) % B::BY, bz = b / (B::BX * B::BY);
-    int mirror, real;
-    const long long gi = box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - HX, y0 + by - HY, z0 + bz - HY, mirror, real);
-    // stored deviations w - wref
-    const T ri = recip(w[gi] + c.wref[0]);
-    T m1 = w[N + gi] + c.wref[1];
-    if (mirror) m1 = -m1;
-    su[0][b] = m1 * ri;
-    su[1][b] = (w[2 * N + gi] + c.wref[2]) * ri;
-    su[2][b] = (w[3 * N + gi] + c.wref[3]) * ri;
+    int real;
+    const long long gi =
+        box_cell(c.nx, c.ny, c.nz, c.wall, x0 + bx - HX, y0 + by - HY, z0 + bz - HY, mir[it], real);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) wv[it][v] = w[v * N + gi];
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int b = threadIdx.x + it * NTH;
+    if (it + 1 < NIT || b < B::NB) {
+      // stored deviations w - wref
+      const T ri = recip(wv[it][0] + c.wref[0]);
+      const T m1 = wv[it][1] + c.wref[1];
+      su[0][b] = (mir[it] ? -m1 : m1) * ri;
+      su[1][b] = (wv[it][2] + c.wref[2]) * ri;
+      su[2][b] = (wv[it][3] + c.wref[3]) * ri;
+    }
   }
 }
 
@@ -488,7 +509,7 @@ __global__ __launch_bounds__(KX * KY * KZ) void k_ked_tile(Consts<T> c, const T*
   constexpr int NTH = KX * KY * KZ;
   using B = TBox<KX, KY, KZ, 1, 1>;
   __shared__ T su[3][B::NB];
-  __shared__ double sh[NTH];
+  __shared__ double sh[NTH / 64];
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   int x0, y0, z0;
   tile_origin<KX, KY, KZ>(t, c.nx, c.ny, x0, y0, z0);
@@ -532,6 +553,22 @@ __global__ __launch_bounds__(KX * KY * KZ) void k_ked_grad_tile(Consts<T> c, con
   __shared__ T ss[6][I::NB];  // sigma xx, yy, zz, xy, xz, yz on the inner box
   int x0, y0, z0;
   tile_origin<KX, KY, KZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
+  const int tid = threadIdx.x;
+  const int tx = tid % KX, ty = (tid / KX) % KY, tz = tid / (KX * KY);
+  const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
+  const bool active = gx < c.nx && gy < c.ny && gz < c.nz;
+  const long long N = c.N;
+  const long long gi = active ? ((long long)gz * c.ny + gy) * c.nx + gx : 0;
+  // the cell's own state and the output it accumulates into, fetched now so that their latency
+  // hides behind the staging and the stress phase
+  T wc[4], dj[4];
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      wc[v] = w[v * N + gi];
+      dj[v] = djdw[v * N + gi];
+    }
+  }
   load_box_u<T, KX, KY, KZ, 2, 2>(c, w, x0, y0, z0, su);
   __syncthreads();
   const int sto[3] = {1, O::SY, O::SZ};
@@ -553,10 +590,7 @@ __global__ __launch_bounds__(KX * KY * KZ) void k_ked_grad_tile(Consts<T> c, con
     ss[5][b] = m * (G[1][2] + G[2][1]);
   }
   __syncthreads();
-  const int tid = threadIdx.x;
-  const int tx = tid % KX, ty = (tid / KX) % KY, tz = tid / (KX * KY);
-  const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
-  if (gx >= c.nx || gy >= c.ny || gz >= c.nz) return;
+  if (!active) return;
   const int sti[3] = {1, I::SY, I::SZ};
   const int p = (tz + 1) * I::SZ + (ty + 1) * I::SY + (tx + 1);
   // sym[l][k]: index of sigma_lk in ss
@@ -569,10 +603,8 @@ __global__ __launch_bounds__(KX * KY * KZ) void k_ked_grad_tile(Consts<T> c, con
     for (int l = 0; l < 3; ++l) acc += (ss[sym[l][k]][p - sti[l]] - ss[sym[l][k]][p + sti[l]]) * c.idx[l];
     uh[k] = acc;
   }
-  const long long N = c.N;
-  const long long gi = ((long long)gz * c.ny + gy) * c.nx + gx;
-  const T ri = recip(w[gi] + c.wref[0]);  // stored deviations w - wref
-  const T u[3] = {(w[N + gi] + c.wref[1]) * ri, (w[2 * N + gi] + c.wref[2]) * ri, (w[3 * N + gi] + c.wref[3]) * ri};
+  const T ri = recip(wc[0] + c.wref[0]);  // stored deviations w - wref
+  const T u[3] = {(wc[1] + c.wref[1]) * ri, (wc[2] + c.wref[2]) * ri, (wc[3] + c.wref[3]) * ri};
   const T f = (T)(wgt / (double)N);
   T o0 = -f * ri * (u[0] * uh[0] + u[1] * uh[1] + u[2] * uh[2]);
   T o[3] = {f * ri * uh[0], f * ri * uh[1], f * ri * uh[2]};
@@ -587,10 +619,10 @@ __global__ __launch_bounds__(KX * KY * KZ) void k_ked_grad_tile(Consts<T> c, con
     o[1] += f * ri * vh[1];
     o[2] += f * ri * vh[2];
   }
-  djdw[gi] += o0;
-  djdw[N + gi] += o[0];
-  djdw[2 * N + gi] += o[1];
-  djdw[3 * N + gi] += o[2];
+  djdw[gi] = dj[0] + o0;
+  djdw[N + gi] = dj[1] + o[0];
+  djdw[2 * N + gi] = dj[2] + o[1];
+  djdw[3 * N + gi] = dj[3] + o[2];
 }
 
 // Stagnation-pressure loss on an x-face plane [Eqs. (1)-(3)]: per face (j,k) the face state
