@@ -75,32 +75,53 @@ __device__ __forceinline__ void stage(const Consts<T>& c, int x0, int y0, int z0
                                       __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rg, bool has_g, T ca, T cg,
                                       T* lds, int np) {
   using E = Ext<D, H>;
+  constexpr int NIT = (E::N + RNT - 1) / RNT;
+  constexpr int NV = KH ? 15 : 5;
   const unsigned fb = (unsigned)(c.N * (long long)sizeof(T));
-  for (int e = threadIdx.x; e < E::N; e += RNT) {
+  // every load of this thread is issued before any is used (one memory latency, not NIT); the
+  // tail iteration re-reads the last cell of the region and does not store it
+  T w[NIT][NV];
+  int mir[NIT], real[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = min((int)threadIdx.x + it * RNT, E::N - 1);
     const int ex = e % E::EX, ey = (e / E::EX) % E::EY, ez = e / (E::EX * E::EY);
     const int gx = x0 + ex - (D == 0 ? H : 0), gy = y0 + ey - (D == 1 ? H : 0), gz = z0 + ez - (D == 2 ? H : 0);
-    int mir, real;
-    const unsigned off = (unsigned)(c.wall ? box_cell32<1>(c.nx, c.ny, c.nz, gx, gy, gz, mir, real)
-                                           : box_cell32<0>(c.nx, c.ny, c.nz, gx, gy, gz, mir, real)) *
+    const unsigned off = (unsigned)(c.wall ? box_cell32<1>(c.nx, c.ny, c.nz, gx, gy, gz, mir[it], real[it])
+                                           : box_cell32<0>(c.nx, c.ny, c.nz, gx, gy, gz, mir[it], real[it])) *
                          (unsigned)sizeof(T);
-    T w[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) w[v] = buf_load(rW, off, v * fb, T());
-    const T mx = w[1] + c.wref[1];
-    lds[e] = w[0] + c.wref[0];
-    lds[np + e] = mir ? -mx : mx;
-    lds[2 * np + e] = w[2] + c.wref[2];
-    lds[3 * np + e] = w[3] + c.wref[3];
-    lds[4 * np + e] = w[4];
+    for (int v = 0; v < 5; ++v) w[it][v] = buf_load(rW, off, v * fb, T());
     if (KH) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        T kh = T(0);
-        if (real) {
-          kh = ca * buf_load(ra, off, v * fb, T());
-          if (has_g) kh += cg * buf_load(rg, off, v * fb, T());
+      for (int v = 0; v < 5; ++v) w[it][KH ? 5 + v : 0] = buf_load(ra, off, v * fb, T());
+      if (has_g) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) w[it][KH ? 10 + v : 0] = buf_load(rg, off, v * fb, T());
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = threadIdx.x + it * RNT;
+    if (it + 1 < NIT || e < E::N) {
+      const T mx = w[it][1] + c.wref[1];
+      lds[e] = w[it][0] + c.wref[0];
+      lds[np + e] = mir[it] ? -mx : mx;
+      lds[2 * np + e] = w[it][2] + c.wref[2];
+      lds[3 * np + e] = w[it][3] + c.wref[3];
+      lds[4 * np + e] = w[it][4];
+      if (KH) {
+        // kh = ca a + cg gnext, zero in ghost cells
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          T kh = T(0);
+          if (real[it]) {
+            kh = ca * w[it][KH ? 5 + v : 0];
+            if (has_g) kh += cg * w[it][KH ? 10 + v : 0];
+          }
+          lds[(5 + v) * np + e] = kh;
         }
-        lds[(5 + v) * np + e] = kh;
       }
     }
   }
