@@ -736,68 +736,101 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// Block-scaled BF16 codec: 4 x 4 x 4 cell blocks, one wavefront each (lane = cell), four blocks
-// consecutive in x per work-group.  Per block and variable m = (max+min)/2, s = (max-min)/2 (1 for
-// an empty range); code = RNE_bf16((w - m)/s) with IEEE division; decode fma(s, code, m).
-// header[b * 10 + 2 v] = m, [b * 10 + 2 v + 1] = s; codes keep the state layout.
-struct CodecBlock {
-  long long i;  // cell index (valid when act)
-  int b;        // block index
-  bool act, live;
+// Block-scaled BF16 codec: 4 x 4 x 4 cell blocks.  Per block and variable m = (max+min)/2,
+// s = (max-min)/2 (1 for an empty range); code = RNE_bf16((w - m)/s) with IEEE division; decode
+// fma(s, code, m).  header[b * 10 + 2 v] = m, [b * 10 + 2 v + 1] = s with blocks numbered x
+// fastest; codes keep the state layout.
+// One wavefront per strip of four blocks along x (16 x 4 x 4 cells): lane = (x, y) of the strip,
+// each lane holds the four cells of its z column, and the four wavefronts of a work-group take
+// consecutive strips, so that a row of 64 cells is read and written whole.  A block's lanes
+// differ in lane bits 0, 1, 4 and 5.
+struct CodecStrip {
+  long long i[4];  // cell index per z (valid when act[z])
+  int b;           // block of the lane
+  bool act[4], live, any;
 };
 
-__device__ __forceinline__ CodecBlock codec_block(const Consts<float>& c) {
+__device__ __forceinline__ CodecStrip codec_strip(const Consts<float>& c) {
   const int lane = threadIdx.x & 63;
-  const int nbx = (c.nx + 3) >> 2, nby = (c.ny + 3) >> 2, nbz = (c.nz + 3) >> 2;
-  CodecBlock q;
-  q.b = blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
-  q.live = q.b < nbx * nby * nbz;
-  const int bx = q.b % nbx, by = (q.b / nbx) % nby, bz = q.b / (nbx * nby);
-  const int x = 4 * bx + (lane & 3), y = 4 * by + ((lane >> 2) & 3), z = 4 * bz + (lane >> 4);
-  q.act = q.live && x < c.nx && y < c.ny && z < c.nz;
-  q.i = q.act ? ((long long)z * c.ny + y) * c.nx + x : 0;
+  const int nbx = (c.nx + 3) >> 2, nby = (c.ny + 3) >> 2, nbz = (c.nz + 3) >> 2, nsx = (nbx + 3) >> 2;
+  const int sidx = blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
+  CodecStrip q;
+  q.any = sidx < nsx * nby * nbz;  // the wavefront has a strip
+  const int sx = sidx % nsx, by = (sidx / nsx) % nby, bz = sidx / (nsx * nby);
+  const int bx = 4 * sx + ((lane >> 2) & 3);
+  q.live = q.any && bx < nbx;
+  q.b = (bz * nby + by) * nbx + bx;
+  const int x = 4 * bx + (lane & 3), y = 4 * by + (lane >> 4);
+#pragma unroll
+  for (int z = 0; z < 4; ++z) {
+    const int gz = 4 * bz + z;
+    q.act[z] = q.live && x < c.nx && y < c.ny && gz < c.nz;
+    q.i[z] = q.act[z] ? ((long long)gz * c.ny + y) * c.nx + x : 0;
+  }
   return q;
 }
 
 __global__ __launch_bounds__(RB) void k_encode(Consts<float> c, const float* __restrict__ w, float* __restrict__ header,
                                                uint16_t* __restrict__ codes) {
-  const CodecBlock q = codec_block(c);
-  if (!q.live) return;  // whole wavefronts only: no lane of a live block leaves early
+  const CodecStrip q = codec_strip(c);
+  if (!q.any) return;  // whole wavefronts only: every lane of a strip takes part in the shuffles
   const long long N = c.N;
+  float x[5][4];
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int z = 0; z < 4; ++z) x[v][z] = q.act[z] ? w[v * N + q.i[z]] : 0.0f;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const float x = q.act ? w[v * N + q.i] : 0.0f;
-    float mn = q.act ? x : INFINITY, mx = q.act ? x : -INFINITY;
+    float mn = INFINITY, mx = -INFINITY;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int z = 0; z < 4; ++z)
+      if (q.act[z]) {
+        mn = fminf(mn, x[v][z]);
+        mx = fmaxf(mx, x[v][z]);
+      }
+#pragma unroll
+    for (int o = 1; o <= 32; o <<= 1) {
+      if (o == 4 || o == 8) continue;  // lane bits 2, 3 select the block
       mn = fminf(mn, __shfl_xor(mn, o));
       mx = fmaxf(mx, __shfl_xor(mx, o));
     }
     const float m = 0.5f * (mx + mn);
     float s = 0.5f * (mx - mn);
     if (!(s > 0.0f)) s = 1.0f;
-    if ((threadIdx.x & 63) == 0) {
+    if (q.live && (threadIdx.x & 0x33) == 0) {
       header[q.b * 10 + 2 * v] = m;
       header[q.b * 10 + 2 * v + 1] = s;
     }
-    if (q.act) codes[v * N + q.i] = bf16_rne(__fdiv_rn(x - m, s));
+#pragma unroll
+    for (int z = 0; z < 4; ++z)
+      if (q.act[z]) codes[v * N + q.i[z]] = bf16_rne(__fdiv_rn(x[v][z] - m, s));
   }
 }
 
 __global__ __launch_bounds__(RB) void k_decode(Consts<float> c, const float* __restrict__ header,
                                                const uint16_t* __restrict__ codes, float* __restrict__ w) {
-  const CodecBlock q = codec_block(c);
-  if (!q.act) return;
+  const CodecStrip q = codec_strip(c);
+  if (!q.live) return;
   const long long N = c.N;
+  uint16_t k[5][4];
 #pragma unroll
   for (int v = 0; v < 5; ++v)
-    w[v * N + q.i] = fmaf(header[q.b * 10 + 2 * v + 1], __uint_as_float((uint32_t)codes[v * N + q.i] << 16),
-                          header[q.b * 10 + 2 * v]);
+#pragma unroll
+    for (int z = 0; z < 4; ++z) k[v][z] = q.act[z] ? codes[v * N + q.i[z]] : (uint16_t)0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const float m = header[q.b * 10 + 2 * v], s = header[q.b * 10 + 2 * v + 1];
+#pragma unroll
+    for (int z = 0; z < 4; ++z)
+      if (q.act[z]) w[v * N + q.i[z]] = fmaf(s, __uint_as_float((uint32_t)k[v][z] << 16), m);
+  }
 }
 
 inline int codec_groups(const Consts<float>& c) {
-  const long long nb = (long long)((c.nx + 3) >> 2) * ((c.ny + 3) >> 2) * ((c.nz + 3) >> 2);
-  return (int)((nb + RB / 64 - 1) / (RB / 64));
+  const long long nbx = (c.nx + 3) >> 2;
+  const long long ns = ((nbx + 3) >> 2) * ((c.ny + 3) >> 2) * ((c.nz + 3) >> 2);
+  return (int)((ns + RB / 64 - 1) / (RB / 64));
 }
 
 }  // namespace
