@@ -183,8 +183,8 @@ __device__ __forceinline__ QS<T> load_qs(const Consts<T>& c, const T* __restrict
   q.p = (g - T(1)) * ((w[4 * N + gi] - T(0.5) * q.rho * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2])) +
                       c.wref[4]);
   const T cs = sqrt(g * q.p * ri);
-  q.a = sqrt((g - T(1)) / g) * cs;
-  q.b = cs / sqrt(g);
+  q.a = sqrt((g - T(1)) / g) * cs;  // the constant factors are common to every call of a thread
+  q.b = cs * recip(sqrt(g));
   return q;
 }
 
@@ -215,7 +215,7 @@ __device__ __forceinline__ T sym5_lambda_max(T (&A)[5][5]) {
     const T nrm = sqrt(ss);
     const T alpha = x0 >= T(0) ? -nrm : nrm;
     const T h = ss - x0 * alpha;  // |v|^2 / 2
-    const T hi = h > T(0) ? T(1) / h : T(0);
+    const T hi = h > T(0) ? recip(h) : T(0);
     T v[5], p[5];
 #pragma unroll
     for (int i = k + 1; i < 5; ++i) v[i] = i == k + 1 ? x0 - alpha : A[i][k];
@@ -249,7 +249,7 @@ __device__ __forceinline__ T sym5_lambda_max(T (&A)[5][5]) {
   for (int i = 0; i < 5; ++i) sc = fmax(sc, fabs(d[i]));
 #pragma unroll
   for (int i = 0; i < 4; ++i) sc = fmax(sc, fabs(e[i]));
-  const T inv = sc > T(0) ? T(1) / sc : T(0);
+  const T inv = sc > T(0) ? recip(sc) : T(0);
   T e2[4], lo = T(0), hi = T(0);
 #pragma unroll
   for (int i = 0; i < 5; ++i) d[i] *= inv;
@@ -280,9 +280,9 @@ __device__ __forceinline__ T sym5_lambda_max(T (&A)[5][5]) {
 // sigma_1 of cell i (0 <= i < N)
 template <typename T>
 __device__ __forceinline__ T sigma1_cell(const Consts<T>& c, const T* __restrict__ w, const long long i) {
-  const int gx = (int)(i % c.nx);
-  const int gy = (int)((i / c.nx) % c.ny);
-  const int gz = (int)(i / ((long long)c.nx * c.ny));
+  // 32-bit decomposition: the C ABI keeps every state array below 4 GiB (N < 2^28)
+  const unsigned ui = (unsigned)i, t = ui / (unsigned)c.nx;
+  const int gx = (int)(ui - t * (unsigned)c.nx), gy = (int)(t % (unsigned)c.ny), gz = (int)(t / (unsigned)c.ny);
   const QS<T> q0 = load_qs(c, w, gx, gy, gz);
   T grho[3], gu[3][3], gp[3], ga[3], gb[3];  // gu[k][j] = d_j u_k
 #pragma unroll
@@ -304,12 +304,12 @@ __device__ __forceinline__ T sigma1_cell(const Consts<T>& c, const T* __restrict
   Mx[0][0] = T(0.5) * div;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    Mx[0][1 + j] = T(0.5) * gb[j] - (q0.b / q0.rho) * grho[j];
+    Mx[0][1 + j] = T(0.5) * gb[j] - (q0.b * recip(q0.rho)) * grho[j];
     Mx[1 + j][0] = T(0.5) * gb[j];
 #pragma unroll
     for (int k = 0; k < 3; ++k) Mx[1 + k][1 + j] = (j == k ? T(0.5) * div : T(0)) - gu[k][j];
-    Mx[1 + j][4] = T(0.5) * ga[j] - (q0.a / (T(2) * q0.p)) * gp[j];
-    Mx[4][1 + j] = T(0.5) * ga[j] - (T(2) / (g - T(1))) * ga[j];
+    Mx[1 + j][4] = T(0.5) * ga[j] - (q0.a * recip(T(2) * q0.p)) * gp[j];
+    Mx[4][1 + j] = T(0.5) * ga[j] - (T(2) * recip(g - T(1))) * ga[j];
     Mx[4][0] = T(0);
   }
   Mx[0][4] = -T(0.5) * sqrt(g - T(1)) * div;
