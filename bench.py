@@ -48,19 +48,24 @@ VALUES_PER_STAGE_LAUNCH_RK3 = 55.0 / 3.0
 
 
 def profile_values(name, kernel_src_hash, tile):
-    """key = value pairs of a committed rocprofv3 summary of the reverse-stage kernel
-    (profiles/<name>), or None when it was taken on a different kernel source or tile."""
-    path = os.path.join(ROOT, "profiles", name)
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    for line in open(path):
-        if "=" in line and not line.startswith("#"):
-            k, v = line.split("=", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != kernel_src_hash or vals.get("tile_f32") != tile:
-        return None
-    return vals
+    """key = value pairs of a committed rocprofv3 summary of the reverse-stage kernel:
+    profiles/<name>, or profiles/<stem>_<tile>.txt (summaries taken in another tile shape, for
+    runs whose tuner keeps that shape), whichever was taken on this kernel source and tile;
+    None if neither was."""
+    stem, ext = os.path.splitext(name)
+    for cand in (name, f"{stem}_{tile}{ext}"):
+        path = os.path.join(ROOT, "profiles", cand)
+        if not os.path.exists(path):
+            continue
+        vals = {}
+        for line in open(path):
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+        if vals.get("kernel_source_sha256") == kernel_src_hash and vals.get("tile_f32") == tile:
+            vals["profile"] = cand
+            return vals
+    return None
 
 
 def valu_roofline(valu, cells, avg_us):
@@ -455,11 +460,14 @@ def main():
         "unit": "GB/s",
         "frac": r32["stage_achieved_gbs"] / HBM_PEAK_GBS,
         "traffic": None if traffic is None else float(traffic["bytes_per_cell_launch_f32"]) * wl.ncells,
+        "traffic_profile": None if traffic is None else "profiles/" + traffic["profile"],
         "kernel": "k_adjoint_stage (reverse-stage gather)",
         "avg_launch_us": r32["stage_avg_us"],
         "alg_bytes_per_launch": r32["stage_alg_bytes"],
     }
     roof_valu = valu_roofline(valu, wl.ncells, r32["stage_avg_us"])
+    if roof_valu is not None:
+        roof_valu["profile"] = "profiles/" + valu["profile"]
     if "roe" in r32:
         # with the Roe flux the transpose of its flux terms takes the largest share of the window
         rk = r32["roe"]["roe_adjoint"]
