@@ -128,8 +128,10 @@ def test_energy_and_dot_parity(orc):
     assert abs(host(d)[0] - float(wh @ b)) <= 1e-12 * np.abs(wh * b).sum()
 
 
-def test_codec_bitwise(orc):
-    shape = (19, 6, 9)
+# (19, 6, 9): two strips of four blocks along x, the second with one block; (37, 13, 10): three
+# strips, the last with two blocks, ragged blocks in every direction; (64, 8, 4): whole strips
+@pytest.mark.parametrize("shape", [(19, 6, 9), (37, 13, 10), (64, 8, 4)], ids=["19x6x9", "37x13x10", "64x8x4"])
+def test_codec_bitwise(orc, shape):
     g = adj.Grid.make(shape, (1, 1, 1), 0.01, 0.01, precision=adj.F32, ckpt_format=adj.CKPT_BF16)
     w = smooth_state(shape, seed=11).astype(np.float32)
     ws = adj.workspace(g)
