@@ -172,7 +172,10 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
   const bool active = gx < c.nx && gy < c.ny && gz < c.nz;
   const long long gi = ((long long)(active ? gz : 0) * c.ny + (active ? gy : 0)) * c.nx + (active ? gx : 0);
   // per-cell operands, fetched before the barrier so that their latency overlaps the staging
-  T sv[5] = {T(0), T(0), T(0), T(0), T(0)}, base[5];
+  T sv[5] = {T(0), T(0), T(0), T(0), T(0)}, base[5], wq[5];
+  // the final stage fetches the cell's own W here too, except where the five more registers would
+  // spill (FP64 work-groups of 1024 threads, capped at 128 registers)
+  constexpr bool PREW = sizeof(T) == 4 || NT <= 512;
   if (active) {
     if (s) {
 #pragma unroll
@@ -189,6 +192,7 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
       for (int v = 0; v < 5; ++v) {
         const long long q = v * N + gi;
         base[v] = (W2[q] + T(2) * W3[q] - wn[q]);
+        if (PREW) wq[v] = W[q];
       }
     }
   }
@@ -212,10 +216,7 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
   } else {
     const T third = T(1) / T(3), h6 = c.dt / T(6);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const long long q = v * N + gi;
-      out[q] = (base[v] + W[q]) * third + h6 * R[v];
-    }
+    for (int v = 0; v < 5; ++v) out[v * N + gi] = (base[v] + (PREW ? wq[v] : W[v * N + gi])) * third + h6 * R[v];
   }
 }
 
@@ -567,7 +568,7 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
   T r0 = T(1), ri = T(0), e = T(0), uc[3] = {T(0), T(0), T(0)};
   // stage-1 operands at the cell itself, fetched now so that their latency hides behind the
   // face phases
-  T fa[5], f2[5], f3[5], f4[5];
+  T fa[5], f2[5], f3[5], f4[5], gs[5];
   if (MODE != STAGE_VJP && active) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -576,6 +577,7 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
       f2[v] = gnext[q];
       f3[v] = g3[q];
       f4[v] = g4[q];
+      if (grad_s) gs[v] = grad_s[q];
     }
   }
   T uh[3] = {T(0), T(0), T(0)}, eh = T(0), rh = T(0);
@@ -662,7 +664,7 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
       const long long q = v * N + gi;
       out[q] = fa[v] + g[v] + f2[v] + f3[v] + f4[v];
       // explicit fused order: every instantiation (and the ensemble form) rounds identically
-      if (grad_s) grad_s[q] = fma(dt, fa[v], fma(dt, f4[v], fma(h2, f3[v] + f2[v], grad_s[q])));
+      if (grad_s) grad_s[q] = fma(dt, fa[v], fma(dt, f4[v], fma(h2, f3[v] + f2[v], gs[v])));
     }
   }
 }
