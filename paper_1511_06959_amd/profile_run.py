@@ -22,7 +22,7 @@
         markdown table of a --kernel-trace --stats run
 
 Run the first two under rocprofv3, e.g.
-    rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o run --output-format csv -- \
+    rocprofv3 --pmc FETCH_SIZE -d prof/pmc_fetch -o run --output-format csv -- \
         python -m paper_1511_06959_amd.profile_run adjoint --n 64 --precision f32 --reps 5 --stages
 """
 import argparse
