@@ -35,7 +35,8 @@
  * device memory in both precisions.  The library never allocates, frees or synchronises: every
  * call enqueues kernels on `stream` (a hipStream_t; NULL = the default stream) and returns.
  * Scratch memory is the caller's `ws` of at least adj_workspace_bytes(grid) bytes, 256-byte
- * aligned; calls that share a `ws` must be ordered on one stream.
+ * aligned; calls that share a `ws` must be ordered on one stream (adj_adjoint_step_noalloc takes
+ * its scratch from a static device array instead).
  *
  * Errors: every entry point validates its arguments on the host before launching anything and
  * returns a negative adj_status without touching device memory when they are invalid;
@@ -177,6 +178,20 @@ int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* 
 int adj_adjoint_step(const adj_grid* grid, const void* w_n, const void* s, const void* wh_np1,
                      double lambda, const adj_objective* obj, double c_n, void* wh_n, void* grad_s,
                      void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory, not even a workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): adj_adjoint_step with its
+ * scratch taken from a static device array of ADJ_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on every GPU it runs on until the process ends (64 MiB: grids up to 64^3 cells in FP64
+ * or FP32; adj_workspace_bytes(grid) must not exceed it).  Same arguments and results as
+ * adj_adjoint_step without ws / ws_bytes; it allocates nothing (the device's address of the array
+ * is looked up once, on that device's first call).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other host threads) race and give
+ * undefined results; order them on one stream.  Returns ADJ_EWORKSPACE when the grid needs more
+ * scratch than the array holds, the other codes as adj_adjoint_step. */
+#define ADJ_NOALLOC_SCRATCH_BYTES (64u << 20)
+int adj_adjoint_step_noalloc(const adj_grid* grid, const void* w_n, const void* s, const void* wh_np1, double lambda,
+                             const adj_objective* obj, double c_n, void* wh_n, void* grad_s, void* stream);
 
 /* Store-stages schedule (for windows whose stage states fit in memory): adj_primal_step_stages
  * is adj_primal_step that also writes the stage states of the step into stages_out (3

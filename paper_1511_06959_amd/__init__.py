@@ -132,7 +132,8 @@ class Objective(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjoint_step", "adj_primal_step_stages",
+EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjoint_step", "adj_adjoint_step_noalloc",
+           "adj_primal_step_stages",
            "adj_adjoint_step_stages", "adj_growth_sigma1",
            "adj_objective_and_grad", "adj_energy_vhat", "adj_dot", "adj_ckpt_encode", "adj_ckpt_decode",
            "adj_residual", "adj_vjp", "adj_profile_enable", "adj_profile_read", "adj_set_tile", "adj_get_tile",
@@ -157,6 +158,7 @@ def lib():
         "adj_ckpt_bytes": ([gp], sz),
         "adj_primal_step": ([gp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "adj_adjoint_step": ([gp, vp, vp, vp, dbl, op, dbl, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_adjoint_step_noalloc": ([gp, vp, vp, vp, dbl, op, dbl, vp, vp, vp], ctypes.c_int),
         "adj_primal_step_stages": ([gp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "adj_adjoint_step_stages": ([gp, vp, vp, vp, vp, dbl, op, dbl, vp, vp, vp, sz, vp], ctypes.c_int),
         "adj_growth_sigma1": ([gp, vp, dbl, vp, vp], ctypes.c_int),
@@ -264,6 +266,18 @@ def adjoint_step(g, w_n, s, wh_np1, wh_n, ws, lam=0.0, obj=None, c_n=0.0, grad_s
     _check(lib().adj_adjoint_step(ctypes.byref(g), wn_p, _state(g, s), _state(g, wh_np1), float(lam),
                                   ctypes.byref(obj) if obj is not None else None, float(c_n), _state(g, wh_n),
                                   _state(g, grad_s), wp, wb, _stream()))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # ADJ_NOALLOC_SCRATCH_BYTES
+
+
+def adjoint_step_noalloc(g, w_n, s, wh_np1, wh_n, lam=0.0, obj=None, c_n=0.0, grad_s=None):
+    """adjoint_step without a workspace: the library's static per-GPU scratch array serves instead
+    (grids whose workspace_bytes(g) <= NOALLOC_SCRATCH_BYTES; calls overlapping on one GPU race)."""
+    wn_p = _ptr(w_n, torch.uint8) if g.ckpt_format == CKPT_BF16 else _state(g, w_n)
+    _check(lib().adj_adjoint_step_noalloc(ctypes.byref(g), wn_p, _state(g, s), _state(g, wh_np1), float(lam),
+                                          ctypes.byref(obj) if obj is not None else None, float(c_n),
+                                          _state(g, wh_n), _state(g, grad_s), _stream()))
 
 
 def _stages(g, t):

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1036,6 +1037,56 @@ int adj_batch_energy_vhat(const adj_batch* batch, int nmem, const void* w, const
     e = launch_energy_batch<float>((const BoxDesc<float>*)batch->dmem, batch->dslm, batch->slm.data(), nmem,
                                    (const float*)w, (const float*)wh, (double*)at(ws, L.partials), E, st);
   return e ? hip_fail(e, "ensemble energy") : ADJ_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Reverse step without a caller workspace: the scratch lives in a file-scope device array (one
+// copy per GPU, allocated when the code object loads and held until the process ends).  Host code
+// never uses the array's name as an address: hipGetSymbolAddress gives each device's own address
+// once, with that device current, and that pointer is what the kernels receive as their workspace.
+// ---------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[ADJ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 256;
+std::mutex g_scratch_mtx;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// This device's address of `scratch` (looked up on the device's first call).
+int scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e;
+  if ((e = hipGetDevice(&dev))) return hip_fail(e, "no-alloc scratch: current device");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(ADJ_EHIP, "no-alloc scratch: device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mtx);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)))) return hip_fail(e, "no-alloc scratch: symbol address");
+    if (!p || (uintptr_t)p % ALIGN) return fail(ADJ_EHIP, "no-alloc scratch: bad symbol address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ADJ_OK;
+}
+}  // namespace
+
+int adj_adjoint_step_noalloc(const adj_grid* grid, const void* w_n, const void* s, const void* wh_np1,
+                             double lambda, const adj_objective* obj, double c_n, void* wh_n, void* grad_s,
+                             void* stream) {
+  int r;
+  if ((r = check_grid(grid, true))) return r;
+  const size_t need = layout(grid).total;
+  if (need > (size_t)ADJ_NOALLOC_SCRATCH_BYTES)
+    return fail(ADJ_EWORKSPACE,
+                "adj_adjoint_step_noalloc: this grid needs %zu bytes of scratch, more than the %zu bytes of the "
+                "static scratch array; use adj_adjoint_step with a workspace",
+                need, (size_t)ADJ_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if ((r = scratch_address(&ws))) return r;
+  // every scratch region of the reverse step is written before it is read, so nothing needs
+  // clearing between calls
+  return adjoint_entry(grid, w_n, nullptr, s, wh_np1, lambda, obj, c_n, wh_n, grad_s, ws,
+                       (size_t)ADJ_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 const char* adj_last_error(void) { return g_err.c_str(); }

@@ -203,3 +203,21 @@ def test_stability_argument_errors():
     assert L.adj_stability(ctypes.byref(g), fake, ctypes.c_double(0.0), fake, None, nb, None) == -6
     bad = _grid(dt=0.0)
     assert L.adj_check_stable(ctypes.byref(bad), fake, ctypes.c_double(0.0), None, wsp, nb, None) == -1
+
+
+def test_noalloc_step_validates_before_touching_the_device():
+    """The no-allocation reverse step rejects bad grids and grids whose scratch exceeds its static
+    array on the host, before it looks up the array or launches anything."""
+    L = adj.lib()
+    fake = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
+    big = _grid(n=(96, 96, 96))
+    assert adj.workspace_bytes(big) > adj.NOALLOC_SCRATCH_BYTES
+    rc = L.adj_adjoint_step_noalloc(ctypes.byref(big), fake, None, fake, 0.0, None, 0.0, ctypes.c_void_p(8192), None,
+                                    None)
+    assert rc == -6 and b"static scratch" in L.adj_last_error()
+    bad = _grid(dt=0.0)
+    rc = L.adj_adjoint_step_noalloc(ctypes.byref(bad), fake, None, fake, 0.0, None, 0.0, ctypes.c_void_p(8192), None,
+                                    None)
+    assert rc == -1
+    # 64^3 FP64, the largest cube the array is sized for, fits
+    assert adj.workspace_bytes(_grid(n=(64, 64, 64))) <= adj.NOALLOC_SCRATCH_BYTES
