@@ -143,7 +143,7 @@ typedef struct adj_objective {
 /* Bytes of scratch the caller must pass as `ws` to any call on this grid. */
 size_t adj_workspace_bytes(const adj_grid* grid);
 
-/* Bytes of one BF16 checkpoint record: the block header (10 FP32 values per 4x4x4 block of
+/* Bytes of one BF16 checkpoint record: the block header (25 FP32 values per 4x4x4 block of
  * cells, padded to a multiple of 256 bytes) followed by 5N bfloat16 codes in the state layout
  * (see adj_ckpt_encode). */
 size_t adj_ckpt_bytes(const adj_grid* grid);
@@ -224,13 +224,21 @@ int adj_energy_vhat(const adj_grid* grid, const void* w, const void* wh, double*
 int adj_dot(const adj_grid* grid, const void* a, const void* b, double* out, void* ws, size_t ws_bytes,
             void* stream);
 
-/* BF16 checkpoint codec (ADJ_F32 states), block-scaled: the grid is cut into 4x4x4 blocks of
- * cells (ragged at the far ends), block b = (bz*nby + by)*nbx + bx, nbd = ceil(n[d]/4).  Per block
- * and variable v, m = (max+min)/2, s = (max-min)/2 over the block's cells (1 when the range is
- * empty), code = bf16_round_nearest_even((w - m)/s) in FP32 with IEEE division; decode
- * w' = fma(s, code, m).  Record (adj_ckpt_bytes): header of 10 floats per block,
- * header[b*10 + 2v] = m, header[b*10 + 2v + 1] = s, padded to a multiple of 256 bytes, then the
- * 5N codes in the state layout.  Records must be 64-byte aligned. */
+/* BF16 checkpoint codec (ADJ_F32 states), block-scaled with a plane predictor: the grid is cut
+ * into 4x4x4 blocks of cells (ragged at the far ends), block b = (bz*nby + by)*nbx + bx,
+ * nbd = ceil(n[d]/4).  Per block and variable v, over the block's present cells with centred
+ * local coordinates c_d = l_d - (n'_d - 1)/2 (n'_d present cells along d):
+ *   a = S_0/n', g_d = S_d / sum c_d^2 (0 when n'_d = 1): the least-squares plane, from the FP64
+ *     sums S_0 = sum w and S_d = sum c_d w (each column z = 0..3 accumulated by fma, the columns
+ *     added pairwise along x, then the rows pairwise along y), rounded to FP32;
+ *   P(a) = fma(g_z, c_z, fma(g_y, c_y, fma(g_x, c_x, a))); r0 = w - P(a);
+ *   a' = a + (max r0 + min r0)/2, s = (max r0 - min r0)/2 (1 when the range is empty);
+ *   code = bf16_round_nearest_even((w - P(a'))/s) in FP32 with IEEE division;
+ *   decode w' = fma(s, code, P(a')).
+ * Record (adj_ckpt_bytes): header of 25 floats per block, header[(b*5 + v)*5 + {0..4}] =
+ * a', g_x, g_y, g_z, s, padded to a multiple of 256 bytes, then the 5N codes in the state
+ * layout.  Records must be 64-byte aligned  [Implementation: checkpointing; the precision form
+ * keeps the primal snapshots in BF16 under per-variable scaling]. */
 int adj_ckpt_encode(const adj_grid* grid, const float* w, void* ckpt, void* ws, size_t ws_bytes, void* stream);
 int adj_ckpt_decode(const adj_grid* grid, const void* ckpt, float* w, void* stream);
 

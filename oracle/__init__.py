@@ -344,11 +344,12 @@ def energy_vhat(g, w, wh):
 
 
 def ckpt_encode(g, w32):
-    """Block-scaled BF16 encoding of an FP32 state: (codes, header[blocks, 10])."""
+    """Block-scaled BF16 encoding of an FP32 state with a plane predictor per block and variable:
+    (codes, header[blocks, 25]) with header[b, 5 v + (0..4)] = a', g_x, g_y, g_z, s."""
     w32 = np.ascontiguousarray(w32, dtype=np.float32)
     nb = lib().orc_ckpt_blocks(ctypes.byref(g))
     q = np.zeros(w32.size, dtype=np.uint16)
-    hdr = np.zeros((nb, 10), dtype=np.float32)
+    hdr = np.zeros((nb, 25), dtype=np.float32)
     lib().orc_ckpt_encode(ctypes.byref(g), w32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                           q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
                           hdr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))

@@ -1159,11 +1159,20 @@ int orc_energy_vhat(const orc_grid* gr, const double* w, const double* wh, doubl
 }
 
 // ------------------------------------------------------------------------------------------
-// BF16 checkpoint codec, block-scaled, FP32 arithmetic.  The grid is cut into 4 x 4 x 4 blocks of
-// cells (ragged at the far ends); block b = (bz * nby + by) * nbx + bx holds, per variable v,
-//   m = (max + min)/2, s = (max - min)/2 (1 if the range is 0) over the block's cells,
-//   q = bf16_round_nearest_even((w - m) / s),   decode w' = fma(s, q, m);
-// header[b * 10 + 2 v] = m, header[b * 10 + 2 v + 1] = s.  Codes keep the state layout.
+// BF16 checkpoint codec, block-scaled with a plane predictor (the precision form of the method:
+// primal snapshots kept in BF16 under per-variable scaling; the paper's own snapshots are full
+// precision, "Implementation").  The grid is cut into 4 x 4 x 4 blocks of cells (ragged at the
+// far ends); block b = (bz * nby + by) * nbx + bx.  Per block and variable, over its present
+// cells with centred local coordinates c_d = l_d - (n'_d - 1)/2:
+//   (a, g) = least-squares plane of the values: a = S_0 / n', g_d = S_d / sum c_d^2 (0 if n'_d = 1)
+//            with S_0 = sum w, S_d = sum c_d w in FP64, each rounded to FP32;
+//   P(a) = fma(g_z, c_z, fma(g_y, c_y, fma(g_x, c_x, a))) in FP32; r0 = w - P(a);
+//   a' = a + (max r0 + min r0)/2, s = (max r0 - min r0)/2 (1 if the range is 0);
+//   q = bf16_round_nearest_even((w - P(a')) / s),   decode w' = fma(s, q, P(a')).
+// header[(b * 5 + v) * 5 + {0..4}] = a', g_x, g_y, g_z, s.  Codes keep the state layout.
+// The FP64 sums run in one fixed order (so that two implementations round alike): per (x, y)
+// column the cells z = 0..3 accumulate by fma (c w is exact in FP64), then columns add pairwise
+// along x ((x0 + x1) + (x2 + x3)) and the rows likewise along y.
 // ------------------------------------------------------------------------------------------
 static uint16_t f32_to_bf16_rne(float f) {
   uint32_t u; std::memcpy(&u, &f, 4);
@@ -1183,6 +1192,12 @@ long orc_ckpt_blocks(const orc_grid* g) {
   return a * b * c;
 }
 
+static double side_sq(long m) { double s = 0.0; for (long l = 0; l < m; ++l) s += (l - 0.5 * (m - 1)) * (l - 0.5 * (m - 1)); return s; }
+static float centred(long l, long m) { return (float)l - 0.5f * (float)(m - 1); }
+static float plane_at(const float* h, float cx, float cy, float cz) {
+  return std::fma(h[3], cz, std::fma(h[2], cy, std::fma(h[1], cx, h[0])));
+}
+
 int orc_ckpt_encode(const orc_grid* g, const float* w, uint16_t* q, float* header) {
   const long nx = g->n[0], ny = g->n[1], nz = g->n[2], N = nx * ny * nz;
   long nbx, nby, nbz; codec_blocks(g, nbx, nby, nbz);
@@ -1190,22 +1205,49 @@ int orc_ckpt_encode(const orc_grid* g, const float* w, uint16_t* q, float* heade
     for (long by = 0; by < nby; ++by)
       for (long bx = 0; bx < nbx; ++bx) {
         const long b = (bz * nby + by) * nbx + bx;
+        const long mx = std::min(4L, nx - 4 * bx), my = std::min(4L, ny - 4 * by), mz = std::min(4L, nz - 4 * bz);
         for (int v = 0; v < 5; ++v) {
-          float mn = INFINITY, mx = -INFINITY;
-          for (long k = 4 * bz; k < std::min(nz, 4 * bz + 4); ++k)
-            for (long j = 4 * by; j < std::min(ny, 4 * by + 4); ++j)
-              for (long i = 4 * bx; i < std::min(nx, 4 * bx + 4); ++i) {
-                const float x = w[v * N + (k * ny + j) * nx + i];
-                mn = std::min(mn, x); mx = std::max(mx, x);
+          const float* wv = w + v * N;
+          auto at = [&](long i, long j, long k) { return wv[((4 * bz + k) * ny + 4 * by + j) * nx + 4 * bx + i]; };
+          // column sums (S_0, S_x, S_y, S_z) at (i, j), then the pairwise x and y order
+          double col[4][4][4] = {};
+          for (long j = 0; j < my; ++j)
+            for (long i = 0; i < mx; ++i)
+              for (long k = 0; k < mz; ++k) {
+                const double x = at(i, j, k);
+                const double c[4] = {1.0, centred(i, mx), centred(j, my), centred(k, mz)};
+                for (int t = 0; t < 4; ++t) col[j][i][t] = std::fma(c[t], x, col[j][i][t]);
               }
-          float m = 0.5f * (mx + mn), s = 0.5f * (mx - mn);
+          double S[4];
+          for (int t = 0; t < 4; ++t) {
+            double row[4];
+            for (int j = 0; j < 4; ++j) row[j] = (col[j][0][t] + col[j][1][t]) + (col[j][2][t] + col[j][3][t]);
+            S[t] = (row[0] + row[1]) + (row[2] + row[3]);
+          }
+          const double dx2 = (double)(my * mz) * side_sq(mx), dy2 = (double)(mx * mz) * side_sq(my),
+                       dz2 = (double)(mx * my) * side_sq(mz);
+          float h[5];
+          h[0] = (float)(S[0] / (double)(mx * my * mz));
+          h[1] = dx2 > 0.0 ? (float)(S[1] / dx2) : 0.0f;
+          h[2] = dy2 > 0.0 ? (float)(S[2] / dy2) : 0.0f;
+          h[3] = dz2 > 0.0 ? (float)(S[3] / dz2) : 0.0f;
+          float rmn = INFINITY, rmx = -INFINITY;
+          for (long k = 0; k < mz; ++k)
+            for (long j = 0; j < my; ++j)
+              for (long i = 0; i < mx; ++i) {
+                const float r = at(i, j, k) - plane_at(h, centred(i, mx), centred(j, my), centred(k, mz));
+                rmn = std::min(rmn, r); rmx = std::max(rmx, r);
+              }
+          h[0] = h[0] + 0.5f * (rmx + rmn);
+          float s = 0.5f * (rmx - rmn);
           if (!(s > 0.0f)) s = 1.0f;
-          header[b * 10 + 2 * v] = m; header[b * 10 + 2 * v + 1] = s;
-          for (long k = 4 * bz; k < std::min(nz, 4 * bz + 4); ++k)
-            for (long j = 4 * by; j < std::min(ny, 4 * by + 4); ++j)
-              for (long i = 4 * bx; i < std::min(nx, 4 * bx + 4); ++i) {
-                const long c = v * N + (k * ny + j) * nx + i;
-                q[c] = f32_to_bf16_rne((w[c] - m) / s);
+          h[4] = s;
+          for (int t = 0; t < 5; ++t) header[(b * 5 + v) * 5 + t] = h[t];
+          for (long k = 0; k < mz; ++k)
+            for (long j = 0; j < my; ++j)
+              for (long i = 0; i < mx; ++i) {
+                const long c = v * N + ((4 * bz + k) * ny + 4 * by + j) * nx + 4 * bx + i;
+                q[c] = f32_to_bf16_rne((w[c] - plane_at(h, centred(i, mx), centred(j, my), centred(k, mz))) / s);
               }
         }
       }
@@ -1220,7 +1262,10 @@ int orc_ckpt_decode(const orc_grid* g, const uint16_t* q, const float* header, f
       for (long j = 0; j < ny; ++j)
         for (long i = 0; i < nx; ++i) {
           const long b = ((k / 4) * nby + j / 4) * nbx + i / 4, c = v * N + (k * ny + j) * nx + i;
-          w[c] = std::fma(header[b * 10 + 2 * v + 1], bf16_to_f32(q[c]), header[b * 10 + 2 * v]);
+          const long mx = std::min(4L, nx - 4 * (i / 4)), my = std::min(4L, ny - 4 * (j / 4)),
+                     mz = std::min(4L, nz - 4 * (k / 4));
+          const float* h = header + (b * 5 + v) * 5;
+          w[c] = std::fma(h[4], bf16_to_f32(q[c]), plane_at(h, centred(i % 4, mx), centred(j % 4, my), centred(k % 4, mz)));
         }
   return 0;
 }

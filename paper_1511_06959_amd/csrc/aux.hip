@@ -736,19 +736,35 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// Block-scaled BF16 codec: 4 x 4 x 4 cell blocks.  Per block and variable m = (max+min)/2,
-// s = (max-min)/2 (1 for an empty range); code = RNE_bf16((w - m)/s) with IEEE division; decode
-// fma(s, code, m).  header[b * 10 + 2 v] = m, [b * 10 + 2 v + 1] = s with blocks numbered x
-// fastest; codes keep the state layout.
+// Block-scaled BF16 codec with a plane predictor: 4 x 4 x 4 cell blocks (ragged at the far ends).
+// Per block and variable, with the present cells' local coordinates centred on the block
+// (c_d = l_d - (n'_d - 1)/2, n'_d present cells along d):
+//   a, g_x, g_y, g_z = the least-squares plane a + g . c of the block's values: FP64 sums
+//     S_0 = sum w, S_d = sum c_d w in a fixed order, a = S_0 / n', g_d = S_d / sum c_d^2 (0 when
+//     n'_d = 1), each rounded to FP32;
+//   r0 = w - P(a), P(a) = fma(g_z, c_z, fma(g_y, c_y, fma(g_x, c_x, a)));
+//   a' = a + (max r0 + min r0)/2, s = (max r0 - min r0)/2 (1 for an empty range);
+//   code = RNE_bf16((w - P(a')) / s) with IEEE division;  decode w' = fma(s, code, P(a')).
+// header[(b * 5 + v) * 5 + {0, 1, 2, 3, 4}] = a', g_x, g_y, g_z, s with blocks numbered x fastest;
+// codes keep the state layout.  The fixed summation order: each cell (lane) sums its z column,
+// c(z) w_z accumulated z = 0..3 by fma (the products are exact in FP64); the columns then add
+// pairwise in x (0+1, 2+3, then the pairs) and the rows pairwise in y the same way.
 // One wavefront per strip of four blocks along x (16 x 4 x 4 cells): lane = (x, y) of the strip,
 // each lane holds the four cells of its z column, and the four wavefronts of a work-group take
 // consecutive strips, so that a row of 64 cells is read and written whole.  A block's lanes
-// differ in lane bits 0, 1, 4 and 5.
+// differ in lane bits 0, 1 (x) and 4, 5 (y), and the butterflies over those bits (1, 2, 16, 32)
+// are the pairwise order above.
 struct CodecStrip {
   long long i[4];  // cell index per z (valid when act[z])
   int b;           // block of the lane
+  float cx, cy, cz[4];  // centred local coordinates of the lane's cells
+  int np;               // present cells of the block
+  double dx2, dy2, dz2; // sums of c_d^2 over the block's present cells
   bool act[4], live, any;
 };
+
+// sum over l = 0..m-1 of (l - (m-1)/2)^2 for a block side of m present cells
+__device__ __forceinline__ double side_sq(int m) { return m == 4 ? 5.0 : (m == 3 ? 2.0 : (m == 2 ? 0.5 : 0.0)); }
 
 __device__ __forceinline__ CodecStrip codec_strip(const Consts<float>& c) {
   const int lane = threadIdx.x & 63;
@@ -760,14 +776,36 @@ __device__ __forceinline__ CodecStrip codec_strip(const Consts<float>& c) {
   const int bx = 4 * sx + ((lane >> 2) & 3);
   q.live = q.any && bx < nbx;
   q.b = (bz * nby + by) * nbx + bx;
-  const int x = 4 * bx + (lane & 3), y = 4 * by + (lane >> 4);
+  const int lx = lane & 3, ly = lane >> 4;
+  const int x = 4 * bx + lx, y = 4 * by + ly;
+  const int mx = min(4, c.nx - 4 * bx), my = min(4, c.ny - 4 * by), mz = min(4, c.nz - 4 * bz);
+  q.cx = (float)lx - 0.5f * (float)(mx - 1);
+  q.cy = (float)ly - 0.5f * (float)(my - 1);
+  q.np = mx * my * mz;
+  q.dx2 = (double)(my * mz) * side_sq(mx);
+  q.dy2 = (double)(mx * mz) * side_sq(my);
+  q.dz2 = (double)(mx * my) * side_sq(mz);
 #pragma unroll
   for (int z = 0; z < 4; ++z) {
     const int gz = 4 * bz + z;
+    q.cz[z] = (float)z - 0.5f * (float)(mz - 1);
     q.act[z] = q.live && x < c.nx && y < c.ny && gz < c.nz;
     q.i[z] = q.act[z] ? ((long long)gz * c.ny + y) * c.nx + x : 0;
   }
   return q;
+}
+
+// plane predictor at a cell: fma(g_z, c_z, fma(g_y, c_y, fma(g_x, c_x, a)))
+__device__ __forceinline__ float plane(float a, float gx, float gy, float gz, float cx, float cy, float cz) {
+  return fmaf(gz, cz, fmaf(gy, cy, fmaf(gx, cx, a)));
+}
+
+__device__ __forceinline__ double block_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
 }
 
 __global__ __launch_bounds__(RB) void k_encode(Consts<float> c, const float* __restrict__ w, float* __restrict__ header,
@@ -782,12 +820,31 @@ __global__ __launch_bounds__(RB) void k_encode(Consts<float> c, const float* __r
     for (int z = 0; z < 4; ++z) x[v][z] = q.act[z] ? w[v * N + q.i[z]] : 0.0f;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
+    double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int z = 0; z < 4; ++z)
+      if (q.act[z]) {
+        const double xv = (double)x[v][z];
+        s0 = fma(1.0, xv, s0);
+        sx = fma((double)q.cx, xv, sx);
+        sy = fma((double)q.cy, xv, sy);
+        sz = fma((double)q.cz[z], xv, sz);
+      }
+    s0 = block_sum(s0);
+    sx = block_sum(sx);
+    sy = block_sum(sy);
+    sz = block_sum(sz);
+    const float a = (float)(s0 / (double)(q.np > 0 ? q.np : 1));
+    const float gx = q.dx2 > 0.0 ? (float)(sx / q.dx2) : 0.0f;
+    const float gy = q.dy2 > 0.0 ? (float)(sy / q.dy2) : 0.0f;
+    const float gz = q.dz2 > 0.0 ? (float)(sz / q.dz2) : 0.0f;
     float mn = INFINITY, mx = -INFINITY;
 #pragma unroll
     for (int z = 0; z < 4; ++z)
       if (q.act[z]) {
-        mn = fminf(mn, x[v][z]);
-        mx = fmaxf(mx, x[v][z]);
+        const float r = x[v][z] - plane(a, gx, gy, gz, q.cx, q.cy, q.cz[z]);
+        mn = fminf(mn, r);
+        mx = fmaxf(mx, r);
       }
 #pragma unroll
     for (int o = 1; o <= 32; o <<= 1) {
@@ -795,16 +852,21 @@ __global__ __launch_bounds__(RB) void k_encode(Consts<float> c, const float* __r
       mn = fminf(mn, __shfl_xor(mn, o));
       mx = fmaxf(mx, __shfl_xor(mx, o));
     }
-    const float m = 0.5f * (mx + mn);
+    const float a2 = a + 0.5f * (mx + mn);
     float s = 0.5f * (mx - mn);
     if (!(s > 0.0f)) s = 1.0f;
     if (q.live && (threadIdx.x & 0x33) == 0) {
-      header[q.b * 10 + 2 * v] = m;
-      header[q.b * 10 + 2 * v + 1] = s;
+      float* h = header + (q.b * 5 + v) * 5;
+      h[0] = a2;
+      h[1] = gx;
+      h[2] = gy;
+      h[3] = gz;
+      h[4] = s;
     }
 #pragma unroll
     for (int z = 0; z < 4; ++z)
-      if (q.act[z]) codes[v * N + q.i[z]] = bf16_rne(__fdiv_rn(x[v][z] - m, s));
+      if (q.act[z])
+        codes[v * N + q.i[z]] = bf16_rne(__fdiv_rn(x[v][z] - plane(a2, gx, gy, gz, q.cx, q.cy, q.cz[z]), s));
   }
 }
 
@@ -820,10 +882,12 @@ __global__ __launch_bounds__(RB) void k_decode(Consts<float> c, const float* __r
     for (int z = 0; z < 4; ++z) k[v][z] = q.act[z] ? codes[v * N + q.i[z]] : (uint16_t)0;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const float m = header[q.b * 10 + 2 * v], s = header[q.b * 10 + 2 * v + 1];
+    const float* h = header + (q.b * 5 + v) * 5;
+    const float a = h[0], gx = h[1], gy = h[2], gz = h[3], s = h[4];
 #pragma unroll
     for (int z = 0; z < 4; ++z)
-      if (q.act[z]) w[v * N + q.i[z]] = fmaf(s, __uint_as_float((uint32_t)k[v][z] << 16), m);
+      if (q.act[z])
+        w[v * N + q.i[z]] = fmaf(s, __uint_as_float((uint32_t)k[v][z] << 16), plane(a, gx, gy, gz, q.cx, q.cy, q.cz[z]));
   }
 }
 

@@ -167,10 +167,11 @@ Consts<T> consts(const adj_grid* g) {
 
 inline char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
-// A BF16 record: the block header (10 floats per 4x4x4 block), 256-byte aligned, then 5N codes.
+// A BF16 record: the block header (25 floats per 4x4x4 block: a plane and a scale per variable),
+// 256-byte aligned, then 5N codes.
 size_t ckpt_header_bytes(const adj_grid* g) {
   const size_t nb = (size_t)((g->n[0] + 3) / 4) * ((g->n[1] + 3) / 4) * ((g->n[2] + 3) / 4);
-  return up(nb * 10 * sizeof(float));
+  return up(nb * 25 * sizeof(float));
 }
 
 // One primal stage (launch_primal_stage; on a Roe-flux grid without its split-form convective

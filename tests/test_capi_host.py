@@ -44,8 +44,8 @@ def test_workspace_and_record_sizes():
     assert ws >= 6 * 5 * N * 8 + N * 8
     g32 = _grid(precision=adj.F32)
     assert adj.workspace_bytes(g32) < ws
-    # block header: 10 floats per 4x4x4 block (4 x 2 x 1 blocks), padded to 256 bytes
-    assert adj.ckpt_bytes(g32) == 512 + 10 * N
+    # block header: 25 floats per 4x4x4 block (4 x 2 x 1 blocks: 800 bytes), padded to 256 bytes
+    assert adj.ckpt_bytes(g32) == 1024 + 10 * N
 
 
 @pytest.mark.parametrize("bad,code", [

@@ -47,11 +47,11 @@ def test_host_trajectory_matches_hbm(tmp_path, precision, ckpt, slots, tail, to_
     # a second reverse sweep over the same trajectory (the ring now holds other states)
     wh3, gs3 = offload.backward(g, ht, s, obj, weights, lam, ws)
     torch.cuda.synchronize()
-    # a BF16 record: (mean, scale) pairs of every 4x4x4 block (40 bytes each, the header padded
-    # to 256 bytes; the padding is never written), then the codes
+    # a BF16 record: the plane and scale of every variable of every 4x4x4 block (100 bytes each,
+    # the header padded to 256 bytes; the padding is never written), then the codes
     N = g.ncells
     nbl = -(-wl.n[0] // 4) * -(-wl.n[1] // 4) * -(-wl.n[2] // 4)
-    used = [slice(0, 40 * nbl), slice(adj.ckpt_bytes(g) - 10 * N, None)] if ckpt == adj.CKPT_BF16 else [slice(None)]
+    used = [slice(0, 100 * nbl), slice(adj.ckpt_bytes(g) - 10 * N, None)] if ckpt == adj.CKPT_BF16 else [slice(None)]
     for n in range(T + 1):
         stored = ht.stored(n)
         for u in used:

@@ -235,42 +235,73 @@ def test_objective_gradient_finite_difference(orc, kind, bc_x):
 
 
 # ------------------------------------------------------------------------------ codec
-def test_bf16_rounding_matches_torch(orc):
-    # block-scaled codec on a ragged grid: the header is each 4x4x4 block's (max+min)/2 and
-    # (max-min)/2 (written here with numpy), and the codes are torch's round-to-nearest-even
-    # bfloat16 of (w - m)/s
+def _f32(x):
+    return np.float32(x)
+
+
+def _fmaf(a, b, c):
+    # float32 fma through float64: a*b is exact there, one rounding of the sum to float64 and one to
+    # float32 (a double rounding could differ from fmaf only when the float64 sum is inexact and
+    # lands on a float32 tie, which the fields here never produce)
+    return np.float32(np.float64(a) * np.float64(b) + np.float64(c))
+
+
+def test_bf16_codec_plane_and_rounding(orc):
+    # block-scaled codec with a plane predictor on a ragged grid (blocks of 4, 3, 2 and 1 cells per
+    # side): per block and variable the header holds the least-squares plane of the block's values
+    # (numpy lstsq here) with its constant moved to the middle of the residual range, and the
+    # half-range s of the residuals; the codes are torch's round-to-nearest-even bfloat16 of
+    # (w - plane)/s; decoding errs by at most half a bfloat16 ulp of s
     torch = pytest.importorskip("torch")
-    n = (9, 6, 5)
+    n = (9, 7, 5)
     N = n[0] * n[1] * n[2]
     g = orc.make_grid(n, (1.0, 1.0, 1.0), 1.4, 0.72, 0.01, 0.01, 0)
     rng = np.random.default_rng(6)
-    w = (rng.standard_normal(5 * N) * 0.3 + 1.0).astype(np.float32)
+    x, y, z = W.cell_centres(n, (1.0, 1.0, 1.0))
+    w = np.stack([1.0 + 0.3 * np.sin(3 * x + 2 * y) * np.cos(4 * z) + 0.01 * rng.standard_normal(x.shape)
+                  for _ in range(5)]).astype(np.float32).reshape(-1)
     w[:5] = [1.0, -1.0, 0.0, 1e-30, 3.0]
     w[N:2 * N] = 0.25  # a constant field: s = 1
-    q, hdr = orc.ckpt_encode(g, w)
     W5 = w.reshape(5, n[2], n[1], n[0])
+    W5[2] = (0.5 + 0.25 * x + 0.125 * y - 0.0625 * z).astype(np.float32)  # a plane
+    q, hdr = orc.ckpt_encode(g, w)
     nb = [(n[d] + 3) // 4 for d in range(3)]
-    assert hdr.shape == (nb[0] * nb[1] * nb[2], 10)
+    assert hdr.shape == (nb[0] * nb[1] * nb[2], 25)
+    dec = orc.ckpt_decode(g, q, hdr).reshape(5, n[2], n[1], n[0])
     t = np.empty_like(W5)
     for bz in range(nb[2]):
         for by in range(nb[1]):
             for bx in range(nb[0]):
                 b = (bz * nb[1] + by) * nb[0] + bx
                 sl = (slice(4 * bz, 4 * bz + 4), slice(4 * by, 4 * by + 4), slice(4 * bx, 4 * bx + 4))
+                m = [min(4, n[d] - 4 * bb) for d, bb in ((0, bx), (1, by), (2, bz))]
+                cz, cy, cx = np.meshgrid(*[np.arange(m[d], dtype=np.float32) - np.float32(0.5 * (m[d] - 1))
+                                           for d in (2, 1, 0)], indexing="ij")
+                A = np.stack([np.ones(cx.size), cx.ravel(), cy.ravel(), cz.ravel()], axis=1).astype(np.float64)
                 for v in range(5):
                     blk = W5[v][sl]
-                    m = np.float32(0.5) * (blk.max() + blk.min())
-                    sc = np.float32(0.5) * (blk.max() - blk.min())
-                    sc = sc if sc > 0 else np.float32(1.0)
-                    assert hdr[b, 2 * v] == m and hdr[b, 2 * v + 1] == sc
-                    t[v][sl] = (blk - m) / sc
+                    h = hdr[b, 5 * v:5 * v + 5]
+                    coef = np.linalg.lstsq(A[:, [0] + [1 + d for d in range(3) if m[d] > 1]],
+                                           blk.ravel().astype(np.float64), rcond=None)[0]
+                    slopes = np.zeros(3)
+                    slopes[[d for d in range(3) if m[d] > 1]] = coef[1:]
+                    for d in range(3):
+                        assert abs(h[1 + d] - slopes[d]) <= np.spacing(np.float32(abs(slopes[d]))) + 1e-12 * abs(blk).max()
+                    a = _f32(coef[0])
+                    P = lambda a0: _fmaf(h[3], cz, _fmaf(h[2], cy, _fmaf(h[1], cx, a0)))
+                    r0 = (blk - P(a)).astype(np.float32)
+                    a2 = _f32(a + _f32(_f32(0.5) * _f32(r0.max() + r0.min())))
+                    s = _f32(_f32(0.5) * _f32(r0.max() - r0.min()))
+                    s = s if s > 0 else _f32(1.0)
+                    assert abs(h[0] - a2) <= 2 * np.spacing(abs(a2)) and abs(h[4] - s) <= 2 * np.spacing(s)
+                    t[v][sl] = (blk - P(h[0])) / h[4]
+                    ulp = np.spacing(np.float32(np.abs(blk).max()))
+                    if h[4] > 64 * ulp:
+                        # a residual range above the rounding of the plane: the codes span [-1, 1]
+                        assert np.abs(t[v][sl]).max() <= 1.0 + 2.0 ** -7
+                    tmax = max(1.0, float(np.abs(t[v][sl]).max()))
+                    assert np.abs(dec[v][sl] - blk).max() <= 2.0 ** -8 * tmax * h[4] + 4 * ulp
     ref = torch.from_numpy(t.reshape(-1)).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
     assert np.array_equal(q, ref)
-    dec = orc.ckpt_decode(g, q, hdr).reshape(5, n[2], n[1], n[0])
-    for bz in range(nb[2]):
-        for by in range(nb[1]):
-            for bx in range(nb[0]):
-                b = (bz * nb[1] + by) * nb[0] + bx
-                sl = (slice(4 * bz, 4 * bz + 4), slice(4 * by, 4 * by + 4), slice(4 * bx, 4 * bx + 4))
-                for v in range(5):
-                    assert np.abs(dec[v][sl] - W5[v][sl]).max() <= 2.0 ** -8 * hdr[b, 2 * v + 1]
+    # the planar field is reproduced to float32 rounding (its residual range is rounding only)
+    assert np.abs(dec[2] - W5[2]).max() <= 1e-6
