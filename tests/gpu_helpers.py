@@ -39,3 +39,15 @@ def relerr(a, b):
     """max |a - b| / max |b| (b the oracle)."""
     den = np.abs(b).max()
     return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def relerr_vars(a, b, floor=1e-6):
+    """Largest per-variable error: max over the five fields v of max |a_v - b_v| / max |b_v|
+    (b the oracle), each field's scale floored at `floor` times the largest field's, so that a
+    field that is orders of magnitude smaller than the others is held to its own scale."""
+    a = np.asarray(a, dtype=np.float64).reshape(5, -1)
+    b = np.asarray(b, dtype=np.float64).reshape(5, -1)
+    top = np.abs(b).max()
+    if top == 0:
+        return float(np.abs(a).max())
+    return float(max(np.abs(a[v] - b[v]).max() / max(np.abs(b[v]).max(), floor * top) for v in range(5)))

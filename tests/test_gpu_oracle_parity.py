@@ -1,0 +1,191 @@
+"""Paths of the library against the FP64 oracle, not against another GPU path: the precision form
+(FP32 stencils with BF16 block-scaled checkpoint records), ensembles of boxes and lambda members,
+windows whose trajectory lives in host memory or a file, and a window on the whole 64^3
+Taylor-Green grid ("Implementation": the discrete adjoint is exact to rounding and runs over
+stored snapshots).
+
+Tolerances: FP64 paths 1e-10 relative (J, dJ/dw_0, dJ/ds in the 2-norm); FP32 stencils with
+BF16 records 1e-4 (the precision form's target); one reverse step from a BF16 record against the
+oracle's step on the oracle-decoded state, element by element per field, 1e-5 (FP32 operator
+arithmetic, the records decoded identically on both sides)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1511_06959_amd as adj
+from paper_1511_06959_amd import offload, sweep
+from paper_1511_06959_amd.ensemble import EnsembleWindow
+import workloads as W
+from tests.gpu_helpers import dev, host, relerr_vars, smooth_state
+from tests.test_gpu_ensemble import _periodic_boxes, _sources, _wall_boxes
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _oracle_window(orc, wl, s, weights, lam=0.0, T=None, obj_kind=None, plane_i=0, pt_ref=0.0):
+    og = orc.grid_from(wl.params())
+    obj = orc.make_obj(wl.obj_kind if obj_kind is None else obj_kind, plane_i, pt_ref)
+    traj = orc.primal_window(og, wl.w0, s, wl.nsteps if T is None else T)
+    J = orc.objective_window(og, obj, traj, weights)
+    wh0, gs = orc.adjoint_window(og, obj, traj, s, weights, lam)
+    return J, wh0, gs
+
+
+@pytest.fixture(scope="module")
+def c1(orc):
+    """The 16^3 Taylor-Green window (Mach 0.3, Re 100, 50 RK4 steps, mean pressure over steps
+    26..50) and its oracle J, dJ/dw_0, dJ/ds."""
+    wl = W.tgv_small()
+    return (wl,) + _oracle_window(orc, wl, wl.s, wl.weights)
+
+
+def _bf16_grid(wl):
+    return adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F32, adj.CKPT_BF16,
+                         adj.reference_state(wl.w0))
+
+
+def _report(name, errs):
+    print(f"{name}: rel err vs oracle J {errs[0]:.2e}, dJ/dw0 {errs[1]:.2e}, dJ/ds {errs[2]:.2e}", flush=True)
+
+
+def test_bf16_records_store_all_window_vs_oracle(c1):
+    wl, J, wh0, gs = c1
+    g = _bf16_grid(wl)
+    obj = adj.Objective.make(wl.obj_kind)
+    ws = adj.workspace(g)
+    s = dev(wl.s, torch.float32)
+    traj, _, Jg = sweep.forward(g, dev(g.to_stored(wl.w0), torch.float32), s, wl.nsteps, obj, wl.weights, ws)
+    whg, gsg, _ = sweep.backward(g, traj, s, obj, wl.weights, 0.0, ws)
+    errs = (abs(host(Jg)[0] - J) / abs(J), _rel(host(whg), wh0), _rel(host(gsg), gs))
+    _report("BF16 records, store-all", errs)
+    assert max(errs) <= 1e-4
+
+
+@pytest.mark.parametrize("slots", [4, 9])
+def test_bf16_revolve_window_vs_oracle(c1, slots):
+    from paper_1511_06959_amd.autograd import CheckpointedWindow, WindowSpec
+    wl, J, wh0, gs = c1
+    g = _bf16_grid(wl)
+    spec = WindowSpec(g, wl.nsteps, adj.Objective.make(wl.obj_kind), list(wl.weights), slots=slots)
+    w0 = dev(g.to_stored(wl.w0), torch.float32).requires_grad_(True)
+    st = dev(wl.s, torch.float32).requires_grad_(True)
+    Jg = CheckpointedWindow.apply(w0, st, spec)
+    Jg.backward()
+    errs = (abs(float(Jg.detach()) - J) / abs(J), _rel(host(w0.grad), wh0), _rel(host(st.grad), gs))
+    _report(f"BF16 revolve slots {slots}", errs)
+    assert spec.last["recompute_steps"] > 0
+    assert max(errs) <= 1e-4
+
+
+@pytest.mark.parametrize("lam_factor", [0.0, 0.1], ids=["lam0", "lam"])
+@pytest.mark.parametrize("bc_x", [0, 1], ids=["periodic", "walls"])
+def test_bf16_record_reverse_step_vs_oracle_on_decoded_state(orc, bc_x, lam_factor):
+    # one reverse step whose primal state comes from a BF16 record, against the oracle's step on
+    # the state the oracle's own decoder returns for the same record (the codecs agree bit for bit)
+    n = (37, 9, 6)
+    L = (2.0, 0.5, 0.4)
+    wfull = smooth_state(n, L, seed=41, wall=bc_x == 1)
+    ref = tuple(wfull.reshape(5, -1).mean(axis=1))
+    g = adj.Grid.make(n, L, 2e-3, 1e-3, bc_x=bc_x, precision=adj.F32, ckpt_format=adj.CKPT_BF16, w_ref=ref)
+    og = orc.make_grid(n, L, 1.4, 0.72, 2e-3, 1e-3, bc_x)
+    dev32 = g.to_stored(wfull).astype(np.float32)
+    rng = np.random.default_rng(42)
+    a = rng.standard_normal(wfull.size)
+    gs0 = 1e-3 * rng.standard_normal(wfull.size)
+    s = 1e-3 * rng.standard_normal(wfull.size)
+    lam = lam_factor * min(L[d] / n[d] for d in range(3)) ** 2
+    ws = adj.workspace(g)
+    rec = torch.empty(adj.ckpt_bytes(g), dtype=torch.uint8, device="cuda")
+    adj.ckpt_encode(g, dev(dev32, torch.float32), rec, ws)
+    wh = torch.empty(wfull.size, dtype=torch.float32, device="cuda")
+    gsd = dev(gs0, torch.float32)
+    oobj = orc.make_obj(W.OBJ_PT_LOSS_PLANE, 20, 1.2)
+    adj.adjoint_step(g, rec, dev(s, torch.float32), dev(a, torch.float32), wh, ws, lam=lam,
+                     obj=adj.Objective.make(W.OBJ_PT_LOSS_PLANE, 20, 1.2), c_n=0.3, grad_s=gsd)
+    q, hdr = orc.ckpt_encode(og, dev32)
+    wdec = (orc.ckpt_decode(og, q, hdr).astype(np.float64).reshape(5, -1) + np.array(ref)[:, None]).ravel()
+    gref = gs0.astype(np.float32).astype(np.float64)
+    whr = orc.adjoint_step(og, wdec, s.astype(np.float32).astype(np.float64), a.astype(np.float32).astype(np.float64),
+                           lam, oobj, 0.3, gref)
+    e1, e2 = relerr_vars(host(wh), whr), relerr_vars(host(gsd), gref)
+    print(f"BF16-record reverse step vs oracle on decoded state: w^_n {e1:.2e}, grad_s {e2:.2e}", flush=True)
+    assert e1 <= 1e-5 and e2 <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["periodic", "walls"])
+def test_ensemble_members_vs_oracle_windows(orc, case):
+    # every member of one FP64 batched sweep (uneven boxes and windows, lambda sweeps, sources on
+    # some boxes) against the oracle's window of its box with its own lambda
+    wls, windows, member_box, factors = _periodic_boxes() if case == "periodic" else _wall_boxes()
+    grids = [adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F64) for wl in wls]
+    lams = []
+    for m, b in enumerate(member_box):
+        dx = min(wls[b].L[d] / wls[b].n[d] for d in range(3))
+        lams.append(factors[m] * dx * dx)
+    s = _sources(wls, 73)
+    win = EnsembleWindow(grids, windows, [wl.w0 for wl in wls], s, member_box, lams)
+    win.forward()
+    wh0, gs = win.backward()
+    J, wh0, gs = host(win.J), host(wh0), host(gs)
+    for m, b in enumerate(member_box):
+        T = windows[b]
+        weights = W.window_weights(T, 1, T)
+        Jo, who, gso = _oracle_window(orc, wls[b], s[b], weights, lams[m], T=T, obj_kind=W.OBJ_MEAN_PRESSURE)
+        lo, hi = 5 * win.ens.offset(1, m), 5 * win.ens.offset(1, m + 1)
+        assert abs(J[m] - Jo) <= 1e-12 * abs(Jo), f"member {m}: J"
+        assert _rel(wh0[lo:hi], who) <= 1e-10, f"member {m}: w^_0"
+        assert _rel(gs[lo:hi], gso) <= 1e-10, f"member {m}: grad_s"
+
+
+@pytest.mark.parametrize("to_file", [False, True], ids=["pinned", "file"])
+def test_offloaded_window_vs_oracle(orc, tmp_path, to_file):
+    # FP64 states in pinned host memory (or a file), streamed over PCIe during the sweeps, with a
+    # source and lambda > 0, against the oracle's window
+    T = 9
+    wl = W.turbulence((12, 10, 8), mach_rms=0.3, nu=0.02, seed=31, nsteps=T)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F64)
+    s = 1e-3 * np.random.default_rng(33).standard_normal(wl.w0.size)
+    weights = W.window_weights(T, 1, T)
+    lam = 0.3 * (wl.L[0] / wl.n[0]) ** 2
+    obj = adj.Objective.make(W.OBJ_MEAN_PRESSURE)
+    ws = adj.workspace(g)
+    ht = offload.HostTrajectory(g, T, slots=2, device_tail=2, path=str(tmp_path / "t.bin") if to_file else None)
+    ht, _, Jg = offload.forward(g, dev(wl.w0), dev(s), T, obj, weights, ws, traj=ht)
+    whg, gsg = offload.backward(g, ht, dev(s), obj, weights, lam, ws)
+    Jg, whg, gsg = host(Jg)[0], host(whg), host(gsg)
+    ht.close()
+    Jo, who, gso = _oracle_window(orc, wl, s, weights, lam, T=T, obj_kind=W.OBJ_MEAN_PRESSURE)
+    assert abs(Jg - Jo) <= 1e-12 * abs(Jo)
+    assert _rel(whg, who) <= 1e-10
+    assert _rel(gsg, gso) <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def tgv64_oracle(orc):
+    """The first 20 steps of the 64^3 Taylor-Green window (Mach 0.1, Re 1600, time-averaged
+    viscous dissipation over steps 1..20, body force) on the oracle."""
+    T = 20
+    wl = W.tgv_64(nsteps=T)
+    weights = W.window_weights(T, 1, T)
+    return (wl, T, weights) + _oracle_window(orc, wl, wl.s, weights, T=T)
+
+
+@pytest.mark.parametrize("precision", [adj.F64, adj.F32], ids=["f64", "f32"])
+def test_tgv64_window_sample_vs_oracle(tgv64_oracle, precision):
+    wl, T, weights, J, wh0, gs = tgv64_oracle
+    ref = adj.reference_state(wl.w0) if precision == adj.F32 else None
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision, w_ref=ref)
+    obj = adj.Objective.make(wl.obj_kind)
+    ws = adj.workspace(g)
+    s = dev(wl.s, g.dtype)
+    traj, _, Jg = sweep.forward(g, dev(g.to_stored(wl.w0), g.dtype), s, T, obj, weights, ws)
+    whg, gsg, _ = sweep.backward(g, traj, s, obj, weights, 0.0, ws)
+    errs = (abs(host(Jg)[0] - J) / abs(J), _rel(host(whg), wh0), _rel(host(gsg), gs))
+    _report(f"64^3 Taylor-Green, {T} steps, {'FP64' if precision == adj.F64 else 'FP32'}", errs)
+    assert max(errs) <= (1e-10 if precision == adj.F64 else 1e-4)

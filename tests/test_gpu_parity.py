@@ -14,7 +14,7 @@ import torch
 
 import paper_1511_06959_amd as adj
 import workloads as W
-from tests.gpu_helpers import dev, grids, host, relerr, smooth_state
+from tests.gpu_helpers import dev, grids, host, relerr, relerr_vars, smooth_state
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +35,10 @@ def test_residual_parity_f64(orc, shape, bc_x):
     s = 1e-2 * np.random.default_rng(1).standard_normal(w.size)
     R = torch.empty(w.size, dtype=torch.float64, device="cuda")
     adj.residual(g, dev(w), dev(s), R)
-    assert relerr(host(R), orc.residual(og, w, s)) <= 1e-13
+    ref = orc.residual(og, w, s)
+    assert relerr(host(R), ref) <= 1e-13
+    # each field against its own scale too (fields far smaller than the largest are held to theirs)
+    assert relerr_vars(host(R), ref) <= 1e-11
 
 
 @pytest.mark.parametrize("shape,bc_x", SHAPES, ids=IDS)
@@ -51,6 +54,7 @@ def test_vjp_parity_f64(orc, shape, bc_x, with_nu):
     if with_nu:
         ref = ref + orc.lnu_apply(og, nu, kh)
     assert relerr(host(out), ref) <= 1e-13
+    assert relerr_vars(host(out), ref) <= 1e-11
 
 
 @pytest.mark.parametrize("shape,bc_x", SHAPES, ids=IDS)
@@ -63,6 +67,7 @@ def test_primal_step_parity_f64(orc, shape, bc_x):
     ref = orc.primal_step(og, w, s)
     # compare the increment, which is what the step computes on top of w
     assert relerr(host(out) - w, ref - w) <= 1e-12
+    assert relerr_vars(host(out) - w, ref - w) <= 1e-10
 
 
 OBJS = [(W.OBJ_NONE, 0), (W.OBJ_MEAN_PRESSURE, 0), (W.OBJ_KE_DISSIPATION, 0), (W.OBJ_PT_LOSS_PLANE, 0),
@@ -88,6 +93,8 @@ def test_adjoint_step_parity_f64(orc, kind, bc_x, lam):
     ref = orc.adjoint_step(og, w, s, a, lam, oobj, 0.37, gref)
     assert relerr(host(wh) - a, ref - a) <= 1e-12
     assert relerr(host(gs) - gs0, gref - gs0) <= 1e-12
+    assert relerr_vars(host(wh) - a, ref - a) <= 1e-10
+    assert relerr_vars(host(gs) - gs0, gref - gs0) <= 1e-10
 
 
 @pytest.mark.parametrize("shape,bc_x", SHAPES, ids=IDS)
