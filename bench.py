@@ -1,24 +1,29 @@
 #!/usr/bin/env python3
 """Throughput of the stabilised discrete unsteady adjoint on one MI355X.
 
-Workload (the GPU configuration of the plain method, FP32 and FP64): 64^3 periodic Taylor-Green
-vortex, Mach 0.1, Re 1600, 1000 RK4 steps forward storing every state in HBM, then the full
-reverse sweep (stage recomputation, transposed convective + viscous operator, objective
-injection, body-force sensitivity), lambda = 0; objective = time-averaged volume-mean viscous
-dissipation; gradient with respect to a 5 x 64^3 body-force field (seeded N(0, 1e-4^2), zero
-mean).  Synthetic data (seeded), inputs resident in HBM before the timed region.
+Default workload (the large single case with autograd): 384^3 periodic decaying turbulence
+(E(k) ~ k^4 exp(-2k^2/k0^2), k0 = 4, Mach_rms 0.4, nu = 2.887e-3), the window of 5000 RK4 steps
+reversed with checkpointing sized to the free HBM, the snapshots BF16 records (block-scaled,
+plane-predicted), lambda = 0.1 dx^2 sigma_1, objective the time-averaged volume-mean pressure,
+gradient with respect to a 5 x 384^3 body force (base 0), FP32 stencils, FP64 reductions.
+Synthetic data (seeded), inputs resident in HBM before the timed region.  The plan that fits is
+two-level: a snapshot every ~28 steps, and in the reverse sweep one segment at a time re-advanced
+from its snapshot with every state and stage state kept, then reversed without recomputation.
 
-One benchmark step = one whole window (forward sweep + reverse sweep).  `value` is the
-whole-job rate in adjoint cell-steps per second: cells x window steps / seconds per window, on
-the FP32 path.  The FP64 path is timed the same way and reported beside it, together with the
-FP32-vs-FP64 relative error of J, dJ/dw_0 and dJ/ds (the FP64 path matches the FP64 oracle to
-1e-10 in the test suite).
+One benchmark step = one time step of that plan: its primal step, its re-advance (with the stage
+states kept) and its reverse step (sigma_1, the four transposed stages, objective injection,
+body-force gradient), with the snapshot encodings and decodings of the window.  `--steps K` times
+one K-step window of the same schedule (one segment); `value` = cells x K / seconds of that
+window (adjoint cell-steps/s).  The FP64 path (FP64 snapshots; the two-level plan does not fit,
+so binomial checkpointing whose sample window recomputes no less per time step than the plan) is
+timed the same way and reported beside it, with the FP32/BF16 error against it, and the 16^3
+Taylor-Green window of every path is checked against the FP64 oracle.
 
-Launch: the timed windows replay the forward and reverse sweeps as two captured HIP graphs.
-Roofline: the dominant kernel is the reverse-stage gather.  Its average launch duration is
-measured with HIP events recorded on its own stream around every launch of `--steps` eager
-(uncaptured) windows timed just before; `achieved` = algorithmic bytes per launch / that
-duration, against 8 TB/s.
+Roofline: each kernel class's average launch duration is measured with the dispatch's own HIP
+events (hipExtLaunchKernel) over a second, profiled run of the same window; `achieved` =
+algorithmic bytes per launch (the hot-path byte counts per adjoint or primal cell-step, a
+quarter of them per stage launch) / that duration, against 8 TB/s; `roofline_valu` sets the
+same launches against the vector ALU.  Other workloads: --workload (see WORKLOADS).
 """
 import argparse
 import hashlib
@@ -34,8 +39,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ROE_DELTA = 0.1  # Roe flux option: |lam| smoothed within 0.1 c~ of zero
-VALU_PEAK_TFLOPS = 157.3  # FP32 vector, 256 CUs x 2.4 GHz x 256 operations per clock
+# FP32 vector peaks: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s without packed
+# FP32 instructions (this library is built without them), 157.3 TFLOP/s with them
+VALU_PEAK_TFLOPS = 78.6
+VALU_PEAK_PACKED_TFLOPS = 157.3
 METRIC = "adjoint cell-steps/s + % HBM roofline, FP32/BF16-ckpt vs FP64 at stated rel err"
+# Algorithmic bytes per cell-step (what the method must move): an adjoint step reads the stored
+# snapshot, reads w^_{n+1}, writes w^_n and updates grad_s; a primal step reads w_n, writes w_{n+1}
+# and writes the snapshot.  A stage launch does a quarter of a step.
+ALG_BYTES = {"adjoint": {"f32": 90.0, "f64": 200.0}, "primal": {"f32": 50.0, "f64": 120.0}}
+PLAN_STEPS = 5000  # the configured window of the 384^3 case
 
 # Algorithmic values moved per cell by the four reverse-stage launches of one adjoint step
 # (stage 4: W, a in, g4 out = 15; stages 3 and 2: W, a, g_next in, g out = 20 each;
@@ -69,8 +82,9 @@ def profile_values(name, kernel_src_hash, tile):
 
 
 def valu_roofline(valu, cells, avg_us):
-    """A reverse kernel against the vector ALU: FP32 operations it issues per launch (committed
-    SQ counter summary) / its live average launch duration, against 157.3 TFLOP/s;
+    """A kernel against the vector ALU: FP32 operations it issues per launch (committed SQ counter
+    summary) / its live average launch duration, against 78.6 TFLOP/s (FP32 without packed
+    instructions; 157.3 with them is stated beside it);
     issue_frac = wave-level VALU instructions x 4 cycles (a wave64 instruction on a 16-lane SIMD)
     / (1024 SIMDs x 2.4 GHz x duration)."""
     if valu is None:
@@ -79,7 +93,8 @@ def valu_roofline(valu, cells, avg_us):
     flops = float(valu["fp32_ops_per_cell_launch_f32"]) * cells
     insts = float(valu["valu_insts_per_cell_launch_f32"]) * cells
     return {"bound": "alu", "achieved": flops / s / 1e12, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": flops / s / 1e12 / VALU_PEAK_TFLOPS, "issue_frac": insts * 4.0 / (1024 * 2.4e9 * s),
+            "frac": flops / s / 1e12 / VALU_PEAK_TFLOPS, "peak_packed_fp32": VALU_PEAK_PACKED_TFLOPS,
+            "issue_frac": insts * 4.0 / (1024 * 2.4e9 * s),
             "fp32_ops_per_launch": flops, "valu_insts_per_launch": insts}
 
 
@@ -343,11 +358,362 @@ def cpu_baseline(wl, budget_s, flux=0):
     }
 
 
+# ---------------------------------------------------------------------------------------------
+# The 384^3 case: a window reversed with binomial checkpointing
+# ---------------------------------------------------------------------------------------------
+def window_slots(K, ratio):
+    """Largest slot count whose K-step binomial schedule advances at least `ratio` primal steps per
+    time step (first sweep included), so that the sample window recomputes no less than the plan."""
+    from paper_1511_06959_amd import revolve
+    best = 1
+    for s_ in range(1, K + 2):
+        if (revolve.min_advances(K, s_) + 1) / K >= ratio - 1e-12:
+            best = s_
+    return best
+
+
+def plan_for(g, plan_steps, budget_bytes):
+    """Checkpointing plan of the plan_steps window within budget_bytes of HBM (sweep.plan_window)
+    and the primal steps it advances per time step."""
+    from paper_1511_06959_amd import revolve, sweep
+    kind, size = sweep.plan_window(g, plan_steps, budget_bytes)
+    rec = sweep.snapshot_bytes(g)
+    if kind == "segments":
+        return {"schedule": "segments", "segment": size, "snapshots": -(-plan_steps // size), "record_bytes": rec,
+                "hbm_gb": sweep.segment_bytes(g, plan_steps, size) / 1e9, "advances_per_step": 2.0,
+                "stage_recomputes_per_step": 0}
+    adv = revolve.min_advances(plan_steps, size) + 1
+    return {"schedule": "binomial", "slots": size, "record_bytes": rec, "hbm_gb": size * rec / 1e9,
+            "advances": adv, "advances_per_step": adv / plan_steps, "stage_recomputes_per_step": 3}
+
+
+PROF_CLASSES = (("adjoint_stage", 0), ("primal_stage", 1), ("sigma1", 2), ("objective", 3), ("codec", 4),
+                ("reduce", 5))
+
+
+def run_plan(wl, precision, K, warmup, tune=True, bf16=True):
+    """K-step window of the 384^3 plan on the GPU, in the schedule the plan picks for the free HBM
+    (segments of the plan's length, or binomial slots that recompute no less per time step than
+    the plan does): timed once, then run again with per-kernel event timing.  Returns timings,
+    the plan, per-kernel durations and the results."""
+    import torch
+
+    import paper_1511_06959_amd as adj
+    from paper_1511_06959_amd import autotune
+    from paper_1511_06959_amd.sweep import RevolveSweep, SegmentSweep
+    import workloads as W
+
+    f32 = precision == adj.F32
+    ref = adj.reference_state(wl.w0) if f32 else None
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision,
+                      adj.CKPT_BF16 if (f32 and bf16) else adj.CKPT_NATIVE, ref)
+    tiles = _tile_report(autotune.tune(g), g, wl.lam > 0.0) if tune else {}
+    obj = adj.Objective.make(wl.obj_kind)
+    w0 = torch.from_numpy(g.to_stored(wl.w0)).to("cuda", g.dtype)
+    ws = adj.workspace(g)
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    # besides the checkpoints, the window's working states, adjoints and a margin stay free
+    plan = plan_for(g, PLAN_STEPS, max(0, free - 6 * 5 * g.ncells * g.dtype.itemsize - (4 << 30)))
+
+    def sweep_of(steps, wts):
+        if plan["schedule"] == "segments":
+            return SegmentSweep(g, steps, min(steps, plan["segment"]), None, obj, wts, wl.lam, ws)
+        return RevolveSweep(g, steps, window_slots(steps, plan["advances_per_step"]), None, obj, wts, wl.lam, ws)
+
+    def window(steps):
+        sw = sweep_of(steps, W.window_weights(steps, 1, steps))
+        J = sw.forward(w0)
+        wh0, gs = sw.backward()
+        return sw, J, wh0, gs
+
+    out = {"plan": plan, "tiles": tiles}
+    if warmup > 0:
+        window(warmup)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    sw, J, wh0, gs = window(K)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    out["window"] = ({"schedule": "segments", "segment": sw.seg, "snapshots": sw.nsnap} if plan["schedule"] == "segments"
+                     else {"schedule": "binomial", "slots": sw.slots})
+    out["ms_per_step"] = sec * 1e3 / K
+    out["value"] = g.ncells * K / sec
+    out["advances"] = sw.advanced
+    out["J"] = float(J.cpu()[0])
+    out["wh0"] = wh0.double().cpu().numpy()
+    out["grad_s"] = gs.double().cpu().numpy()
+    del sw, wh0, gs
+    torch.cuda.empty_cache()
+    # the same window with every launch timed by its own dispatch events
+    adj.profile_enable(True)
+    window(K)
+    torch.cuda.synchronize()
+    adj.profile_enable(False)
+    out["prof"] = {name: adj.profile_read(cls) for name, cls in PROF_CLASSES}
+    out["cells"] = g.ncells
+    del ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def kernel_roofline(kind, prec, cells, ms, n):
+    """HBM roofline of one stage-kernel class: algorithmic bytes per launch (a quarter of the
+    per-cell-step bytes, times the cells) / mean launch duration."""
+    avg_s = ms / n / 1e3
+    alg = ALG_BYTES[kind][prec] / 4.0 * cells
+    return {"bound": "hbm", "achieved": alg / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": alg / avg_s / 1e9 / HBM_PEAK_GBS, "avg_launch_us": avg_s * 1e6, "launches": n,
+            "alg_bytes_per_launch": alg, "alg_bytes_per_cell_step": ALG_BYTES[kind][prec]}
+
+
+def c1_vs_oracle():
+    """The 16^3 Taylor-Green window (50 steps, mean pressure over steps 26..50) of every path on
+    the GPU against the FP64 oracle's window: relative errors of J, dJ/dw_0 and dJ/ds."""
+    import torch
+
+    import oracle
+    import paper_1511_06959_amd as adj
+    from paper_1511_06959_amd import sweep
+    from paper_1511_06959_amd.sweep import RevolveSweep
+    import workloads as W
+
+    wl = W.tgv_small()
+    og = oracle.grid_from(wl.params())
+    oobj = oracle.make_obj(wl.obj_kind)
+    traj = oracle.primal_window(og, wl.w0, wl.s, wl.nsteps)
+    J = oracle.objective_window(og, oobj, traj, wl.weights)
+    wh0, gs = oracle.adjoint_window(og, oobj, traj, wl.s, wl.weights)
+    ref = adj.reference_state(wl.w0)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out = {}
+    for name, prec, ck, slots in (("f64", adj.F64, adj.CKPT_NATIVE, None), ("f32", adj.F32, adj.CKPT_NATIVE, None),
+                                  ("f32_bf16_records", adj.F32, adj.CKPT_BF16, None),
+                                  ("f32_bf16_revolve_4_slots", adj.F32, adj.CKPT_BF16, 4)):
+        g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, prec, ck,
+                          ref if prec == adj.F32 else None)
+        obj = adj.Objective.make(wl.obj_kind)
+        ws = adj.workspace(g)
+        w0 = torch.from_numpy(g.to_stored(wl.w0)).to("cuda", g.dtype)
+        s = torch.from_numpy(wl.s).to("cuda", g.dtype)
+        if slots is None:
+            tr, _, Jg = sweep.forward(g, w0, s, wl.nsteps, obj, wl.weights, ws)
+            whg, gsg, _ = sweep.backward(g, tr, s, obj, wl.weights, 0.0, ws)
+        else:
+            sw = RevolveSweep(g, wl.nsteps, slots, s, obj, wl.weights, 0.0, ws)
+            Jg = sw.forward(w0)
+            whg, gsg = sw.backward()
+        out[name] = {"J": abs(float(Jg.cpu()[0]) - J) / abs(J), "dJ_dw0": rel(whg.double().cpu().numpy(), wh0),
+                     "dJ_ds": rel(gsg.double().cpu().numpy(), gs)}
+    out["workload"] = ("Taylor-Green vortex 16^3, Mach 0.3, Re 100, 50 RK4 steps, mean pressure averaged over "
+                       "steps 26..50, lambda 0; GPU windows against the FP64 oracle's")
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline_block(wl, n, budget_s, threads=None):
+    """The FP64 oracle as it stands on the host cores: primal + reverse steps (lambda and objective
+    of the workload) of an n^3 block cut from the workload's initial field and treated as periodic,
+    with its cell size, viscosity and dt, repeated for about budget_s seconds.  threads: OpenMP
+    threads (None: all)."""
+    import oracle
+
+    N = wl.n
+    w = wl.w0.reshape(5, N[2], N[1], N[0])[:, :n, :n, :n].copy().reshape(-1)
+    p = wl.params()
+    p["n"] = (n, n, n)
+    p["L"] = tuple(wl.L[d] / wl.n[d] * n for d in range(3))
+    og = oracle.grid_from(p)
+    obj = oracle.make_obj(wl.obj_kind)
+    prev = oracle.num_threads()
+    if threads is not None:
+        oracle.set_num_threads(threads)
+    used = oracle.num_threads()
+    a = np.random.default_rng(0).standard_normal(w.size) * 1e-3
+    gs = np.zeros_like(w)
+    steps, t_pr, t_ad = 0, 0.0, 0.0
+    t_start = time.perf_counter()
+    try:
+        while True:
+            t0 = time.perf_counter()
+            wn = oracle.primal_step(og, w)
+            t1 = time.perf_counter()
+            a = oracle.adjoint_step(og, w, None, a, wl.lam, obj, 1.0 / PLAN_STEPS, gs)
+            t2 = time.perf_counter()
+            t_pr += t1 - t0
+            t_ad += t2 - t1
+            w = wn
+            steps += 1
+            if time.perf_counter() - t_start >= budget_s:
+                break
+    finally:
+        oracle.set_num_threads(prev)
+    cells = n ** 3
+    return {"value": cells * steps / (t_pr + t_ad), "threads": used, "steps": steps, "seconds": t_pr + t_ad,
+            "primal_cell_steps_per_s": cells * steps / t_pr, "adjoint_cell_steps_per_s": cells * steps / t_ad}
+
+
+def schedule_text(r, K):
+    p, w = r["plan"], r["window"]
+    if p["schedule"] == "segments":
+        return (f"two-level checkpointing: the {PLAN_STEPS}-step plan keeps {p['snapshots']} snapshots, one every "
+                f"{p['segment']} steps, and re-advances one segment at a time with its stage states kept "
+                f"({p['hbm_gb']:.0f} GB of HBM): 2 primal steps and no stage recomputation per time step; the timed "
+                f"{K}-step window is one segment ({w['snapshots']} snapshot) of the same schedule")
+    return (f"binomial checkpointing: the {PLAN_STEPS}-step plan fits {p['slots']} snapshot slots ({p['hbm_gb']:.0f} "
+            f"GB) and advances {p['advances_per_step']:.3f} primal steps per time step, plus 3 stage evaluations in "
+            f"each reverse step; the timed {K}-step window uses {w['slots']} slots and advances "
+            f"{r['advances'] / K:.3f}")
+
+
+def main_c5(args):
+    import torch
+
+    import paper_1511_06959_amd as adj
+    import workloads as W
+
+    K, Wm = args.steps, args.warmup
+    print("[bench] generating the 384^3 turbulence field", file=sys.stderr, flush=True)
+    wl = W.turb_384(nsteps=PLAN_STEPS, lam_factor=0.1)
+    print(f"[bench] workload {wl.name}: {wl.n} cells, plan {PLAN_STEPS} steps, dt {wl.dt:.4e}, lambda {wl.lam:.3e}",
+          file=sys.stderr, flush=True)
+    r32 = run_plan(wl, adj.F32, K, Wm, not args.no_autotune, bf16=True)
+    print(f"[bench] f32/bf16 window {r32['ms_per_step']:.2f} ms per step, window {r32['window']}, plan "
+          f"{r32['plan']}", file=sys.stderr, flush=True)
+    r64 = None
+    if not args.no_f64:
+        r64 = run_plan(wl, adj.F64, K, Wm, not args.no_autotune)
+        print(f"[bench] f64 window {r64['ms_per_step']:.2f} ms per step", file=sys.stderr, flush=True)
+    cells = wl.ncells
+
+    def rooflines(r, prec):
+        out = {}
+        for name, kind in (("adjoint_stage", "adjoint"), ("primal_stage", "primal")):
+            ms, n = r["prof"][name]
+            out[name] = kernel_roofline(kind, prec, cells, ms, n)
+        return out
+
+    roofs = rooflines(r32, "f32")
+    dom = max(("adjoint_stage", "primal_stage"), key=lambda k: r32["prof"][k][0])
+    kname = {"adjoint_stage": "k_adjoint_stage", "primal_stage": "k_primal_stage"}[dom]
+    khash = kernel_hash()
+    tile = r32["tiles"].get(dom, {}).get("launched")
+    traffic = profile_values(f"traffic_{dom}_turb384.txt", khash, tile)
+    valu = profile_values(f"valu_{dom}_turb384.txt", khash, tile)
+    roof = dict(roofs[dom])
+    roof["kernel"] = kname
+    roof["traffic"] = None if traffic is None else float(traffic["bytes_per_cell_launch_f32"]) * cells
+    roof["traffic_profile"] = None if traffic is None else "profiles/" + traffic["profile"]
+    roof_valu = valu_roofline(valu, cells, roof["avg_launch_us"])
+    if roof_valu is not None:
+        roof_valu["profile"] = "profiles/" + valu["profile"]
+        roof_valu["kernel"] = kname
+    kms = {k: v[0] / K for k, v in r32["prof"].items()}
+    line = {
+        "metric": METRIC,
+        "value": r32["value"],
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOADS["turb384"],
+            "cells": cells,
+            "plan_steps": PLAN_STEPS,
+            "dt": wl.dt,
+            "lambda": wl.lam,
+            "step": "one time step of the plan: primal step with snapshot encoding, its share of the binomial "
+                    "recomputation, reverse step (decode, stage recomputation, sigma_1, four transposed stages, "
+                    "objective injection, body-force gradient)",
+            "schedule": schedule_text(r32, K),
+            "plan": r32["plan"],
+            "window": r32["window"],
+            "checkpoints": "BF16 snapshot records (per 4x4x4 block and variable a least-squares plane and the BF16 "
+                           "residual); the segment being reversed in native FP32 states and stage states",
+            "source": "body force s = 0 (the base of the gradient), so primal stages skip reading it",
+        },
+        "roofline": roof,
+        "roofline_valu": roof_valu,
+        "roofline_by_kernel": roofs,
+        "hbm_per_time_step": {"alg_bytes_per_cell_step": ALG_BYTES["adjoint"]["f32"] + ALG_BYTES["primal"]["f32"],
+                              "achieved": (ALG_BYTES["adjoint"]["f32"] + ALG_BYTES["primal"]["f32"]) * r32["value"] / 1e9,
+                              "unit": "GB/s",
+                              "frac": (ALG_BYTES["adjoint"]["f32"] + ALG_BYTES["primal"]["f32"]) * r32["value"] / 1e9
+                              / HBM_PEAK_GBS},
+        "kernel_ms_per_step": kms,
+        "primal_steps_per_time_step": r32["advances"] / K,
+        "launch": "eager launches on one stream (each 384^3 launch runs for milliseconds)",
+        "tiles": r32["tiles"],
+    }
+    if r64 is not None:
+        r64roofs = rooflines(r64, "f64")
+        line["f64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "plan": r64["plan"],
+                       "window": r64["window"], "schedule": schedule_text(r64, K),
+                       "primal_steps_per_time_step": r64["advances"] / K,
+                       "roofline_by_kernel": r64roofs, "kernel_ms_per_step": {k: v[0] / K for k, v in r64["prof"].items()},
+                       "tiles": r64["tiles"]}
+        line["f32_speedup_over_f64"] = r32["value"] / r64["value"]
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        line["rel_err_f32_bf16_vs_gpu_f64"] = {
+            "J": abs(r32["J"] - r64["J"]) / abs(r64["J"]), "dJ_dw0": rel(r32["wh0"], r64["wh0"]),
+            "dJ_ds": rel(r32["grad_s"], r64["grad_s"]),
+            "note": f"the timed {K}-step 384^3 window, lambda 0.1 dx^2 sigma_1; the FP64 path is pinned to the FP64 "
+                    "oracle (rel_err_vs_oracle and the test suite), which cannot run 384^3 windows"}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"], line["rel_err_vs_oracle"] = cpu_baseline_leg(wl, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_leg(wl, seconds):
+    """The oracle's leg of the benchmark (the only part of it that runs the oracle): the oracle's
+    own rate on the host cores, all of them and one, and the 16^3 windows of every GPU path
+    checked against the oracle's window."""
+    print("[bench] 16^3 windows against the oracle", file=sys.stderr, flush=True)
+    rel = c1_vs_oracle()
+    print("[bench] oracle on the host cores", file=sys.stderr, flush=True)
+    allc = cpu_baseline_block(wl, 48, seconds)
+    one = cpu_baseline_block(wl, 24, seconds / 2, threads=1)
+    cpu = {
+        "value": allc["value"], "unit": "cell-steps/s", "cores": allc["threads"], "kind": "oracle",
+        "sample": (f"{allc['steps']} primal + {allc['steps']} reverse FP64 steps (lambda 0.1 dx^2 sigma_1, mean "
+                   f"pressure) of a 48^3 block cut from the 384^3 field, periodic, {allc['seconds']:.1f} s on "
+                   f"{allc['threads']} OpenMP threads; rate = cells x steps / (primal + reverse time), no "
+                   "checkpointing recomputation"),
+        "cpu_model": cpu_model(),
+        "primal_cell_steps_per_s": allc["primal_cell_steps_per_s"],
+        "adjoint_cell_steps_per_s": allc["adjoint_cell_steps_per_s"],
+        "single_thread": {"value": one["value"], "threads": 1, "steps": one["steps"],
+                          "sample": f"24^3 block, {one['steps']} primal + reverse steps, {one['seconds']:.1f} s",
+                          "primal_cell_steps_per_s": one["primal_cell_steps_per_s"],
+                          "adjoint_cell_steps_per_s": one["adjoint_cell_steps_per_s"]},
+    }
+    return cpu, rel
+
+
 WORKLOADS = {
     "tgv64": "Taylor-Green vortex 64^3 periodic, Mach 0.1, Re 1600, {n} RK4 steps forward + full adjoint sweep, "
              "lambda 0, objective time-averaged viscous dissipation, gradient wrt a 5x64^3 body force",
-    "turb384": "decaying turbulence 384^3 periodic (k^4 exp(-2k^2/k0^2), k0 4, Mach_rms 0.4, nu 2.887e-3), "
-               "{n}-step window sample of the 5000-step case, lambda 0.1 dx^2 sigma_1, mean pressure",
+    "turb384": "decaying turbulence 384^3 periodic (k^4 exp(-2k^2/k0^2), k0 4, Mach_rms 0.4, nu 2.887e-3), 5000 "
+               "RK4 steps reversed with checkpointing sized to the free HBM (BF16 snapshots), lambda 0.1 dx^2 "
+               "sigma_1, time-averaged mean pressure, gradient wrt a 5x384^3 body force",
+    "turb384_sample": "decaying turbulence 384^3 periodic (k^4 exp(-2k^2/k0^2), k0 4, Mach_rms 0.4, nu 2.887e-3), "
+                      "{n}-step store-all window sample of the 5000-step case, lambda 0.1 dx^2 sigma_1, mean pressure",
     "wake": "temporally developing wake 512x256x32 (slip walls in x, free stream Mach 0.85, centre 0.5, Re 5e4), "
             "{n}-step window sample of the 4000-step case, lambda 0.1 dx^2 sigma_1, stagnation-pressure loss",
     "ensemble": "batched ensemble of 64 periodic decaying-turbulence boxes (sizes from {32,48,64,96}^3, Mach_rms "
@@ -371,7 +737,7 @@ def make_workload(name, window):
     import workloads as W
     if name == "tgv64":
         return W.tgv_64(nsteps=window or 1000)
-    if name == "turb384":
+    if name == "turb384_sample":
         return W.turb_384(nsteps=window or 10, lam_factor=0.1)
     if name == "wake":
         return W.wake(nsteps=window or 20, lam_factor=0.1)
@@ -383,9 +749,10 @@ def make_workload(name, window):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3, help="timed windows")
-    ap.add_argument("--warmup", type=int, default=1, help="untimed windows before the timed ones")
-    ap.add_argument("--workload", default="tgv64", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed steps: time steps of the 384^3 plan (default workload), windows otherwise")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps (windows) before the timed ones")
+    ap.add_argument("--workload", default="turb384", choices=sorted(WORKLOADS))
     ap.add_argument("--window", type=int, default=0, help="RK4 steps per window (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -415,6 +782,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     adj.lib()
+    if args.workload == "turb384":
+        main_c5(args)
+        return
     if args.workload == "ensemble":
         main_ensemble(args)
         return
@@ -687,7 +1057,7 @@ def main_offload(args):
     import workloads as W
     from paper_1511_06959_amd import autotune, offload, sweep
 
-    wl = make_workload("turb384", args.window)
+    wl = make_workload("turb384_sample", args.window)
     T = wl.nsteps
     g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F32, adj.CKPT_BF16,
                       adj.reference_state(wl.w0))

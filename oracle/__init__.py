@@ -94,12 +94,19 @@ def lib():
         L.orc_matrix_sigma1.restype = ctypes.c_double
         L.orc_ckpt_blocks.restype = ctypes.c_long
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """OpenMP threads of the following oracle calls; returns the count in force."""
+    return lib().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------------------------

@@ -832,6 +832,14 @@ extern "C" {
 
 int orc_num_threads(void) { return nthreads(); }
 
+// OpenMP threads of the following calls (timing on one core or all of them)
+int orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#endif
+  return nthreads();
+}
+
 static int check(const orc_grid* g) {
   if (!g) return -1;
   for (int d = 0; d < 3; ++d)

@@ -9,8 +9,12 @@ computed by the HIP kernels behind the C ABI.
   ObjectiveValue.apply(w, spec)         -> j(w) (FP64)   backward: adj_objective_and_grad
   CheckpointedWindow.apply(w0, s, spec) -> J = sum_n c_n j(w_n)   backward: revolve schedule
 
-``spec`` (a WindowSpec) carries the grid, objective, weights, lambda and slot budget.  With
-lambda > 0 the backward is the paper's stabilised adjoint, deliberately not the exact gradient.
+``spec`` (a WindowSpec) carries the grid, objective, weights, lambda and the checkpointing plan:
+``schedule = "binomial"`` (revolve with ``slots`` snapshot slots), ``"segments"`` (snapshots every
+``segment`` steps, each segment re-advanced with its stage states kept, sweep.SegmentSweep) or
+``"auto"`` (the default: the plan that sweep.plan_window picks for the free HBM less
+``reserve_bytes``; slots or segment given explicitly take precedence).  With lambda > 0 the
+backward is the paper's stabilised adjoint, deliberately not the exact gradient.
 """
 from dataclasses import dataclass, field
 from typing import Optional
@@ -18,7 +22,7 @@ from typing import Optional
 import torch
 
 from . import Grid, Objective, adjoint_step, objective_and_grad, primal_step, workspace
-from .sweep import RevolveSweep
+from .sweep import RevolveSweep, SegmentSweep, binomial_slots, plan_window, segment_length
 
 
 @dataclass(eq=False)
@@ -28,14 +32,31 @@ class WindowSpec:
     obj: Optional[Objective] = None
     weights: Optional[list] = None
     lam: float = 0.0
-    slots: int = 2
+    slots: Optional[int] = None
     ws: Optional[torch.Tensor] = None
-    last: dict = field(default_factory=dict)  # diagnostics of the last backward (advances etc.)
+    last: dict = field(default_factory=dict)  # diagnostics of the last backward (plan, advances)
+    schedule: str = "auto"
+    segment: Optional[int] = None
+    reserve_bytes: int = 8 << 30  # HBM left free beside the checkpoints (auto plans)
 
     def workspace(self):
         if self.ws is None:
             self.ws = workspace(self.g)
         return self.ws
+
+    def plan(self, device):
+        """(schedule, size): ("binomial", slots) or ("segments", segment length)."""
+        if self.slots is not None and self.schedule in ("auto", "binomial"):
+            return "binomial", int(self.slots)
+        if self.segment is not None and self.schedule in ("auto", "segments"):
+            return "segments", int(self.segment)
+        free, _ = torch.cuda.mem_get_info(device)
+        budget = max(0, free - self.reserve_bytes)
+        if self.schedule == "binomial":
+            return "binomial", binomial_slots(self.g, self.nsteps, budget)
+        if self.schedule == "segments":
+            return "segments", segment_length(self.g, self.nsteps)
+        return plan_window(self.g, self.nsteps, budget)
 
 
 def _zero_if_none(t, like):
@@ -86,18 +107,21 @@ class ObjectiveValue(torch.autograd.Function):
 
 
 class CheckpointedWindow(torch.autograd.Function):
-    """J = sum_n c_n j(w_n) over nsteps RK4 steps from w0, with binomial checkpointing in
-    spec.slots snapshot slots (BF16 records when spec.g.ckpt_format says so)."""
+    """J = sum_n c_n j(w_n) over nsteps RK4 steps from w0 with the checkpointing plan of spec
+    (snapshots as BF16 records when spec.g.ckpt_format says so)."""
 
     @staticmethod
     def forward(ctx, w0, s, spec):
-        sweep = RevolveSweep(spec.g, spec.nsteps, spec.slots, None if s is None else s.contiguous(), spec.obj,
-                             spec.weights, spec.lam, spec.workspace(), w0.device)
+        kind, size = spec.plan(w0.device)
+        cls = RevolveSweep if kind == "binomial" else SegmentSweep
+        sweep = cls(spec.g, spec.nsteps, size, None if s is None else s.contiguous(), spec.obj, spec.weights,
+                    spec.lam, spec.workspace(), w0.device)
         J = sweep.forward(w0.contiguous())
         ctx.sweep = sweep
         ctx.spec = spec
         ctx.has_s = s is not None
-        spec.last = {"forward_steps": sweep.advanced}
+        spec.last = {"schedule": kind, "slots" if kind == "binomial" else "segment": size,
+                     "forward_steps": sweep.advanced}
         return J[0]
 
     @staticmethod

@@ -6,6 +6,9 @@
         lambda 0: the reverse-stage kernel as the benchmark launches it (with --tune, in the tile
         shapes of the tuning cache that a preceding bench.py run filled; with --flux roe, followed
         by the Roe flux kernels)
+    python -m paper_1511_06959_amd.profile_run step384 --reps 3 [--cache FILE.npy]
+        time steps of the 384^3 turbulence case as the benchmark runs them: primal step with BF16
+        snapshot encoding, reverse step from the record (lambda 0.1 dx^2 sigma_1, mean pressure)
     python -m paper_1511_06959_amd.profile_run copy --mib 1024 --reps 5
         torch's device-to-device copy of a buffer of known size, the calibration of the byte
         counters (it reads and writes exactly mib MiB per launch)
@@ -74,6 +77,52 @@ def run_adjoint(n, precision, reps, stages, tune=False, flux="split"):
     torch.cuda.synchronize()
     print(f"adjoint: {reps} reverse steps on {n}^3 ({precision}, {'stored' if stages else 'recomputed'} stages, "
           f"{flux} flux)", flush=True)
+
+
+def run_step384(reps, cache=None, tune=True):
+    """Time steps of the 384^3 decaying-turbulence case as the benchmark runs them (FP32 states
+    stored as deviations, BF16 snapshot records, lambda = 0.1 dx^2 sigma_1, mean pressure): each
+    rep is a primal step that encodes its snapshot and a reverse step from that record.  cache:
+    an .npy file holding the initial field (written on the first run, read afterwards)."""
+    import numpy as np
+    import torch
+
+    import paper_1511_06959_amd as adj
+    import workloads as W
+
+    wl = W.turb_384(nsteps=5000, lam_factor=0.1) if not (cache and os.path.exists(cache)) else None
+    if wl is None:
+        w0 = np.load(cache)
+        wl = W.turbulence(8, mach_rms=0.4, nu=2.887e-3, seed=4, nsteps=5000, lam_factor=0.1)  # parameters only
+        n, L = (384, 384, 384), (2 * math.pi,) * 3
+        dx = L[0] / 384
+        # the dt and lambda of the 384^3 field (dt from its realised velocities, as turb_384 sets it)
+        u = w0.reshape(5, -1)[1:4] / w0.reshape(5, -1)[0]
+        c0 = 1.0 / 0.4
+        rate = float((np.abs(u).sum(axis=0) + 3 * c0).max()) / dx
+        wl.n, wl.L, wl.w0, wl.dt, wl.lam = n, L, w0, 0.5 / rate, 0.1 * dx * dx
+    elif cache:
+        np.save(cache, wl.w0)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F32, adj.CKPT_BF16,
+                      adj.reference_state(wl.w0))
+    if tune:
+        from . import autotune
+        autotune.tune(g)
+    w = torch.from_numpy(g.to_stored(wl.w0)).to("cuda", torch.float32)
+    nxt = torch.empty_like(w)
+    ws = adj.workspace(g)
+    rec = torch.empty(adj.ckpt_bytes(g), dtype=torch.uint8, device="cuda")
+    obj = adj.Objective.make(adj.OBJ_MEAN_PRESSURE)
+    a = torch.randn(w.numel(), dtype=torch.float32, device="cuda") * 1e-3
+    b = torch.empty_like(a)
+    gs = torch.zeros_like(a)
+    for _ in range(reps):
+        adj.primal_step(g, w, None, nxt, ws, ckpt_out=rec)
+        adj.adjoint_step(g, rec, None, a, b, ws, lam=wl.lam, obj=obj, c_n=1.0 / 5000, grad_s=gs)
+        a, b = b, a
+        w, nxt = nxt, w
+    torch.cuda.synchronize()
+    print(f"step384: {reps} primal + reverse steps on 384^3 (dt {wl.dt:.4e}, lambda {wl.lam:.3e})", flush=True)
 
 
 def run_copy(mib, reps):
@@ -258,6 +307,10 @@ def main():
     a.add_argument("--tune", action="store_true", help="install the autotuned tiles (tuning cache) first")
     a.add_argument("--flux", choices=("split", "roe"), default="split",
                    help="roe: the Roe flux option (its kernels run after each stage kernel)")
+    q = sub.add_parser("step384")
+    q.add_argument("--reps", type=int, default=3)
+    q.add_argument("--cache", default=None, help=".npy file of the initial field (written if missing)")
+    q.add_argument("--no-tune", action="store_true")
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=1024)
     c.add_argument("--reps", type=int, default=5)
@@ -293,6 +346,8 @@ def main():
         return
     if args.cmd == "adjoint":
         run_adjoint(args.n, args.precision, args.reps, args.stages, args.tune, args.flux)
+    elif args.cmd == "step384":
+        run_step384(args.reps, args.cache, not args.no_tune)
     elif args.cmd == "copy":
         run_copy(args.mib, args.reps)
     else:

@@ -1,10 +1,13 @@
 """Window schedules around the C ABI: forward sweep storing the trajectory in HBM, reverse sweep.
 
 The paper stores periodic primal snapshots and recomputes in between ("Implementation",
-checkpointing); with 288 GB of HBM the whole trajectory of a window usually fits, so the
-default schedule here keeps every state (natively or as BF16 records) on the device and the
-reverse sweep recomputes only the three inner RK4 stage states of each step, inside
-``adjoint_step``.  Binomial checkpointing for windows that do not fit lives in ``revolve.py``.
+checkpointing).  With 288 GB of HBM the whole trajectory of a moderate window fits, so the plain
+schedule keeps every state (natively or as BF16 records) on the device and the reverse sweep
+recomputes only the three inner RK4 stage states of each step, inside ``adjoint_step``
+(``Trajectory``, ``forward``, ``backward``).  Longer windows keep snapshots: ``SegmentSweep``
+every seg steps, re-advancing one segment at a time with its stage states kept, and
+``RevolveSweep`` in a fixed number of slots with the binomial schedule of ``revolve.py``;
+``plan_window`` picks between them for a byte budget.
 
 Only scheduling happens here; all arithmetic runs in the library's kernels.
 """
@@ -295,3 +298,133 @@ class RevolveSweep:
                                  grad_s=grad_s)
                 a, b = b, a
         return a, grad_s
+
+
+class SegmentSweep:
+    """Two-level checkpointing: the forward sweep keeps a snapshot (a BF16 record when
+    ``g.ckpt_format == CKPT_BF16``, else a native state) every ``seg`` steps; the reverse sweep
+    re-advances one segment at a time from its snapshot, keeping every state of the segment and the
+    stage states of each of its steps in HBM (``primal_step_stages``), and then reverses the
+    segment with ``adjoint_step_stages``, so that no reverse step recomputes a stage state.
+
+    Per time step this costs one primal step in the forward sweep and one in the re-advance, against
+    the binomial schedule's (1 + recomputation) primal steps plus three stage evaluations inside
+    every reverse step; it needs ``nsnap`` snapshots plus one segment of states and stage states
+    (see ``segment_bytes``).  The paper keeps periodic snapshots and recomputes between them
+    ("Implementation", checkpointing); the working state is always full precision.
+    """
+
+    def __init__(self, g, nsteps, seg, s=None, obj=None, weights=None, lam=0.0, ws=None, device="cuda"):
+        self.g = g
+        self.bf16 = g.ckpt_format == CKPT_BF16
+        self.gn = Grid.make(tuple(g.n), tuple(g.L), g.mu, g.dt, g.gamma, g.prandtl, g.bc_x, g.precision, 0,
+                            tuple(g.w_ref), tuple(g.nu_weight), g.time_scheme, g.flux, g.roe_delta,
+                            (tuple(g.w_far[0:5]), tuple(g.w_far[5:10])))
+        self.nsteps, self.seg = int(nsteps), max(1, min(int(seg), int(nsteps)))
+        self.nsnap = -(-self.nsteps // self.seg)
+        self.s, self.obj, self.weights, self.lam = s, obj, weights, lam
+        self.ws = workspace(g, device) if ws is None else ws
+        N5 = 5 * g.ncells
+        if self.bf16:
+            self.snaps = torch.empty((self.nsnap, ckpt_bytes(g)), dtype=torch.uint8, device=device)
+        else:
+            self.snaps = torch.empty((self.nsnap, N5), dtype=g.dtype, device=device)
+        self.states = torch.empty((self.seg + 1, N5), dtype=g.dtype, device=device)
+        self.stages = torch.empty((self.seg, 3 * N5), dtype=g.dtype, device=device)
+        self.wN = torch.empty(N5, dtype=g.dtype, device=device)
+        self.advanced = 0
+        self.use_obj = obj is not None and obj.kind != OBJ_NONE and weights is not None
+
+    def _store(self, k, state):
+        if self.bf16:
+            from . import ckpt_encode
+            ckpt_encode(self.g, state, self.snaps[k], self.ws)
+        else:
+            self.snaps[k].copy_(state)
+
+    def _load(self, k, dst):
+        if self.bf16:
+            from . import ckpt_decode
+            ckpt_decode(self.g, self.snaps[k], dst)
+        else:
+            dst.copy_(self.snaps[k])
+
+    def forward(self, w0, J=None):
+        """Primal sweep keeping the snapshots; J (device FP64) += sum_n c_n j(w_n).  Returns J."""
+        dev = w0.device
+        J = torch.zeros(1, dtype=torch.float64, device=dev) if J is None else J
+        cur, nxt = self.states[0], self.states[1]
+        cur.copy_(w0)
+        self.advanced = 0
+        self._store(0, cur)
+        if self.use_obj and self.weights[0] != 0.0:
+            objective_and_grad(self.gn, self.obj, cur, self.ws, weight=float(self.weights[0]), J_accum=J)
+        for n in range(self.nsteps):
+            out = self.wN if n + 1 == self.nsteps else nxt
+            primal_step(self.gn, cur, self.s, out, self.ws)
+            self.advanced += 1
+            if (n + 1) % self.seg == 0 and n + 1 < self.nsteps:
+                self._store((n + 1) // self.seg, out)
+            if self.use_obj and self.weights[n + 1] != 0.0:
+                objective_and_grad(self.gn, self.obj, out, self.ws, weight=float(self.weights[n + 1]), J_accum=J)
+            cur, nxt = out, cur
+        return J
+
+    def backward(self, scale=1.0, grad_s=None):
+        """Reverse sweep, segment by segment.  Returns (w^_0, grad_s)."""
+        g, dev = self.g, self.states.device
+        N5 = 5 * g.ncells
+        a = torch.zeros(N5, dtype=g.dtype, device=dev)
+        b = torch.empty_like(a)
+        grad_s = torch.zeros(N5, dtype=g.dtype, device=dev) if grad_s is None else grad_s
+        if self.use_obj and self.weights[self.nsteps] != 0.0:
+            objective_and_grad(self.gn, self.obj, self.wN, self.ws, weight=scale * float(self.weights[self.nsteps]),
+                               djdw=a)
+        o = self.obj if self.use_obj else None
+        for k in range(self.nsnap - 1, -1, -1):
+            first, last = k * self.seg, min(self.nsteps, (k + 1) * self.seg)
+            L = last - first
+            self._load(k, self.states[0])
+            for i in range(L):
+                # the state after the segment's last step is the next segment's start, already reversed
+                primal_step_stages(self.gn, self.states[i], self.s, self.states[i + 1], self.stages[i], self.ws)
+                self.advanced += 1
+            for n in range(last - 1, first - 1, -1):
+                c_n = scale * float(self.weights[n]) if self.use_obj else 0.0
+                adjoint_step_stages(self.gn, self.states[n - first], self.stages[n - first], self.s, a, b, self.ws,
+                                    lam=self.lam, obj=o, c_n=c_n, grad_s=grad_s)
+                a, b = b, a
+        return a, grad_s
+
+
+def segment_bytes(g, nsteps, seg):
+    """HBM of a SegmentSweep: the snapshots plus one segment of states and stage states."""
+    N5 = 5 * g.ncells
+    esz = 8 if g.precision == 0 else 4
+    return -(-nsteps // seg) * snapshot_bytes(g) + (seg + 1) * N5 * esz + seg * 3 * N5 * esz
+
+
+def snapshot_bytes(g):
+    """Bytes of one snapshot: a BF16 record or a native state."""
+    return ckpt_bytes(g) if g.ckpt_format == CKPT_BF16 else 5 * g.ncells * (8 if g.precision == 0 else 4)
+
+
+def segment_length(g, nsteps):
+    """Segment length of least HBM for a SegmentSweep of nsteps steps."""
+    return min(range(1, nsteps + 1), key=lambda L: segment_bytes(g, nsteps, L))
+
+
+def binomial_slots(g, nsteps, budget_bytes):
+    """Snapshot slots of a RevolveSweep that fit budget_bytes (revolve.slots_for_budget)."""
+    from . import revolve
+    return revolve.slots_for_budget(snapshot_bytes(g), budget_bytes, nsteps)
+
+
+def plan_window(g, nsteps, budget_bytes):
+    """Checkpointing plan of an nsteps window within budget_bytes of HBM: ("segments", seg) with
+    the segment length of least memory when that two-level plan fits, else ("binomial", slots)
+    with the snapshot slots that fit."""
+    best = segment_length(g, nsteps)
+    if segment_bytes(g, nsteps, best) <= budget_bytes:
+        return "segments", best
+    return "binomial", binomial_slots(g, nsteps, budget_bytes)

@@ -8,6 +8,7 @@ import torch
 
 import paper_1511_06959_amd as adj
 from paper_1511_06959_amd import revolve, sweep
+from paper_1511_06959_amd.sweep import SegmentSweep
 from paper_1511_06959_amd.autograd import CheckpointedWindow, ObjectiveValue, PrimalStep, WindowSpec
 import workloads as W
 from tests.gpu_helpers import dev, host, smooth_state
@@ -128,3 +129,48 @@ def test_window_gradient_finite_differences_turbulence():
             Jm = float(CheckpointedWindow.apply(w0, s0 - eps * dev(d), spec))
         fd = (Jp - Jm) / (2 * eps)
         assert abs(fd - grad @ d) <= 1e-6 * abs(grad @ d) + 1e-12
+
+
+@pytest.mark.parametrize("seg", [1, 3, 5, 12])
+def test_segment_sweep_equals_store_all(seg):
+    # two-level checkpointing with native snapshots: every re-advanced state and stage state equals
+    # the forward sweep's, so J, dJ/dw_0 and dJ/ds equal the store-all sweep's bit for bit
+    wl = W.tgv_small(n=16, nsteps=12)
+    wl.weights = W.window_weights(12, 3, 12)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F64)
+    obj = adj.Objective.make(W.OBJ_KE_DISSIPATION)
+    s = dev(1e-3 * np.random.default_rng(24).standard_normal(wl.w0.size))
+    w0 = dev(wl.w0)
+    ws = adj.workspace(g)
+    traj, _, Jr = sweep.forward(g, w0, s, wl.nsteps, obj, wl.weights, ws)
+    whr, gsr, _ = sweep.backward(g, traj, s, obj, wl.weights, 2e-3, ws)
+    sw = SegmentSweep(g, wl.nsteps, seg, s, obj, wl.weights, 2e-3, ws)
+    J = sw.forward(w0)
+    wh, gs = sw.backward()
+    assert host(J)[0] == host(Jr)[0]
+    assert np.array_equal(host(wh), host(whr))
+    assert np.array_equal(host(gs), host(gsr))
+    assert sw.advanced == 2 * wl.nsteps and sw.nsnap == -(-wl.nsteps // seg)
+
+
+def test_checkpointed_window_plans_from_free_hbm():
+    # with no slots or segment given, the window takes the plan that the free HBM allows (here the
+    # two-level plan of least memory) and records it
+    wl = W.tgv_small(n=16, nsteps=12)
+    wl.weights = W.window_weights(12, 3, 12)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F64)
+    obj = adj.Objective.make(W.OBJ_MEAN_PRESSURE)
+    w0 = dev(wl.w0)
+    ws = adj.workspace(g)
+    traj, _, Jr = sweep.forward(g, w0, None, wl.nsteps, obj, wl.weights, ws)
+    whr, _, _ = sweep.backward(g, traj, None, obj, wl.weights, 0.0, ws)
+    spec = WindowSpec(g, wl.nsteps, obj, list(wl.weights))
+    w0t = w0.clone().requires_grad_(True)
+    J = CheckpointedWindow.apply(w0t, None, spec)
+    J.backward()
+    assert spec.last["schedule"] == "segments" and spec.last["segment"] == sweep.segment_length(g, wl.nsteps)
+    assert spec.last["forward_steps"] == wl.nsteps and spec.last["recompute_steps"] == wl.nsteps
+    assert float(J.detach()) == host(Jr)[0]
+    assert np.array_equal(host(w0t.grad), host(whr))
+    binom = WindowSpec(g, wl.nsteps, obj, list(wl.weights), schedule="binomial", reserve_bytes=0)
+    assert binom.plan(w0.device)[0] == "binomial"

@@ -83,6 +83,24 @@ def test_bf16_revolve_window_vs_oracle(c1, slots):
     assert max(errs) <= 1e-4
 
 
+@pytest.mark.parametrize("seg", [5, 10])
+def test_bf16_segment_window_vs_oracle(c1, seg):
+    # two-level checkpointing with BF16 snapshots: each segment re-advanced from a decoded snapshot
+    # (on this coarse grid a snapshot's code error runs through its whole segment: segments of 25
+    # steps reach 1.3e-4)
+    from paper_1511_06959_amd.sweep import SegmentSweep
+    wl, J, wh0, gs = c1
+    g = _bf16_grid(wl)
+    ws = adj.workspace(g)
+    s = dev(wl.s, torch.float32)
+    sw = SegmentSweep(g, wl.nsteps, seg, s, adj.Objective.make(wl.obj_kind), wl.weights, 0.0, ws)
+    Jg = sw.forward(dev(g.to_stored(wl.w0), torch.float32))
+    whg, gsg = sw.backward()
+    errs = (abs(host(Jg)[0] - J) / abs(J), _rel(host(whg), wh0), _rel(host(gsg), gs))
+    _report(f"BF16 snapshots, segments of {seg}", errs)
+    assert max(errs) <= 1e-4
+
+
 @pytest.mark.parametrize("lam_factor", [0.0, 0.1], ids=["lam0", "lam"])
 @pytest.mark.parametrize("bc_x", [0, 1], ids=["periodic", "walls"])
 def test_bf16_record_reverse_step_vs_oracle_on_decoded_state(orc, bc_x, lam_factor):
