@@ -706,6 +706,177 @@ def cpu_baseline_leg(wl, seconds):
     return cpu, rel
 
 
+# ---------------------------------------------------------------------------------------------
+# The configured windows, run once: the 5000-step 384^3 gradient with finite-difference checks,
+# and the 4000-step wake with a lambda sweep over one BF16 trajectory
+# ---------------------------------------------------------------------------------------------
+def _direction(n5, seed):
+    """Seeded N(0, 1) direction of the body force (torch's device generator, FP64)."""
+    import torch
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(seed))
+    return torch.randn(n5, dtype=torch.float64, device="cuda", generator=gen)
+
+
+def main_c5_window(args):
+    """--parts f32_lam,f32_lam0,f64_lam0: autograd gradients of the whole window (dJ/ds at s = 0,
+    checkpointing sized to the free HBM) and their products with the seeded directions;
+    --parts fd: central differences of J along the directions (FP64 primal, --fd-eps)."""
+    import torch
+
+    import paper_1511_06959_amd as adj
+    from paper_1511_06959_amd.autograd import CheckpointedWindow, WindowSpec
+    import workloads as W
+
+    T = args.window or PLAN_STEPS
+    seeds = [int(x) for x in args.fd_seeds.split(",")]
+    print("[window] generating the 384^3 turbulence field", file=sys.stderr, flush=True)
+    wl = W.turb_384(nsteps=T, lam_factor=0.1)
+    obj = adj.Objective.make(wl.obj_kind)
+    out = {"workload": f"decaying turbulence 384^3 (Mach_rms 0.4, nu 2.887e-3), {T} RK4 steps, dt {wl.dt:.6g}, "
+                       "time-averaged mean pressure over steps 1..T, gradient wrt the body force at s = 0",
+           "steps": T, "dt": wl.dt, "lambda_0.1": wl.lam, "directions": seeds, "parts": {}}
+    n5 = 5 * wl.ncells
+    for part in args.parts.split(","):
+        t0 = time.perf_counter()
+        if part == "fd":
+            g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F64)
+            ws = adj.workspace(g)
+            w0 = torch.from_numpy(wl.w0).to("cuda")
+            cur, nxt = torch.empty_like(w0), torch.empty_like(w0)
+            J = torch.zeros(1, dtype=torch.float64, device="cuda")
+            eps = args.fd_eps
+            res = {}
+            for seed in seeds:
+                d = _direction(n5, seed)
+                vals = []
+                for sign in (1.0, -1.0):
+                    s = sign * eps * d
+                    J.zero_()
+                    cur.copy_(w0)
+                    for n in range(T):
+                        adj.primal_step(g, cur, s, nxt, ws)
+                        adj.objective_and_grad(g, obj, nxt, ws, weight=float(wl.weights[n + 1]), J_accum=J)
+                        cur, nxt = nxt, cur
+                        if (n + 1) % 1000 == 0:
+                            print(f"[window] fd seed {seed} sign {sign:+.0f}: step {n + 1}", file=sys.stderr,
+                                  flush=True)
+                    vals.append(float(J.cpu()[0]))
+                    del s
+                res[str(seed)] = {"J_plus": vals[0], "J_minus": vals[1], "fd": (vals[0] - vals[1]) / (2 * eps)}
+                del d
+                torch.cuda.empty_cache()
+            out["parts"]["fd"] = {"eps": eps, "primal": "FP64", "values": res, "seconds": time.perf_counter() - t0}
+            print(json.dumps({"part": "fd", **out["parts"]["fd"]}), flush=True)
+            continue
+        prec = adj.F64 if part.startswith("f64") else adj.F32
+        lam = wl.lam if part.endswith("_lam") else 0.0
+        ref = adj.reference_state(wl.w0) if prec == adj.F32 else None
+        g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, prec,
+                          adj.CKPT_BF16 if prec == adj.F32 else adj.CKPT_NATIVE, ref)
+        if not args.no_autotune:
+            from paper_1511_06959_amd import autotune
+            autotune.tune(g)
+        last = [time.perf_counter()]
+
+        def progress(n):
+            if time.perf_counter() - last[0] > 30.0:
+                last[0] = time.perf_counter()
+                print(f"[window] {part}: reverse step {n}", file=sys.stderr, flush=True)
+
+        spec = WindowSpec(g, T, obj, list(wl.weights), lam=lam, energy_every=50 if prec == adj.F32 else 0,
+                          progress=progress)
+        w0 = torch.from_numpy(g.to_stored(wl.w0)).to("cuda", g.dtype)
+        st = torch.zeros(n5, dtype=g.dtype, device="cuda", requires_grad=True)
+        print(f"[window] {part}: forward sweep", file=sys.stderr, flush=True)
+        J = CheckpointedWindow.apply(w0, st, spec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        print(f"[window] {part}: J = {float(J.detach()):.12g} after {t1 - t0:.1f} s; reverse sweep", file=sys.stderr,
+              flush=True)
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        grad = st.grad.double()
+        dots = {str(seed): float(torch.dot(grad, _direction(n5, seed))) for seed in seeds}
+        rec = {"J": float(J.detach()), "grad_norm": float(grad.norm()), "dots": dots, "plan": dict(spec.last),
+               "forward_s": t1 - t0, "reverse_s": t2 - t1,
+               "cell_steps_per_s": wl.ncells * T / (t2 - t0), "lambda": lam,
+               "precision": "FP32 stencils, BF16 snapshots, FP64 reductions" if prec == adj.F32 else "FP64"}
+        rec["plan"].pop("energy", None)
+        if spec.last.get("energy"):
+            rec["energy"] = spec.last["energy"]
+        out["parts"][part] = rec
+        print(json.dumps({"part": part, **rec}), flush=True)
+        print(f"[window] {part}: done in {t2 - t0:.1f} s", file=sys.stderr, flush=True)
+        del st, grad, w0, spec, J
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
+def main_wake_lambda(args):
+    """The 4000-step wake: forward sweep storing BF16 records of every state, then one reverse
+    sweep for lambda = (0, 0.1, 1) dx^2 sigma_1 at once over that trajectory, with the adjoint
+    energy of every member after every reverse step."""
+    import torch
+
+    import paper_1511_06959_amd as adj
+    from paper_1511_06959_amd import autotune, sweep
+    from paper_1511_06959_amd.ensemble import LambdaSweep
+    import workloads as W
+
+    T = args.window or 4000
+    wl = W.wake(nsteps=T)
+    dx = min(wl.L[d] / wl.n[d] for d in range(3))
+    factors = [0.0, 0.1, 1.0]
+    lams = [f * dx * dx for f in factors]
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F32, adj.CKPT_BF16,
+                      adj.reference_state(wl.w0))
+    if not args.no_autotune:
+        autotune.tune(g)
+    obj = adj.Objective.make(wl.obj_kind, wl.plane_i, wl.pt_ref)
+    ws = adj.workspace(g)
+    s = torch.zeros(5 * wl.ncells, dtype=torch.float32, device="cuda")
+    print(f"[wake] {wl.n}, {T} steps, dt {wl.dt:.4e}; forward sweep", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    traj, _, J = sweep.forward(g, torch.from_numpy(g.to_stored(wl.w0)).to("cuda", torch.float32), s, T, obj,
+                               wl.weights, ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(f"[wake] J = {float(J.cpu()[0]):.10g} after {t1 - t0:.1f} s; lambda sweep", file=sys.stderr, flush=True)
+    ls = LambdaSweep(g, traj, lams, obj, wl.weights, s=s, energy=True)
+    last = [time.perf_counter()]
+
+    def progress(n):
+        if n % 500 == 0:
+            print(f"[wake] reverse step {n}", file=sys.stderr, flush=True)
+
+    wh, gs = ls.backward(progress=progress)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    E = ls.E.cpu().numpy()
+    from paper_1511_06959_amd import lamest
+    members = []
+    g0 = ls.member(gs, 0).double()
+    for m, f in enumerate(factors):
+        gm = ls.member(gs, m).double()
+        wm = ls.member(wh, m).double()
+        members.append({"lambda_factor": f, "lambda": lams[m], "grad_s_norm": float(gm.norm()),
+                        "w0_adjoint_norm": float(wm.norm()),
+                        "grad_s_rel_dev_from_lambda0": float((gm - g0).norm() / g0.norm()),
+                        "energy_growth_rate": lamest.growth_rate(E[:, m], wl.dt),
+                        "energy_first_last": [float(E[0, m]), float(E[T, m])],
+                        "energy_every_500": [float(E[n, m]) for n in range(0, T + 1, 500)]})
+    traj_gb = traj.store.numel() / 1e9
+    out = {"workload": "temporally developing wake 512x256x32 (slip walls in x, free stream Mach 0.85, centre 0.5, "
+                       f"Re 5e4), {T} RK4 steps, stagnation-pressure loss on the face x = 0.75 L_x, BF16 records of "
+                       "every state, one reverse sweep for lambda = (0, 0.1, 1) dx^2 sigma_1 at once",
+           "steps": T, "J": float(J.cpu()[0]), "trajectory_gb": traj_gb, "forward_s": t1 - t0, "reverse_s": t2 - t1,
+           "member_cell_steps_per_s": wl.ncells * T * len(lams) / (t2 - t1), "members": members}
+    print(json.dumps(out), flush=True)
+
+
 WORKLOADS = {
     "tgv64": "Taylor-Green vortex 64^3 periodic, Mach 0.1, Re 1600, {n} RK4 steps forward + full adjoint sweep, "
              "lambda 0, objective time-averaged viscous dissipation, gradient wrt a 5x64^3 body force",
@@ -727,6 +898,8 @@ WORKLOADS = {
                "dx^2 sigma_1, mean pressure; the window's BF16 records kept in pinned host memory and streamed "
                "over PCIe (device-to-host after each primal step, host-to-device one step ahead of the reverse "
                "sweep), against the same sweeps with the records in HBM",
+    "turb384_window": "the whole 5000-step 384^3 window once: autograd gradients and finite differences",
+    "wake_lambda": "the 4000-step wake with a lambda sweep over one BF16 trajectory",
     "lamest": "choice of lambda for decaying turbulence 128^3 periodic (Mach_rms 0.4, nu 2.887e-3): {n}-step window, "
               "6 candidate scales {{0,0.01,0.03,0.1,0.3,1}} dx^2 swept backward together as one batched ensemble "
               "from a white-noise terminal adjoint, adjoint energy after every reverse step",
@@ -755,6 +928,10 @@ def main():
     ap.add_argument("--workload", default="turb384", choices=sorted(WORKLOADS))
     ap.add_argument("--window", type=int, default=0, help="RK4 steps per window (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--parts", default="f32_lam,f32_lam0,f64_lam0",
+                    help="turb384_window: f32_lam, f32_lam0, f64_lam0 (gradients), fd (finite differences)")
+    ap.add_argument("--fd-seeds", default="10,11,12,13,14,15,16,17", help="turb384_window: direction seeds")
+    ap.add_argument("--fd-eps", type=float, default=1e-3, help="turb384_window: finite-difference step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -784,6 +961,12 @@ def main():
     adj.lib()
     if args.workload == "turb384":
         main_c5(args)
+        return
+    if args.workload == "turb384_window":
+        main_c5_window(args)
+        return
+    if args.workload == "wake_lambda":
+        main_wake_lambda(args)
         return
     if args.workload == "ensemble":
         main_ensemble(args)

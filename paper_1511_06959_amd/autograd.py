@@ -37,7 +37,9 @@ class WindowSpec:
     last: dict = field(default_factory=dict)  # diagnostics of the last backward (plan, advances)
     schedule: str = "auto"
     segment: Optional[int] = None
-    reserve_bytes: int = 8 << 30  # HBM left free beside the checkpoints (auto plans)
+    reserve_bytes: int = 2 << 30  # HBM left free beside the checkpoints and working states (auto plans)
+    energy_every: int = 0  # segment plans: keep the adjoint energy every so many reverse steps
+    progress: Optional[object] = None  # called with the step index after every reverse step
 
     def workspace(self):
         if self.ws is None:
@@ -50,8 +52,12 @@ class WindowSpec:
             return "binomial", int(self.slots)
         if self.segment is not None and self.schedule in ("auto", "segments"):
             return "segments", int(self.segment)
+        self.workspace()  # allocated before the free memory is read
         free, _ = torch.cuda.mem_get_info(device)
-        budget = max(0, free - self.reserve_bytes)
+        # besides the checkpoints: the sweep's working states and adjoints (a, b, grad_s, current,
+        # next and final state) and the caller's w0, s and gradients
+        state = 5 * self.g.ncells * (8 if self.g.precision == 0 else 4)
+        budget = max(0, free - self.reserve_bytes - 8 * state)
         if self.schedule == "binomial":
             return "binomial", binomial_slots(self.g, self.nsteps, budget)
         if self.schedule == "segments":
@@ -128,7 +134,11 @@ class CheckpointedWindow(torch.autograd.Function):
     def backward(ctx, gJ):
         sweep, spec = ctx.sweep, ctx.spec
         before = sweep.advanced
-        wh0, gs = sweep.backward(scale=float(gJ))
+        if isinstance(sweep, SegmentSweep):
+            wh0, gs = sweep.backward(scale=float(gJ), energy_every=spec.energy_every, progress=spec.progress)
+            spec.last["energy"] = [(n, float(E.cpu()[0])) for n, E in sweep.energy]
+        else:
+            wh0, gs = sweep.backward(scale=float(gJ), progress=spec.progress)
         spec.last["recompute_steps"] = sweep.advanced - before
         ctx.sweep = None
         return wh0, (gs if ctx.has_s else None), None

@@ -223,3 +223,81 @@ class PlannedEnsemble:
 
     def results(self, m):
         return self._res[m]
+
+
+class LambdaSweep:
+    """Reverse sweeps of one stored window for several artificial-viscosity scales at once (the
+    lambda study of the paper, "Stabilizing adjoint equations" and Results, Table 2): one batched
+    ensemble of one box and one member per lambda.  Each reverse step reads the stored state once
+    (a BF16 record is decoded once), recomputes the box's stage states once inside the batched
+    adjoint step, and transposes the stages of every member; the objective gradient is then added
+    to each member (any objective kind) and, optionally, each member's adjoint energy recorded.
+
+    g:       the grid of the trajectory (BF16 records or native states, RK4, split flux)
+    traj:    a sweep.Trajectory of the window (states 0..T)
+    lams:    lambda of each member (length^2 units: nu = lambda sigma_1)
+    Every member's w^_0 and dJ/ds equal those of a single-box reverse sweep with its lambda over
+    the same trajectory bit for bit (same kernels, same order of operations).
+    """
+
+    def __init__(self, g, traj, lams, obj=None, weights=None, s=None, energy=False, device="cuda"):
+        from . import CKPT_BF16, Grid
+        self.g, self.traj = g, traj
+        self.bf16 = g.ckpt_format == CKPT_BF16
+        self.gn = Grid.make(tuple(g.n), tuple(g.L), g.mu, g.dt, g.gamma, g.prandtl, g.bc_x, g.precision, 0,
+                            tuple(g.w_ref), tuple(g.nu_weight), g.time_scheme, g.flux, g.roe_delta)
+        self.lams = [float(x) for x in lams]
+        self.M = len(self.lams)
+        self.obj, self.weights, self.s = obj, weights, s
+        self.ens = Ensemble([self.gn], [0] * self.M, self.lams, None, device)
+        N5 = 5 * g.ncells
+        self.ws = self.ens.workspace(device)
+        from . import workspace
+        self.ws1 = workspace(self.gn, device)
+        self.dec = torch.empty(N5, dtype=self.gn.dtype, device=device)
+        self.a = torch.zeros(self.M * N5, dtype=self.gn.dtype, device=device)
+        self.b = torch.zeros_like(self.a)
+        self.grad_s = torch.zeros_like(self.a)
+        T = traj.nsteps
+        self.E = torch.zeros((T + 1, self.M), dtype=torch.float64, device=device) if energy else None
+        self.use_obj = obj is not None and obj.kind != 0 and weights is not None
+
+    def _state(self, n):
+        if not self.bf16:
+            return self.traj.slot(n)
+        from . import ckpt_decode
+        ckpt_decode(self.g, self.traj.slot(n), self.dec)
+        return self.dec
+
+    def _inject(self, w, c, dst):
+        from . import objective_and_grad
+        for m in range(self.M):
+            objective_and_grad(self.gn, self.obj, w, self.ws1, weight=c, djdw=self.ens.member_slice(dst, m))
+
+    def backward(self, progress=None):
+        """Returns (w^_0, grad_s) member-packed (member m: ens.member_slice(t, m)); self.E holds the
+        adjoint energies (index [n, m]) when energy=True.  progress(n) is called every step."""
+        T = self.traj.nsteps
+        a, b = self.a, self.b
+        a.zero_()
+        self.grad_s.zero_()
+        w = self._state(T)
+        if self.use_obj and self.weights[T] != 0.0:
+            self._inject(w, float(self.weights[T]), a)
+        if self.E is not None:
+            self.ens.energy_vhat(self.M, w, a, self.E[T], self.ws)
+        for n in range(T - 1, -1, -1):
+            w = self._state(n)
+            self.ens.adjoint_step(self.M, w, self.s, a, b, self.ws, grad_s=self.grad_s)
+            if self.use_obj and self.weights[n] != 0.0:
+                self._inject(w, float(self.weights[n]), b)
+            a, b = b, a
+            if self.E is not None:
+                self.ens.energy_vhat(self.M, w, a, self.E[n], self.ws)
+            if progress is not None:
+                progress(n)
+        self.wh0 = a
+        return a, self.grad_s
+
+    def member(self, t, m):
+        return self.ens.member_slice(t, m)

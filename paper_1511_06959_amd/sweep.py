@@ -269,7 +269,9 @@ class RevolveSweep:
             objective_and_grad(self.gn, self.obj, self.wN, self.ws, weight=float(self.weights[self.nsteps]), J_accum=J)
         return J
 
-    def backward(self, scale=1.0, grad_s=None):
+    def backward(self, scale=1.0, grad_s=None, progress=None):
+        """Replays the reverse part of the schedule.  progress(n) is called after every reverse
+        step.  Returns (w^_0, grad_s)."""
         g, dev = self.g, self.cur.device
         N5 = 5 * g.ncells
         a = torch.zeros(N5, dtype=g.dtype, device=dev)
@@ -297,6 +299,8 @@ class RevolveSweep:
                     adjoint_step(gg, self.pool[self.where[n]], self.s, a, b, self.ws, lam=self.lam, obj=o, c_n=c_n,
                                  grad_s=grad_s)
                 a, b = b, a
+                if progress is not None:
+                    progress(n)
         return a, grad_s
 
 
@@ -370,9 +374,13 @@ class SegmentSweep:
             cur, nxt = out, cur
         return J
 
-    def backward(self, scale=1.0, grad_s=None):
-        """Reverse sweep, segment by segment.  Returns (w^_0, grad_s)."""
+    def backward(self, scale=1.0, grad_s=None, energy_every=0, progress=None):
+        """Reverse sweep, segment by segment.  Returns (w^_0, grad_s).  energy_every > 0: the
+        adjoint energy after every energy_every-th reverse step (and the terminal one) is kept in
+        self.energy, a list of (step, device FP64 scalar).  progress(n) is called after every
+        reverse step."""
         g, dev = self.g, self.states.device
+        self.energy = []
         N5 = 5 * g.ncells
         a = torch.zeros(N5, dtype=g.dtype, device=dev)
         b = torch.empty_like(a)
@@ -381,6 +389,10 @@ class SegmentSweep:
             objective_and_grad(self.gn, self.obj, self.wN, self.ws, weight=scale * float(self.weights[self.nsteps]),
                                djdw=a)
         o = self.obj if self.use_obj else None
+        if energy_every > 0:
+            E = torch.zeros(1, dtype=torch.float64, device=dev)
+            energy_vhat(self.gn, self.wN, a, E, self.ws)
+            self.energy.append((self.nsteps, E))
         for k in range(self.nsnap - 1, -1, -1):
             first, last = k * self.seg, min(self.nsteps, (k + 1) * self.seg)
             L = last - first
@@ -394,6 +406,12 @@ class SegmentSweep:
                 adjoint_step_stages(self.gn, self.states[n - first], self.stages[n - first], self.s, a, b, self.ws,
                                     lam=self.lam, obj=o, c_n=c_n, grad_s=grad_s)
                 a, b = b, a
+                if energy_every > 0 and (n % energy_every == 0):
+                    E = torch.zeros(1, dtype=torch.float64, device=dev)
+                    energy_vhat(self.gn, self.states[n - first], a, E, self.ws)
+                    self.energy.append((n, E))
+                if progress is not None:
+                    progress(n)
         return a, grad_s
 
 

@@ -135,3 +135,62 @@ def test_planned_groups_equal_single_ensemble():
         assert Jm == J[m], f"member {m}: J"
         assert np.array_equal(whm.double().numpy(), wh[lo:hi]), f"member {m}: w^_0"
         assert np.array_equal(gsm.double().numpy(), gs[lo:hi]), f"member {m}: grad_s"
+
+
+def _wake_like(n=(24, 12, 8), T=10, seed=80):
+    # a small box between slip walls with a shear layer, the stagnation-pressure loss on an x-face
+    L = (2.0, 1.0, 0.7)
+    w = smooth_state(n, L, seed=seed, wall=True)
+    dx = [L[d] / n[d] for d in range(3)]
+    wl = W.Workload("wake_like", n, L, 2e-3, 0.25 * min(dx) / 2.0, w, None, T, W.OBJ_PT_LOSS_PLANE,
+                    W.window_weights(T, 1, T), bc_x=1, plane_i=3 * n[0] // 4, pt_ref=1.05)
+    return wl
+
+
+@pytest.mark.parametrize("ckpt", [adj.CKPT_BF16, adj.CKPT_NATIVE], ids=["bf16", "native"])
+def test_lambda_sweep_members_equal_single_sweeps(ckpt):
+    # several lambdas swept backward together over one stored trajectory (BF16 records decoded once
+    # per step): every member equals the single-box reverse sweep with its lambda bit for bit
+    from paper_1511_06959_amd.ensemble import LambdaSweep
+    wl = _wake_like()
+    ref = adj.reference_state(wl.w0)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F32, ckpt, ref)
+    obj = adj.Objective.make(wl.obj_kind, wl.plane_i, wl.pt_ref)
+    dx = min(wl.L[d] / wl.n[d] for d in range(3))
+    lams = [0.0, 0.1 * dx * dx, 1.0 * dx * dx]
+    s = torch.from_numpy(1e-3 * np.random.default_rng(81).standard_normal(wl.w0.size)).to("cuda", torch.float32)
+    ws = adj.workspace(g)
+    traj, _, _ = sweep.forward(g, torch.from_numpy(g.to_stored(wl.w0)).to("cuda", torch.float32), s, wl.nsteps, obj,
+                               wl.weights, ws)
+    ls = LambdaSweep(g, traj, lams, obj, wl.weights, s=s, energy=True)
+    wh, gs = ls.backward()
+    wh, gs, E = host(wh), host(gs), host(ls.E)
+    for m, lam in enumerate(lams):
+        whs, gss, Es = sweep.backward(g, traj, s, obj, wl.weights, lam, ws, energy=True)
+        lo, hi = 5 * ls.ens.offset(1, m), 5 * ls.ens.offset(1, m + 1)
+        assert np.array_equal(wh[lo:hi], host(whs)), f"member {m}: w^_0"
+        assert np.array_equal(gs[lo:hi], host(gss)), f"member {m}: grad_s"
+        assert np.allclose(E[:, m], host(Es), rtol=1e-13, atol=0.0), f"member {m}: adjoint energy"
+
+
+def test_lambda_sweep_vs_oracle(orc):
+    # FP64 native trajectory, three lambdas at once, against the oracle's window for each lambda
+    from paper_1511_06959_amd.ensemble import LambdaSweep
+    wl = _wake_like(n=(20, 10, 6), T=8, seed=82)
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F64)
+    obj = adj.Objective.make(wl.obj_kind, wl.plane_i, wl.pt_ref)
+    dx = min(wl.L[d] / wl.n[d] for d in range(3))
+    lams = [0.0, 0.3 * dx * dx, 1.0 * dx * dx]
+    ws = adj.workspace(g)
+    traj, _, _ = sweep.forward(g, torch.from_numpy(wl.w0).to("cuda"), None, wl.nsteps, obj, wl.weights, ws)
+    ls = LambdaSweep(g, traj, lams, obj, wl.weights)
+    wh, gs = ls.backward()
+    wh, gs = host(wh), host(gs)
+    og = orc.grid_from(wl.params())
+    oobj = orc.make_obj(wl.obj_kind, wl.plane_i, wl.pt_ref)
+    otraj = orc.primal_window(og, wl.w0, None, wl.nsteps)
+    for m, lam in enumerate(lams):
+        who, gso = orc.adjoint_window(og, oobj, otraj, None, wl.weights, lam)
+        lo, hi = 5 * ls.ens.offset(1, m), 5 * ls.ens.offset(1, m + 1)
+        assert np.linalg.norm(wh[lo:hi] - who) <= 1e-10 * np.linalg.norm(who), f"member {m}: w^_0"
+        assert np.linalg.norm(gs[lo:hi] - gso) <= 1e-10 * np.linalg.norm(gso), f"member {m}: grad_s"
