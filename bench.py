@@ -412,7 +412,13 @@ def run_plan(wl, precision, K, warmup, tune=True, bf16=True):
     w0 = torch.from_numpy(g.to_stored(wl.w0)).to("cuda", g.dtype)
     ws = adj.workspace(g)
     torch.cuda.synchronize()
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
+    print(f"[bench] {'f64' if precision == adj.F64 else 'f32'}: {free / 1e9:.1f} GB free, torch holds "
+          f"{torch.cuda.memory_allocated() / 1e9:.1f} GB allocated, {torch.cuda.memory_reserved() / 1e9:.1f} GB reserved",
+          file=sys.stderr, flush=True)
     # besides the checkpoints, the window's working states, adjoints and a margin stay free
     plan = plan_for(g, PLAN_STEPS, max(0, free - 6 * 5 * g.ncells * g.dtype.itemsize - (4 << 30)))
 

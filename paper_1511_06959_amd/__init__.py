@@ -132,7 +132,8 @@ class Objective(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_adjoint_step", "adj_adjoint_step_noalloc",
+EXPORTS = ("adj_workspace_bytes", "adj_ckpt_bytes", "adj_primal_step", "adj_primal_step_obj", "adj_adjoint_step",
+           "adj_adjoint_step_noalloc",
            "adj_primal_step_stages",
            "adj_adjoint_step_stages", "adj_growth_sigma1",
            "adj_objective_and_grad", "adj_energy_vhat", "adj_dot", "adj_ckpt_encode", "adj_ckpt_decode",
@@ -157,6 +158,7 @@ def lib():
         "adj_workspace_bytes": ([gp], sz),
         "adj_ckpt_bytes": ([gp], sz),
         "adj_primal_step": ([gp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "adj_primal_step_obj": ([gp, vp, vp, vp, vp, vp, op, dbl, vp, vp, sz, vp], ctypes.c_int),
         "adj_adjoint_step": ([gp, vp, vp, vp, dbl, op, dbl, vp, vp, vp, sz, vp], ctypes.c_int),
         "adj_adjoint_step_noalloc": ([gp, vp, vp, vp, dbl, op, dbl, vp, vp, vp], ctypes.c_int),
         "adj_primal_step_stages": ([gp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
@@ -257,6 +259,15 @@ def primal_step(g, w_n, s, w_np1, ws, ckpt_out=None):
     wp, wb = _ws(ws)
     _check(lib().adj_primal_step(ctypes.byref(g), _state(g, w_n), _state(g, s), _state(g, w_np1),
                                  _ptr(ckpt_out, torch.uint8), wp, wb, _stream()))
+
+
+def primal_step_obj(g, w_n, s, w_np1, ws, obj, weight, J_accum, ckpt_out=None, stages_out=None):
+    """primal_step (primal_step_stages with stages_out) that also adds weight * j(w_np1) to J_accum."""
+    wp, wb = _ws(ws)
+    _check(lib().adj_primal_step_obj(ctypes.byref(g), _state(g, w_n), _state(g, s), _state(g, w_np1),
+                                     _ptr(ckpt_out, torch.uint8), None if stages_out is None else _stages(g, stages_out),
+                                     ctypes.byref(obj) if obj is not None else None, float(weight),
+                                     _ptr(J_accum, torch.float64), wp, wb, _stream()))
 
 
 def adjoint_step(g, w_n, s, wh_np1, wh_n, ws, lam=0.0, obj=None, c_n=0.0, grad_s=None):

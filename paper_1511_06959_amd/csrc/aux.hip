@@ -87,28 +87,11 @@ __global__ __launch_bounds__(RB) void k_dot_partial(const T* __restrict__ a, con
 }
 
 // Primitive quantities of a cell (or its wall mirror image), in FP64.
-struct Q64 {
-  double rho, u[3], e, p, ri;
-};
-
 template <typename T>
 __device__ __forceinline__ Q64 load_q64(const Consts<T>& c, const T* __restrict__ w, long long gi, int mirror,
                                         double gamma) {
   const long long N = c.N;
-  Q64 q;
-  // stored deviations w - wref, restored in FP64
-  q.rho = (double)w[gi] + (double)c.wref[0];
-  double m1 = (double)w[N + gi] + (double)c.wref[1];
-  if (mirror) m1 = -m1;
-  const double m2 = (double)w[2 * N + gi] + (double)c.wref[2], m3 = (double)w[3 * N + gi] + (double)c.wref[3];
-  const double Et = (double)w[4 * N + gi] + (double)c.wref[4];
-  q.ri = 1.0 / q.rho;
-  q.u[0] = m1 * q.ri;
-  q.u[1] = m2 * q.ri;
-  q.u[2] = m3 * q.ri;
-  q.e = Et * q.ri - 0.5 * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
-  q.p = (gamma - 1.0) * q.rho * q.e;
-  return q;
+  return q64_of(c, w[gi], w[N + gi], w[2 * N + gi], w[3 * N + gi], w[4 * N + gi], mirror, gamma);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -364,13 +347,10 @@ __global__ __launch_bounds__(RB) void k_meanp(Consts<T> c, const T* __restrict__
     const Q64 q = load_q64(c, w, i, 0, g);
     v += q.p;
     if (djdw) {
-      const double f = wgt * (g - 1.0) / (double)N;
-      const double usq = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
-      djdw[i] += (T)(f * 0.5 * usq);
-      djdw[N + i] += (T)(-f * q.u[0]);
-      djdw[2 * N + i] += (T)(-f * q.u[1]);
-      djdw[3 * N + i] += (T)(-f * q.u[2]);
-      djdw[4 * N + i] += (T)f;
+      T t[5];
+      meanp_grad_terms(q, meanp_factor(wgt, g, N), t);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) djdw[k * N + i] += t[k];
     }
   }
   if (partials) {
@@ -401,13 +381,10 @@ __global__ __launch_bounds__(RB) void k_meanp_batch(const BoxDesc<T>* __restrict
     v = q.p;
     if (djdw) {
       T* d = djdw + 5 * mems[m].aoff;
-      const double f = wgt[m] * (g - 1.0) / (double)N;
-      const double usq = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
-      d[i] += (T)(f * 0.5 * usq);
-      d[N + i] += (T)(-f * q.u[0]);
-      d[2 * N + i] += (T)(-f * q.u[1]);
-      d[3 * N + i] += (T)(-f * q.u[2]);
-      d[4 * N + i] += (T)f;
+      T t[5];
+      meanp_grad_terms(q, meanp_factor(wgt[m], g, N), t);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) d[k * N + i] += t[k];
     }
   }
   if (partials) {
@@ -967,6 +944,12 @@ hipError_t launch_objective(const Consts<T>& c, int kind, int plane_i, double pt
       hipLaunchKernelGGL((k_ptloss_grad<T>), dim3(ng), dim3(RB), 0, st, c, w, plane_i, pt_ref, scratch, weight, djdw);
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fold(const double* partials, int n, double* dst, double alpha, double beta, hipStream_t st) {
+  ProfScope ps(ADJ_PROF_OBJECTIVE, st);
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(RB), 0, st, partials, n, 1, dst, alpha, beta);
   return hipGetLastError();
 }
 

@@ -180,10 +180,12 @@ size_t ckpt_header_bytes(const adj_grid* g) {
 // stage 4; 1 for the plain residual).
 template <typename T>
 int primal_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
-                 const T* W3, T cR, T* out, hipStream_t st, const char* what, T ca = T(0), T cb = T(0)) {
+                 const T* W3, T cR, T* out, hipStream_t st, const char* what, T ca = T(0), T cb = T(0),
+                 double* jpart = nullptr) {
   hipError_t e;
   const int split = g->flux == ADJ_FLUX_SPLIT;
-  if ((e = launch_primal_stage<T>(mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb, split))) return hip_fail(e, what);
+  if ((e = launch_primal_stage<T>(mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb, split, jpart)))
+    return hip_fail(e, what);
   const T coef = mode == STAGE_FIN ? c.dt / T(6) : (mode == STAGE_RES ? T(1) : cR);
   const int open = g->bc_x == ADJ_BC_CHARACTERISTIC;
   if (!split) {
@@ -202,10 +204,10 @@ int primal_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, co
 template <typename T>
 int adjoint_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext,
                   const T* nu, T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st,
-                  const char* what) {
+                  const char* what, double objw = 0.0) {
   hipError_t e;
   const int split = g->flux == ADJ_FLUX_SPLIT;
-  if ((e = launch_adjoint_stage<T>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st, split)))
+  if ((e = launch_adjoint_stage<T>(mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st, split, objw)))
     return hip_fail(e, what);
   const int open = g->bc_x == ADJ_BC_CHARACTERISTIC;
   if (!split) {
@@ -218,8 +220,10 @@ int adjoint_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, c
   return ADJ_OK;
 }
 
+// jpart: per-tile pressure sums of the new state from the final RK4 stage (see fuse_meanp), or NULL
 template <typename T>
-int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, T* stages, void* ws, hipStream_t st) {
+int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, T* stages, void* ws, hipStream_t st,
+                double* jpart = nullptr) {
   const Consts<T> c = consts<T>(g);
   const WsLayout L = layout(g);
   const long long S5 = 5 * c.N;
@@ -243,7 +247,8 @@ int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, 
     if ((r = primal_stage<T>(g, STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st, "primal stage 1"))) return r;
     if ((r = primal_stage<T>(g, STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st, "primal stage 2"))) return r;
     if ((r = primal_stage<T>(g, STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st, "primal stage 3"))) return r;
-    if ((r = primal_stage<T>(g, STAGE_FIN, c, W4, wn, s, W2, W3, T(0), out, st, "primal stage 4"))) return r;
+    if ((r = primal_stage<T>(g, STAGE_FIN, c, W4, wn, s, W2, W3, T(0), out, st, "primal stage 4", T(0), T(0), jpart)))
+      return r;
   }
   if (ckpt) {
     if constexpr (sizeof(T) == sizeof(float)) {
@@ -364,10 +369,14 @@ int adjoint_step(const adj_grid* g, const void* wn_in, const T* stages, const T*
   if ((r = adjoint_stage<T>(g, STAGE_VJP, c, sW2, a, g3, nup, dt / T(3), dt * T(0.5), nullptr, nullptr, g2, nullptr, st,
                             "adjoint stage 2")))
     return r;
+  // the mean-pressure objective's injection rides in the stage-1 kernel when nothing is added to
+  // w^_n after it (no Roe or boundary corrections)
+  const bool fuse = o && o->kind == ADJ_OBJ_MEAN_PRESSURE && c_n != 0.0 && g->flux == ADJ_FLUX_SPLIT &&
+                    g->bc_x != ADJ_BC_CHARACTERISTIC;
   if ((r = adjoint_stage<T>(g, STAGE_FIN, c, wn, a, g2, nup, dt / T(6), dt * T(0.5), g3, g4, wh, grad_s, st,
-                            "adjoint stage 1")))
+                            "adjoint stage 1", fuse ? c_n : 0.0)))
     return r;
-  if (o && o->kind != ADJ_OBJ_NONE && c_n != 0.0) {
+  if (!fuse && o && o->kind != ADJ_OBJ_NONE && c_n != 0.0) {
     if ((e = launch_objective<T>(c, o->kind, o->plane_i, o->pt_ref, wn, c_n, nullptr, wh,
                                  (double*)at(ws, L.partials), (double*)at(ws, L.scratch), st)))
       return hip_fail(e, "objective gradient");
@@ -407,6 +416,56 @@ static int primal_entry(const adj_grid* grid, const void* w_n, const void* s, vo
 int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out, void* ws,
                     size_t ws_bytes, void* stream) {
   return primal_entry(grid, w_n, s, w_np1, ckpt_out, nullptr, ws, ws_bytes, stream);
+}
+
+extern "C++" {
+// The mean-pressure objective of the new state rides in the final RK4 stage when that stage's output
+// is the new state (no Roe or boundary correction follows it).
+static bool fuse_meanp(const adj_grid* g, const adj_objective* o) {
+  return o->kind == ADJ_OBJ_MEAN_PRESSURE && g->time_scheme == ADJ_RK4 && g->flux == ADJ_FLUX_SPLIT &&
+         g->bc_x != ADJ_BC_CHARACTERISTIC;
+}
+
+template <typename T>
+static int primal_obj(const adj_grid* grid, const T* w_n, const T* s, T* w_np1, void* ckpt, T* stages,
+                      const adj_objective* obj, double weight, double* J_accum, void* ws, hipStream_t st) {
+  const Consts<T> c = consts<T>(grid);
+  const WsLayout L = layout(grid);
+  double* part = (double*)at(ws, L.partials);
+  const bool fuse = fuse_meanp(grid, obj);
+  int r;
+  if ((r = primal_step<T>(grid, w_n, s, w_np1, ckpt, stages, ws, st, fuse ? part : nullptr))) return r;
+  hipError_t e;
+  if (fuse)
+    e = launch_fold(part, primal_tiles<T>(c), J_accum, weight / (double)c.N, 1.0, st);
+  else
+    e = launch_objective<T>(c, obj->kind, obj->plane_i, obj->pt_ref, w_np1, weight, J_accum, nullptr, part,
+                            (double*)at(ws, L.scratch), st);
+  return e ? hip_fail(e, "objective of the new state") : ADJ_OK;
+}
+}  // extern "C++"
+
+int adj_primal_step_obj(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out,
+                        void* stages_out, const adj_objective* obj, double weight, double* J_accum, void* ws,
+                        size_t ws_bytes, void* stream) {
+  int r;
+  if ((r = check_grid(grid, true))) return r;
+  if ((r = check_ws(grid, ws, ws_bytes))) return r;
+  if ((r = check_obj(grid, obj))) return r;
+  if (!std::isfinite(weight)) return fail(ADJ_EINVAL, "weight must be finite");
+  const bool active = obj && obj->kind != ADJ_OBJ_NONE && weight != 0.0;
+  if (active && !J_accum) return fail(ADJ_EINVAL, "J_accum must be non-NULL");
+  if (!w_n || !w_np1) return fail(ADJ_EINVAL, "w_n and w_np1 must be non-NULL");
+  if (w_n == w_np1) return fail(ADJ_EINVAL, "w_np1 must not alias w_n");
+  if (ckpt_out && grid->precision != ADJ_F32) return fail(ADJ_EINVAL, "BF16 checkpoints need precision ADJ_F32");
+  if (stages_out && grid->ckpt_format != ADJ_CKPT_NATIVE) return fail(ADJ_EINVAL, "stage states are stored natively");
+  if (!active) return primal_entry(grid, w_n, s, w_np1, ckpt_out, stages_out, ws, ws_bytes, stream);
+  hipStream_t st = (hipStream_t)stream;
+  if (grid->precision == ADJ_F64)
+    return primal_obj<double>(grid, (const double*)w_n, (const double*)s, (double*)w_np1, nullptr, (double*)stages_out,
+                              obj, weight, J_accum, ws, st);
+  return primal_obj<float>(grid, (const float*)w_n, (const float*)s, (float*)w_np1, ckpt_out, (float*)stages_out, obj,
+                           weight, J_accum, ws, st);
 }
 
 int adj_primal_step_stages(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* stages_out,
@@ -817,14 +876,11 @@ int batch_adjoint(const adj_batch* b, int nm, const T* wn, const T* s, const T* 
   if ((e = launch_adjoint_stage_batch<T>(STAGE_VJP, tl, wl, ln, mm, b->dsa, nm, ablk, W2, a, g3, sig, T(3), T(0.5),
                                          nullptr, nullptr, g2, nullptr, st)))
     return hip_fail(e, "ensemble adjoint stage 2");
+  // the mean-pressure objective's c_n dj/dw(w_n) of every member is added inside the stage-1 kernel
+  const double* cn = b->obj == ADJ_OBJ_MEAN_PRESSURE ? c_n : nullptr;
   if ((e = launch_adjoint_stage_batch<T>(STAGE_FIN, tl, wl, ln, mm, b->dsa, nm, ablk, wn, a, g2, sig, T(6), T(0.5), g3,
-                                         g4, wh, grad_s, st)))
+                                         g4, wh, grad_s, st, cn)))
     return hip_fail(e, "ensemble adjoint stage 1");
-  if (c_n && b->obj == ADJ_OBJ_MEAN_PRESSURE) {
-    if ((e = launch_meanp_batch<T>(mm, b->dslm, b->slm.data(), 0, nm, wn, c_n, nullptr, wh,
-                                   (double*)at(ws, L.partials), st)))
-      return hip_fail(e, "ensemble objective gradient");
-  }
   return ADJ_OK;
 }
 

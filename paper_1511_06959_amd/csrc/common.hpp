@@ -38,6 +38,45 @@ struct Consts {
   T nuw[5];   // weight of the artificial viscosity on each adjoint component
 };
 
+// FP64 primitives of one cell from its five stored values (deviations w - wref), in one fixed order
+// of operations shared by every kernel that evaluates the mean-pressure objective or its gradient
+// (the objective kernels and the stage kernels that fuse them), so that they round alike.
+struct Q64 {
+  double rho, u[3], e, p, ri;
+};
+
+template <typename T>
+__device__ __forceinline__ Q64 q64_of(const Consts<T>& c, T w0, T w1, T w2, T w3, T w4, int mirror, double gamma) {
+  Q64 q;
+  q.rho = (double)w0 + (double)c.wref[0];
+  double m1 = (double)w1 + (double)c.wref[1];
+  if (mirror) m1 = -m1;
+  const double m2 = (double)w2 + (double)c.wref[2], m3 = (double)w3 + (double)c.wref[3];
+  const double Et = (double)w4 + (double)c.wref[4];
+  q.ri = 1.0 / q.rho;
+  q.u[0] = m1 * q.ri;
+  q.u[1] = m2 * q.ri;
+  q.u[2] = m3 * q.ri;
+  q.e = Et * q.ri - 0.5 * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
+  q.p = (gamma - 1.0) * q.rho * q.e;
+  return q;
+}
+
+// Mean pressure j = (1/N) sum p: weight * dj/dw at a cell is f (|u|^2/2, -u, 1) with
+// f = weight (gamma - 1)/N (gamma as the kernels hold it, in the state precision).
+__device__ __forceinline__ double meanp_factor(double weight, double gamma, long long N) {
+  return weight * (gamma - 1.0) / (double)N;
+}
+template <typename T>
+__device__ __forceinline__ void meanp_grad_terms(const Q64& q, double f, T t[5]) {
+  const double usq = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+  t[0] = (T)(f * 0.5 * usq);
+  t[1] = (T)(-f * q.u[0]);
+  t[2] = (T)(-f * q.u[1]);
+  t[3] = (T)(-f * q.u[2]);
+  t[4] = (T)f;
+}
+
 // Buffer loads: a 128-bit resource (base, byte size) in scalar registers plus a 32-bit per-lane
 // byte offset and a scalar offset.  One offset per cell then serves every field of every array
 // (the scalar offset selects the field), instead of a 64-bit address per load; a read outside

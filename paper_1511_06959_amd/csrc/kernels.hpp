@@ -10,9 +10,16 @@ enum { STAGE_VJP = 0 };                                  // adjoint stage modes 
 
 // STAGE_AFF: out = ca * wn + cb * W + cR * R(W; s)  (the SSP-RK3 stages)
 // conv = 0: R without the split-form convective flux (the Roe option adds its own afterwards)
+// jpart (STAGE_FIN, may be NULL): receives one FP64 partial per tile (primal_tiles of them), the sum of
+// the pressures of the stage output over the tile's cells (the mean-pressure objective of the step)
 template <typename T>
 hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
-                               const T* W3, T cR, T* out, hipStream_t st, T ca = T(0), T cb = T(0), int conv = 1);
+                               const T* W3, T cR, T* out, hipStream_t st, T ca = T(0), T cb = T(0), int conv = 1,
+                               double* jpart = nullptr);
+template <typename T>
+int primal_tiles(const Consts<T>& c);
+// dst = beta dst + alpha (sum of the n partials), in a fixed order (one work-group)
+hipError_t launch_fold(const double* partials, int n, double* dst, double alpha, double beta, hipStream_t st);
 
 // SSP-RK3 reverse step, after the three stage transposes g3 (at u2), g2 (at u1), g1 (at w_n):
 // rk3_mid:     h = g2 + g3/4                               (in place of g2; k^1 = dt/6 a + dt h)
@@ -24,9 +31,12 @@ hipError_t launch_rk3_combine(const T* a, const T* g1, const T* h, const T* g3, 
                               hipStream_t st);
 
 // conv = 0: without the transpose of the split-form convective flux
+// objw (STAGE_FIN only): weight c_n of the mean-pressure objective, whose c_n dj/dw(w_n) is added to
+// w^_n at each cell (0: none)
 template <typename T>
 hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,
-                                T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st, int conv = 1);
+                                T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st, int conv = 1,
+                                double objw = 0.0);
 
 // Roe flux option: the Roe convective flux F of every face (roe.hip), added after the stage
 // kernel (launched with conv = 0) that wrote `out` from the same W:
@@ -85,10 +95,12 @@ template <typename T>
 hipError_t launch_primal_stage_batch(int mode, int tile, const BoxDesc<T>* boxes, const int* start, int nbox,
                                      int nblocks, const T* W, const T* wn, const T* s, const T* W2, const T* W3,
                                      T cfac, T* out, hipStream_t st);
+// cn (STAGE_FIN, may be NULL): per-member weights of the mean-pressure objective (see objw)
 template <typename T>
 hipError_t launch_adjoint_stage_batch(int mode, int tile, int wall, int lnu, const BoxDesc<T>* mems, const int* start,
                                       int nmem, int nblocks, const T* W, const T* a, const T* gnext, const T* sigma1,
-                                      T da, T mg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st);
+                                      T da, T mg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st,
+                                      const double* cn = nullptr);
 template <typename T>
 hipError_t launch_sigma1_batch(const BoxDesc<T>* boxes, const int* start, int nbox, int nblocks, const T* w, T* out,
                                hipStream_t st);

@@ -117,7 +117,8 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
                                                  const T* __restrict__ W, const T* __restrict__ wn,
                                                  const T* __restrict__ s, const T* __restrict__ W2,
                                                  const T* __restrict__ W3, const T cR, T* __restrict__ out,
-                                                 const T ca = T(0), const T cb = T(0)) {
+                                                 const T ca = T(0), const T cb = T(0), double* __restrict__ jpart = nullptr,
+                                                 const int tile = 0) {
   constexpr int NT = TX * TY * TZ;
   using Bx = TBox<TX, TY, TZ, 1, 1>;
   constexpr int NB = Bx::NB;
@@ -197,26 +198,48 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
     }
   }
   __syncthreads();
-  if (!active) return;
-  const int st[3] = {1, Bx::SY, Bx::SZ};
-  const int p = (tz + 1) * Bx::SZ + (ty + 1) * Bx::SY + (tx + 1);
-  T R[5] = {sv[0], sv[1], sv[2], sv[3], sv[4]};
-  residual_dir<T, NB, 0, CONV>(sm, st, p, c, R);
-  __builtin_amdgcn_sched_barrier(0);
-  residual_dir<T, NB, 1, CONV>(sm, st, p, c, R);
-  __builtin_amdgcn_sched_barrier(0);
-  residual_dir<T, NB, 2, CONV>(sm, st, p, c, R);
-  __builtin_amdgcn_sched_barrier(0);
-  if (MODE == STAGE_RES) {
+  double pv = 0.0;  // the new state's pressure at the cell (final stage with jpart)
+  if (active) {
+    const int st[3] = {1, Bx::SY, Bx::SZ};
+    const int p = (tz + 1) * Bx::SZ + (ty + 1) * Bx::SY + (tx + 1);
+    T R[5] = {sv[0], sv[1], sv[2], sv[3], sv[4]};
+    residual_dir<T, NB, 0, CONV>(sm, st, p, c, R);
+    __builtin_amdgcn_sched_barrier(0);
+    residual_dir<T, NB, 1, CONV>(sm, st, p, c, R);
+    __builtin_amdgcn_sched_barrier(0);
+    residual_dir<T, NB, 2, CONV>(sm, st, p, c, R);
+    __builtin_amdgcn_sched_barrier(0);
+    if (MODE == STAGE_RES) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out[v * N + gi] = R[v];
-  } else if (MODE == STAGE_LIN || MODE == STAGE_AFF) {
+      for (int v = 0; v < 5; ++v) out[v * N + gi] = R[v];
+    } else if (MODE == STAGE_LIN || MODE == STAGE_AFF) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out[v * N + gi] = base[v] + cR * R[v];
-  } else {
-    const T third = T(1) / T(3), h6 = c.dt / T(6);
+      for (int v = 0; v < 5; ++v) out[v * N + gi] = base[v] + cR * R[v];
+    } else {
+      const T third = T(1) / T(3), h6 = c.dt / T(6);
+      T o[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out[v * N + gi] = (base[v] + (PREW ? wq[v] : W[v * N + gi])) * third + h6 * R[v];
+      for (int v = 0; v < 5; ++v) {
+        o[v] = (base[v] + (PREW ? wq[v] : W[v * N + gi])) * third + h6 * R[v];
+        out[v * N + gi] = o[v];
+      }
+      if (MODE == STAGE_FIN && jpart) pv = q64_of(c, o[0], o[1], o[2], o[3], o[4], 0, (double)c.gamma).p;
+    }
+  }
+  if (MODE == STAGE_FIN && jpart) {
+    // the tile's sum of the new state's pressures (the mean-pressure objective of the step's
+    // output), in a fixed order: butterfly within each wavefront, then the wavefronts in order
+    __shared__ double red[NT / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pv += __shfl_xor(pv, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = pv;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < NT / 64; ++k) t += red[k];
+      jpart[tile] = t;
+    }
   }
 }
 
@@ -224,10 +247,12 @@ template <typename T, int MODE, int CONV, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, const T* __restrict__ W,
                                                                const T* __restrict__ wn, const T* __restrict__ s,
                                                                const T* __restrict__ W2, const T* __restrict__ W3,
-                                                               T cR, T* __restrict__ out, T ca, T cb) {
+                                                               T cR, T* __restrict__ out, T ca, T cb,
+                                                               double* __restrict__ jpart) {
   int x0, y0, z0;
-  tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
-  primal_tile_body<T, MODE, CONV, TX, TY, TZ>(c, x0, y0, z0, W, wn, s, W2, W3, cR, out, ca, cb);
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  tile_origin<TX, TY, TZ>(t, c.nx, c.ny, x0, y0, z0);
+  primal_tile_body<T, MODE, CONV, TX, TY, TZ>(c, x0, y0, z0, W, wn, s, W2, W3, cR, out, ca, cb, jpart, t);
 }
 
 // Ensemble form: work-group -> (box, tile) through the tile offsets `start`; every array is
@@ -491,7 +516,7 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
                                                   const T* __restrict__ gnext, const T* __restrict__ nu,
                                                   const T nscale, const T ca, const T cg, const T* __restrict__ g3,
                                                   const T* __restrict__ g4, T* __restrict__ out,
-                                                  T* __restrict__ grad_s) {
+                                                  T* __restrict__ grad_s, const double objw) {
   constexpr int NT = TX * TY * TZ;
   constexpr int HX = WALL ? 2 : 1;
   using Bx = TBox<TX, TY, TZ, HX, 1>;
@@ -659,10 +684,19 @@ __device__ __forceinline__ void adjoint_tile_body(const Consts<T>& c, const int 
     for (int v = 0; v < 5; ++v) out[v * N + gi] = g[v];
   } else {
     const T dt = c.dt, h2 = T(0.5) * c.dt;
+    // the mean-pressure objective's c_n dj/dw(w_n) at the cell (W is w_n in this stage), added to
+    // w^_n as the objective kernel would add it afterwards
+    T inj[5] = {T(0), T(0), T(0), T(0), T(0)};
+    if (objw != 0.0) {
+      const Q64 qc = q64_of(c, W[gi], W[N + gi], W[2 * N + gi], W[3 * N + gi], W[4 * N + gi], 0, (double)c.gamma);
+      meanp_grad_terms(qc, meanp_factor(objw, (double)c.gamma, N), inj);
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const long long q = v * N + gi;
-      out[q] = fa[v] + g[v] + f2[v] + f3[v] + f4[v];
+      T o = fa[v] + g[v] + f2[v] + f3[v] + f4[v];
+      if (objw != 0.0) o += inj[v];
+      out[q] = o;
       // explicit fused order: every instantiation (and the ensemble form) rounds identically
       if (grad_s) grad_s[q] = fma(dt, fa[v], fma(dt, f4[v], fma(h2, f3[v] + f2[v], gs[v])));
     }
@@ -674,11 +708,12 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
                                                                 const T* __restrict__ a, const T* __restrict__ gnext,
                                                                 const T* __restrict__ nu, T ca, T cg,
                                                                 const T* __restrict__ g3, const T* __restrict__ g4,
-                                                                T* __restrict__ out, T* __restrict__ grad_s) {
+                                                                T* __restrict__ out, T* __restrict__ grad_s,
+                                                                double objw) {
   int x0, y0, z0;
   tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
   adjoint_tile_body<T, MODE, WALL, LNU, CONV, TX, TY, TZ>(c, x0, y0, z0, W, a, gnext, nu, T(1), ca, cg, g3, g4, out,
-                                                          grad_s);
+                                                          grad_s, objw);
 }
 
 // Ensemble form over the members: state arrays (W, the sigma_1 field) at the member's box,
@@ -688,7 +723,8 @@ template <typename T, int MODE, int WALL, int LNU, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage_batch(
     const BoxDesc<T>* __restrict__ mems, const int* __restrict__ start, int nmem, const T* __restrict__ W,
     const T* __restrict__ a, const T* __restrict__ gnext, const T* __restrict__ sigma1, T da, T mg,
-    const T* __restrict__ g3, const T* __restrict__ g4, T* __restrict__ out, T* __restrict__ grad_s) {
+    const T* __restrict__ g3, const T* __restrict__ g4, T* __restrict__ out, T* __restrict__ grad_s,
+    const double* __restrict__ cn) {
   const int blk = xcd_tile(blockIdx.x, gridDim.x);
   const int m = find_box(start, nmem, blk);
   const Consts<T> c = mems[m].c;
@@ -698,7 +734,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage_batch(
   adjoint_tile_body<T, MODE, WALL, LNU, 1, TX, TY, TZ>(
       c, x0, y0, z0, W + o, a + ao, gnext ? gnext + ao : nullptr, LNU ? sigma1 + mems[m].off : nullptr,
       mems[m].lam, c.dt / da, c.dt * mg, g3 ? g3 + ao : nullptr, g4 ? g4 + ao : nullptr, out + ao,
-      grad_s ? grad_s + ao : nullptr);
+      grad_s ? grad_s + ao : nullptr, (MODE != STAGE_VJP && cn) ? cn[m] : 0.0);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -765,32 +801,47 @@ constexpr bool adjoint_fits() {
 
 template <typename T, int CONV, int TX, int TY, int TZ>
 static void primal_launch(ProfScope& ps, int mode, const Consts<T>& c, const T* W, const T* wn, const T* s,
-                          const T* W2, const T* W3, T cR, T* out, hipStream_t st, T ca, T cb) {
+                          const T* W2, const T* W3, T cR, T* out, hipStream_t st, T ca, T cb, double* jpart) {
   const dim3 grid = tile_grid<TX, TY, TZ>(c.nx, c.ny, c.nz), blk(TX * TY * TZ);
+  double* nj = nullptr;
   if (mode == STAGE_RES)
     timed_launch(ps, k_primal_stage<T, STAGE_RES, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
-                 cb);
+                 cb, nj);
   else if (mode == STAGE_LIN)
     timed_launch(ps, k_primal_stage<T, STAGE_LIN, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
-                 cb);
+                 cb, nj);
   else if (mode == STAGE_AFF)
     timed_launch(ps, k_primal_stage<T, STAGE_AFF, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
-                 cb);
+                 cb, nj);
   else
     timed_launch(ps, k_primal_stage<T, STAGE_FIN, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
-                 cb);
+                 cb, jpart);
 }
+
+// Work-groups (tiles) of a primal-stage launch in the current tile shape: the number of per-tile
+// partial sums a final stage with jpart writes.
+template <typename T>
+int primal_tiles(const Consts<T>& c) {
+  int n = 0;
+  with_tile(tile_choice(ADJ_PROF_PRIMAL_STAGE, sizeof(T) == 8), [&](auto S) {
+    using Sh = decltype(S);
+    n = (int)tile_grid<Sh::tx, Sh::ty, Sh::tz>(c.nx, c.ny, c.nz).x;
+  });
+  return n;
+}
+template int primal_tiles<float>(const Consts<float>&);
+template int primal_tiles<double>(const Consts<double>&);
 
 template <typename T>
 hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
-                               const T* W3, T cR, T* out, hipStream_t st, T ca, T cb, int conv) {
+                               const T* W3, T cR, T* out, hipStream_t st, T ca, T cb, int conv, double* jpart) {
   ProfScope ps(ADJ_PROF_PRIMAL_STAGE, st, true);
   with_tile(tile_choice(ADJ_PROF_PRIMAL_STAGE, sizeof(T) == 8), [&](auto S) {
     using Sh = decltype(S);
     if (conv)
-      primal_launch<T, 1, Sh::tx, Sh::ty, Sh::tz>(ps, mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb);
+      primal_launch<T, 1, Sh::tx, Sh::ty, Sh::tz>(ps, mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb, jpart);
     else
-      primal_launch<T, 0, Sh::tx, Sh::ty, Sh::tz>(ps, mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb);
+      primal_launch<T, 0, Sh::tx, Sh::ty, Sh::tz>(ps, mode, c, W, wn, s, W2, W3, cR, out, st, ca, cb, jpart);
   });
   return hipGetLastError();
 }
@@ -798,29 +849,32 @@ hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T
 template <typename T, int WALL, int LNU, int CONV, int TX, int TY, int TZ>
 static void adjoint_launch_conv(ProfScope& ps, int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext,
                                 const T* nu, T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s,
-                                hipStream_t st) {
+                                hipStream_t st, double objw) {
   const dim3 grid = tile_grid<TX, TY, TZ>(c.nx, c.ny, c.nz), blk(TX * TY * TZ);
   if (mode == STAGE_VJP)
     timed_launch(ps, k_adjoint_stage<T, STAGE_VJP, WALL, LNU, CONV, TX, TY, TZ>, grid, blk, st, c, W, a, gnext, nu, ca,
-                 cg, g3, g4, out, grad_s);
+                 cg, g3, g4, out, grad_s, 0.0);
   else
     timed_launch(ps, k_adjoint_stage<T, STAGE_FIN, WALL, LNU, CONV, TX, TY, TZ>, grid, blk, st, c, W, a, gnext, nu, ca,
-                 cg, g3, g4, out, grad_s);
+                 cg, g3, g4, out, grad_s, objw);
 }
 
 template <typename T, int WALL, int LNU, int TX, int TY, int TZ>
 static void adjoint_launch(ProfScope& ps, int mode, int conv, const Consts<T>& c, const T* W, const T* a,
                            const T* gnext, const T* nu, T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s,
-                           hipStream_t st) {
+                           hipStream_t st, double objw) {
   if (conv)
-    adjoint_launch_conv<T, WALL, LNU, 1, TX, TY, TZ>(ps, mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
+    adjoint_launch_conv<T, WALL, LNU, 1, TX, TY, TZ>(ps, mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st,
+                                                     objw);
   else
-    adjoint_launch_conv<T, WALL, LNU, 0, TX, TY, TZ>(ps, mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
+    adjoint_launch_conv<T, WALL, LNU, 0, TX, TY, TZ>(ps, mode, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st,
+                                                     objw);
 }
 
 template <typename T>
 hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const T* a, const T* gnext, const T* nu,
-                                T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st, int conv) {
+                                T ca, T cg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st, int conv,
+                                double objw) {
   ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st, true);
   with_variant(c.wall, nu != nullptr, [&](auto WL, auto LN) {
     constexpr int WALL = decltype(WL)::value, LNU = decltype(LN)::value;
@@ -828,9 +882,10 @@ hipError_t launch_adjoint_stage(int mode, const Consts<T>& c, const T* W, const 
       using Sh = decltype(S);
       if constexpr (adjoint_fits<T, WALL, LNU, Sh>())
         adjoint_launch<T, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>(ps, mode, conv, c, W, a, gnext, nu, ca, cg, g3, g4, out,
-                                                             grad_s, st);
+                                                             grad_s, st, objw);
       else
-        adjoint_launch<T, WALL, LNU, 16, 4, 4>(ps, mode, conv, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st);
+        adjoint_launch<T, WALL, LNU, 16, 4, 4>(ps, mode, conv, c, W, a, gnext, nu, ca, cg, g3, g4, out, grad_s, st,
+                                               objw);
     });
   });
   return hipGetLastError();
@@ -884,7 +939,8 @@ hipError_t launch_primal_stage_batch(int mode, int tile, const BoxDesc<T>* boxes
 template <typename T>
 hipError_t launch_adjoint_stage_batch(int mode, int tile, int wall, int lnu, const BoxDesc<T>* mems, const int* start,
                                       int nmem, int nblocks, const T* W, const T* a, const T* gnext, const T* sigma1,
-                                      T da, T mg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st) {
+                                      T da, T mg, const T* g3, const T* g4, T* out, T* grad_s, hipStream_t st,
+                                      const double* cn) {
   ProfScope ps(ADJ_PROF_ADJOINT_STAGE, st, true);
   with_variant(wall, lnu, [&](auto WL, auto LN) {
     constexpr int WALL = decltype(WL)::value, LNU = decltype(LN)::value;
@@ -893,11 +949,11 @@ hipError_t launch_adjoint_stage_batch(int mode, int tile, int wall, int lnu, con
       if constexpr (adjoint_fits<T, WALL, LNU, Sh>()) {
         const dim3 grid(nblocks), blk(Sh::tx * Sh::ty * Sh::tz);
         if (mode == STAGE_VJP)
-          timed_launch(ps, k_adjoint_stage_batch<T, STAGE_VJP, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, mems, start, nmem, W, a, gnext, sigma1, da, mg, g3, g4,
-                       out, grad_s);
+          timed_launch(ps, k_adjoint_stage_batch<T, STAGE_VJP, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, mems,
+                       start, nmem, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, (const double*)nullptr);
         else
-          timed_launch(ps, k_adjoint_stage_batch<T, STAGE_FIN, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, mems, start, nmem, W, a, gnext, sigma1, da, mg, g3, g4,
-                       out, grad_s);
+          timed_launch(ps, k_adjoint_stage_batch<T, STAGE_FIN, WALL, LNU, Sh::tx, Sh::ty, Sh::tz>, grid, blk, st, mems,
+                       start, nmem, W, a, gnext, sigma1, da, mg, g3, g4, out, grad_s, cn);
       }
     });
   });
@@ -909,22 +965,22 @@ hipError_t launch_adjoint_stage_batch(int mode, int tile, int wall, int lnu, con
                                                    const T*, const T*, const T*, const T*, T, T*, hipStream_t);  \
   template hipError_t launch_adjoint_stage_batch<T>(int, int, int, int, const BoxDesc<T>*, const int*, int, int,  \
                                                     const T*, const T*, const T*, const T*, T, T, const T*,       \
-                                                    const T*, T*, T*, hipStream_t);
+                                                    const T*, T*, T*, hipStream_t, const double*);
 ADJNS_BATCH_INST(float)
 ADJNS_BATCH_INST(double)
 #undef ADJNS_BATCH_INST
 
 template hipError_t launch_primal_stage<float>(int, const Consts<float>&, const float*, const float*, const float*,
                                                const float*, const float*, float, float*, hipStream_t, float, float,
-                                               int);
+                                               int, double*);
 template hipError_t launch_primal_stage<double>(int, const Consts<double>&, const double*, const double*, const double*,
                                                 const double*, const double*, double, double*, hipStream_t, double,
-                                                double, int);
+                                                double, int, double*);
 template hipError_t launch_adjoint_stage<float>(int, const Consts<float>&, const float*, const float*, const float*,
                                                 const float*, float, float, const float*, const float*, float*,
-                                                float*, hipStream_t, int);
+                                                float*, hipStream_t, int, double);
 template hipError_t launch_adjoint_stage<double>(int, const Consts<double>&, const double*, const double*,
                                                  const double*, const double*, double, double, const double*,
-                                                 const double*, double*, double*, hipStream_t, int);
+                                                 const double*, double*, double*, hipStream_t, int, double);
 
 }  // namespace adjns

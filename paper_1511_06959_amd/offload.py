@@ -21,7 +21,8 @@ import numpy as np
 import torch
 
 from . import (CKPT_BF16, OBJ_NONE, adjoint_step, ckpt_bytes, ckpt_decode, ckpt_encode, objective_and_grad,
-               primal_step, workspace)
+               workspace)
+from .sweep import step_obj
 
 
 class _PinnedStore:
@@ -216,14 +217,13 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
         objective_and_grad(g, obj, cur, ws, weight=float(weights[0]), J_accum=J)
     for n in range(nsteps):
         take(n + 1)
+        wgt = float(weights[n + 1]) if use_obj else 0.0
         if traj.bf16:
-            primal_step(g, cur, s, nxt, ws, ckpt_out=traj.buffer(n + 1))
+            step_obj(g, cur, s, nxt, ws, obj, wgt, J, ckpt_out=traj.buffer(n + 1))
         else:
             # the step reads w_n from its buffer and writes w_{n+1} into the next one
-            primal_step(g, cur, s, traj.buffer(n + 1), ws)
+            step_obj(g, cur, s, traj.buffer(n + 1), ws, obj, wgt, J)
             nxt = traj.buffer(n + 1)
-        if use_obj and weights[n + 1] != 0.0:
-            objective_and_grad(g, obj, nxt, ws, weight=float(weights[n + 1]), J_accum=J)
         send(n + 1)
         if traj.bf16:
             cur, nxt = nxt, cur

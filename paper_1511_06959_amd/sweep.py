@@ -14,7 +14,18 @@ Only scheduling happens here; all arithmetic runs in the library's kernels.
 import torch
 
 from . import (CKPT_BF16, OBJ_NONE, Grid, Objective, adjoint_step, adjoint_step_stages, ckpt_bytes, energy_vhat,
-               objective_and_grad, primal_step, primal_step_stages, workspace)
+               objective_and_grad, primal_step, primal_step_obj, primal_step_stages, workspace)
+
+
+def step_obj(g, w, s, out, ws, obj, weight, J, ckpt_out=None, stages_out=None):
+    """One primal step w -> out that adds weight * j(out) to J when an objective and a non-zero
+    weight are given (the library fuses the mean pressure into the step), else a plain step."""
+    if obj is not None and obj.kind != OBJ_NONE and weight != 0.0 and J is not None:
+        primal_step_obj(g, w, s, out, ws, obj, weight, J, ckpt_out=ckpt_out, stages_out=stages_out)
+    elif stages_out is not None:
+        primal_step_stages(g, w, s, out, stages_out, ws)
+    else:
+        primal_step(g, w, s, out, ws, ckpt_out=ckpt_out)
 
 
 class Trajectory:
@@ -62,16 +73,13 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
     if use_obj and weights[0] != 0.0:
         objective_and_grad(g, obj, cur, ws, weight=float(weights[0]), J_accum=J)
     for n in range(nsteps):
+        wgt = float(weights[n + 1]) if use_obj else 0.0
         if bf16:
-            primal_step(g, cur, s, nxt, ws, ckpt_out=traj.slot(n + 1))
+            step_obj(g, cur, s, nxt, ws, obj, wgt, J, ckpt_out=traj.slot(n + 1))
         else:
-            if traj.stages is not None:
-                primal_step_stages(g, cur, s, traj.slot(n + 1), traj.stage_slot(n), ws)
-            else:
-                primal_step(g, cur, s, traj.slot(n + 1), ws)
+            step_obj(g, cur, s, traj.slot(n + 1), ws, obj, wgt, J,
+                     stages_out=traj.stage_slot(n) if traj.stages is not None else None)
             nxt = traj.slot(n + 1)
-        if use_obj and weights[n + 1] != 0.0:
-            objective_and_grad(g, obj, nxt, ws, weight=float(weights[n + 1]), J_accum=J)
         if bf16:
             cur, nxt = nxt, cur
         else:
@@ -234,11 +242,10 @@ class RevolveSweep:
         if self.cur_step != i:
             self._load(i)
         for n in range(i, j):
-            primal_step(self.gn, self.cur, self.s, self.tmp, self.ws)
+            wgt = float(self.weights[n + 1]) if (J is not None and self.use_obj) else 0.0
+            step_obj(self.gn, self.cur, self.s, self.tmp, self.ws, self.obj, wgt, J)
             self.cur, self.tmp = self.tmp, self.cur
             self.advanced += 1
-            if J is not None and self.use_obj and self.weights[n + 1] != 0.0:
-                objective_and_grad(self.gn, self.obj, self.cur, self.ws, weight=float(self.weights[n + 1]), J_accum=J)
         self.cur_step = j
 
     # -- sweeps ------------------------------------------------------------------------------
@@ -263,10 +270,9 @@ class RevolveSweep:
         # the working state is w_{N-1}; the final state w_N feeds J and the terminal adjoint
         if self.cur_step != self.nsteps - 1:
             self._advance(self.cur_step, self.nsteps - 1, J)
-        primal_step(self.gn, self.cur, self.s, self.wN, self.ws)
+        step_obj(self.gn, self.cur, self.s, self.wN, self.ws, self.obj,
+                 float(self.weights[self.nsteps]) if self.use_obj else 0.0, J)
         self.advanced += 1
-        if self.use_obj and self.weights[self.nsteps] != 0.0:
-            objective_and_grad(self.gn, self.obj, self.wN, self.ws, weight=float(self.weights[self.nsteps]), J_accum=J)
         return J
 
     def backward(self, scale=1.0, grad_s=None, progress=None):
@@ -365,12 +371,11 @@ class SegmentSweep:
             objective_and_grad(self.gn, self.obj, cur, self.ws, weight=float(self.weights[0]), J_accum=J)
         for n in range(self.nsteps):
             out = self.wN if n + 1 == self.nsteps else nxt
-            primal_step(self.gn, cur, self.s, out, self.ws)
+            step_obj(self.gn, cur, self.s, out, self.ws, self.obj, float(self.weights[n + 1]) if self.use_obj else 0.0,
+                     J)
             self.advanced += 1
             if (n + 1) % self.seg == 0 and n + 1 < self.nsteps:
                 self._store((n + 1) // self.seg, out)
-            if self.use_obj and self.weights[n + 1] != 0.0:
-                objective_and_grad(self.gn, self.obj, out, self.ws, weight=float(self.weights[n + 1]), J_accum=J)
             cur, nxt = out, cur
         return J
 

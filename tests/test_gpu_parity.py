@@ -290,3 +290,52 @@ def test_reference_state_offset_f64(orc, bc_x):
     adj.energy_vhat(g, wd, dev(a), E, ws)
     Er, _ = orc.energy_vhat(og, w, a)
     assert abs(host(E)[0] - Er) <= 1e-12 * abs(Er)
+
+
+@pytest.mark.parametrize("precision", [adj.F64, adj.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("kind,bc_x,scheme,flux", [
+    (W.OBJ_MEAN_PRESSURE, 0, adj.RK4, adj.FLUX_SPLIT), (W.OBJ_MEAN_PRESSURE, 1, adj.RK4, adj.FLUX_SPLIT),
+    (W.OBJ_MEAN_PRESSURE, 0, adj.SSPRK3, adj.FLUX_SPLIT), (W.OBJ_MEAN_PRESSURE, 1, adj.RK4, adj.FLUX_ROE),
+    (W.OBJ_KE_DISSIPATION, 0, adj.RK4, adj.FLUX_SPLIT), (W.OBJ_PT_LOSS_PLANE, 1, adj.RK4, adj.FLUX_SPLIT)],
+    ids=["meanp", "meanp-walls", "meanp-ssprk3", "meanp-roe", "ked", "ptloss-walls"])
+def test_primal_step_with_objective(orc, precision, kind, bc_x, scheme, flux):
+    # the step that also accumulates the objective of its new state (fused into the final stage for
+    # the mean pressure on RK4 split-flux grids) writes the same state as the plain step, bit for
+    # bit, and the same J as the objective call to rounding of the sum, which the oracle confirms
+    shape = (37, 9, 6)
+    L = (2.0, 1.3, 1.7)
+    w = smooth_state(shape, L, seed=12)
+    ref = tuple(w.reshape(5, -1).mean(axis=1)) if precision == adj.F32 else None
+    g = adj.Grid.make(shape, L, 0.02, 0.004, bc_x=bc_x, precision=precision, w_ref=ref, time_scheme=scheme, flux=flux)
+    og = orc.make_grid(shape, L, 1.4, 0.72, 0.02, 0.004, bc_x, scheme, flux)
+    dt = g.dtype
+    s = 1e-2 * np.random.default_rng(13).standard_normal(w.size)
+    obj = adj.Objective.make(kind, 20, 1.1)
+    ws = adj.workspace(g)
+    wd, sd = dev(g.to_stored(w), dt), dev(s, dt)
+    plain = torch.empty_like(wd)
+    adj.primal_step(g, wd, sd, plain, ws)
+    J1 = torch.full((1,), 0.5, dtype=torch.float64, device="cuda")
+    adj.objective_and_grad(g, obj, plain, ws, weight=0.3, J_accum=J1)
+    out = torch.empty_like(wd)
+    J2 = torch.full((1,), 0.5, dtype=torch.float64, device="cuda")
+    adj.primal_step_obj(g, wd, sd, out, ws, obj, 0.3, J2)
+    assert np.array_equal(host(out), host(plain))
+    assert abs(host(J2)[0] - host(J1)[0]) <= 1e-14 * abs(host(J1)[0])
+    jr = orc.objective(og, orc.make_obj(kind, 20, 1.1), orc.primal_step(og, w, s), grad=False)
+    tol = 1e-12 if precision == adj.F64 else 1e-6
+    assert abs(host(J2)[0] - (0.5 + 0.3 * jr)) <= tol * abs(0.5 + 0.3 * jr)
+    if precision == adj.F32 and scheme == adj.RK4:
+        gb = adj.Grid.make(shape, L, 0.02, 0.004, bc_x=bc_x, precision=precision, ckpt_format=adj.CKPT_BF16, w_ref=ref,
+                           flux=flux)
+        r1 = torch.zeros(adj.ckpt_bytes(gb), dtype=torch.uint8, device="cuda")
+        r2 = torch.zeros_like(r1)
+        adj.primal_step(gb, wd, sd, plain, ws, ckpt_out=r1)
+        adj.primal_step_obj(gb, wd, sd, out, ws, obj, 0.3, J2, ckpt_out=r2)
+        assert torch.equal(r1, r2) and torch.equal(out, plain)
+    if scheme == adj.RK4:
+        st1 = torch.empty(3 * w.size, dtype=dt, device="cuda")
+        st2 = torch.empty_like(st1)
+        adj.primal_step_stages(g, wd, sd, plain, st1, ws)
+        adj.primal_step_obj(g, wd, sd, out, ws, obj, 0.3, J2, stages_out=st2)
+        assert torch.equal(st1, st2) and torch.equal(out, plain)
