@@ -15,8 +15,10 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "libnsoracle.so")
+# ADJNS_ORACLE_SO selects another build of the same source (the sanitizer build of the tests)
+_SO = os.environ.get("ADJNS_ORACLE_SO") or os.path.join(_HERE, "libnsoracle.so")
 _SRC = os.path.join(_HERE, "ns_oracle.cpp")
+SANITIZED_SO = os.path.join(_HERE, "libnsoracle_san.so")
 
 
 class OrcGrid(ctypes.Structure):
@@ -50,6 +52,18 @@ def build(force=True):
         subprocess.check_call(cmd)
         os.replace(_SO + ".tmp", _SO)
     return _SO
+
+
+def build_sanitized():
+    """The oracle built for checking the oracle itself: AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal), no optimisation that hides frames, one OpenMP thread per call as usual.
+    Load it in a process started with the ASan runtime preloaded (see tests/test_oracle_sanitized.py)."""
+    cmd = ["g++", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-fopenmp", "-fPIC", "-shared", "-std=c++17",
+           "-o", SANITIZED_SO + ".tmp", _SRC]
+    subprocess.check_call(cmd)
+    os.replace(SANITIZED_SO + ".tmp", SANITIZED_SO)
+    return SANITIZED_SO
 
 
 _lib = None
