@@ -415,12 +415,14 @@ def run_plan(wl, precision, K, warmup, tune=True, bf16=True):
     import gc
     gc.collect()
     torch.cuda.empty_cache()
-    free, _ = torch.cuda.mem_get_info()
-    print(f"[bench] {'f64' if precision == adj.F64 else 'f32'}: {free / 1e9:.1f} GB free, torch holds "
-          f"{torch.cuda.memory_allocated() / 1e9:.1f} GB allocated, {torch.cuda.memory_reserved() / 1e9:.1f} GB reserved",
-          file=sys.stderr, flush=True)
-    # besides the checkpoints, the window's working states, adjoints and a margin stay free
-    plan = plan_for(g, PLAN_STEPS, max(0, free - 6 * 5 * g.ncells * g.dtype.itemsize - (4 << 30)))
+    free, total = torch.cuda.mem_get_info()
+    held = torch.cuda.memory_allocated()
+    print(f"[bench] {'f64' if precision == adj.F64 else 'f32'}: {free / 1e9:.1f} GB free of {total / 1e9:.1f}, torch "
+          f"holds {held / 1e9:.1f} GB", file=sys.stderr, flush=True)
+    # the plan of a process that runs this window alone: the device's memory less what this one
+    # holds (grid, workspace), the window's working states and adjoints, and a margin for the
+    # runtime (an earlier window of this process may leave memory that the runtime has not returned)
+    plan = plan_for(g, PLAN_STEPS, max(0, total - held - 6 * 5 * g.ncells * g.dtype.itemsize - (6 << 30)))
 
     def sweep_of(steps, wts):
         if plan["schedule"] == "segments":
@@ -583,6 +585,9 @@ def schedule_text(r, K):
 
 
 def main_c5(args):
+    if args.fl or args.ts or args.nw:
+        raise SystemExit("--flux, --time-scheme and --nu-weight apply to the store-all window workloads (tgv64, "
+                         "turb384_sample, wake, spatial_wake); the 384^3 plan runs the configured RK4 split-flux case")
     import torch
 
     import paper_1511_06959_amd as adj
@@ -644,9 +649,10 @@ def main_c5(args):
             "plan_steps": PLAN_STEPS,
             "dt": wl.dt,
             "lambda": wl.lam,
-            "step": "one time step of the plan: primal step with snapshot encoding, its share of the binomial "
-                    "recomputation, reverse step (decode, stage recomputation, sigma_1, four transposed stages, "
-                    "objective injection, body-force gradient)",
+            "step": "one time step of the plan: its primal steps (the forward step with snapshot encoding and "
+                    "the re-advance of the segment, or its share of the binomial recomputation) with the objective "
+                    "folded in, and the reverse step (sigma_1, four transposed stages with the objective's "
+                    "injection, body-force gradient; with binomial plans also the decode and stage recomputation)",
             "schedule": schedule_text(r32, K),
             "plan": r32["plan"],
             "window": r32["window"],

@@ -80,9 +80,10 @@ def run_adjoint(n, precision, reps, stages, tune=False, flux="split"):
 
 
 def run_step384(reps, cache=None, tune=True):
-    """Time steps of the 384^3 decaying-turbulence case as the benchmark runs them (FP32 states
-    stored as deviations, BF16 snapshot records, lambda = 0.1 dx^2 sigma_1, mean pressure): each
-    rep is a primal step that encodes its snapshot and a reverse step from that record.  cache:
+    """Time steps of the 384^3 decaying-turbulence case with the benchmark's kernels (FP32 states
+    stored as deviations, BF16 snapshot records, lambda = 0.1 dx^2 sigma_1, mean pressure fused
+    into the stages): each rep is a primal step that encodes its snapshot and accumulates J, and a
+    reverse step from that record (which recomputes the stage states).  cache:
     an .npy file holding the initial field (written on the first run, read afterwards)."""
     import numpy as np
     import torch
@@ -116,8 +117,9 @@ def run_step384(reps, cache=None, tune=True):
     a = torch.randn(w.numel(), dtype=torch.float32, device="cuda") * 1e-3
     b = torch.empty_like(a)
     gs = torch.zeros_like(a)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
     for _ in range(reps):
-        adj.primal_step(g, w, None, nxt, ws, ckpt_out=rec)
+        adj.primal_step_obj(g, w, None, nxt, ws, obj, 1.0 / 5000, J, ckpt_out=rec)
         adj.adjoint_step(g, rec, None, a, b, ws, lam=wl.lam, obj=obj, c_n=1.0 / 5000, grad_s=gs)
         a, b = b, a
         w, nxt = nxt, w
@@ -126,14 +128,22 @@ def run_step384(reps, cache=None, tune=True):
 
 
 def run_copy(mib, reps):
+    """reps device copies of a buffer of mib MiB; prints the copy rate (bytes read + written per
+    second, HIP events around the copies after one untimed copy)."""
     import torch
 
     x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
     for _ in range(reps):
         y.copy_(x)
+    b.record()
     torch.cuda.synchronize()
-    print(f"copy: {reps} copies of {mib} MiB", flush=True)
+    ms = a.elapsed_time(b) / reps
+    print(f"copy: {reps} copies of {mib} MiB, {ms:.3f} ms each, {2 * (mib << 20) / ms / 1e6:.0f} GB/s read + write",
+          flush=True)
 
 
 def short_name(name):
