@@ -489,7 +489,7 @@ __global__ __launch_bounds__(KX * KY * KZ) void k_ked_tile(Consts<T> c, const T*
   __shared__ double sh[NTH / 64];
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   int x0, y0, z0;
-  tile_origin<KX, KY, KZ>(t, c.nx, c.ny, x0, y0, z0);
+  tile_origin<KX, KY, KZ>(t, c.nx, c.ny, c.nz, x0, y0, z0);
   load_box_u<T, KX, KY, KZ, 1, 1>(c, w, x0, y0, z0, su);
   __syncthreads();
   const int tid = threadIdx.x;
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(KX * KY * KZ) void k_ked_grad_tile(Consts<T> c, con
   __shared__ T su[3][O::NB];
   __shared__ T ss[6][I::NB];  // sigma xx, yy, zz, xy, xz, yz on the inner box
   int x0, y0, z0;
-  tile_origin<KX, KY, KZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
+  tile_origin<KX, KY, KZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, c.nz, x0, y0, z0);
   const int tid = threadIdx.x;
   const int tx = tid % KX, ty = (tid / KX) % KY, tz = tid / (KX * KY);
   const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;

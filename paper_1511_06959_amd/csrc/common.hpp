@@ -108,13 +108,27 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-// Origin of logical tile t of a TX x TY x TZ tiling of an nx x ny x nz grid (x fastest).
+#ifndef ADJNS_TILE_SLAB
+#define ADJNS_TILE_SLAB 4
+#endif
+
+// Origin of logical tile t of a TX x TY x TZ tiling of an nx x ny x nz grid.  The tiles are taken
+// in slabs of ADJNS_TILE_SLAB tile rows in y: x fastest, then y inside the slab, then z, then the
+// next slab.  A tile's x, y and z neighbours then run at most ntx * ADJNS_TILE_SLAB tiles before
+// or after it (not a whole x-y layer of tiles), on the same XCD, so the halo planes that they
+// share are still in its L2 when the second of them stages its box.  A bijection of [0, ntiles).
 template <int TX_, int TY_, int TZ_>
-__device__ __forceinline__ void tile_origin(int t, int nx, int ny, int& x0, int& y0, int& z0) {
-  const int ntx = (nx + TX_ - 1) / TX_, nty = (ny + TY_ - 1) / TY_;
-  x0 = (t % ntx) * TX_;
-  y0 = ((t / ntx) % nty) * TY_;
-  z0 = (t / (ntx * nty)) * TZ_;
+__device__ __forceinline__ void tile_origin(int t, int nx, int ny, int nz, int& x0, int& y0, int& z0) {
+  constexpr int SB = ADJNS_TILE_SLAB;
+  const int ntx = (nx + TX_ - 1) / TX_, nty = (ny + TY_ - 1) / TY_, ntz = (nz + TZ_ - 1) / TZ_;
+  const int slab = ntx * SB * ntz;  // tiles of a full slab; the last slab may hold fewer rows
+  const int yb = t / slab;
+  const int r = t - yb * slab;
+  const int by = min(SB, nty - yb * SB);
+  const int r2 = r / ntx;
+  x0 = (r - r2 * ntx) * TX_;
+  y0 = (yb * SB + r2 % by) * TY_;
+  z0 = (r2 / by) * TZ_;
 }
 
 // One box of an ensemble (batched launches).  Ensemble arrays are packed box after box: the

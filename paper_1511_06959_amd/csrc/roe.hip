@@ -185,7 +185,7 @@ __global__ __launch_bounds__(RNT) void k_roe_primal(Consts<T> c, RoeC<T> k, cons
   __shared__ T sw[5 * NSP];
   __shared__ T sf[5 * NFP];
   int x0, y0, z0;
-  tile_origin<RX, RY, RZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
+  tile_origin<RX, RY, RZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, c.nz, x0, y0, z0);
   const int tid = threadIdx.x, tx = tid % RX, ty = (tid / RX) % RY, tz = tid / (RX * RY);
   const auto rW = buf_rsrc(W, 5 * c.N);
   T acc[5] = {T(0), T(0), T(0), T(0), T(0)};
@@ -317,7 +317,7 @@ void k_roe_adjoint(Consts<T> c, RoeC<T> k, const T* __restrict__ W,
                                                      T* __restrict__ out) {
   __shared__ T lds[NLA];
   int x0, y0, z0;
-  tile_origin<RX, RY, RZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
+  tile_origin<RX, RY, RZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, c.nz, x0, y0, z0);
   const int tid = threadIdx.x, tx = tid % RX, ty = (tid / RX) % RY, tz = tid / (RX * RY);
   const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
   const bool active = gx < c.nx && gy < c.ny && gz < c.nz;

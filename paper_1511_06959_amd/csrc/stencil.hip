@@ -251,7 +251,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage(Consts<T> c, cons
                                                                double* __restrict__ jpart) {
   int x0, y0, z0;
   const int t = xcd_tile(blockIdx.x, gridDim.x);
-  tile_origin<TX, TY, TZ>(t, c.nx, c.ny, x0, y0, z0);
+  tile_origin<TX, TY, TZ>(t, c.nx, c.ny, c.nz, x0, y0, z0);
   primal_tile_body<T, MODE, CONV, TX, TY, TZ>(c, x0, y0, z0, W, wn, s, W2, W3, cR, out, ca, cb, jpart, t);
 }
 
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_primal_stage_batch(const BoxDe
   const Consts<T> c = boxes[b].c;
   const long long o = 5 * boxes[b].off;
   int x0, y0, z0;
-  tile_origin<TX, TY, TZ>(blk - start[b], c.nx, c.ny, x0, y0, z0);
+  tile_origin<TX, TY, TZ>(blk - start[b], c.nx, c.ny, c.nz, x0, y0, z0);
   primal_tile_body<T, MODE, 1, TX, TY, TZ>(c, x0, y0, z0, W + o, wn + o, s ? s + o : nullptr,
                                         W2 ? W2 + o : nullptr, W3 ? W3 + o : nullptr, c.dt * cfac, out + o);
 }
@@ -711,7 +711,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage(Consts<T> c, con
                                                                 T* __restrict__ out, T* __restrict__ grad_s,
                                                                 double objw) {
   int x0, y0, z0;
-  tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, x0, y0, z0);
+  tile_origin<TX, TY, TZ>(xcd_tile(blockIdx.x, gridDim.x), c.nx, c.ny, c.nz, x0, y0, z0);
   adjoint_tile_body<T, MODE, WALL, LNU, CONV, TX, TY, TZ>(c, x0, y0, z0, W, a, gnext, nu, T(1), ca, cg, g3, g4, out,
                                                           grad_s, objw);
 }
@@ -730,7 +730,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void k_adjoint_stage_batch(
   const Consts<T> c = mems[m].c;
   const long long o = 5 * mems[m].off, ao = 5 * mems[m].aoff;
   int x0, y0, z0;
-  tile_origin<TX, TY, TZ>(blk - start[m], c.nx, c.ny, x0, y0, z0);
+  tile_origin<TX, TY, TZ>(blk - start[m], c.nx, c.ny, c.nz, x0, y0, z0);
   adjoint_tile_body<T, MODE, WALL, LNU, 1, TX, TY, TZ>(
       c, x0, y0, z0, W + o, a + ao, gnext ? gnext + ao : nullptr, LNU ? sigma1 + mems[m].off : nullptr,
       mems[m].lam, c.dt / da, c.dt * mg, g3 ? g3 + ao : nullptr, g4 ? g4 + ao : nullptr, out + ao,
