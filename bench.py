@@ -98,6 +98,26 @@ def valu_roofline(valu, cells, avg_us):
             "fp32_ops_per_launch": flops, "valu_insts_per_launch": insts}
 
 
+def device_copy_gbs(mib=4096, reps=10):
+    """Bytes read + written per second by a device-to-device copy of mib MiB (HIP events around
+    reps copies after an untimed one): the streaming rate a kernel can reach on this device."""
+    import torch
+
+    x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
 def kernel_hash(family="stage"):
     """sha256 of a kernel family's sources ("stage": the stage kernels, "roe": the Roe flux
     kernels), as the committed counter summaries record it."""
@@ -598,6 +618,7 @@ def main_c5(args):
     wl = W.turb_384(nsteps=PLAN_STEPS, lam_factor=0.1)
     print(f"[bench] workload {wl.name}: {wl.n} cells, plan {PLAN_STEPS} steps, dt {wl.dt:.4e}, lambda {wl.lam:.3e}",
           file=sys.stderr, flush=True)
+    copy_gbs = device_copy_gbs()
     r32 = run_plan(wl, adj.F32, K, Wm, not args.no_autotune, bf16=True)
     print(f"[bench] f32/bf16 window {r32['ms_per_step']:.2f} ms per step, window {r32['window']}, plan "
           f"{r32['plan']}", file=sys.stderr, flush=True)
@@ -625,6 +646,10 @@ def main_c5(args):
     roof["kernel"] = kname
     roof["traffic"] = None if traffic is None else float(traffic["bytes_per_cell_launch_f32"]) * cells
     roof["traffic_profile"] = None if traffic is None else "profiles/" + traffic["profile"]
+    # the counters' bytes over the live launch duration: the HBM rate the kernel really draws
+    roof["traffic_gbs"] = None if traffic is None else roof["traffic"] / (roof["avg_launch_us"] * 1e-6) / 1e9
+    roof["traffic_frac"] = None if traffic is None else roof["traffic_gbs"] / HBM_PEAK_GBS
+    roof["device_copy_gbs"] = copy_gbs
     roof_valu = valu_roofline(valu, cells, roof["avg_launch_us"])
     if roof_valu is not None:
         roof_valu["profile"] = "profiles/" + valu["profile"]
@@ -716,6 +741,143 @@ def cpu_baseline_leg(wl, seconds):
                           "adjoint_cell_steps_per_s": one["adjoint_cell_steps_per_s"]},
     }
     return cpu, rel
+
+
+def _oracle_rates(og, obj, w, lam, cn, steps, best_of=3, threads=None):
+    """The oracle's own rates on a state w: after one untimed primal and reverse step, best_of
+    timings of `steps` primal steps (advancing the state) and `steps` reverse steps (each
+    recomputing its stage states, with the objective's injection and lambda)."""
+    import oracle
+
+    prev = oracle.num_threads()
+    if threads is not None:
+        oracle.set_num_threads(threads)
+    used = oracle.num_threads()
+    cells = w.size // 5
+    a = np.random.default_rng(0).standard_normal(w.size) * 1e-3
+    gs = np.zeros_like(w)
+    best_p = best_a = 0.0
+    try:
+        w1 = oracle.primal_step(og, w)
+        oracle.adjoint_step(og, w, None, a, lam, obj, cn, gs)
+        for _ in range(best_of):
+            wc = w1
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                wc = oracle.primal_step(og, wc)
+            t1 = time.perf_counter()
+            for _ in range(steps):
+                oracle.adjoint_step(og, w1, None, a, lam, obj, cn, gs)
+            t2 = time.perf_counter()
+            best_p = max(best_p, cells * steps / (t1 - t0))
+            best_a = max(best_a, cells * steps / (t2 - t1))
+    finally:
+        oracle.set_num_threads(prev)
+    return {"threads": used, "steps": steps, "best_of": best_of, "primal_cell_steps_per_s": best_p,
+            "adjoint_cell_steps_per_s": best_a, "cell_steps_per_s": 1.0 / (1.0 / best_p + 1.0 / best_a)}
+
+
+def _block(wl, lo, n, bc_x=None):
+    """Block of n cells at lo cut from a workload's initial field, with its cell size, viscosity and
+    dt (periodic in y and z; x as given)."""
+    import oracle
+
+    N = wl.n
+    w = wl.w0.reshape(5, N[2], N[1], N[0])[:, lo[2]:lo[2] + n[2], lo[1]:lo[1] + n[1], lo[0]:lo[0] + n[0]]
+    p = wl.params()
+    p["n"] = tuple(n)
+    p["L"] = tuple(wl.L[d] / wl.n[d] * n[d] for d in range(3))
+    if bc_x is not None:
+        p["bc_x"] = bc_x
+    return oracle.grid_from(p), np.ascontiguousarray(w).reshape(-1)
+
+
+def main_cpu_baseline(args):
+    """The FP64 oracle timed on the host cores for every configuration (nothing runs on the GPU):
+    per-cell-step rates of the primal step and of the reverse step (stage recomputation included),
+    with lambda = 0 and lambda = 0.1 dx^2 sigma_1, best of three after a warm-up step, on all cores
+    and (for the 16^3 window and a 24^3 block) on one.  Large configurations run slices: a few steps,
+    or a block cut from the field with the configuration's cell size; only rates are reported."""
+    import oracle
+    import workloads as W
+
+    rows = []
+
+    def row(name, sample, og, obj, w, lam, cn, steps, threads=None):
+        t0 = time.perf_counter()
+        r = _oracle_rates(og, obj, w, lam, cn, steps, threads=threads)
+        r.update({"config": name, "sample": sample, "lambda": lam, "cells": w.size // 5,
+                  "wall_s": time.perf_counter() - t0})
+        print(f"[cpu] {name} {sample} lambda {lam:.3g} threads {r['threads']}: primal "
+              f"{r['primal_cell_steps_per_s']:.3e}, reverse {r['adjoint_cell_steps_per_s']:.3e} cell-steps/s "
+              f"({r['wall_s']:.1f} s)", file=sys.stderr, flush=True)
+        rows.append(r)
+
+    # 16^3 Taylor-Green window (50 + 50 steps) in full, all cores and one
+    wl = W.tgv_small()
+    og = oracle.grid_from(wl.params())
+    obj = oracle.make_obj(wl.obj_kind)
+    for threads in (None, 1):
+        prev = oracle.num_threads()
+        if threads:
+            oracle.set_num_threads(threads)
+        try:
+            oracle.primal_window(og, wl.w0, wl.s, 2)
+            best = None
+            for _ in range(3):
+                t0 = time.perf_counter()
+                traj = oracle.primal_window(og, wl.w0, wl.s, wl.nsteps)
+                t1 = time.perf_counter()
+                oracle.adjoint_window(og, obj, traj, wl.s, wl.weights)
+                t2 = time.perf_counter()
+                best = (t1 - t0, t2 - t1) if best is None else (min(best[0], t1 - t0), min(best[1], t2 - t1))
+            used = oracle.num_threads()
+        finally:
+            oracle.set_num_threads(prev)
+        cs = wl.ncells * wl.nsteps
+        rows.append({"config": "tgv16", "sample": f"the whole {wl.nsteps}-step window (forward, then reverse)",
+                     "lambda": 0.0, "cells": wl.ncells, "threads": used, "steps": wl.nsteps, "best_of": 3,
+                     "primal_cell_steps_per_s": cs / best[0], "adjoint_cell_steps_per_s": cs / best[1],
+                     "cell_steps_per_s": cs / (best[0] + best[1])})
+        print(f"[cpu] tgv16 window threads {used}: {cs / (best[0] + best[1]):.3e} cell-steps/s", file=sys.stderr,
+              flush=True)
+    # 64^3 Taylor-Green (dissipation objective): two-step slice of the 1000-step window
+    wl = W.tgv_64()
+    og = oracle.grid_from(wl.params())
+    obj = oracle.make_obj(wl.obj_kind)
+    dx = wl.L[0] / wl.n[0]
+    for lf in (0.0, 0.1):
+        row("tgv64", "2-step slice", og, obj, wl.w0, lf * dx * dx, 1.0 / wl.nsteps, 2)
+    # the wake: a 128 x 64 x 32 block around the shear layer, slip walls at its x ends
+    wl = W.wake(nsteps=4000)
+    og, w = _block(wl, (192, 0, 0), (128, 64, 32), bc_x=1)
+    obj = oracle.make_obj(wl.obj_kind, 96, wl.pt_ref)
+    dx = wl.L[0] / wl.n[0]
+    for lf in (0.0, 0.1):
+        row("wake", "128x64x32 block from the centre of the 512x256x32 field, 2 steps", og, obj, w, lf * dx * dx,
+            1.0 / wl.nsteps, 2)
+    del wl, w
+    # 384^3 decaying turbulence: 48^3 block (all cores) and 24^3 block (one core)
+    wl = W.turb_384()
+    dx = wl.L[0] / wl.n[0]
+    for n, threads in ((48, None), (24, 1)):
+        og, w = _block(wl, (0, 0, 0), (n, n, n))
+        obj = oracle.make_obj(wl.obj_kind)
+        for lf in (0.0, 0.1):
+            row("turb384", f"{n}^3 block of the 384^3 field, {2 if n == 48 else 1} steps", og, obj, w, lf * dx * dx,
+                1.0 / PLAN_STEPS, 2 if n == 48 else 1, threads=threads)
+    del wl
+    # the ensemble's box sizes, one box of each
+    for n in (32, 48, 64, 96):
+        wl = W.turbulence(n, mach_rms=0.3, nu=0.0175, seed=4, nsteps=2)
+        og = oracle.grid_from(wl.params())
+        obj = oracle.make_obj(wl.obj_kind)
+        dx = wl.L[0] / n
+        for lf in (0.0, 0.1):
+            row(f"ensemble_box{n}", f"{n}^3 box, 1 step", og, obj, wl.w0, lf * dx * dx, 0.01, 1)
+    print(json.dumps({"kind": "oracle_cpu_baseline", "unit": "cell-steps/s", "cpu_model": cpu_model(),
+                      "host_cpus": os.cpu_count(), "all_core_threads": max(r["threads"] for r in rows),
+                      "rows": rows}), flush=True)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -912,6 +1074,7 @@ WORKLOADS = {
                "sweep), against the same sweeps with the records in HBM",
     "turb384_window": "the whole 5000-step 384^3 window once: autograd gradients and finite differences",
     "wake_lambda": "the 4000-step wake with a lambda sweep over one BF16 trajectory",
+    "cpu_baseline": "the FP64 oracle's rates on the host cores for every configuration (no GPU work)",
     "lamest": "choice of lambda for decaying turbulence 128^3 periodic (Mach_rms 0.4, nu 2.887e-3): {n}-step window, "
               "6 candidate scales {{0,0.01,0.03,0.1,0.3,1}} dx^2 swept backward together as one batched ensemble "
               "from a white-noise terminal adjoint, adjoint energy after every reverse step",
@@ -964,6 +1127,10 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
               "design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "cpu_baseline":
+        main_cpu_baseline(args)
+        return
 
     import torch
 
