@@ -591,6 +591,30 @@ def cpu_baseline_block(wl, n, budget_s, threads=None):
             "primal_cell_steps_per_s": cells * steps / t_pr, "adjoint_cell_steps_per_s": cells * steps / t_ad}
 
 
+def schedule_ceiling(r, cells, khash, copy_gbs, K):
+    """The schedule's own ceiling: HBM bytes one time step of the plan moves per cell (the stage
+    kernels' counter summaries: four reverse-stage launches, four primal-stage launches per
+    primal step and the stage recomputations of binomial plans; sigma_1 at its 24 algorithmic
+    bytes), and the cell-steps/s that 8 TB/s and the
+    device's copy rate would allow at that traffic.  None when a summary was taken on other
+    kernel sources or tiles."""
+    per = {}
+    for name in ("adjoint_stage", "primal_stage"):
+        tile = r["tiles"].get(name, {}).get("launched")
+        t = profile_values(f"traffic_{name}_turb384.txt", khash, tile)
+        if t is None:
+            return None
+        per[name] = float(t["bytes_per_cell_launch_f32"])
+    prim = r["advances"] / K
+    # binomial plans also evaluate three stage states inside every reverse step
+    rec = r["plan"].get("stage_recomputes_per_step", 0)
+    b = 4 * per["adjoint_stage"] + (4 * prim + rec) * per["primal_stage"] + 24.0
+    return {"bytes_per_cell_step": b, "reverse_stage_bytes_per_cell_launch": per["adjoint_stage"],
+            "primal_stage_bytes_per_cell_launch": per["primal_stage"], "primal_steps_per_time_step": prim,
+            "ceiling_at_8tbs": HBM_PEAK_GBS * 1e9 / b, "ceiling_at_copy_rate": copy_gbs * 1e9 / b,
+            "value_over_copy_ceiling": r["value"] / (copy_gbs * 1e9 / b)}
+
+
 def schedule_text(r, K):
     p, w = r["plan"], r["window"]
     if p["schedule"] == "segments":
@@ -693,6 +717,7 @@ def main_c5(args):
                               "unit": "GB/s",
                               "frac": (ALG_BYTES["adjoint"]["f32"] + ALG_BYTES["primal"]["f32"]) * r32["value"] / 1e9
                               / HBM_PEAK_GBS},
+        "schedule_ceiling": schedule_ceiling(r32, cells, khash, copy_gbs, K),
         "kernel_ms_per_step": kms,
         "primal_steps_per_time_step": r32["advances"] / K,
         "launch": "eager launches on one stream (each 384^3 launch runs for milliseconds)",
