@@ -808,6 +808,8 @@ def _block(wl, lo, n, bc_x=None):
     import oracle
 
     N = wl.n
+    if any(lo[d] < 0 or lo[d] + n[d] > N[d] for d in range(3)):
+        raise ValueError(f"block at {lo} of {n} cells does not fit the {N} grid")
     w = wl.w0.reshape(5, N[2], N[1], N[0])[:, lo[2]:lo[2] + n[2], lo[1]:lo[1] + n[1], lo[0]:lo[0] + n[0]]
     p = wl.params()
     p["n"] = tuple(n)

@@ -1,0 +1,59 @@
+"""Host parts of bench.py: the oracle's timing leg on a tiny grid, the algorithmic-byte roofline
+arithmetic and the schedule ceiling (no GPU)."""
+import numpy as np
+import pytest
+
+import bench
+import workloads as W
+
+
+def test_oracle_rates_tiny_grid(orc):
+    wl = W.turbulence(8, mach_rms=0.3, nu=0.0175, seed=4, nsteps=2)
+    og = orc.grid_from(wl.params())
+    r = bench._oracle_rates(og, orc.make_obj(wl.obj_kind), wl.w0, 0.0, 0.5, 1, best_of=2, threads=1)
+    assert r["threads"] == 1 and r["steps"] == 1 and r["best_of"] == 2
+    assert r["primal_cell_steps_per_s"] > 0 and r["adjoint_cell_steps_per_s"] > 0
+    # one primal plus one reverse step per cell-step
+    hm = 1.0 / (1.0 / r["primal_cell_steps_per_s"] + 1.0 / r["adjoint_cell_steps_per_s"])
+    assert r["cell_steps_per_s"] == pytest.approx(hm)
+
+
+def test_block_cut_keeps_cell_size(orc):
+    wl = W.turbulence(16, mach_rms=0.3, nu=0.0175, seed=4, nsteps=1)
+    og, w = bench._block(wl, (10, 3, 9), (6, 5, 4))
+    assert w.size == 5 * 6 * 5 * 4
+    full = wl.w0.reshape(5, 16, 16, 16)
+    assert np.array_equal(w.reshape(5, 4, 5, 6), full[:, 9:13, 3:8, 10:16])
+    assert og.n[0] == 6 and og.n[1] == 5 and og.n[2] == 4
+    assert og.L[0] / og.n[0] == pytest.approx(wl.L[0] / 16)
+    with pytest.raises(ValueError):
+        bench._block(wl, (12, 3, 9), (6, 5, 4))
+
+
+def test_kernel_roofline_uses_per_unit_bytes():
+    # 90 B per adjoint cell-step, a quarter per stage launch; 80 launches of 2.5 ms each
+    cells = 384 ** 3
+    r = bench.kernel_roofline("adjoint", "f32", cells, 80 * 2.5, 80)
+    assert r["alg_bytes_per_launch"] == pytest.approx(22.5 * cells)
+    assert r["achieved"] == pytest.approx(22.5 * cells / 2.5e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+    r64 = bench.kernel_roofline("primal", "f64", cells, 10.0, 4)
+    assert r64["alg_bytes_per_launch"] == pytest.approx(30.0 * cells)
+
+
+def test_schedule_ceiling_counts_every_launch(monkeypatch):
+    per = {"adjoint_stage": 100.0, "primal_stage": 60.0}
+
+    def fake(name, khash, tile):
+        kind = "adjoint_stage" if "adjoint" in name else "primal_stage"
+        return {"bytes_per_cell_launch_f32": str(per[kind]), "profile": name}
+
+    monkeypatch.setattr(bench, "profile_values", fake)
+    tiles = {"adjoint_stage": {"launched": "32x4x4"}, "primal_stage": {"launched": "32x4x4"}}
+    seg = {"tiles": tiles, "advances": 40, "plan": {"schedule": "segments"}, "value": 1e9}
+    c = bench.schedule_ceiling(seg, 1000, "h", 4000.0, 20)
+    assert c["bytes_per_cell_step"] == pytest.approx(4 * 100 + 8 * 60 + 24)
+    assert c["ceiling_at_8tbs"] == pytest.approx(8e12 / c["bytes_per_cell_step"])
+    binom = dict(seg, plan={"schedule": "binomial", "stage_recomputes_per_step": 3})
+    c2 = bench.schedule_ceiling(binom, 1000, "h", 4000.0, 20)
+    assert c2["bytes_per_cell_step"] == pytest.approx(c["bytes_per_cell_step"] + 3 * 60)
