@@ -225,10 +225,16 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     esz = 8 if precision == adj.F64 else 4
     ms, n = prof["adjoint_stage"]
     avg_s = ms / n / 1e3
-    alg_bytes = (VALUES_PER_STAGE_LAUNCH_RK3 if time_scheme == 1 else VALUES_PER_STAGE_LAUNCH) * esz * cells
+    nst = 3 if time_scheme == 1 else 4
+    # the per-unit figure (90 B / 200 B per adjoint cell-step) spread over the step's stage launches,
+    # and beside it the values this store-all schedule's stage launches read and write
+    alg_bytes = ALG_BYTES["adjoint"]["f64" if precision == adj.F64 else "f32"] / nst * cells
+    sched_bytes = (VALUES_PER_STAGE_LAUNCH_RK3 if time_scheme == 1 else VALUES_PER_STAGE_LAUNCH) * esz * cells
     out["stage_avg_us"] = avg_s * 1e6
     out["stage_alg_bytes"] = alg_bytes
     out["stage_achieved_gbs"] = alg_bytes / avg_s / 1e9
+    out["stage_schedule_bytes"] = sched_bytes
+    out["stage_schedule_gbs"] = sched_bytes / avg_s / 1e9
     if flux == 1:
         # Roe flux kernels: the primal kernel reads W and updates out (15 values per cell), the
         # reverse kernel reads W, a, gnext and updates out (25 values per cell)
@@ -323,9 +329,11 @@ def run_ensemble(boxes, precision, steps, warmup, tune=True):
     out["prof"] = prof
     esz = 8 if precision == adj.F64 else 4
     ms, n = prof["adjoint_stage"]
-    # every reverse step launches the four stages over the members still running
-    alg = VALUES_PER_STAGE_LAUNCH * esz * 4 * acs
+    # every reverse step launches the four stages over the members still running: the per-unit
+    # figure per member cell-step, and beside it the values the stage launches read and write
+    alg = ALG_BYTES["adjoint"]["f64" if precision == adj.F64 else "f32"] * acs
     out["stage_achieved_gbs"] = alg / (ms / 1e3) / 1e9
+    out["stage_schedule_gbs"] = VALUES_PER_STAGE_LAUNCH * esz * 4 * acs / (ms / 1e3) / 1e9
     out["stage_avg_us"] = ms / n * 1e3
     out["stage_launches"] = n
     out["cells"] = win.ens.offset(0, win.nbox)
@@ -1223,6 +1231,10 @@ def main():
         "kernel": "k_adjoint_stage (reverse-stage gather)",
         "avg_launch_us": r32["stage_avg_us"],
         "alg_bytes_per_launch": r32["stage_alg_bytes"],
+        "alg_bytes_per_cell_step": ALG_BYTES["adjoint"]["f32"],
+        "schedule_bytes_per_launch": r32["stage_schedule_bytes"],
+        "schedule_gbs": r32["stage_schedule_gbs"],
+        "schedule_frac": r32["stage_schedule_gbs"] / HBM_PEAK_GBS,
     }
     roof_valu = valu_roofline(valu, wl.ncells, r32["stage_avg_us"])
     if roof_valu is not None:
@@ -1352,6 +1364,9 @@ def main_ensemble(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": r["stage_achieved_gbs"] / HBM_PEAK_GBS,
+            "alg_bytes_per_cell_step": ALG_BYTES["adjoint"]["f32"],
+            "schedule_gbs": r["stage_schedule_gbs"],
+            "schedule_frac": r["stage_schedule_gbs"] / HBM_PEAK_GBS,
             "traffic": None,
             "kernel": "k_adjoint_stage_batch (reverse-stage gather over all running members)",
             "avg_launch_us": r["stage_avg_us"],
@@ -1407,7 +1422,8 @@ def main_lamest(args):
     k = lamest.choose(factors, rates, [True] * len(factors), 0.0)
     cells = g.ncells * len(factors) * T
     avg_s = ms / n / 1e3
-    alg = VALUES_PER_STAGE_LAUNCH * 4 * g.ncells * len(factors)
+    alg = ALG_BYTES["adjoint"]["f32"] / 4 * g.ncells * len(factors)
+    sched = VALUES_PER_STAGE_LAUNCH * 4 * g.ncells * len(factors)
     print(f"[bench] lamest sweep {sec * 1e3:.1f} ms, chosen factor {factors[k] if k is not None else None}",
           file=sys.stderr, flush=True)
     line = {
@@ -1429,7 +1445,8 @@ def main_lamest(args):
         "roofline": {"bound": "hbm", "achieved": alg / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_adjoint_stage_batch (reverse-stage gather over all members)",
-                     "avg_launch_us": avg_s * 1e6},
+                     "avg_launch_us": avg_s * 1e6, "alg_bytes_per_cell_step": ALG_BYTES["adjoint"]["f32"],
+                     "schedule_gbs": sched / avg_s / 1e9, "schedule_frac": sched / avg_s / 1e9 / HBM_PEAK_GBS},
         "estimate": {"factors": factors, "growth_rates": rates,
                      "chosen_factor": factors[k] if k is not None else None},
         "tiles": tiles,
