@@ -512,7 +512,7 @@ def c1_vs_oracle():
     import oracle
     import paper_1511_06959_amd as adj
     from paper_1511_06959_amd import sweep
-    from paper_1511_06959_amd.sweep import RevolveSweep
+    from paper_1511_06959_amd.sweep import RevolveSweep, SegmentSweep
     import workloads as W
 
     wl = W.tgv_small()
@@ -524,9 +524,13 @@ def c1_vs_oracle():
     ref = adj.reference_state(wl.w0)
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
     out = {}
+    # slots: None store-all, an int binomial slots, ("seg", L) two-level segments of L steps (the
+    # benchmark's own schedule)
     for name, prec, ck, slots in (("f64", adj.F64, adj.CKPT_NATIVE, None), ("f32", adj.F32, adj.CKPT_NATIVE, None),
                                   ("f32_bf16_records", adj.F32, adj.CKPT_BF16, None),
-                                  ("f32_bf16_revolve_4_slots", adj.F32, adj.CKPT_BF16, 4)):
+                                  ("f32_bf16_revolve_4_slots", adj.F32, adj.CKPT_BF16, 4),
+                                  ("f32_bf16_segments_10", adj.F32, adj.CKPT_BF16, ("seg", 10)),
+                                  ("f64_segments_10", adj.F64, adj.CKPT_NATIVE, ("seg", 10))):
         g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, prec, ck,
                           ref if prec == adj.F32 else None)
         obj = adj.Objective.make(wl.obj_kind)
@@ -537,7 +541,10 @@ def c1_vs_oracle():
             tr, _, Jg = sweep.forward(g, w0, s, wl.nsteps, obj, wl.weights, ws)
             whg, gsg, _ = sweep.backward(g, tr, s, obj, wl.weights, 0.0, ws)
         else:
-            sw = RevolveSweep(g, wl.nsteps, slots, s, obj, wl.weights, 0.0, ws)
+            if isinstance(slots, tuple):
+                sw = SegmentSweep(g, wl.nsteps, slots[1], s, obj, wl.weights, 0.0, ws)
+            else:
+                sw = RevolveSweep(g, wl.nsteps, slots, s, obj, wl.weights, 0.0, ws)
             Jg = sw.forward(w0)
             whg, gsg = sw.backward()
         out[name] = {"J": abs(float(Jg.cpu()[0]) - J) / abs(J), "dJ_dw0": rel(whg.double().cpu().numpy(), wh0),
