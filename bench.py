@@ -98,6 +98,14 @@ def valu_roofline(valu, cells, avg_us):
             "fp32_ops_per_launch": flops, "valu_insts_per_launch": insts}
 
 
+def record_format(args):
+    """Checkpoint record format of the FP32 paths: BF16 codes (the configured form) unless
+    --ckpt i16 asks for the 16-bit fixed-point codes of the same size."""
+    import paper_1511_06959_amd as adj
+
+    return adj.CKPT_I16 if getattr(args, "ckpt", "bf16") == "i16" else adj.CKPT_BF16
+
+
 def device_copy_gbs(mib=4096, reps=10):
     """Bytes read + written per second by a device-to-device copy of mib MiB (HIP events around
     reps copies after an untimed one): the streaming rate a kernel can reach on this device."""
@@ -143,7 +151,7 @@ def _tile_report(res, g, lnu):
 
 
 def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=False, time_scheme=0, flux=0,
-            nu_weight=None):
+            nu_weight=None, rec_fmt=None):
     import torch
 
     import paper_1511_06959_amd as adj
@@ -153,7 +161,8 @@ def run_gpu(wl, precision, steps, warmup, tune=True, stages=False, ckpt_bf16=Fal
     # FP32 states are stored as deviations from the mean initial state (see adj_grid.w_ref)
     w_ref = adj.reference_state(wl.w0) if precision == adj.F32 else None
     g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision,
-                      adj.CKPT_BF16 if ckpt_bf16 else adj.CKPT_NATIVE, w_ref, time_scheme=time_scheme, flux=flux,
+                      (rec_fmt or adj.CKPT_BF16) if ckpt_bf16 else adj.CKPT_NATIVE, w_ref, time_scheme=time_scheme,
+                      flux=flux,
                       roe_delta=ROE_DELTA, w_far=wl.extra.get("w_far"), nu_weight=nu_weight)
     tiles = {}
     if tune:
@@ -419,7 +428,7 @@ PROF_CLASSES = (("adjoint_stage", 0), ("primal_stage", 1), ("sigma1", 2), ("obje
                 ("reduce", 5))
 
 
-def run_plan(wl, precision, K, warmup, tune=True, bf16=True):
+def run_plan(wl, precision, K, warmup, tune=True, bf16=True, rec_fmt=None):
     """K-step window of the 384^3 plan on the GPU, in the schedule the plan picks for the free HBM
     (segments of the plan's length, or binomial slots that recompute no less per time step than
     the plan does): timed once, then run again with per-kernel event timing.  Returns timings,
@@ -434,7 +443,7 @@ def run_plan(wl, precision, K, warmup, tune=True, bf16=True):
     f32 = precision == adj.F32
     ref = adj.reference_state(wl.w0) if f32 else None
     g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, precision,
-                      adj.CKPT_BF16 if (f32 and bf16) else adj.CKPT_NATIVE, ref)
+                      (rec_fmt or adj.CKPT_BF16) if (f32 and bf16) else adj.CKPT_NATIVE, ref)
     tiles = _tile_report(autotune.tune(g), g, wl.lam > 0.0) if tune else {}
     obj = adj.Objective.make(wl.obj_kind)
     w0 = torch.from_numpy(g.to_stored(wl.w0)).to("cuda", g.dtype)
@@ -530,6 +539,7 @@ def c1_vs_oracle():
                                   ("f32_bf16_records", adj.F32, adj.CKPT_BF16, None),
                                   ("f32_bf16_revolve_4_slots", adj.F32, adj.CKPT_BF16, 4),
                                   ("f32_bf16_segments_10", adj.F32, adj.CKPT_BF16, ("seg", 10)),
+                                  ("f32_i16_segments_10", adj.F32, adj.CKPT_I16, ("seg", 10)),
                                   ("f64_segments_10", adj.F64, adj.CKPT_NATIVE, ("seg", 10))):
         g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, prec, ck,
                           ref if prec == adj.F32 else None)
@@ -658,7 +668,7 @@ def main_c5(args):
     print(f"[bench] workload {wl.name}: {wl.n} cells, plan {PLAN_STEPS} steps, dt {wl.dt:.4e}, lambda {wl.lam:.3e}",
           file=sys.stderr, flush=True)
     copy_gbs = device_copy_gbs()
-    r32 = run_plan(wl, adj.F32, K, Wm, not args.no_autotune, bf16=True)
+    r32 = run_plan(wl, adj.F32, K, Wm, not args.no_autotune, bf16=True, rec_fmt=record_format(args))
     print(f"[bench] f32/bf16 window {r32['ms_per_step']:.2f} ms per step, window {r32['window']}, plan "
           f"{r32['plan']}", file=sys.stderr, flush=True)
     r64 = None
@@ -720,8 +730,9 @@ def main_c5(args):
             "schedule": schedule_text(r32, K),
             "plan": r32["plan"],
             "window": r32["window"],
-            "checkpoints": "BF16 snapshot records (per 4x4x4 block and variable a least-squares plane and the BF16 "
-                           "residual); the segment being reversed in native FP32 states and stage states",
+            "checkpoints": ("BF16" if args.ckpt == "bf16" else "16-bit fixed-point") + " snapshot records (per "
+                           "4x4x4 block and variable a least-squares plane and the 16-bit code of the residual); the "
+                           "segment being reversed in native FP32 states and stage states",
             "source": "body force s = 0 (the base of the gradient), so primal stages skip reading it",
         },
         "roofline": roof,
@@ -989,7 +1000,7 @@ def main_c5_window(args):
         lam = wl.lam if part.endswith("_lam") else 0.0
         ref = adj.reference_state(wl.w0) if prec == adj.F32 else None
         g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, prec,
-                          adj.CKPT_BF16 if prec == adj.F32 else adj.CKPT_NATIVE, ref)
+                          record_format(args) if prec == adj.F32 else adj.CKPT_NATIVE, ref)
         if not args.no_autotune:
             from paper_1511_06959_amd import autotune
             autotune.tune(g)
@@ -1046,7 +1057,7 @@ def main_wake_lambda(args):
     dx = min(wl.L[d] / wl.n[d] for d in range(3))
     factors = [0.0, 0.1, 1.0]
     lams = [f * dx * dx for f in factors]
-    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F32, adj.CKPT_BF16,
+    g = adj.Grid.make(wl.n, wl.L, wl.mu, wl.dt, wl.gamma, wl.prandtl, wl.bc_x, adj.F32, record_format(args),
                       adj.reference_state(wl.w0))
     if not args.no_autotune:
         autotune.tune(g)
@@ -1150,6 +1161,9 @@ def main():
     ap.add_argument("--fd-seeds", default="10,11,12,13,14,15,16,17", help="turb384_window: direction seeds")
     ap.add_argument("--fd-eps", type=float, default=1e-3, help="turb384_window: finite-difference step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ckpt", default="bf16", choices=("bf16", "i16"),
+                    help="record format of the FP32 paths' snapshots: BF16 codes (default) or 16-bit fixed-point "
+                         "codes of the same size")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--schedule", default="stages", choices=("stages", "recompute"),
@@ -1205,6 +1219,7 @@ def main():
           file=sys.stderr, flush=True)
     # the large configurations keep BF16 checkpoint records on the FP32 path
     r32 = run_gpu(wl, adj.F32, args.steps, args.warmup, not args.no_autotune, stages=stages, ckpt_bf16=big,
+                  rec_fmt=record_format(args),
                   time_scheme=args.ts, flux=args.fl, nu_weight=args.nw)
     print(f"[bench] f32 window {r32['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
     r32b = None
@@ -1295,7 +1310,9 @@ def main():
             "step": "one whole window: forward sweep + reverse sweep",
             "schedule": ("stage states of every step kept in HBM by the forward sweep" if stages else
                          "reverse step recomputes the stage states from the stored w_n"),
-            "checkpoints": "BF16 records (block-scaled, one affine map per variable and 4x4x4 block)" if big else "native FP32 / FP64 states",
+            "checkpoints": (("BF16" if args.ckpt == "bf16" else "16-bit fixed-point") + " records (per 4x4x4 block and "
+                            "variable a least-squares plane and the 16-bit code of the residual)") if big
+                           else "native FP32 / FP64 states",
         },
         "roofline": roof,
         "roofline_valu": roof_valu,

@@ -64,7 +64,7 @@ typedef enum adj_status {
 
 enum { ADJ_BC_PERIODIC = 0, ADJ_BC_SLIP_WALLS = 1, ADJ_BC_CHARACTERISTIC = 2 };
 enum { ADJ_F64 = 0, ADJ_F32 = 1 };
-enum { ADJ_CKPT_NATIVE = 0, ADJ_CKPT_BF16 = 1 };
+enum { ADJ_CKPT_NATIVE = 0, ADJ_CKPT_BF16 = 1, ADJ_CKPT_I16 = 2 };
 enum { ADJ_RK4 = 0, ADJ_SSPRK3 = 1 };
 enum { ADJ_FLUX_SPLIT = 0, ADJ_FLUX_ROE = 1 };
 enum {
@@ -88,8 +88,9 @@ typedef struct adj_grid {
   double mu;           /* constant dynamic viscosity                                         */
   double dt;           /* time step                                                          */
   int32_t precision;   /* ADJ_F64 or ADJ_F32: element type of states and stencil arithmetic  */
-  int32_t ckpt_format; /* ADJ_CKPT_NATIVE or ADJ_CKPT_BF16 (ADJ_F32 only): form of w_n handed
-                          to adj_adjoint_step and of ckpt_out written by adj_primal_step       */
+  int32_t ckpt_format; /* ADJ_CKPT_NATIVE, ADJ_CKPT_BF16 or ADJ_CKPT_I16 (the two records:
+                          ADJ_F32 only): form of w_n handed to adj_adjoint_step and of ckpt_out
+                          written by adj_primal_step (see adj_ckpt_encode)                     */
   double w_ref[5];     /* reference state: every state array holds w - w_ref (all zero = the
                           plain state).  A constant near the mean state keeps FP32 states
                           accurate at low Mach number, where rho E is dominated by the internal
@@ -143,9 +144,9 @@ typedef struct adj_objective {
 /* Bytes of scratch the caller must pass as `ws` to any call on this grid. */
 size_t adj_workspace_bytes(const adj_grid* grid);
 
-/* Bytes of one BF16 checkpoint record: the block header (25 FP32 values per 4x4x4 block of
- * cells, padded to a multiple of 256 bytes) followed by 5N bfloat16 codes in the state layout
- * (see adj_ckpt_encode). */
+/* Bytes of one checkpoint record: the block header (25 FP32 values per 4x4x4 block of cells,
+ * padded to a multiple of 256 bytes) followed by 5N 16-bit codes in the state layout (see
+ * adj_ckpt_encode; the same size for BF16 and fixed-point codes). */
 size_t adj_ckpt_bytes(const adj_grid* grid);
 
 /* One time step of the primal (classical RK4, or SSP-RK3 when grid->time_scheme says so)
@@ -153,8 +154,9 @@ size_t adj_ckpt_bytes(const adj_grid* grid);
  *   w_n   in : state at step n                     (state-sized)
  *   s     in : source field, or NULL for s = 0      (state-sized)
  *   w_np1 out: state at step n+1 (must not alias w_n)
- *   ckpt_out : NULL, or an adj_ckpt_bytes() record receiving the BF16 encoding of w_np1
- *              (precision ADJ_F32 only)  [Implementation: checkpointing] */
+ *   ckpt_out : NULL, or an adj_ckpt_bytes() record receiving the encoding of w_np1 (BF16
+ *              codes, fixed-point codes when ckpt_format is ADJ_CKPT_I16; precision ADJ_F32
+ *              only)  [Implementation: checkpointing] */
 int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out,
                     void* ws, size_t ws_bytes, void* stream);
 
@@ -178,7 +180,7 @@ int adj_primal_step_obj(const adj_grid* grid, const void* w_n, const void* s, vo
  * where a = w^_{n+1} and (L_nu q)_i = sum_d [nu_{i+1/2}(q_{i+1}-q_i) - nu_{i-1/2}(q_i-q_{i-1})]/dx_d^2
  * with face nu the mean of its cells (no artificial flux through slip walls), applied to each
  * component with the nu of its variable group (grid->nu_weight).
- *   w_n     in : primal state at step n (state-sized), or a BF16 record when ckpt_format says so
+ *   w_n     in : primal state at step n (state-sized), or a record when ckpt_format says so
  *   s       in : source field or NULL
  *   wh_np1  in : adjoint at step n+1 (state-sized)
  *   lambda  in : artificial-viscosity scale, units length^2 (>= 0; 0 = plain adjoint)
@@ -234,7 +236,7 @@ int adj_energy_vhat(const adj_grid* grid, const void* w, const void* wh, double*
 int adj_dot(const adj_grid* grid, const void* a, const void* b, double* out, void* ws, size_t ws_bytes,
             void* stream);
 
-/* BF16 checkpoint codec (ADJ_F32 states), block-scaled with a plane predictor: the grid is cut
+/* Checkpoint codec (ADJ_F32 states), block-scaled with a plane predictor: the grid is cut
  * into 4x4x4 blocks of cells (ragged at the far ends), block b = (bz*nby + by)*nbx + bx,
  * nbd = ceil(n[d]/4).  Per block and variable v, over the block's present cells with centred
  * local coordinates c_d = l_d - (n'_d - 1)/2 (n'_d present cells along d):
@@ -243,12 +245,20 @@ int adj_dot(const adj_grid* grid, const void* a, const void* b, double* out, voi
  *     added pairwise along x, then the rows pairwise along y), rounded to FP32;
  *   P(a) = fma(g_z, c_z, fma(g_y, c_y, fma(g_x, c_x, a))); r0 = w - P(a);
  *   a' = a + (max r0 + min r0)/2, s = (max r0 - min r0)/2 (1 when the range is empty);
- *   code = bf16_round_nearest_even((w - P(a'))/s) in FP32 with IEEE division;
- *   decode w' = fma(s, code, P(a')).
+ *   t = (w - P(a'))/s in FP32 with IEEE division (|t| <= 1 up to rounding);
+ *   BF16 codes (ckpt_format ADJ_CKPT_BF16, and NATIVE grids calling the codec directly):
+ *     code = bf16_round_nearest_even(t), decode w' = fma(s, code, P(a'));
+ *   fixed-point codes (ADJ_CKPT_I16): code = the int16 nearest (ties to even) to the FP32
+ *     product t * 32767, clamped to +-32767; decode w' = fma(s, code * h, P(a')) with
+ *     h = 1/32767 rounded to FP32 and the product rounded to FP32.  The BF16 code keeps 2^-9
+ *     of each value's own magnitude; the fixed-point code keeps s/65534 whatever the value
+ *     (128 times finer at the ends of the range), which matters for fields whose blocks are
+ *     perturbations at the grid scale.
  * Record (adj_ckpt_bytes): header of 25 floats per block, header[(b*5 + v)*5 + {0..4}] =
  * a', g_x, g_y, g_z, s, padded to a multiple of 256 bytes, then the 5N codes in the state
  * layout.  Records must be 64-byte aligned  [Implementation: checkpointing; the precision form
- * keeps the primal snapshots in BF16 under per-variable scaling]. */
+ * keeps the primal snapshots in BF16 under per-variable scaling; the fixed-point codes are an
+ * alternative of the same size]. */
 int adj_ckpt_encode(const adj_grid* grid, const float* w, void* ckpt, void* ws, size_t ws_bytes, void* stream);
 int adj_ckpt_decode(const adj_grid* grid, const void* ckpt, float* w, void* stream);
 

@@ -97,8 +97,10 @@ def lib():
             "orc_cell_growth_matrix": [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp],
             "orc_energy_vhat": [gp, dp, dp, dp, dp],
             "orc_ckpt_blocks": [ctypes.POINTER(OrcGrid)],
-            "orc_ckpt_encode": [ctypes.POINTER(OrcGrid), P(ctypes.c_float), P(ctypes.c_uint16), P(ctypes.c_float)],
-            "orc_ckpt_decode": [ctypes.POINTER(OrcGrid), P(ctypes.c_uint16), P(ctypes.c_float), P(ctypes.c_float)],
+            "orc_ckpt_encode": [ctypes.POINTER(OrcGrid), P(ctypes.c_float), P(ctypes.c_uint16), P(ctypes.c_float),
+                                ctypes.c_int],
+            "orc_ckpt_decode": [ctypes.POINTER(OrcGrid), P(ctypes.c_uint16), P(ctypes.c_float), P(ctypes.c_float),
+                                ctypes.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -364,26 +366,27 @@ def energy_vhat(g, w, wh):
     return E.value, vhat
 
 
-def ckpt_encode(g, w32):
-    """Block-scaled BF16 encoding of an FP32 state with a plane predictor per block and variable:
-    (codes, header[blocks, 25]) with header[b, 5 v + (0..4)] = a', g_x, g_y, g_z, s."""
+def ckpt_encode(g, w32, i16=False):
+    """Block-scaled encoding of an FP32 state with a plane predictor per block and variable:
+    (codes, header[blocks, 25]) with header[b, 5 v + (0..4)] = a', g_x, g_y, g_z, s; BF16 codes,
+    or 16-bit fixed-point codes when i16."""
     w32 = np.ascontiguousarray(w32, dtype=np.float32)
     nb = lib().orc_ckpt_blocks(ctypes.byref(g))
     q = np.zeros(w32.size, dtype=np.uint16)
     hdr = np.zeros((nb, 25), dtype=np.float32)
     lib().orc_ckpt_encode(ctypes.byref(g), w32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                           q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
-                          hdr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+                          hdr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(bool(i16)))
     return q, hdr
 
 
-def ckpt_decode(g, q, hdr):
+def ckpt_decode(g, q, hdr, i16=False):
     q = np.ascontiguousarray(q, dtype=np.uint16)
     hdr = np.ascontiguousarray(hdr, dtype=np.float32)
     out = np.zeros(q.size, dtype=np.float32)
     lib().orc_ckpt_decode(ctypes.byref(g), q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
                           hdr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
-                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(bool(i16)))
     return out
 
 

@@ -1176,7 +1176,8 @@ int orc_energy_vhat(const orc_grid* gr, const double* w, const double* wh, doubl
 //            with S_0 = sum w, S_d = sum c_d w in FP64, each rounded to FP32;
 //   P(a) = fma(g_z, c_z, fma(g_y, c_y, fma(g_x, c_x, a))) in FP32; r0 = w - P(a);
 //   a' = a + (max r0 + min r0)/2, s = (max r0 - min r0)/2 (1 if the range is 0);
-//   q = bf16_round_nearest_even((w - P(a')) / s),   decode w' = fma(s, q, P(a')).
+//   q = bf16_round_nearest_even((w - P(a')) / s),   decode w' = fma(s, q, P(a'));
+//   or, with 16-bit fixed-point codes, q = i16 of (w - P(a')) / s (below), same decode form.
 // header[(b * 5 + v) * 5 + {0..4}] = a', g_x, g_y, g_z, s.  Codes keep the state layout.
 // The FP64 sums run in one fixed order (so that two implementations round alike): per (x, y)
 // column the cells z = 0..3 accumulate by fma (c w is exact in FP64), then columns add pairwise
@@ -1190,6 +1191,17 @@ static uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 static float bf16_to_f32(uint16_t h) { uint32_t u = (uint32_t)h << 16; float f; std::memcpy(&f, &u, 4); return f; }
+
+// The fixed-point alternative of the same size: code = the int16 nearest to t * 32767 (ties to
+// even, the product rounded to FP32), clamped to +-32767; its value is code * h with
+// h = 1/32767 rounded to FP32 (the product rounded to FP32).
+static uint16_t f32_to_i16(float t) {
+  float k = std::nearbyint(t * 32767.0f);
+  if (k > 32767.0f) k = 32767.0f;
+  if (k < -32767.0f) k = -32767.0f;
+  return (uint16_t)(int16_t)k;
+}
+static float i16_to_f32(uint16_t q) { return (float)(int16_t)q * (1.0f / 32767.0f); }
 
 static void codec_blocks(const orc_grid* g, long& nbx, long& nby, long& nbz) {
   nbx = (g->n[0] + 3) / 4; nby = (g->n[1] + 3) / 4; nbz = (g->n[2] + 3) / 4;
@@ -1206,7 +1218,7 @@ static float plane_at(const float* h, float cx, float cy, float cz) {
   return std::fma(h[3], cz, std::fma(h[2], cy, std::fma(h[1], cx, h[0])));
 }
 
-int orc_ckpt_encode(const orc_grid* g, const float* w, uint16_t* q, float* header) {
+int orc_ckpt_encode(const orc_grid* g, const float* w, uint16_t* q, float* header, int i16) {
   const long nx = g->n[0], ny = g->n[1], nz = g->n[2], N = nx * ny * nz;
   long nbx, nby, nbz; codec_blocks(g, nbx, nby, nbz);
   for (long bz = 0; bz < nbz; ++bz)
@@ -1255,14 +1267,15 @@ int orc_ckpt_encode(const orc_grid* g, const float* w, uint16_t* q, float* heade
             for (long j = 0; j < my; ++j)
               for (long i = 0; i < mx; ++i) {
                 const long c = v * N + ((4 * bz + k) * ny + 4 * by + j) * nx + 4 * bx + i;
-                q[c] = f32_to_bf16_rne((w[c] - plane_at(h, centred(i, mx), centred(j, my), centred(k, mz))) / s);
+                const float t = (w[c] - plane_at(h, centred(i, mx), centred(j, my), centred(k, mz))) / s;
+                q[c] = i16 ? f32_to_i16(t) : f32_to_bf16_rne(t);
               }
         }
       }
   return 0;
 }
 
-int orc_ckpt_decode(const orc_grid* g, const uint16_t* q, const float* header, float* w) {
+int orc_ckpt_decode(const orc_grid* g, const uint16_t* q, const float* header, float* w, int i16) {
   const long nx = g->n[0], ny = g->n[1], nz = g->n[2], N = nx * ny * nz;
   long nbx, nby, nbz; codec_blocks(g, nbx, nby, nbz);
   for (int v = 0; v < 5; ++v)
@@ -1273,7 +1286,8 @@ int orc_ckpt_decode(const orc_grid* g, const uint16_t* q, const float* header, f
           const long mx = std::min(4L, nx - 4 * (i / 4)), my = std::min(4L, ny - 4 * (j / 4)),
                      mz = std::min(4L, nz - 4 * (k / 4));
           const float* h = header + (b * 5 + v) * 5;
-          w[c] = std::fma(h[4], bf16_to_f32(q[c]), plane_at(h, centred(i % 4, mx), centred(j % 4, my), centred(k % 4, mz)));
+          w[c] = std::fma(h[4], i16 ? i16_to_f32(q[c]) : bf16_to_f32(q[c]),
+                          plane_at(h, centred(i % 4, mx), centred(j % 4, my), centred(k % 4, mz)));
         }
   return 0;
 }

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libadjns.so")
 
 F64, F32 = 0, 1
-CKPT_NATIVE, CKPT_BF16 = 0, 1
+CKPT_NATIVE, CKPT_BF16, CKPT_I16 = 0, 1, 2  # CKPT_BF16 and CKPT_I16 keep 16-bit records
 BC_PERIODIC, BC_SLIP_WALLS, BC_CHARACTERISTIC = 0, 1, 2
 RK4, SSPRK3 = 0, 1
 FLUX_SPLIT, FLUX_ROE = 0, 1
@@ -271,9 +271,9 @@ def primal_step_obj(g, w_n, s, w_np1, ws, obj, weight, J_accum, ckpt_out=None, s
 
 
 def adjoint_step(g, w_n, s, wh_np1, wh_n, ws, lam=0.0, obj=None, c_n=0.0, grad_s=None):
-    """w_n is a state tensor, or a uint8 BF16 record when g.ckpt_format == CKPT_BF16."""
+    """w_n is a state tensor, or a uint8 record (BF16 or fixed-point codes) when g.ckpt_format != CKPT_NATIVE."""
     wp, wb = _ws(ws)
-    wn_p = _ptr(w_n, torch.uint8) if g.ckpt_format == CKPT_BF16 else _state(g, w_n)
+    wn_p = _ptr(w_n, torch.uint8) if g.ckpt_format != CKPT_NATIVE else _state(g, w_n)
     _check(lib().adj_adjoint_step(ctypes.byref(g), wn_p, _state(g, s), _state(g, wh_np1), float(lam),
                                   ctypes.byref(obj) if obj is not None else None, float(c_n), _state(g, wh_n),
                                   _state(g, grad_s), wp, wb, _stream()))
@@ -285,7 +285,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20  # ADJ_NOALLOC_SCRATCH_BYTES
 def adjoint_step_noalloc(g, w_n, s, wh_np1, wh_n, lam=0.0, obj=None, c_n=0.0, grad_s=None):
     """adjoint_step without a workspace: the library's static per-GPU scratch array serves instead
     (grids whose workspace_bytes(g) <= NOALLOC_SCRATCH_BYTES; calls overlapping on one GPU race)."""
-    wn_p = _ptr(w_n, torch.uint8) if g.ckpt_format == CKPT_BF16 else _state(g, w_n)
+    wn_p = _ptr(w_n, torch.uint8) if g.ckpt_format != CKPT_NATIVE else _state(g, w_n)
     _check(lib().adj_adjoint_step_noalloc(ctypes.byref(g), wn_p, _state(g, s), _state(g, wh_np1), float(lam),
                                           ctypes.byref(obj) if obj is not None else None, float(c_n),
                                           _state(g, wh_n), _state(g, grad_s), _stream()))

@@ -704,7 +704,7 @@ __global__ __launch_bounds__(RB) void k_ptloss_grad(Consts<T> c, const T* __rest
 }
 
 // ------------------------------------------------------------------------------------------
-// BF16 codec
+// BF16 codec (and its 16-bit fixed-point variant)
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
@@ -712,6 +712,16 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
+
+// Fixed-point code of t = r / s in [-1, 1]: the nearest integer (ties to even) of t * 32767,
+// clamped to +-32767, as the bits of an int16; its value is code * (1/32767 rounded to FP32).
+constexpr float I16_SCALE = 32767.0f;
+constexpr float I16_STEP = 1.0f / 32767.0f;
+__device__ __forceinline__ uint16_t i16_code(float t) {
+  const float k = fminf(fmaxf(rintf(t * I16_SCALE), -I16_SCALE), I16_SCALE);
+  return (uint16_t)(int16_t)(int)k;
+}
+__device__ __forceinline__ float i16_value(uint16_t q) { return (float)(int16_t)q * I16_STEP; }
 
 // Block-scaled BF16 codec with a plane predictor: 4 x 4 x 4 cell blocks (ragged at the far ends).
 // Per block and variable, with the present cells' local coordinates centred on the block
@@ -722,6 +732,9 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 //   r0 = w - P(a), P(a) = fma(g_z, c_z, fma(g_y, c_y, fma(g_x, c_x, a)));
 //   a' = a + (max r0 + min r0)/2, s = (max r0 - min r0)/2 (1 for an empty range);
 //   code = RNE_bf16((w - P(a')) / s) with IEEE division;  decode w' = fma(s, code, P(a')).
+//   The fixed-point variant (I16) codes the same quotient as i16_code and decodes
+//   fma(s, i16_value(code), P(a')): an error of at most s / 65534 whatever the value, where BF16
+//   keeps 2^-9 of each value (better near zero, 128 times worse at the edges of the range).
 // header[(b * 5 + v) * 5 + {0, 1, 2, 3, 4}] = a', g_x, g_y, g_z, s with blocks numbered x fastest;
 // codes keep the state layout.  The fixed summation order: each cell (lane) sums its z column,
 // c(z) w_z accumulated z = 0..3 by fma (the products are exact in FP64); the columns then add
@@ -785,6 +798,7 @@ __device__ __forceinline__ double block_sum(double v) {
   return v;
 }
 
+template <bool I16>
 __global__ __launch_bounds__(RB) void k_encode(Consts<float> c, const float* __restrict__ w, float* __restrict__ header,
                                                uint16_t* __restrict__ codes) {
   const CodecStrip q = codec_strip(c);
@@ -842,11 +856,14 @@ __global__ __launch_bounds__(RB) void k_encode(Consts<float> c, const float* __r
     }
 #pragma unroll
     for (int z = 0; z < 4; ++z)
-      if (q.act[z])
-        codes[v * N + q.i[z]] = bf16_rne(__fdiv_rn(x[v][z] - plane(a2, gx, gy, gz, q.cx, q.cy, q.cz[z]), s));
+      if (q.act[z]) {
+        const float t = __fdiv_rn(x[v][z] - plane(a2, gx, gy, gz, q.cx, q.cy, q.cz[z]), s);
+        codes[v * N + q.i[z]] = I16 ? i16_code(t) : bf16_rne(t);
+      }
   }
 }
 
+template <bool I16>
 __global__ __launch_bounds__(RB) void k_decode(Consts<float> c, const float* __restrict__ header,
                                                const uint16_t* __restrict__ codes, float* __restrict__ w) {
   const CodecStrip q = codec_strip(c);
@@ -864,7 +881,8 @@ __global__ __launch_bounds__(RB) void k_decode(Consts<float> c, const float* __r
 #pragma unroll
     for (int z = 0; z < 4; ++z)
       if (q.act[z])
-        w[v * N + q.i[z]] = fmaf(s, __uint_as_float((uint32_t)k[v][z] << 16), plane(a, gx, gy, gz, q.cx, q.cy, q.cz[z]));
+        w[v * N + q.i[z]] = fmaf(s, I16 ? i16_value(k[v][z]) : __uint_as_float((uint32_t)k[v][z] << 16),
+                                 plane(a, gx, gy, gz, q.cx, q.cy, q.cz[z]));
   }
 }
 
@@ -953,17 +971,23 @@ hipError_t launch_fold(const double* partials, int n, double* dst, double alpha,
   return hipGetLastError();
 }
 
-hipError_t launch_ckpt_encode(const Consts<float>& c, const float* w, float* header, uint16_t* codes,
+hipError_t launch_ckpt_encode(const Consts<float>& c, const float* w, float* header, uint16_t* codes, bool i16,
                               hipStream_t st) {
   ProfScope ps(ADJ_PROF_CODEC, st, true);
-  timed_launch(ps, k_encode, dim3(codec_groups(c)), dim3(RB), st, c, w, header, codes);
+  if (i16)
+    timed_launch(ps, k_encode<true>, dim3(codec_groups(c)), dim3(RB), st, c, w, header, codes);
+  else
+    timed_launch(ps, k_encode<false>, dim3(codec_groups(c)), dim3(RB), st, c, w, header, codes);
   return hipGetLastError();
 }
 
-hipError_t launch_ckpt_decode(const Consts<float>& c, const float* header, const uint16_t* codes, float* w,
+hipError_t launch_ckpt_decode(const Consts<float>& c, const float* header, const uint16_t* codes, float* w, bool i16,
                               hipStream_t st) {
   ProfScope ps(ADJ_PROF_CODEC, st, true);
-  timed_launch(ps, k_decode, dim3(codec_groups(c)), dim3(RB), st, c, header, codes, w);
+  if (i16)
+    timed_launch(ps, k_decode<true>, dim3(codec_groups(c)), dim3(RB), st, c, header, codes, w);
+  else
+    timed_launch(ps, k_decode<false>, dim3(codec_groups(c)), dim3(RB), st, c, header, codes, w);
   return hipGetLastError();
 }
 

@@ -114,10 +114,10 @@ int check_grid(const adj_grid* g, bool need_dt) {
   }
   if (5 * (double)ncells(g) * (g->precision == ADJ_F64 ? 8.0 : 4.0) >= 4294967296.0)
     return fail(ADJ_ESHAPE, "state arrays must span less than 4 GiB (%lld cells)", ncells(g));
-  if (g->ckpt_format != ADJ_CKPT_NATIVE && g->ckpt_format != ADJ_CKPT_BF16)
+  if (g->ckpt_format != ADJ_CKPT_NATIVE && g->ckpt_format != ADJ_CKPT_BF16 && g->ckpt_format != ADJ_CKPT_I16)
     return fail(ADJ_EINVAL, "bad ckpt_format %d", g->ckpt_format);
-  if (g->ckpt_format == ADJ_CKPT_BF16 && g->precision != ADJ_F32)
-    return fail(ADJ_EINVAL, "BF16 checkpoints need precision ADJ_F32");
+  if (g->ckpt_format != ADJ_CKPT_NATIVE && g->precision != ADJ_F32)
+    return fail(ADJ_EINVAL, "checkpoint records need precision ADJ_F32");
   return ADJ_OK;
 }
 
@@ -254,7 +254,7 @@ int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, 
     if constexpr (sizeof(T) == sizeof(float)) {
       float* hdr = (float*)ckpt;
       uint16_t* codes = (uint16_t*)at(ckpt, ckpt_header_bytes(g));
-      if ((e = launch_ckpt_encode(c, (const float*)out, hdr, codes, st)))
+      if ((e = launch_ckpt_encode(c, (const float*)out, hdr, codes, g->ckpt_format == ADJ_CKPT_I16, st)))
         return hip_fail(e, "checkpoint encode");
     }
   }
@@ -328,11 +328,12 @@ int adjoint_step(const adj_grid* g, const void* wn_in, const T* stages, const T*
   T* nu = (T*)at(ws, L.nu);
   hipError_t e;
   const T* wn = (const T*)wn_in;
-  if (g->ckpt_format == ADJ_CKPT_BF16) {
+  if (g->ckpt_format != ADJ_CKPT_NATIVE) {
     if constexpr (sizeof(T) == sizeof(float)) {
       float* dec = (float*)at(ws, L.wdec);
       if ((e = launch_ckpt_decode(c, (const float*)wn_in,
-                                  (const uint16_t*)((const char*)wn_in + ckpt_header_bytes(g)), dec, st)))
+                                  (const uint16_t*)((const char*)wn_in + ckpt_header_bytes(g)), dec,
+                                  g->ckpt_format == ADJ_CKPT_I16, st)))
         return hip_fail(e, "checkpoint decode");
       wn = (const T*)dec;
     }
@@ -642,24 +643,24 @@ int adj_dot(const adj_grid* grid, const void* a, const void* b, double* out, voi
 int adj_ckpt_encode(const adj_grid* grid, const float* w, void* ckpt, void* ws, size_t ws_bytes, void* stream) {
   int r;
   if ((r = check_grid(grid, false))) return r;
-  if (grid->precision != ADJ_F32) return fail(ADJ_EINVAL, "BF16 checkpoints need precision ADJ_F32");
+  if (grid->precision != ADJ_F32) return fail(ADJ_EINVAL, "checkpoint records need precision ADJ_F32");
   if ((r = check_ws(grid, ws, ws_bytes))) return r;
   if (!w || !ckpt) return fail(ADJ_EINVAL, "w and ckpt must be non-NULL");
   if ((uintptr_t)ckpt % 64) return fail(ADJ_EINVAL, "ckpt must be 64-byte aligned");
   hipError_t e = launch_ckpt_encode(consts<float>(grid), w, (float*)ckpt, (uint16_t*)at(ckpt, ckpt_header_bytes(grid)),
-                                    (hipStream_t)stream);
+                                    grid->ckpt_format == ADJ_CKPT_I16, (hipStream_t)stream);
   return e ? hip_fail(e, "encode") : ADJ_OK;
 }
 
 int adj_ckpt_decode(const adj_grid* grid, const void* ckpt, float* w, void* stream) {
   int r;
   if ((r = check_grid(grid, false))) return r;
-  if (grid->precision != ADJ_F32) return fail(ADJ_EINVAL, "BF16 checkpoints need precision ADJ_F32");
+  if (grid->precision != ADJ_F32) return fail(ADJ_EINVAL, "checkpoint records need precision ADJ_F32");
   if (!w || !ckpt) return fail(ADJ_EINVAL, "w and ckpt must be non-NULL");
   if ((uintptr_t)ckpt % 64) return fail(ADJ_EINVAL, "ckpt must be 64-byte aligned");
   hipError_t e = launch_ckpt_decode(consts<float>(grid), (const float*)ckpt,
                                     (const uint16_t*)((const char*)ckpt + ckpt_header_bytes(grid)), w,
-                                    (hipStream_t)stream);
+                                    grid->ckpt_format == ADJ_CKPT_I16, (hipStream_t)stream);
   return e ? hip_fail(e, "decode") : ADJ_OK;
 }
 

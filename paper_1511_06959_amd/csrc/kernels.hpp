@@ -113,11 +113,11 @@ template <typename T>
 hipError_t launch_energy_batch(const BoxDesc<T>* mems, const int* start, const int* start_host, int count, const T* w,
                                const T* wh, double* partials, double* E, hipStream_t st);
 
-// block-scaled BF16 checkpoint codec; header = 25 floats (plane a, g_x, g_y, g_z and scale s) x 5 per
-// 4x4x4 block
-hipError_t launch_ckpt_encode(const Consts<float>& c, const float* w, float* header, uint16_t* codes,
+// block-scaled checkpoint codec (BF16 codes, or 16-bit fixed-point codes when i16); header = 25
+// floats (plane a, g_x, g_y, g_z and scale s) x 5 per 4x4x4 block
+hipError_t launch_ckpt_encode(const Consts<float>& c, const float* w, float* header, uint16_t* codes, bool i16,
                               hipStream_t st);
-hipError_t launch_ckpt_decode(const Consts<float>& c, const float* header, const uint16_t* codes, float* w,
+hipError_t launch_ckpt_decode(const Consts<float>& c, const float* header, const uint16_t* codes, float* w, bool i16,
                               hipStream_t st);
 
 }  // namespace adjns

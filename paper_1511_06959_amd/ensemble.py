@@ -241,9 +241,9 @@ class LambdaSweep:
     """
 
     def __init__(self, g, traj, lams, obj=None, weights=None, s=None, energy=False, device="cuda"):
-        from . import CKPT_BF16, Grid
+        from . import CKPT_NATIVE, Grid
         self.g, self.traj = g, traj
-        self.bf16 = g.ckpt_format == CKPT_BF16
+        self.bf16 = g.ckpt_format != CKPT_NATIVE
         self.gn = Grid.make(tuple(g.n), tuple(g.L), g.mu, g.dt, g.gamma, g.prandtl, g.bc_x, g.precision, 0,
                             tuple(g.w_ref), tuple(g.nu_weight), g.time_scheme, g.flux, g.roe_delta)
         self.lams = [float(x) for x in lams]

@@ -20,7 +20,7 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import torch
 
-from . import (CKPT_BF16, OBJ_NONE, adjoint_step, ckpt_bytes, ckpt_decode, ckpt_encode, objective_and_grad,
+from . import (CKPT_NATIVE, OBJ_NONE, adjoint_step, ckpt_bytes, ckpt_decode, ckpt_encode, objective_and_grad,
                workspace)
 from .sweep import step_obj
 
@@ -137,7 +137,7 @@ class HostTrajectory:
         if slots < 2:
             raise ValueError("at least two device slots")
         self.g, self.nsteps = g, nsteps
-        self.bf16 = g.ckpt_format == CKPT_BF16
+        self.bf16 = g.ckpt_format != CKPT_NATIVE
         if self.bf16:
             self.rec_len, dt = ckpt_bytes(g), torch.uint8
         else:

@@ -13,7 +13,7 @@ Only scheduling happens here; all arithmetic runs in the library's kernels.
 """
 import torch
 
-from . import (CKPT_BF16, OBJ_NONE, Grid, Objective, adjoint_step, adjoint_step_stages, ckpt_bytes, energy_vhat,
+from . import (CKPT_NATIVE, OBJ_NONE, Grid, Objective, adjoint_step, adjoint_step_stages, ckpt_bytes, energy_vhat,
                objective_and_grad, primal_step, primal_step_obj, primal_step_stages, workspace)
 
 
@@ -37,7 +37,7 @@ class Trajectory:
         self.g = g
         self.nsteps = nsteps
         N5 = 5 * g.ncells
-        if g.ckpt_format == CKPT_BF16:
+        if g.ckpt_format != CKPT_NATIVE:
             if stages:
                 raise ValueError("stage states are stored natively, not as BF16 records")
             self.rec_bytes = ckpt_bytes(g)
@@ -61,7 +61,7 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
     ws = workspace(g) if ws is None else ws
     traj = Trajectory(g, nsteps, w0.device) if traj is None else traj
     J = torch.zeros(1, dtype=torch.float64, device=w0.device) if J is None else J
-    bf16 = g.ckpt_format == CKPT_BF16
+    bf16 = g.ckpt_format != CKPT_NATIVE
     cur = w0.clone()
     nxt = torch.empty_like(w0)
     if bf16:
@@ -98,7 +98,7 @@ def backward(g, traj, s, obj=None, weights=None, lam=0.0, ws=None, grad_s=None, 
     b = torch.empty_like(a)
     grad_s = torch.zeros(N5, dtype=g.dtype, device=dev) if grad_s is None else grad_s
     use_obj = obj is not None and obj.kind != OBJ_NONE and weights is not None
-    bf16 = g.ckpt_format == CKPT_BF16
+    bf16 = g.ckpt_format != CKPT_NATIVE
     dec = None
     if bf16 or energy:
         dec = torch.empty(N5, dtype=g.dtype, device=dev)
@@ -188,14 +188,14 @@ class RevolveSweep:
     ``forward(w0)`` runs the primal once over the window, accumulating J on every state and
     storing the snapshots the reverse schedule starts from; ``backward(scale)`` replays the rest
     of the schedule: recomputation from snapshots and reverse steps, with objective weights
-    multiplied by ``scale``.  With ``g.ckpt_format == CKPT_BF16`` the slots hold BF16 records; the
+    multiplied by ``scale``.  With ``g.ckpt_format != CKPT_NATIVE`` the slots hold records (BF16 or fixed-point codes); the
     working state is always full precision.  Slots = nsteps + 1 reproduces the store-all sweep.
     """
 
     def __init__(self, g, nsteps, slots, s=None, obj=None, weights=None, lam=0.0, ws=None, device="cuda"):
         from . import revolve
         self.g = g
-        self.bf16 = g.ckpt_format == CKPT_BF16
+        self.bf16 = g.ckpt_format != CKPT_NATIVE
         self.gn = Grid.make(tuple(g.n), tuple(g.L), g.mu, g.dt, g.gamma, g.prandtl, g.bc_x, g.precision, 0,
                             tuple(g.w_ref), tuple(g.nu_weight), g.time_scheme, g.flux, g.roe_delta,
                             (tuple(g.w_far[0:5]), tuple(g.w_far[5:10])))
@@ -311,8 +311,8 @@ class RevolveSweep:
 
 
 class SegmentSweep:
-    """Two-level checkpointing: the forward sweep keeps a snapshot (a BF16 record when
-    ``g.ckpt_format == CKPT_BF16``, else a native state) every ``seg`` steps; the reverse sweep
+    """Two-level checkpointing: the forward sweep keeps a snapshot (a 16-bit record when
+    ``g.ckpt_format != CKPT_NATIVE``, else a native state) every ``seg`` steps; the reverse sweep
     re-advances one segment at a time from its snapshot, keeping every state of the segment and the
     stage states of each of its steps in HBM (``primal_step_stages``), and then reverses the
     segment with ``adjoint_step_stages``, so that no reverse step recomputes a stage state.
@@ -326,7 +326,7 @@ class SegmentSweep:
 
     def __init__(self, g, nsteps, seg, s=None, obj=None, weights=None, lam=0.0, ws=None, device="cuda"):
         self.g = g
-        self.bf16 = g.ckpt_format == CKPT_BF16
+        self.bf16 = g.ckpt_format != CKPT_NATIVE
         self.gn = Grid.make(tuple(g.n), tuple(g.L), g.mu, g.dt, g.gamma, g.prandtl, g.bc_x, g.precision, 0,
                             tuple(g.w_ref), tuple(g.nu_weight), g.time_scheme, g.flux, g.roe_delta,
                             (tuple(g.w_far[0:5]), tuple(g.w_far[5:10])))
@@ -429,7 +429,7 @@ def segment_bytes(g, nsteps, seg):
 
 def snapshot_bytes(g):
     """Bytes of one snapshot: a BF16 record or a native state."""
-    return ckpt_bytes(g) if g.ckpt_format == CKPT_BF16 else 5 * g.ncells * (8 if g.precision == 0 else 4)
+    return ckpt_bytes(g) if g.ckpt_format != CKPT_NATIVE else 5 * g.ncells * (8 if g.precision == 0 else 4)
 
 
 def segment_length(g, nsteps):

@@ -51,6 +51,7 @@ def test_workspace_and_record_sizes():
 @pytest.mark.parametrize("bad,code", [
     (dict(n=(0, 8, 4)), -1), (dict(L=(0.0, 1.0, 1.0)), -1), (dict(gamma=1.0), -1), (dict(prandtl=0.0), -1),
     (dict(mu=-1.0), -1), (dict(precision=7), -1), (dict(ckpt_format=adj.CKPT_BF16), -1),
+    (dict(ckpt_format=adj.CKPT_I16), -1), (dict(ckpt_format=3), -1),
     (dict(n=(1, 8, 4), bc_x=adj.BC_SLIP_WALLS), -2), (dict(bc_x=5), -1), (dict(dt=0.0), -1),
     (dict(nu_weight=(1.0, -0.5, 1.0)), -1), (dict(nu_weight=(1.0, 1.0, float("nan"))), -1), (dict(time_scheme=2), -1),
     (dict(flux=2), -1), (dict(flux=adj.FLUX_ROE, roe_delta=0.0), -1),

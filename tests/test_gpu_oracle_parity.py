@@ -103,14 +103,16 @@ def test_bf16_segment_window_vs_oracle(c1, seg):
 
 @pytest.mark.parametrize("lam_factor", [0.0, 0.1], ids=["lam0", "lam"])
 @pytest.mark.parametrize("bc_x", [0, 1], ids=["periodic", "walls"])
-def test_bf16_record_reverse_step_vs_oracle_on_decoded_state(orc, bc_x, lam_factor):
-    # one reverse step whose primal state comes from a BF16 record, against the oracle's step on
-    # the state the oracle's own decoder returns for the same record (the codecs agree bit for bit)
+@pytest.mark.parametrize("fmt", [adj.CKPT_BF16, adj.CKPT_I16], ids=["bf16", "i16"])
+def test_bf16_record_reverse_step_vs_oracle_on_decoded_state(orc, bc_x, lam_factor, fmt):
+    # one reverse step whose primal state comes from a record (BF16 or fixed-point codes), against
+    # the oracle's step on the state the oracle's own decoder returns for the same record (the
+    # codecs agree bit for bit)
     n = (37, 9, 6)
     L = (2.0, 0.5, 0.4)
     wfull = smooth_state(n, L, seed=41, wall=bc_x == 1)
     ref = tuple(wfull.reshape(5, -1).mean(axis=1))
-    g = adj.Grid.make(n, L, 2e-3, 1e-3, bc_x=bc_x, precision=adj.F32, ckpt_format=adj.CKPT_BF16, w_ref=ref)
+    g = adj.Grid.make(n, L, 2e-3, 1e-3, bc_x=bc_x, precision=adj.F32, ckpt_format=fmt, w_ref=ref)
     og = orc.make_grid(n, L, 1.4, 0.72, 2e-3, 1e-3, bc_x)
     dev32 = g.to_stored(wfull).astype(np.float32)
     rng = np.random.default_rng(42)
@@ -126,8 +128,9 @@ def test_bf16_record_reverse_step_vs_oracle_on_decoded_state(orc, bc_x, lam_fact
     oobj = orc.make_obj(W.OBJ_PT_LOSS_PLANE, 20, 1.2)
     adj.adjoint_step(g, rec, dev(s, torch.float32), dev(a, torch.float32), wh, ws, lam=lam,
                      obj=adj.Objective.make(W.OBJ_PT_LOSS_PLANE, 20, 1.2), c_n=0.3, grad_s=gsd)
-    q, hdr = orc.ckpt_encode(og, dev32)
-    wdec = (orc.ckpt_decode(og, q, hdr).astype(np.float64).reshape(5, -1) + np.array(ref)[:, None]).ravel()
+    q, hdr = orc.ckpt_encode(og, dev32, i16=fmt == adj.CKPT_I16)
+    wdec = (orc.ckpt_decode(og, q, hdr, i16=fmt == adj.CKPT_I16).astype(np.float64).reshape(5, -1)
+            + np.array(ref)[:, None]).ravel()
     gref = gs0.astype(np.float32).astype(np.float64)
     whr = orc.adjoint_step(og, wdec, s.astype(np.float32).astype(np.float64), a.astype(np.float32).astype(np.float64),
                            lam, oobj, 0.3, gref)

@@ -137,9 +137,11 @@ def test_energy_and_dot_parity(orc):
 
 # (19, 6, 9): two strips of four blocks along x, the second with one block; (37, 13, 10): three
 # strips, the last with two blocks, ragged blocks in every direction; (64, 8, 4): whole strips
+@pytest.mark.parametrize("fmt", [adj.CKPT_BF16, adj.CKPT_I16], ids=["bf16", "i16"])
 @pytest.mark.parametrize("shape", [(19, 6, 9), (37, 13, 10), (64, 8, 4)], ids=["19x6x9", "37x13x10", "64x8x4"])
-def test_codec_bitwise(orc, shape):
-    g = adj.Grid.make(shape, (1, 1, 1), 0.01, 0.01, precision=adj.F32, ckpt_format=adj.CKPT_BF16)
+def test_codec_bitwise(orc, shape, fmt):
+    g = adj.Grid.make(shape, (1, 1, 1), 0.01, 0.01, precision=adj.F32, ckpt_format=fmt)
+    i16 = fmt == adj.CKPT_I16
     w = smooth_state(shape, seed=11).astype(np.float32)
     ws = adj.workspace(g)
     rec = torch.zeros(adj.ckpt_bytes(g), dtype=torch.uint8, device="cuda")
@@ -147,7 +149,7 @@ def test_codec_bitwise(orc, shape):
     torch.cuda.synchronize()
     raw = rec.cpu().numpy()
     og = orc.make_grid(shape, (1, 1, 1), 1.4, 0.72, 0.01, 0.01, 0)
-    q, hdr_ref = orc.ckpt_encode(og, w)
+    q, hdr_ref = orc.ckpt_encode(og, w, i16=i16)
     hb = raw.size - 2 * w.size  # header bytes (block headers, padded)
     hdr = raw[:hdr_ref.size * 4].view(np.float32).reshape(hdr_ref.shape)
     codes = raw[hb:].view(np.uint16)
@@ -157,7 +159,7 @@ def test_codec_bitwise(orc, shape):
     out = torch.empty(w.size, dtype=torch.float32, device="cuda")
     adj.ckpt_decode(g, rec, out)
     torch.cuda.synchronize()
-    assert np.array_equal(out.cpu().numpy(), orc.ckpt_decode(og, q, hdr_ref))
+    assert np.array_equal(out.cpu().numpy(), orc.ckpt_decode(og, q, hdr_ref, i16=i16))
 
 
 def test_adjoint_step_deterministic():

@@ -20,7 +20,8 @@ which no block plane predicts, so the BF16 snapshot keeps each perturbation valu
 significand (2^-9 of itself): the adjoints of the small cross-stream and spanwise momenta
 (an order of magnitude below the other fields) move by up to ~1e-3 of their own scale, while the
 gradient as a whole stays within 1e-4.  The wake's FP32 path with native FP32 snapshots holds
-1e-4 per field, so the excess is the BF16 storage, not the FP32 arithmetic.
+1e-4 per field, so the excess is the BF16 storage, not the FP32 arithmetic; records of the same
+size with 16-bit fixed-point codes (s/65534 whatever the value) hold 1e-4 per field as well.
 """
 import numpy as np
 import pytest
@@ -68,7 +69,7 @@ def _window_parity(orc, wl, precision, ckpt, starts, seed, flux=0, block=36):
     s = (wl.s + 1e-3 * np.random.default_rng(seed).standard_normal(5 * N)).astype(npdt)
     weights = W.window_weights(K, 1, K)
     obj = adj.Objective.make(W.OBJ_MEAN_PRESSURE)
-    print(f"[window parity] {wl.name} {'f32' if f32 else 'f64'} {'bf16' if ckpt == adj.CKPT_BF16 else 'native'} "
+    print(f"[window parity] {wl.name} {'f32' if f32 else 'f64'} {('native', 'bf16', 'i16')[ckpt]} "
           f"snapshots{' roe' if flux else ''} K={K}", flush=True)
     sw = SegmentSweep(g, K, K, torch.from_numpy(s).to("cuda"), obj, weights, lam, adj.workspace(g))
     sw.forward(torch.from_numpy(stored).to("cuda"))
@@ -120,7 +121,8 @@ def test_turb384_window_sampled(orc, turb384, precision, ckpt, tol):
 
 @pytest.mark.parametrize("precision,ckpt,tol_field,tol_whole",
                          [(adj.F64, adj.CKPT_NATIVE, 1e-10, 1e-10), (adj.F32, adj.CKPT_NATIVE, 1e-4, 1e-4),
-                          (adj.F32, adj.CKPT_BF16, 2e-3, 1e-4)], ids=["f64", "f32", "f32-bf16"])
+                          (adj.F32, adj.CKPT_BF16, 2e-3, 1e-4), (adj.F32, adj.CKPT_I16, 1e-4, 1e-4)],
+                         ids=["f64", "f32", "f32-bf16", "f32-i16"])
 def test_wake_window_sampled(orc, wake, precision, ckpt, tol_field, tol_whole):
     nx = wake.n[0]
     starts = [(0, 10, 0), (nx - SAMPLE, 250, 8), (254, 100, 20)]

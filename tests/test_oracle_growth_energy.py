@@ -305,3 +305,49 @@ def test_bf16_codec_plane_and_rounding(orc):
     assert np.array_equal(q, ref)
     # the planar field is reproduced to float32 rounding (its residual range is rounding only)
     assert np.abs(dec[2] - W5[2]).max() <= 1e-6
+
+
+def test_i16_codec_codes_and_bound(orc):
+    # the fixed-point codes of the same records: the header is the BF16 encoding's bit for bit (it
+    # does not depend on the codes); each code is the integer nearest (ties to even, numpy rint)
+    # to the float32 product of (w - P(a'))/s and 32767, clipped to +-32767; decoding
+    # fma(s, code * float32(1/32767), P(a')) errs by at most s/65534 plus the rounding of the sum
+    n = (9, 7, 5)
+    N = n[0] * n[1] * n[2]
+    g = orc.make_grid(n, (1.0, 1.0, 1.0), 1.4, 0.72, 0.01, 0.01, 0)
+    rng = np.random.default_rng(8)
+    x, y, z = W.cell_centres(n, (1.0, 1.0, 1.0))
+    w = np.stack([1.0 + 0.3 * np.sin(3 * x + 2 * y) * np.cos(4 * z) + 0.02 * rng.standard_normal(x.shape)
+                  for _ in range(5)]).astype(np.float32).reshape(-1)
+    w[N:2 * N] = 0.25  # a constant field: s = 1, codes 0
+    q16, hdr16 = orc.ckpt_encode(g, w, i16=True)
+    qbf, hdrbf = orc.ckpt_encode(g, w)
+    assert np.array_equal(hdr16.view(np.uint32), hdrbf.view(np.uint32))
+    assert not np.array_equal(q16, qbf)
+    dec = orc.ckpt_decode(g, q16, hdr16, i16=True).reshape(5, n[2], n[1], n[0])
+    W5 = w.reshape(5, n[2], n[1], n[0])
+    codes = q16.view(np.int16).reshape(5, n[2], n[1], n[0])
+    nb = [(n[d] + 3) // 4 for d in range(3)]
+    step = np.float32(1.0 / 32767.0)
+    for bz in range(nb[2]):
+        for by in range(nb[1]):
+            for bx in range(nb[0]):
+                b = (bz * nb[1] + by) * nb[0] + bx
+                sl = (slice(4 * bz, 4 * bz + 4), slice(4 * by, 4 * by + 4), slice(4 * bx, 4 * bx + 4))
+                m = [min(4, n[d] - 4 * bb) for d, bb in ((0, bx), (1, by), (2, bz))]
+                cz, cy, cx = np.meshgrid(*[np.arange(m[d], dtype=np.float32) - np.float32(0.5 * (m[d] - 1))
+                                           for d in (2, 1, 0)], indexing="ij")
+                for v in range(5):
+                    h = hdr16[b, 5 * v:5 * v + 5]
+                    Pa = _fmaf(h[3], cz, _fmaf(h[2], cy, _fmaf(h[1], cx, h[0])))
+                    t = ((W5[v][sl] - Pa) / h[4]).astype(np.float32)
+                    want = np.clip(np.rint((t * np.float32(32767.0)).astype(np.float32)), -32767, 32767)
+                    assert np.array_equal(codes[v][sl].astype(np.float64), want.astype(np.float64))
+                    back = _fmaf(h[4], (codes[v][sl].astype(np.float32) * step).astype(np.float32), Pa)
+                    assert np.array_equal(dec[v][sl], back)
+                    ulp = np.spacing(np.float32(np.abs(W5[v][sl]).max()))
+                    assert np.abs(dec[v][sl] - W5[v][sl]).max() <= h[4] / 65534.0 * 1.0001 + 4 * ulp
+    # 128 times finer than the BF16 codes at the ends of the range: on these noisy blocks the
+    # largest decoding error drops by more than 30
+    decbf = orc.ckpt_decode(g, qbf, hdrbf).reshape(W5.shape)
+    assert np.abs(decbf - W5).max() > 30 * np.abs(dec - W5).max()
