@@ -243,7 +243,7 @@ class LambdaSweep:
     def __init__(self, g, traj, lams, obj=None, weights=None, s=None, energy=False, device="cuda"):
         from . import CKPT_NATIVE, Grid
         self.g, self.traj = g, traj
-        self.bf16 = g.ckpt_format != CKPT_NATIVE
+        self.records = g.ckpt_format != CKPT_NATIVE
         self.gn = Grid.make(tuple(g.n), tuple(g.L), g.mu, g.dt, g.gamma, g.prandtl, g.bc_x, g.precision, 0,
                             tuple(g.w_ref), tuple(g.nu_weight), g.time_scheme, g.flux, g.roe_delta)
         self.lams = [float(x) for x in lams]
@@ -263,7 +263,7 @@ class LambdaSweep:
         self.use_obj = obj is not None and obj.kind != 0 and weights is not None
 
     def _state(self, n):
-        if not self.bf16:
+        if not self.records:
             return self.traj.slot(n)
         from . import ckpt_decode
         ckpt_decode(self.g, self.traj.slot(n), self.dec)

@@ -137,8 +137,8 @@ class HostTrajectory:
         if slots < 2:
             raise ValueError("at least two device slots")
         self.g, self.nsteps = g, nsteps
-        self.bf16 = g.ckpt_format != CKPT_NATIVE
-        if self.bf16:
+        self.records = g.ckpt_format != CKPT_NATIVE
+        if self.records:
             self.rec_len, dt = ckpt_bytes(g), torch.uint8
         else:
             self.rec_len, dt = 5 * g.ncells, g.dtype
@@ -208,7 +208,7 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
     cur = w0.clone()
     nxt = torch.empty_like(w0)
     take(0)
-    if traj.bf16:
+    if traj.records:
         ckpt_encode(g, cur, traj.buffer(0), ws)
     else:
         traj.buffer(0).copy_(cur)
@@ -218,14 +218,14 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
     for n in range(nsteps):
         take(n + 1)
         wgt = float(weights[n + 1]) if use_obj else 0.0
-        if traj.bf16:
+        if traj.records:
             step_obj(g, cur, s, nxt, ws, obj, wgt, J, ckpt_out=traj.buffer(n + 1))
         else:
             # the step reads w_n from its buffer and writes w_{n+1} into the next one
             step_obj(g, cur, s, traj.buffer(n + 1), ws, obj, wgt, J)
             nxt = traj.buffer(n + 1)
         send(n + 1)
-        if traj.bf16:
+        if traj.records:
             cur, nxt = nxt, cur
         else:
             cur = nxt
@@ -250,7 +250,7 @@ def backward(g, traj, s, obj=None, weights=None, lam=0.0, ws=None, grad_s=None):
     b = torch.empty_like(a)
     grad_s = torch.zeros(N5, dtype=g.dtype, device=dev) if grad_s is None else grad_s
     use_obj = obj is not None and obj.kind != OBJ_NONE and weights is not None
-    dec = torch.empty(N5, dtype=g.dtype, device=dev) if traj.bf16 else None
+    dec = torch.empty(N5, dtype=g.dtype, device=dev) if traj.records else None
     free = [None] * K   # last kernel reading each ring slot finished
     ready = {}          # stored state n has arrived in its ring slot (None: it was there already)
     held = list(traj.in_ring)
@@ -283,7 +283,7 @@ def backward(g, traj, s, obj=None, weights=None, lam=0.0, ws=None, grad_s=None):
             free[n % K] = main.record_event()
 
     def full(rec):
-        if not traj.bf16:
+        if not traj.records:
             return rec
         ckpt_decode(g, rec, dec)
         return dec

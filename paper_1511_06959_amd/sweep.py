@@ -2,7 +2,7 @@
 
 The paper stores periodic primal snapshots and recomputes in between ("Implementation",
 checkpointing).  With 288 GB of HBM the whole trajectory of a moderate window fits, so the plain
-schedule keeps every state (natively or as BF16 records) on the device and the reverse sweep
+schedule keeps every state (natively or as 16-bit records) on the device and the reverse sweep
 recomputes only the three inner RK4 stage states of each step, inside ``adjoint_step``
 (``Trajectory``, ``forward``, ``backward``).  Longer windows keep snapshots: ``SegmentSweep``
 every seg steps, re-advancing one segment at a time with its stage states kept, and
@@ -29,7 +29,7 @@ def step_obj(g, w, s, out, ws, obj, weight, J, ckpt_out=None, stages_out=None):
 
 
 class Trajectory:
-    """States w_0..w_N of one window, kept in HBM as full-precision states or BF16 records;
+    """States w_0..w_N of one window, kept in HBM as full-precision states or 16-bit records;
     with ``stages=True`` also the RK4 stage states W2, W3, W4 of every step (native states),
     so that the reverse sweep needs no recomputation (4x the memory of the states)."""
 
@@ -39,7 +39,7 @@ class Trajectory:
         N5 = 5 * g.ncells
         if g.ckpt_format != CKPT_NATIVE:
             if stages:
-                raise ValueError("stage states are stored natively, not as BF16 records")
+                raise ValueError("stage states are stored natively, not as 16-bit records")
             self.rec_bytes = ckpt_bytes(g)
             self.store = torch.empty((nsteps + 1, self.rec_bytes), dtype=torch.uint8, device=device)
         else:
@@ -61,10 +61,10 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
     ws = workspace(g) if ws is None else ws
     traj = Trajectory(g, nsteps, w0.device) if traj is None else traj
     J = torch.zeros(1, dtype=torch.float64, device=w0.device) if J is None else J
-    bf16 = g.ckpt_format != CKPT_NATIVE
+    records = g.ckpt_format != CKPT_NATIVE
     cur = w0.clone()
     nxt = torch.empty_like(w0)
-    if bf16:
+    if records:
         from . import ckpt_encode
         ckpt_encode(g, cur, traj.slot(0), ws)
     else:
@@ -74,13 +74,13 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
         objective_and_grad(g, obj, cur, ws, weight=float(weights[0]), J_accum=J)
     for n in range(nsteps):
         wgt = float(weights[n + 1]) if use_obj else 0.0
-        if bf16:
+        if records:
             step_obj(g, cur, s, nxt, ws, obj, wgt, J, ckpt_out=traj.slot(n + 1))
         else:
             step_obj(g, cur, s, traj.slot(n + 1), ws, obj, wgt, J,
                      stages_out=traj.stage_slot(n) if traj.stages is not None else None)
             nxt = traj.slot(n + 1)
-        if bf16:
+        if records:
             cur, nxt = nxt, cur
         else:
             cur = nxt
@@ -98,13 +98,13 @@ def backward(g, traj, s, obj=None, weights=None, lam=0.0, ws=None, grad_s=None, 
     b = torch.empty_like(a)
     grad_s = torch.zeros(N5, dtype=g.dtype, device=dev) if grad_s is None else grad_s
     use_obj = obj is not None and obj.kind != OBJ_NONE and weights is not None
-    bf16 = g.ckpt_format != CKPT_NATIVE
+    records = g.ckpt_format != CKPT_NATIVE
     dec = None
-    if bf16 or energy:
+    if records or energy:
         dec = torch.empty(N5, dtype=g.dtype, device=dev)
 
     def state(n):
-        if not bf16:
+        if not records:
             return traj.slot(n)
         from . import ckpt_decode
         ckpt_decode(g, traj.slot(n), dec)
@@ -188,14 +188,15 @@ class RevolveSweep:
     ``forward(w0)`` runs the primal once over the window, accumulating J on every state and
     storing the snapshots the reverse schedule starts from; ``backward(scale)`` replays the rest
     of the schedule: recomputation from snapshots and reverse steps, with objective weights
-    multiplied by ``scale``.  With ``g.ckpt_format != CKPT_NATIVE`` the slots hold records (BF16 or fixed-point codes); the
-    working state is always full precision.  Slots = nsteps + 1 reproduces the store-all sweep.
+    multiplied by ``scale``.  With ``g.ckpt_format != CKPT_NATIVE`` the slots hold 16-bit records
+    (BF16 or fixed-point codes); the working state is always full precision.  Slots = nsteps + 1
+    reproduces the store-all sweep.
     """
 
     def __init__(self, g, nsteps, slots, s=None, obj=None, weights=None, lam=0.0, ws=None, device="cuda"):
         from . import revolve
         self.g = g
-        self.bf16 = g.ckpt_format != CKPT_NATIVE
+        self.records = g.ckpt_format != CKPT_NATIVE
         self.gn = Grid.make(tuple(g.n), tuple(g.L), g.mu, g.dt, g.gamma, g.prandtl, g.bc_x, g.precision, 0,
                             tuple(g.w_ref), tuple(g.nu_weight), g.time_scheme, g.flux, g.roe_delta,
                             (tuple(g.w_far[0:5]), tuple(g.w_far[5:10])))
@@ -205,7 +206,7 @@ class RevolveSweep:
         self.acts = revolve.schedule(nsteps, self.slots)
         self.first_rev = next(i for i, a in enumerate(self.acts) if a[0] == "reverse")
         N5 = 5 * g.ncells
-        if self.bf16:
+        if self.records:
             self.pool = torch.empty((self.slots, ckpt_bytes(g)), dtype=torch.uint8, device=device)
         else:
             self.pool = torch.empty((self.slots, N5), dtype=g.dtype, device=device)
@@ -222,7 +223,7 @@ class RevolveSweep:
     def _store(self, n, state):
         k = self.free.pop()
         self.where[n] = k
-        if self.bf16:
+        if self.records:
             from . import ckpt_encode
             ckpt_encode(self.g, state, self.pool[k], self.ws)
         else:
@@ -231,7 +232,7 @@ class RevolveSweep:
     def _load(self, n):
         """Working state := stored state n."""
         k = self.where[n]
-        if self.bf16:
+        if self.records:
             from . import ckpt_decode
             ckpt_decode(self.g, self.pool[k], self.cur)
         else:
@@ -301,7 +302,7 @@ class RevolveSweep:
                 if self.cur_step == n:
                     adjoint_step(self.gn, self.cur, self.s, a, b, self.ws, lam=self.lam, obj=o, c_n=c_n, grad_s=grad_s)
                 else:
-                    gg = self.g if self.bf16 else self.gn
+                    gg = self.g if self.records else self.gn
                     adjoint_step(gg, self.pool[self.where[n]], self.s, a, b, self.ws, lam=self.lam, obj=o, c_n=c_n,
                                  grad_s=grad_s)
                 a, b = b, a
@@ -326,7 +327,7 @@ class SegmentSweep:
 
     def __init__(self, g, nsteps, seg, s=None, obj=None, weights=None, lam=0.0, ws=None, device="cuda"):
         self.g = g
-        self.bf16 = g.ckpt_format != CKPT_NATIVE
+        self.records = g.ckpt_format != CKPT_NATIVE
         self.gn = Grid.make(tuple(g.n), tuple(g.L), g.mu, g.dt, g.gamma, g.prandtl, g.bc_x, g.precision, 0,
                             tuple(g.w_ref), tuple(g.nu_weight), g.time_scheme, g.flux, g.roe_delta,
                             (tuple(g.w_far[0:5]), tuple(g.w_far[5:10])))
@@ -335,7 +336,7 @@ class SegmentSweep:
         self.s, self.obj, self.weights, self.lam = s, obj, weights, lam
         self.ws = workspace(g, device) if ws is None else ws
         N5 = 5 * g.ncells
-        if self.bf16:
+        if self.records:
             self.snaps = torch.empty((self.nsnap, ckpt_bytes(g)), dtype=torch.uint8, device=device)
         else:
             self.snaps = torch.empty((self.nsnap, N5), dtype=g.dtype, device=device)
@@ -346,14 +347,14 @@ class SegmentSweep:
         self.use_obj = obj is not None and obj.kind != OBJ_NONE and weights is not None
 
     def _store(self, k, state):
-        if self.bf16:
+        if self.records:
             from . import ckpt_encode
             ckpt_encode(self.g, state, self.snaps[k], self.ws)
         else:
             self.snaps[k].copy_(state)
 
     def _load(self, k, dst):
-        if self.bf16:
+        if self.records:
             from . import ckpt_decode
             ckpt_decode(self.g, self.snaps[k], dst)
         else:
