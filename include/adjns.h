@@ -161,14 +161,16 @@ int adj_primal_step(const adj_grid* grid, const void* w_n, const void* s, void* 
                     void* ws, size_t ws_bytes, void* stream);
 
 /* adj_primal_step (or adj_primal_step_stages when stages_out is non-NULL) that also accumulates the
- * objective of the new state: J_accum (device double) += weight * j(w_np1)  [Eqs. (1)-(3); the
- * time-averaged objective is the sum of such terms over the steps of a window].  For the
- * mean-pressure objective on RK4, split-flux grids without characteristic boundaries the pressure
- * sums ride in the final stage kernel (per-tile partials in the workspace, then a fixed-order fold);
- * otherwise the objective kernel runs after the step.  obj NULL, kind NONE or weight 0: plain step. */
+ * objective of its input and of its new state: J_accum (device double) += weight_in * j(w_n) +
+ * weight * j(w_np1)  [Eqs. (1)-(3); the time-averaged objective is the sum of such terms over the
+ * steps of a window].  Where a stage kernel already stages the state, the objective rides in it
+ * (per-tile partials in the workspace, then a fixed-order fold): the mean pressure of w_np1 in the
+ * final stage (RK4, split flux, no characteristic boundaries), the dissipation of w_n in stage 1
+ * (periodic or slip-wall x boundaries); otherwise the objective kernel runs before or after the
+ * step.  obj NULL, kind NONE or both weights 0: plain step. */
 int adj_primal_step_obj(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out,
-                        void* stages_out, const adj_objective* obj, double weight, double* J_accum, void* ws,
-                        size_t ws_bytes, void* stream);
+                        void* stages_out, const adj_objective* obj, double weight_in, double weight, double* J_accum,
+                        void* ws, size_t ws_bytes, void* stream);
 
 /* One reverse step of the discrete adjoint with artificial viscosity (below for RK4; an
  * ADJ_SSPRK3 grid reverses its three Shu-Osher stages the same way, see time_scheme)  [Unsteady adjoint:

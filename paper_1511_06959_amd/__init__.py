@@ -158,7 +158,7 @@ def lib():
         "adj_workspace_bytes": ([gp], sz),
         "adj_ckpt_bytes": ([gp], sz),
         "adj_primal_step": ([gp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
-        "adj_primal_step_obj": ([gp, vp, vp, vp, vp, vp, op, dbl, vp, vp, sz, vp], ctypes.c_int),
+        "adj_primal_step_obj": ([gp, vp, vp, vp, vp, vp, op, dbl, dbl, vp, vp, sz, vp], ctypes.c_int),
         "adj_adjoint_step": ([gp, vp, vp, vp, dbl, op, dbl, vp, vp, vp, sz, vp], ctypes.c_int),
         "adj_adjoint_step_noalloc": ([gp, vp, vp, vp, dbl, op, dbl, vp, vp, vp], ctypes.c_int),
         "adj_primal_step_stages": ([gp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
@@ -261,12 +261,13 @@ def primal_step(g, w_n, s, w_np1, ws, ckpt_out=None):
                                  _ptr(ckpt_out, torch.uint8), wp, wb, _stream()))
 
 
-def primal_step_obj(g, w_n, s, w_np1, ws, obj, weight, J_accum, ckpt_out=None, stages_out=None):
-    """primal_step (primal_step_stages with stages_out) that also adds weight * j(w_np1) to J_accum."""
+def primal_step_obj(g, w_n, s, w_np1, ws, obj, weight, J_accum, ckpt_out=None, stages_out=None, weight_in=0.0):
+    """primal_step (primal_step_stages with stages_out) that also adds weight_in * j(w_n) +
+    weight * j(w_np1) to J_accum."""
     wp, wb = _ws(ws)
     _check(lib().adj_primal_step_obj(ctypes.byref(g), _state(g, w_n), _state(g, s), _state(g, w_np1),
                                      _ptr(ckpt_out, torch.uint8), None if stages_out is None else _stages(g, stages_out),
-                                     ctypes.byref(obj) if obj is not None else None, float(weight),
+                                     ctypes.byref(obj) if obj is not None else None, float(weight_in), float(weight),
                                      _ptr(J_accum, torch.float64), wp, wb, _stream()))
 
 

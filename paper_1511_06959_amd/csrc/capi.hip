@@ -220,10 +220,12 @@ int adjoint_stage(const adj_grid* g, int mode, const Consts<T>& c, const T* W, c
   return ADJ_OK;
 }
 
-// jpart: per-tile pressure sums of the new state from the final RK4 stage (see fuse_meanp), or NULL
+// jpart: per-tile pressure sums of the new state from the final RK4 stage (see fuse_meanp), or NULL;
+// jin: per-tile dissipation sums of w_n from stage 1 (see fuse_dissipation_in), folded into
+// *J_in with factor jin_scale right after that stage, or NULL
 template <typename T>
 int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, T* stages, void* ws, hipStream_t st,
-                double* jpart = nullptr) {
+                double* jpart = nullptr, double* jin = nullptr, double* J_in = nullptr, double jin_scale = 0.0) {
   const Consts<T> c = consts<T>(g);
   const WsLayout L = layout(g);
   const long long S5 = 5 * c.N;
@@ -236,7 +238,11 @@ int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, 
   if (g->time_scheme == ADJ_SSPRK3) {
     // u1 = w + dt R(w) (in W2), u2 = 3/4 w + 1/4 u1 + dt/4 R(u1) (in W3), w_next = 1/3 w + 2/3 u2 +
     // 2 dt/3 R(u2); the affine weights sum to one, so stored deviations w - w_ref combine alike
-    if ((r = primal_stage<T>(g, STAGE_LIN, c, wn, wn, s, nullptr, nullptr, c.dt, W2, st, "primal stage 1"))) return r;
+    if ((r = primal_stage<T>(g, STAGE_LIN, c, wn, wn, s, nullptr, nullptr, c.dt, W2, st, "primal stage 1", T(0), T(0),
+                             jin)))
+      return r;
+    if (jin && (e = launch_fold(jin, primal_tiles<T>(c), J_in, jin_scale, 1.0, st)))
+      return hip_fail(e, "dissipation of the step's state");
     if ((r = primal_stage<T>(g, STAGE_AFF, c, W2, wn, s, nullptr, nullptr, c.dt * T(0.25), W3, st, "primal stage 2",
                              T(0.75), T(0.25))))
       return r;
@@ -244,7 +250,11 @@ int primal_step(const adj_grid* g, const T* wn, const T* s, T* out, void* ckpt, 
                              "primal stage 3", T(1.0 / 3.0), T(2.0 / 3.0))))
       return r;
   } else {
-    if ((r = primal_stage<T>(g, STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st, "primal stage 1"))) return r;
+    if ((r = primal_stage<T>(g, STAGE_LIN, c, wn, wn, s, nullptr, nullptr, h, W2, st, "primal stage 1", T(0), T(0),
+                             jin)))
+      return r;
+    if (jin && (e = launch_fold(jin, primal_tiles<T>(c), J_in, jin_scale, 1.0, st)))
+      return hip_fail(e, "dissipation of the step's state");
     if ((r = primal_stage<T>(g, STAGE_LIN, c, W2, wn, s, nullptr, nullptr, h, W3, st, "primal stage 2"))) return r;
     if ((r = primal_stage<T>(g, STAGE_LIN, c, W3, wn, s, nullptr, nullptr, c.dt, W4, st, "primal stage 3"))) return r;
     if ((r = primal_stage<T>(g, STAGE_FIN, c, W4, wn, s, W2, W3, T(0), out, st, "primal stage 4", T(0), T(0), jpart)))
@@ -427,34 +437,50 @@ static bool fuse_meanp(const adj_grid* g, const adj_objective* o) {
          g->bc_x != ADJ_BC_CHARACTERISTIC;
 }
 
+// The dissipation of the step's own state w_n rides in stage 1, which stages w_n with one halo
+// cell: periodic or slip-wall x boundaries (whose ghost cells the objective kernel mirrors alike).
+static bool fuse_dissipation_in(const adj_grid* g, const adj_objective* o) {
+  return o->kind == ADJ_OBJ_KE_DISSIPATION && g->bc_x != ADJ_BC_CHARACTERISTIC;
+}
+
 template <typename T>
 static int primal_obj(const adj_grid* grid, const T* w_n, const T* s, T* w_np1, void* ckpt, T* stages,
-                      const adj_objective* obj, double weight, double* J_accum, void* ws, hipStream_t st) {
+                      const adj_objective* obj, double weight_in, double weight, double* J_accum, void* ws,
+                      hipStream_t st) {
   const Consts<T> c = consts<T>(grid);
   const WsLayout L = layout(grid);
   double* part = (double*)at(ws, L.partials);
-  const bool fuse = fuse_meanp(grid, obj);
-  int r;
-  if ((r = primal_step<T>(grid, w_n, s, w_np1, ckpt, stages, ws, st, fuse ? part : nullptr))) return r;
+  double* scr = (double*)at(ws, L.scratch);
+  const bool fuse_in = weight_in != 0.0 && fuse_dissipation_in(grid, obj);
+  const bool fuse_out = weight != 0.0 && fuse_meanp(grid, obj);
   hipError_t e;
-  if (fuse)
+  int r;
+  if (weight_in != 0.0 && !fuse_in &&
+      (e = launch_objective<T>(c, obj->kind, obj->plane_i, obj->pt_ref, w_n, weight_in, J_accum, nullptr, part, scr,
+                               st)))
+    return hip_fail(e, "objective of the step's state");
+  // the stage-1 partials are folded before the final stage writes its own into the same region
+  if ((r = primal_step<T>(grid, w_n, s, w_np1, ckpt, stages, ws, st, fuse_out ? part : nullptr,
+                          fuse_in ? part : nullptr, J_accum, weight_in / (double)c.N)))
+    return r;
+  if (weight == 0.0) return ADJ_OK;
+  if (fuse_out)
     e = launch_fold(part, primal_tiles<T>(c), J_accum, weight / (double)c.N, 1.0, st);
   else
-    e = launch_objective<T>(c, obj->kind, obj->plane_i, obj->pt_ref, w_np1, weight, J_accum, nullptr, part,
-                            (double*)at(ws, L.scratch), st);
+    e = launch_objective<T>(c, obj->kind, obj->plane_i, obj->pt_ref, w_np1, weight, J_accum, nullptr, part, scr, st);
   return e ? hip_fail(e, "objective of the new state") : ADJ_OK;
 }
 }  // extern "C++"
 
 int adj_primal_step_obj(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* ckpt_out,
-                        void* stages_out, const adj_objective* obj, double weight, double* J_accum, void* ws,
-                        size_t ws_bytes, void* stream) {
+                        void* stages_out, const adj_objective* obj, double weight_in, double weight, double* J_accum,
+                        void* ws, size_t ws_bytes, void* stream) {
   int r;
   if ((r = check_grid(grid, true))) return r;
   if ((r = check_ws(grid, ws, ws_bytes))) return r;
   if ((r = check_obj(grid, obj))) return r;
-  if (!std::isfinite(weight)) return fail(ADJ_EINVAL, "weight must be finite");
-  const bool active = obj && obj->kind != ADJ_OBJ_NONE && weight != 0.0;
+  if (!std::isfinite(weight) || !std::isfinite(weight_in)) return fail(ADJ_EINVAL, "weights must be finite");
+  const bool active = obj && obj->kind != ADJ_OBJ_NONE && (weight != 0.0 || weight_in != 0.0);
   if (active && !J_accum) return fail(ADJ_EINVAL, "J_accum must be non-NULL");
   if (!w_n || !w_np1) return fail(ADJ_EINVAL, "w_n and w_np1 must be non-NULL");
   if (w_n == w_np1) return fail(ADJ_EINVAL, "w_np1 must not alias w_n");
@@ -464,9 +490,9 @@ int adj_primal_step_obj(const adj_grid* grid, const void* w_n, const void* s, vo
   hipStream_t st = (hipStream_t)stream;
   if (grid->precision == ADJ_F64)
     return primal_obj<double>(grid, (const double*)w_n, (const double*)s, (double*)w_np1, nullptr, (double*)stages_out,
-                              obj, weight, J_accum, ws, st);
+                              obj, weight_in, weight, J_accum, ws, st);
   return primal_obj<float>(grid, (const float*)w_n, (const float*)s, (float*)w_np1, ckpt_out, (float*)stages_out, obj,
-                           weight, J_accum, ws, st);
+                           weight_in, weight, J_accum, ws, st);
 }
 
 int adj_primal_step_stages(const adj_grid* grid, const void* w_n, const void* s, void* w_np1, void* stages_out,

@@ -10,8 +10,10 @@ enum { STAGE_VJP = 0 };                                  // adjoint stage modes 
 
 // STAGE_AFF: out = ca * wn + cb * W + cR * R(W; s)  (the SSP-RK3 stages)
 // conv = 0: R without the split-form convective flux (the Roe option adds its own afterwards)
-// jpart (STAGE_FIN, may be NULL): receives one FP64 partial per tile (primal_tiles of them), the sum of
-// the pressures of the stage output over the tile's cells (the mean-pressure objective of the step)
+// jpart (STAGE_FIN or STAGE_LIN, may be NULL): receives one FP64 partial per tile (primal_tiles of
+// them): for STAGE_FIN the sum of the pressures of the stage output over the tile's cells (the
+// mean-pressure objective of the step's new state), for STAGE_LIN the sum of the viscous dissipation
+// of the staged state W (in stage 1, W = w_n: the dissipation objective of the step's own state)
 template <typename T>
 hipError_t launch_primal_stage(int mode, const Consts<T>& c, const T* W, const T* wn, const T* s, const T* W2,
                                const T* W3, T cR, T* out, hipStream_t st, T ca = T(0), T cb = T(0), int conv = 1,

@@ -198,10 +198,31 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
     }
   }
   __syncthreads();
-  double pv = 0.0;  // the new state's pressure at the cell (final stage with jpart)
+  double pv = 0.0;  // the new state's pressure (final stage) or w_n's dissipation (stage 1) at the cell
   if (active) {
     const int st[3] = {1, Bx::SY, Bx::SZ};
     const int p = (tz + 1) * Bx::SZ + (ty + 1) * Bx::SY + (tx + 1);
+    if (MODE == STAGE_LIN && jpart) {
+      // the viscous dissipation sigma : grad u of the staged state at the cell (stage 1 of a step,
+      // W = w_n): central velocity gradients from the LDS planes, which hold u/2, so that a
+      // difference times 1/dx is the central derivative
+      T G[3][3];
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) G[l][k] = (sm[P_U1 + k][p + st[l]] - sm[P_U1 + k][p - st[l]]) * c.idx[l];
+      const T div = G[0][0] + G[1][1] + G[2][2];
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          T sg = c.mu * (G[l][k] + G[k][l]);
+          if (l == k) sg -= (T(2) / T(3)) * c.mu * div;
+          acc += sg * G[l][k];
+        }
+      pv = (double)acc;
+    }
     T R[5] = {sv[0], sv[1], sv[2], sv[3], sv[4]};
     residual_dir<T, NB, 0, CONV>(sm, st, p, c, R);
     __builtin_amdgcn_sched_barrier(0);
@@ -226,9 +247,10 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
       if (MODE == STAGE_FIN && jpart) pv = q64_of(c, o[0], o[1], o[2], o[3], o[4], 0, (double)c.gamma).p;
     }
   }
-  if (MODE == STAGE_FIN && jpart) {
-    // the tile's sum of the new state's pressures (the mean-pressure objective of the step's
-    // output), in a fixed order: butterfly within each wavefront, then the wavefronts in order
+  if ((MODE == STAGE_FIN || MODE == STAGE_LIN) && jpart) {
+    // the tile's sum of the new state's pressures (final stage: the mean-pressure objective of
+    // the step's output) or of the input state's dissipation (stage 1), in a fixed order:
+    // butterfly within each wavefront, then the wavefronts in order
     __shared__ double red[NT / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) pv += __shfl_xor(pv, o, 64);
@@ -809,7 +831,7 @@ static void primal_launch(ProfScope& ps, int mode, const Consts<T>& c, const T* 
                  cb, nj);
   else if (mode == STAGE_LIN)
     timed_launch(ps, k_primal_stage<T, STAGE_LIN, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
-                 cb, nj);
+                 cb, jpart);
   else if (mode == STAGE_AFF)
     timed_launch(ps, k_primal_stage<T, STAGE_AFF, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
                  cb, nj);
@@ -819,7 +841,7 @@ static void primal_launch(ProfScope& ps, int mode, const Consts<T>& c, const T* 
 }
 
 // Work-groups (tiles) of a primal-stage launch in the current tile shape: the number of per-tile
-// partial sums a final stage with jpart writes.
+// partial sums a final stage or a stage 1 (STAGE_LIN) with jpart writes.
 template <typename T>
 int primal_tiles(const Consts<T>& c) {
   int n = 0;

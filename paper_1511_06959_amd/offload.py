@@ -22,7 +22,7 @@ import torch
 
 from . import (CKPT_NATIVE, OBJ_NONE, adjoint_step, ckpt_bytes, ckpt_decode, ckpt_encode, objective_and_grad,
                workspace)
-from .sweep import step_obj
+from .sweep import step_obj, step_weights
 
 
 class _PinnedStore:
@@ -213,16 +213,16 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
     else:
         traj.buffer(0).copy_(cur)
     send(0)
-    if use_obj and weights[0] != 0.0:
+    if use_obj and nsteps == 0 and weights[0] != 0.0:
         objective_and_grad(g, obj, cur, ws, weight=float(weights[0]), J_accum=J)
     for n in range(nsteps):
         take(n + 1)
-        wgt = float(weights[n + 1]) if use_obj else 0.0
+        win, wgt = step_weights(obj if use_obj else None, weights, n, nsteps)
         if traj.records:
-            step_obj(g, cur, s, nxt, ws, obj, wgt, J, ckpt_out=traj.buffer(n + 1))
+            step_obj(g, cur, s, nxt, ws, obj, win, wgt, J, ckpt_out=traj.buffer(n + 1))
         else:
             # the step reads w_n from its buffer and writes w_{n+1} into the next one
-            step_obj(g, cur, s, traj.buffer(n + 1), ws, obj, wgt, J)
+            step_obj(g, cur, s, traj.buffer(n + 1), ws, obj, win, wgt, J)
             nxt = traj.buffer(n + 1)
         send(n + 1)
         if traj.records:

@@ -13,15 +13,30 @@ Only scheduling happens here; all arithmetic runs in the library's kernels.
 """
 import torch
 
-from . import (CKPT_NATIVE, OBJ_NONE, Grid, Objective, adjoint_step, adjoint_step_stages, ckpt_bytes, energy_vhat,
+from . import (CKPT_NATIVE, OBJ_KE_DISSIPATION, OBJ_NONE, Grid, Objective, adjoint_step, adjoint_step_stages, ckpt_bytes, energy_vhat,
                objective_and_grad, primal_step, primal_step_obj, primal_step_stages, workspace)
 
 
-def step_obj(g, w, s, out, ws, obj, weight, J, ckpt_out=None, stages_out=None):
-    """One primal step w -> out that adds weight * j(out) to J when an objective and a non-zero
-    weight are given (the library fuses the mean pressure into the step), else a plain step."""
-    if obj is not None and obj.kind != OBJ_NONE and weight != 0.0 and J is not None:
-        primal_step_obj(g, w, s, out, ws, obj, weight, J, ckpt_out=ckpt_out, stages_out=stages_out)
+def step_weights(obj, weights, n, nsteps):
+    """(weight_in, weight) of step n (w_n -> w_{n+1}) such that the steps of an nsteps window
+    together add J = sum_m c_m j(w_m): the dissipation, which the library evaluates inside a
+    step's first stage for the step's own state, is taken as each step's input (and the last
+    state as the last step's output); every other objective as each step's output (and w_0 as the
+    first step's input).  (0, 0) without an objective."""
+    if obj is None or obj.kind == OBJ_NONE or weights is None:
+        return 0.0, 0.0
+    if obj.kind == OBJ_KE_DISSIPATION:
+        return float(weights[n]), (float(weights[nsteps]) if n == nsteps - 1 else 0.0)
+    return (float(weights[0]) if n == 0 else 0.0), float(weights[n + 1])
+
+
+def step_obj(g, w, s, out, ws, obj, weight_in, weight, J, ckpt_out=None, stages_out=None):
+    """One primal step w -> out that adds weight_in * j(w) + weight * j(out) to J when an objective
+    and a non-zero weight are given (the library fuses what it can into the step's stages), else a
+    plain step."""
+    if obj is not None and obj.kind != OBJ_NONE and (weight != 0.0 or weight_in != 0.0) and J is not None:
+        primal_step_obj(g, w, s, out, ws, obj, weight, J, ckpt_out=ckpt_out, stages_out=stages_out,
+                        weight_in=weight_in)
     elif stages_out is not None:
         primal_step_stages(g, w, s, out, stages_out, ws)
     else:
@@ -70,14 +85,14 @@ def forward(g, w0, s, nsteps, obj=None, weights=None, ws=None, traj=None, J=None
     else:
         traj.slot(0).copy_(cur)
     use_obj = obj is not None and obj.kind != OBJ_NONE and weights is not None
-    if use_obj and weights[0] != 0.0:
+    if use_obj and nsteps == 0 and weights[0] != 0.0:
         objective_and_grad(g, obj, cur, ws, weight=float(weights[0]), J_accum=J)
     for n in range(nsteps):
-        wgt = float(weights[n + 1]) if use_obj else 0.0
+        win, wgt = step_weights(obj if use_obj else None, weights, n, nsteps)
         if records:
-            step_obj(g, cur, s, nxt, ws, obj, wgt, J, ckpt_out=traj.slot(n + 1))
+            step_obj(g, cur, s, nxt, ws, obj, win, wgt, J, ckpt_out=traj.slot(n + 1))
         else:
-            step_obj(g, cur, s, traj.slot(n + 1), ws, obj, wgt, J,
+            step_obj(g, cur, s, traj.slot(n + 1), ws, obj, win, wgt, J,
                      stages_out=traj.stage_slot(n) if traj.stages is not None else None)
             nxt = traj.slot(n + 1)
         if records:
@@ -243,8 +258,9 @@ class RevolveSweep:
         if self.cur_step != i:
             self._load(i)
         for n in range(i, j):
-            wgt = float(self.weights[n + 1]) if (J is not None and self.use_obj) else 0.0
-            step_obj(self.gn, self.cur, self.s, self.tmp, self.ws, self.obj, wgt, J)
+            win, wgt = step_weights(self.obj if (J is not None and self.use_obj) else None, self.weights, n,
+                                    self.nsteps)
+            step_obj(self.gn, self.cur, self.s, self.tmp, self.ws, self.obj, win, wgt, J)
             self.cur, self.tmp = self.tmp, self.cur
             self.advanced += 1
         self.cur_step = j
@@ -259,8 +275,6 @@ class RevolveSweep:
         self.cur_step = 0
         self.advanced = 0
         self._store(0, self.cur)
-        if self.use_obj and self.weights[0] != 0.0:
-            objective_and_grad(self.gn, self.obj, self.cur, self.ws, weight=float(self.weights[0]), J_accum=J)
         for act in self.acts[:self.first_rev]:
             if act[0] == "advance":
                 self._advance(act[1], act[2], J)
@@ -271,8 +285,8 @@ class RevolveSweep:
         # the working state is w_{N-1}; the final state w_N feeds J and the terminal adjoint
         if self.cur_step != self.nsteps - 1:
             self._advance(self.cur_step, self.nsteps - 1, J)
-        step_obj(self.gn, self.cur, self.s, self.wN, self.ws, self.obj,
-                 float(self.weights[self.nsteps]) if self.use_obj else 0.0, J)
+        win, wgt = step_weights(self.obj if self.use_obj else None, self.weights, self.nsteps - 1, self.nsteps)
+        step_obj(self.gn, self.cur, self.s, self.wN, self.ws, self.obj, win, wgt, J)
         self.advanced += 1
         return J
 
@@ -368,12 +382,10 @@ class SegmentSweep:
         cur.copy_(w0)
         self.advanced = 0
         self._store(0, cur)
-        if self.use_obj and self.weights[0] != 0.0:
-            objective_and_grad(self.gn, self.obj, cur, self.ws, weight=float(self.weights[0]), J_accum=J)
         for n in range(self.nsteps):
             out = self.wN if n + 1 == self.nsteps else nxt
-            step_obj(self.gn, cur, self.s, out, self.ws, self.obj, float(self.weights[n + 1]) if self.use_obj else 0.0,
-                     J)
+            win, wgt = step_weights(self.obj if self.use_obj else None, self.weights, n, self.nsteps)
+            step_obj(self.gn, cur, self.s, out, self.ws, self.obj, win, wgt, J)
             self.advanced += 1
             if (n + 1) % self.seg == 0 and n + 1 < self.nsteps:
                 self._store((n + 1) // self.seg, out)

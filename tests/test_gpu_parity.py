@@ -341,3 +341,22 @@ def test_primal_step_with_objective(orc, precision, kind, bc_x, scheme, flux):
         adj.primal_step_stages(g, wd, sd, plain, st1, ws)
         adj.primal_step_obj(g, wd, sd, out, ws, obj, 0.3, J2, stages_out=st2)
         assert torch.equal(st1, st2) and torch.equal(out, plain)
+    # the objective of the step's input as well (the dissipation rides in stage 1, the others run
+    # the objective kernel before the step): J += 0.7 j(w_n) + 0.3 j(w_np1)
+    J3 = torch.full((1,), 0.5, dtype=torch.float64, device="cuda")
+    adj.primal_step_obj(g, wd, sd, out, ws, obj, 0.3, J3, weight_in=0.7)
+    assert np.array_equal(host(out), host(plain))
+    J4 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    adj.objective_and_grad(g, obj, wd, ws, weight=1.0, J_accum=J4)
+    want = host(J1)[0] + 0.7 * host(J4)[0]
+    # the fused dissipation sums its cells in other tiles (and a cell's terms may contract
+    # differently), so it agrees with the objective kernel to the rounding of its precision
+    tol_in = 1e-14 if (kind != W.OBJ_KE_DISSIPATION or precision == adj.F64) else 1e-6
+    assert abs(host(J3)[0] - want) <= tol_in * abs(want)
+    jin = orc.objective(og, orc.make_obj(kind, 20, 1.1), g.from_stored(g.to_stored(w)), grad=False)
+    assert abs(host(J3)[0] - (0.5 + 0.3 * jr + 0.7 * jin)) <= tol * abs(0.5 + 0.3 * jr + 0.7 * jin)
+    # the input's objective alone, with the new state's weight zero
+    J5 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    adj.primal_step_obj(g, wd, sd, out, ws, obj, 0.0, J5, weight_in=0.7)
+    assert np.array_equal(host(out), host(plain))
+    assert abs(host(J5)[0] - 0.7 * host(J4)[0]) <= tol_in * abs(0.7 * host(J4)[0])
