@@ -138,7 +138,8 @@ def kernel_hash(family="stage"):
 
 def _tile_report(res, g, lnu):
     """Autotuner result as bench fields: the selected tile, the tile the launches of this
-    workload really use (lnu: a lambda term is applied) and the timed candidates (us)."""
+    workload really use (lnu: a lambda term is applied) and the timed candidates (us; for the
+    primal stage, per stage of a whole RK step)."""
     import paper_1511_06959_amd as adj
 
     name = lambda t: "x".join(map(str, adj.TILES[t]))

@@ -1,8 +1,10 @@
 """Tile-shape autotuner for the two stencil kernel classes.
 
 For a grid and precision, every compiled tile shape of the reverse-stage kernel (timed through
-``vjp``) and of the primal-stage kernel (timed through ``residual``) is run on the device with
-HIP events, and the fastest is installed with ``set_tile``.  Results are cached in a JSON file
+``vjp``) and of the primal-stage kernel (timed through whole RK steps, ``primal_step``: the
+residual alone can rank the tiles otherwise than the stage launches a step makes, whose stage
+updates and final combination change the kernel's registers and stores) is run on the device
+with HIP events, and the fastest is installed with ``set_tile``.  Results are cached in a JSON file
 keyed by library build, kernel class, precision, grid shape and boundary type, so a process pays
 for the search once per configuration.
 """
@@ -11,8 +13,8 @@ import os
 
 import torch
 
-from . import (F64, PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, TILES, get_tile, residual, set_tile, tile_launched,
-               vjp)
+from . import (F64, PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE, SSPRK3, TILES, get_tile, primal_step, set_tile,
+               tile_launched, vjp, workspace)
 
 CACHE = os.environ.get("ADJNS_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "adjns_tiles.json"))
 
@@ -75,13 +77,14 @@ def _time(fn, reps):
 
 def tune(g, reps=20, use_cache=True, verbose=False, rounds=3, margin=0.03):
     """Pick and install the fastest tile of both kernel classes for grid g; returns
-    {kernel_class: (tile_id, {tile_id: ms})}.  Every tile is timed in `rounds` interleaved rounds
+    {kernel_class: (tile_id, {tile_id: ms})} (primal class: ms per stage of an RK step).  Every tile is timed in `rounds` interleaved rounds
     (best round kept); the tile installed before tuning stays unless another is faster by more
     than `margin`, so that near-ties do not flip between runs."""
     db = _load() if use_cache else {}
     out = {}
     w, kh = _state(g, 0)
     buf = torch.empty_like(w)
+    ws = None
     for kclass in (PROF_ADJOINT_STAGE, PROF_PRIMAL_STAGE):
         key = _key(g, kclass)
         if use_cache and key in db:
@@ -98,7 +101,10 @@ def tune(g, reps=20, use_cache=True, verbose=False, rounds=3, margin=0.03):
                 if kclass == PROF_ADJOINT_STAGE:
                     ms = _time(lambda: vjp(g, w, kh, buf), reps)
                 else:
-                    ms = _time(lambda: residual(g, w, None, buf), reps)
+                    ws = workspace(g) if ws is None else ws
+                    # time per stage of an RK step (one stage-kernel launch each)
+                    nst = 3 if g.time_scheme == SSPRK3 else 4
+                    ms = _time(lambda: primal_step(g, w, None, buf, ws), max(1, reps // nst)) / nst
                 times[t] = min(times.get(t, ms), ms)
         best = min(times, key=times.get) if times else prev
         if prev in times and times[prev] <= (1.0 + margin) * times[best]:

@@ -106,12 +106,16 @@ __device__ __forceinline__ void residual_dir(const T (*sm)[NB], const int st[3],
 
 // MODE: RES  out = R(W; s)
 //       LIN  out = wn + cR * R(W; s)                           (RK4 stages 1-3)
+//       LIN_DISS  LIN that also sums the viscous dissipation of W over the tile into jpart (stage 1:
+//            W = w_n; a mode of its own, so that the other stage launches carry none of its work)
 //       AFF  out = ca wn + cb W + cR * R(W; s)                 (SSP-RK3 stages)
 //       FIN  out = (W2 + 2 W3 + W - wn)/3 + (dt/6) R(W; s)      (stage 4, W = W4;
 //            equals wn + dt/6 (k1 + 2 k2 + 2 k3 + k4) since k1 = 2(W2-wn)/dt, k2 = 2(W3-wn)/dt,
 //            k3 = (W4-wn)/dt)
 // CONV = 0 leaves out the split-form convective flux (the Roe option adds its own).
 // One work-group: the tile with origin (x0, y0, z0).
+constexpr int STAGE_LIN_DISS = 4;
+
 template <typename T, int MODE, int CONV, int TX, int TY, int TZ>
 __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x0, const int y0, const int z0,
                                                  const T* __restrict__ W, const T* __restrict__ wn,
@@ -182,7 +186,7 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
 #pragma unroll
       for (int v = 0; v < 5; ++v) sv[v] = s[v * N + gi];
     }
-    if (MODE == STAGE_LIN) {
+    if (MODE == STAGE_LIN || MODE == STAGE_LIN_DISS) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) base[v] = wn[v * N + gi];
     } else if (MODE == STAGE_AFF) {
@@ -202,7 +206,7 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
   if (active) {
     const int st[3] = {1, Bx::SY, Bx::SZ};
     const int p = (tz + 1) * Bx::SZ + (ty + 1) * Bx::SY + (tx + 1);
-    if (MODE == STAGE_LIN && jpart) {
+    if (MODE == STAGE_LIN_DISS) {
       // the viscous dissipation sigma : grad u of the staged state at the cell (stage 1 of a step,
       // W = w_n): central velocity gradients from the LDS planes, which hold u/2, so that a
       // difference times 1/dx is the central derivative
@@ -233,7 +237,7 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
     if (MODE == STAGE_RES) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) out[v * N + gi] = R[v];
-    } else if (MODE == STAGE_LIN || MODE == STAGE_AFF) {
+    } else if (MODE == STAGE_LIN || MODE == STAGE_LIN_DISS || MODE == STAGE_AFF) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) out[v * N + gi] = base[v] + cR * R[v];
     } else {
@@ -247,7 +251,7 @@ __device__ __forceinline__ void primal_tile_body(const Consts<T>& c, const int x
       if (MODE == STAGE_FIN && jpart) pv = q64_of(c, o[0], o[1], o[2], o[3], o[4], 0, (double)c.gamma).p;
     }
   }
-  if ((MODE == STAGE_FIN || MODE == STAGE_LIN) && jpart) {
+  if ((MODE == STAGE_FIN && jpart) || MODE == STAGE_LIN_DISS) {
     // the tile's sum of the new state's pressures (final stage: the mean-pressure objective of
     // the step's output) or of the input state's dissipation (stage 1), in a fixed order:
     // butterfly within each wavefront, then the wavefronts in order
@@ -829,9 +833,12 @@ static void primal_launch(ProfScope& ps, int mode, const Consts<T>& c, const T* 
   if (mode == STAGE_RES)
     timed_launch(ps, k_primal_stage<T, STAGE_RES, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
                  cb, nj);
+  else if (mode == STAGE_LIN && jpart)
+    timed_launch(ps, k_primal_stage<T, STAGE_LIN_DISS, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out,
+                 ca, cb, jpart);
   else if (mode == STAGE_LIN)
     timed_launch(ps, k_primal_stage<T, STAGE_LIN, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
-                 cb, jpart);
+                 cb, nj);
   else if (mode == STAGE_AFF)
     timed_launch(ps, k_primal_stage<T, STAGE_AFF, CONV, TX, TY, TZ>, grid, blk, st, c, W, wn, s, W2, W3, cR, out, ca,
                  cb, nj);

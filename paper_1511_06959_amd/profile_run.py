@@ -21,7 +21,9 @@
     python -m paper_1511_06959_amd.profile_run valu <dir> --cells N [--kernel k_adjoint_stage]
         vector-ALU instructions and FP32 operations per launch from one run with the SQ counters
         of VALU_COUNTERS
-    python -m paper_1511_06959_amd.profile_run trace <dir> --title T --command C
+    python -m paper_1511_06959_amd.profile_run stall <dir> --cells N [--kernel _stage]
+        issue, wait and LDS fractions per kernel from one run with the SQ counters of STALL_COUNTERS
+    python -m paper_1511_06959_amd.profile_run trace <dir> --title T --command C [--note PARAGRAPH ...]
         markdown table of a --kernel-trace --stats run
 
 Run the first two under rocprofv3, e.g.
@@ -283,8 +285,46 @@ def valu(outdir, cells, kernel, commands):
     print(f"fp32_ops_per_cell_launch_f32 = {flops / cells:.6g}")
 
 
-def trace_summary(outdir, title, command):
-    """Markdown table of a rocprofv3 --kernel-trace --stats run (*_kernel_stats.csv)."""
+STALL_COUNTERS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU",
+                  "SQ_INSTS_LDS", "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT")
+
+
+def stall(outdir, cells, kernel, commands):
+    """Averages per dispatch of STALL_COUNTERS for every kernel whose name holds `kernel`, and their
+    fractions of SQ_WAVE_CYCLES (the summed wave lifetimes, so the counters' common unit cancels):
+    VALU issue, waiting for any instruction, waiting for LDS; bank-conflict cycles per LDS
+    instruction."""
+    acc, disp = defaultdict(lambda: defaultdict(float)), defaultdict(set)
+    for f in glob.glob(os.path.join(outdir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                k = short_name(row.get("Kernel_Name", ""))
+                if kernel in k:
+                    acc[k][row["Counter_Name"]] += float(row["Counter_Value"])
+                    disp[k].add(row.get("Dispatch_Id"))
+    if not acc:
+        sys.exit(f"no {kernel} dispatches under {outdir}")
+    print(f"# stall and issue counters of the *{kernel}* kernels (rocprofv3 SQ counters, one run), {cells} cells")
+    for c in commands:
+        print(f"# command: {c}")
+    print("# averages per dispatch; the fractions are of SQ_WAVE_CYCLES (summed wave lifetimes), so the counters' "
+          "common unit")
+    print("# cancels; lds_conflict_per_lds_inst = SQ_LDS_BANK_CONFLICT cycles per LDS instruction")
+    print(f"# kernel_source_sha256 = {_src_hash(kernel)}")
+    for k in sorted(acc):
+        n = len(disp[k])
+        a = {c: v / n for c, v in acc[k].items()}
+        print(f"{k}: {n} dispatches, " + ", ".join(f"{c} {a[c]:.6g}" for c in sorted(a)))
+        wc = a.get("SQ_WAVE_CYCLES", 0.0) or float("nan")
+        print(f"  valu_active_frac = {a.get('SQ_ACTIVE_INST_VALU', 0.0) / wc:.3f}, "
+              f"wait_issue_frac = {a.get('SQ_WAIT_INST_ANY', 0.0) / wc:.3f}, "
+              f"wait_lds_frac = {a.get('SQ_WAIT_INST_LDS', 0.0) / wc:.3f}, "
+              f"lds_conflict_per_lds_inst = {a.get('SQ_LDS_BANK_CONFLICT', 0.0) / max(a.get('SQ_INSTS_LDS', 0.0), 1.0):.3f}")
+
+
+def trace_summary(outdir, title, command, notes=()):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (*_kernel_stats.csv), after the
+    paragraphs `notes`."""
     files = glob.glob(os.path.join(outdir, "**", "*kernel_stats.csv"), recursive=True)
     if not files:
         sys.exit(f"no kernel_stats.csv under {outdir}")
@@ -295,6 +335,8 @@ def trace_summary(outdir, title, command):
     print(f"# {title}\n")
     print("Command (from the repository root):\n")
     print("```\n" + command + "\n```\n")
+    for n in notes:
+        print(n + "\n")
     print("rocprofv3 kernel-trace statistics:\n")
     print("| kernel | calls | total (ms) | average (us) | % |")
     print("|---|---:|---:|---:|---:|")
@@ -339,10 +381,16 @@ def main():
     v.add_argument("--cells", type=int, required=True)
     v.add_argument("--kernel", default="k_adjoint_stage")
     v.add_argument("--command", action="append", default=[])
+    st = sub.add_parser("stall")
+    st.add_argument("outdir")
+    st.add_argument("--cells", type=int, required=True)
+    st.add_argument("--kernel", default="_stage")
+    st.add_argument("--command", action="append", default=[])
     r = sub.add_parser("trace")
     r.add_argument("outdir")
     r.add_argument("--title", required=True)
     r.add_argument("--command", required=True)
+    r.add_argument("--note", action="append", default=[], help="a paragraph printed before the table")
     args = ap.parse_args()
     if args.cmd == "traffic":
         traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.mib, args.cells, args.kernel,
@@ -351,8 +399,11 @@ def main():
     if args.cmd == "valu":
         valu(args.outdir, args.cells, args.kernel, args.command)
         return
+    if args.cmd == "stall":
+        stall(args.outdir, args.cells, args.kernel, args.command)
+        return
     if args.cmd == "trace":
-        trace_summary(args.outdir, args.title, args.command)
+        trace_summary(args.outdir, args.title, args.command, args.note)
         return
     if args.cmd == "adjoint":
         run_adjoint(args.n, args.precision, args.reps, args.stages, args.tune, args.flux)

@@ -57,3 +57,56 @@ def test_schedule_ceiling_counts_every_launch(monkeypatch):
     binom = dict(seg, plan={"schedule": "binomial", "stage_recomputes_per_step": 3})
     c2 = bench.schedule_ceiling(binom, 1000, "h", 4000.0, 20)
     assert c2["bytes_per_cell_step"] == pytest.approx(c["bytes_per_cell_step"] + 3 * 60)
+
+
+def _counter_csv(path, rows):
+    import csv
+    import os
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(("Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"), r)))
+
+
+def test_profile_summaries_from_counter_files(tmp_path, capsys):
+    from paper_1511_06959_amd import profile_run as pr
+    k = "void adjns::k_adjoint_stage<float, 0, 0, 1, 1, 32, 4, 4>(adjns::Consts<float>, float const*)"
+    # stall fractions: two dispatches, averaged, then divided by the summed wave cycles
+    rows = []
+    for d, scale in ((1, 1.0), (2, 3.0)):
+        for c, v in (("SQ_WAVE_CYCLES", 1000.0), ("SQ_ACTIVE_INST_VALU", 200.0), ("SQ_WAIT_INST_ANY", 400.0),
+                     ("SQ_WAIT_INST_LDS", 100.0), ("SQ_INSTS_LDS", 50.0), ("SQ_LDS_BANK_CONFLICT", 25.0)):
+            rows.append((d, k, c, v * scale))
+    _counter_csv(str(tmp_path / "stall" / "run_counter_collection.csv"), rows)
+    pr.stall(str(tmp_path / "stall"), 64, "_stage", ["cmd"])
+    out = capsys.readouterr().out
+    assert "2 dispatches" in out and "SQ_WAVE_CYCLES 2000" in out
+    assert "valu_active_frac = 0.200, wait_issue_frac = 0.400, wait_lds_frac = 0.100" in out
+    assert "lds_conflict_per_lds_inst = 0.500" in out
+    # traffic: counters scaled by what a copy of known size reads (here fetch x2, write x1)
+    copyk = "__amd_rocclr_copyBuffer"
+    _counter_csv(str(tmp_path / "cf" / "a_counter_collection.csv"), [(1, copyk, "FETCH_SIZE", 512.0)])
+    _counter_csv(str(tmp_path / "cw" / "a_counter_collection.csv"), [(1, copyk, "WRITE_SIZE", 1024.0)])
+    _counter_csv(str(tmp_path / "f" / "a_counter_collection.csv"), [(1, k, "FETCH_SIZE", 10.0), (2, k, "FETCH_SIZE", 30.0)])
+    _counter_csv(str(tmp_path / "w" / "a_counter_collection.csv"), [(1, k, "WRITE_SIZE", 5.0), (2, k, "WRITE_SIZE", 5.0)])
+    pr.traffic(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"), 1, 1024,
+               "k_adjoint_stage", [])
+    vals = dict(l.split(" = ") for l in capsys.readouterr().out.splitlines() if " = " in l and not l.startswith("#"))
+    assert float(vals["fetch_bytes_per_launch"]) == pytest.approx(2 * 20.0 * 1024)
+    assert float(vals["write_bytes_per_launch"]) == pytest.approx(5.0 * 1024)
+    assert float(vals["bytes_per_cell_launch_f32"]) == pytest.approx((40.0 + 5.0) * 1024 / 1024)
+    assert vals["tile_f32"] == "32x4x4" and vals["kernel_source_sha256"] == pr._src_hash("k_adjoint_stage")
+    # trace table with a note paragraph before it
+    import csv
+    os_dir = tmp_path / "tr"
+    os_dir.mkdir()
+    with open(os_dir / "x_kernel_stats.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"])
+        w.writeheader()
+        w.writerow({"Name": k, "Calls": 4, "TotalDurationNs": 4e6, "AverageNs": 1e6, "Percentage": 100.0})
+    pr.trace_summary(str(os_dir), "T", "C", ["a note"])
+    out = capsys.readouterr().out
+    assert out.index("a note") < out.index("| kernel |")
+    assert "| `k_adjoint_stage<float, 0, 0, 1, 1, 32, 4, 4>` | 4 | 4.00 | 1000.00 | 100.0 |" in out
