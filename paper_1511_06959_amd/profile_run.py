@@ -21,8 +21,8 @@
     python -m paper_1511_06959_amd.profile_run valu <dir> --cells N [--kernel k_adjoint_stage]
         vector-ALU instructions and FP32 operations per launch from one run with the SQ counters
         of VALU_COUNTERS
-    python -m paper_1511_06959_amd.profile_run stall <dir> --cells N [--kernel _stage]
-        issue, wait and LDS fractions per kernel from one run with the SQ counters of STALL_COUNTERS
+    python -m paper_1511_06959_amd.profile_run stall <dir> [<dir> ...] --cells N [--kernel _stage]
+        issue, wait and LDS fractions per kernel from runs with SQ counters (STALL_COUNTERS and others)
     python -m paper_1511_06959_amd.profile_run trace <dir> --title T --command C [--note PARAGRAPH ...]
         markdown table of a --kernel-trace --stats run
 
@@ -289,22 +289,34 @@ STALL_COUNTERS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_
                   "SQ_INSTS_LDS", "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT")
 
 
-def stall(outdir, cells, kernel, commands):
-    """Averages per dispatch of STALL_COUNTERS for every kernel whose name holds `kernel`, and their
+FRACTIONS = (("valu_active_frac", "SQ_ACTIVE_INST_VALU"), ("wait_issue_frac", "SQ_WAIT_INST_ANY"),
+             ("wait_lds_frac", "SQ_WAIT_INST_LDS"), ("wait_any_frac", "SQ_WAIT_ANY"),
+             ("lds_active_frac", "SQ_ACTIVE_INST_LDS"), ("active_any_frac", "SQ_ACTIVE_INST_ANY"))
+
+
+def stall(outdirs, cells, kernel, commands):
+    """Averages per dispatch of the SQ counters of one or more runs (each counter averaged over
+    the dispatches of the run that took it) for every kernel whose name holds `kernel`, and their
     fractions of SQ_WAVE_CYCLES (the summed wave lifetimes, so the counters' common unit cancels):
-    VALU issue, waiting for any instruction, waiting for LDS; bank-conflict cycles per LDS
-    instruction."""
-    acc, disp = defaultdict(lambda: defaultdict(float)), defaultdict(set)
-    for f in glob.glob(os.path.join(outdir, "**", "*counter_collection.csv"), recursive=True):
-        with open(f) as fh:
-            for row in csv.DictReader(fh):
-                k = short_name(row.get("Kernel_Name", ""))
-                if kernel in k:
-                    acc[k][row["Counter_Name"]] += float(row["Counter_Value"])
-                    disp[k].add(row.get("Dispatch_Id"))
+    VALU issue, waiting to issue, waiting for LDS, waiting on any counter, LDS and any-unit
+    activity, as far as the runs hold them; bank-conflict cycles per LDS instruction and per
+    LDS-active cycle."""
+    if isinstance(outdirs, str):
+        outdirs = [outdirs]
+    acc, disp = defaultdict(lambda: defaultdict(float)), defaultdict(lambda: defaultdict(set))
+    for d in outdirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    k = short_name(row.get("Kernel_Name", ""))
+                    if kernel in k:
+                        c = row["Counter_Name"]
+                        acc[k][c] += float(row["Counter_Value"])
+                        disp[k][c].add((d, row.get("Dispatch_Id")))
     if not acc:
-        sys.exit(f"no {kernel} dispatches under {outdir}")
-    print(f"# stall and issue counters of the *{kernel}* kernels (rocprofv3 SQ counters, one run), {cells} cells")
+        sys.exit(f"no {kernel} dispatches under {', '.join(outdirs)}")
+    print(f"# stall and issue counters of the *{kernel}* kernels (rocprofv3 SQ counters, "
+          f"{len(outdirs)} run{'s' if len(outdirs) > 1 else ''}), {cells} cells")
     for c in commands:
         print(f"# command: {c}")
     print("# averages per dispatch; the fractions are of SQ_WAVE_CYCLES (summed wave lifetimes), so the counters' "
@@ -312,14 +324,17 @@ def stall(outdir, cells, kernel, commands):
     print("# cancels; lds_conflict_per_lds_inst = SQ_LDS_BANK_CONFLICT cycles per LDS instruction")
     print(f"# kernel_source_sha256 = {_src_hash(kernel)}")
     for k in sorted(acc):
-        n = len(disp[k])
-        a = {c: v / n for c, v in acc[k].items()}
+        a = {c: v / len(disp[k][c]) for c, v in acc[k].items()}
+        n = max(len(v) for v in disp[k].values())
         print(f"{k}: {n} dispatches, " + ", ".join(f"{c} {a[c]:.6g}" for c in sorted(a)))
         wc = a.get("SQ_WAVE_CYCLES", 0.0) or float("nan")
-        print(f"  valu_active_frac = {a.get('SQ_ACTIVE_INST_VALU', 0.0) / wc:.3f}, "
-              f"wait_issue_frac = {a.get('SQ_WAIT_INST_ANY', 0.0) / wc:.3f}, "
-              f"wait_lds_frac = {a.get('SQ_WAIT_INST_LDS', 0.0) / wc:.3f}, "
-              f"lds_conflict_per_lds_inst = {a.get('SQ_LDS_BANK_CONFLICT', 0.0) / max(a.get('SQ_INSTS_LDS', 0.0), 1.0):.3f}")
+        parts = [f"{name} = {a[c] / wc:.3f}" for name, c in FRACTIONS if c in a]
+        if "SQ_LDS_BANK_CONFLICT" in a and "SQ_INSTS_LDS" in a:
+            parts.append(f"lds_conflict_per_lds_inst = {a['SQ_LDS_BANK_CONFLICT'] / max(a['SQ_INSTS_LDS'], 1.0):.3f}")
+        if "SQ_LDS_BANK_CONFLICT" in a and "SQ_ACTIVE_INST_LDS" in a:
+            parts.append("lds_conflict_per_lds_active_cycle = "
+                         f"{a['SQ_LDS_BANK_CONFLICT'] / max(a['SQ_ACTIVE_INST_LDS'], 1.0):.3f}")
+        print("  " + ", ".join(parts))
 
 
 def trace_summary(outdir, title, command, notes=()):
@@ -382,7 +397,7 @@ def main():
     v.add_argument("--kernel", default="k_adjoint_stage")
     v.add_argument("--command", action="append", default=[])
     st = sub.add_parser("stall")
-    st.add_argument("outdir")
+    st.add_argument("outdir", nargs="+")
     st.add_argument("--cells", type=int, required=True)
     st.add_argument("--kernel", default="_stage")
     st.add_argument("--command", action="append", default=[])

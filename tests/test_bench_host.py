@@ -85,6 +85,14 @@ def test_profile_summaries_from_counter_files(tmp_path, capsys):
     assert "2 dispatches" in out and "SQ_WAVE_CYCLES 2000" in out
     assert "valu_active_frac = 0.200, wait_issue_frac = 0.400, wait_lds_frac = 0.100" in out
     assert "lds_conflict_per_lds_inst = 0.500" in out
+    # a second run with other counters: each counter averaged over the dispatches of its own run
+    rows2 = [(d, k, c, v) for d in (7, 8, 9) for c, v in (("SQ_WAVE_CYCLES", 2000.0), ("SQ_WAIT_ANY", 600.0),
+                                                          ("SQ_ACTIVE_INST_LDS", 100.0))]
+    _counter_csv(str(tmp_path / "stall2" / "run_counter_collection.csv"), rows2)
+    pr.stall([str(tmp_path / "stall"), str(tmp_path / "stall2")], 64, "_stage", [])
+    out = capsys.readouterr().out
+    assert "5 dispatches" in out and "wait_any_frac = 0.300" in out and "lds_active_frac = 0.050" in out
+    assert "valu_active_frac = 0.200" in out and "lds_conflict_per_lds_active_cycle = 0.500" in out
     # traffic: counters scaled by what a copy of known size reads (here fetch x2, write x1)
     copyk = "__amd_rocclr_copyBuffer"
     _counter_csv(str(tmp_path / "cf" / "a_counter_collection.csv"), [(1, copyk, "FETCH_SIZE", 512.0)])
