@@ -53,6 +53,7 @@ class WindowSpec:
         if self.segment is not None and self.schedule in ("auto", "segments"):
             return "segments", int(self.segment)
         self.workspace()  # allocated before the free memory is read
+        torch.cuda.empty_cache()  # blocks the caching allocator holds free count as free
         free, _ = torch.cuda.mem_get_info(device)
         # besides the checkpoints: the sweep's working states and adjoints (a, b, grad_s, current,
         # next and final state) and the caller's w0, s and gradients

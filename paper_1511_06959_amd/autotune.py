@@ -117,4 +117,7 @@ def tune(g, reps=20, use_cache=True, verbose=False, rounds=3, margin=0.03):
                   flush=True)
     if use_cache:
         _store(db)
+    # the timing buffers go back to the device, so that a plan sized from free memory sees them
+    del w, kh, buf, ws
+    torch.cuda.empty_cache()
     return out

@@ -201,6 +201,7 @@ class PlannedEnsemble:
         self.member_lam = [0.0] * len(self.member_box) if member_lam is None else [float(x) for x in member_lam]
         self.obj_kind, self.device = obj_kind, device
         if budget_bytes is None:
+            torch.cuda.empty_cache()
             free, _ = torch.cuda.mem_get_info()
             budget_bytes = int(0.5 * free)
         self.groups = plan(self.grids, self.windows, self.member_box, budget_bytes)
