@@ -6,7 +6,8 @@ in HBM go to pinned host memory, or through pinned staging buffers to a file (an
 file, say): after each primal step the new state is copied device-to-host on a copy stream while
 the next step computes, and the reverse sweep fetches w_{n-1} while step n runs.  A small ring of
 device slots holds the states in flight; events order every reuse of a slot after the copy or the
-kernel that last touched it, and file reads and writes run on a worker thread.  The last states of
+kernel that last touched it, and file reads and writes run on worker threads (a record in
+page-aligned slices, moved in parallel).  The last states of
 the window may stay in HBM (`device_tail`): the reverse sweep consumes them first, while the first
 stored states are already on their way.
 
@@ -17,7 +18,6 @@ Only scheduling and copies happen here.
 import os
 from concurrent.futures import ThreadPoolExecutor
 
-import numpy as np
 import torch
 
 from . import (CKPT_NATIVE, OBJ_NONE, adjoint_step, ckpt_bytes, ckpt_decode, ckpt_encode, objective_and_grad,
@@ -52,31 +52,62 @@ class _PinnedStore:
 
 
 class _FileStore:
-    """Stored states in a file, moved through `nstage` pinned staging buffers by one worker
-    thread (file writes after the device-to-host copy has landed, file reads ahead of the
-    host-to-device copy)."""
+    """Stored states in a file, moved through `nstage` staging buffers (pinned unless pin=False).
+    One scheduling thread orders the transfers (a file write after its device-to-host copy has
+    landed, a file read ahead of its host-to-device copy); `io_threads` threads move the slices
+    of one record with positioned writes and reads, which release the interpreter lock, so a
+    record's slices go to and from the page cache (or the drive) in parallel.  Page-aligned
+    slices; the file is sized once, so no write extends it."""
 
-    def __init__(self, n, rec_len, dtype, path, nstage=3):
-        np_dtype = torch.empty(0, dtype=dtype).numpy().dtype
-        self.mm = np.memmap(path, dtype=np_dtype, mode="w+", shape=(max(n, 1), rec_len))
+    def __init__(self, n, rec_len, dtype, path, nstage=3, io_threads=4, pin=True):
         self.path = path
-        self.stage = [torch.empty(rec_len, dtype=dtype, pin_memory=True) for _ in range(nstage)]
-        self.busy = [None] * nstage     # pending worker job on each staging buffer
+        self.rec_len, self.dtype = rec_len, dtype
+        self.rec_bytes = rec_len * torch.empty(0, dtype=dtype).element_size()
+        self.fd = os.open(path, os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o600)
+        os.ftruncate(self.fd, max(n, 1) * self.rec_bytes)
+        self.stage = [torch.empty(rec_len, dtype=dtype, pin_memory=pin) for _ in range(nstage)]
+        self.busy = [None] * nstage     # pending scheduled job on each staging buffer
         self.h2d = [None] * nstage      # host-to-device copy out of each staging buffer
         self.reads = {}
         self.pool = ThreadPoolExecutor(max_workers=1)
+        self.io = ThreadPoolExecutor(max_workers=io_threads)
+        step = -(-self.rec_bytes // io_threads)
+        step = -(-step // 4096) * 4096
+        self.slices = [(o, min(step, self.rec_bytes - o)) for o in range(0, self.rec_bytes, step)]
 
     def _slot(self, n):
         return n % len(self.stage)
 
+    @staticmethod
+    def _bytes(t):
+        return memoryview(t.numpy()).cast("B")
+
+    def _pwrite(self, view, off):
+        while len(view):
+            k = os.pwrite(self.fd, view, off)
+            view, off = view[k:], off + k
+
+    def _pread(self, view, off):
+        while len(view):
+            k = os.preadv(self.fd, [view], off)
+            if k == 0:
+                raise OSError(f"{self.path}: end of file inside a stored record")
+            view, off = view[k:], off + k
+
+    def _move(self, fn, t, n):
+        """fn (_pwrite or _pread) over every slice of record n and host tensor t, in parallel."""
+        view, base = self._bytes(t), n * self.rec_bytes
+        for f in [self.io.submit(fn, view[o:o + ln], base + o) for o, ln in self.slices]:
+            f.result()
+
     def _write(self, n, j, ev):
         ev.synchronize()
-        self.mm[n] = self.stage[j].numpy()
+        self._move(self._pwrite, self.stage[j], n)
 
     def _read(self, n, j, prior):
         if prior is not None:
             prior.synchronize()
-        self.stage[j].numpy()[:] = self.mm[n]
+        self._move(self._pread, self.stage[j], n)
 
     def _claim(self, j):
         if self.busy[j] is not None:
@@ -112,16 +143,18 @@ class _FileStore:
     def finish(self):
         for j in range(len(self.stage)):
             self._claim(j)
-        self.mm.flush()
 
     def read(self, n):
-        return torch.from_numpy(np.array(self.mm[n]))
+        out = torch.empty(self.rec_len, dtype=self.dtype)
+        self._move(self._pread, out, n)
+        return out
 
     def close(self):
         for j in range(len(self.stage)):
             self._claim(j)
         self.pool.shutdown()
-        del self.mm
+        self.io.shutdown()
+        os.close(self.fd)
         if os.path.exists(self.path):
             os.remove(self.path)
 
