@@ -1181,8 +1181,8 @@ def main():
     args.fl = 1 if args.flux == "roe" else 0
     args.nw = tuple(float(x) for x in args.nu_weight.split(",")) if args.nu_weight else None
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
-              "design note, not part of this build)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sharding over several GPUs "
+              "is described in the design notes and not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "cpu_baseline":

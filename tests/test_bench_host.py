@@ -118,3 +118,11 @@ def test_profile_summaries_from_counter_files(tmp_path, capsys):
     out = capsys.readouterr().out
     assert out.index("a note") < out.index("| kernel |")
     assert "| `k_adjoint_stage<float, 0, 0, 1, 1, 32, 4, 4>` | 4 | 4.00 | 1000.00 | 100.0 |" in out
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True, text=True, timeout=120,
+                       cwd=str(__import__("pathlib").Path(bench.__file__).parent))
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
