@@ -126,3 +126,18 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True, text=True, timeout=120,
                        cwd=str(__import__("pathlib").Path(bench.__file__).parent))
     assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_valu_summary_per_cell(tmp_path, capsys):
+    from paper_1511_06959_amd import profile_run as pr
+    k = "void adjns::k_primal_stage<float, 1, 1, 32, 4, 4>(adjns::Consts<float>, float const*)"
+    vals = {"SQ_WAVES": 8.0, "SQ_INSTS_VALU": 6400.0, "SQ_INSTS_VALU_ADD_F32": 100.0, "SQ_INSTS_VALU_MUL_F32": 50.0,
+            "SQ_INSTS_VALU_FMA_F32": 200.0, "SQ_INSTS_VALU_TRANS_F32": 10.0}
+    _counter_csv(str(tmp_path / "v" / "run_counter_collection.csv"),
+                 [(d, k, c, v) for d in (1, 2) for c, v in vals.items()])
+    pr.valu(str(tmp_path / "v"), 512, "k_primal_stage", [])
+    out = dict(l.split(" = ") for l in capsys.readouterr().out.splitlines() if " = " in l and not l.startswith("#"))
+    assert float(out["valu_insts_per_cell_launch_f32"]) == pytest.approx(6400.0 / 512)
+    # 64 lanes per wave instruction, an FMA counts two operations
+    assert float(out["fp32_ops_per_cell_launch_f32"]) == pytest.approx(64.0 * (100 + 50 + 10 + 2 * 200) / 512)
+    assert out["tile_f32"] == "32x4x4"
