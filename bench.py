@@ -504,6 +504,19 @@ def run_plan(wl, precision, K, warmup, tune=True, bf16=True, rec_fmt=None):
     return out
 
 
+def with_traffic(roof, name, khash, tile, cells):
+    """Adds to a 384^3 kernel roofline entry the HBM bytes per launch that the committed counter
+    summary profiles/traffic_<name>_turb384.txt gives (null when it was taken on other kernel
+    sources or another tile), and those bytes over the live launch duration: the HBM rate the
+    kernel really draws."""
+    t = profile_values(f"traffic_{name}_turb384.txt", khash, tile)
+    roof["traffic"] = None if t is None else float(t["bytes_per_cell_launch_f32"]) * cells
+    roof["traffic_profile"] = None if t is None else "profiles/" + t["profile"]
+    roof["traffic_gbs"] = None if t is None else roof["traffic"] / (roof["avg_launch_us"] * 1e-6) / 1e9
+    roof["traffic_frac"] = None if t is None else roof["traffic_gbs"] / HBM_PEAK_GBS
+    return roof
+
+
 def kernel_roofline(kind, prec, cells, ms, n):
     """HBM roofline of one stage-kernel class: algorithmic bytes per launch (a quarter of the
     per-cell-step bytes, times the cells) / mean launch duration."""
@@ -690,15 +703,11 @@ def main_c5(args):
     kname = {"adjoint_stage": "k_adjoint_stage", "primal_stage": "k_primal_stage"}[dom]
     khash = kernel_hash()
     tile = r32["tiles"].get(dom, {}).get("launched")
-    traffic = profile_values(f"traffic_{dom}_turb384.txt", khash, tile)
     valu = profile_values(f"valu_{dom}_turb384.txt", khash, tile)
+    for name in roofs:
+        with_traffic(roofs[name], name, khash, r32["tiles"].get(name, {}).get("launched"), cells)
     roof = dict(roofs[dom])
     roof["kernel"] = kname
-    roof["traffic"] = None if traffic is None else float(traffic["bytes_per_cell_launch_f32"]) * cells
-    roof["traffic_profile"] = None if traffic is None else "profiles/" + traffic["profile"]
-    # the counters' bytes over the live launch duration: the HBM rate the kernel really draws
-    roof["traffic_gbs"] = None if traffic is None else roof["traffic"] / (roof["avg_launch_us"] * 1e-6) / 1e9
-    roof["traffic_frac"] = None if traffic is None else roof["traffic_gbs"] / HBM_PEAK_GBS
     roof["device_copy_gbs"] = copy_gbs
     roof_valu = valu_roofline(valu, cells, roof["avg_launch_us"])
     if roof_valu is not None:

@@ -141,3 +141,18 @@ def test_valu_summary_per_cell(tmp_path, capsys):
     # 64 lanes per wave instruction, an FMA counts two operations
     assert float(out["fp32_ops_per_cell_launch_f32"]) == pytest.approx(64.0 * (100 + 50 + 10 + 2 * 200) / 512)
     assert out["tile_f32"] == "32x4x4"
+
+
+def test_with_traffic_fills_or_nulls(monkeypatch):
+    cells = 1000
+    roof = bench.kernel_roofline("primal", "f32", cells, 8 * 2.0, 8)   # 2 ms per launch
+    monkeypatch.setattr(bench, "profile_values",
+                        lambda name, h, tile: {"bytes_per_cell_launch_f32": "60", "profile": name}
+                        if tile == "32x4x4" else None)
+    r = bench.with_traffic(dict(roof), "primal_stage", "h", "32x4x4", cells)
+    assert r["traffic"] == pytest.approx(60.0 * cells)
+    assert r["traffic_gbs"] == pytest.approx(60.0 * cells / 2e-3 / 1e9)
+    assert r["traffic_frac"] == pytest.approx(r["traffic_gbs"] / 8000.0)
+    assert r["traffic_profile"] == "profiles/traffic_primal_stage_turb384.txt"
+    r2 = bench.with_traffic(dict(roof), "primal_stage", "h", "32x8x2", cells)
+    assert r2["traffic"] is None and r2["traffic_gbs"] is None and r2["traffic_frac"] is None
