@@ -61,12 +61,27 @@ __device__ __forceinline__ void note_nonfinite(double x) {
 }
 
 // partials has `nsets` consecutive arrays of `nblk` values; dst[s] = beta dst[s] + alpha[s] sum_s
+// Each thread adds the values i = t, t + RB, t + 2 RB, ... in that order; it issues their loads
+// FOLD_BATCH at a time, so that the memory latency is paid once per batch (a fold over the
+// per-tile partials of a large grid holds 10^5 values), and the order of the additions, so the
+// result, is the same as one load at a time.
+constexpr int FOLD_BATCH = 16;
+
 __global__ __launch_bounds__(RB) void k_fold(const double* __restrict__ partials, int nblk, int nsets,
                                              double* __restrict__ dst, double alpha, double beta) {
   __shared__ double sh[RB];
   for (int s = 0; s < nsets; ++s) {
+    const double* __restrict__ p = partials + (long long)s * nblk;
     double v = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += RB) v += partials[s * nblk + i];
+    int i = threadIdx.x;
+    for (; i + (FOLD_BATCH - 1) * RB < nblk; i += FOLD_BATCH * RB) {
+      double q[FOLD_BATCH];
+#pragma unroll
+      for (int k = 0; k < FOLD_BATCH; ++k) q[k] = p[i + k * RB];
+#pragma unroll
+      for (int k = 0; k < FOLD_BATCH; ++k) v += q[k];
+    }
+    for (; i < nblk; i += RB) v += p[i];
     const double tot = block_sum(v, sh);
     if (threadIdx.x == 0) {
       dst[s] = beta * dst[s] + alpha * tot;
