@@ -86,7 +86,8 @@ def valu_roofline(valu, cells, avg_us):
     summary) / its live average launch duration, against 78.6 TFLOP/s (FP32 without packed
     instructions; 157.3 with them is stated beside it);
     issue_frac = wave-level VALU instructions x 4 cycles (a wave64 instruction on a 16-lane SIMD)
-    / (1024 SIMDs x 2.4 GHz x duration)."""
+    / (1024 SIMDs x 2.4 GHz x duration), an upper bound of the issue share: some VALU instructions
+    issue in fewer cycles on this part (a VALU-bound kernel can exceed 1 by this count)."""
     if valu is None:
         return None
     s = avg_us * 1e-6
